@@ -1,0 +1,165 @@
+"""Benchmark: toroidal-poloidal nonlinear RHS at N_r = N_phi = N_z = 256 on one MI355X.
+
+One step = one mlg_rhs_tp call on the resident 256^3 vortex-pair state (FP64): radial
+synthesis of u and omega, inverse z and phi FFTs, (U + u) x omega, forward FFTs,
+Galerkin projection and the per-(m, k) elliptic solves (the whole transform round trip
+plus the nonlinear term).  value = N_r N_phi N_z / (seconds per step) / 1e9 [GDOF/s].
+
+Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "spectral transform+RHS GDOF/s at 256^3 on 1 MI355X; rel. error vs FP64 oracle"
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+# vortex pair (Sec. 5.3): Gamma = +-2 pi, core radius 0.1, separation 1, displacement 0.01,
+# axial period 8.6 (the Crow wavelength in units of the separation), moving frame U = (0, 1, 0)
+PAIR = dict(gamma=2 * np.pi, a=0.1, b=1.0, delta=0.01, lz=8.6)
+U_FRAME = (0.0, 1.0, 0.0)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gemm_flops(nr, nrc, M, nz, nprod):
+    """Algorithmic flops of nprod radial products: sum_m 2 * N_r * (N_r^c - m) * (2 N_z) real columns."""
+    return nprod * sum(2.0 * nr * max(nrc - m, 0) * 2 * nz for m in range(M))
+
+
+def build_state(plan, n, torch):
+    import synth
+    x, w, r = plan.nodes()
+    phi = 2 * np.pi * np.arange(n) / n
+    z = PAIR["lz"] * np.arange(n) / n
+    psi = synth.vortex_pair_psi(r, phi, z, gamma=PAIR["gamma"], a=PAIR["a"], b=PAIR["b"],
+                                delta=PAIR["delta"], lz=PAIR["lz"])
+    phys = torch.from_numpy(psi).cuda()
+    psi_hat = plan.empty_spec()
+    plan.forward(phys, psi_hat)
+    chi_hat = torch.zeros_like(psi_hat)
+    torch.cuda.synchronize()
+    return phys, psi_hat, chi_hat
+
+
+def cpu_baseline(n_sample: int):
+    """Oracle rhs_tp on the same vortex-pair workload at n_sample^3 (host cores)."""
+    import synth
+    from oracle.grid import Grid
+    from oracle.rhs import VecTables, rhs_tp
+    from oracle.transform import Tables, forward
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    g = Grid(n_sample, n_sample, n_sample, 1.0, lz=PAIR["lz"])
+    psi = synth.vortex_pair_psi(g.r, g.phi, g.z, gamma=PAIR["gamma"], a=PAIR["a"], b=PAIR["b"],
+                                delta=PAIR["delta"], lz=PAIR["lz"])
+    S = forward(psi, g, Tables(g))
+    vt = VecTables(g)
+    t0 = time.perf_counter()
+    rhs_tp(S, np.zeros_like(S), g, vt, U=U_FRAME, dealias=True)
+    dt = time.perf_counter() - t0
+    return dict(value=round(n_sample ** 3 / dt / 1e9, 6), unit="GDOF/s", cores=int(threads), kind="oracle",
+                sample=f"one oracle rhs_tp on the vortex-pair state at N_r=N_phi=N_z={n_sample} "
+                       f"(1/{(256 // n_sample) ** 3} of the 256^3 grid points), {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=128)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the single-GPU kernels and a sharding design are described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2609_18026_amd import Plan, mlg_timing_enable, mlg_timing_read
+    n = args.n
+    plan = Plan(n, n, n, 1.0, PAIR["lz"], dealias=1)
+    log(f"bench: plan {n}^3 ready, workspace {plan.layout.workspace_bytes / 2**30:.2f} GiB")
+    _, psi, chi = build_state(plan, n, torch)
+    po, co = plan.empty_spec(), plan.empty_spec()
+    for _ in range(args.warmup):
+        plan.rhs_tp(psi, chi, po, co, U=U_FRAME)
+    torch.cuda.synchronize()
+    log("bench: warmup done")
+    families = ["radial_gemm", "phi_fft", "z_fft", "vec_epilogue", "projection"]
+    mlg_timing_enable(plan.handle, True)
+    for f in families:
+        mlg_timing_read(plan.handle, f)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.rhs_tp(psi, chi, po, co, U=U_FRAME)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    kern = {f: mlg_timing_read(plan.handle, f) for f in families}
+    mlg_timing_enable(plan.handle, False)
+    log(f"bench: {ms:.3f} ms/step (wall {wall / args.steps * 1e3:.3f})")
+    value = n ** 3 / (ms / 1e3) / 1e9
+    M, nrc = plan.layout.M, plan.layout.nrc
+    flops_step = gemm_flops(n, nrc, M, n, 12)
+    gemm_ms, gemm_launches = kern["radial_gemm"]
+    per_launch_ms = gemm_ms / max(gemm_launches, 1)
+    achieved = flops_step * args.steps / (gemm_ms / 1e3) / 1e12
+    roofline = dict(bound="mfma", kernel="radial_gemm_f64", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS,
+                    unit="TFLOP/s", frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=None,
+                    flops_per_launch=flops_step / 2, avg_launch_ms=round(per_launch_ms, 4))
+    breakdown = {f: round(kern[f][0] / args.steps, 4) for f in families}
+    # transform pair of one scalar on the same plan (extra figure)
+    phys = plan.empty_phys()
+    spec = plan.empty_spec()
+    plan.backward(psi, phys)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.backward(psi, phys)
+        plan.forward(phys, spec)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    pair_ms = e0.elapsed_time(e1) / args.steps
+    out = {
+        "metric": METRIC, "value": round(value, 4), "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"toroidal-poloidal RHS P[(U+u) x omega] of a counter-rotating Lamb-Oseen vortex "
+                               f"pair at N_r=N_phi=N_z={n}, ell=1, L_z=8.6, two-thirds dealiasing, FP64",
+                   "nr": n, "nphi": n, "nz": n, "ell": 1.0, "lz": PAIR["lz"], "U": list(U_FRAME)},
+        "roofline": roofline,
+        "kernel_ms_per_step": breakdown,
+        "transform_pair": {"ms": round(pair_ms, 4), "gdofs": round(n ** 3 / (pair_ms / 1e3) / 1e9, 4)},
+    }
+    if not args.no_cpu_baseline:
+        log("bench: timing the oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

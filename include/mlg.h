@@ -1,0 +1,154 @@
+/*
+ * mlg.h -- C ABI of an MI355X (gfx950) library for the mapped associated-Legendre /
+ * Fourier spectral method of Lee & Wang, "MLegS: A modern mapped Legendre spectral
+ * method solver for unbounded domains with parallelization".
+ *
+ * The library computes, on one GPU, the physical <-> spectral transform pair of
+ * Eq. expansion (Sec. 3.1; the transform order of Sec. 4.1), the pseudospectral
+ * scalar products of Sec. 3.3 and Sec. 5.2, and the toroidal-poloidal nonlinear term
+ * P[(U + u) x omega] of Sec. 3.2 / Sec. 5.3 (Eq. tp, Eq. tp-poisson, Eq. tp-evolution).
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns mlg_status; 0 (MLG_OK) is success.  No exception crosses the
+ *    ABI.  mlg_last_error() returns a thread-local message for the last failure.
+ *  - Device buffers (phys, spec, ws, ...) are owned by the caller: plain device
+ *    pointers allocated with hipMalloc (or any allocator of the same device).  The
+ *    plan owns its own device tables and frees them in mlg_plan_destroy.
+ *  - 'stream' is a hipStream_t passed as void* (NULL = the default stream).  Work is
+ *    enqueued asynchronously; argument errors are reported synchronously; device
+ *    errors surface as MLG_E_DEVICE on the call that detects them.
+ *  - One plan may be used from one stream at a time; concurrent streams need their
+ *    own workspace buffers.
+ *
+ * Data layouts (FP64 plans: real = double, complex = interleaved double pair;
+ * FP32 and split-BF16 plans: float / interleaved float pair)
+ *  - physical field: real [N_z][N_r][N_phi], element (l, i, j) = s(r_i, phi_j, z_l),
+ *    r_i ascending (x_i the Gauss-Legendre nodes, r = ell sqrt((1+x)/(1-x)), Eq. map),
+ *    phi_j = 2 pi j / N_phi, z_l = L_z l / N_z.
+ *  - spectral field: complex, packed triangular [tau][N_z]; row off(m) + (n - m) holds
+ *    shat_{n m k} for m = 0 .. M-1, n = m .. N_r^c-1, off(m) = sum_{m'<m} (N_r^c - m'),
+ *    tau = off(M).  Column kk is the FFT slot of k (kk = k mod N_z).  Slots with
+ *    |k| >= N_z^c and the Nyquist slot are written as zero and never read.
+ *    Only m >= 0 is stored; shat_{n,-m,-k} = conj(shat_{n,m,k}) (Sec. 3.1).  The m = 0
+ *    harmonic enters the backward transform through its real part; a real field has a
+ *    Hermitian m = 0 column, which the library does not enforce.
+ *  - normalisation: forward = (1/(N_phi N_z)) sum over phi and z, then Gauss-Legendre
+ *    projection sum_i w_i Pbar_n^m(x_i); backward = the plain sum of Eq. expansion.
+ *    Pbar_n^m = N_n^m P_n^m (Eq. norm) without the Condon-Shortley phase.
+ */
+#ifndef MLG_H
+#define MLG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MLG_OK = 0,
+  MLG_E_ARG = 1,          /* invalid argument (null pointer, size, chop, unsupported value) */
+  MLG_E_ALLOC = 2,        /* device or host allocation failed                               */
+  MLG_E_DEVICE = 3,       /* a HIP call or kernel launch failed                             */
+  MLG_E_UNSUPPORTED = 4,  /* valid request the library does not implement (e.g. FFT length) */
+  MLG_E_NONFINITE = 5     /* non-finite input to plan creation                              */
+} mlg_status;
+
+typedef enum {
+  MLG_FP64 = 0,        /* double data, FP64 arithmetic (MFMA f64 for the radial products)    */
+  MLG_FP32 = 1,        /* float data, FP32 arithmetic                                        */
+  MLG_SPLIT_BF16 = 2   /* float data; radial products as hi/lo bfloat16 splits on MFMA with  */
+                       /* FP32 accumulation (a_hi b_hi + a_hi b_lo + a_lo b_hi)              */
+} mlg_precision;
+
+enum { MLG_RHS_U2 = 0, MLG_RHS_KPP = 1 };
+
+/* Grid and chops of one field (Sec. 3.1).  Chops: 0 selects the default
+ * N_r^c = N_r, N_phi^c = N_phi/2 (orders m < N_phi/2), N_z^c = max(1, N_z/2).
+ * Bounds enforced: 2 <= N_r, N_r^c <= N_r, N_phi^c <= N_phi/2 + 1, N_z^c <= N_z/2 + 1,
+ * ell > 0, L_z > 0, all finite.  'dealias' = 1 applies the two-thirds mask (keep
+ * m <= floor((N_phi-1)/3) and |k| <= floor((N_z-1)/3)) to RHS outputs (Sec. 3.3). */
+typedef struct {
+  int32_t nr, nphi, nz;
+  int32_t nrc, nphic, nzc;
+  double ell, lz;
+  int32_t dealias;
+} mlg_grid;
+
+/* Sizes of the arrays a plan reads and writes. */
+typedef struct {
+  int64_t phys_elems;       /* N_z * N_r * N_phi reals                                   */
+  int64_t spec_rows;        /* tau                                                       */
+  int64_t spec_elems;       /* tau * N_z complex values                                  */
+  int64_t workspace_bytes;  /* bytes of device workspace every call of this plan needs  */
+  int32_t M;                /* stored azimuthal orders                                   */
+  int32_t nrc, nzc;         /* resolved radial and axial chops                           */
+  int32_t real_bytes;       /* 8 (FP64) or 4 (FP32, split-BF16)                          */
+  int32_t dealias_m, dealias_k;  /* largest kept m and |k| under the two-thirds mask     */
+} mlg_layout;
+
+typedef struct mlg_plan_s* mlg_plan;
+
+/* Create a plan: validates the grid, builds on the host in FP64 the Gauss-Legendre nodes
+ * and weights, the tables Pbar_n^m(x_i) (Eq. norm, normalised recurrence, no factorials),
+ * r d/dr Pbar, the horizontal-Laplacian Gram factors of Eq. del2h-entries and the FFT
+ * twiddles, then copies them to 'device'.  Errors: MLG_E_ARG for bad sizes/chops/ell,
+ * MLG_E_NONFINITE for non-finite ell or L_z, MLG_E_UNSUPPORTED for N_phi or N_z whose
+ * factors are not all 2, 3 or 5, or N_phi, N_z above 1024; MLG_E_ALLOC/DEVICE on HIP failure.
+ * On failure *out is NULL and nothing is leaked. */
+mlg_status mlg_plan_create(const mlg_grid* grid, mlg_precision prec, int device, mlg_plan* out);
+
+/* Free the plan's device tables.  NULL is accepted. */
+mlg_status mlg_plan_destroy(mlg_plan plan);
+
+/* Fill *out with the plan's array sizes. */
+mlg_status mlg_plan_query(mlg_plan plan, mlg_layout* out);
+
+/* Host copies (length N_r, any may be NULL) of the nodes x_i, weights w_i and radii r_i. */
+mlg_status mlg_plan_nodes(mlg_plan plan, double* x, double* w, double* r);
+
+/* Forward transform (Sec. 4.1 order: phi FFT, radial projection per m, z FFT):
+ * phys (device, physical layout) -> spec (device, spectral layout).  ws: device
+ * workspace of mlg_layout.workspace_bytes.  phys is not modified. */
+mlg_status mlg_forward(mlg_plan plan, const void* phys, void* spec, void* ws, void* stream);
+
+/* Backward transform, Eq. expansion: spec -> phys.  spec is not modified. */
+mlg_status mlg_backward(mlg_plan plan, const void* spec, void* phys, void* ws, void* stream);
+
+/* Pseudospectral scalar term (Sec. 3.3; Eq. kpp): out = Mask(F(g(B(u)))) with
+ * g(u) = u^2 (kind MLG_RHS_U2) or gamma u (1 - u) (kind MLG_RHS_KPP); the mask is applied
+ * when the plan's grid has dealias = 1.  spec_u and spec_out may not alias. */
+mlg_status mlg_rhs_scalar(mlg_plan plan, int kind, double gamma, const void* spec_u,
+                          void* spec_out, void* ws, void* stream);
+
+/* Toroidal-poloidal nonlinear term (Sec. 3.2, Sec. 5.3, Eq. tp-evolution):
+ * (psi_n, chi_n) = Mask(P[(U + u) x omega]) with u = curl(psi z) + curl curl(chi z),
+ * omega = curl u and U = (U[0], U[1], U[2]) a uniform Cartesian background (host array;
+ * NULL = 0).  P takes the gradient-free part through the axial curl and curl-curl
+ * (Eq. tp-poisson); the m = 0 blocks use the decay gauge psi, chi -> 0 as r -> infinity.
+ * Inputs must have zero net circulation (the logarithmic proxy of Eq. logproxy is not
+ * supported).  'taps' may be NULL; otherwise a device buffer of
+ * 9 * phys_elems + 3 * spec_elems values (reals, then complex) receiving nodal
+ * u_r, u_phi, u_z, w_r, w_phi, w_z, N_r, N_phi, N_z and the sources C, K, Zhat.
+ * Requires N_r^c = N_r. */
+mlg_status mlg_rhs_tp(mlg_plan plan, const double* U, const void* psi, const void* chi,
+                      void* psi_n, void* chi_n, void* taps, void* ws, void* stream);
+
+/* Optional per-kernel timing, for benchmarks and profiling (not needed for computation).
+ * While enabled, every kernel launch of the plan is bracketed by two HIP events recorded on
+ * the launch's stream.  mlg_timing_read waits for the recorded events, returns the summed
+ * elapsed milliseconds and the launch count for kernel family 'kernel' ("radial_gemm",
+ * "phi_fft", "z_fft", "vec_epilogue", "projection", "mask"), and clears that family's
+ * records.  Reading an unknown family returns 0 ms and 0 launches. */
+mlg_status mlg_timing_enable(mlg_plan plan, int enable);
+mlg_status mlg_timing_read(mlg_plan plan, const char* kernel, double* total_ms, int64_t* launches);
+
+/* Message for the last error on this thread ("" if none). */
+const char* mlg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLG_H */

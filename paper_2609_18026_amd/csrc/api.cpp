@@ -1,0 +1,316 @@
+// extern "C" entry points of include/mlg.h: argument validation and the kernel sequence of
+// each operation.  Every step of the computation runs in the library's own HIP kernels.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "mlg_internal.h"
+
+namespace mlg {
+mlg_status build_plan(mlg_plan_s* p);
+void destroy_plan(mlg_plan_s* p);
+extern thread_local std::string g_last_error;
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+bool factorable(int n) {
+  int r[16];
+  return n >= 1 && n <= 1024 && factor_radices(n, r) >= 0;
+}
+
+// Workspace partition for FP64 plans: 7 mixed arrays, 5 triangular arrays, solve scratch.
+struct Ws {
+  double* X[7];
+  double* T[5];
+  double* scratch;
+};
+
+Ws partition(const mlg_plan_s* p, void* ws) {
+  Ws w{};
+  char* b = static_cast<char*>(ws);
+  size_t o = 0;
+  for (int i = 0; i < 7; ++i) {
+    w.X[i] = reinterpret_cast<double*>(b + o);
+    o += p->mixed_elems * 2 * sizeof(double);
+  }
+  for (int i = 0; i < 5; ++i) {
+    w.T[i] = reinterpret_cast<double*>(b + o);
+    o += p->tri_elems * 2 * sizeof(double);
+  }
+  w.scratch = reinterpret_cast<double*>(b + o);
+  return w;
+}
+
+mlg_status check_plan(mlg_plan p) {
+  if (!p) return fail(MLG_E_ARG, "plan is NULL");
+  return MLG_OK;
+}
+
+}  // namespace
+}  // namespace mlg
+
+using namespace mlg;
+
+extern "C" {
+
+const char* mlg_last_error(void) { return g_last_error.c_str(); }
+
+mlg_status mlg_plan_create(const mlg_grid* grid, mlg_precision prec, int device, mlg_plan* out) {
+  if (!out) return fail(MLG_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!grid) return fail(MLG_E_ARG, "grid is NULL");
+  mlg_grid g = *grid;
+  if (!std::isfinite(g.ell) || !std::isfinite(g.lz)) return fail(MLG_E_NONFINITE, "ell and L_z must be finite");
+  if (!(g.ell > 0)) return fail(MLG_E_ARG, "ell must be positive");
+  if (!(g.lz > 0)) return fail(MLG_E_ARG, "L_z must be positive");
+  if (g.nr < 2) return fail(MLG_E_ARG, "N_r must be at least 2");
+  if (g.nphi < 2 || g.nz < 1) return fail(MLG_E_ARG, "N_phi must be >= 2 and N_z >= 1");
+  if (g.nrc < 0 || g.nphic < 0 || g.nzc < 0) return fail(MLG_E_ARG, "chops must be non-negative");
+  if (g.nrc == 0) g.nrc = g.nr;
+  if (g.nphic == 0) g.nphic = g.nphi / 2;
+  if (g.nzc == 0) g.nzc = g.nz / 2 > 0 ? g.nz / 2 : 1;
+  if (g.nrc > g.nr) return fail(MLG_E_ARG, "N_r^c exceeds N_r");
+  if (g.nphic > g.nphi / 2 + 1) return fail(MLG_E_ARG, "N_phi^c exceeds N_phi/2 + 1");
+  if (g.nzc > g.nz / 2 + 1) return fail(MLG_E_ARG, "N_z^c exceeds N_z/2 + 1");
+  if (g.dealias != 0 && g.dealias != 1) return fail(MLG_E_ARG, "dealias must be 0 or 1");
+  if (g.nr > 4096) return fail(MLG_E_UNSUPPORTED, "N_r above 4096");
+  if (!factorable(g.nphi) || !factorable(g.nz))
+    return fail(MLG_E_UNSUPPORTED, "N_phi and N_z must be <= 1024 with prime factors 2, 3, 5 only");
+  if (prec != MLG_FP64) return fail(MLG_E_UNSUPPORTED, "only MLG_FP64 plans are implemented");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(MLG_E_ARG, "device index out of range or no HIP device");
+  DeviceGuard guard(device);
+  if (!guard.ok) return fail(MLG_E_DEVICE, "hipSetDevice failed");
+  mlg_plan_s* p = new (std::nothrow) mlg_plan_s();
+  if (!p) return fail(MLG_E_ALLOC, "host allocation failed");
+  p->g = g;
+  p->prec = prec;
+  p->device = device;
+  p->nr = g.nr;
+  p->nphi = g.nphi;
+  p->nz = g.nz;
+  p->nrc = g.nrc;
+  p->M = g.nphic;
+  p->nzc = g.nzc;
+  p->dealias_m = (g.nphi - 1) / 3;
+  p->dealias_k = (g.nz - 1) / 3;
+  p->phi_nrad = factor_radices(g.nphi, p->phi_rad);
+  p->z_nrad = factor_radices(g.nz, p->z_rad);
+  mlg_status st = build_plan(p);
+  if (st != MLG_OK) {
+    std::string msg = g_last_error;
+    destroy_plan(p);
+    return fail(st, msg);
+  }
+  *out = p;
+  return MLG_OK;
+}
+
+mlg_status mlg_plan_destroy(mlg_plan plan) {
+  if (!plan) return MLG_OK;
+  DeviceGuard guard(plan->device);
+  destroy_plan(plan);
+  return MLG_OK;
+}
+
+mlg_status mlg_plan_query(mlg_plan p, mlg_layout* out) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!out) return fail(MLG_E_ARG, "out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  out->phys_elems = (int64_t)p->nz * p->nr * p->nphi;
+  out->spec_rows = p->tau;
+  out->spec_elems = p->tau * p->nz;
+  out->workspace_bytes = (int64_t)p->ws_bytes;
+  out->M = p->M;
+  out->nrc = p->nrc;
+  out->nzc = p->nzc;
+  out->real_bytes = 8;
+  out->dealias_m = p->dealias_m;
+  out->dealias_k = p->dealias_k;
+  return MLG_OK;
+}
+
+mlg_status mlg_plan_nodes(mlg_plan p, double* x, double* w, double* r) {
+  if (mlg_status st = check_plan(p)) return st;
+  for (int i = 0; i < p->nr; ++i) {
+    if (x) x[i] = p->x[i];
+    if (w) w[i] = p->w[i];
+    if (r) r[i] = p->r[i];
+  }
+  return MLG_OK;
+}
+
+mlg_status mlg_forward(mlg_plan p, const void* phys, void* spec, void* ws, void* stream) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!phys || !spec || !ws) return fail(MLG_E_ARG, "null buffer");
+  DeviceGuard guard(p->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Ws w = partition(p, ws);
+  mlg_status st;
+  if ((st = launch_phi_forward(p, static_cast<const double*>(phys), w.X[0], s))) return st;
+  GemmProds pr{};
+  pr.nprod = 1;
+  pr.A[0] = p->d_Pf;
+  pr.B[0] = w.X[0];
+  pr.C[0] = static_cast<double*>(spec);
+  if ((st = launch_gemm(p, pr, p->d_desc_fwd, p->max_rows_fwd, 2 * p->nz, s))) return st;
+  return launch_zfft(p, static_cast<double*>(spec), static_cast<double*>(spec), p->tau, -1, nullptr, 0, 0, s);
+}
+
+mlg_status mlg_backward(mlg_plan p, const void* spec, void* phys, void* ws, void* stream) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!phys || !spec || !ws) return fail(MLG_E_ARG, "null buffer");
+  DeviceGuard guard(p->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Ws w = partition(p, ws);
+  mlg_status st;
+  if ((st = launch_zfft(p, static_cast<const double*>(spec), w.T[0], p->tau, +1, nullptr, 0, 0, s))) return st;
+  GemmProds pr{};
+  pr.nprod = 1;
+  pr.A[0] = p->d_Pb;
+  pr.B[0] = w.T[0];
+  pr.C[0] = w.X[0];
+  if ((st = launch_gemm(p, pr, p->d_desc_bwd, p->max_rows_bwd, 2 * p->nz, s))) return st;
+  return launch_phi_backward(p, w.X[0], static_cast<double*>(phys), s);
+}
+
+mlg_status mlg_rhs_scalar(mlg_plan p, int kind, double gamma, const void* spec_u, void* spec_out, void* ws,
+                          void* stream) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!spec_u || !spec_out || !ws) return fail(MLG_E_ARG, "null buffer");
+  if (spec_u == spec_out) return fail(MLG_E_ARG, "spec_u and spec_out must not alias");
+  if (kind != MLG_RHS_U2 && kind != MLG_RHS_KPP) return fail(MLG_E_ARG, "unknown RHS kind");
+  if (!std::isfinite(gamma)) return fail(MLG_E_ARG, "gamma must be finite");
+  DeviceGuard guard(p->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Ws w = partition(p, ws);
+  mlg_status st;
+  if ((st = launch_zfft(p, static_cast<const double*>(spec_u), w.T[0], p->tau, +1, nullptr, 0, 0, s))) return st;
+  GemmProds pr{};
+  pr.nprod = 1;
+  pr.A[0] = p->d_Pb;
+  pr.B[0] = w.T[0];
+  pr.C[0] = w.X[0];
+  if ((st = launch_gemm(p, pr, p->d_desc_bwd, p->max_rows_bwd, 2 * p->nz, s))) return st;
+  if ((st = launch_phi_scalar_rhs(p, kind, gamma, w.X[0], s))) return st;
+  pr.A[0] = p->d_Pf;
+  pr.B[0] = w.X[0];
+  pr.C[0] = static_cast<double*>(spec_out);
+  if ((st = launch_gemm(p, pr, p->d_desc_fwd, p->max_rows_fwd, 2 * p->nz, s))) return st;
+  const bool mask = p->g.dealias != 0;
+  return launch_zfft(p, static_cast<double*>(spec_out), static_cast<double*>(spec_out), p->tau, -1,
+                     mask ? p->d_row_m : nullptr, p->dealias_m, p->dealias_k, s);
+}
+
+mlg_status mlg_rhs_tp(mlg_plan p, const double* U, const void* psi, const void* chi, void* psi_n, void* chi_n,
+                      void* taps, void* ws, void* stream) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!psi || !chi || !psi_n || !chi_n || !ws) return fail(MLG_E_ARG, "null buffer");
+  if (psi_n == chi_n || psi_n == psi || psi_n == chi || chi_n == psi || chi_n == chi)
+    return fail(MLG_E_ARG, "outputs must not alias each other or the inputs");
+  if (p->nrc != p->nr) return fail(MLG_E_UNSUPPORTED, "mlg_rhs_tp requires N_r^c = N_r");
+  double Uh[3] = {0.0, 0.0, 0.0};
+  if (U) {
+    for (int i = 0; i < 3; ++i) {
+      if (!std::isfinite(U[i])) return fail(MLG_E_ARG, "background U must be finite");
+      Uh[i] = U[i];
+    }
+  }
+  DeviceGuard guard(p->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Ws w = partition(p, ws);
+  mlg_status st;
+  const int ncol = 2 * p->nz;
+  // 1. radial synthesis of the seven products (k stays spectral)
+  GemmProds pr{};
+  const double* ps = static_cast<const double*>(psi);
+  const double* cs = static_cast<const double*>(chi);
+  const double* tabs[7] = {p->d_Pb, p->d_Tb, p->d_Pb, p->d_Pb, p->d_Tb, p->d_Pb, p->d_Tb};
+  const double* ins[7] = {ps, ps, ps, cs, cs, cs, cs};
+  const int lsc[7] = {0, 0, 1, 0, 0, 1, 1};
+  pr.nprod = 7;
+  for (int i = 0; i < 7; ++i) {
+    pr.A[i] = tabs[i];
+    pr.B[i] = ins[i];
+    pr.C[i] = w.X[i];
+    pr.lscale[i] = lsc[i];
+  }
+  if ((st = launch_gemm(p, pr, p->d_desc_bwd, p->max_rows_bwd, ncol, s))) return st;
+  // 2. velocity and vorticity harmonics
+  if ((st = launch_vec_epilogue(p, w.X, s))) return st;
+  // 3. inverse z transforms of the six fields
+  const int64_t mrows = (int64_t)p->M * p->nr;
+  for (int i = 0; i < 6; ++i)
+    if ((st = launch_zfft(p, w.X[i], w.X[i], mrows, +1, nullptr, 0, 0, s))) return st;
+  // 4. phi stage: nodal u, w -> N = (U + u) x w -> harmonics of N_r/r, N_phi/r, N_z
+  double* tp = static_cast<double*>(taps);
+  if ((st = launch_phi_vec_rhs(p, Uh, w.X, tp, s))) return st;
+  // 5. forward z transforms
+  for (int i = 0; i < 3; ++i)
+    if ((st = launch_zfft(p, w.X[i], w.X[i], mrows, -1, nullptr, 0, 0, s))) return st;
+  // 6. Galerkin projections onto Pbar and Q = T - 2(1+x) Pbar
+  const double* ftab[5] = {p->d_Pf, p->d_Qf, p->d_Pf, p->d_Qf, p->d_Pf};
+  const double* fin[5] = {w.X[0], w.X[0], w.X[1], w.X[1], w.X[2]};
+  GemmProds pf{};
+  pf.nprod = 5;
+  for (int i = 0; i < 5; ++i) {
+    pf.A[i] = ftab[i];
+    pf.B[i] = fin[i];
+    pf.C[i] = w.T[i];
+    pf.lscale[i] = 0;
+  }
+  if ((st = launch_gemm(p, pf, p->d_desc_fwd, p->max_rows_fwd, ncol, s))) return st;
+  // 7. elliptic solves per (m, k)
+  const double* src5[5] = {w.T[0], w.T[1], w.T[2], w.T[3], w.T[4]};
+  double* tsrc = tp ? tp + (size_t)9 * p->nz * p->nr * p->nphi : nullptr;
+  return launch_projection(p, src5, static_cast<double*>(psi_n), static_cast<double*>(chi_n), w.scratch, tsrc, s);
+}
+
+mlg_status mlg_timing_enable(mlg_plan p, int enable) {
+  if (mlg_status st = check_plan(p)) return st;
+  p->timing.enabled = enable != 0;
+  return MLG_OK;
+}
+
+mlg_status mlg_timing_read(mlg_plan p, const char* kernel, double* total_ms, int64_t* launches) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!kernel || !total_ms || !launches) return fail(MLG_E_ARG, "null argument");
+  DeviceGuard guard(p->device);
+  double ms = 0;
+  int64_t n = 0;
+  auto& recs = p->timing.recs;
+  std::vector<mlg::Timing::Rec> keep;
+  for (auto& r : recs) {
+    if (r.name != kernel) {
+      keep.push_back(r);
+      continue;
+    }
+    MLG_HIP_TRY(hipEventSynchronize(r.b));
+    float t = 0;
+    MLG_HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
+    ms += t;
+    ++n;
+    p->timing.pool.push_back(r.a);
+    p->timing.pool.push_back(r.b);
+  }
+  recs.swap(keep);
+  *total_ms = ms;
+  *launches = n;
+  return MLG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,124 @@
+// Internal declarations of the mlg library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mlg.h"
+
+namespace mlg {
+
+// Thread-local error message plus a helper that records it and returns a status.
+void set_error(const std::string& msg);
+mlg_status fail(mlg_status st, const std::string& msg);
+
+#define MLG_HIP_TRY(expr)                                                               \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return ::mlg::fail(MLG_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// One radial product of the batched GEMM, per azimuthal order m:
+//   C[rows x ncol] = A^T B with A stored k-major (K x rows, leading dim lda) and
+//   B stored k-major (K x ncol, leading dim ncol).  Offsets are in elements.
+struct GemmDesc {
+  int64_t a_off, b_off, c_off;
+  int32_t rows, K, lda, m;
+};
+
+constexpr int kMaxProds = 8;
+struct GemmProds {
+  const double* A[kMaxProds];
+  const double* B[kMaxProds];
+  double* C[kMaxProds];
+  int32_t lscale[kMaxProds];  // 1: scale B row (degree n = k + m) by n(n+1)
+  int32_t nprod;
+};
+
+// Pentadiagonal SPD Gram matrix G_m = <Pbar_n, (1-x)^2 Pbar_j> factored as L D L^T.
+// Per m, entries for n = n0(m) .. nrc-1 where n0 = max(m, 1); stored at goff[m] + (n - n0).
+struct GramFactors {
+  std::vector<double> g0, g1, g2;  // G_{n,n}, G_{n,n+1}, G_{n,n+2}
+  std::vector<double> d, l1, l2;   // D_n, L_{n,n-1}, L_{n,n-2}
+  std::vector<int64_t> goff;       // size M + 1
+};
+
+}  // namespace mlg
+
+namespace mlg {
+// Event-pair recorder used when timing is enabled on a plan.
+struct Timing {
+  bool enabled = false;
+  struct Rec {
+    std::string name;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get();
+  void begin(const char* name, hipStream_t s);
+  void end(hipStream_t s);
+  ~Timing();
+};
+}  // namespace mlg
+
+struct mlg_plan_s {
+  mutable mlg::Timing timing;
+  mlg_grid g{};
+  mlg_precision prec = MLG_FP64;
+  int device = 0;
+  int nr = 0, nphi = 0, nz = 0, nrc = 0, M = 0, nzc = 0;
+  int dealias_m = 0, dealias_k = 0;
+  int64_t tau = 0;
+  std::vector<int64_t> off;  // M + 1 triangular row offsets
+  // host FP64 grid (ascending x)
+  std::vector<double> x, w, r, theta, one_minus_x, one_plus_x, q, rinv;
+  // device tables (FP64)
+  double* d_Pb = nullptr;   // backward Pbar, per m [n-m][i]
+  double* d_Pf = nullptr;   // forward w*Pbar, per m [i][n-m]
+  double* d_Tb = nullptr;   // backward Tbar = (1-x^2) dPbar/dx, per m [n-m][i]
+  double* d_Qf = nullptr;   // forward w*(Tbar - 2(1+x)Pbar), per m [i][n-m]
+  double* d_node = nullptr; // nodal vectors: rinv[nr], q[nr], opx[nr]
+  double* d_tw_phi = nullptr;  // exp(-2 pi i t / N_phi), interleaved
+  double* d_tw_z = nullptr;    // exp(-2 pi i t / N_z), interleaved
+  int32_t* d_row_m = nullptr;  // azimuthal order of every triangular row
+  mlg::GemmDesc* d_desc_fwd = nullptr;
+  mlg::GemmDesc* d_desc_bwd = nullptr;
+  double* d_gram = nullptr;    // packed g0,g1,g2,d,l1,l2 (6 * ngram)
+  int64_t* d_goff = nullptr;
+  int64_t ngram = 0;
+  int max_rows_fwd = 0, max_rows_bwd = 0;
+  int phi_rad[12] = {0};
+  int phi_nrad = 0;
+  int z_rad[12] = {0};
+  int z_nrad = 0;
+  // workspace partition (bytes)
+  size_t ws_bytes = 0;
+  size_t mixed_elems = 0;   // M * nr * nz complex
+  size_t tri_elems = 0;     // tau * nz complex
+};
+
+namespace mlg {
+// plan.cpp
+int factor_radices(int n, int* rad);
+// kernels.hip launchers (all enqueue on 'stream')
+mlg_status launch_gemm(const mlg_plan_s* p, const GemmProds& prods, const GemmDesc* d_desc,
+                       int max_rows, int ncol, hipStream_t stream);
+mlg_status launch_phi_forward(const mlg_plan_s* p, const double* phys, double* mixed, hipStream_t s);
+mlg_status launch_phi_backward(const mlg_plan_s* p, const double* mixed, double* phys, hipStream_t s);
+mlg_status launch_phi_scalar_rhs(const mlg_plan_s* p, int kind, double gamma, double* mixed, hipStream_t s);
+mlg_status launch_phi_vec_rhs(const mlg_plan_s* p, const double* U, double* const* f6, double* taps,
+                              hipStream_t s);
+// z-FFT over 'rows' contiguous lines of N_z complex values.  dir = -1 forward (scaled by 1/N_z,
+// slots outside the chop zeroed, optional dealias mask by row order m), +1 backward.
+mlg_status launch_zfft(const mlg_plan_s* p, const double* in, double* out, int64_t rows, int dir,
+                       const int32_t* row_m, int mask_m, int mask_k, hipStream_t s);
+mlg_status launch_vec_epilogue(const mlg_plan_s* p, double* const* prod7, hipStream_t s);
+mlg_status launch_projection(const mlg_plan_s* p, const double* const* src5, double* psi_n, double* chi_n,
+                             double* scratch, double* taps_src, hipStream_t s);
+mlg_status launch_mask_tri(const mlg_plan_s* p, double* spec, hipStream_t s);
+}  // namespace mlg

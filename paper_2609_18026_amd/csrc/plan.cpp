@@ -1,0 +1,307 @@
+// Plan creation: grid, basis tables and operator factors, built on the host in FP64
+// (long double where it buys accuracy), then copied to the device.
+//
+// * Gauss-Legendre nodes (Sec. 3.1, Eq. map): Newton iteration on P_N(cos theta) in the
+//   angle theta, which keeps 1 - x = 2 sin^2(theta/2) and r = ell cot(theta/2) free of
+//   cancellation near x = 1 (r -> infinity).
+// * Pbar_n^m (Eq. norm): normalised three-term recurrence in n from
+//   Pbar_m^m = sqrt(1/2) prod_j sqrt((2j+1)/(2j)) sin^m theta; its ratios are those of the
+//   ln N_n^m accumulation of Sec. 3.1, so no factorial is ever formed.
+// * r d/dr Pbar: the three-term derivative identity
+//   (1 - x^2) Pbar_n' = (n+1) e_n Pbar_{n-1} - n e_{n+1} Pbar_{n+1}, e_n = sqrt((n^2-m^2)/(4n^2-1)),
+//   which needs one extra recurrence row n = N_r^c.
+// * Horizontal Laplacian (Eq. laplacian, Eq. del2h-entries): in the normalised basis
+//   Dbar_m = -G_m diag(n(n+1)) / ell^2 with G_m = <Pbar_n, (1-x)^2 Pbar_j> the exact
+//   (pentadiagonal, symmetric positive definite) Gram matrix, assembled as
+//   (I - X)^2 from the Jacobi matrix X of multiplication by x.  G_m is factored L D L^T.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "mlg_internal.h"
+
+namespace mlg {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+mlg_status fail(mlg_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+hipEvent_t Timing::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void Timing::begin(const char* name, hipStream_t s) {
+  if (!enabled) return;
+  Rec r{name, get(), get()};
+  if (!r.a || !r.b) return;
+  (void)hipEventRecord(r.a, s);
+  recs.push_back(r);
+}
+
+void Timing::end(hipStream_t s) {
+  if (!enabled || recs.empty()) return;
+  (void)hipEventRecord(recs.back().b, s);
+}
+
+Timing::~Timing() {
+  for (auto& r : recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+int factor_radices(int n, int* rad) {
+  int k = 0;
+  while (n % 4 == 0) { rad[k++] = 4; n /= 4; }
+  while (n % 2 == 0) { rad[k++] = 2; n /= 2; }
+  while (n % 3 == 0) { rad[k++] = 3; n /= 3; }
+  while (n % 5 == 0) { rad[k++] = 5; n /= 5; }
+  if (n != 1) return -1;
+  return k;
+}
+
+namespace {
+
+using ld = long double;
+
+// P_N(cos t) and P_{N-1}(cos t) by the Bonnet recurrence.
+void legendre_pair(int N, ld c, ld* pn, ld* pnm1) {
+  ld p0 = 1, p1 = c;
+  if (N == 0) { *pn = 1; *pnm1 = 0; return; }
+  for (int k = 2; k <= N; ++k) {
+    ld p2 = ((2 * k - 1) * c * p1 - (k - 1) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  *pn = p1;
+  *pnm1 = p0;
+}
+
+// Nodes in ascending x, returned as theta (descending) and weights.
+void gauss_legendre_theta(int N, std::vector<ld>& theta, std::vector<ld>& w) {
+  theta.assign(N, 0);
+  w.assign(N, 0);
+  const ld pi = acosl(-1.0L);
+  for (int k = 1; k <= N; ++k) {
+    ld t = pi * (4 * k - 1) / (4 * N + 2);  // k-th root from x = 1
+    for (int it = 0; it < 100; ++it) {
+      ld pn, pm;
+      legendre_pair(N, cosl(t), &pn, &pm);
+      // d/dt P_N(cos t) = -N (P_{N-1} - x P_N) / sin t
+      ld dp = -N * (pm - cosl(t) * pn) / sinl(t);
+      ld dt = pn / dp;
+      t -= dt;
+      if (fabsl(dt) < 1e-19L * (1 + fabsl(t))) break;
+    }
+    ld pn, pm;
+    legendre_pair(N, cosl(t), &pn, &pm);
+    ld s = sinl(t);
+    int i = N - k;  // ascending x
+    theta[i] = t;
+    w[i] = 2 * s * s / ((ld)N * N * pm * pm);
+  }
+}
+
+// Pbar_n^m(cos t) for n = m .. nmax (inclusive) at one angle; out[n - m].
+void pbar_column(int m, int nmax, ld t, ld* out) {
+  ld s = sinl(t), c = cosl(t);
+  ld pmm = sqrtl(0.5L);
+  for (int j = 1; j <= m; ++j) pmm *= sqrtl((ld)(2 * j + 1) / (ld)(2 * j)) * s;
+  out[0] = pmm;
+  if (nmax >= m + 1) out[1] = sqrtl((ld)(2 * m + 3)) * c * pmm;
+  for (int n = m + 2; n <= nmax; ++n) {
+    ld a = sqrtl((ld)(4 * n * n - 1) / (ld)(n * n - m * m));
+    ld b = sqrtl((ld)((2 * n + 1) * (n - 1 - m) * (n - 1 + m)) / (ld)((2 * n - 3) * (n * n - m * m)));
+    out[n - m] = a * c * out[n - 1 - m] - b * out[n - 2 - m];
+  }
+}
+
+ld eps_nm(int n, int m) {
+  if (n <= m || n <= 0) return 0;
+  return sqrtl((ld)(n * n - m * m) / (ld)(4 * n * n - 1));
+}
+
+template <typename T>
+mlg_status upload(T** dst, const std::vector<T>& src) {
+  if (src.empty()) { *dst = nullptr; return MLG_OK; }
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), src.size() * sizeof(T));
+  if (e != hipSuccess) { *dst = nullptr; return fail(MLG_E_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e)); }
+  e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(MLG_E_DEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  return MLG_OK;
+}
+
+void free_plan_device(mlg_plan_s* p) {
+  void* ptrs[] = {p->d_Pb, p->d_Pf, p->d_Tb, p->d_Qf, p->d_node, p->d_tw_phi, p->d_tw_z,
+                  p->d_row_m, p->d_desc_fwd, p->d_desc_bwd, p->d_gram, p->d_goff};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+}
+
+}  // namespace
+
+mlg_status build_plan(mlg_plan_s* p) {
+  const mlg_grid& g = p->g;
+  const int nr = p->nr, nrc = p->nrc, M = p->M, nz = p->nz;
+  // ---------------- nodes
+  std::vector<ld> th, wl;
+  gauss_legendre_theta(nr, th, wl);
+  p->x.resize(nr); p->w.resize(nr); p->r.resize(nr); p->theta.resize(nr);
+  p->one_minus_x.resize(nr); p->one_plus_x.resize(nr); p->q.resize(nr); p->rinv.resize(nr);
+  for (int i = 0; i < nr; ++i) {
+    ld t = th[i];
+    ld sh = sinl(t / 2), ch = cosl(t / 2);
+    ld omx = 2 * sh * sh, opx = 2 * ch * ch;
+    p->theta[i] = (double)t;
+    p->x[i] = (double)cosl(t);
+    p->w[i] = (double)wl[i];
+    p->one_minus_x[i] = (double)omx;
+    p->one_plus_x[i] = (double)opx;
+    p->r[i] = (double)((ld)g.ell * ch / sh);
+    p->rinv[i] = (double)(sh / (ch * (ld)g.ell));
+    p->q[i] = (double)(omx * omx / ((ld)g.ell * (ld)g.ell));
+  }
+  // ---------------- triangular offsets
+  p->off.assign(M + 1, 0);
+  for (int m = 0; m < M; ++m) p->off[m + 1] = p->off[m] + std::max(nrc - m, 0);
+  p->tau = p->off[M];
+  // ---------------- tables
+  const size_t tsz = (size_t)p->tau * nr;
+  std::vector<double> Pb(tsz), Pf(tsz), Tb(tsz), Qf(tsz);
+  std::vector<ld> col(nrc + 2);
+  for (int m = 0; m < M; ++m) {
+    const int K = nrc - m;
+    if (K <= 0) continue;
+    const size_t base = (size_t)p->off[m] * nr;
+    for (int i = 0; i < nr; ++i) {
+      pbar_column(m, nrc, th[i], col.data());  // rows n = m .. nrc (one extra)
+      ld opx = 2 * cosl(th[i] / 2) * cosl(th[i] / 2);
+      for (int n = m; n < nrc; ++n) {
+        ld P = col[n - m];
+        ld Pm1 = (n - 1 >= m) ? col[n - 1 - m] : 0;
+        ld Pp1 = col[n + 1 - m];
+        ld T = (n + 1) * eps_nm(n, m) * Pm1 - n * eps_nm(n + 1, m) * Pp1;
+        ld Q = T - 2 * opx * P;
+        Pb[base + (size_t)(n - m) * nr + i] = (double)P;
+        Tb[base + (size_t)(n - m) * nr + i] = (double)T;
+        Pf[base + (size_t)i * K + (n - m)] = (double)(wl[i] * P);
+        Qf[base + (size_t)i * K + (n - m)] = (double)(wl[i] * Q);
+      }
+    }
+  }
+  // ---------------- Gram factors for the elliptic solves
+  GramFactors gf;
+  gf.goff.assign(M + 1, 0);
+  for (int m = 0; m < M; ++m) gf.goff[m + 1] = gf.goff[m] + std::max(nrc - m, 0);
+  p->ngram = gf.goff[M];
+  gf.g0.assign(p->ngram, 0); gf.g1.assign(p->ngram, 0); gf.g2.assign(p->ngram, 0);
+  gf.d.assign(p->ngram, 0); gf.l1.assign(p->ngram, 0); gf.l2.assign(p->ngram, 0);
+  for (int m = 0; m < M; ++m) {
+    for (int n = m; n < nrc; ++n) {
+      const int64_t k = gf.goff[m] + (n - m);
+      ld en = eps_nm(n, m), en1 = eps_nm(n + 1, m), en2 = eps_nm(n + 2, m);
+      gf.g0[k] = (double)(1 + en * en + en1 * en1);  // exact Galerkin incl. degree nrc
+      gf.g1[k] = (double)(-2 * en1);
+      gf.g2[k] = (double)(en1 * en2);
+    }
+    const int n0 = std::max(m, 1);
+    for (int n = n0; n < nrc; ++n) {
+      const int64_t k = gf.goff[m] + (n - m);
+      ld l2 = 0, l1 = 0;
+      if (n - 2 >= n0) l2 = (ld)gf.g2[k - 2] / (ld)gf.d[k - 2];
+      if (n - 1 >= n0) {
+        ld a = gf.g1[k - 1];
+        if (n - 2 >= n0) a -= l2 * (ld)gf.d[k - 2] * (ld)gf.l1[k - 1];
+        l1 = a / (ld)gf.d[k - 1];
+      }
+      ld d = gf.g0[k];
+      if (n - 1 >= n0) d -= l1 * l1 * (ld)gf.d[k - 1];
+      if (n - 2 >= n0) d -= l2 * l2 * (ld)gf.d[k - 2];
+      gf.l1[k] = (double)l1;
+      gf.l2[k] = (double)l2;
+      gf.d[k] = (double)d;
+    }
+  }
+  std::vector<double> gram(6 * (size_t)std::max<int64_t>(p->ngram, 1));
+  for (int64_t k = 0; k < p->ngram; ++k) {
+    gram[0 * p->ngram + k] = gf.g0[k];
+    gram[1 * p->ngram + k] = gf.g1[k];
+    gram[2 * p->ngram + k] = gf.g2[k];
+    gram[3 * p->ngram + k] = gf.d[k];
+    gram[4 * p->ngram + k] = gf.l1[k];
+    gram[5 * p->ngram + k] = gf.l2[k];
+  }
+  // ---------------- nodal vectors, twiddles, row orders, GEMM descriptors
+  std::vector<double> node(3 * nr);
+  for (int i = 0; i < nr; ++i) {
+    node[i] = p->rinv[i];
+    node[nr + i] = p->q[i];
+    node[2 * nr + i] = p->one_plus_x[i];
+  }
+  auto twiddles = [](int n) {
+    std::vector<double> tw(2 * n);
+    const ld pi = acosl(-1.0L);
+    for (int t = 0; t < n; ++t) {
+      ld a = -2 * pi * t / n;
+      tw[2 * t] = (double)cosl(a);
+      tw[2 * t + 1] = (double)sinl(a);
+    }
+    return tw;
+  };
+  std::vector<double> twp = twiddles(p->nphi), twz = twiddles(nz);
+  std::vector<int32_t> rowm(std::max<int64_t>(p->tau, 1));
+  for (int m = 0; m < M; ++m)
+    for (int64_t k = p->off[m]; k < p->off[m + 1]; ++k) rowm[k] = m;
+  std::vector<GemmDesc> dfwd(M), dbwd(M);
+  const int ncol = 2 * nz;
+  p->max_rows_fwd = 0;
+  p->max_rows_bwd = 0;
+  for (int m = 0; m < M; ++m) {
+    const int K = std::max(nrc - m, 0);
+    GemmDesc b{};
+    b.a_off = (int64_t)p->off[m] * nr; b.lda = nr; b.K = K; b.rows = K > 0 ? nr : 0;
+    b.b_off = (int64_t)p->off[m] * ncol; b.c_off = (int64_t)m * nr * ncol; b.m = m;
+    dbwd[m] = b;
+    GemmDesc f{};
+    f.a_off = (int64_t)p->off[m] * nr; f.lda = std::max(K, 1); f.K = K > 0 ? nr : 0; f.rows = K;
+    f.b_off = (int64_t)m * nr * ncol; f.c_off = (int64_t)p->off[m] * ncol; f.m = m;
+    dfwd[m] = f;
+    p->max_rows_fwd = std::max(p->max_rows_fwd, f.rows);
+    p->max_rows_bwd = std::max(p->max_rows_bwd, b.rows);
+  }
+  mlg_status st;
+  if ((st = upload(&p->d_Pb, Pb)) || (st = upload(&p->d_Pf, Pf)) || (st = upload(&p->d_Tb, Tb)) ||
+      (st = upload(&p->d_Qf, Qf)) || (st = upload(&p->d_node, node)) || (st = upload(&p->d_tw_phi, twp)) ||
+      (st = upload(&p->d_tw_z, twz)) || (st = upload(&p->d_row_m, rowm)) ||
+      (st = upload(&p->d_desc_fwd, dfwd)) || (st = upload(&p->d_desc_bwd, dbwd)) ||
+      (st = upload(&p->d_gram, gram)) || (st = upload(&p->d_goff, gf.goff)))
+    return st;
+  // ---------------- workspace: 7 mixed + 5 triangular + solve scratch (5 reals per column and degree)
+  p->mixed_elems = (size_t)M * nr * nz;
+  p->tri_elems = (size_t)p->tau * nz;
+  const size_t scratch = (size_t)5 * nrc * M * nz;
+  p->ws_bytes = (7 * p->mixed_elems * 2 + 5 * p->tri_elems * 2 + scratch) * sizeof(double) + 1024;
+  return MLG_OK;
+}
+
+void destroy_plan(mlg_plan_s* p) {
+  if (!p) return;
+  free_plan_device(p);
+  delete p;
+}
+
+}  // namespace mlg
