@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain device copy of 256 MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build "
@@ -94,6 +96,13 @@ def main():
         sys.exit(2)
     import torch
     from paper_2609_18026_amd import Plan, mlg_timing_enable, mlg_timing_read
+    if args.calibrate_copy:
+        src = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")  # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: calibration copy of 268435456 bytes x3 done")
     n = args.n
     plan = Plan(n, n, n, 1.0, PAIR["lz"], dealias=1)
     log(f"bench: plan {n}^3 ready, workspace {plan.layout.workspace_bytes / 2**30:.2f} GiB")
