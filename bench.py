@@ -35,9 +35,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def gemm_flops(nr, nrc, M, nz, nprod):
-    """Algorithmic flops of nprod radial products: sum_m 2 * N_r * (N_r^c - m) * (2 N_z) real columns."""
-    return nprod * sum(2.0 * nr * max(nrc - m, 0) * 2 * nz for m in range(M))
+def active_columns(nphi, nz, M, nrc, dealias=True):
+    """Orders and k slots the projection computes: m < mmax, |k| <= kmax (two-thirds mask)."""
+    kmax = min(max(nz // 2, 1) - 1, nz // 2 - 1) if nz > 1 else 0
+    mmax = min(M, nrc)
+    if dealias:
+        kmax = min(kmax, (nz - 1) // 3)
+        mmax = min(mmax, (nphi - 1) // 3 + 1)
+    nkact = 1 if nz == 1 else 2 * kmax + 1
+    return mmax, nkact
+
+
+def kernel_work(nr, nphi, nz, M, nrc):
+    """Algorithmic flops / HBM bytes per RHS step for each kernel family (FP64)."""
+    tau = sum(max(nrc - m, 0) for m in range(M))
+    mmax, nkact = active_columns(nphi, nz, M, nrc)
+    tau_a = sum(max(nrc - m, 0) for m in range(mmax))
+    mixed = M * nr * nz * 16                     # one harmonic field, complex
+    w = {}
+    w["synth_gemm"] = dict(flops=7 * 2.0 * nr * tau * 2 * nz,
+                           bytes=2 * tau * nr * 8 + 2 * tau * nz * 16 + 6 * mixed)
+    w["proj_gemm"] = dict(flops=5 * 2.0 * nr * tau_a * 2 * nkact,
+                          bytes=2 * tau_a * nr * 8 + 3 * mmax * nr * nkact * 16 + 3 * tau_a * nkact * 16)
+    w["phi_fft"] = dict(flops=None, bytes=9 * mixed)
+    w["z_fft"] = dict(flops=None, bytes=6 * 2 * mixed + 3 * 2 * mmax * nr * nz * 16)
+    w["projection"] = dict(flops=None, bytes=3 * tau_a * nkact * 16 + 2 * tau * nz * 16)
+    return w
 
 
 def build_state(plan, n, torch):
@@ -112,9 +135,9 @@ def main():
         plan.rhs_tp(psi, chi, po, co, U=U_FRAME)
     torch.cuda.synchronize()
     log("bench: warmup done")
-    families = ["radial_gemm", "phi_fft", "z_fft", "vec_epilogue", "projection"]
+    families = ["synth_gemm", "proj_gemm", "phi_fft", "z_fft", "projection"]
     mlg_timing_enable(plan.handle, True)
-    for f in families:
+    for f in families + ["radial_gemm", "mask"]:
         mlg_timing_read(plan.handle, f)
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -132,15 +155,32 @@ def main():
     mlg_timing_enable(plan.handle, False)
     log(f"bench: {ms:.3f} ms/step (wall {wall / args.steps * 1e3:.3f})")
     value = n ** 3 / (ms / 1e3) / 1e9
-    M, nrc = plan.layout.M, plan.layout.nrc
-    flops_step = gemm_flops(n, nrc, M, n, 12)
-    gemm_ms, gemm_launches = kern["radial_gemm"]
-    per_launch_ms = gemm_ms / max(gemm_launches, 1)
-    achieved = flops_step * args.steps / (gemm_ms / 1e3) / 1e12
-    roofline = dict(bound="mfma", kernel="radial_gemm_f64", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS,
-                    unit="TFLOP/s", frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=None,
-                    flops_per_launch=flops_step / 2, avg_launch_ms=round(per_launch_ms, 4))
-    breakdown = {f: round(kern[f][0] / args.steps, 4) for f in families}
+    work = kernel_work(n, n, n, plan.layout.M, plan.layout.nrc)
+    per_kernel = {}
+    for f in families:
+        tot_ms, launches = kern[f]
+        step_ms = tot_ms / args.steps
+        wk = work[f]
+        ent = {"ms_per_step": round(step_ms, 4), "launches_per_step": launches / args.steps,
+               "avg_launch_ms": round(tot_ms / max(launches, 1), 4)}
+        if wk["flops"]:
+            ent["tflops"] = round(wk["flops"] / (step_ms / 1e3) / 1e12, 3)
+            ent["frac_fp64_peak"] = round(ent["tflops"] / PEAK_FP64_TFLOPS, 4)
+        ent["gbs"] = round(wk["bytes"] / (step_ms / 1e3) / 1e9, 1)
+        ent["frac_hbm_peak"] = round(ent["gbs"] / PEAK_HBM_GBS, 4)
+        per_kernel[f] = ent
+    dom = max(families, key=lambda f: kern[f][0])
+    d = per_kernel[dom]
+    if work[dom]["flops"]:
+        launches = max(kern[dom][1], 1)
+        roofline = dict(bound="mfma", kernel=dom, achieved=d["tflops"], peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                        frac=d["frac_fp64_peak"], traffic=None,
+                        work_per_launch=work[dom]["flops"] * args.steps / launches, avg_launch_ms=d["avg_launch_ms"])
+    else:
+        launches = max(kern[dom][1], 1)
+        roofline = dict(bound="hbm", kernel=dom, achieved=d["gbs"], peak=PEAK_HBM_GBS, unit="GB/s",
+                        frac=d["frac_hbm_peak"], traffic=None,
+                        work_per_launch=work[dom]["bytes"] * args.steps / launches, avg_launch_ms=d["avg_launch_ms"])
     # transform pair of one scalar on the same plan (extra figure)
     phys = plan.empty_phys()
     spec = plan.empty_spec()
@@ -161,7 +201,7 @@ def main():
                                f"pair at N_r=N_phi=N_z={n}, ell=1, L_z=8.6, two-thirds dealiasing, FP64",
                    "nr": n, "nphi": n, "nz": n, "ell": 1.0, "lz": PAIR["lz"], "U": list(U_FRAME)},
         "roofline": roofline,
-        "kernel_ms_per_step": breakdown,
+        "kernels": per_kernel,
         "transform_pair": {"ms": round(pair_ms, 4), "gdofs": round(n ** 3 / (pair_ms / 1e3) / 1e9, 4)},
     }
     if not args.no_cpu_baseline:

@@ -131,7 +131,7 @@ mlg_status mlg_rhs_scalar(mlg_plan plan, int kind, double gamma, const void* spe
  * supported).  'taps' may be NULL; otherwise a device buffer of
  * 9 * phys_elems + 3 * spec_elems values (reals, then complex) receiving nodal
  * u_r, u_phi, u_z, w_r, w_phi, w_z, N_r, N_phi, N_z and the sources C, K, Zhat.
- * Requires N_r^c = N_r. */
+ * Requires N_r^c = N_r <= 512 (MLG_E_UNSUPPORTED otherwise). */
 mlg_status mlg_rhs_tp(mlg_plan plan, const double* U, const void* psi, const void* chi,
                       void* psi_n, void* chi_n, void* taps, void* ws, void* stream);
 
@@ -139,7 +139,7 @@ mlg_status mlg_rhs_tp(mlg_plan plan, const double* U, const void* psi, const voi
  * While enabled, every kernel launch of the plan is bracketed by two HIP events recorded on
  * the launch's stream.  mlg_timing_read waits for the recorded events, returns the summed
  * elapsed milliseconds and the launch count for kernel family 'kernel' ("radial_gemm",
- * "phi_fft", "z_fft", "vec_epilogue", "projection", "mask"), and clears that family's
+ * "synth_gemm", "proj_gemm", "phi_fft", "z_fft", "projection", "mask"), and clears that family's
  * records.  Reading an unknown family returns 0 ms and 0 launches. */
 mlg_status mlg_timing_enable(mlg_plan plan, int enable);
 mlg_status mlg_timing_read(mlg_plan plan, const char* kernel, double* total_ms, int64_t* launches);

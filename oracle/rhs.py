@@ -169,7 +169,7 @@ def projection_sources(Nr_, Np_, Nz_, g: Grid, vt: VecTables):
     C = np.zeros((g.M, g.nrc, g.nz), dtype=np.complex128)
     K = np.zeros_like(C)
     Z = np.zeros_like(C)
-    for m in range(g.M):
+    for m in range(min(g.M, g.nrc)):   # orders m >= N_r^c have no coefficients
         WP = vt.P[m] * g.w[None, :]
         WQ = vt.Q[m] * g.w[None, :]
         Pa, Qa = WP @ a[m], WQ @ a[m]
@@ -199,7 +199,7 @@ def solve_projection(C, K, Z, g: Grid, dealias: bool = True):
     mask = dealias_mask(g) if dealias else np.ones((g.M, g.nz), bool) & keep[None, :]
     psi = np.zeros_like(C)
     chi = np.zeros_like(C)
-    for m in range(g.M):
+    for m in range(min(g.M, g.nrc)):
         cols = np.nonzero(mask[m] & keep)[0]
         if cols.size == 0:
             continue

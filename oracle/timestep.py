@@ -35,7 +35,7 @@ class Dissipation:
         self.g = g
         kap = g.kappa()
         self.L = {}
-        for m in range(g.M):
+        for m in range(min(g.M, g.nrc)):
             D = laplacian_matrix(m, g.nrc, g.ell)
             eye = np.eye(D.shape[0])
             for kk in range(g.nz):

@@ -223,6 +223,7 @@ mlg_status mlg_rhs_tp(mlg_plan p, const double* U, const void* psi, const void* 
   if (psi_n == chi_n || psi_n == psi || psi_n == chi || chi_n == psi || chi_n == chi)
     return fail(MLG_E_ARG, "outputs must not alias each other or the inputs");
   if (p->nrc != p->nr) return fail(MLG_E_UNSUPPORTED, "mlg_rhs_tp requires N_r^c = N_r");
+  if (p->nrc > 512) return fail(MLG_E_UNSUPPORTED, "mlg_rhs_tp supports N_r up to 512");
   double Uh[3] = {0.0, 0.0, 0.0};
   if (U) {
     for (int i = 0; i < 3; ++i) {
@@ -234,50 +235,29 @@ mlg_status mlg_rhs_tp(mlg_plan p, const double* U, const void* psi, const void* 
   hipStream_t s = static_cast<hipStream_t>(stream);
   Ws w = partition(p, ws);
   mlg_status st;
-  const int ncol = 2 * p->nz;
-  // 1. radial synthesis of the seven products (k stays spectral)
-  GemmProds pr{};
-  const double* ps = static_cast<const double*>(psi);
-  const double* cs = static_cast<const double*>(chi);
-  const double* tabs[7] = {p->d_Pb, p->d_Tb, p->d_Pb, p->d_Pb, p->d_Tb, p->d_Pb, p->d_Tb};
-  const double* ins[7] = {ps, ps, ps, cs, cs, cs, cs};
-  const int lsc[7] = {0, 0, 1, 0, 0, 1, 1};
-  pr.nprod = 7;
-  for (int i = 0; i < 7; ++i) {
-    pr.A[i] = tabs[i];
-    pr.B[i] = ins[i];
-    pr.C[i] = w.X[i];
-    pr.lscale[i] = lsc[i];
-  }
-  if ((st = launch_gemm(p, pr, p->d_desc_bwd, p->max_rows_bwd, ncol, s))) return st;
-  // 2. velocity and vorticity harmonics
-  if ((st = launch_vec_epilogue(p, w.X, s))) return st;
-  // 3. inverse z transforms of the six fields
+  // 1. radial synthesis: the six velocity / vorticity harmonics (k spectral), fused
+  if ((st = launch_synth_gemm(p, static_cast<const double*>(psi), static_cast<const double*>(chi), w.X, s)))
+    return st;
+  // 2. inverse z transforms of the six fields
   const int64_t mrows = (int64_t)p->M * p->nr;
   for (int i = 0; i < 6; ++i)
     if ((st = launch_zfft(p, w.X[i], w.X[i], mrows, +1, nullptr, 0, 0, s))) return st;
-  // 4. phi stage: nodal u, w -> N = (U + u) x w -> harmonics of N_r/r, N_phi/r, N_z
+  // 3. phi stage: nodal u, w -> N = (U + u) x w -> harmonics of N_r/r, N_phi/r, N_z
   double* tp = static_cast<double*>(taps);
   if ((st = launch_phi_vec_rhs(p, Uh, w.X, tp, s))) return st;
-  // 5. forward z transforms
+  // 4. forward z transforms of the orders the projection uses
+  int mmax, kmax;
+  active_columns(p, &mmax, &kmax);
+  const int64_t frows = (int64_t)mmax * p->nr;
   for (int i = 0; i < 3; ++i)
-    if ((st = launch_zfft(p, w.X[i], w.X[i], mrows, -1, nullptr, 0, 0, s))) return st;
-  // 6. Galerkin projections onto Pbar and Q = T - 2(1+x) Pbar
-  const double* ftab[5] = {p->d_Pf, p->d_Qf, p->d_Pf, p->d_Qf, p->d_Pf};
-  const double* fin[5] = {w.X[0], w.X[0], w.X[1], w.X[1], w.X[2]};
-  GemmProds pf{};
-  pf.nprod = 5;
-  for (int i = 0; i < 5; ++i) {
-    pf.A[i] = ftab[i];
-    pf.B[i] = fin[i];
-    pf.C[i] = w.T[i];
-    pf.lscale[i] = 0;
-  }
-  if ((st = launch_gemm(p, pf, p->d_desc_fwd, p->max_rows_fwd, ncol, s))) return st;
-  // 7. elliptic solves per (m, k)
-  const double* src5[5] = {w.T[0], w.T[1], w.T[2], w.T[3], w.T[4]};
+    if ((st = launch_zfft(p, w.X[i], w.X[i], frows, -1, nullptr, 0, 0, s))) return st;
+  // 5. Galerkin projections onto Pbar and Q = T - 2(1+x) Pbar with the C, K', Zhat epilogue
+  double* src3[3] = {w.T[0], w.T[1], w.T[2]};
+  if ((st = launch_proj_gemm(p, w.X, src3, mmax, kmax, s))) return st;
+  // 6. elliptic solves per (m, k)
+  const double* csrc[3] = {w.T[0], w.T[1], w.T[2]};
   double* tsrc = tp ? tp + (size_t)9 * p->nz * p->nr * p->nphi : nullptr;
-  return launch_projection(p, src5, static_cast<double*>(psi_n), static_cast<double*>(chi_n), w.scratch, tsrc, s);
+  return launch_projection(p, csrc, static_cast<double*>(psi_n), static_cast<double*>(chi_n), w.scratch, tsrc, s);
 }
 
 mlg_status mlg_timing_enable(mlg_plan p, int enable) {

@@ -1,0 +1,478 @@
+// 256-point FFTs for gfx950 held in registers: 16 threads per line, each owning the 16 samples
+// x[s + 16 j] (s = thread index within the line, j = 0..15).  A four-step 16 x 16 factorisation
+// does a 16-point DFT in registers, a twiddle, one LDS exchange, and a second 16-point DFT,
+// which leaves X[s + 16 k] in the same registers: input and output share one distribution, so
+// inverse -> pointwise -> forward chains need no reshuffle.  LDS rows are padded to 17 so that
+// both exchange patterns are free of bank conflicts.
+//
+// Kernels: z transforms over contiguous lines (global loads go straight to registers, 16
+// consecutive samples per 16 lanes) and the azimuthal stages (harmonics of 8 lines are gathered
+// through LDS so that every global access covers 8 consecutive lines = 128 bytes).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "dev_common.h"
+#include "mlg_internal.h"
+
+namespace mlg {
+namespace {
+
+using namespace ::mlg::dev;
+
+constexpr double kC1 = 0.92387953251128674;   // cos(pi/8)
+constexpr double kS1 = 0.38268343236508976;   // sin(pi/8)
+constexpr double kR2 = 0.70710678118654752;   // sqrt(2)/2
+
+// multiply by w16^j, w16 = exp(-+ 2 pi i / 16) (forward: minus), for the j used by dft16
+template <bool INV, int J>
+__device__ __forceinline__ double2 tw16(double2 a) {
+  constexpr double sg = INV ? 1.0 : -1.0;
+  if constexpr (J == 0) return a;
+  else if constexpr (J == 1) return cmul(a, make_double2(kC1, sg * kS1));
+  else if constexpr (J == 2) return cmul(a, make_double2(kR2, sg * kR2));
+  else if constexpr (J == 3) return cmul(a, make_double2(kS1, sg * kC1));
+  else if constexpr (J == 4) return cmul_mi(a, INV);
+  else if constexpr (J == 6) return cmul(a, make_double2(-kR2, sg * kR2));
+  else return cmul(a, make_double2(-kC1, -sg * kS1));  // J == 9
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(double2& a, double2& b, double2& c, double2& d) {
+  const double2 t0 = cadd(a, c), t1 = csub(a, c);
+  const double2 t2 = cadd(b, d), t3 = cmul_mi(csub(b, d), INV);
+  a = cadd(t0, t2);
+  b = cadd(t1, t3);
+  c = csub(t0, t2);
+  d = csub(t1, t3);
+}
+
+// In-register 16-point DFT: v[n] -> V[k] = sum_n v[n] w16^(n k).
+template <bool INV>
+__device__ __forceinline__ void dft16(double2 (&v)[16]) {
+  // n = n1 + 4 n2: DFT4 over n2 for each n1 -> Y[n1][k2] at v[n1 + 4 k2]
+#pragma unroll
+  for (int n1 = 0; n1 < 4; ++n1) dft4<INV>(v[n1], v[n1 + 4], v[n1 + 8], v[n1 + 12]);
+  // twiddles w16^(n1 k2)
+  v[1 + 4 * 1] = tw16<INV, 1>(v[1 + 4 * 1]);
+  v[1 + 4 * 2] = tw16<INV, 2>(v[1 + 4 * 2]);
+  v[1 + 4 * 3] = tw16<INV, 3>(v[1 + 4 * 3]);
+  v[2 + 4 * 1] = tw16<INV, 2>(v[2 + 4 * 1]);
+  v[2 + 4 * 2] = tw16<INV, 4>(v[2 + 4 * 2]);
+  v[2 + 4 * 3] = tw16<INV, 6>(v[2 + 4 * 3]);
+  v[3 + 4 * 1] = tw16<INV, 3>(v[3 + 4 * 1]);
+  v[3 + 4 * 2] = tw16<INV, 6>(v[3 + 4 * 2]);
+  v[3 + 4 * 3] = tw16<INV, 9>(v[3 + 4 * 3]);
+  // DFT4 over n1 for each k2 -> X[k2 + 4 k1] at v[4 k2 + k1]
+#pragma unroll
+  for (int k2 = 0; k2 < 4; ++k2) dft4<INV>(v[4 * k2], v[4 * k2 + 1], v[4 * k2 + 2], v[4 * k2 + 3]);
+  double2 o[16];
+#pragma unroll
+  for (int k2 = 0; k2 < 4; ++k2)
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) o[k2 + 4 * k1] = v[4 * k2 + k1];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = o[k];
+}
+
+// 256-point DFT of one line spread over 16 threads.  On entry v[j] = x[s + 16 j]; on exit
+// v[k] = X[s + 16 k] (unscaled).  Z is this line's LDS row block (16 x 17 complex).  Contains
+// one barrier: all threads of the block must call it.
+template <bool INV>
+__device__ __forceinline__ void fft256(double2 (&v)[16], double2* Z, int s, const double2* __restrict__ tw) {
+  dft16<INV>(v);  // over j: v[k2] = Y[s][k2]
+#pragma unroll
+  for (int k2 = 1; k2 < 16; ++k2) {
+    double2 w = tw[s * k2];
+    if (INV) w = cconj(w);
+    v[k2] = cmul(v[k2], w);
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) Z[s + 17 * k2] = v[k2];
+  __syncthreads();
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) v[n1] = Z[n1 + 17 * s];
+  dft16<INV>(v);
+}
+
+__device__ __forceinline__ int kval(int kk, int nz) { return (2 * kk < nz) ? kk : kk - nz; }
+__device__ __forceinline__ bool kkept(int kk, int nz, int nzc) {
+  const int k = kval(kk, nz);
+  if (nz % 2 == 0 && nz > 1 && k == -(nz / 2)) return false;
+  return (k < 0 ? -k : k) < nzc;
+}
+
+constexpr int ZL = 8;  // lines per block (128 threads)
+
+template <bool INV>
+__global__ __launch_bounds__(128) void zfft256_kernel(const double2* __restrict__ tw, const double2* in,
+                                                      double2* out, int64_t rows, int nzc,
+                                                      const int32_t* __restrict__ row_m, int mask_m,
+                                                      int mask_k) {
+  __shared__ double2 Zs[ZL][16 * 17];
+  const int t = threadIdx.x, ll = t >> 4, s = t & 15;
+  const int64_t row = (int64_t)blockIdx.x * ZL + ll;
+  const bool valid = row < rows;
+  double2 v[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int kk = s + 16 * j;
+    double2 a = make_double2(0.0, 0.0);
+    if (valid) a = in[row * 256 + kk];
+    if (INV && !kkept(kk, 256, nzc)) a = make_double2(0.0, 0.0);
+    v[j] = a;
+  }
+  fft256<INV>(v, Zs[ll], s, tw);
+  if (!valid) return;
+  const int mrow = (!INV && row_m) ? row_m[row] : 0;
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) {
+    const int kk = s + 16 * k1;
+    double2 a = v[k1];
+    if (!INV) {
+      a = cscale(a, 1.0 / 256.0);
+      bool keep = kkept(kk, 256, nzc);
+      if (row_m) {
+        const int k = kval(kk, 256);
+        keep = keep && mrow <= mask_m && (k < 0 ? -k : k) <= mask_k;
+      }
+      if (!keep) a = make_double2(0.0, 0.0);
+    }
+    out[row * 256 + kk] = a;
+  }
+}
+
+// ---------------------------------------------------------------- azimuthal stages
+// Line q = i N_z + l; physical samples at (l N_r + i) 256 + j; harmonic m at m * nlines + q.
+constexpr int PL = 8;  // lines per block (128 threads, 16 per line)
+
+struct Phi256 {
+  int nr, nz, M, mkeep;
+  int64_t nlines;
+};
+
+__device__ __forceinline__ int64_t phys_off(const Phi256& g, int64_t q) {
+  const int64_t i = q / g.nz;
+  const int64_t l = q - i * g.nz;
+  return (l * g.nr + i) * 256;
+}
+
+// Gather the harmonics of fields (fa, fb) for the block's lines into Z as the Hermitian
+// spectrum of z = a + i b (orders m < M, the rest zero).  Ends with a barrier.
+__device__ __forceinline__ void gather_pair(double2 (*Z)[16 * 17], const Phi256& g, int64_t q0,
+                                            const double2* __restrict__ fa, const double2* __restrict__ fb) {
+  const int t = threadIdx.x;
+  for (int e = t; e < PL * 256; e += 128) {
+    const int ll = e & (PL - 1), p = e >> 3;  // zero-fill all 256 positions
+    Z[ll][(p & 15) + 17 * (p >> 4)] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const int mmax = g.M < 128 ? g.M : 128;
+  for (int e = t; e < PL * mmax; e += 128) {
+    const int ll = e & (PL - 1), m = e >> 3;
+    const int64_t q = q0 + ll;
+    if (q >= g.nlines) continue;
+    const double2 a = fa[(int64_t)m * g.nlines + q];
+    const double2 b = fb ? fb[(int64_t)m * g.nlines + q] : make_double2(0.0, 0.0);
+    if (m == 0) {
+      Z[ll][0] = make_double2(a.x, b.x);
+    } else {
+      Z[ll][(m & 15) + 17 * (m >> 4)] = make_double2(a.x - b.y, a.y + b.x);
+      const int mm = 256 - m;
+      Z[ll][(mm & 15) + 17 * (mm >> 4)] = make_double2(a.x + b.y, -a.y + b.x);
+    }
+  }
+  __syncthreads();
+}
+
+// Scatter the spectrum X (registers, X[s + 16 k]) of z = a + i b to harmonics of a and b
+// (orders m < M, scaled by 1/256; orders above mkeep written as zero).  Uses Z; contains barriers.
+__device__ __forceinline__ void scatter_pair(double2 (&v)[16], double2 (*Z)[16 * 17], const Phi256& g, int64_t q0,
+                                             int ll, int s, double2* fa, double2* fb) {
+  __syncthreads();  // the fft's LDS reads are complete
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) Z[ll][s + 17 * k1] = v[k1];
+  __syncthreads();
+  const int t = threadIdx.x;
+  const int mmax = g.M < 128 ? g.M : 128;
+  for (int e = t; e < PL * g.M; e += 128) {
+    const int l2 = e & (PL - 1), m = e >> 3;
+    const int64_t q = q0 + l2;
+    if (q >= g.nlines) continue;
+    double2 A = make_double2(0.0, 0.0), B = A;
+    if (m < mmax && m <= g.mkeep) {
+      const double2 zm = Z[l2][(m & 15) + 17 * (m >> 4)];
+      const int mm = (256 - m) & 255;
+      const double2 zc = cconj(Z[l2][(mm & 15) + 17 * (mm >> 4)]);
+      A = cscale(cadd(zm, zc), 0.5 / 256.0);
+      const double2 d = csub(zm, zc);
+      B = make_double2(0.5 / 256.0 * d.y, -0.5 / 256.0 * d.x);
+    }
+    fa[(int64_t)m * g.nlines + q] = A;
+    if (fb) fb[(int64_t)m * g.nlines + q] = B;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(128) void phi_fwd256_kernel(Phi256 g, const double2* __restrict__ tw,
+                                                         const double* __restrict__ phys, double2* mixed) {
+  __shared__ double2 Z[PL][16 * 17];
+  const int t = threadIdx.x, ll = t >> 4, s = t & 15;
+  const int64_t q0 = (int64_t)blockIdx.x * PL;
+  // pairs of lines: line 2p in the real part, 2p+1 in the imaginary part; thread group ll
+  // handles the pair (ll & ~1, ll | 1) as one complex line only for even ll
+  const int64_t qa = q0 + (ll & ~1), qb = qa + 1;
+  double2 v[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const double a = (qa < g.nlines) ? phys[phys_off(g, qa) + s + 16 * j] : 0.0;
+    const double b = (qb < g.nlines) ? phys[phys_off(g, qb) + s + 16 * j] : 0.0;
+    v[j] = make_double2(a, b);
+  }
+  fft256<false>(v, Z[ll], s, tw);
+  // groups with odd ll computed the same pair; only even groups write their spectra
+  __syncthreads();
+  if ((ll & 1) == 0) {
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) Z[ll][s + 17 * k1] = v[k1];
+  }
+  __syncthreads();
+  for (int e = t; e < PL * g.M; e += 128) {
+    const int l2 = e & (PL - 1), m = e >> 3;
+    const int64_t q = q0 + l2;
+    if (q >= g.nlines) continue;
+    double2 r = make_double2(0.0, 0.0);
+    if (m < 128 && m <= g.mkeep) {
+      const double2* Zp = Z[l2 & ~1];
+      const double2 zm = Zp[(m & 15) + 17 * (m >> 4)];
+      const int mm = (256 - m) & 255;
+      const double2 zc = cconj(Zp[(mm & 15) + 17 * (mm >> 4)]);
+      if ((l2 & 1) == 0) {
+        r = cscale(cadd(zm, zc), 0.5 / 256.0);
+      } else {
+        const double2 d = csub(zm, zc);
+        r = make_double2(0.5 / 256.0 * d.y, -0.5 / 256.0 * d.x);
+      }
+    }
+    mixed[(int64_t)m * g.nlines + q] = r;
+  }
+}
+
+__global__ __launch_bounds__(128) void phi_bwd256_kernel(Phi256 g, const double2* __restrict__ tw,
+                                                         const double2* __restrict__ mixed, double* phys) {
+  __shared__ double2 Z[PL][16 * 17];
+  const int t = threadIdx.x, ll = t >> 4, s = t & 15;
+  const int64_t q0 = (int64_t)blockIdx.x * PL;
+  // pack line pairs (2p, 2p+1) into one complex spectrum stored at Z[2p]
+  for (int e = t; e < PL * 256; e += 128) {
+    const int l2 = e & (PL - 1), p = e >> 3;
+    Z[l2][(p & 15) + 17 * (p >> 4)] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const int mmax = g.M < 128 ? g.M : 128;
+  for (int e = t; e < (PL / 2) * mmax; e += 128) {
+    const int pr = e & (PL / 2 - 1), m = e >> 2;
+    const int64_t qa = q0 + 2 * pr, qb = qa + 1;
+    const double2 a = (qa < g.nlines) ? mixed[(int64_t)m * g.nlines + qa] : make_double2(0.0, 0.0);
+    const double2 b = (qb < g.nlines) ? mixed[(int64_t)m * g.nlines + qb] : make_double2(0.0, 0.0);
+    double2* Zp = Z[2 * pr];
+    if (m == 0) {
+      Zp[0] = make_double2(a.x, b.x);
+    } else {
+      Zp[(m & 15) + 17 * (m >> 4)] = make_double2(a.x - b.y, a.y + b.x);
+      const int mm = 256 - m;
+      Zp[(mm & 15) + 17 * (mm >> 4)] = make_double2(a.x + b.y, -a.y + b.x);
+    }
+  }
+  __syncthreads();
+  double2 v[16];
+  const double2* Zsrc = Z[ll & ~1];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = Zsrc[s + 17 * j];
+  __syncthreads();  // odd groups read the even row before any group overwrites its own row
+  fft256<true>(v, Z[ll], s, tw);
+  const int64_t q = q0 + ll;
+  if (q < g.nlines) {
+    const bool imag = (ll & 1) != 0;
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) phys[phys_off(g, q) + s + 16 * k1] = imag ? v[k1].y : v[k1].x;
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(128) void phi_scalar256_kernel(Phi256 g, const double2* __restrict__ tw, double2* mixed,
+                                                            double gamma) {
+  __shared__ double2 Z[PL][16 * 17];
+  const int t = threadIdx.x, ll = t >> 4, s = t & 15;
+  const int64_t q0 = (int64_t)blockIdx.x * PL;
+  (void)t;
+  // each line is transformed on its own (imaginary part zero): u = B(u_hat), g(u), F(g)
+  gather_pair(Z, g, q0, mixed, nullptr);  // fb == null -> b = 0
+  // gather_pair packed each line ll into Z[ll] as a + i*0 -- with fb null the layout per line is correct
+  double2 v[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = Z[ll][s + 17 * j];
+  __syncthreads();
+  fft256<true>(v, Z[ll], s, tw);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const double u = v[k].x;
+    const double r = (MODE == MLG_RHS_U2) ? u * u : gamma * u * (1.0 - u);
+    v[k] = make_double2(r, 0.0);
+  }
+  __syncthreads();
+  fft256<false>(v, Z[ll], s, tw);
+  scatter_pair(v, Z, g, q0, ll, s, mixed, nullptr);
+}
+
+struct Six256 {
+  double2* f[6];
+};
+
+__global__ __launch_bounds__(128) void phi_vec256_kernel(Phi256 g, const double2* __restrict__ tw, Six256 fs,
+                                                         const double* __restrict__ rinv, double Ux, double Uy,
+                                                         double Uz, double* __restrict__ taps) {
+  __shared__ double2 Z[PL][16 * 17];
+  const int t = threadIdx.x, ll = t >> 4, s = t & 15;
+  (void)t;
+  const int64_t q0 = (int64_t)blockIdx.x * PL;
+  const int64_t q = q0 + ll;
+  double2 v[16];
+  double ur[16], up[16], uz[16], wr[16];
+  // pair 0: (u_r, u_phi)
+  gather_pair(Z, g, q0, fs.f[0], fs.f[1]);
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = Z[ll][s + 17 * j];
+  __syncthreads();
+  fft256<true>(v, Z[ll], s, tw);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) { ur[k] = v[k].x; up[k] = v[k].y; }
+  __syncthreads();
+  // pair 1: (u_z, w_r)
+  gather_pair(Z, g, q0, fs.f[2], fs.f[3]);
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = Z[ll][s + 17 * j];
+  __syncthreads();
+  fft256<true>(v, Z[ll], s, tw);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) { uz[k] = v[k].x; wr[k] = v[k].y; }
+  __syncthreads();
+  // pair 2: (w_phi, w_z)
+  gather_pair(Z, g, q0, fs.f[4], fs.f[5]);
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = Z[ll][s + 17 * j];
+  __syncthreads();
+  fft256<true>(v, Z[ll], s, tw);
+  // nodal cross product at phi_j, j = s + 16 k: cos(phi_j) = tw[j].x, sin(phi_j) = -tw[j].y
+  const bool valid = q < g.nlines;
+  const double ri = valid ? rinv[q / g.nz] : 0.0;
+  const int64_t pe = g.nlines * 256;
+  double2 nz_[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int j = s + 16 * k;
+    const double2 c = tw[j];
+    const double cphi = c.x, sphi = -c.y;
+    const double wp = v[k].x, wz = v[k].y;
+    const double Ur = ur[k] + Ux * cphi + Uy * sphi;
+    const double Up = up[k] - Ux * sphi + Uy * cphi;
+    const double Uzz = uz[k] + Uz;
+    const double Nr = Up * wz - Uzz * wp;
+    const double Np = Uzz * wr[k] - Ur * wz;
+    const double Nz = Ur * wp - Up * wr[k];
+    if (taps != nullptr && valid) {
+      const int64_t o = phys_off(g, q) + j;
+      taps[0 * pe + o] = ur[k]; taps[1 * pe + o] = up[k]; taps[2 * pe + o] = uz[k];
+      taps[3 * pe + o] = wr[k]; taps[4 * pe + o] = wp; taps[5 * pe + o] = wz;
+      taps[6 * pe + o] = Nr; taps[7 * pe + o] = Np; taps[8 * pe + o] = Nz;
+    }
+    v[k] = make_double2(Nr * ri, Np * ri);
+    nz_[k] = make_double2(Nz, 0.0);
+  }
+  __syncthreads();
+  fft256<false>(v, Z[ll], s, tw);
+  scatter_pair(v, Z, g, q0, ll, s, fs.f[0], fs.f[1]);
+  fft256<false>(nz_, Z[ll], s, tw);
+  scatter_pair(nz_, Z, g, q0, ll, s, fs.f[2], nullptr);
+}
+
+Phi256 phi256_geom(const mlg_plan_s* p, bool masked) {
+  Phi256 g{};
+  g.nr = p->nr;
+  g.nz = p->nz;
+  g.M = p->M;
+  g.mkeep = masked ? p->dealias_m : (1 << 30);
+  g.nlines = (int64_t)p->nr * p->nz;
+  return g;
+}
+
+mlg_status check(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(MLG_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return MLG_OK;
+}
+
+}  // namespace
+
+mlg_status launch_zfft256(const mlg_plan_s* p, const double* in, double* out, int64_t rows, int dir,
+                          const int32_t* row_m, int mask_m, int mask_k, hipStream_t s) {
+  const double2* tw = reinterpret_cast<const double2*>(p->d_tw_z);
+  dim3 grid((unsigned)((rows + ZL - 1) / ZL));
+  p->timing.begin("z_fft", s);
+  if (dir > 0)
+    zfft256_kernel<true><<<grid, 128, 0, s>>>(tw, reinterpret_cast<const double2*>(in), reinterpret_cast<double2*>(out),
+                                              rows, p->nzc, nullptr, 0, 0);
+  else
+    zfft256_kernel<false><<<grid, 128, 0, s>>>(tw, reinterpret_cast<const double2*>(in),
+                                               reinterpret_cast<double2*>(out), rows, p->nzc, row_m, mask_m, mask_k);
+  p->timing.end(s);
+  return check("zfft256_kernel");
+}
+
+mlg_status launch_phi256_forward(const mlg_plan_s* p, const double* phys, double* mixed, hipStream_t s) {
+  Phi256 g = phi256_geom(p, false);
+  dim3 grid((unsigned)((g.nlines + PL - 1) / PL));
+  p->timing.begin("phi_fft", s);
+  phi_fwd256_kernel<<<grid, 128, 0, s>>>(g, reinterpret_cast<const double2*>(p->d_tw_phi), phys,
+                                         reinterpret_cast<double2*>(mixed));
+  p->timing.end(s);
+  return check("phi_fwd256_kernel");
+}
+
+mlg_status launch_phi256_backward(const mlg_plan_s* p, const double* mixed, double* phys, hipStream_t s) {
+  Phi256 g = phi256_geom(p, false);
+  dim3 grid((unsigned)((g.nlines + PL - 1) / PL));
+  p->timing.begin("phi_fft", s);
+  phi_bwd256_kernel<<<grid, 128, 0, s>>>(g, reinterpret_cast<const double2*>(p->d_tw_phi),
+                                         reinterpret_cast<const double2*>(mixed), phys);
+  p->timing.end(s);
+  return check("phi_bwd256_kernel");
+}
+
+mlg_status launch_phi256_scalar(const mlg_plan_s* p, int kind, double gamma, double* mixed, hipStream_t s) {
+  Phi256 g = phi256_geom(p, p->g.dealias != 0);
+  dim3 grid((unsigned)((g.nlines + PL - 1) / PL));
+  const double2* tw = reinterpret_cast<const double2*>(p->d_tw_phi);
+  p->timing.begin("phi_fft", s);
+  if (kind == MLG_RHS_U2)
+    phi_scalar256_kernel<MLG_RHS_U2><<<grid, 128, 0, s>>>(g, tw, reinterpret_cast<double2*>(mixed), gamma);
+  else
+    phi_scalar256_kernel<MLG_RHS_KPP><<<grid, 128, 0, s>>>(g, tw, reinterpret_cast<double2*>(mixed), gamma);
+  p->timing.end(s);
+  return check("phi_scalar256_kernel");
+}
+
+mlg_status launch_phi256_vec(const mlg_plan_s* p, const double* U, double* const* f6, double* taps, hipStream_t s) {
+  Phi256 g = phi256_geom(p, p->g.dealias != 0);
+  dim3 grid((unsigned)((g.nlines + PL - 1) / PL));
+  Six256 six;
+  for (int i = 0; i < 6; ++i) six.f[i] = reinterpret_cast<double2*>(f6[i]);
+  p->timing.begin("phi_fft", s);
+  phi_vec256_kernel<<<grid, 128, 0, s>>>(g, reinterpret_cast<const double2*>(p->d_tw_phi), six, p->d_node, U[0], U[1],
+                                         U[2], taps);
+  p->timing.end(s);
+  return check("phi_vec256_kernel");
+}
+
+}  // namespace mlg

@@ -7,24 +7,13 @@
 #include <cmath>
 #include <cstdint>
 
+#include "dev_common.h"
 #include "mlg_internal.h"
 
 namespace mlg {
 namespace {
 
-typedef double double4_t __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
-__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
-// multiply by -i (forward) or +i (inverse)
-__device__ __forceinline__ double2 cmul_mi(double2 a, bool inv) {
-  return inv ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
-}
+using namespace ::mlg::dev;
 
 // =====================================================================================
 // Radial transform: batched C = A^T B on MFMA f64 16x16x4.
@@ -43,7 +32,7 @@ __global__ __launch_bounds__(256) void radial_gemm_f64(GemmProds prods, const Ge
   const GemmDesc d = desc[bi];
   const int row0 = blockIdx.y * GT_M;
   const int col0 = blockIdx.x * GT_N;
-  if (row0 >= d.rows || col0 >= ncol || d.K <= 0) return;
+  if (row0 >= d.rows || col0 >= ncol) return;  // K == 0 (orders m >= N_r^c) writes zeros
   const double* __restrict__ A = prods.A[prod] + d.a_off;
   const double* __restrict__ B = prods.B[prod] + d.b_off;
   double* __restrict__ C = prods.C[prod] + d.c_off;
@@ -530,250 +519,275 @@ __global__ __launch_bounds__(256) void zfft_kernel(ZGeom g, FftRadices fr, const
   }
 }
 
-// ---------------------------------------------------------------- toroidal-poloidal epilogue
-// In place over the seven radial products A1 = Pbar psi, A2 = T psi, A3 = Pbar(L psi), B1 = Pbar chi,
-// B2 = T chi, B3 = Pbar(L chi), B4 = T(L chi) (mixed layout, k spectral), writing the harmonics
-//   u_r = (i m A1 + i kap B2)/r, u_phi = (-A2 - m kap B1)/r, u_z = q B3,
-//   w_r = (i kap A2 + i m q B3 + i m kap^2 B1)/r, w_phi = (-m kap A1 - q (B4 - 2(1+x) B3) - kap^2 B2)/r,
-//   w_z = q A3   into buffers 0..5.
-struct Seven {
-  double2* f[7];
-};
-
-__global__ __launch_bounds__(256) void vec_epilogue_kernel(Seven s, const double* __restrict__ node, int nr, int nz,
-                                                           int M, double kap0) {
-  const int64_t total = (int64_t)M * nr * nz;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int kk = (int)(e % nz);
-    const int64_t mi = e / nz;
-    const int i = (int)(mi % nr);
-    const int m = (int)(mi / nr);
-    const double kap = kap0 * kval(kk, nz);
-    const double rinv = node[i], q = node[nr + i], opx = node[2 * nr + i];
-    const double2 A1 = s.f[0][e], A2 = s.f[1][e], A3 = s.f[2][e];
-    const double2 B1 = s.f[3][e], B2 = s.f[4][e], B3 = s.f[5][e], B4 = s.f[6][e];
-    const double fm = (double)m;
-    // i*m*A1 + i*kap*B2
-    double2 ur = make_double2(-(fm * A1.y + kap * B2.y), fm * A1.x + kap * B2.x);
-    double2 up = make_double2(-A2.x - fm * kap * B1.x, -A2.y - fm * kap * B1.y);
-    double2 uz = cscale(B3, q);
-    // i*(kap*A2 + m*q*B3 + m*kap^2*B1)
-    double2 t = make_double2(kap * A2.x + fm * q * B3.x + fm * kap * kap * B1.x,
-                             kap * A2.y + fm * q * B3.y + fm * kap * kap * B1.y);
-    double2 wr = make_double2(-t.y, t.x);
-    double2 wp = make_double2(-fm * kap * A1.x - q * (B4.x - 2.0 * opx * B3.x) - kap * kap * B2.x,
-                              -fm * kap * A1.y - q * (B4.y - 2.0 * opx * B3.y) - kap * kap * B2.y);
-    double2 wz = cscale(A3, q);
-    s.f[0][e] = cscale(ur, rinv);
-    s.f[1][e] = cscale(up, rinv);
-    s.f[2][e] = uz;
-    s.f[3][e] = cscale(wr, rinv);
-    s.f[4][e] = cscale(wp, rinv);
-    s.f[5][e] = wz;
-  }
-}
-
 // ---------------------------------------------------------------- projection solves
-// One thread per (m, k slot) column.  Inputs (triangular, k spectral): Pa = Pbar^T W (N_r/r),
-// Qa = Q^T W (N_r/r), Pb = Pbar^T W (N_phi/r), Qb = Q^T W (N_phi/r), Pc = Pbar^T W N_z.
-//   C = -Qb - i m Pa,  K = -i kap Qa - m kap Pb - Dbar Pc,  Dbar = -G L / ell^2.
-//   psi: G (L psi) = ell^2 C ;  q = -Pc at k = 0, else (G + kap^2 ell^2 L^-1)(L q) = -ell^2 K ;
-//   chi: G (L chi) = -ell^2 q.  For m = 0 the unknowns n >= 1 are solved with G restricted to
-//   n >= 1 and n = 0 follows from the gauge sum_n sqrt((2n+1)/2) s_n = 0.
+// One thread per active (m, k slot) column (kept by the axial chop and, with dealiasing, by the
+// two-thirds mask).  Inputs (triangular, k spectral) from the fused projection GEMM: the curl
+// source C = [z . curl N]^, K' = -i kap [(1/r) d_r(r N_r)]^ - m kap [N_phi/r]^ and Zhat = [N_z]^.
+//   K = K' - Dbar Zhat,  Dbar = -G L / ell^2.
+//   psi: G (L psi) = ell^2 C              (precomputed L D L^T of G)
+//   q:   q = -Zhat at k = 0, else (G + kap^2 ell^2 L^-1)(L q) = -ell^2 K   (L D L^T on the fly)
+//   chi: G (L chi) = -ell^2 q             (precomputed U D U^T of G, started from the top degree)
+// For m = 0 the unknowns n >= 1 use G restricted to n >= 1 and n = 0 follows from the decay
+// gauge sum_n sqrt((2n+1)/2) s_n = 0.  Three passes over n: ascending (sources, forward
+// substitutions), descending (psi and q back substitution, first chi sweep), ascending (chi).
+// Inputs of each pass are fetched D degrees ahead so that a thread keeps several loads in flight.
 struct ProjArgs {
-  const double2* Pa;
-  const double2* Qa;
-  const double2* Pb;
-  const double2* Qb;
-  const double2* Pc;
-  double2* psi;
-  double2* chi;
-  double* scratch;       // 5 reals per (column, degree)
-  double2* taps;         // C, K, Zhat (triangular) or null
-  const double* gram;    // g0 g1 g2 d l1 l2, each ngram long
-  const int64_t* goff;
-  const int64_t* off;    // triangular offsets (device)
-  int64_t ngram, tri_elems;
-  int M, nz, nrc, nzc, mask_m, mask_k, dealias;
+  const double2* __restrict__ Cs;
+  const double2* __restrict__ Kp;
+  const double2* __restrict__ Pc;
+  double2* __restrict__ psi;
+  double2* __restrict__ chi;
+  double* __restrict__ scratch;  // 5 reals per (active column, degree)
+  double2* __restrict__ taps;    // C, K, Zhat (triangular) or null
+  const double* __restrict__ gram;
+  const int64_t* __restrict__ off;
+  int64_t ngram, tri_elems, nact;
+  int M, nz, nrc, nzc, kmax, mmax;  // active: m < mmax, |k| <= kmax and kept
+  int nkact;                        // active k slots per m
   double ell2, kap0;
 };
 
-__global__ __launch_bounds__(64) void projection_kernel(ProjArgs a) {
-  const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t ncols = (int64_t)a.M * a.nz;
-  if (col >= ncols) return;
-  const int m = (int)(col / a.nz);
-  const int kk = (int)(col - (int64_t)m * a.nz);
-  if (m >= a.nrc) return;
-  const int nz = a.nz;
-  const int64_t base = a.off[m];  // row of n = m
-  auto at = [&](int n) -> int64_t { return (base + (n - m)) * nz + kk; };
-  const int k = kval(kk, nz);
-  bool keep = kkept(kk, nz, a.nzc);
-  if (a.dealias) keep = keep && m <= a.mask_m && (k < 0 ? -k : k) <= a.mask_k;
-  const double2 z0 = make_double2(0.0, 0.0);
-  if (!keep) {
-    for (int n = m; n < a.nrc; ++n) {
-      a.psi[at(n)] = z0;
-      a.chi[at(n)] = z0;
-      if (a.taps) {
-        a.taps[at(n)] = z0;
-        a.taps[a.tri_elems + at(n)] = z0;
-        a.taps[2 * a.tri_elems + at(n)] = z0;
-      }
-    }
-    return;
-  }
-  const double kap = a.kap0 * k;
-  const double fm = (double)m;
-  const double* g0 = a.gram;
-  const double* g1 = a.gram + a.ngram;
-  const double* g2 = a.gram + 2 * a.ngram;
-  const double* dd = a.gram + 3 * a.ngram;
-  const double* l1 = a.gram + 4 * a.ngram;
-  const double* l2 = a.gram + 5 * a.ngram;
-  const int64_t gb = a.goff[m] - m;  // index of degree n is gb + n
-  const int n0 = m > 0 ? m : 1;
-  const int64_t sstride = ncols;     // scratch: [slot][n][col]
-  auto sidx = [&](int slot, int n) -> int64_t { return ((int64_t)slot * a.nrc + n) * sstride + col; };
-  auto Lf = [](int n) { return (double)n * (n + 1.0); };
+__device__ __forceinline__ int active_slot(int a, int kmax, int nz) {
+  // a in [0, 2 kmax + 1): k = 0..kmax then k = -kmax..-1
+  return (a <= kmax) ? a : nz - (2 * kmax + 1 - a);
+}
 
-  // ---- pass 1 (ascending): sources, forward substitution for psi and for q
-  double2 zpsi1 = z0, zpsi2 = z0;  // z_{n-1}, z_{n-2}
-  double2 zq1 = z0, zq2 = z0;
-  double dq1 = 0, dq2 = 0, lq1p = 0;  // d'_{n-1}, d'_{n-2}, l1'_{n-1}
+constexpr int PJ_D = 8;        // degrees fetched ahead per chunk
+
+// One block (one wave) per (m, 64 active k slots): the per-m coefficients (Gram entries,
+// reciprocal pivots, 1/(n(n+1)), gauge weights) are staged in LDS once per block.
+__global__ __launch_bounds__(64) void projection_kernel(ProjArgs a) {
+  extern __shared__ double sm[];
+  const int m = blockIdx.y;
+  const int nrc = a.nrc;
+  const int cnt = nrc - m;  // degrees n = m .. nrc-1 at index n - m
+  double* sg0 = sm;
+  double* sg1 = sg0 + cnt;
+  double* sg2 = sg1 + cnt;
+  double* srd = sg2 + cnt;
+  double* sl1 = srd + cnt;
+  double* sl2 = sl1 + cnt;
+  double* sru = sl2 + cnt;
+  double* su1 = sru + cnt;
+  double* su2 = su1 + cnt;
+  double* srL = su2 + cnt;
+  double* sgw = srL + cnt;
+  const int64_t gbase = a.off[m];
+  for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+    const int64_t g = gbase + t;
+    sg0[t] = a.gram[g];
+    sg1[t] = a.gram[a.ngram + g];
+    sg2[t] = a.gram[2 * a.ngram + g];
+    srd[t] = a.gram[3 * a.ngram + g];
+    sl1[t] = a.gram[4 * a.ngram + g];
+    sl2[t] = a.gram[5 * a.ngram + g];
+    sru[t] = a.gram[6 * a.ngram + g];
+    su1[t] = a.gram[7 * a.ngram + g];
+    su2[t] = a.gram[8 * a.ngram + g];
+    const double n = (double)(m + t);
+    srL[t] = (m + t) > 0 ? 1.0 / (n * (n + 1.0)) : 0.0;
+    sgw[t] = sqrt((2.0 * n + 1.0) * 0.5);
+  }
+  __syncthreads();
+  const int ca = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ca >= a.nkact) return;
+  const int64_t col = (int64_t)m * a.nkact + ca;
+  const int kk = active_slot(ca, a.kmax, a.nz);
+  const int nz = a.nz;
+  const int k = kval(kk, nz);
+  const double kap = a.kap0 * k;
+  const int n0 = m > 0 ? m : 1;
+  const int i0 = n0 - m;  // first solved index
+  const int64_t sstride = a.nact;
+  double* __restrict__ scr = a.scratch;
+  const double2* __restrict__ Cs = a.Cs + gbase * nz + kk;
+  const double2* __restrict__ Kp = a.Kp + gbase * nz + kk;
+  const double2* __restrict__ Zc = a.Pc + gbase * nz + kk;
+  double2* __restrict__ ps = a.psi + gbase * nz + kk;
+  double2* __restrict__ chv = a.chi + gbase * nz + kk;
+  auto sidx = [&](int slot, int t) -> int64_t { return ((int64_t)slot * nrc + t) * sstride + col; };
+  const double2 z0 = make_double2(0.0, 0.0);
   const double s = kap * kap * a.ell2;
-  // Zhat window for Dbar Pc: (L Z)_j for j = n-2 .. n+2
-  auto LZ = [&](int j) -> double2 {
-    if (j < m || j >= a.nrc) return z0;
-    return cscale(a.Pc[at(j)], Lf(j));
-  };
-  double2 lz_m2 = LZ(m - 2), lz_m1 = LZ(m - 1), lz_0 = LZ(m), lz_p1 = LZ(m + 1), lz_p2 = LZ(m + 2);
-  for (int n = m; n < a.nrc; ++n) {
-    const int64_t idx = at(n);
-    const double2 pa = a.Pa[idx], qa = a.Qa[idx], pb = a.Pb[idx], qb = a.Qb[idx];
-    // (G L Z)_n = g2_{n-2} LZ_{n-2} + g1_{n-1} LZ_{n-1} + g0_n LZ_n + g1_n LZ_{n+1} + g2_n LZ_{n+2}
-    double2 glz = cscale(lz_0, g0[gb + n]);
-    if (n - 1 >= m) glz = cadd(glz, cscale(lz_m1, g1[gb + n - 1]));
-    if (n - 2 >= m) glz = cadd(glz, cscale(lz_m2, g2[gb + n - 2]));
-    if (n + 1 < a.nrc) glz = cadd(glz, cscale(lz_p1, g1[gb + n]));
-    if (n + 2 < a.nrc) glz = cadd(glz, cscale(lz_p2, g2[gb + n]));
-    // C = -Qb - i m Pa
-    const double2 C = make_double2(-qb.x + fm * pa.y, -qb.y - fm * pa.x);
-    // K = -i kap Qa - m kap Pb + (G L Z)/ell^2
-    const double2 K = make_double2(kap * qa.y - fm * kap * pb.x + glz.x / a.ell2,
-                                   -kap * qa.x - fm * kap * pb.y + glz.y / a.ell2);
-    if (a.taps) {
-      a.taps[idx] = C;
-      a.taps[a.tri_elems + idx] = K;
-      a.taps[2 * a.tri_elems + idx] = a.Pc[idx];
+  const double inv_ell2 = 1.0 / a.ell2;
+  const double ell2 = a.ell2;
+
+  // ---- pass 1 (ascending index t = n - m): sources, forward substitutions for psi and q
+  double2 zpsi1 = z0, zpsi2 = z0, zq1 = z0, zq2 = z0;
+  double rq1 = 1, rq2 = 1, dq1 = 1, dq2 = 1, lq1p = 0;
+  auto LZ = [&](int t, double2 z) -> double2 { return cscale(z, t >= 0 && t < cnt ? (double)(m + t) * (m + t + 1.0) : 0.0); };
+  double2 lz_m2 = z0, lz_m1 = z0;
+  double2 lz_0 = LZ(0, cnt > 0 ? Zc[0] : z0), lz_p1 = LZ(1, cnt > 1 ? Zc[nz] : z0), lz_p2 = LZ(2, cnt > 2 ? Zc[2 * nz] : z0);
+  double2 cb[PJ_D], kb[PJ_D], zb[PJ_D];
+#pragma unroll
+  for (int d = 0; d < PJ_D; ++d) {
+    cb[d] = d < cnt ? Cs[(int64_t)d * nz] : z0;
+    kb[d] = d < cnt ? Kp[(int64_t)d * nz] : z0;
+    zb[d] = d + 3 < cnt ? Zc[(int64_t)(d + 3) * nz] : z0;
+  }
+  for (int tb = 0; tb < cnt; tb += PJ_D) {
+    double2 cn[PJ_D], kn[PJ_D], zn[PJ_D];
+#pragma unroll
+    for (int d = 0; d < PJ_D; ++d) {  // next chunk in flight while this one is computed
+      const int t = tb + PJ_D + d;
+      cn[d] = t < cnt ? Cs[(int64_t)t * nz] : z0;
+      kn[d] = t < cnt ? Kp[(int64_t)t * nz] : z0;
+      zn[d] = t + 3 < cnt ? Zc[(int64_t)(t + 3) * nz] : z0;
     }
-    // slide the L Z window
-    lz_m2 = lz_m1; lz_m1 = lz_0; lz_0 = lz_p1; lz_p1 = lz_p2; lz_p2 = LZ(n + 3);
-    if (n < n0) continue;  // m = 0, n = 0: gauge row
-    // psi forward substitution with the precomputed unit-lower factor
-    {
-      double2 b = cscale(C, a.ell2);
-      if (n - 1 >= n0) b = csub(b, cscale(zpsi1, l1[gb + n]));
-      if (n - 2 >= n0) b = csub(b, cscale(zpsi2, l2[gb + n]));
-      zpsi2 = zpsi1;
-      zpsi1 = b;
-      a.psi[idx] = b;
-    }
-    if (k != 0) {
-      // on-the-fly L D L^T of A' = G + s L^-1 (same off-diagonals as G)
-      const double diag = g0[gb + n] + s / Lf(n);
-      double l2n = 0, l1n = 0;
-      if (n - 2 >= n0) l2n = g2[gb + n - 2] / dq2;
-      if (n - 1 >= n0) {
-        double t = g1[gb + n - 1];
-        if (n - 2 >= n0) t -= l2n * dq2 * lq1p;
-        l1n = t / dq1;
+#pragma unroll
+    for (int d = 0; d < PJ_D; ++d) {
+      const int t = tb + d;
+      if (t >= cnt) break;
+      const int n = m + t;
+      double2 glz = cscale(lz_0, sg0[t]);
+      if (t >= 1) glz = cadd(glz, cscale(lz_m1, sg1[t - 1]));
+      if (t >= 2) glz = cadd(glz, cscale(lz_m2, sg2[t - 2]));
+      if (t + 1 < cnt) glz = cadd(glz, cscale(lz_p1, sg1[t]));
+      if (t + 2 < cnt) glz = cadd(glz, cscale(lz_p2, sg2[t]));
+      const double2 C = cb[d];
+      const double2 K = make_double2(kb[d].x + glz.x * inv_ell2, kb[d].y + glz.y * inv_ell2);
+      if (a.taps) {
+        const int64_t idx = (gbase + t) * nz + kk;
+        a.taps[idx] = C;
+        a.taps[a.tri_elems + idx] = K;
+        a.taps[2 * a.tri_elems + idx] = Zc[(int64_t)t * nz];
       }
-      double dn = diag;
-      if (n - 1 >= n0) dn -= l1n * l1n * dq1;
-      if (n - 2 >= n0) dn -= l2n * l2n * dq2;
-      double2 b = cscale(K, -a.ell2);
-      if (n - 1 >= n0) b = csub(b, cscale(zq1, l1n));
-      if (n - 2 >= n0) b = csub(b, cscale(zq2, l2n));
-      zq2 = zq1;
-      zq1 = b;
-      dq2 = dq1;
-      dq1 = dn;
-      lq1p = l1n;
-      a.scratch[sidx(0, n)] = b.x;
-      a.scratch[sidx(1, n)] = b.y;
-      a.scratch[sidx(2, n)] = l1n;
-      a.scratch[sidx(3, n)] = l2n;
-      a.scratch[sidx(4, n)] = dn;
+      lz_m2 = lz_m1; lz_m1 = lz_0; lz_0 = lz_p1; lz_p1 = lz_p2; lz_p2 = LZ(t + 3, zb[d]);
+      if (t < i0) continue;  // m = 0, n = 0: the gauge row
+      {
+        double2 b = cscale(C, ell2);
+        if (t - 1 >= i0) b = csub(b, cscale(zpsi1, sl1[t]));
+        if (t - 2 >= i0) b = csub(b, cscale(zpsi2, sl2[t]));
+        zpsi2 = zpsi1;
+        zpsi1 = b;
+        ps[(int64_t)t * nz] = b;
+      }
+      if (k != 0) {
+        double l2n = 0, l1n = 0;
+        if (t - 2 >= i0) l2n = sg2[t - 2] * rq2;
+        if (t - 1 >= i0) {
+          double u = sg1[t - 1];
+          if (t - 2 >= i0) u -= l2n * dq2 * lq1p;
+          l1n = u * rq1;
+        }
+        double dn = sg0[t] + s * srL[t];
+        if (t - 1 >= i0) dn -= l1n * l1n * dq1;
+        if (t - 2 >= i0) dn -= l2n * l2n * dq2;
+        const double rn = 1.0 / dn;
+        double2 b = cscale(K, -ell2);
+        if (t - 1 >= i0) b = csub(b, cscale(zq1, l1n));
+        if (t - 2 >= i0) b = csub(b, cscale(zq2, l2n));
+        zq2 = zq1; zq1 = b;
+        dq2 = dq1; dq1 = dn; rq2 = rq1; rq1 = rn; lq1p = l1n;
+        scr[sidx(0, t)] = b.x;
+        scr[sidx(1, t)] = b.y;
+        scr[sidx(2, t)] = l1n;
+        scr[sidx(3, t)] = l2n;
+        scr[sidx(4, t)] = rn;
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < PJ_D; ++d) { cb[d] = cn[d]; kb[d] = kn[d]; zb[d] = zn[d]; }
+  }
+  (void)lq1p;
+  // ---- pass 2 (descending): psi and q back substitution, chi sweep U w = -ell^2 q
+  double2 yp1 = z0, yp2 = z0, yq1 = z0, yq2 = z0, w1 = z0, w2 = z0;
+  double l1q_n1 = 0, l2q_n2 = 0, l2q_n1 = 0;
+  double gpr = 0, gpi = 0;
+  for (int tb = cnt - 1; tb >= i0; tb -= PJ_D) {
+    double2 pz[PJ_D], qz[PJ_D];
+    double ql1[PJ_D], ql2[PJ_D], qr[PJ_D];
+#pragma unroll
+    for (int d = 0; d < PJ_D; ++d) {
+      const int t = tb - d;
+      const bool ok = t >= i0;
+      pz[d] = ok ? ps[(int64_t)t * nz] : z0;
+      if (k != 0) {
+        qz[d] = ok ? make_double2(scr[sidx(0, t)], scr[sidx(1, t)]) : z0;
+        ql1[d] = ok ? scr[sidx(2, t)] : 0.0;
+        ql2[d] = ok ? scr[sidx(3, t)] : 0.0;
+        qr[d] = ok ? scr[sidx(4, t)] : 1.0;
+      } else {
+        qz[d] = ok ? Zc[(int64_t)t * nz] : z0;
+        ql1[d] = ql2[d] = 0.0;
+        qr[d] = 1.0;
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < PJ_D; ++d) {
+      const int t = tb - d;
+      if (t < i0) break;
+      {
+        double2 y = cscale(pz[d], srd[t]);
+        if (t + 1 < cnt) y = csub(y, cscale(yp1, sl1[t + 1]));
+        if (t + 2 < cnt) y = csub(y, cscale(yp2, sl2[t + 2]));
+        yp2 = yp1; yp1 = y;
+        const double2 v = cscale(y, srL[t]);
+        ps[(int64_t)t * nz] = v;
+        gpr += sgw[t] * v.x;
+        gpi += sgw[t] * v.y;
+      }
+      double2 qn;
+      if (k != 0) {
+        double2 y = cscale(qz[d], qr[d]);
+        if (t + 1 < cnt) y = csub(y, cscale(yq1, l1q_n1));
+        if (t + 2 < cnt) y = csub(y, cscale(yq2, l2q_n2));
+        yq2 = yq1; yq1 = y;
+        l2q_n2 = l2q_n1;
+        l1q_n1 = ql1[d];
+        l2q_n1 = ql2[d];
+        qn = cscale(y, srL[t]);
+      } else {
+        qn = cscale(qz[d], -1.0);
+      }
+      double2 w = cscale(qn, -ell2);
+      if (t + 1 < cnt) w = csub(w, cscale(w1, su1[t]));
+      if (t + 2 < cnt) w = csub(w, cscale(w2, su2[t]));
+      w2 = w1; w1 = w;
+      chv[(int64_t)t * nz] = w;
     }
   }
-  // ---- pass 2 (descending): back substitution for psi and q
-  double2 ypsi1 = z0, ypsi2 = z0, yq1 = z0, yq2 = z0;
-  double l1q_n1 = 0, l2q_n2 = 0, l2q_n1 = 0;  // l1'_{n+1}, l2'_{n+2}, l2'_{n+1}
-  double gauge_psi_re = 0, gauge_psi_im = 0;
-  for (int n = a.nrc - 1; n >= n0; --n) {
-    const int64_t idx = at(n);
-    {
-      double2 y = cscale(a.psi[idx], 1.0 / dd[gb + n]);
-      if (n + 1 < a.nrc) y = csub(y, cscale(ypsi1, l1[gb + n + 1]));
-      if (n + 2 < a.nrc) y = csub(y, cscale(ypsi2, l2[gb + n + 2]));
-      ypsi2 = ypsi1;
-      ypsi1 = y;
-      const double2 v = cscale(y, 1.0 / Lf(n));
-      a.psi[idx] = v;
-      const double gw = sqrt((2.0 * n + 1.0) * 0.5);
-      gauge_psi_re += gw * v.x;
-      gauge_psi_im += gw * v.y;
-    }
-    double2 qn;
-    if (k != 0) {
-      const double2 zb = make_double2(a.scratch[sidx(0, n)], a.scratch[sidx(1, n)]);
-      const double dn = a.scratch[sidx(4, n)];
-      double2 y = cscale(zb, 1.0 / dn);
-      if (n + 1 < a.nrc) y = csub(y, cscale(yq1, l1q_n1));
-      if (n + 2 < a.nrc) y = csub(y, cscale(yq2, l2q_n2));
-      yq2 = yq1;
-      yq1 = y;
-      l2q_n2 = l2q_n1;
-      l1q_n1 = a.scratch[sidx(2, n)];
-      l2q_n1 = a.scratch[sidx(3, n)];
-      qn = cscale(y, 1.0 / Lf(n));
-    } else {
-      qn = cscale(a.Pc[idx], -1.0);
-    }
-    a.scratch[sidx(0, n)] = qn.x;
-    a.scratch[sidx(1, n)] = qn.y;
-  }
-  if (m == 0) a.psi[at(0)] = make_double2(-gauge_psi_re / sqrt(0.5), -gauge_psi_im / sqrt(0.5));
-  // ---- pass 3 (ascending): chi forward substitution, G (L chi) = -ell^2 q
-  double2 zc1 = z0, zc2 = z0;
-  for (int n = n0; n < a.nrc; ++n) {
-    const double2 qn = make_double2(a.scratch[sidx(0, n)], a.scratch[sidx(1, n)]);
-    double2 b = cscale(qn, -a.ell2);
-    if (n - 1 >= n0) b = csub(b, cscale(zc1, l1[gb + n]));
-    if (n - 2 >= n0) b = csub(b, cscale(zc2, l2[gb + n]));
-    zc2 = zc1;
-    zc1 = b;
-    a.chi[at(n)] = b;
-  }
-  // ---- pass 4 (descending): chi back substitution
+  if (m == 0) ps[0] = make_double2(-gpr / sgw[0], -gpi / sgw[0]);
+  // ---- pass 3 (ascending): D U^T y = w
   double2 yc1 = z0, yc2 = z0;
-  double gauge_chi_re = 0, gauge_chi_im = 0;
-  for (int n = a.nrc - 1; n >= n0; --n) {
-    const int64_t idx = at(n);
-    double2 y = cscale(a.chi[idx], 1.0 / dd[gb + n]);
-    if (n + 1 < a.nrc) y = csub(y, cscale(yc1, l1[gb + n + 1]));
-    if (n + 2 < a.nrc) y = csub(y, cscale(yc2, l2[gb + n + 2]));
-    yc2 = yc1;
-    yc1 = y;
-    const double2 v = cscale(y, 1.0 / Lf(n));
-    a.chi[idx] = v;
-    const double gw = sqrt((2.0 * n + 1.0) * 0.5);
-    gauge_chi_re += gw * v.x;
-    gauge_chi_im += gw * v.y;
+  double gcr = 0, gci = 0;
+  for (int tb = i0; tb < cnt; tb += PJ_D) {
+    double2 wz[PJ_D];
+#pragma unroll
+    for (int d = 0; d < PJ_D; ++d) wz[d] = (tb + d < cnt) ? chv[(int64_t)(tb + d) * nz] : z0;
+#pragma unroll
+    for (int d = 0; d < PJ_D; ++d) {
+      const int t = tb + d;
+      if (t >= cnt) break;
+      double2 y = cscale(wz[d], sru[t]);
+      if (t - 1 >= i0) y = csub(y, cscale(yc1, su1[t - 1]));
+      if (t - 2 >= i0) y = csub(y, cscale(yc2, su2[t - 2]));
+      yc2 = yc1; yc1 = y;
+      const double2 v = cscale(y, srL[t]);
+      chv[(int64_t)t * nz] = v;
+      gcr += sgw[t] * v.x;
+      gci += sgw[t] * v.y;
+    }
   }
-  if (m == 0) a.chi[at(0)] = make_double2(-gauge_chi_re / sqrt(0.5), -gauge_chi_im / sqrt(0.5));
+  if (m == 0) chv[0] = make_double2(-gcr / sgw[0], -gci / sgw[0]);
+}
+
+// Zero every entry of the packed arrays whose (m, k) column is not active.
+__global__ void zero_inactive_kernel(double2* __restrict__ x0, double2* __restrict__ x1, double2* __restrict__ x2,
+                                     double2* __restrict__ x3, double2* __restrict__ x4,
+                                     const int32_t* __restrict__ row_m, int64_t rows, int nz, int nzc, int mmax,
+                                     int kmax) {
+  const int64_t total = rows * nz;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = e / nz;
+    const int kk = (int)(e - row * nz);
+    const int k = kval(kk, nz);
+    const bool active = row_m[row] < mmax && (k < 0 ? -k : k) <= kmax && kkept(kk, nz, nzc);
+    if (active) continue;
+    const double2 z = make_double2(0.0, 0.0);
+    x0[e] = z;
+    x1[e] = z;
+    if (x2) { x2[e] = z; x3[e] = z; x4[e] = z; }
+  }
 }
 
 __global__ void mask_tri_kernel(double2* spec, const int32_t* __restrict__ row_m, int64_t rows, int nz, int mask_m,
@@ -832,6 +846,7 @@ mlg_status launch_gemm(const mlg_plan_s* p, const GemmProds& prods, const GemmDe
 }
 
 mlg_status launch_phi_forward(const mlg_plan_s* p, const double* phys, double* mixed, hipStream_t s) {
+  if (p->nphi == 256 && p->use_fast_fft) return launch_phi256_forward(p, phys, mixed, s);
   PhiGeom g = phi_geom(p, false);
   const int lb = phi_lines_per_block(p->nphi);
   const int npair = lb / 2;
@@ -846,6 +861,7 @@ mlg_status launch_phi_forward(const mlg_plan_s* p, const double* phys, double* m
 }
 
 mlg_status launch_phi_backward(const mlg_plan_s* p, const double* mixed, double* phys, hipStream_t s) {
+  if (p->nphi == 256 && p->use_fast_fft) return launch_phi256_backward(p, mixed, phys, s);
   PhiGeom g = phi_geom(p, false);
   const int lb = phi_lines_per_block(p->nphi);
   const size_t shm = (size_t)2 * (lb / 2) * p->nphi * sizeof(double2);
@@ -859,6 +875,7 @@ mlg_status launch_phi_backward(const mlg_plan_s* p, const double* mixed, double*
 }
 
 mlg_status launch_phi_scalar_rhs(const mlg_plan_s* p, int kind, double gamma, double* mixed, hipStream_t s) {
+  if (p->nphi == 256 && p->use_fast_fft) return launch_phi256_scalar(p, kind, gamma, mixed, s);
   PhiGeom g = phi_geom(p, p->g.dealias != 0);
   const int lb = phi_lines_per_block(p->nphi);
   const size_t shm = (size_t)2 * (lb / 2) * p->nphi * sizeof(double2);
@@ -875,6 +892,7 @@ mlg_status launch_phi_scalar_rhs(const mlg_plan_s* p, int kind, double gamma, do
 }
 
 mlg_status launch_phi_vec_rhs(const mlg_plan_s* p, const double* U, double* const* f6, double* taps, hipStream_t s) {
+  if (p->nphi == 256 && p->use_fast_fft) return launch_phi256_vec(p, U, f6, taps, s);
   PhiGeom g = phi_geom(p, p->g.dealias != 0);
   int lb = 1024 / p->nphi;  // 4 buffers of n complex per line: 64 * lb * n bytes <= 64 KB
   if (lb < 1) lb = 1;
@@ -894,6 +912,7 @@ mlg_status launch_phi_vec_rhs(const mlg_plan_s* p, const double* U, double* cons
 mlg_status launch_zfft(const mlg_plan_s* p, const double* in, double* out, int64_t rows, int dir, const int32_t* row_m,
                        int mask_m, int mask_k, hipStream_t s) {
   if (rows <= 0) return MLG_OK;
+  if (p->nz == 256 && p->use_fast_fft) return launch_zfft256(p, in, out, rows, dir, row_m, mask_m, mask_k, s);
   ZGeom g{};
   g.nz = p->nz;
   g.nzc = p->nzc;
@@ -913,49 +932,65 @@ mlg_status launch_zfft(const mlg_plan_s* p, const double* in, double* out, int64
   return check_launch("zfft_kernel");
 }
 
-mlg_status launch_vec_epilogue(const mlg_plan_s* p, double* const* prod7, hipStream_t s) {
-  Seven sv;
-  for (int i = 0; i < 7; ++i) sv.f[i] = reinterpret_cast<double2*>(prod7[i]);
-  const int64_t total = (int64_t)p->M * p->nr * p->nz;
-  int blocks = (int)std::min<int64_t>((total + 255) / 256, 65536);
-  const double kap0 = 2.0 * M_PI / p->g.lz;
-  p->timing.begin("vec_epilogue", s);
-  vec_epilogue_kernel<<<blocks, 256, 0, s>>>(sv, p->d_node, p->nr, p->nz, p->M, kap0);
-  p->timing.end(s);
-  return check_launch("vec_epilogue_kernel");
+void active_columns(const mlg_plan_s* p, int* mmax_out, int* kmax_out) {
+  // chop-kept k (never the Nyquist slot) and, when dealiasing, the two-thirds mask
+  int kmax = p->nzc - 1;
+  if (p->nz % 2 == 0 && p->nz > 1) kmax = std::min(kmax, p->nz / 2 - 1);
+  int mmax = std::min(p->M, p->nrc);
+  if (2 * (p->M - 1) >= p->nphi) mmax = std::min(mmax, p->nphi / 2);  // no Nyquist order
+  if (p->g.dealias) {
+    kmax = std::min(kmax, p->dealias_k);
+    mmax = std::min(mmax, p->dealias_m + 1);
+  }
+  *mmax_out = mmax;
+  *kmax_out = kmax;
 }
 
-mlg_status launch_projection(const mlg_plan_s* p, const double* const* src5, double* psi_n, double* chi_n,
+mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, double* psi_n, double* chi_n,
                              double* scratch, double* taps_src, hipStream_t s) {
   ProjArgs a{};
-  a.Pa = reinterpret_cast<const double2*>(src5[0]);
-  a.Qa = reinterpret_cast<const double2*>(src5[1]);
-  a.Pb = reinterpret_cast<const double2*>(src5[2]);
-  a.Qb = reinterpret_cast<const double2*>(src5[3]);
-  a.Pc = reinterpret_cast<const double2*>(src5[4]);
+  a.Cs = reinterpret_cast<const double2*>(src3[0]);
+  a.Kp = reinterpret_cast<const double2*>(src3[1]);
+  a.Pc = reinterpret_cast<const double2*>(src3[2]);
   a.psi = reinterpret_cast<double2*>(psi_n);
   a.chi = reinterpret_cast<double2*>(chi_n);
   a.scratch = scratch;
   a.taps = reinterpret_cast<double2*>(taps_src);
   a.gram = p->d_gram;
-  a.goff = p->d_goff;
+  a.off = p->d_goff;  // the Gram offsets coincide with the triangular row offsets
   a.ngram = p->ngram;
   a.tri_elems = (int64_t)p->tri_elems;
   a.M = p->M;
   a.nz = p->nz;
   a.nrc = p->nrc;
   a.nzc = p->nzc;
-  a.mask_m = p->dealias_m;
-  a.mask_k = p->dealias_k;
-  a.dealias = p->g.dealias;
+  int mmax, kmax;
+  active_columns(p, &mmax, &kmax);
+  a.kmax = kmax;
+  a.mmax = mmax;
+  a.nkact = 2 * kmax + 1;
+  if (p->nz == 1) a.nkact = 1;
+  a.nact = (int64_t)mmax * a.nkact;
   a.ell2 = p->g.ell * p->g.ell;
   a.kap0 = 2.0 * M_PI / p->g.lz;
-  a.off = p->d_goff;  // the Gram offsets coincide with the triangular row offsets
-  const int64_t ncols = (int64_t)p->M * p->nz;
-  dim3 grid((unsigned)((ncols + 63) / 64));
-  p->timing.begin("projection", s);
-  projection_kernel<<<grid, 64, 0, s>>>(a);
-  p->timing.end(s);
+  const int64_t total = p->tau * p->nz;
+  if (total > 0) {
+    int blocks = (int)std::min<int64_t>((total + 255) / 256, 65536);
+    double2* t0 = a.taps;
+    p->timing.begin("projection", s);
+    zero_inactive_kernel<<<blocks, 256, 0, s>>>(a.psi, a.chi, t0, t0 ? t0 + p->tri_elems : nullptr,
+                                                t0 ? t0 + 2 * p->tri_elems : nullptr, p->d_row_m, p->tau, p->nz, p->nzc,
+                                                mmax, kmax);
+    p->timing.end(s);
+    if (mlg_status st = check_launch("zero_inactive_kernel")) return st;
+  }
+  if (a.nact > 0) {
+    dim3 grid((unsigned)((a.nkact + 63) / 64), (unsigned)mmax);
+    const size_t shm = (size_t)11 * p->nrc * sizeof(double);
+    p->timing.begin("projection", s);
+    projection_kernel<<<grid, 64, shm, s>>>(a);
+    p->timing.end(s);
+  }
   return check_launch("projection_kernel");
 }
 

@@ -88,10 +88,11 @@ struct mlg_plan_s {
   int32_t* d_row_m = nullptr;  // azimuthal order of every triangular row
   mlg::GemmDesc* d_desc_fwd = nullptr;
   mlg::GemmDesc* d_desc_bwd = nullptr;
-  double* d_gram = nullptr;    // packed g0,g1,g2,d,l1,l2 (6 * ngram)
+  double* d_gram = nullptr;    // packed g0,g1,g2 | LDL^T 1/d,l1,l2 | UDU^T 1/d,u1,u2 (9 * ngram)
   int64_t* d_goff = nullptr;
   int64_t ngram = 0;
   int max_rows_fwd = 0, max_rows_bwd = 0;
+  bool use_fast_fft = true;   // register-resident 256-point kernels when a length is 256
   int phi_rad[12] = {0};
   int phi_nrad = 0;
   int z_rad[12] = {0};
@@ -117,8 +118,23 @@ mlg_status launch_phi_vec_rhs(const mlg_plan_s* p, const double* U, double* cons
 // slots outside the chop zeroed, optional dealias mask by row order m), +1 backward.
 mlg_status launch_zfft(const mlg_plan_s* p, const double* in, double* out, int64_t rows, int dir,
                        const int32_t* row_m, int mask_m, int mask_k, hipStream_t s);
-mlg_status launch_vec_epilogue(const mlg_plan_s* p, double* const* prod7, hipStream_t s);
-mlg_status launch_projection(const mlg_plan_s* p, const double* const* src5, double* psi_n, double* chi_n,
+// Elliptic solves from the projection sources (C, K', Zhat); taps_src receives C, K, Zhat.
+mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, double* psi_n, double* chi_n,
                              double* scratch, double* taps_src, hipStream_t s);
+// gemm_fused.hip: synthesis of the six velocity / vorticity harmonics from (psi, chi), and the five
+// projection products with the C, K', Zhat epilogue on the active (m < mmax, |k| <= kmax) columns.
+mlg_status launch_synth_gemm(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,
+                             hipStream_t s);
+mlg_status launch_proj_gemm(const mlg_plan_s* p, double* const* in3, double* const* out3, int mmax, int kmax,
+                            hipStream_t s);
+// active column bounds of the projection: m < mmax, |k| <= kmax
+void active_columns(const mlg_plan_s* p, int* mmax, int* kmax);
 mlg_status launch_mask_tri(const mlg_plan_s* p, double* spec, hipStream_t s);
+// fft256.hip: register-resident 256-point transforms (used when N_z or N_phi equals 256)
+mlg_status launch_zfft256(const mlg_plan_s* p, const double* in, double* out, int64_t rows, int dir,
+                          const int32_t* row_m, int mask_m, int mask_k, hipStream_t s);
+mlg_status launch_phi256_forward(const mlg_plan_s* p, const double* phys, double* mixed, hipStream_t s);
+mlg_status launch_phi256_backward(const mlg_plan_s* p, const double* mixed, double* phys, hipStream_t s);
+mlg_status launch_phi256_scalar(const mlg_plan_s* p, int kind, double gamma, double* mixed, hipStream_t s);
+mlg_status launch_phi256_vec(const mlg_plan_s* p, const double* U, double* const* f6, double* taps, hipStream_t s);
 }  // namespace mlg

@@ -236,14 +236,39 @@ mlg_status build_plan(mlg_plan_s* p) {
       gf.d[k] = (double)d;
     }
   }
-  std::vector<double> gram(6 * (size_t)std::max<int64_t>(p->ngram, 1));
+  // U D U^T factors of the same matrices (unit upper U with superdiagonals u1, u2), so that a
+  // solve can start from the highest degree
+  std::vector<double> du(p->ngram, 0), u1(p->ngram, 0), u2(p->ngram, 0);
+  for (int m = 0; m < M; ++m) {
+    const int n0 = std::max(m, 1);
+    for (int n = nrc - 1; n >= n0; --n) {
+      const int64_t k = gf.goff[m] + (n - m);
+      ld a2 = 0, a1 = 0;
+      if (n + 2 < nrc) a2 = (ld)gf.g2[k] / (ld)du[k + 2];
+      if (n + 1 < nrc) {
+        ld t = gf.g1[k];
+        if (n + 2 < nrc) t -= a2 * (ld)du[k + 2] * (ld)u1[k + 1];
+        a1 = t / (ld)du[k + 1];
+      }
+      ld d = gf.g0[k];
+      if (n + 1 < nrc) d -= a1 * a1 * (ld)du[k + 1];
+      if (n + 2 < nrc) d -= a2 * a2 * (ld)du[k + 2];
+      u1[k] = (double)a1;
+      u2[k] = (double)a2;
+      du[k] = (double)d;
+    }
+  }
+  std::vector<double> gram(9 * (size_t)std::max<int64_t>(p->ngram, 1));
   for (int64_t k = 0; k < p->ngram; ++k) {
     gram[0 * p->ngram + k] = gf.g0[k];
     gram[1 * p->ngram + k] = gf.g1[k];
     gram[2 * p->ngram + k] = gf.g2[k];
-    gram[3 * p->ngram + k] = gf.d[k];
+    gram[3 * p->ngram + k] = gf.d[k] != 0 ? 1.0 / gf.d[k] : 0.0;   // reciprocal pivots
     gram[4 * p->ngram + k] = gf.l1[k];
     gram[5 * p->ngram + k] = gf.l2[k];
+    gram[6 * p->ngram + k] = du[k] != 0 ? 1.0 / du[k] : 0.0;
+    gram[7 * p->ngram + k] = u1[k];
+    gram[8 * p->ngram + k] = u2[k];
   }
   // ---------------- nodal vectors, twiddles, row orders, GEMM descriptors
   std::vector<double> node(3 * nr);
@@ -273,7 +298,7 @@ mlg_status build_plan(mlg_plan_s* p) {
   for (int m = 0; m < M; ++m) {
     const int K = std::max(nrc - m, 0);
     GemmDesc b{};
-    b.a_off = (int64_t)p->off[m] * nr; b.lda = nr; b.K = K; b.rows = K > 0 ? nr : 0;
+    b.a_off = (int64_t)p->off[m] * nr; b.lda = nr; b.K = K; b.rows = nr;  // K = 0: zero harmonics
     b.b_off = (int64_t)p->off[m] * ncol; b.c_off = (int64_t)m * nr * ncol; b.m = m;
     dbwd[m] = b;
     GemmDesc f{};
