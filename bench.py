@@ -204,6 +204,33 @@ def main():
         "kernels": per_kernel,
         "transform_pair": {"ms": round(pair_ms, 4), "gdofs": round(n ** 3 / (pair_ms / 1e3) / 1e9, 4)},
     }
+    # split-bfloat16 radial products on the same state: time, and the error against the FP64 result
+    # at the tap that is well conditioned: the velocity V(psi_N, chi_N) the potentials represent
+    from paper_2609_18026_amd import MLG_SPLIT_BF16
+    ref_p, ref_c = po.clone(), co.clone()
+    splan = Plan(n, n, n, 1.0, PAIR["lz"], dealias=1, prec=MLG_SPLIT_BF16)
+    sp, sc = splan.empty_spec(), splan.empty_spec()
+    for _ in range(args.warmup):
+        splan.rhs_tp(psi, chi, sp, sc, U=U_FRAME)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        splan.rhs_tp(psi, chi, sp, sc, U=U_FRAME)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sms = e0.elapsed_time(e1) / args.steps
+    del splan
+    uw_ref = torch.empty(6 * plan.layout.phys_elems, dtype=torch.float64, device="cuda")
+    uw_spl = torch.empty_like(uw_ref)
+    plan.synthesize(ref_p, ref_c, uw_ref)
+    plan.synthesize(sp, sc, uw_spl)
+    torch.cuda.synchronize()
+    pe = plan.layout.phys_elems
+    verr = float(torch.linalg.vector_norm(uw_spl[:3 * pe] - uw_ref[:3 * pe]) / torch.linalg.vector_norm(uw_ref[:3 * pe]))
+    cerr = float(torch.linalg.vector_norm(sp - ref_p) / torch.linalg.vector_norm(ref_p))
+    out["split_bf16"] = {"ms_per_step": round(sms, 4), "gdofs": round(n ** 3 / (sms / 1e3) / 1e9, 4),
+                         "rel_err_velocity_of_output_vs_fp64": verr, "rel_err_psi_coefficients_vs_fp64": cerr}
+    log(f"bench: split-bf16 {sms:.3f} ms/step, velocity rel err {verr:.2e} (coefficients {cerr:.2e})")
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)

@@ -135,6 +135,12 @@ mlg_status mlg_rhs_scalar(mlg_plan plan, int kind, double gamma, const void* spe
 mlg_status mlg_rhs_tp(mlg_plan plan, const double* U, const void* psi, const void* chi,
                       void* psi_n, void* chi_n, void* taps, void* ws, void* stream);
 
+/* Nodal velocity and vorticity of a toroidal-poloidal pair (Sec. 3.2, Eq. tp):
+ * u = curl(psi z) + curl curl(chi z), omega = curl u.  'uw' is a device buffer of
+ * 6 * phys_elems reals receiving u_r, u_phi, u_z, w_r, w_phi, w_z (physical layout each).
+ * The radial products use the plan's precision. */
+mlg_status mlg_synthesize(mlg_plan plan, const void* psi, const void* chi, void* uw, void* ws, void* stream);
+
 /* Optional per-kernel timing, for benchmarks and profiling (not needed for computation).
  * While enabled, every kernel launch of the plan is bracketed by two HIP events recorded on
  * the launch's stream.  mlg_timing_read waits for the recorded events, returns the summed

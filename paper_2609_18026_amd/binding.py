@@ -42,7 +42,7 @@ class mlg_layout(ctypes.Structure):
 _lib = None
 
 EXPORTS = ["mlg_plan_create", "mlg_plan_destroy", "mlg_plan_query", "mlg_plan_nodes", "mlg_forward",
-           "mlg_backward", "mlg_rhs_scalar", "mlg_rhs_tp", "mlg_timing_enable", "mlg_timing_read",
+           "mlg_backward", "mlg_rhs_scalar", "mlg_rhs_tp", "mlg_synthesize", "mlg_timing_enable", "mlg_timing_read",
            "mlg_last_error"]
 
 
@@ -63,6 +63,7 @@ def lib() -> ctypes.CDLL:
     L.mlg_backward.argtypes = [vp, vp, vp, vp, vp]
     L.mlg_rhs_scalar.argtypes = [vp, i32, f64, vp, vp, vp, vp]
     L.mlg_rhs_tp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.mlg_synthesize.argtypes = [vp, vp, vp, vp, vp, vp]
     L.mlg_timing_enable.argtypes = [vp, i32]
     L.mlg_timing_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTS[:-1]:
@@ -127,6 +128,10 @@ def mlg_rhs_tp(plan: int, U, psi: int, chi: int, psi_n: int, chi_n: int, taps: i
     _check(lib().mlg_rhs_tp(plan, Uarr, psi, chi, psi_n, chi_n, taps, ws, stream))
 
 
+def mlg_synthesize(plan: int, psi: int, chi: int, uw: int, ws: int, stream: int = 0) -> None:
+    _check(lib().mlg_synthesize(plan, psi, chi, uw, ws, stream))
+
+
 def mlg_timing_enable(plan: int, enable: bool) -> None:
     _check(lib().mlg_timing_enable(plan, 1 if enable else 0))
 
@@ -189,6 +194,10 @@ class Plan:
     def rhs_tp(self, psi, chi, psi_n, chi_n, U=None, taps=None):
         mlg_rhs_tp(self.handle, U, psi.data_ptr(), chi.data_ptr(), psi_n.data_ptr(), chi_n.data_ptr(),
                    0 if taps is None else taps.data_ptr(), self.ws.data_ptr(), self._stream())
+
+    def synthesize(self, psi, chi, uw):
+        """uw: float64 tensor of 6 * phys_elems (u_r, u_phi, u_z, w_r, w_phi, w_z)."""
+        mlg_synthesize(self.handle, psi.data_ptr(), chi.data_ptr(), uw.data_ptr(), self.ws.data_ptr(), self._stream())
 
     def taps_buffer(self):
         import torch

@@ -89,7 +89,8 @@ mlg_status mlg_plan_create(const mlg_grid* grid, mlg_precision prec, int device,
   if (g.nr > 4096) return fail(MLG_E_UNSUPPORTED, "N_r above 4096");
   if (!factorable(g.nphi) || !factorable(g.nz))
     return fail(MLG_E_UNSUPPORTED, "N_phi and N_z must be <= 1024 with prime factors 2, 3, 5 only");
-  if (prec != MLG_FP64) return fail(MLG_E_UNSUPPORTED, "only MLG_FP64 plans are implemented");
+  if (prec != MLG_FP64 && prec != MLG_SPLIT_BF16)
+    return fail(MLG_E_UNSUPPORTED, "plans support MLG_FP64 and MLG_SPLIT_BF16");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
     return fail(MLG_E_ARG, "device index out of range or no HIP device");
@@ -236,8 +237,11 @@ mlg_status mlg_rhs_tp(mlg_plan p, const double* U, const void* psi, const void* 
   Ws w = partition(p, ws);
   mlg_status st;
   // 1. radial synthesis: the six velocity / vorticity harmonics (k spectral), fused
-  if ((st = launch_synth_gemm(p, static_cast<const double*>(psi), static_cast<const double*>(chi), w.X, s)))
-    return st;
+  if (p->prec == MLG_SPLIT_BF16)
+    st = launch_split_synth(p, static_cast<const double*>(psi), static_cast<const double*>(chi), w.X, s);
+  else
+    st = launch_synth_gemm(p, static_cast<const double*>(psi), static_cast<const double*>(chi), w.X, s);
+  if (st) return st;
   // 2. inverse z transforms of the six fields
   const int64_t mrows = (int64_t)p->M * p->nr;
   for (int i = 0; i < 6; ++i)
@@ -253,11 +257,34 @@ mlg_status mlg_rhs_tp(mlg_plan p, const double* U, const void* psi, const void* 
     if ((st = launch_zfft(p, w.X[i], w.X[i], frows, -1, nullptr, 0, 0, s))) return st;
   // 5. Galerkin projections onto Pbar and Q = T - 2(1+x) Pbar with the C, K', Zhat epilogue
   double* src3[3] = {w.T[0], w.T[1], w.T[2]};
-  if ((st = launch_proj_gemm(p, w.X, src3, mmax, kmax, s))) return st;
+  st = (p->prec == MLG_SPLIT_BF16) ? launch_split_proj(p, w.X, src3, mmax, kmax, s)
+                                   : launch_proj_gemm(p, w.X, src3, mmax, kmax, s);
+  if (st) return st;
   // 6. elliptic solves per (m, k)
   const double* csrc[3] = {w.T[0], w.T[1], w.T[2]};
   double* tsrc = tp ? tp + (size_t)9 * p->nz * p->nr * p->nphi : nullptr;
   return launch_projection(p, csrc, static_cast<double*>(psi_n), static_cast<double*>(chi_n), w.scratch, tsrc, s);
+}
+
+mlg_status mlg_synthesize(mlg_plan p, const void* psi, const void* chi, void* uw, void* ws, void* stream) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!psi || !chi || !uw || !ws) return fail(MLG_E_ARG, "null buffer");
+  DeviceGuard guard(p->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Ws w = partition(p, ws);
+  mlg_status st;
+  if (p->prec == MLG_SPLIT_BF16)
+    st = launch_split_synth(p, static_cast<const double*>(psi), static_cast<const double*>(chi), w.X, s);
+  else
+    st = launch_synth_gemm(p, static_cast<const double*>(psi), static_cast<const double*>(chi), w.X, s);
+  if (st) return st;
+  const int64_t mrows = (int64_t)p->M * p->nr;
+  const size_t pe = (size_t)p->nz * p->nr * p->nphi;
+  for (int i = 0; i < 6; ++i) {
+    if ((st = launch_zfft(p, w.X[i], w.X[i], mrows, +1, nullptr, 0, 0, s))) return st;
+    if ((st = launch_phi_backward(p, w.X[i], static_cast<double*>(uw) + i * pe, s))) return st;
+  }
+  return MLG_OK;
 }
 
 mlg_status mlg_timing_enable(mlg_plan p, int enable) {

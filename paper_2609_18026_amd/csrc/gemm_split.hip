@@ -1,0 +1,342 @@
+// Split-bfloat16 radial products for the toroidal-poloidal RHS (plans of precision
+// MLG_SPLIT_BF16).  Every operand x is represented as hi + lo with hi = bf16(x) and
+// lo = bf16(x - hi); a product is accumulated in FP32 as hi_a hi_b + hi_a lo_b + lo_a hi_b
+// (the lo_a lo_b term, ~2^-18 relative, is dropped) with v_mfma_f32_16x16x32_bf16.
+// Tables are split once on the host; the FP64 data are split while they are staged in LDS.
+// The epilogues, layouts and outputs are those of the FP64 kernels in gemm_fused.hip.
+//
+// MFMA operand layout (16x16x32 bf16): lane l supplies A[l%16][8(l/16) .. 8(l/16)+7] and
+// B[8(l/16) .. +7][l%16]; FP32 accumulator value v of lane l is C[4(l/16) + v][l%16].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "dev_common.h"
+#include "mlg_internal.h"
+
+namespace mlg {
+namespace {
+
+using namespace ::mlg::dev;
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int TM = 64;  // rows per block (4 waves x 16)
+constexpr int TC = 16;  // complex columns per block
+constexpr int TK = 32;  // one MFMA k step
+
+__device__ __forceinline__ int kval(int kk, int nz) { return (2 * kk < nz) ? kk : kk - nz; }
+
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ unsigned short bf16_bits(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_float(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+__device__ __forceinline__ void split2(double x, unsigned short& hi, unsigned short& lo) {
+  const float f = (float)x;
+  hi = bf16_bits(f);
+  lo = bf16_bits(f - bf16_to_float(hi));
+}
+
+__device__ __forceinline__ floatx4 mfma3(bf16x8 ah, bf16x8 al, bf16x8 bh, bf16x8 bl, floatx4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+  return c;
+}
+
+__device__ __forceinline__ bf16x8 ldfrag(const unsigned short* p) {
+  const u16x8 v = *reinterpret_cast<const u16x8*>(p);
+  return __builtin_bit_cast(bf16x8, v);
+}
+
+struct SplitSynthArgs {
+  const unsigned short* tab[4];  // Pbar hi, Pbar lo, Tbar hi, Tbar lo: per m [i][kpad], k = n - m
+  const int64_t* toff;           // per m element offset of the split tables
+  const int32_t* kpad;           // per m padded K (multiple of 32)
+  const double2* psi;
+  const double2* chi;
+  double2* out[6];
+  const int64_t* off;
+  const double* node;
+  int nr, nrc, nz;
+  double kap0;
+};
+
+// B staging: [buf][var][col][k] with var = input(psi, chi) x scaled(1, L) x part(re, im) x (hi, lo)
+__global__ __launch_bounds__(256) void split_synth_kernel(SplitSynthArgs a) {
+  const int m = blockIdx.z;
+  const int row0 = blockIdx.y * TM;
+  const int kk0 = blockIdx.x * TC;
+  if (row0 >= a.nr || kk0 >= a.nz) return;
+  const int K = a.nrc > m ? a.nrc - m : 0;
+  const int nr = a.nr, nz = a.nz;
+  const int kp = a.kpad[m];
+  const double2* __restrict__ ps = a.psi + a.off[m] * nz;
+  const double2* __restrict__ ch = a.chi + a.off[m] * nz;
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][16][TC][TK];  // 32 KB
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rowl = row0 + wave * 16 + (lane & 15);
+  const int kg = 8 * (lane >> 4);
+  const bool rowok = rowl < nr;
+  const unsigned short* tp[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) tp[t] = a.tab[t] + a.toff[m] + (int64_t)(rowok ? rowl : 0) * kp + kg;
+
+  floatx4 acc[7][2];
+#pragma unroll
+  for (int p = 0; p < 7; ++p) acc[p][0] = acc[p][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  // each thread stages 2 (k, col) entries of psi and chi per chunk
+  auto stage = [&](int buf, int k0) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = tid + 256 * h;
+      const int kr = e >> 4, c = e & 15;
+      const int k = k0 + kr, kk = kk0 + c;
+      const bool ok = k < K && kk < nz;
+      const double Ln = (double)(k + m) * (k + m + 1.0);
+      const double2 vp = ok ? ps[(int64_t)k * nz + kk] : make_double2(0.0, 0.0);
+      const double2 vc = ok ? ch[(int64_t)k * nz + kk] : make_double2(0.0, 0.0);
+      const double vals[8] = {vp.x, vp.y, Ln * vp.x, Ln * vp.y, vc.x, vc.y, Ln * vc.x, Ln * vc.y};
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        unsigned short hi, lo;
+        split2(vals[q], hi, lo);
+        Bs[buf][2 * q][c][kr] = hi;
+        Bs[buf][2 * q + 1][c][kr] = lo;
+      }
+    }
+  };
+  const int nk = (K + TK - 1) / TK;
+  stage(0, 0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    const int64_t ko = (int64_t)kt * TK;
+    const bf16x8 pH = ldfrag(tp[0] + ko), pL = ldfrag(tp[1] + ko);
+    const bf16x8 tH = ldfrag(tp[2] + ko), tL = ldfrag(tp[3] + ko);
+    if (kt + 1 < nk) stage(buf ^ 1, (kt + 1) * TK);
+    const int c = lane & 15;
+    // var index: q = 0 psi re, 1 psi im, 2 Lpsi re, 3 Lpsi im, 4 chi re, 5 chi im, 6 Lchi re, 7 Lchi im
+    bf16x8 bh[8], bl[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      bh[q] = ldfrag(&Bs[buf][2 * q][c][kg]);
+      bl[q] = ldfrag(&Bs[buf][2 * q + 1][c][kg]);
+    }
+#pragma unroll
+    for (int ri = 0; ri < 2; ++ri) {
+      acc[0][ri] = mfma3(pH, pL, bh[0 + ri], bl[0 + ri], acc[0][ri]);  // A1 = P psi
+      acc[1][ri] = mfma3(tH, tL, bh[0 + ri], bl[0 + ri], acc[1][ri]);  // A2 = T psi
+      acc[2][ri] = mfma3(pH, pL, bh[2 + ri], bl[2 + ri], acc[2][ri]);  // A3 = P L psi
+      acc[3][ri] = mfma3(pH, pL, bh[4 + ri], bl[4 + ri], acc[3][ri]);  // B1 = P chi
+      acc[4][ri] = mfma3(tH, tL, bh[4 + ri], bl[4 + ri], acc[4][ri]);  // B2 = T chi
+      acc[5][ri] = mfma3(pH, pL, bh[6 + ri], bl[6 + ri], acc[5][ri]);  // B3 = P L chi
+      acc[6][ri] = mfma3(tH, tL, bh[6 + ri], bl[6 + ri], acc[6][ri]);  // B4 = T L chi
+    }
+    __syncthreads();
+  }
+  const int kk = kk0 + (lane & 15);
+  if (kk >= nz) return;
+  const double kap = a.kap0 * kval(kk, nz);
+  const double fm = (double)m;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = row0 + wave * 16 + 4 * (lane >> 4) + v;
+    if (i >= nr) continue;
+    const double rinv = a.node[i], q = a.node[nr + i], opx = a.node[2 * nr + i];
+    const double2 A1 = make_double2(acc[0][0][v], acc[0][1][v]);
+    const double2 A2 = make_double2(acc[1][0][v], acc[1][1][v]);
+    const double2 A3 = make_double2(acc[2][0][v], acc[2][1][v]);
+    const double2 B1 = make_double2(acc[3][0][v], acc[3][1][v]);
+    const double2 B2 = make_double2(acc[4][0][v], acc[4][1][v]);
+    const double2 B3 = make_double2(acc[5][0][v], acc[5][1][v]);
+    const double2 B4 = make_double2(acc[6][0][v], acc[6][1][v]);
+    const double2 ur = make_double2(-(fm * A1.y + kap * B2.y) * rinv, (fm * A1.x + kap * B2.x) * rinv);
+    const double2 up = make_double2((-A2.x - fm * kap * B1.x) * rinv, (-A2.y - fm * kap * B1.y) * rinv);
+    const double2 uz = make_double2(q * B3.x, q * B3.y);
+    const double tr = kap * A2.x + fm * q * B3.x + fm * kap * kap * B1.x;
+    const double ti = kap * A2.y + fm * q * B3.y + fm * kap * kap * B1.y;
+    const double2 wr = make_double2(-ti * rinv, tr * rinv);
+    const double2 wp = make_double2((-fm * kap * A1.x - q * (B4.x - 2.0 * opx * B3.x) - kap * kap * B2.x) * rinv,
+                                    (-fm * kap * A1.y - q * (B4.y - 2.0 * opx * B3.y) - kap * kap * B2.y) * rinv);
+    const double2 wz = make_double2(q * A3.x, q * A3.y);
+    const int64_t o = ((int64_t)m * nr + i) * nz + kk;
+    a.out[0][o] = ur;
+    a.out[1][o] = up;
+    a.out[2][o] = uz;
+    a.out[3][o] = wr;
+    a.out[4][o] = wp;
+    a.out[5][o] = wz;
+  }
+}
+
+struct SplitProjArgs {
+  const unsigned short* tab[4];  // W Pbar hi, lo, W Q hi, lo: per m [n-m][ipad], k = i
+  const int64_t* toff;
+  int ipad;
+  const double2* in[3];
+  double2* out[3];
+  const int64_t* off;
+  int nr, nrc, nz, kmax, nkact;
+  double kap0;
+};
+
+__device__ __forceinline__ int active_kk(int a, int kmax, int nz) {
+  return (a <= kmax) ? a : nz - (2 * kmax + 1 - a);
+}
+
+__global__ __launch_bounds__(256) void split_proj_kernel(SplitProjArgs a) {
+  const int m = blockIdx.z;
+  const int row0 = blockIdx.y * TM;
+  const int c0 = blockIdx.x * TC;
+  const int rows = a.nrc > m ? a.nrc - m : 0;
+  if (row0 >= rows || c0 >= a.nkact) return;
+  const int nr = a.nr, nz = a.nz;
+  const double2* __restrict__ X0 = a.in[0] + (int64_t)m * nr * nz;
+  const double2* __restrict__ X1 = a.in[1] + (int64_t)m * nr * nz;
+  const double2* __restrict__ X2 = a.in[2] + (int64_t)m * nr * nz;
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][12][TC][TK];  // 24 KB
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rowl = row0 + wave * 16 + (lane & 15);
+  const int kg = 8 * (lane >> 4);
+  const bool rowok = rowl < rows;
+  const unsigned short* tp[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) tp[t] = a.tab[t] + a.toff[m] + (int64_t)(rowok ? rowl : 0) * a.ipad + kg;
+  floatx4 acc[5][2];
+#pragma unroll
+  for (int p = 0; p < 5; ++p) acc[p][0] = acc[p][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+  auto stage = [&](int buf, int k0) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = tid + 256 * h;
+      const int kr = e >> 4, c = e & 15;
+      const int k = k0 + kr, ca = c0 + c;
+      const bool ok = k < nr && ca < a.nkact;
+      const int kk = ok ? active_kk(ca, a.kmax, nz) : 0;
+      const int64_t idx = (int64_t)k * nz + kk;
+      const double2 v0 = ok ? X0[idx] : make_double2(0.0, 0.0);
+      const double2 v1 = ok ? X1[idx] : make_double2(0.0, 0.0);
+      const double2 v2 = ok ? X2[idx] : make_double2(0.0, 0.0);
+      const double vals[6] = {v0.x, v0.y, v1.x, v1.y, v2.x, v2.y};
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        unsigned short hi, lo;
+        split2(vals[q], hi, lo);
+        Bs[buf][2 * q][c][kr] = hi;
+        Bs[buf][2 * q + 1][c][kr] = lo;
+      }
+    }
+  };
+  const int nk = (nr + TK - 1) / TK;
+  stage(0, 0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    const int64_t ko = (int64_t)kt * TK;
+    const bf16x8 pH = ldfrag(tp[0] + ko), pL = ldfrag(tp[1] + ko);
+    const bf16x8 qH = ldfrag(tp[2] + ko), qL = ldfrag(tp[3] + ko);
+    if (kt + 1 < nk) stage(buf ^ 1, (kt + 1) * TK);
+    const int c = lane & 15;
+    bf16x8 bh[6], bl[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      bh[q] = ldfrag(&Bs[buf][2 * q][c][kg]);
+      bl[q] = ldfrag(&Bs[buf][2 * q + 1][c][kg]);
+    }
+#pragma unroll
+    for (int ri = 0; ri < 2; ++ri) {
+      acc[0][ri] = mfma3(pH, pL, bh[0 + ri], bl[0 + ri], acc[0][ri]);  // Pa
+      acc[1][ri] = mfma3(qH, qL, bh[0 + ri], bl[0 + ri], acc[1][ri]);  // Qa
+      acc[2][ri] = mfma3(pH, pL, bh[2 + ri], bl[2 + ri], acc[2][ri]);  // Pb
+      acc[3][ri] = mfma3(qH, qL, bh[2 + ri], bl[2 + ri], acc[3][ri]);  // Qb
+      acc[4][ri] = mfma3(pH, pL, bh[4 + ri], bl[4 + ri], acc[4][ri]);  // Pc
+    }
+    __syncthreads();
+  }
+  const int cidx = c0 + (lane & 15);
+  if (cidx >= a.nkact) return;
+  const int kk = active_kk(cidx, a.kmax, nz);
+  const double kap = a.kap0 * kval(kk, nz);
+  const double fm = (double)m;
+  const int64_t tb = a.off[m];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = row0 + wave * 16 + 4 * (lane >> 4) + v;
+    if (r >= rows) continue;
+    const double2 Pa = make_double2(acc[0][0][v], acc[0][1][v]);
+    const double2 Qa = make_double2(acc[1][0][v], acc[1][1][v]);
+    const double2 Pb = make_double2(acc[2][0][v], acc[2][1][v]);
+    const double2 Qb = make_double2(acc[3][0][v], acc[3][1][v]);
+    const double2 Pc = make_double2(acc[4][0][v], acc[4][1][v]);
+    const int64_t o = (tb + r) * nz + kk;
+    a.out[0][o] = make_double2(-Qb.x + fm * Pa.y, -Qb.y - fm * Pa.x);
+    a.out[1][o] = make_double2(kap * Qa.y - fm * kap * Pb.x, -kap * Qa.x - fm * kap * Pb.y);
+    a.out[2][o] = Pc;
+  }
+}
+
+mlg_status check(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(MLG_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return MLG_OK;
+}
+
+}  // namespace
+
+mlg_status launch_split_synth(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,
+                              hipStream_t s) {
+  SplitSynthArgs a{};
+  for (int t = 0; t < 4; ++t) a.tab[t] = p->d_split_syn[t];
+  a.toff = p->d_split_syn_off;
+  a.kpad = p->d_split_syn_kpad;
+  a.psi = reinterpret_cast<const double2*>(psi);
+  a.chi = reinterpret_cast<const double2*>(chi);
+  for (int i = 0; i < 6; ++i) a.out[i] = reinterpret_cast<double2*>(out6[i]);
+  a.off = p->d_goff;
+  a.node = p->d_node;
+  a.nr = p->nr;
+  a.nrc = p->nrc;
+  a.nz = p->nz;
+  a.kap0 = 2.0 * M_PI / p->g.lz;
+  dim3 grid((unsigned)((p->nz + TC - 1) / TC), (unsigned)((p->nr + TM - 1) / TM), (unsigned)p->M);
+  p->timing.begin("synth_gemm", s);
+  split_synth_kernel<<<grid, 256, 0, s>>>(a);
+  p->timing.end(s);
+  return check("split_synth_kernel");
+}
+
+mlg_status launch_split_proj(const mlg_plan_s* p, double* const* in3, double* const* out3, int mmax, int kmax,
+                             hipStream_t s) {
+  SplitProjArgs a{};
+  for (int t = 0; t < 4; ++t) a.tab[t] = p->d_split_prj[t];
+  a.toff = p->d_split_prj_off;
+  a.ipad = p->split_ipad;
+  for (int i = 0; i < 3; ++i) {
+    a.in[i] = reinterpret_cast<const double2*>(in3[i]);
+    a.out[i] = reinterpret_cast<double2*>(out3[i]);
+  }
+  a.off = p->d_goff;
+  a.nr = p->nr;
+  a.nrc = p->nrc;
+  a.nz = p->nz;
+  a.kmax = kmax;
+  a.nkact = (p->nz == 1) ? 1 : 2 * kmax + 1;
+  a.kap0 = 2.0 * M_PI / p->g.lz;
+  if (mmax <= 0 || a.nkact <= 0) return MLG_OK;
+  dim3 grid((unsigned)((a.nkact + TC - 1) / TC), (unsigned)((p->nrc + TM - 1) / TM), (unsigned)mmax);
+  p->timing.begin("proj_gemm", s);
+  split_proj_kernel<<<grid, 256, 0, s>>>(a);
+  p->timing.end(s);
+  return check("split_proj_kernel");
+}
+
+}  // namespace mlg

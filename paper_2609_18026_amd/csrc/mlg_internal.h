@@ -92,6 +92,13 @@ struct mlg_plan_s {
   int64_t* d_goff = nullptr;
   int64_t ngram = 0;
   int max_rows_fwd = 0, max_rows_bwd = 0;
+  // split-bfloat16 tables (MLG_SPLIT_BF16 plans): hi / lo parts, rows padded to 32 entries
+  unsigned short* d_split_syn[4] = {nullptr, nullptr, nullptr, nullptr};  // Pbar^T hi/lo, Tbar^T hi/lo [i][kpad]
+  int64_t* d_split_syn_off = nullptr;
+  int32_t* d_split_syn_kpad = nullptr;
+  unsigned short* d_split_prj[4] = {nullptr, nullptr, nullptr, nullptr};  // W Pbar hi/lo, W Q hi/lo [n-m][ipad]
+  int64_t* d_split_prj_off = nullptr;
+  int split_ipad = 0;
   bool use_fast_fft = true;   // register-resident 256-point kernels when a length is 256
   int phi_rad[12] = {0};
   int phi_nrad = 0;
@@ -127,6 +134,11 @@ mlg_status launch_synth_gemm(const mlg_plan_s* p, const double* psi, const doubl
                              hipStream_t s);
 mlg_status launch_proj_gemm(const mlg_plan_s* p, double* const* in3, double* const* out3, int mmax, int kmax,
                             hipStream_t s);
+// gemm_split.hip: the same two products with split-bfloat16 operands and FP32 accumulation
+mlg_status launch_split_synth(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,
+                              hipStream_t s);
+mlg_status launch_split_proj(const mlg_plan_s* p, double* const* in3, double* const* out3, int mmax, int kmax,
+                             hipStream_t s);
 // active column bounds of the projection: m < mmax, |k| <= kmax
 void active_columns(const mlg_plan_s* p, int* mmax, int* kmax);
 mlg_status launch_mask_tri(const mlg_plan_s* p, double* spec, hipStream_t s);

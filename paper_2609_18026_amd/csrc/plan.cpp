@@ -147,9 +147,31 @@ mlg_status upload(T** dst, const std::vector<T>& src) {
 
 void free_plan_device(mlg_plan_s* p) {
   void* ptrs[] = {p->d_Pb, p->d_Pf, p->d_Tb, p->d_Qf, p->d_node, p->d_tw_phi, p->d_tw_z,
-                  p->d_row_m, p->d_desc_fwd, p->d_desc_bwd, p->d_gram, p->d_goff};
+                  p->d_row_m, p->d_desc_fwd, p->d_desc_bwd, p->d_gram, p->d_goff,
+                  p->d_split_syn[0], p->d_split_syn[1], p->d_split_syn[2], p->d_split_syn[3],
+                  p->d_split_syn_off, p->d_split_syn_kpad, p->d_split_prj[0], p->d_split_prj[1],
+                  p->d_split_prj[2], p->d_split_prj[3], p->d_split_prj_off};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
+}
+
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+uint16_t bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float bf16_float(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+void split_into(double x, uint16_t* hi, uint16_t* lo) {
+  const float f = (float)x;
+  *hi = bf16_bits(f);
+  *lo = bf16_bits(f - bf16_float(*hi));
 }
 
 }  // namespace
@@ -202,6 +224,48 @@ mlg_status build_plan(mlg_plan_s* p) {
         Qf[base + (size_t)i * K + (n - m)] = (double)(wl[i] * Q);
       }
     }
+  }
+  // ---------------- split-bfloat16 tables (MLG_SPLIT_BF16 plans only)
+  if (p->prec == MLG_SPLIT_BF16) {
+    std::vector<int64_t> soff(M + 1, 0), poff(M + 1, 0);
+    std::vector<int32_t> kpad(M, 0);
+    const int ipad = (nr + 31) / 32 * 32;
+    p->split_ipad = ipad;
+    for (int m = 0; m < M; ++m) {
+      const int K = std::max(nrc - m, 0);
+      kpad[m] = (K + 31) / 32 * 32;
+      soff[m + 1] = soff[m] + (int64_t)nr * kpad[m];
+      poff[m + 1] = poff[m] + (int64_t)K * ipad;
+    }
+    std::vector<uint16_t> sy[4], pj[4];
+    for (int t = 0; t < 4; ++t) {
+      sy[t].assign(std::max<int64_t>(soff[M], 1), 0);
+      pj[t].assign(std::max<int64_t>(poff[M], 1), 0);
+    }
+    for (int m = 0; m < M; ++m) {
+      const int K = std::max(nrc - m, 0);
+      const size_t base = (size_t)p->off[m] * nr;
+      for (int kk = 0; kk < K; ++kk)
+        for (int i = 0; i < nr; ++i) {
+          const double P = Pb[base + (size_t)kk * nr + i];
+          const double T = Tb[base + (size_t)kk * nr + i];
+          const double WP = Pf[base + (size_t)i * K + kk];
+          const double WQ = Qf[base + (size_t)i * K + kk];
+          const int64_t s1 = soff[m] + (int64_t)i * kpad[m] + kk;  // [i][n - m]
+          const int64_t s2 = poff[m] + (int64_t)kk * ipad + i;     // [n - m][i]
+          split_into(P, &sy[0][s1], &sy[1][s1]);
+          split_into(T, &sy[2][s1], &sy[3][s1]);
+          split_into(WP, &pj[0][s2], &pj[1][s2]);
+          split_into(WQ, &pj[2][s2], &pj[3][s2]);
+        }
+    }
+    mlg_status st2;
+    for (int t = 0; t < 4; ++t) {
+      if ((st2 = upload(&p->d_split_syn[t], sy[t])) || (st2 = upload(&p->d_split_prj[t], pj[t]))) return st2;
+    }
+    if ((st2 = upload(&p->d_split_syn_off, soff)) || (st2 = upload(&p->d_split_syn_kpad, kpad)) ||
+        (st2 = upload(&p->d_split_prj_off, poff)))
+      return st2;
   }
   // ---------------- Gram factors for the elliptic solves
   GramFactors gf;
