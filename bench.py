@@ -102,6 +102,43 @@ def cpu_baseline(n_sample: int):
                        f"(1/{(256 // n_sample) ** 3} of the 256^3 grid points), {dt:.1f} s")
 
 
+def bench_batched(torch, args, stream, e0, e1, count=64, seed=3):
+    """64 uneven 2D KPP instances in one persistent launch (autotuned), FP64 and FP32."""
+    import synth
+    from paper_2609_18026_amd import MLG_FP32, Batch, mlg_grid
+    insts = synth.batched_instances(count, seed)
+    grids = [mlg_grid(d["nr"], d["nphi"], 1, 0, 0, 0, d["ell"], 2 * np.pi, 1) for d in insts]
+    dofs = sum(d["nr"] * d["nphi"] for d in insts)
+    res = {"instances": count, "grid_points": dofs}
+    outs = {}
+    for prec, name in ((0, "fp64"), (MLG_FP32, "fp32")):
+        b = Batch(grids, prec=prec)
+        sin = b.empty_spec()
+        for k, d in enumerate(insts):
+            M = d["nphi"] // 2
+            S = synth.geometric_spectrum(M, d["nr"], 1, 1, seed=1000 + k, a=0.9, b=0.85, c=1.0)
+            sin[int(b.offsets[k]):int(b.offsets[k + 1])] = torch.from_numpy(synth.to_packed(S)[:, 0]).to(sin.dtype).cuda()
+        sout = b.empty_spec()
+        chosen, tune_ms = b.autotune(0.25, sin, sout)
+        for _ in range(args.warmup):
+            b.rhs_kpp(0.25, sin, sout)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            b.rhs_kpp(0.25, sin, sout)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        outs[name] = sout.to(torch.complex128)
+        res[name] = {"ms_per_launch": round(ms, 4), "gdofs": round(dofs / (ms / 1e3) / 1e9, 4),
+                     "autotuned": b.get_config()}
+        b.close()
+    res["fp32_rel_err_vs_fp64"] = float(torch.linalg.vector_norm(outs["fp32"] - outs["fp64"]) /
+                                        torch.linalg.vector_norm(outs["fp64"]))
+    log(f"bench: batched 2D fp64 {res['fp64']['ms_per_launch']:.3f} ms, fp32 {res['fp32']['ms_per_launch']:.3f} ms")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,6 +268,7 @@ def main():
     out["split_bf16"] = {"ms_per_step": round(sms, 4), "gdofs": round(n ** 3 / (sms / 1e3) / 1e9, 4),
                          "rel_err_velocity_of_output_vs_fp64": verr, "rel_err_psi_coefficients_vs_fp64": cerr}
     log(f"bench: split-bf16 {sms:.3f} ms/step, velocity rel err {verr:.2e} (coefficients {cerr:.2e})")
+    out["batched_2d"] = bench_batched(torch, args, stream, e0, e1)
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)

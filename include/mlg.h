@@ -150,6 +150,41 @@ mlg_status mlg_synthesize(mlg_plan plan, const void* psi, const void* chi, void*
 mlg_status mlg_timing_enable(mlg_plan plan, int enable);
 mlg_status mlg_timing_read(mlg_plan plan, const char* kernel, double* total_ms, int64_t* launches);
 
+/* ---------------------------------------------------------------- batched 2D instances
+ * Many independent 2D fields (N_z = 1) of uneven sizes, each with its own grid, advanced by one
+ * persistent (cooperative) kernel launch: the pseudospectral KPP term
+ * R_b = Mask(F(gamma u (1 - u))), u = B(u_hat_b), of Sec. 3.3 and Sec. 5.2 (Eq. kpp), for every
+ * instance b.  Spectra of all instances are packed in one device buffer: instance b occupies the
+ * complex elements [spec_offsets[b], spec_offsets[b+1]) in the packed triangular layout of a
+ * single 2D plan.  Data are complex128 (MLG_FP64) or complex64 (MLG_FP32); tables and the in-kernel
+ * Legendre recurrence are built in FP64. */
+typedef struct mlg_batch_s* mlg_batch;
+
+/* Launch shape of the persistent kernel: regenerate Pbar by its recurrence in the backward
+ * phase (1) or stream tables (0); threads per block (64, 128, 256); blocks per compute unit
+ * (1..8, capped by occupancy); azimuthal lines per work item (even, 2..32). */
+typedef struct {
+  int32_t recurrence, threads, blocks_per_cu, lines;
+} mlg_batch_config;
+
+/* Build per-instance nodes, tables and work lists on the host (FP64) and copy them to 'device'.
+ * Each grid needs N_z = 1, 2 <= N_r <= 256, 2 <= N_phi <= 256 with prime factors 2, 3, 5, ell > 0.
+ * Errors: MLG_E_ARG, MLG_E_UNSUPPORTED, MLG_E_ALLOC, MLG_E_DEVICE; *out is NULL on failure. */
+mlg_status mlg_batch_create(int count, const mlg_grid* grids, mlg_precision prec, int device, mlg_batch* out);
+mlg_status mlg_batch_destroy(mlg_batch batch);
+/* spec_offsets: host array of count + 1 entries (may be NULL); workspace_bytes may be NULL. */
+mlg_status mlg_batch_query(mlg_batch batch, int64_t* spec_offsets, int64_t* workspace_bytes);
+/* One persistent launch over all instances.  spec_in and spec_out must not alias. */
+mlg_status mlg_batch_rhs_scalar(mlg_batch batch, double gamma, const void* spec_in, void* spec_out, void* ws,
+                                void* stream);
+mlg_status mlg_batch_set_config(mlg_batch batch, const mlg_batch_config* config);
+mlg_status mlg_batch_get_config(mlg_batch batch, mlg_batch_config* config);
+/* Autotuner: times every candidate launch shape (recurrence or tables x 128/256 threads x 1, 2, 4
+ * blocks per CU x 4, 8, 16 lines per item) on the given buffers with HIP events, keeps the fastest
+ * for later calls and returns it (chosen, best_ms may be NULL).  Overwrites spec_out. */
+mlg_status mlg_batch_autotune(mlg_batch batch, double gamma, const void* spec_in, void* spec_out, void* ws,
+                              void* stream, mlg_batch_config* chosen, double* best_ms);
+
 /* Message for the last error on this thread ("" if none). */
 const char* mlg_last_error(void);
 

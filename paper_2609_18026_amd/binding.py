@@ -43,7 +43,13 @@ _lib = None
 
 EXPORTS = ["mlg_plan_create", "mlg_plan_destroy", "mlg_plan_query", "mlg_plan_nodes", "mlg_forward",
            "mlg_backward", "mlg_rhs_scalar", "mlg_rhs_tp", "mlg_synthesize", "mlg_timing_enable", "mlg_timing_read",
-           "mlg_last_error"]
+           "mlg_batch_create", "mlg_batch_destroy", "mlg_batch_query", "mlg_batch_rhs_scalar", "mlg_batch_set_config",
+           "mlg_batch_get_config", "mlg_batch_autotune", "mlg_last_error"]
+
+
+class mlg_batch_config(ctypes.Structure):
+    _fields_ = [("recurrence", ctypes.c_int32), ("threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("lines", ctypes.c_int32)]
 
 
 def lib() -> ctypes.CDLL:
@@ -66,6 +72,14 @@ def lib() -> ctypes.CDLL:
     L.mlg_synthesize.argtypes = [vp, vp, vp, vp, vp, vp]
     L.mlg_timing_enable.argtypes = [vp, i32]
     L.mlg_timing_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)]
+    L.mlg_batch_create.argtypes = [i32, ctypes.POINTER(mlg_grid), i32, i32, ctypes.POINTER(vp)]
+    L.mlg_batch_destroy.argtypes = [vp]
+    L.mlg_batch_query.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int64)]
+    L.mlg_batch_rhs_scalar.argtypes = [vp, f64, vp, vp, vp, vp]
+    L.mlg_batch_set_config.argtypes = [vp, ctypes.POINTER(mlg_batch_config)]
+    L.mlg_batch_get_config.argtypes = [vp, ctypes.POINTER(mlg_batch_config)]
+    L.mlg_batch_autotune.argtypes = [vp, f64, vp, vp, vp, vp, ctypes.POINTER(mlg_batch_config),
+                                     ctypes.POINTER(f64)]
     for name in EXPORTS[:-1]:
         getattr(L, name).restype = ctypes.c_int
     L.mlg_last_error.restype = ctypes.c_char_p
@@ -207,6 +221,92 @@ class Plan:
     def close(self):
         if self.handle:
             mlg_plan_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mlg_batch_create(grids, prec: int = MLG_FP64, device: int = 0) -> int:
+    arr = (mlg_grid * len(grids))(*grids)
+    h = ctypes.c_void_p()
+    _check(lib().mlg_batch_create(len(grids), arr, prec, device, ctypes.byref(h)))
+    return h.value
+
+
+def mlg_batch_destroy(batch: int) -> None:
+    _check(lib().mlg_batch_destroy(batch))
+
+
+def mlg_batch_query(batch: int, count: int):
+    import numpy as np
+    offs = np.zeros(count + 1, dtype=np.int64)
+    ws = ctypes.c_int64()
+    _check(lib().mlg_batch_query(batch, offs.ctypes.data, ctypes.byref(ws)))
+    return offs, ws.value
+
+
+def mlg_batch_rhs_scalar(batch: int, gamma: float, spec_in: int, spec_out: int, ws: int, stream: int = 0) -> None:
+    _check(lib().mlg_batch_rhs_scalar(batch, gamma, spec_in, spec_out, ws, stream))
+
+
+def mlg_batch_set_config(batch: int, cfg: mlg_batch_config) -> None:
+    _check(lib().mlg_batch_set_config(batch, ctypes.byref(cfg)))
+
+
+def mlg_batch_get_config(batch: int) -> mlg_batch_config:
+    c = mlg_batch_config()
+    _check(lib().mlg_batch_get_config(batch, ctypes.byref(c)))
+    return c
+
+
+def mlg_batch_autotune(batch: int, gamma: float, spec_in: int, spec_out: int, ws: int, stream: int = 0):
+    c = mlg_batch_config()
+    ms = ctypes.c_double()
+    _check(lib().mlg_batch_autotune(batch, gamma, spec_in, spec_out, ws, stream, ctypes.byref(c), ctypes.byref(ms)))
+    return c, ms.value
+
+
+class Batch:
+    """Uneven 2D instances advanced together; packed spectra in one torch tensor."""
+
+    def __init__(self, grids, prec=MLG_FP64, device=0):
+        import torch
+        self.count = len(grids)
+        self.prec = prec
+        self.device = device
+        self.handle = mlg_batch_create(grids, prec, device)
+        self.offsets, ws = mlg_batch_query(self.handle, self.count)
+        self.ws = torch.empty(max(ws, 8), dtype=torch.uint8, device=f"cuda:{device}")
+        self.cdtype = torch.complex64 if prec == MLG_FP32 else torch.complex128
+
+    def empty_spec(self):
+        import torch
+        return torch.zeros(int(self.offsets[-1]), dtype=self.cdtype, device=f"cuda:{self.device}")
+
+    def rhs_kpp(self, gamma, spec_in, spec_out):
+        import torch
+        mlg_batch_rhs_scalar(self.handle, gamma, spec_in.data_ptr(), spec_out.data_ptr(), self.ws.data_ptr(),
+                             torch.cuda.current_stream().cuda_stream)
+
+    def autotune(self, gamma, spec_in, spec_out):
+        import torch
+        return mlg_batch_autotune(self.handle, gamma, spec_in.data_ptr(), spec_out.data_ptr(), self.ws.data_ptr(),
+                                  torch.cuda.current_stream().cuda_stream)
+
+    def set_config(self, recurrence, threads, blocks_per_cu, lines):
+        mlg_batch_set_config(self.handle, mlg_batch_config(recurrence, threads, blocks_per_cu, lines))
+
+    def get_config(self):
+        c = mlg_batch_get_config(self.handle)
+        return dict(recurrence=c.recurrence, threads=c.threads, blocks_per_cu=c.blocks_per_cu, lines=c.lines)
+
+    def close(self):
+        if self.handle:
+            mlg_batch_destroy(self.handle)
             self.handle = 0
 
     def __del__(self):

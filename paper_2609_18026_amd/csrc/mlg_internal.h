@@ -113,6 +113,10 @@ struct mlg_plan_s {
 namespace mlg {
 // plan.cpp
 int factor_radices(int n, int* rad);
+// Gauss-Legendre nodes as angles theta_i (ascending x = cos theta) and weights, long double
+void gl_theta(int N, std::vector<long double>& theta, std::vector<long double>& w);
+// Pbar_n^m(cos t) for n = m .. nmax into out[n - m]
+void pbar_col(int m, int nmax, long double t, long double* out);
 // kernels.hip launchers (all enqueue on 'stream')
 mlg_status launch_gemm(const mlg_plan_s* p, const GemmProds& prods, const GemmDesc* d_desc,
                        int max_rows, int ncol, hipStream_t stream);

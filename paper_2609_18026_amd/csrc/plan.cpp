@@ -176,6 +176,9 @@ void split_into(double x, uint16_t* hi, uint16_t* lo) {
 
 }  // namespace
 
+void gl_theta(int N, std::vector<long double>& theta, std::vector<long double>& w) { gauss_legendre_theta(N, theta, w); }
+void pbar_col(int m, int nmax, long double t, long double* out) { pbar_column(m, nmax, t, out); }
+
 mlg_status build_plan(mlg_plan_s* p) {
   const mlg_grid& g = p->g;
   const int nr = p->nr, nrc = p->nrc, M = p->M, nz = p->nz;
