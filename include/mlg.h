@@ -135,6 +135,26 @@ mlg_status mlg_rhs_scalar(mlg_plan plan, int kind, double gamma, const void* spe
 mlg_status mlg_rhs_tp(mlg_plan plan, const double* U, const void* psi, const void* chi,
                       void* psi_n, void* chi_n, void* taps, void* ws, void* stream);
 
+/* ---------------------------------------------------------------- semi-implicit time stepping
+ * ds/dt = A(s) + L s (Sec. 3.3, Eq. split) with L = nu grad^2 - nu_h (-grad^2)^{p/2}
+ * (Eq. dissipation), composed per (m, k) from the truncated horizontal Laplacian of
+ * Eq. del2h-entries (grad^2 = Dbar_m - kappa^2). */
+typedef struct {
+  double nu, nu_h;  /* nu >= 0, nu_h >= 0 */
+  int32_t p;        /* 4, 6 or 8 (used when nu_h > 0) */
+  double dt;        /* > 0 */
+} mlg_dissip;
+
+/* Build (host, long double) and upload the band of L and banded LU factors with partial
+ * pivoting of I - (dt/2) L and I - dt L for every (m, |k|).  Replaces earlier step operators. */
+mlg_status mlg_step_setup(mlg_plan plan, const mlg_dissip* d);
+/* FE-BE step: out = (I - h L)^{-1} (s + h A) with h = dt/2 (half = 1) or h = dt (half = 0); the
+ * Richardson start-up of Sec. 3.3 is s1 = 2 S_{dt/2}(S_{dt/2}(s0)) - S_dt(s0). */
+mlg_status mlg_step_febe(mlg_plan plan, int half, const void* s, const void* A, void* out, void* stream);
+/* AB-CN step, Eq. abcn: out = (I - dt/2 L)^{-1} [(I + dt/2 L) s + dt/2 (3 A_now - A_prev)].
+ * All arrays spectral (packed triangular); out must not alias s. */
+mlg_status mlg_step_abcn(mlg_plan plan, const void* s, const void* A_now, const void* A_prev, void* out, void* stream);
+
 /* Nodal velocity and vorticity of a toroidal-poloidal pair (Sec. 3.2, Eq. tp):
  * u = curl(psi z) + curl curl(chi z), omega = curl u.  'uw' is a device buffer of
  * 6 * phys_elems reals receiving u_r, u_phi, u_z, w_r, w_phi, w_z (physical layout each).

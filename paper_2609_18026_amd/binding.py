@@ -44,7 +44,12 @@ _lib = None
 EXPORTS = ["mlg_plan_create", "mlg_plan_destroy", "mlg_plan_query", "mlg_plan_nodes", "mlg_forward",
            "mlg_backward", "mlg_rhs_scalar", "mlg_rhs_tp", "mlg_synthesize", "mlg_timing_enable", "mlg_timing_read",
            "mlg_batch_create", "mlg_batch_destroy", "mlg_batch_query", "mlg_batch_rhs_scalar", "mlg_batch_set_config",
-           "mlg_batch_get_config", "mlg_batch_autotune", "mlg_last_error"]
+           "mlg_batch_get_config", "mlg_batch_autotune", "mlg_step_setup", "mlg_step_febe", "mlg_step_abcn",
+           "mlg_last_error"]
+
+
+class mlg_dissip(ctypes.Structure):
+    _fields_ = [("nu", ctypes.c_double), ("nu_h", ctypes.c_double), ("p", ctypes.c_int32), ("dt", ctypes.c_double)]
 
 
 class mlg_batch_config(ctypes.Structure):
@@ -80,6 +85,9 @@ def lib() -> ctypes.CDLL:
     L.mlg_batch_get_config.argtypes = [vp, ctypes.POINTER(mlg_batch_config)]
     L.mlg_batch_autotune.argtypes = [vp, f64, vp, vp, vp, vp, ctypes.POINTER(mlg_batch_config),
                                      ctypes.POINTER(f64)]
+    L.mlg_step_setup.argtypes = [vp, ctypes.POINTER(mlg_dissip)]
+    L.mlg_step_febe.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.mlg_step_abcn.argtypes = [vp, vp, vp, vp, vp, vp]
     for name in EXPORTS[:-1]:
         getattr(L, name).restype = ctypes.c_int
     L.mlg_last_error.restype = ctypes.c_char_p
@@ -140,6 +148,19 @@ def mlg_rhs_tp(plan: int, U, psi: int, chi: int, psi_n: int, chi_n: int, taps: i
     if U is not None:
         Uarr = (ctypes.c_double * 3)(*[float(u) for u in U])
     _check(lib().mlg_rhs_tp(plan, Uarr, psi, chi, psi_n, chi_n, taps, ws, stream))
+
+
+def mlg_step_setup(plan: int, nu: float, nu_h: float, p: int, dt: float) -> None:
+    d = mlg_dissip(nu, nu_h, p, dt)
+    _check(lib().mlg_step_setup(plan, ctypes.byref(d)))
+
+
+def mlg_step_febe(plan: int, half: int, s: int, A: int, out: int, stream: int = 0) -> None:
+    _check(lib().mlg_step_febe(plan, half, s, A, out, stream))
+
+
+def mlg_step_abcn(plan: int, s: int, A_now: int, A_prev: int, out: int, stream: int = 0) -> None:
+    _check(lib().mlg_step_abcn(plan, s, A_now, A_prev, out, stream))
 
 
 def mlg_synthesize(plan: int, psi: int, chi: int, uw: int, ws: int, stream: int = 0) -> None:
@@ -212,6 +233,15 @@ class Plan:
     def synthesize(self, psi, chi, uw):
         """uw: float64 tensor of 6 * phys_elems (u_r, u_phi, u_z, w_r, w_phi, w_z)."""
         mlg_synthesize(self.handle, psi.data_ptr(), chi.data_ptr(), uw.data_ptr(), self.ws.data_ptr(), self._stream())
+
+    def step_setup(self, nu, nu_h=0.0, p=8, dt=1e-2):
+        mlg_step_setup(self.handle, nu, nu_h, p, dt)
+
+    def step_febe(self, half, s, A, out):
+        mlg_step_febe(self.handle, half, s.data_ptr(), A.data_ptr(), out.data_ptr(), self._stream())
+
+    def step_abcn(self, s, A_now, A_prev, out):
+        mlg_step_abcn(self.handle, s.data_ptr(), A_now.data_ptr(), A_prev.data_ptr(), out.data_ptr(), self._stream())
 
     def taps_buffer(self):
         import torch

@@ -266,6 +266,37 @@ mlg_status mlg_rhs_tp(mlg_plan p, const double* U, const void* psi, const void* 
   return launch_projection(p, csrc, static_cast<double*>(psi_n), static_cast<double*>(chi_n), w.scratch, tsrc, s);
 }
 
+mlg_status mlg_step_setup(mlg_plan p, const mlg_dissip* d) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!d) return fail(MLG_E_ARG, "dissip is NULL");
+  if (!std::isfinite(d->nu) || !std::isfinite(d->nu_h) || !std::isfinite(d->dt))
+    return fail(MLG_E_NONFINITE, "non-finite step parameters");
+  if (d->nu < 0 || d->nu_h < 0 || !(d->dt > 0)) return fail(MLG_E_ARG, "need nu >= 0, nu_h >= 0, dt > 0");
+  if (d->p != 4 && d->p != 6 && d->p != 8) return fail(MLG_E_ARG, "p must be 4, 6 or 8");
+  DeviceGuard guard(p->device);
+  return step_setup(p, d);
+}
+
+mlg_status mlg_step_febe(mlg_plan p, int half, const void* s, const void* A, void* out, void* stream) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!p->step_ready) return fail(MLG_E_ARG, "mlg_step_setup has not been called");
+  if (!s || !A || !out) return fail(MLG_E_ARG, "null buffer");
+  if (out == s || out == A) return fail(MLG_E_ARG, "out must not alias the inputs");
+  DeviceGuard guard(p->device);
+  return launch_step(p, 0, half ? 0 : 1, static_cast<const double*>(s), static_cast<const double*>(A), nullptr,
+                     static_cast<double*>(out), static_cast<hipStream_t>(stream));
+}
+
+mlg_status mlg_step_abcn(mlg_plan p, const void* s, const void* A_now, const void* A_prev, void* out, void* stream) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!p->step_ready) return fail(MLG_E_ARG, "mlg_step_setup has not been called");
+  if (!s || !A_now || !A_prev || !out) return fail(MLG_E_ARG, "null buffer");
+  if (out == s || out == A_now || out == A_prev) return fail(MLG_E_ARG, "out must not alias the inputs");
+  DeviceGuard guard(p->device);
+  return launch_step(p, 1, 0, static_cast<const double*>(s), static_cast<const double*>(A_now),
+                     static_cast<const double*>(A_prev), static_cast<double*>(out), static_cast<hipStream_t>(stream));
+}
+
 mlg_status mlg_synthesize(mlg_plan p, const void* psi, const void* chi, void* uw, void* ws, void* stream) {
   if (mlg_status st = check_plan(p)) return st;
   if (!psi || !chi || !uw || !ws) return fail(MLG_E_ARG, "null buffer");

@@ -99,6 +99,12 @@ struct mlg_plan_s {
   unsigned short* d_split_prj[4] = {nullptr, nullptr, nullptr, nullptr};  // W Pbar hi/lo, W Q hi/lo [n-m][ipad]
   int64_t* d_split_prj_off = nullptr;
   int split_ipad = 0;
+  // semi-implicit step operators (mlg_step_setup)
+  double* d_step_band = nullptr;
+  double* d_step_fac[2] = {nullptr, nullptr};
+  int step_b = 0, step_nkabs = 0;
+  double step_dt = 0;
+  bool step_ready = false;
   bool use_fast_fft = true;   // register-resident 256-point kernels when a length is 256
   int phi_rad[12] = {0};
   int phi_nrad = 0;
@@ -143,6 +149,10 @@ mlg_status launch_split_synth(const mlg_plan_s* p, const double* psi, const doub
                               hipStream_t s);
 mlg_status launch_split_proj(const mlg_plan_s* p, double* const* in3, double* const* out3, int mmax, int kmax,
                              hipStream_t s);
+// step.hip: semi-implicit operators and the step kernel (mode 0 FE-BE, 1 AB-CN; which 0: h = dt/2, 1: h = dt)
+mlg_status step_setup(mlg_plan_s* p, const mlg_dissip* d);
+mlg_status launch_step(const mlg_plan_s* p, int mode, int which, const double* s, const double* a1, const double* a0,
+                       double* out, hipStream_t st);
 // active column bounds of the projection: m < mmax, |k| <= kmax
 void active_columns(const mlg_plan_s* p, int* mmax, int* kmax);
 mlg_status launch_mask_tri(const mlg_plan_s* p, double* spec, hipStream_t s);
