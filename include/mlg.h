@@ -205,6 +205,89 @@ mlg_status mlg_batch_get_config(mlg_batch batch, mlg_batch_config* config);
 mlg_status mlg_batch_autotune(mlg_batch batch, double gamma, const void* spec_in, void* spec_out, void* ws,
                               void* stream, mlg_batch_config* chosen, double* best_ms);
 
+/* ---------------------------------------------------------------- spectral truncation
+ * Coefficients of the mapped Legendre-Fourier expansion (Sec. 3.1, Eq. expansion) do not depend
+ * on the grid size, since Pbar_n^m is independent of N_r; moving a state between two plans is
+ * therefore a copy: dst(m, n, k) = src(m, n, k) where the source stores (m, n, k) and the
+ * destination's axial chop keeps k, else 0.  Both plans FP64 with equal ell and L_z
+ * (MLG_E_ARG otherwise); src and dst are packed spectral arrays of their plans; no aliasing. */
+mlg_status mlg_truncate(mlg_plan from, mlg_plan to, const void* src, void* dst, void* stream);
+
+/* ---------------------------------------------------------------- learned coarse-grid closure
+ * An addition to the paper's method (no passage defines it).  For a coarse FP64 plan with
+ * N_r^c <= 64, a network corrects every (m, k) column of the toroidal-poloidal nonlinear term:
+ * (psi_n, chi_n) <- (psi_n, chi_n) + C(psi, chi).  Columns: m = 0 .. M-1 times the axial slots
+ * kept by the chop, in FFT order (k = 0, 1, .., k_max, -k_max, .., -1); column index
+ * m * n_k + j.  Features of a column (MLG_CLOSURE_NIN = 258): Re psi_n, Im psi_n, Re chi_n,
+ * Im chi_n for n = 0 .. 63 at offsets 0, 64, 128, 192 (zero for n < m or n >= N_r^c), then
+ * m / M and k / k_max.  Outputs (MLG_CLOSURE_NOUT = 256) use the same four blocks of 64.
+ * Network: tanh(W1 x' + b1) -> tanh(W2 h1 + b2) -> W3 h2 + b3 with x' = x * x_scale
+ * (per feature); correction = output * y_scale (per output).  Hidden width 256; products in
+ * bfloat16 on MFMA with FP32 accumulation; FP32 master weights, trained with Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the mean squared error in the
+ * normalised output space.  m = 0 corrections are made Hermitian in k.
+ * The plain solver is the judge: a correction is dropped (fallback: the plain coarse term is
+ * kept) when ||C|| or ||RHS|| is non-finite or ||C|| > beta ||RHS||, norms over both fields. */
+#define MLG_CLOSURE_NIN 258
+#define MLG_CLOSURE_NOUT 256
+#define MLG_CLOSURE_HIDDEN 256
+typedef struct mlg_closure_s* mlg_closure;
+typedef struct {
+  int32_t max_batch;  /* largest training batch (rows), 1 .. 2^20 */
+  double beta;        /* judge threshold, >= 0 */
+} mlg_closure_cfg;
+
+/* Parameters in host order W1 [256][258], b1 [256], W2 [256][256], b2, W3 [256][256], b3. */
+int32_t mlg_closure_param_count(void);
+/* The closure keeps a pointer to 'coarse', which must outlive it.  Weights start at zero and
+ * scales at one.  Errors: MLG_E_ARG, MLG_E_UNSUPPORTED (non-FP64 plan or N_r^c > 64), MLG_E_ALLOC. */
+mlg_status mlg_closure_create(const mlg_closure_cfg* cfg, mlg_plan coarse, mlg_closure* out);
+mlg_status mlg_closure_destroy(mlg_closure closure);
+mlg_status mlg_closure_columns(mlg_closure closure, int32_t* ncols);
+/* Host arrays of mlg_closure_param_count() floats.  set_params also clears the Adam moments and
+ * step count; get_grads returns the gradient of the last training step.  These synchronise. */
+mlg_status mlg_closure_set_params(mlg_closure closure, const float* params);
+mlg_status mlg_closure_get_params(mlg_closure closure, float* params);
+mlg_status mlg_closure_get_grads(mlg_closure closure, float* grads);
+/* Host arrays: x_scale [258] (finite), y_scale [256] (finite, non-zero). */
+mlg_status mlg_closure_set_scales(mlg_closure closure, const float* x_scale, const float* y_scale);
+mlg_status mlg_closure_get_scales(mlg_closure closure, float* x_scale, float* y_scale);
+/* Raw (unscaled) features of every column of the coarse state (psi, chi): device float
+ * [ncols][258]. */
+mlg_status mlg_closure_features(mlg_closure closure, const void* psi, const void* chi, float* x_out, void* stream);
+/* Raw targets: y_out [ncols][256] (device float) = (ref - coarse term) at the output positions,
+ * with ref the truncated fine term and (psi_n, chi_n) the coarse term, all coarse-plan arrays. */
+mlg_status mlg_closure_targets(mlg_closure closure, const void* ref_psi, const void* ref_chi, const void* psi_n,
+                               const void* chi_n, float* y_out, void* stream);
+/* Network on nb raw feature rows x [nb][258] -> raw outputs y [nb][256] (device floats);
+ * 1 <= nb <= max(max_batch, ncols). */
+mlg_status mlg_closure_forward(mlg_closure closure, const float* x, int32_t nb, float* y, void* stream);
+/* One Adam step on nb rows of the raw data set (data_x [count][258], data_y [count][256], device
+ * floats): rows idx[0 .. nb-1] (device int32, NULL = rows 0 .. nb-1), 1 <= nb <= max_batch.
+ * loss_out (host, may be NULL) receives the batch loss before the update; the call then
+ * synchronises the stream and reports MLG_E_ARG if an index was outside [0, count) (such rows
+ * count as zero rows). */
+mlg_status mlg_closure_train_step(mlg_closure closure, const float* data_x, const float* data_y,
+                                  const int32_t* idx, int64_t count, int32_t nb, float lr, float* loss_out,
+                                  void* stream);
+/* Correct the coarse term (rhs_psi, rhs_chi) of the coarse state (psi, chi) in place, subject to
+ * the judge.  used_fallback (host, may be NULL; non-NULL synchronises the stream) receives 1 when
+ * the correction was dropped.  Calls that overlap on one closure race (shared buffers). */
+mlg_status mlg_closure_infer(mlg_closure closure, const void* psi, const void* chi, void* rhs_psi, void* rhs_chi,
+                             int32_t* used_fallback, void* stream);
+/* Judge decisions so far (synchronises the device). */
+mlg_status mlg_closure_stats(mlg_closure closure, int64_t* calls, int64_t* fallbacks);
+
+/* ---------------------------------------------------------------- time integration of (psi, chi)
+ * nsteps steps of Eq. abcn for both potentials (the operators of mlg_step_setup, which must have
+ * been called), with A = mlg_rhs_tp(U, psi, chi), corrected by 'closure' when non-NULL (its
+ * plan must be 'plan').  start = 1: the first step is the Richardson start-up of Sec. 3.3 and
+ * (hist_psi, hist_chi) are outputs; start = 0: they hold A^{j-1} from the previous call.  On
+ * return they hold A of the last state a step started from.  psi, chi are advanced in place.
+ * tmp: device buffer of 6 * spec_elems complex128; ws: the plan workspace. */
+mlg_status mlg_tp_advance(mlg_plan plan, const double* U, void* psi, void* chi, void* hist_psi, void* hist_chi,
+                          int32_t nsteps, int32_t start, mlg_closure closure, void* tmp, void* ws, void* stream);
+
 /* Message for the last error on this thread ("" if none). */
 const char* mlg_last_error(void);
 

@@ -45,7 +45,17 @@ EXPORTS = ["mlg_plan_create", "mlg_plan_destroy", "mlg_plan_query", "mlg_plan_no
            "mlg_backward", "mlg_rhs_scalar", "mlg_rhs_tp", "mlg_synthesize", "mlg_timing_enable", "mlg_timing_read",
            "mlg_batch_create", "mlg_batch_destroy", "mlg_batch_query", "mlg_batch_rhs_scalar", "mlg_batch_set_config",
            "mlg_batch_get_config", "mlg_batch_autotune", "mlg_step_setup", "mlg_step_febe", "mlg_step_abcn",
+           "mlg_truncate", "mlg_tp_advance", "mlg_closure_param_count", "mlg_closure_create", "mlg_closure_destroy",
+           "mlg_closure_columns", "mlg_closure_set_params", "mlg_closure_get_params", "mlg_closure_get_grads",
+           "mlg_closure_set_scales", "mlg_closure_get_scales", "mlg_closure_features", "mlg_closure_targets",
+           "mlg_closure_forward", "mlg_closure_train_step", "mlg_closure_infer", "mlg_closure_stats",
            "mlg_last_error"]
+
+MLG_CLOSURE_NIN, MLG_CLOSURE_NOUT, MLG_CLOSURE_HIDDEN = 258, 256, 256
+
+
+class mlg_closure_cfg(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int32), ("beta", ctypes.c_double)]
 
 
 class mlg_dissip(ctypes.Structure):
@@ -88,6 +98,24 @@ def lib() -> ctypes.CDLL:
     L.mlg_step_setup.argtypes = [vp, ctypes.POINTER(mlg_dissip)]
     L.mlg_step_febe.argtypes = [vp, i32, vp, vp, vp, vp]
     L.mlg_step_abcn.argtypes = [vp, vp, vp, vp, vp, vp]
+    i64, f32 = ctypes.c_int64, ctypes.c_float
+    L.mlg_truncate.argtypes = [vp, vp, vp, vp, vp]
+    L.mlg_tp_advance.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp]
+    L.mlg_closure_param_count.argtypes = []
+    L.mlg_closure_create.argtypes = [ctypes.POINTER(mlg_closure_cfg), vp, ctypes.POINTER(vp)]
+    L.mlg_closure_destroy.argtypes = [vp]
+    L.mlg_closure_columns.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.mlg_closure_set_params.argtypes = [vp, vp]
+    L.mlg_closure_get_params.argtypes = [vp, vp]
+    L.mlg_closure_get_grads.argtypes = [vp, vp]
+    L.mlg_closure_set_scales.argtypes = [vp, vp, vp]
+    L.mlg_closure_get_scales.argtypes = [vp, vp, vp]
+    L.mlg_closure_features.argtypes = [vp, vp, vp, vp, vp]
+    L.mlg_closure_targets.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.mlg_closure_forward.argtypes = [vp, vp, i32, vp, vp]
+    L.mlg_closure_train_step.argtypes = [vp, vp, vp, vp, i64, i32, f32, ctypes.POINTER(f32), vp]
+    L.mlg_closure_infer.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int32), vp]
+    L.mlg_closure_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     for name in EXPORTS[:-1]:
         getattr(L, name).restype = ctypes.c_int
     L.mlg_last_error.restype = ctypes.c_char_p
@@ -179,6 +207,114 @@ def mlg_timing_read(plan: int, kernel: str):
     return ms.value, n.value
 
 
+def mlg_truncate(src_plan: int, dst_plan: int, src: int, dst: int, stream: int = 0) -> None:
+    _check(lib().mlg_truncate(src_plan, dst_plan, src, dst, stream))
+
+
+def mlg_tp_advance(plan: int, U, psi: int, chi: int, hist_psi: int, hist_chi: int, nsteps: int, start: int,
+                   closure: int, tmp: int, ws: int, stream: int = 0) -> None:
+    u = None if U is None else (ctypes.c_double * 3)(*U)
+    _check(lib().mlg_tp_advance(plan, u, psi, chi, hist_psi, hist_chi, nsteps, start, closure or None, tmp, ws,
+                                stream))
+
+
+def mlg_closure_param_count() -> int:
+    return int(lib().mlg_closure_param_count())
+
+
+def mlg_closure_create(plan: int, max_batch: int, beta: float) -> int:
+    h = ctypes.c_void_p()
+    cfg = mlg_closure_cfg(int(max_batch), float(beta))
+    _check(lib().mlg_closure_create(ctypes.byref(cfg), plan, ctypes.byref(h)))
+    return h.value
+
+
+def mlg_closure_destroy(closure: int) -> None:
+    _check(lib().mlg_closure_destroy(closure))
+
+
+def mlg_closure_columns(closure: int) -> int:
+    n = ctypes.c_int32()
+    _check(lib().mlg_closure_columns(closure, ctypes.byref(n)))
+    return n.value
+
+
+def _f32_host(a, n):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32).reshape(-1)
+    if a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def mlg_closure_set_params(closure: int, params) -> None:
+    a = _f32_host(params, mlg_closure_param_count())
+    _check(lib().mlg_closure_set_params(closure, a.ctypes.data))
+
+
+def mlg_closure_get_params(closure: int):
+    import numpy as np
+    a = np.empty(mlg_closure_param_count(), dtype=np.float32)
+    _check(lib().mlg_closure_get_params(closure, a.ctypes.data))
+    return a
+
+
+def mlg_closure_get_grads(closure: int):
+    import numpy as np
+    a = np.empty(mlg_closure_param_count(), dtype=np.float32)
+    _check(lib().mlg_closure_get_grads(closure, a.ctypes.data))
+    return a
+
+
+def mlg_closure_set_scales(closure: int, x_scale, y_scale) -> None:
+    xs = _f32_host(x_scale, MLG_CLOSURE_NIN)
+    ys = _f32_host(y_scale, MLG_CLOSURE_NOUT)
+    _check(lib().mlg_closure_set_scales(closure, xs.ctypes.data, ys.ctypes.data))
+
+
+def mlg_closure_get_scales(closure: int):
+    import numpy as np
+    xs = np.empty(MLG_CLOSURE_NIN, dtype=np.float32)
+    ys = np.empty(MLG_CLOSURE_NOUT, dtype=np.float32)
+    _check(lib().mlg_closure_get_scales(closure, xs.ctypes.data, ys.ctypes.data))
+    return xs, ys
+
+
+def mlg_closure_features(closure: int, psi: int, chi: int, x_out: int, stream: int = 0) -> None:
+    _check(lib().mlg_closure_features(closure, psi, chi, x_out, stream))
+
+
+def mlg_closure_targets(closure: int, ref_psi: int, ref_chi: int, psi_n: int, chi_n: int, y_out: int,
+                        stream: int = 0) -> None:
+    _check(lib().mlg_closure_targets(closure, ref_psi, ref_chi, psi_n, chi_n, y_out, stream))
+
+
+def mlg_closure_forward(closure: int, x: int, nb: int, y: int, stream: int = 0) -> None:
+    _check(lib().mlg_closure_forward(closure, x, nb, y, stream))
+
+
+def mlg_closure_train_step(closure: int, data_x: int, data_y: int, idx: int, count: int, nb: int, lr: float,
+                           want_loss: bool = False, stream: int = 0):
+    loss = ctypes.c_float()
+    _check(lib().mlg_closure_train_step(closure, data_x, data_y, idx or None, count, nb, lr,
+                                        ctypes.byref(loss) if want_loss else None, stream))
+    return loss.value if want_loss else None
+
+
+def mlg_closure_infer(closure: int, psi: int, chi: int, rhs_psi: int, rhs_chi: int, want_flag: bool = False,
+                      stream: int = 0):
+    f = ctypes.c_int32()
+    _check(lib().mlg_closure_infer(closure, psi, chi, rhs_psi, rhs_chi, ctypes.byref(f) if want_flag else None,
+                                   stream))
+    return f.value if want_flag else None
+
+
+def mlg_closure_stats(closure: int):
+    c, f = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().mlg_closure_stats(closure, ctypes.byref(c), ctypes.byref(f)))
+    return c.value, f.value
+
+
 class Plan:
     """A plan plus its workspace, for torch tensors on the plan's device.
 
@@ -242,6 +378,20 @@ class Plan:
 
     def step_abcn(self, s, A_now, A_prev, out):
         mlg_step_abcn(self.handle, s.data_ptr(), A_now.data_ptr(), A_prev.data_ptr(), out.data_ptr(), self._stream())
+
+    def truncate_to(self, other: "Plan", src, dst):
+        """dst (spectral of 'other') = src (spectral of this plan) moved to the other grid."""
+        mlg_truncate(self.handle, other.handle, src.data_ptr(), dst.data_ptr(), self._stream())
+
+    def advance(self, psi, chi, hist_psi, hist_chi, nsteps, start, U=None, closure=None, tmp=None):
+        """nsteps AB-CN steps of (psi, chi) in place; tmp: complex128 tensor of 6 * spec_elems."""
+        import torch
+        if tmp is None:
+            tmp = torch.empty(6 * self.layout.spec_elems, dtype=torch.complex128, device=f"cuda:{self.device}")
+        mlg_tp_advance(self.handle, U, psi.data_ptr(), chi.data_ptr(), hist_psi.data_ptr(), hist_chi.data_ptr(),
+                       int(nsteps), int(start), closure.handle if closure is not None else 0, tmp.data_ptr(),
+                       self.ws.data_ptr(), self._stream())
+        return tmp
 
     def taps_buffer(self):
         import torch
@@ -337,6 +487,69 @@ class Batch:
     def close(self):
         if self.handle:
             mlg_batch_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Closure:
+    """A learned closure on a coarse Plan (see include/mlg.h for the network and the judge)."""
+
+    def __init__(self, plan: Plan, max_batch: int = 4096, beta: float = 1.0):
+        self.plan = plan  # the closure holds a pointer to the plan; keep it alive
+        self.handle = mlg_closure_create(plan.handle, max_batch, beta)
+        self.ncols = mlg_closure_columns(self.handle)
+        self.max_batch = max_batch
+
+    @staticmethod
+    def _stream():
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+
+    def set_params(self, params):
+        mlg_closure_set_params(self.handle, params)
+
+    def get_params(self):
+        return mlg_closure_get_params(self.handle)
+
+    def get_grads(self):
+        return mlg_closure_get_grads(self.handle)
+
+    def set_scales(self, x_scale, y_scale):
+        mlg_closure_set_scales(self.handle, x_scale, y_scale)
+
+    def get_scales(self):
+        return mlg_closure_get_scales(self.handle)
+
+    def features(self, psi, chi, x_out):
+        mlg_closure_features(self.handle, psi.data_ptr(), chi.data_ptr(), x_out.data_ptr(), self._stream())
+
+    def targets(self, ref_psi, ref_chi, psi_n, chi_n, y_out):
+        mlg_closure_targets(self.handle, ref_psi.data_ptr(), ref_chi.data_ptr(), psi_n.data_ptr(), chi_n.data_ptr(),
+                            y_out.data_ptr(), self._stream())
+
+    def forward(self, x, y):
+        mlg_closure_forward(self.handle, x.data_ptr(), int(x.shape[0]), y.data_ptr(), self._stream())
+
+    def train_step(self, data_x, data_y, idx, nb, lr, want_loss=False):
+        return mlg_closure_train_step(self.handle, data_x.data_ptr(), data_y.data_ptr(),
+                                      0 if idx is None else idx.data_ptr(), int(data_x.shape[0]), int(nb), float(lr),
+                                      want_loss, self._stream())
+
+    def infer(self, psi, chi, rhs_psi, rhs_chi, want_flag=False):
+        return mlg_closure_infer(self.handle, psi.data_ptr(), chi.data_ptr(), rhs_psi.data_ptr(), rhs_chi.data_ptr(),
+                                 want_flag, self._stream())
+
+    def stats(self):
+        return mlg_closure_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            mlg_closure_destroy(self.handle)
             self.handle = 0
 
     def __del__(self):

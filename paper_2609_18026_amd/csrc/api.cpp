@@ -297,6 +297,60 @@ mlg_status mlg_step_abcn(mlg_plan p, const void* s, const void* A_now, const voi
                      static_cast<const double*>(A_prev), static_cast<double*>(out), static_cast<hipStream_t>(stream));
 }
 
+mlg_status mlg_tp_advance(mlg_plan p, const double* U, void* psi, void* chi, void* hist_psi, void* hist_chi,
+                          int32_t nsteps, int32_t start, mlg_closure closure, void* tmp, void* ws, void* stream) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!p->step_ready) return fail(MLG_E_ARG, "mlg_step_setup has not been called");
+  if (!psi || !chi || !hist_psi || !hist_chi || !tmp || !ws) return fail(MLG_E_ARG, "null buffer");
+  if (nsteps < 0) return fail(MLG_E_ARG, "nsteps must be >= 0");
+  if (closure && closure_plan(closure) != p) return fail(MLG_E_ARG, "the closure belongs to another plan");
+  if (nsteps == 0) return MLG_OK;
+  DeviceGuard guard(p->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t n = (size_t)p->tau * p->nz * 2;  // doubles per spectral array
+  double* t[6];
+  for (int i = 0; i < 6; ++i) t[i] = static_cast<double*>(tmp) + i * n;
+  double* sp = static_cast<double*>(psi);
+  double* sc = static_cast<double*>(chi);
+  double* hp = static_cast<double*>(hist_psi);
+  double* hc = static_cast<double*>(hist_chi);
+  mlg_status st;
+  auto rhs = [&](const double* a, const double* b, double* ra, double* rb) -> mlg_status {
+    if (mlg_status e = mlg_rhs_tp(p, U, a, b, ra, rb, nullptr, ws, stream)) return e;
+    return closure ? closure_correct(closure, a, b, ra, rb, s) : MLG_OK;
+  };
+  int done = 0;
+  if (start) {
+    // s1 = 2 S_{dt/2}(S_{dt/2}(s0)) - S_dt(s0), S_h(s) = (I - h L)^{-1} (s + h A(s))
+    if ((st = rhs(sp, sc, hp, hc))) return st;
+    if ((st = launch_step(p, 0, 1, sp, hp, nullptr, t[2], s)) || (st = launch_step(p, 0, 1, sc, hc, nullptr, t[3], s)))
+      return st;
+    if ((st = launch_step(p, 0, 0, sp, hp, nullptr, t[4], s)) || (st = launch_step(p, 0, 0, sc, hc, nullptr, t[5], s)))
+      return st;
+    if ((st = rhs(t[4], t[5], t[0], t[1]))) return st;
+    if ((st = launch_step(p, 0, 0, t[4], t[0], nullptr, t[4], s)) ||
+        (st = launch_step(p, 0, 0, t[5], t[1], nullptr, t[5], s)))
+      return st;
+    if ((st = launch_richardson(p, t[4], t[2], sp, s)) || (st = launch_richardson(p, t[5], t[3], sc, s))) return st;
+    done = 1;
+  }
+  // AB-CN: the nonlinear terms alternate between (hist) and (t0, t1); the step runs in place
+  double* prev[2] = {hp, hc};
+  for (; done < nsteps; ++done) {
+    double* now[2] = {prev[0] == hp ? t[0] : hp, prev[0] == hp ? t[1] : hc};
+    if ((st = rhs(sp, sc, now[0], now[1]))) return st;
+    if ((st = launch_step(p, 1, 0, sp, now[0], prev[0], sp, s)) || (st = launch_step(p, 1, 0, sc, now[1], prev[1], sc, s)))
+      return st;
+    prev[0] = now[0];
+    prev[1] = now[1];
+  }
+  if (prev[0] != hp) {
+    MLG_HIP_TRY(hipMemcpyAsync(hp, prev[0], n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    MLG_HIP_TRY(hipMemcpyAsync(hc, prev[1], n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  return MLG_OK;
+}
+
 mlg_status mlg_synthesize(mlg_plan p, const void* psi, const void* chi, void* uw, void* ws, void* stream) {
   if (mlg_status st = check_plan(p)) return st;
   if (!psi || !chi || !uw || !ws) return fail(MLG_E_ARG, "null buffer");

@@ -153,6 +153,13 @@ mlg_status launch_split_proj(const mlg_plan_s* p, double* const* in3, double* co
 mlg_status step_setup(mlg_plan_s* p, const mlg_dissip* d);
 mlg_status launch_step(const mlg_plan_s* p, int mode, int which, const double* s, const double* a1, const double* a0,
                        double* out, hipStream_t st);
+// s1 = 2 half - full over all spectral elements (the Richardson start-up of Sec. 3.3)
+mlg_status launch_richardson(const mlg_plan_s* p, const double* half, const double* full, double* out,
+                             hipStream_t st);
+// closure.hip: features -> network -> judge -> corrected (rpsi, rchi), all on 'st'
+mlg_status closure_correct(mlg_closure_s* c, const double* psi, const double* chi, double* rpsi, double* rchi,
+                           hipStream_t st);
+const mlg_plan_s* closure_plan(const mlg_closure_s* c);
 // active column bounds of the projection: m < mmax, |k| <= kmax
 void active_columns(const mlg_plan_s* p, int* mmax, int* kmax);
 mlg_status launch_mask_tri(const mlg_plan_s* p, double* spec, hipStream_t s);

@@ -309,4 +309,21 @@ mlg_status launch_step(const mlg_plan_s* p, int mode, int which, const double* s
   return MLG_OK;
 }
 
+__global__ __launch_bounds__(256) void richardson_kernel(const double* half, const double* full, double* out,
+                                                         int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = 2.0 * half[i] - full[i];
+}
+
+mlg_status launch_richardson(const mlg_plan_s* p, const double* half, const double* full, double* out,
+                             hipStream_t st) {
+  const int64_t n = 2 * p->tau * p->nz;
+  p->timing.begin("step", st);
+  richardson_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(half, full, out, n);
+  p->timing.end(st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(MLG_E_DEVICE, std::string("richardson_kernel: ") + hipGetErrorString(e));
+  return MLG_OK;
+}
+
 }  // namespace mlg

@@ -106,18 +106,19 @@ def _ein(s: np.ndarray) -> np.ndarray:
 
 def vortex_pair_psi(r: np.ndarray, phi: np.ndarray, z: np.ndarray, *, gamma: float = 2 * np.pi,
                     a: float = 0.1, b: float = 1.0, delta: float = 0.01, lz: float = 8.6,
-                    incline_deg: float = 48.0) -> np.ndarray:
+                    incline_deg: float = 48.0, phase: float = 0.0) -> np.ndarray:
     """psi(z, r, phi) on the tensor grid, shape (len(z), len(r), len(phi)).
 
     Each Lamb-Oseen vortex of circulation G has omega = G/(pi a^2) exp(-rho^2/a^2) and
     stream function -(G / 4 pi) Ein(rho^2 / a^2); the pair has +Gamma at x > 0 and
-    -Gamma at x < 0, so psi decays like a dipole.
+    -Gamma at x < 0, so psi decays like a dipole.  Both cores are displaced by
+    delta sin(2 pi z / L_z + phase) along (+-cos incline, sin incline), mirror-symmetric.
     """
     ang = np.deg2rad(incline_deg)
     Z, R, P = np.meshgrid(z, r, phi, indexing="ij")
     X = R * np.cos(P)
     Y = R * np.sin(P)
-    disp = delta * np.sin(2 * np.pi * Z / lz)
+    disp = delta * np.sin(2 * np.pi * Z / lz + phase)
     x1 = b / 2 + disp * np.cos(ang)
     y1 = disp * np.sin(ang)
     x2 = -b / 2 - disp * np.cos(ang)
@@ -163,3 +164,33 @@ def _is_5smooth(n: int) -> bool:
         while n % p == 0:
             n //= p
     return n == 1
+
+
+def closure_init(seed: int, nin: int = 258, hidden: int = 256, nout: int = 256,
+                 last_gain: float = 0.1) -> np.ndarray:
+    """Initial closure weights, float32, in the order W1 [h][nin], b1, W2 [h][h], b2, W3 [nout][h], b3.
+
+    Glorot-uniform weights (the last layer scaled by last_gain) and zero biases.
+    """
+    g = rng(seed)
+
+    def glorot(fo, fi, gain=1.0):
+        a = gain * np.sqrt(6.0 / (fi + fo))
+        return g.uniform(-a, a, (fo, fi))
+
+    parts = [glorot(hidden, nin), np.zeros(hidden), glorot(hidden, hidden), np.zeros(hidden),
+             glorot(nout, hidden, last_gain), np.zeros(nout)]
+    return np.concatenate([p.reshape(-1) for p in parts]).astype(np.float32)
+
+
+def batch_indices(count: int, nb: int, steps: int, seed: int) -> np.ndarray:
+    """steps x nb int32 row indices: consecutive slices of seeded permutations of range(count)."""
+    g = rng(seed)
+    out = np.empty((steps, nb), dtype=np.int32)
+    perm, pos = g.permutation(count), 0
+    for s in range(steps):
+        if pos + nb > count:
+            perm, pos = g.permutation(count), 0
+        out[s] = perm[pos:pos + nb]
+        pos += nb
+    return out
