@@ -145,14 +145,20 @@ typedef struct {
   double dt;        /* > 0 */
 } mlg_dissip;
 
-/* Build (host, long double) and upload the band of L and banded LU factors with partial
- * pivoting of I - (dt/2) L and I - dt L for every (m, |k|).  Replaces earlier step operators. */
+/* Prepare the step operators for every m: -grad^2 = X_m + kappa^2 with X_m = G_m diag(n(n+1)) / ell^2
+ * is diagonalised on the host in FP64 (X_m = V diag(lam) V^{-1}, V = L^{-1/2} Q with Q the
+ * orthogonal eigenvectors of L^{1/2} G_m L^{1/2} / ell^2; the n = 0 row of m = 0 is treated
+ * exactly as the block-triangular part it is), and V, V^{-1}, lam are uploaded.  A step then
+ * applies the scalar functions of Eq. abcn / FE-BE to lam + kappa^2 between two products per m,
+ * the same operator as a banded factorisation of I - h L per (m, k).  Replaces earlier step
+ * operators; synchronises the device.  Errors: MLG_E_ARG, MLG_E_NONFINITE, MLG_E_ALLOC. */
 mlg_status mlg_step_setup(mlg_plan plan, const mlg_dissip* d);
 /* FE-BE step: out = (I - h L)^{-1} (s + h A) with h = dt/2 (half = 1) or h = dt (half = 0); the
  * Richardson start-up of Sec. 3.3 is s1 = 2 S_{dt/2}(S_{dt/2}(s0)) - S_dt(s0). */
 mlg_status mlg_step_febe(mlg_plan plan, int half, const void* s, const void* A, void* out, void* stream);
 /* AB-CN step, Eq. abcn: out = (I - dt/2 L)^{-1} [(I + dt/2 L) s + dt/2 (3 A_now - A_prev)].
- * All arrays spectral (packed triangular); out must not alias s. */
+ * All arrays spectral (packed triangular); out must not alias the inputs.  Calls on one plan
+ * share its step scratch and must not overlap. */
 mlg_status mlg_step_abcn(mlg_plan plan, const void* s, const void* A_now, const void* A_prev, void* out, void* stream);
 
 /* Nodal velocity and vorticity of a toroidal-poloidal pair (Sec. 3.2, Eq. tp):

@@ -99,11 +99,19 @@ struct mlg_plan_s {
   unsigned short* d_split_prj[4] = {nullptr, nullptr, nullptr, nullptr};  // W Pbar hi/lo, W Q hi/lo [n-m][ipad]
   int64_t* d_split_prj_off = nullptr;
   int split_ipad = 0;
-  // semi-implicit step operators (mlg_step_setup)
-  double* d_step_band = nullptr;
-  double* d_step_fac[2] = {nullptr, nullptr};
-  int step_b = 0, step_nkabs = 0;
-  double step_dt = 0;
+  // semi-implicit step operators (mlg_step_setup): per m, X_m = G_m L / ell^2 restricted to
+  // n >= max(m, 1) is L^{-1/2} Q diag(lam) Q^T L^{1/2}; the step applies scalar functions of
+  // lam + kappa^2 between the two products
+  double* d_step_fwd = nullptr;   // per m [n][j] = Q[n][j] sqrt(L_n)     (V^{-1} as a k-major A operand)
+  double* d_step_bwd = nullptr;   // per m [j][n] = Q[n][j] / sqrt(L_n)   (V as a k-major A operand)
+  double* d_step_lam = nullptr;   // per m eigenvalues
+  double* d_step_u = nullptr;     // m = 0: u_j = sum_n X_{0 n} V[n][j]
+  int64_t* d_step_qoff = nullptr; // per m offsets into fwd / bwd (M + 1)
+  int64_t* d_step_loff = nullptr; // per m offsets into lam (M + 1)
+  double* d_step_w = nullptr;     // scratch: tau * nz complex + (nrc - 1) * nz complex
+  int step_maxk = 0;
+  double step_dt = 0, step_nu = 0, step_nuh = 0;
+  int step_q = 1;                 // p / 2 (hyperviscosity power of grad^2), 1 when nu_h = 0
   bool step_ready = false;
   bool use_fast_fft = true;   // register-resident 256-point kernels when a length is 256
   int phi_rad[12] = {0};

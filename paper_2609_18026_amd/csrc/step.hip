@@ -1,280 +1,391 @@
 // Semi-implicit time stepping of ds/dt = A(s) + L s (Sec. 3.3) on the GPU.
 //
-// L = nu grad^2 - nu_h (-grad^2)^{p/2} (Eq. dissipation) acts per (m, k) harmonic as a banded
-// matrix composed from the truncated horizontal Laplacian: grad^2 = Dbar_m - kappa^2 with
-// Dbar_m = -G_m diag(n(n+1)) / ell^2 (G_m the exact Gram matrix <Pbar_n, (1-x)^2 Pbar_j>).  Its
-// half-bandwidth is b = p with hyperviscosity, else 2.  At setup the host forms, per (m, |k|),
-// the band of L and banded LU factors with partial pivoting of I - h L for h = dt/2 (AB-CN,
-// Eq. abcn, and the half FE-BE sub-step) and h = dt (the full FE-BE sub-step of the Richardson
-// start-up).  A step kernel runs one thread per (m, k) column: it forms the right-hand side
-// (applying L with a register window of 2b + 1 coefficients), then forward elimination with
-// the recorded row interchanges and back substitution with U (upper bandwidth 2b).
+// L = nu grad^2 - nu_h (-grad^2)^{p/2} (Eq. dissipation) acts per (m, k) harmonic through the
+// truncated horizontal Laplacian: -grad^2 = X_m + kappa^2 with X_m = G_m diag(n(n+1)) / ell^2
+// (G_m the exact Gram matrix <Pbar_n, (1-x)^2 Pbar_j>, Eq. del2h-entries).  Every step operator
+// is a rational function of -grad^2:
+//   FE-BE  out = Phi s + Psi A,       Phi = 1 / (1 - h L),          Psi = h / (1 - h L);
+//   AB-CN  out = Phi s + Psi (3 A1 - A0), Phi = (1 + h L) / (1 - h L), Psi = h / (1 - h L),  h = dt / 2
+// (Eq. abcn).  The paper factors the banded matrices I - h L per (m, k); here X_m is
+// diagonalised once per m on the host, X_m = V diag(lam) V^{-1} with V = L^{-1/2} Q and
+// S = L^{1/2} G L^{1/2} / ell^2 = Q diag(lam) Q^T symmetric (n >= max(m, 1), where L > 0).
+// The eigenvectors do not depend on kappa, so for all k at once
+//   out = V [Phi(lam + kappa^2) (V^{-1} s) + Psi(lam + kappa^2) (V^{-1} a)],
+// two FP64 MFMA products per m with the scalar functions applied in between.  For m = 0 the
+// n = 0 row of X is (0, b^T) (its column is zero since L_0 = 0), so X is block upper triangular
+// and the n = 0 output gains b^T V diag((f(mu) - f(alpha)) / lam) V^{-1} s' terms (divided
+// differences, alpha = kappa^2), evaluated in closed form without cancellation.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "dev_common.h"
 #include "mlg_internal.h"
 
 namespace mlg {
+bool sym_eig(int n, std::vector<double>& A, std::vector<double>& w, std::vector<double>& Q);
+
 namespace {
 
 using namespace ::mlg::dev;
 using ld = long double;
 
-constexpr int BMAX = 8;
+constexpr int TM = 64;  // rows per block
+constexpr int TC = 16;  // complex columns per block
+constexpr int TK = 16;  // k depth per LDS stage
+
+#define MFMA(a, b, c) __builtin_amdgcn_mfma_f64_16x16x4f64((a), (b), (c), 0, 0, 0)
 
 __device__ __forceinline__ int kval(int kk, int nz) { return (2 * kk < nz) ? kk : kk - nz; }
 
 struct StepArgs {
   const double2* s;
-  const double2* a1;   // A^j (or A for FE-BE)
-  const double2* a0;   // A^{j-1} (AB-CN only)
+  const double2* a1;
+  const double2* a0;   // AB-CN: A^{j-1}; FE-BE: null
   double2* out;
-  const double* band;  // L band: per (row, c = 0..2b) x nkabs
-  const double* fac;   // LU: per (row, c) x nkabs, c = 0..b-1 multipliers, b pivot offset, b+1.. U (1/U_nn first)
+  double2* W;          // packed like the spectra (rows n >= n0 of each m)
+  double2* W0;         // m = 0 divided-difference products [j][kk]
+  const double* fwd;
+  const double* bwd;
+  const double* lam;
+  const double* u;
+  const int64_t* qoff;
+  const int64_t* loff;
   const int64_t* off;
-  int M, nrc, nz, nzc, b, nkabs, ncoef_band, ncoef_fac, mode;  // mode 0 FE-BE, 1 AB-CN
-  double h;
+  int M, nrc, nz, nzc, mode, q;   // mode 0 FE-BE, 1 AB-CN; q = p / 2 (1 without hyperviscosity)
+  double h, nu, nuh, kap0;
 };
 
-__global__ __launch_bounds__(64) void step_kernel(StepArgs a) {
-  const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= (int64_t)a.M * a.nz) return;
-  const int m = (int)(col / a.nz);
-  const int kk = (int)(col - (int64_t)m * a.nz);
-  if (m >= a.nrc) return;
-  const int nz = a.nz;
-  const int K = a.nrc - m;
-  const int64_t base = a.off[m];
+__device__ __forceinline__ bool active_slot(int kk, int nz, int nzc) {
   const int k = kval(kk, nz);
   const int ka = k < 0 ? -k : k;
-  const bool nyq = (nz % 2 == 0 && nz > 1 && k == -(nz / 2));
-  double2* out = a.out + base * nz + kk;
-  const double2 z0 = make_double2(0.0, 0.0);
-  if (nyq || ka >= a.nzc) {
-    for (int t = 0; t < K; ++t) out[(int64_t)t * nz] = z0;
-    return;
-  }
-  const double2* s = a.s + base * nz + kk;
-  const double2* a1 = a.a1 + base * nz + kk;
-  const double2* a0 = a.a0 ? a.a0 + base * nz + kk : nullptr;
-  const int b = a.b;
-  const int nk = a.nkabs;
-  auto bandv = [&](int t, int c) { return a.band[((base + t) * a.ncoef_band + c) * nk + ka]; };
-  auto facv = [&](int t, int c) { return a.fac[((base + t) * a.ncoef_fac + c) * nk + ka]; };
-  // ---- right-hand side
-  double2 win[2 * BMAX + 1];  // s_{t-b} .. s_{t+b}
+  return ka < nzc && !(nz % 2 == 0 && nz > 1 && k == -(nz / 2));
+}
+
+// 1 - h L(mu) with L(mu) = -nu mu - nu_h mu^q
+__device__ __forceinline__ double denom(const StepArgs& a, double mu) {
+  double pw = mu;
+  for (int i = 1; i < a.q; ++i) pw *= mu;
+  return 1.0 + a.h * (a.nu * mu + a.nuh * pw);
+}
+
+// Z = V^{-1} [s | a] per m, then W = Phi Zs + Psi Za (and the m = 0 divided differences)
+__global__ __launch_bounds__(256) void step_fwd_kernel(StepArgs a) {
+  const int m = blockIdx.z;
+  if (m >= a.M || m >= a.nrc) return;
+  const int n0 = m == 0 ? 1 : 0;
+  const int K = a.nrc - m - n0;
+  const int j0 = blockIdx.y * TM, kk0 = blockIdx.x * TC;
+  if (j0 >= K || kk0 >= a.nz) return;
+  const int nz = a.nz;
+  const double* __restrict__ A = a.fwd + a.qoff[m];
+  const int64_t rb = (a.off[m] + n0) * nz;
+  const double2* __restrict__ s = a.s + rb;
+  const double2* __restrict__ p1 = a.a1 + rb;
+  const double2* __restrict__ p0 = a.a0 ? a.a0 + rb : nullptr;
+  __shared__ double As[2][TK][TM];
+  __shared__ double Bs[2][2][TK][2 * TC];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double4_t acc[2][2];
 #pragma unroll
-  for (int j = 0; j < 2 * BMAX + 1; ++j) {
-    const int t = j - b;
-    win[j] = (j <= 2 * b && t >= 0 && t < K) ? s[(int64_t)t * nz] : z0;
-  }
-  for (int t = 0; t < K; ++t) {
-    double2 r;
-    if (a.mode == 1) {
-      double2 Ls = z0;
+  for (int p = 0; p < 2; ++p) acc[p][0] = acc[p][1] = double4_t{0.0, 0.0, 0.0, 0.0};
+  double ra[4];
+  double2 rbv[2];
+  auto load = [&](int k0) {
 #pragma unroll
-      for (int j = 0; j < 2 * BMAX + 1; ++j)
-        if (j <= 2 * b) Ls = cadd(Ls, cscale(win[j], bandv(t, j)));
-      const double2 A1 = a1[(int64_t)t * nz], A0 = a0[(int64_t)t * nz];
-      r = make_double2(win[b].x + a.h * Ls.x + a.h * (3.0 * A1.x - A0.x),
-                       win[b].y + a.h * Ls.y + a.h * (3.0 * A1.y - A0.y));
-    } else {
-      const double2 A1 = a1[(int64_t)t * nz];
-      r = make_double2(win[b].x + a.h * A1.x, win[b].y + a.h * A1.y);
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + 256 * t;
+      const int kr = e >> 6, rr = e & 63;
+      const int k = k0 + kr, j = j0 + rr;
+      ra[t] = (k < K && j < K) ? A[(int64_t)k * K + j] : 0.0;
     }
-    out[(int64_t)t * nz] = r;
+    const int kr = tid >> 4, cc = tid & 15;
+    const int k = k0 + kr, kk = kk0 + cc;
+    const bool ok = k < K && kk < nz;
+    const int64_t i = (int64_t)k * nz + kk;
+    rbv[0] = ok ? s[i] : make_double2(0.0, 0.0);
+    double2 v = ok ? p1[i] : make_double2(0.0, 0.0);
+    if (ok && p0) {
+      const double2 w = p0[i];
+      v = make_double2(3.0 * v.x - w.x, 3.0 * v.y - w.y);
+    }
+    rbv[1] = v;
+  };
+  auto store = [&](int buf) {
 #pragma unroll
-    for (int j = 0; j < 2 * BMAX; ++j) win[j] = win[j + 1];
-    const int tn = t + b + 1;
-    win[2 * BMAX] = z0;
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + 256 * t;
+      As[buf][e >> 6][e & 63] = ra[t];
+    }
+    const int kr = tid >> 4, cc = tid & 15;
+    Bs[buf][0][kr][cc] = rbv[0].x;
+    Bs[buf][0][kr][TC + cc] = rbv[0].y;
+    Bs[buf][1][kr][cc] = rbv[1].x;
+    Bs[buf][1][kr][TC + cc] = rbv[1].y;
+  };
+  const int nk = (K + TK - 1) / TK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * TK);
 #pragma unroll
-    for (int j = 0; j < 2 * BMAX + 1; ++j)
-      if (j == 2 * b) win[j] = tn < K ? s[(int64_t)tn * nz] : z0;
+    for (int ks = 0; ks < TK; ks += 4) {
+      const int kr = ks + (lane >> 4);
+      const double av = As[buf][kr][wave * 16 + (lane & 15)];
+      acc[0][0] = MFMA(av, Bs[buf][0][kr][lane & 15], acc[0][0]);
+      acc[0][1] = MFMA(av, Bs[buf][0][kr][TC + (lane & 15)], acc[0][1]);
+      acc[1][0] = MFMA(av, Bs[buf][1][kr][lane & 15], acc[1][0]);
+      acc[1][1] = MFMA(av, Bs[buf][1][kr][TC + (lane & 15)], acc[1][1]);
+    }
+    if (kt + 1 < nk) store(buf ^ 1);
+    __syncthreads();
   }
-  // ---- forward elimination with row interchanges: window v[0..b] = rows t .. t+b
-  double2 v[BMAX + 1];
+  const int kk = kk0 + (lane & 15);
+  if (kk >= nz || !active_slot(kk, nz, a.nzc)) return;
+  const double kap = a.kap0 * kval(kk, nz);
+  const double alpha = kap * kap;
+  const double* lam = a.lam + a.loff[m];
+  const double Da = denom(a, alpha);
 #pragma unroll
-  for (int j = 0; j < BMAX + 1; ++j) v[j] = (j <= b && j < K) ? out[(int64_t)j * nz] : z0;
-  for (int t = 0; t < K; ++t) {
-    const int pv = (int)facv(t, b);
-    double2 vp = v[0];
-#pragma unroll
-    for (int j = 1; j < BMAX + 1; ++j)
-      if (j == pv) vp = v[j];
-#pragma unroll
-    for (int j = 1; j < BMAX + 1; ++j)
-      if (j == pv) v[j] = v[0];
-    v[0] = vp;
-#pragma unroll
-    for (int j = 1; j < BMAX + 1; ++j)
-      if (j <= b) v[j] = csub(v[j], cscale(v[0], facv(t, j - 1)));
-    out[(int64_t)t * nz] = v[0];
-#pragma unroll
-    for (int j = 0; j < BMAX; ++j) v[j] = v[j + 1];
-    v[BMAX] = z0;
-    const int tn = t + b + 1;
-#pragma unroll
-    for (int j = 0; j < BMAX + 1; ++j)
-      if (j == b) v[j] = tn < K ? out[(int64_t)tn * nz] : z0;
-  }
-  // ---- back substitution with U (diagonal stored as its reciprocal, then 2b superdiagonals)
-  double2 x[2 * BMAX];  // x_{t+1} .. x_{t+2b}
-#pragma unroll
-  for (int j = 0; j < 2 * BMAX; ++j) x[j] = z0;
-  for (int t = K - 1; t >= 0; --t) {
-    double2 r = out[(int64_t)t * nz];
-#pragma unroll
-    for (int j = 0; j < 2 * BMAX; ++j)
-      if (j < 2 * b) r = csub(r, cscale(x[j], facv(t, b + 2 + j)));
-    const double2 xt = cscale(r, facv(t, b + 1));
-    out[(int64_t)t * nz] = xt;
-#pragma unroll
-    for (int j = 2 * BMAX - 1; j > 0; --j) x[j] = x[j - 1];
-    x[0] = xt;
+  for (int v = 0; v < 4; ++v) {
+    const int j = j0 + wave * 16 + (lane >> 4) + 4 * v;
+    if (j >= K) continue;
+    const double lj = lam[j];
+    const double mu = lj + alpha;
+    const double D = denom(a, mu);
+    const double psi = a.h / D;
+    const double phi = a.mode == 1 ? 2.0 / D - 1.0 : 1.0 / D;
+    const double zsr = acc[0][0][v], zsi = acc[0][1][v], zar = acc[1][0][v], zai = acc[1][1][v];
+    a.W[rb + (int64_t)j * nz + kk] = make_double2(phi * zsr + psi * zar, phi * zsi + psi * zai);
+    if (m == 0) {
+      // (f(mu) - f(alpha)) / lam in closed form: L(mu) - L(alpha) = lam * dl
+      double sum = 0.0, mp = 1.0;
+      for (int i = 0; i < a.q; ++i) {
+        double ap = 1.0;
+        for (int t = 0; t < a.q - 1 - i; ++t) ap *= alpha;
+        sum += mp * ap;
+        mp *= mu;
+      }
+      const double dl = -a.nu - a.nuh * sum;
+      const double inv = a.h * dl / (D * Da);
+      const double dphi = (a.mode == 1 ? 2.0 : 1.0) * inv;
+      const double dpsi = a.h * inv;
+      a.W0[(int64_t)j * nz + kk] = make_double2(dphi * zsr + dpsi * zar, dphi * zsi + dpsi * zai);
+    }
   }
 }
 
-// Banded helpers on the host (long double).  A band matrix of half-bandwidth w over n rows is
-// stored row-major as n x (2w + 1), entry (i, j) at [i][j - i + w].
-struct Band {
-  int n = 0, w = 0;
-  std::vector<ld> a;
-  Band(int n_, int w_) : n(n_), w(w_), a((size_t)n_ * (2 * w_ + 1), 0) {}
-  ld get(int i, int j) const {
-    if (j < i - w || j > i + w || j < 0 || j >= n) return 0;
-    return a[(size_t)i * (2 * w + 1) + (j - i + w)];
-  }
-  void set(int i, int j, ld v) { a[(size_t)i * (2 * w + 1) + (j - i + w)] = v; }
-};
-
-Band band_mul(const Band& A, const Band& B) {
-  Band C(A.n, A.w + B.w);
-  for (int i = 0; i < A.n; ++i)
-    for (int j = std::max(0, i - C.w); j <= std::min(A.n - 1, i + C.w); ++j) {
-      ld s = 0;
-      for (int q = std::max({0, i - A.w, j - B.w}); q <= std::min({A.n - 1, i + A.w, j + B.w}); ++q)
-        s += A.get(i, q) * B.get(q, j);
-      C.set(i, j, s);
+// out rows n >= n0 = V W per m; inactive axial slots are zeroed
+__global__ __launch_bounds__(256) void step_bwd_kernel(StepArgs a) {
+  const int m = blockIdx.z;
+  if (m >= a.M || m >= a.nrc) return;
+  const int n0 = m == 0 ? 1 : 0;
+  const int K = a.nrc - m - n0;
+  const int r0 = blockIdx.y * TM, kk0 = blockIdx.x * TC;
+  if (r0 >= K || kk0 >= a.nz) return;
+  const int nz = a.nz;
+  const double* __restrict__ A = a.bwd + a.qoff[m];
+  const int64_t rb = (a.off[m] + n0) * nz;
+  const double2* __restrict__ Wm = a.W + rb;
+  __shared__ double As[2][TK][TM];
+  __shared__ double Bs[2][TK][2 * TC];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double4_t acc[2];
+  acc[0] = acc[1] = double4_t{0.0, 0.0, 0.0, 0.0};
+  double ra[4];
+  double2 rbv;
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + 256 * t;
+      const int kr = e >> 6, rr = e & 63;
+      const int k = k0 + kr, r = r0 + rr;
+      ra[t] = (k < K && r < K) ? A[(int64_t)k * K + r] : 0.0;
     }
-  return C;
+    const int kr = tid >> 4, cc = tid & 15;
+    const int k = k0 + kr, kk = kk0 + cc;
+    rbv = (k < K && kk < nz) ? Wm[(int64_t)k * nz + kk] : make_double2(0.0, 0.0);
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + 256 * t;
+      As[buf][e >> 6][e & 63] = ra[t];
+    }
+    const int kr = tid >> 4, cc = tid & 15;
+    Bs[buf][kr][cc] = rbv.x;
+    Bs[buf][kr][TC + cc] = rbv.y;
+  };
+  const int nk = (K + TK - 1) / TK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * TK);
+#pragma unroll
+    for (int ks = 0; ks < TK; ks += 4) {
+      const int kr = ks + (lane >> 4);
+      const double av = As[buf][kr][wave * 16 + (lane & 15)];
+      acc[0] = MFMA(av, Bs[buf][kr][lane & 15], acc[0]);
+      acc[1] = MFMA(av, Bs[buf][kr][TC + (lane & 15)], acc[1]);
+    }
+    if (kt + 1 < nk) store(buf ^ 1);
+    __syncthreads();
+  }
+  const int kk = kk0 + (lane & 15);
+  if (kk >= nz) return;
+  const bool act = active_slot(kk, nz, a.nzc);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = r0 + wave * 16 + (lane >> 4) + 4 * v;
+    if (r >= K) continue;
+    a.out[rb + (int64_t)r * nz + kk] = act ? make_double2(acc[0][v], acc[1][v]) : make_double2(0.0, 0.0);
+  }
+}
+
+// m = 0, n = 0: out = Phi(alpha) s0 + Psi(alpha) a0 + sum_j u_j W0[j]
+__global__ __launch_bounds__(64) void step_row0_kernel(StepArgs a) {
+  const int kk = blockIdx.x * blockDim.x + threadIdx.x;
+  if (kk >= a.nz) return;
+  if (!active_slot(kk, a.nz, a.nzc)) {
+    a.out[kk] = make_double2(0.0, 0.0);
+    return;
+  }
+  const double kap = a.kap0 * kval(kk, a.nz);
+  const double alpha = kap * kap;
+  const double D = denom(a, alpha);
+  const double psi = a.h / D;
+  const double phi = a.mode == 1 ? 2.0 / D - 1.0 : 1.0 / D;
+  const double2 s0 = a.s[kk];
+  double2 v = a.a1[kk];
+  if (a.a0) v = make_double2(3.0 * v.x - a.a0[kk].x, 3.0 * v.y - a.a0[kk].y);
+  double re = phi * s0.x + psi * v.x, im = phi * s0.y + psi * v.y;
+  const int K = a.nrc - 1;
+  for (int j = 0; j < K; ++j) {
+    const double2 w = a.W0[(int64_t)j * a.nz + kk];
+    re += a.u[j] * w.x;
+    im += a.u[j] * w.y;
+  }
+  a.out[kk] = make_double2(re, im);
 }
 
 }  // namespace
 
 mlg_status step_setup(mlg_plan_s* p, const mlg_dissip* d) {
   const int nrc = p->nrc, M = p->M, nz = p->nz;
-  const int half = d->nu_h > 0 ? d->p / 2 : 1;
-  const int b = 2 * half;
-  const int kmax = std::max(0, std::min(p->nzc - 1, nz > 1 ? (nz - 1) / 2 : 0));
-  const int nkabs = kmax + 1;
-  const int ncb = 2 * b + 1, ncf = b + 2 + 2 * b;
+  const int Mm = std::min(M, nrc);
   const ld ell2 = (ld)p->g.ell * (ld)p->g.ell;
-  std::vector<double> band((size_t)p->tau * ncb * nkabs, 0.0);
-  std::vector<double> fac[2];
-  fac[0].assign((size_t)p->tau * ncf * nkabs, 0.0);
-  fac[1].assign((size_t)p->tau * ncf * nkabs, 0.0);
-  const ld hs[2] = {(ld)d->dt / 2, (ld)d->dt};
+  std::vector<int64_t> qoff(M + 1, 0), loff(M + 1, 0);
   for (int m = 0; m < M; ++m) {
-    const int K = std::max(nrc - m, 0);
-    if (K == 0) continue;
-    // Gram entries of this order (the same exact construction as the projection's G)
-    auto eps = [&](int n) -> ld { return (n <= m || n <= 0) ? 0 : sqrtl((ld)(n * n - m * m) / (ld)(4 * n * n - 1)); };
-    for (int ka = 0; ka < nkabs; ++ka) {
-      const ld kap = 2 * acosl(-1.0L) * ka / (ld)p->g.lz;
-      Band X(K, 2);  // X = -(Dbar - kappa^2) = G L / ell^2 + kappa^2
+    const int Kp = m < Mm ? nrc - m - (m == 0 ? 1 : 0) : 0;
+    qoff[m + 1] = qoff[m] + (int64_t)Kp * Kp;
+    loff[m + 1] = loff[m] + Kp;
+  }
+  std::vector<double> fwd(std::max<int64_t>(qoff[M], 1)), bwd(std::max<int64_t>(qoff[M], 1));
+  std::vector<double> lam(std::max<int64_t>(loff[M], 1)), u(std::max(nrc - 1, 1), 0.0);
+  std::atomic<int> next{0};
+  std::atomic<bool> failed{false};
+  auto work = [&]() {
+    for (int m = next++; m < Mm; m = next++) {
+      const int n0 = m == 0 ? 1 : 0;
+      const int K = nrc - m - n0;
+      if (K <= 0) continue;
+      auto eps = [&](int n) -> ld {
+        return (n <= m || n <= 0) ? 0 : sqrtl((ld)(n * n - m * m) / (ld)(4 * n * n - 1));
+      };
+      auto gram = [&](int n, int nj) -> ld {  // G_{n, nj} (pentadiagonal, symmetric)
+        const int lo = std::min(n, nj), hi = std::max(n, nj);
+        if (hi == lo) return 1 + eps(lo) * eps(lo) + eps(lo + 1) * eps(lo + 1);
+        if (hi == lo + 1) return -2 * eps(hi);
+        if (hi == lo + 2) return eps(lo + 1) * eps(lo + 2);
+        return 0;
+      };
+      std::vector<ld> sq(K);
       for (int i = 0; i < K; ++i) {
-        const int n = m + i;
-        for (int dj = -2; dj <= 2; ++dj) {
-          const int j = i + dj;
-          if (j < 0 || j >= K) continue;
-          const int nj = m + j;
-          ld g;
-          const int lo = std::min(n, nj), hi = std::max(n, nj);
-          if (hi == lo) g = 1 + eps(lo) * eps(lo) + eps(lo + 1) * eps(lo + 1);
-          else if (hi == lo + 1) g = -2 * eps(hi);
-          else g = eps(lo + 1) * eps(lo + 2);
-          ld v = g * (ld)nj * (nj + 1) / ell2;
-          if (dj == 0) v += kap * kap;
-          X.set(i, j, v);
-        }
+        const ld n = m + n0 + i;
+        sq[i] = sqrtl(n * (n + 1));
       }
-      // L = -nu X - nu_h X^{p/2}
-      Band Lb(K, b);
-      Band Xp = X;
-      if (d->nu_h > 0)
-        for (int q = 1; q < half; ++q) Xp = band_mul(Xp, X);
+      std::vector<double> S((size_t)K * K, 0.0), w, Q;
       for (int i = 0; i < K; ++i)
-        for (int j = std::max(0, i - b); j <= std::min(K - 1, i + b); ++j) {
-          ld v = -(ld)d->nu * X.get(i, j);
-          if (d->nu_h > 0) v -= (ld)d->nu_h * Xp.get(i, j);
-          Lb.set(i, j, v);
-        }
+        for (int j = std::max(0, i - 2); j <= std::min(K - 1, i + 2); ++j)
+          S[(size_t)i * K + j] = (double)(sq[i] * gram(m + n0 + i, m + n0 + j) * sq[j] / ell2);
+      if (!sym_eig(K, S, w, Q)) {
+        failed = true;
+        continue;
+      }
+      double* F = fwd.data() + qoff[m];
+      double* B = bwd.data() + qoff[m];
       for (int i = 0; i < K; ++i)
-        for (int c = 0; c < ncb; ++c) {
-          const int j = i + c - b;
-          band[((size_t)(p->off[m] + i) * ncb + c) * nkabs + ka] = (double)Lb.get(i, j);
+        for (int j = 0; j < K; ++j) {
+          F[(size_t)i * K + j] = (double)(Q[(size_t)i * K + j] * sq[i]);
+          B[(size_t)j * K + i] = (double)(Q[(size_t)i * K + j] / sq[i]);
         }
-      // banded LU with partial pivoting of I - h L (upper bandwidth grows to 2b)
-      for (int hi = 0; hi < 2; ++hi) {
-        const int wu = 2 * b;
-        std::vector<ld> A((size_t)K * (b + wu + 1), 0);  // row i holds columns i - b .. i + wu
-        auto at = [&](int i, int j) -> ld& { return A[(size_t)i * (b + wu + 1) + (j - i + b)]; };
-        for (int i = 0; i < K; ++i)
-          for (int j = std::max(0, i - b); j <= std::min(K - 1, i + b); ++j)
-            at(i, j) = (i == j ? 1 : 0) - hs[hi] * Lb.get(i, j);
-        for (int t = 0; t < K; ++t) {
-          int pr = t;
-          ld best = fabsl(at(t, t));
-          for (int r = t + 1; r <= std::min(K - 1, t + b); ++r)
-            if (fabsl(at(r, t)) > best) { best = fabsl(at(r, t)); pr = r; }
-          if (pr != t)
-            for (int j = std::max(0, t - b); j <= std::min(K - 1, t + wu); ++j) {
-              // rows t and pr both cover columns t .. t + wu after elimination of earlier columns
-              if (j < pr - b || j > pr + wu || j < t - b || j > t + wu) continue;
-              std::swap(at(t, j), at(pr, j));
-            }
-          const size_t fb = ((size_t)(p->off[m] + t) * ncf) * nkabs + ka;
-          fac[hi][fb + (size_t)b * nkabs] = (double)(pr - t);
-          const ld piv = at(t, t);
-          for (int r = t + 1; r <= std::min(K - 1, t + b); ++r) {
-            const ld l = at(r, t) / piv;
-            at(r, t) = 0;
-            fac[hi][fb + (size_t)(r - t - 1) * nkabs] = (double)l;
-            if (l != 0)
-              for (int j = t + 1; j <= std::min(K - 1, t + wu); ++j)
-                if (j <= r + wu) at(r, j) -= l * at(t, j);
+      std::copy(w.begin(), w.end(), lam.begin() + loff[m]);
+      if (m == 0) {
+        // b_n = X_{0 n} = G_{0 n} n (n + 1) / ell^2 (n = 1, 2); u_j = sum_n b_n V[n][j]
+        for (int j = 0; j < K; ++j) {
+          ld acc = 0;
+          for (int i = 0; i < std::min(K, 2); ++i) {
+            const int n = 1 + i;
+            const ld b = gram(0, n) * (ld)n * (n + 1) / ell2;
+            acc += b * (ld)Q[(size_t)i * K + j] / sq[i];
           }
-          fac[hi][fb + (size_t)(b + 1) * nkabs] = (double)(1 / piv);
-          for (int j = 1; j <= wu; ++j)
-            fac[hi][fb + (size_t)(b + 1 + j) * nkabs] = (t + j < K) ? (double)at(t, t + j) : 0.0;
+          u[j] = (double)acc;
         }
       }
     }
-  }
-  for (double* q : {p->d_step_band, p->d_step_fac[0], p->d_step_fac[1]})
-    if (q) (void)hipFree(q);
-  p->d_step_band = p->d_step_fac[0] = p->d_step_fac[1] = nullptr;
-  auto upl = [&](double** dst, const std::vector<double>& v) -> mlg_status {
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), std::max<size_t>(v.size(), 1) * sizeof(double));
+  };
+  const unsigned hw = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+  const int nthreads = (int)std::min<unsigned>(hw, (unsigned)std::max(Mm, 1));
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nthreads; ++t) pool.emplace_back(work);
+  work();
+  for (auto& t : pool) t.join();
+  if (failed) return fail(MLG_E_DEVICE, "step setup: eigen-decomposition did not converge");
+
+  double** bufs[] = {&p->d_step_fwd, &p->d_step_bwd, &p->d_step_lam, &p->d_step_u, &p->d_step_w};
+  for (double** q : bufs)
+    if (*q) (void)hipFree(*q);
+  if (p->d_step_qoff) (void)hipFree(p->d_step_qoff);
+  if (p->d_step_loff) (void)hipFree(p->d_step_loff);
+  p->d_step_fwd = p->d_step_bwd = p->d_step_lam = p->d_step_u = p->d_step_w = nullptr;
+  p->d_step_qoff = p->d_step_loff = nullptr;
+  p->step_ready = false;
+  auto upl = [&](auto** dst, const auto& v) -> mlg_status {
+    using T = typename std::decay_t<decltype(v)>::value_type;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), std::max<size_t>(v.size(), 1) * sizeof(T));
     if (e != hipSuccess) { *dst = nullptr; return fail(MLG_E_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e)); }
-    if (!v.empty() && hipMemcpy(*dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    if (!v.empty() && hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
       return fail(MLG_E_DEVICE, "hipMemcpy failed");
     return MLG_OK;
   };
   mlg_status st;
-  if ((st = upl(&p->d_step_band, band)) || (st = upl(&p->d_step_fac[0], fac[0])) ||
-      (st = upl(&p->d_step_fac[1], fac[1])))
+  if ((st = upl(&p->d_step_fwd, fwd)) || (st = upl(&p->d_step_bwd, bwd)) || (st = upl(&p->d_step_lam, lam)) ||
+      (st = upl(&p->d_step_u, u)) || (st = upl(&p->d_step_qoff, qoff)) || (st = upl(&p->d_step_loff, loff)))
     return st;
-  p->step_b = b;
-  p->step_nkabs = nkabs;
+  const size_t wel = ((size_t)p->tau + std::max(nrc - 1, 1)) * nz * 2;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->d_step_w), wel * sizeof(double));
+  if (e != hipSuccess) {
+    p->d_step_w = nullptr;
+    return fail(MLG_E_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  int maxk = 0;
+  for (int m = 0; m < Mm; ++m) maxk = std::max(maxk, nrc - m - (m == 0 ? 1 : 0));
+  p->step_maxk = maxk;
   p->step_dt = d->dt;
+  p->step_nu = d->nu;
+  p->step_nuh = d->nu_h;
+  p->step_q = d->nu_h > 0 ? d->p / 2 : 1;
   p->step_ready = true;
   return MLG_OK;
 }
@@ -284,28 +395,38 @@ mlg_status launch_step(const mlg_plan_s* p, int mode, int which, const double* s
   StepArgs a{};
   a.s = reinterpret_cast<const double2*>(s);
   a.a1 = reinterpret_cast<const double2*>(a1);
-  a.a0 = reinterpret_cast<const double2*>(a0);
+  a.a0 = mode == 1 ? reinterpret_cast<const double2*>(a0) : nullptr;
   a.out = reinterpret_cast<double2*>(out);
-  a.band = p->d_step_band;
-  a.fac = p->d_step_fac[which];
+  a.W = reinterpret_cast<double2*>(p->d_step_w);
+  a.W0 = a.W + (size_t)p->tau * p->nz;
+  a.fwd = p->d_step_fwd;
+  a.bwd = p->d_step_bwd;
+  a.lam = p->d_step_lam;
+  a.u = p->d_step_u;
+  a.qoff = p->d_step_qoff;
+  a.loff = p->d_step_loff;
   a.off = p->d_goff;
   a.M = p->M;
   a.nrc = p->nrc;
   a.nz = p->nz;
   a.nzc = p->nzc;
-  a.b = p->step_b;
-  a.nkabs = p->step_nkabs;
-  a.ncoef_band = 2 * p->step_b + 1;
-  a.ncoef_fac = p->step_b + 2 + 2 * p->step_b;
   a.mode = mode;
-  a.h = which == 0 ? p->step_dt / 2 : p->step_dt;
-  const int64_t cols = (int64_t)p->M * p->nz;
-  dim3 grid((unsigned)((cols + 63) / 64));
+  a.q = p->step_q;
+  a.h = (mode == 1 || which == 0) ? p->step_dt / 2 : p->step_dt;
+  a.nu = p->step_nu;
+  a.nuh = p->step_nuh;
+  a.kap0 = 2.0 * M_PI / p->g.lz;
+  const int mz = std::min(p->M, p->nrc);
   p->timing.begin("step", st);
-  step_kernel<<<grid, 64, 0, st>>>(a);
+  if (p->step_maxk > 0) {
+    dim3 grid((unsigned)((p->nz + TC - 1) / TC), (unsigned)((p->step_maxk + TM - 1) / TM), (unsigned)mz);
+    step_fwd_kernel<<<grid, 256, 0, st>>>(a);
+    step_bwd_kernel<<<grid, 256, 0, st>>>(a);
+  }
+  step_row0_kernel<<<(unsigned)((p->nz + 63) / 64), 64, 0, st>>>(a);
   p->timing.end(st);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail(MLG_E_DEVICE, std::string("step_kernel: ") + hipGetErrorString(e));
+  if (e != hipSuccess) return fail(MLG_E_DEVICE, std::string("step kernels: ") + hipGetErrorString(e));
   return MLG_OK;
 }
 

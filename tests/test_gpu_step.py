@@ -29,6 +29,9 @@ def _gpu():
     (40, 16, 6, 0.7, 3.0, 0.1, 0.0, 8, 0.05),
     (33, 10, 1, 1.5, 2 * np.pi, 0.02, 1e-5, 4, 0.02),
     (20, 8, 12, 2.0, 5.0, 0.001, 1e-7, 6, 0.1),
+    (64, 16, 16, 1.0, 8.6, 1e-4, 1e-14, 8, 5e-4),
+    (200, 6, 4, 1.0, 8.6, 1e-4, 1e-16, 8, 5e-4),
+    (256, 4, 2, 0.8, 3.0, 0.01, 0.0, 8, 1e-2),
 ])
 def test_step_parity(case):
     Plan = _gpu()
