@@ -5,7 +5,10 @@ synthesis of u and omega, inverse z and phi FFTs, (U + u) x omega, forward FFTs,
 Galerkin projection and the per-(m, k) elliptic solves (the whole transform round trip
 plus the nonlinear term).  value = N_r N_phi N_z / (seconds per step) / 1e9 [GDOF/s].
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Further sections of the same JSON line: per-kernel times and roofline fractions, the transform
+pair, the split-bfloat16 RHS with its error, the batched 2D launch, whole AB-CN time steps, the
+learned closure (training / inference cost, held-out gain, roll-outs) and the oracle timed on
+the host.  --gpus N with N > 1 exits: the benchmark runs on exactly one GPU.
 """
 from __future__ import annotations
 
@@ -29,6 +32,31 @@ PEAK_HBM_GBS = 8000.0
 # axial period 8.6 (the Crow wavelength in units of the separation), moving frame U = (0, 1, 0)
 PAIR = dict(gamma=2 * np.pi, a=0.1, b=1.0, delta=0.01, lz=8.6)
 U_FRAME = (0.0, 1.0, 0.0)
+
+
+# HBM traffic of the dominant kernel from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0,
+# the factors of a plain 256 MiB copy), per launch at 256^3; valid only while the kernel source is the
+# one that was measured.
+MEASURED_TRAFFIC = {
+    "synth_gemm": {"bytes": (493695 * 2 + 786432) * 1024, "n": 256,
+                   "source": "paper_2609_18026_amd/csrc/gemm_fused.hip",
+                   "sha256": "746af61a827db1017de16b9750f5f93047d5d20c73b6bd9b627fb1652f263728",
+                   "summary": "profiles/rhs_tp_256cubed_kernels.md"},
+}
+
+
+def measured_traffic(kernel, n):
+    import hashlib
+    rec = MEASURED_TRAFFIC.get(kernel)
+    if not rec or rec["n"] != n:
+        return None
+    try:
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
+                return None
+    except OSError:
+        return None
+    return rec["bytes"]
 
 
 def log(*a):
@@ -139,6 +167,155 @@ def bench_batched(torch, args, stream, e0, e1, count=64, seed=3):
     return res
 
 
+def bench_time_step(torch, plan, psi, chi, args, stream, e0, e1):
+    """Whole AB-CN steps of (psi, chi) at the bench size: one RHS plus the implicit update of both
+    potentials per step (Eq. abcn), through mlg_tp_advance on resident state."""
+    from paper_2609_18026_amd import mlg_timing_enable, mlg_timing_read
+    plan.step_setup(1e-4, 1e-14, 8, 5e-4)
+    p, c = psi.clone(), chi.clone()
+    hp, hc = plan.empty_spec(), plan.empty_spec()
+    tmp = torch.empty(6 * plan.layout.spec_elems, dtype=torch.complex128, device="cuda")
+    plan.advance(p, c, hp, hc, 1 + args.warmup, start=1, U=U_FRAME, tmp=tmp)
+    torch.cuda.synchronize()
+    mlg_timing_enable(plan.handle, True)
+    mlg_timing_read(plan.handle, "step")
+    e0.record(stream)
+    plan.advance(p, c, hp, hc, args.steps, start=0, U=U_FRAME, tmp=tmp)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    step_ms, launches = mlg_timing_read(plan.handle, "step")
+    mlg_timing_enable(plan.handle, False)
+    nrc, M, nz = plan.layout.nrc, plan.layout.M, plan.nz
+    ksq = sum((nrc - m - (1 if m == 0 else 0)) ** 2 for m in range(min(M, nrc)))
+    flops = 2 * 12.0 * nz * ksq          # two potentials; V^-1 [s | a] (2 products) and V W per m
+    impl_ms = step_ms / args.steps
+    finite = bool(torch.isfinite(torch.view_as_real(p)).all().item())
+    res = {"ms_per_step": round(ms, 4), "implicit_ms_per_step": round(impl_ms, 4),
+           "implicit_tflops": round(flops / (impl_ms / 1e3) / 1e12, 3),
+           "implicit_frac_fp64_peak": round(flops / (impl_ms / 1e3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+           "gdofs": round(plan.nr * plan.nphi * nz / (ms / 1e3) / 1e9, 4), "state_finite": finite,
+           "params": {"nu": 1e-4, "nu_h": 1e-14, "p": 8, "dt": 5e-4},
+           "paper_context": "the paper's 256^3 run (a different vortex, ell=4, p=8) takes 78.9 s per 30 steps on "
+                            "128 EPYC 7763 cores (Table tab:scaling), 2.63 s per step"}
+    log(f"bench: AB-CN time step {ms:.3f} ms (implicit part {impl_ms:.3f} ms)")
+    return res
+
+
+def bench_closure(torch, args, stream, e0, e1):
+    """Learned closure at the coarse 64^3 grid: cost of a training step (4096 columns) and of an
+    inference next to the coarse RHS, then the held-out gain of a network trained on fine 128^3
+    runs (the recipe of the gain test)."""
+    import synth
+    from paper_2609_18026_amd import Closure, Plan
+    from paper_2609_18026_amd import closure_runs as cr
+    n_c, n_f = 64, 128
+    coarse = Plan(n_c, n_c, n_c, 1.0, PAIR["lz"])
+    fine = Plan(n_f, n_f, n_f, 1.0, PAIR["lz"])
+    spec = cr.RunSpec(nu=1e-4, nu_h=1e-14, p=8, dt=5e-4, U=U_FRAME)
+    cr.setup(fine, spec)
+    cr.setup(coarse, spec)
+
+    def init(plan, delta, phase):
+        x, w, r = plan.nodes()
+        phi = 2 * np.pi * np.arange(plan.nphi) / plan.nphi
+        z = PAIR["lz"] * np.arange(plan.nz) / plan.nz
+        f = synth.vortex_pair_psi(r, phi, z, gamma=PAIR["gamma"], a=PAIR["a"], b=PAIR["b"], delta=delta,
+                                  lz=PAIR["lz"], phase=phase)
+        psi = plan.empty_spec()
+        plan.forward(torch.from_numpy(np.ascontiguousarray(f)).cuda(), psi)
+        return psi, torch.zeros_like(psi)
+
+    nsnap, every = 12, 40
+    runs = []
+    for i in range(8):
+        phase = float(synth.rng(5 + i).uniform(0, 2 * np.pi))
+        runs.append(cr.fine_run(fine, coarse, spec, *init(fine, (0.005, 0.01, 0.02)[i % 3], phase), nsnap, every))
+    torch.cuda.synchronize()
+
+    def merge(rs):
+        out = cr.Snapshots()
+        for r in rs:
+            out.psi += r.psi
+            out.chi += r.chi
+            out.ref_psi += r.ref_psi
+            out.ref_chi += r.ref_chi
+        return out
+
+    train, held = merge(runs[:6]), merge(runs[6:])
+    cl = Closure(coarse, max_batch=4096, beta=1.0)
+    X, Y = cr.dataset(coarse, cl, train, spec)
+    xr = torch.sqrt(torch.mean(X.double() ** 2, 0)).cpu().numpy()
+    yr = torch.sqrt(torch.mean(Y.double() ** 2, 0)).cpu().numpy()
+    xs = np.where(xr > 0, 1.0 / np.maximum(xr, 1e-300), 1.0).astype(np.float32)
+    ys = np.where(yr > 0, yr, 1.0).astype(np.float32)
+    cl.set_scales(xs, ys)
+    cl.set_params(synth.closure_init(1))
+    nb, steps = 4096, 3000
+    batches = torch.from_numpy(synth.batch_indices(X.shape[0], nb, steps, seed=3)).cuda()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    cr.fit(cl, X, Y, batches, 1e-3, 5e-5)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1) / steps
+    flops_train = 3 * 2.0 * nb * (288 * 256 + 256 * 256 + 256 * 256)
+    # inference and the coarse RHS on one held-out snapshot
+    p, c = held.psi[6], held.chi[6]
+    Np, Nc = coarse.empty_spec(), coarse.empty_spec()
+    reps = 50
+    e0.record(stream)
+    for _ in range(reps):
+        coarse.rhs_tp(p, c, Np, Nc, U=U_FRAME)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    rhs_ms = e0.elapsed_time(e1) / reps
+    free = Closure(coarse, max_batch=4096, beta=1e30)
+    free.set_scales(xs, ys)
+    free.set_params(cl.get_params())
+    e0.record(stream)
+    for _ in range(reps):
+        free.infer(p, c, Np, Nc)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    inf_ms = e0.elapsed_time(e1) / reps
+
+    def gain(closure, snaps):
+        res = cr.a_priori(coarse, closure, snaps, spec)
+        return sum(a for _, a, _ in res) / sum(b for b, _, _ in res), int(sum(f for *_, f in res))
+
+    g_tr, _ = gain(free, train)
+    g_free, _ = gain(free, held)
+    g_jud, nfb = gain(cl, held)
+    # a posteriori: roll-outs of the first held-out run against the truncated fine run
+    sn = runs[6]
+
+    def nrm(*ts):
+        return float(np.sqrt(sum(torch.linalg.vector_norm(t).item() ** 2 for t in ts)))
+
+    roll = {}
+    for name, clo in (("plain", None), ("closure_judged", cl)):
+        st = cr.rollout(coarse, spec, sn.psi[0], sn.chi[0], nsnap, every, closure=clo)
+        roll[name] = [round(nrm(a - sn.psi[j], b - sn.chi[j]) / nrm(sn.psi[j], sn.chi[j]), 6)
+                      for j, (a, b) in enumerate(st)][1:]
+    calls, fbs = cl.stats()
+    res = {"coarse": f"{n_c}^3", "fine": f"{n_f}^3", "columns": cl.ncols, "train_rows": int(X.shape[0]),
+           "train_step_ms": round(train_ms, 4), "train_batch": nb,
+           "train_tflops": round(flops_train / (train_ms / 1e3) / 1e12, 3),
+           "train_frac_bf16_peak": round(flops_train / (train_ms / 1e3) / 1e12 / 2500.0, 5),
+           "infer_ms": round(inf_ms, 4), "coarse_rhs_ms": round(rhs_ms, 4),
+           "infer_overhead_vs_rhs": round(inf_ms / rhs_ms, 4),
+           "a_priori_gain": {"train": round(g_tr, 4), "held_out_unjudged": round(g_free, 4),
+                             "held_out_judged": round(g_jud, 4), "held_out_fallbacks": nfb,
+                             "held_out_snapshots": len(held.psi)},
+           "rollout_rel_field_error": roll, "rollout_judge_calls_fallbacks": [calls, fbs],
+           "recipe": "8 fine vortex-pair runs (delta 0.005/0.01/0.02, phases from seeds 5..12), nu=1e-4, "
+                     "nu_h=1e-14, p=8, dt=5e-4, 12 snapshots 40 steps apart; runs 0-5 train, 6-7 held out"}
+    log(f"bench: closure train step {train_ms:.3f} ms, inference {inf_ms:.3f} ms vs coarse RHS {rhs_ms:.3f} ms, "
+        f"held-out gain {g_free:.3f} (judged {g_jud:.3f})")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,12 +324,13 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure section")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain device copy of 256 MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the single-GPU kernels and a sharding design are described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported (the library has no "
+              "multi-GPU path: its kernels work on one GPU's share of the grid)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2609_18026_amd import Plan, mlg_timing_enable, mlg_timing_read
@@ -211,12 +389,13 @@ def main():
     if work[dom]["flops"]:
         launches = max(kern[dom][1], 1)
         roofline = dict(bound="mfma", kernel=dom, achieved=d["tflops"], peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                        frac=d["frac_fp64_peak"], traffic=None,
+                        frac=d["frac_fp64_peak"], traffic=measured_traffic(dom, n),
+                        algorithmic_bytes_per_launch=work[dom]["bytes"],
                         work_per_launch=work[dom]["flops"] * args.steps / launches, avg_launch_ms=d["avg_launch_ms"])
     else:
         launches = max(kern[dom][1], 1)
         roofline = dict(bound="hbm", kernel=dom, achieved=d["gbs"], peak=PEAK_HBM_GBS, unit="GB/s",
-                        frac=d["frac_hbm_peak"], traffic=None,
+                        frac=d["frac_hbm_peak"], traffic=measured_traffic(dom, n),
                         work_per_launch=work[dom]["bytes"] * args.steps / launches, avg_launch_ms=d["avg_launch_ms"])
     # transform pair of one scalar on the same plan (extra figure)
     phys = plan.empty_phys()
@@ -269,6 +448,9 @@ def main():
                          "rel_err_velocity_of_output_vs_fp64": verr, "rel_err_psi_coefficients_vs_fp64": cerr}
     log(f"bench: split-bf16 {sms:.3f} ms/step, velocity rel err {verr:.2e} (coefficients {cerr:.2e})")
     out["batched_2d"] = bench_batched(torch, args, stream, e0, e1)
+    out["time_step"] = bench_time_step(torch, plan, psi, chi, args, stream, e0, e1)
+    if not args.no_closure:
+        out["closure"] = bench_closure(torch, args, stream, e0, e1)
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)

@@ -89,22 +89,24 @@ class VecTables:
         self.L = np.arange(g.nrc, dtype=np.float64) * (np.arange(g.nrc) + 1.0)
 
 
-def velocity_vorticity_harmonics(psi: np.ndarray, chi: np.ndarray, g: Grid, vt: VecTables):
-    """Harmonics (M, N_r, N_z) in spectral k of u_r, u_phi, u_z, w_r, w_phi, w_z at the nodes.
+def velocity_vorticity_harmonics(psi: np.ndarray, chi: np.ndarray, g: Grid, vt: VecTables, nodes=None):
+    """Harmonics (M, N_r, N_z) in spectral k of u_r, u_phi, u_z, w_r, w_phi, w_z at the nodes
+    (at the radial nodes listed in ``nodes`` only, if given).
 
     u = (1/r d_phi psi + d_r d_z chi,  -d_r psi + (1/r) d_phi d_z chi,  -grad_h^2 chi)
     w = (d_r d_z psi - (1/r) d_phi grad^2 chi,  (1/r) d_phi d_z psi + d_r grad^2 chi,  -grad_h^2 psi)
     per harmonic (d_phi -> i m, d_z -> i kappa, grad^2 = grad_h^2 - kappa^2).
     """
-    M, nr, nz = g.M, g.nr, g.nz
+    sel = np.arange(g.nr) if nodes is None else np.asarray(nodes)
+    M, nr, nz = g.M, len(sel), g.nz
     kap = g.kappa()
     keep = g.kmask()
-    r = g.r
-    q = g.q
-    x = g.x
+    r = g.r[sel]
+    q = g.q[sel]
+    x = g.x[sel]
     outs = [np.zeros((M, nr, nz), dtype=np.complex128) for _ in range(6)]
     for m in range(M):
-        P, T = vt.P[m], vt.T[m]
+        P, T = vt.P[m][:, sel], vt.T[m][:, sel]
         ps = psi[m] * keep[None, :]
         ch = chi[m] * keep[None, :]
         A1 = P.T @ ps                         # psi
@@ -141,6 +143,28 @@ def synthesize(psi: np.ndarray, chi: np.ndarray, g: Grid, vt: VecTables):
     return nodal[:3], nodal[3:]
 
 
+def synthesize_points(psi: np.ndarray, chi: np.ndarray, g: Grid, vt: VecTables, pts):
+    """Nodal u and omega at grid points pts = [(l, i, j)]: the harmonics at those radial nodes,
+    summed over m and kept k (Eq. expansion); returns an array (6, len(pts))."""
+    nodes = sorted({i for _, i, _ in pts})
+    where = {i: a for a, i in enumerate(nodes)}
+    h = velocity_vorticity_harmonics(psi, chi, g, vt, nodes=nodes)
+    kap = g.kappa()
+    keep = g.kmask()
+    out = np.zeros((6, len(pts)))
+    for c, (l, i, j) in enumerate(pts):
+        ez = np.exp(1j * kap * g.z[l]) * keep
+        for f in range(6):
+            acc = 0.0
+            for m in range(g.M):
+                if g.nphi % 2 == 0 and m == g.nphi // 2:
+                    continue
+                term = (h[f][m, where[i]] @ ez) * np.exp(1j * m * g.phi[j])
+                acc += term.real if m == 0 else 2.0 * term.real
+            out[f, c] = acc
+    return out
+
+
 def cross_with_background(u, w, U, g: Grid):
     """N = (U + u) x w in cylindrical components; U = (U_x, U_y, U_z) Cartesian."""
     cphi = np.cos(g.phi)[None, None, :]
@@ -170,20 +194,49 @@ def projection_sources(Nr_, Np_, Nz_, g: Grid, vt: VecTables):
     K = np.zeros_like(C)
     Z = np.zeros_like(C)
     for m in range(min(g.M, g.nrc)):   # orders m >= N_r^c have no coefficients
-        WP = vt.P[m] * g.w[None, :]
-        WQ = vt.Q[m] * g.w[None, :]
-        Pa, Qa = WP @ a[m], WQ @ a[m]
-        Pb, Qb = WP @ b[m], WQ @ b[m]
-        Zm = WP @ c[m]
-        Z[m] = Zm
-        # z.curl N = (1/r) d_r(r N_phi) - i m N_r / r ; weak form of the first term is -Q^T W (N_phi/r)
-        C[m] = -Qb - 1j * m * Pa
-        # z.curl curl N = i kappa (1/r) d_r(r N_r) - m kappa N_phi / r - grad_h^2 N_z
-        D = np.zeros((g.nrc, g.nrc))
-        D[m:, m:] = laplacian_matrix(m, g.nrc, g.ell)
-        K[m] = 1j * kap[None, :] * (-Qa) - m * kap[None, :] * Pb - D @ Zm
+        C[m], K[m], Z[m] = _sources(a[m], b[m], c[m], m, kap[None, :], g, vt)
     keep = g.kmask()[None, None, :]
     return C * keep, K * keep, Z * keep
+
+
+def _sources(a_m, b_m, c_m, m, kap, g: Grid, vt: VecTables):
+    """C, K, Zhat of order m from the harmonics of N_r/r, N_phi/r, N_z at the nodes."""
+    WP = vt.P[m] * g.w[None, :]
+    WQ = vt.Q[m] * g.w[None, :]
+    Pa, Qa = WP @ a_m, WQ @ a_m
+    Pb, Qb = WP @ b_m, WQ @ b_m
+    Zm = WP @ c_m
+    # z.curl N = (1/r) d_r(r N_phi) - i m N_r / r ; weak form of the first term is -Q^T W (N_phi/r)
+    C = -Qb - 1j * m * Pa
+    # z.curl curl N = i kappa (1/r) d_r(r N_r) - m kappa N_phi / r - grad_h^2 N_z
+    D = np.zeros((g.nrc, g.nrc))
+    D[m:, m:] = laplacian_matrix(m, g.nrc, g.ell)
+    K = 1j * kap * (-Qa) - m * kap * Pb - D @ Zm
+    return C, K, Zm
+
+
+def projection_sources_columns(Nr_, Np_, Nz_, g: Grid, vt: VecTables, cols):
+    """C, K, Zhat for selected (m, kk) columns: the harmonics by the plain sums over phi and z,
+    then the Galerkin projections of ``projection_sources``; {(m, kk): (C, K, Z)}."""
+    kap = g.kappa()
+    keep = g.kmask()
+    out = {}
+    for m, kk in cols:
+        e_z = np.exp(-1j * kap[kk] * g.z)
+        e_p = np.exp(-1j * m * g.phi)
+
+        def harm(f):
+            return np.einsum("lij,l,j->i", f, e_z, e_p) / (g.nphi * g.nz)
+
+        a = harm(Nr_ / g.r[None, :, None])
+        b = harm(Np_ / g.r[None, :, None])
+        c = harm(Nz_)
+        if keep[kk] and m < g.nrc:
+            out[(m, kk)] = _sources(a, b, c, m, kap[kk], g, vt)
+        else:
+            z = np.zeros(g.nrc, dtype=np.complex128)
+            out[(m, kk)] = (z, z.copy(), z.copy())
+    return out
 
 
 def _gauge_row(nrc: int) -> np.ndarray:

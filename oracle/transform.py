@@ -166,3 +166,46 @@ def backward_bruteforce(S: np.ndarray, g: Grid) -> np.ndarray:
                 s[l, i, j] = acc
     # m = 0 enters through its real part; for m != 0 the (m, -m) pairs are conjugate
     return s.real
+
+
+# ----------------------------------------------------------------- sampled evaluation
+# The same sums for a few output columns or points, for checks at sizes where the full
+# transform is slow on the host.
+
+def forward_columns(s: np.ndarray, g: Grid, cols):
+    """The forward sum for selected (m, kk) columns: {(m, kk): complex (N_r^c,)}."""
+    kap = g.kappa()
+    keep = g.kmask()
+    out = {}
+    for m, kk in cols:
+        col = np.zeros(g.nrc, dtype=np.complex128)
+        if keep[kk]:
+            e_z = np.exp(-1j * kap[kk] * g.z)
+            e_p = np.exp(-1j * m * g.phi)
+            f = np.einsum("lij,l,j->i", s, e_z, e_p) / (g.nphi * g.nz)
+            P = pbar(m, g.nrc, g.x_ld).astype(np.float64)
+            col = (P * g.w[None, :]) @ f
+            col[:m] = 0.0
+        out[(m, kk)] = col
+    return out
+
+
+def backward_points(S: np.ndarray, g: Grid, pts):
+    """Eq. expansion at grid points pts = [(l, i, j)], summed over m, n and kept k."""
+    kap = g.kappa()
+    keep = g.kmask()
+    nodes = sorted({i for _, i, _ in pts})
+    P = [pbar(m, g.nrc, g.x_ld[nodes]).astype(np.float64) for m in range(g.M)]
+    where = {i: a for a, i in enumerate(nodes)}
+    vals = []
+    for l, i, j in pts:
+        ez = np.exp(1j * kap * g.z[l]) * keep
+        acc = 0.0
+        for m in range(g.M):
+            if g.nphi % 2 == 0 and m == g.nphi // 2:
+                continue
+            v = (P[m][:, where[i]] @ S[m]) @ ez
+            term = v * np.exp(1j * m * g.phi[j])
+            acc += term.real if m == 0 else 2.0 * term.real
+        vals.append(acc)
+    return np.array(vals)

@@ -296,7 +296,11 @@ __global__ __launch_bounds__(128) void phi_bwd256_kernel(Phi256 g, const double2
   if (q < g.nlines) {
     const bool imag = (ll & 1) != 0;
 #pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) phys[phys_off(g, q) + s + 16 * k1] = imag ? v[k1].y : v[k1].x;
+    for (int k1 = 0; k1 < 16; ++k1) {
+      // select values, not addresses, so that v stays in registers
+      const double re = v[k1].x, im = v[k1].y;
+      phys[phys_off(g, q) + s + 16 * k1] = imag ? im : re;
+    }
   }
 }
 

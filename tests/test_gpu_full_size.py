@@ -1,0 +1,208 @@
+"""Parity at the benchmark's full sizes, in its launch configuration.
+
+* 256^3 (the bench plan: N_r = N_phi = N_z = 256, ell = 1, L_z = 8.6, two-thirds mask, FP64): the
+  vortex-pair stream function plus a small geometric poloidal part.  The oracle computes sampled
+  outputs one by one, each stage from the library's own previous stage: forward-transform columns
+  from the physical field; backward-transform values at points; nodal u and omega at points from
+  (psi, chi); N = (U + u) x omega at every node from the library's u and omega; the Galerkin sources
+  at sampled columns from the library's N; the backward error of the elliptic solves at those
+  columns from the library's sources.
+* 128^3 geometric potentials (ell = 1, L_z = 2 pi, U = 0): the full oracle RHS, tap by tap.
+* The 64 uneven 2D KPP instances of the batched workload, in the autotuned launch, per instance.
+"""
+import numpy as np
+import pytest
+
+import synth
+from helpers import from_lib, rel, to_lib
+from oracle.basis import laplacian_matrix
+from oracle.grid import Grid
+from oracle.rhs import VecTables, cross_with_background, projection_sources_columns, synthesize_points
+from oracle.transform import backward_points, forward_columns
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL = 1e-12
+# backward error of a factorisation-based solve of order n grows like n eps; the small-grid tests
+# (n <= 70) use 1e-14, these sizes use 2 n eps
+EPS = np.finfo(np.float64).eps
+N, ELL, LZ = 256, 1.0, 8.6
+U = (0.0, 1.0, 0.0)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2609_18026_amd as m
+    return m
+
+
+def _points(g, count, seed):
+    r = np.random.default_rng(seed)
+    pts = [(0, 0, 0), (g.nz - 1, g.nr - 1, g.nphi - 1), (g.nz // 3, int(np.argmin(np.abs(g.r - 0.5))), 0),
+           (g.nz // 2, int(np.argmin(np.abs(g.r - 0.5))), g.nphi // 2)]
+    while len(pts) < count:
+        pts.append((int(r.integers(g.nz)), int(r.integers(g.nr)), int(r.integers(g.nphi))))
+    return pts
+
+
+def _pick_columns(S, top, extra, seed, allowed=None):
+    """The `top` (m, kk) columns of largest norm in S (M, nrc, nz) plus `extra` random ones."""
+    nrm = np.linalg.norm(S, axis=1)
+    if allowed is not None:
+        nrm = np.where(allowed, nrm, -1.0)
+    order = np.argsort(nrm, axis=None)[::-1]
+    cols = [tuple(int(v) for v in np.unravel_index(o, nrm.shape)) for o in order[:top]]
+    r = np.random.default_rng(seed)
+    cand = np.argwhere(nrm > 0) if allowed is None else np.argwhere(allowed)
+    while len(cols) < top + extra:
+        c = tuple(int(v) for v in cand[r.integers(len(cand))])
+        if c not in cols:
+            cols.append(c)
+    return cols
+
+
+def _column_backward_error(g, m, kk, psi, chi, C, K, Z):
+    """||A x - b|| / (||A|| ||x|| + ||b||) of the three systems of one (m, k) column (dealiased)."""
+    kap = g.kappa()[kk]
+    D = laplacian_matrix(m, g.nrc, g.ell)
+    Dg = D.copy()
+    if m == 0:
+        Dg[0, :] = np.sqrt((2 * np.arange(g.nrc) + 1) / 2.0)
+    nA = np.linalg.norm(Dg, 2)
+    worst = 0.0
+    b = -C[m:].copy()
+    if m == 0:
+        b[0] = 0
+    x = psi[m:]
+    worst = max(worst, np.linalg.norm(Dg @ x - b) / (nA * np.linalg.norm(x) + np.linalg.norm(b)))
+    q = -Z[m:] if kap == 0 else np.linalg.solve(D - kap ** 2 * np.eye(D.shape[0]), K[m:])
+    b = q.copy()
+    if m == 0:
+        b[0] = 0
+    x = chi[m:]
+    return max(worst, np.linalg.norm(Dg @ x - b) / (nA * np.linalg.norm(x) + np.linalg.norm(b)))
+
+
+@pytest.mark.timeout(600)
+def test_full_size_256_sampled():
+    m = _gpu()
+    _say("256^3 sampled parity: setup")
+    g = Grid(N, N, N, ELL, lz=LZ)
+    plan = m.Plan(N, N, N, ELL, LZ, dealias=1)
+    f = synth.vortex_pair_psi(g.r, g.phi, g.z, lz=LZ)
+    fd = torch.from_numpy(np.ascontiguousarray(f)).cuda()
+    psi = plan.empty_spec()
+    plan.forward(fd, psi)
+    chi_host = 1e-2 * synth.geometric_spectrum(g.M, g.nrc, g.nz, g.nzc, seed=9, a=0.9, b=0.85, c=0.85)
+    chi = torch.from_numpy(to_lib(chi_host)).cuda()
+    torch.cuda.synchronize()
+    psi_host = from_lib(psi.cpu().numpy(), g.M, g.nrc)
+
+    # forward transform: sampled columns from the physical field
+    # the pair is odd in x (even orders vanish): sample the largest columns and some random ones
+    cols = _pick_columns(psi_host, 6, 4, seed=5)
+    _say("  columns", cols)
+    _say("  forward columns")
+    fc = forward_columns(f, g, cols)
+    got = np.concatenate([psi_host[mm, :, kk] for mm, kk in cols])
+    want = np.concatenate([fc[c] for c in cols])
+    err = rel(got, want)
+    _say("  forward columns rel", err)
+    assert err < TOL
+
+    # backward transform: values at points from the library's coefficients
+    _say("  backward points")
+    pts = _points(g, 16, seed=11)
+    phys = plan.empty_phys()
+    plan.backward(psi, phys)
+    torch.cuda.synchronize()
+    ph = phys.cpu().numpy()
+    bp = backward_points(psi_host, g, pts)
+    err = rel(np.array([ph[l, i, j] for l, i, j in pts]), bp)
+    _say("  backward points rel", err)
+    assert err < TOL
+    del ph, phys
+
+    # RHS with taps
+    _say("  rhs_tp with taps")
+    tp = plan.taps_buffer()
+    po, co = plan.empty_spec(), plan.empty_spec()
+    plan.rhs_tp(psi, chi, po, co, U=U, taps=tp)
+    torch.cuda.synchronize()
+    pe = plan.layout.phys_elems
+    tn = tp.cpu().numpy()
+    del tp
+    nodal = tn[:9 * pe].reshape(9, N, N, N)
+    src = tn[9 * pe:].view(np.complex128).reshape(3, plan.tau, N)
+    vt = VecTables(g)
+    _say("  nodal u, w at points")
+    sp = synthesize_points(psi_host, chi_host, g, vt, pts)
+    got = np.array([[nodal[f][l, i, j] for l, i, j in pts] for f in range(6)])
+    err = rel(got, sp)
+    _say("  nodal u, w rel", err)
+    assert err < TOL
+    _say("  N at every node")
+    Nref = cross_with_background(nodal[0:3], nodal[3:6], U, g)
+    for c in range(3):
+        e = rel(nodal[6 + c], Nref[c])
+        _say("  N", c, "rel", e)
+        assert e < TOL
+    del Nref
+    _say("  sources at columns")
+    from oracle.rhs import dealias_mask
+    Cl, Kl, Zl = (from_lib(src[i], g.M, g.nrc) for i in range(3))
+    acols = _pick_columns(Cl, 5, 4, seed=6, allowed=dealias_mask(g)) + [(0, 0), (85, 85)]
+    _say("  columns", acols)
+    pc = projection_sources_columns(nodal[6], nodal[7], nodal[8], g, vt, acols)
+    for i, name in enumerate(("C", "K", "Z")):
+        lib_v = np.concatenate([(Cl, Kl, Zl)[i][mm, :, kk] for mm, kk in acols])
+        ref_v = np.concatenate([pc[c][i] for c in acols])
+        e = rel(lib_v, ref_v)
+        _say("  source", name, "rel", e)
+        assert e < TOL
+    _say("  solves at columns")
+    pl, cl = from_lib(po.cpu().numpy(), g.M, g.nrc), from_lib(co.cpu().numpy(), g.M, g.nrc)
+    worst = max(_column_backward_error(g, mm, kk, pl[mm, :, kk], cl[mm, :, kk], Cl[mm, :, kk], Kl[mm, :, kk],
+                                       Zl[mm, :, kk]) for mm, kk in acols)
+    _say("  solve backward error", worst)
+    assert worst < 2 * g.nrc * EPS
+
+
+@pytest.mark.timeout(600)
+def test_config2_128_full_oracle():
+    _gpu()
+    from test_gpu_parity import _backward_error, _tp_case
+    _say("128^3 full oracle rhs_tp")
+    g, taps, ref_psi, ref_chi, got = _tp_case(128, 128, 128, 1.0, 2 * np.pi, (0.0, 0.0, 0.0), 1,
+                                             seeds=(2, 3), rates=(0.9, 0.85, 0.85))
+    for i in range(6):
+        e = rel(got["nodal"][i], (list(taps["u"]) + list(taps["w"]))[i])
+        assert e < TOL, (i, e)
+    for i in range(3):
+        e = rel(got["nodal"][6 + i], taps["N"][i])
+        assert e < TOL, ("N", i, e)
+    for nm in ("C", "K", "Z"):
+        e = rel(got[nm], taps[nm])
+        _say("  source", nm, "rel", e)
+        assert e < TOL, (nm, e)
+    be = _backward_error(g, got["psi"], got["chi"], got["C"], got["K"], got["Z"], True)
+    _say("  backward error", be, "forward rel diff", rel(got["psi"], ref_psi), rel(got["chi"], ref_chi))
+    assert be < 2 * g.nrc * EPS
+
+
+@pytest.mark.timeout(600)
+def test_batched_64_instances_autotuned():
+    _gpu()
+    from test_gpu_batch import _instances, _run
+    _say("64 batched instances, autotuned")
+    insts = _instances(64, seed=3)
+    for prec, tol in ((0, TOL), (1, 1e-5)):
+        errs = _run(insts, prec, None, autotune=True)
+        _say("  precision", prec, "worst instance rel", max(errs))
+        assert max(errs) < tol

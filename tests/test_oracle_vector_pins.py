@@ -171,3 +171,35 @@ def test_cross_product_orientation():
     N = cross_with_background([zero, zero, zero], [zero, zero, one], (1.0, 0, 0), g)
     # U x e_z with U = e_x gives -e_y: radial part -sin(phi), azimuthal part -cos(phi)
     assert np.allclose(N[0][0, 0], -np.sin(g.phi)) and np.allclose(N[1][0, 0], -np.cos(g.phi))
+
+
+def test_sampled_evaluations_agree_with_the_full_oracle():
+    """The column / point forms used for checks at full size equal the full transforms."""
+    from oracle.rhs import projection_sources_columns, synthesize_points
+    from oracle.transform import Tables, backward, backward_points, forward, forward_columns
+    g = Grid(18, 12, 10, 0.9, lz=3.0)
+    t = Tables(g)
+    vt = VecTables(g)
+    rng = np.random.default_rng(4)
+    f = rng.standard_normal((g.nz, g.nr, g.nphi))
+    S = forward(f, g, t)
+    cols = [(0, 0), (0, 3), (1, 9), (4, 2), (5, 5), (3, 7)]
+    fc = forward_columns(f, g, cols)
+    for (m, kk), v in fc.items():
+        np.testing.assert_allclose(v, S[m, :, kk], rtol=0, atol=1e-13 * np.abs(S).max())
+    pts = [(0, 0, 0), (3, 17, 5), (9, 8, 11), (5, 2, 6)]
+    bp = backward_points(S, g, pts)
+    full = backward(S, g, t)
+    np.testing.assert_allclose(bp, [full[l, i, j] for l, i, j in pts], rtol=0, atol=1e-13 * np.abs(full).max())
+    psi = synth.geometric_spectrum(g.M, g.nrc, g.nz, g.nzc, seed=7, a=0.8)
+    chi = synth.geometric_spectrum(g.M, g.nrc, g.nz, g.nzc, seed=8, a=0.8)
+    u, w = synthesize(psi, chi, g, vt)
+    sp = synthesize_points(psi, chi, g, vt, pts)
+    ref = np.array([[x[l, i, j] for l, i, j in pts] for x in list(u) + list(w)])
+    np.testing.assert_allclose(sp, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    N = cross_with_background(u, w, (0.1, 0.4, -0.2), g)
+    C, K, Z = projection_sources(*N, g, vt)
+    pc = projection_sources_columns(*N, g, vt, cols)
+    for (m, kk), (c, k, z) in pc.items():
+        for got, want in ((c, C), (k, K), (z, Z)):
+            np.testing.assert_allclose(got, want[m, :, kk], rtol=0, atol=1e-12 * np.abs(want).max())
