@@ -137,7 +137,7 @@ __device__ __forceinline__ void bpass(const Cx<T>* in, Cx<T>* out, int n, int Ns
 }
 
 template <typename T>
-__device__ Cx<T>* bfft(Cx<T>* x, Cx<T>* y, const BatchInst& I, const double* __restrict__ tw, bool inv, int nl) {
+__device__ __forceinline__ Cx<T>* bfft(Cx<T>* x, Cx<T>* y, const BatchInst& I, const double* __restrict__ tw, bool inv, int nl) {
   const int tid = threadIdx.x, nth = blockDim.x;
   int Ns = 1;
   Cx<T>* a = x;
@@ -175,7 +175,7 @@ struct BatchArgs {
 
 template <typename T>
 __device__ void phase_backward(const BatchArgs<T>& A, int b, int m, char* smem) {
-  const BatchInst I = A.inst[b];
+  const BatchInst& I = A.inst[b];
   const int K = I.nrc > m ? I.nrc - m : 0;
   Cx<T>* mix = A.mix + I.mix_off + (int64_t)m * I.nr;
   if (K == 0) {
@@ -210,8 +210,20 @@ __device__ void phase_backward(const BatchArgs<T>& A, int b, int m, char* smem) 
       }
       acc = cx<T>((T)ar, (T)ai);
     } else {
+      // eight independent partial sums keep eight table loads in flight
       const T* P = A.tabT + I.tb_off + trow * I.nr + i;
-      for (int t = 0; t < K; ++t) acc = acc + scl(s[t], P[(int64_t)t * I.nr]);
+      Cx<T> part[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) part[u] = cx<T>(0, 0);
+      int t = 0;
+      for (; t + 8 <= K; t += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) part[u] = part[u] + scl(s[t + u], P[(int64_t)(t + u) * I.nr]);
+      }
+      for (; t < K; ++t) part[0] = part[0] + scl(s[t], P[(int64_t)t * I.nr]);
+#pragma unroll
+      for (int u = 1; u < 8; ++u) part[0] = part[0] + part[u];
+      acc = part[0];
     }
     mix[i] = acc;
   }
@@ -220,7 +232,7 @@ __device__ void phase_backward(const BatchArgs<T>& A, int b, int m, char* smem) 
 
 template <typename T>
 __device__ void phase_phi(const BatchArgs<T>& A, int b, int q0, char* smem) {
-  const BatchInst I = A.inst[b];
+  const BatchInst& I = A.inst[b];
   const int n = I.nphi, L = A.lines, np = L / 2;
   Cx<T>* X = reinterpret_cast<Cx<T>*>(smem);
   Cx<T>* Y = X + np * n;
@@ -273,7 +285,7 @@ __device__ void phase_phi(const BatchArgs<T>& A, int b, int q0, char* smem) {
 
 template <typename T>
 __device__ void phase_forward(const BatchArgs<T>& A, int b, int m, char* smem) {
-  const BatchInst I = A.inst[b];
+  const BatchInst& I = A.inst[b];
   const int K = I.nrc > m ? I.nrc - m : 0;
   if (K == 0) return;
   const int64_t trow = A.tri[I.tri_off + m];
@@ -288,9 +300,19 @@ __device__ void phase_forward(const BatchArgs<T>& A, int b, int m, char* smem) {
   __syncthreads();
   const T* P = A.tabT + I.tf_off + trow * I.nr;
   for (int t = threadIdx.x; t < K; t += blockDim.x) {
-    Cx<T> acc = cx<T>(0, 0);
-    for (int i = 0; i < I.nr; ++i) acc = acc + scl(g[i], P[(int64_t)i * K + t]);
-    out[t] = acc;
+    // eight independent partial sums keep eight table loads in flight
+    Cx<T> part[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) part[u] = cx<T>(0, 0);
+    int i = 0;
+    for (; i + 8 <= I.nr; i += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) part[u] = part[u] + scl(g[i + u], P[(int64_t)(i + u) * K + t]);
+    }
+    for (; i < I.nr; ++i) part[0] = part[0] + scl(g[i], P[(int64_t)i * K + t]);
+#pragma unroll
+    for (int u = 1; u < 8; ++u) part[0] = part[0] + part[u];
+    out[t] = part[0];
   }
   __syncthreads();
 }
