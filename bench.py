@@ -74,17 +74,25 @@ def active_columns(nphi, nz, M, nrc, dealias=True):
     return mmax, nkact
 
 
+def radial_folded(nr):
+    """Even N_r: the library folds the radial products over the node symmetry (half the flops),
+    unless MLG_RADIAL_FOLD=0 was set when the plan was created."""
+    return nr % 2 == 0 and os.environ.get("MLG_RADIAL_FOLD", "1") != "0"
+
+
 def kernel_work(nr, nphi, nz, M, nrc):
-    """Algorithmic flops / HBM bytes per RHS step for each kernel family (FP64)."""
+    """Algorithmic flops / HBM bytes per RHS step for each kernel family (FP64); with parity
+    folding the radial products count half the flops and read half of each table."""
     tau = sum(max(nrc - m, 0) for m in range(M))
     mmax, nkact = active_columns(nphi, nz, M, nrc)
     tau_a = sum(max(nrc - m, 0) for m in range(mmax))
     mixed = M * nr * nz * 16                     # one harmonic field, complex
+    f = 0.5 if radial_folded(nr) else 1.0
     w = {}
-    w["synth_gemm"] = dict(flops=7 * 2.0 * nr * tau * 2 * nz,
-                           bytes=2 * tau * nr * 8 + 2 * tau * nz * 16 + 6 * mixed)
-    w["proj_gemm"] = dict(flops=5 * 2.0 * nr * tau_a * 2 * nkact,
-                          bytes=2 * tau_a * nr * 8 + 3 * mmax * nr * nkact * 16 + 3 * tau_a * nkact * 16)
+    w["synth_gemm"] = dict(flops=f * 7 * 2.0 * nr * tau * 2 * nz,
+                           bytes=f * 2 * tau * nr * 8 + 2 * tau * nz * 16 + 6 * mixed)
+    w["proj_gemm"] = dict(flops=f * 5 * 2.0 * nr * tau_a * 2 * nkact,
+                          bytes=f * 2 * tau_a * nr * 8 + 3 * mmax * nr * nkact * 16 + 3 * tau_a * nkact * 16)
     w["phi_fft"] = dict(flops=None, bytes=9 * mixed)
     w["z_fft"] = dict(flops=None, bytes=6 * 2 * mixed + 3 * 2 * mmax * nr * nz * 16)
     w["projection"] = dict(flops=None, bytes=3 * tau_a * nkact * 16 + 2 * tau * nz * 16)

@@ -96,7 +96,9 @@ typedef struct mlg_plan_s* mlg_plan;
  * twiddles, then copies them to 'device'.  Errors: MLG_E_ARG for bad sizes/chops/ell,
  * MLG_E_NONFINITE for non-finite ell or L_z, MLG_E_UNSUPPORTED for N_phi or N_z whose
  * factors are not all 2, 3 or 5, or N_phi, N_z above 1024; MLG_E_ALLOC/DEVICE on HIP failure.
- * On failure *out is NULL and nothing is leaked. */
+ * On failure *out is NULL and nothing is leaked.  For even N_r the FP64 radial products of the
+ * vector RHS use the node symmetry x -> -x and the parity of Pbar_n^m (half the flops); the
+ * environment variable MLG_RADIAL_FOLD=0, read at creation, selects the unfolded products. */
 mlg_status mlg_plan_create(const mlg_grid* grid, mlg_precision prec, int device, mlg_plan* out);
 
 /* Free the plan's device tables.  NULL is accepted. */

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmlg.so")
-SOURCES = ["plan.cpp", "api.cpp", "kernels.hip", "fft256.hip", "gemm_fused.hip", "gemm_split.hip", "batch.hip", "step.hip", "closure.hip", "symeig.cpp"]
+SOURCES = ["plan.cpp", "api.cpp", "kernels.hip", "fft256.hip", "gemm_fused.hip", "gemm_fold.hip", "gemm_split.hip", "batch.hip", "step.hip", "closure.hip", "symeig.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

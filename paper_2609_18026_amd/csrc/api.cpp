@@ -1,6 +1,7 @@
 // extern "C" entry points of include/mlg.h: argument validation and the kernel sequence of
 // each operation.  Every step of the computation runs in the library's own HIP kernels.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -111,6 +112,7 @@ mlg_status mlg_plan_create(const mlg_grid* grid, mlg_precision prec, int device,
   p->dealias_k = (g.nz - 1) / 3;
   p->phi_nrad = factor_radices(g.nphi, p->phi_rad);
   p->z_nrad = factor_radices(g.nz, p->z_rad);
+  if (const char* e = std::getenv("MLG_RADIAL_FOLD")) p->use_fold = std::strcmp(e, "0") != 0;
   mlg_status st = build_plan(p);
   if (st != MLG_OK) {
     std::string msg = g_last_error;

@@ -1,0 +1,378 @@
+// Parity-folded radial products (even N_r): the Gauss-Legendre nodes are symmetric,
+// x_{N-1-i} = -x_i, and Pbar_n^m(-x) = (-1)^(n-m) Pbar_n^m(x), Tbar_n^m(-x) = -(-1)^(n-m) Tbar_n^m(x)
+// (Tbar = (1 - x^2) dPbar/dx).  Each product is split over even and odd j = n - m and contracted
+// over half the nodes, which halves the flops of the synthesis and of the projection.
+//
+// synthesis (backward): with E = sum_{j even}, O = sum_{j odd} over the half nodes i < N/2,
+//   Pbar-type product at node i: E + O, at its mirror i' = N-1-i: E - O;
+//   Tbar-type product at node i: E + O, at i': O - E.
+// projection (forward): with X_s = X_i + X_i', X_d = X_i - X_i' (i < N/2) and w symmetric,
+//   sum_i w Pbar_n X_i = sum_{i<N/2} w Pbar_n (j even ? X_s : X_d);
+//   Q = Tbar - 2(1 + x) Pbar = Q_A - 2 Pbar with Q_A = Tbar - 2 x Pbar of parity -(-1)^j, so
+//   sum_i w Q_n X_i = sum_{i<N/2} w Q_A,n (j even ? X_d : X_s) - 2 sum_i w Pbar_n X_i.
+// Tiles, MFMA layout and epilogues follow gemm_fused.hip (v_mfma_f64_16x16x4f64, accumulator
+// value v of lane l = C[l/16 + 4v][l%16]).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "dev_common.h"
+#include "mlg_internal.h"
+
+namespace mlg {
+namespace {
+
+using namespace ::mlg::dev;
+
+constexpr int TM = 64;  // rows per block (half nodes, or pairs of degrees)
+constexpr int TC8 = 8;  // complex columns per block (re and im share the 16 MFMA columns)
+constexpr int TP = 8;   // k depth per LDS stage (pairs of degrees, or half nodes)
+
+#define MFMA(a, b, c) __builtin_amdgcn_mfma_f64_16x16x4f64((a), (b), (c), 0, 0, 0)
+
+__device__ __forceinline__ int kval(int kk, int nz) { return (2 * kk < nz) ? kk : kk - nz; }
+
+struct FoldSynthArgs {
+  const double* Pb;        // backward Pbar tables, per m [n-m][i]
+  const double* Tb;        // backward Tbar tables
+  const double2* psi;
+  const double2* chi;
+  double2* out[6];         // mixed layout [m][i][kk]
+  const int64_t* off;
+  const double* node;      // rinv[nr], q[nr], opx[nr]
+  int nr, nrc, nz;
+  double kap0;
+};
+
+// the Eq. tp harmonics of u and omega at node i from the seven products
+__device__ __forceinline__ void synth_write(const FoldSynthArgs& a, int m, int i, int kk, double kap,
+                                            const double2 (&p)[7]) {
+  const int nr = a.nr, nz = a.nz;
+  const double rinv = a.node[i], q = a.node[nr + i], opx = a.node[2 * nr + i];
+  const double fm = (double)m;
+  const double2 A1 = p[0], A2 = p[1], A3 = p[2], B1 = p[3], B2 = p[4], B3 = p[5], B4 = p[6];
+  const double2 ur = make_double2(-(fm * A1.y + kap * B2.y) * rinv, (fm * A1.x + kap * B2.x) * rinv);
+  const double2 up = make_double2((-A2.x - fm * kap * B1.x) * rinv, (-A2.y - fm * kap * B1.y) * rinv);
+  const double2 uz = make_double2(q * B3.x, q * B3.y);
+  const double tr = kap * A2.x + fm * q * B3.x + fm * kap * kap * B1.x;
+  const double ti = kap * A2.y + fm * q * B3.y + fm * kap * kap * B1.y;
+  const double2 wr = make_double2(-ti * rinv, tr * rinv);
+  const double2 wp = make_double2((-fm * kap * A1.x - q * (B4.x - 2.0 * opx * B3.x) - kap * kap * B2.x) * rinv,
+                                  (-fm * kap * A1.y - q * (B4.y - 2.0 * opx * B3.y) - kap * kap * B2.y) * rinv);
+  const double2 wz = make_double2(q * A3.x, q * A3.y);
+  const int64_t o = ((int64_t)m * nr + i) * nz + kk;
+  a.out[0][o] = ur;
+  a.out[1][o] = up;
+  a.out[2][o] = uz;
+  a.out[3][o] = wr;
+  a.out[4][o] = wp;
+  a.out[5][o] = wz;
+}
+
+// Block tile: 64 half nodes x 8 complex columns; the 16 MFMA columns hold [re 0..7 | im 0..7], so
+// lane l accumulates the real (l%16 < 8) or imaginary part of complex column (l%16) % 8; partner
+// lanes l and l ^ 8 exchange their parts in the epilogue, then one writes node i and the other
+// its mirror.
+__global__ __launch_bounds__(256, 2) void synth_fold_kernel(FoldSynthArgs a) {
+  const int m = blockIdx.z;
+  const int half = a.nr / 2;
+  const int row0 = blockIdx.y * TM;
+  const int kk0 = blockIdx.x * TC8;
+  if (row0 >= half || kk0 >= a.nz) return;
+  const int K = a.nrc > m ? a.nrc - m : 0;
+  const int KP = (K + 1) / 2;
+  const int nr = a.nr, nz = a.nz;
+  const double* __restrict__ P = a.Pb + a.off[m] * nr;
+  const double* __restrict__ T = a.Tb + a.off[m] * nr;
+  const double2* __restrict__ ps = a.psi + a.off[m] * nz;
+  const double2* __restrict__ ch = a.chi + a.off[m] * nz;
+
+  __shared__ double As[2][2][2][TP][TM];  // [buf][P, T][parity][pair][half node]
+  __shared__ double Bs[2][2][2][TP][16];  // [buf][psi, chi][parity][pair][re 0..7 | im 0..7]
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cl = lane & 15;
+  double4_t acc[2][7];  // [parity][product]
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int p = 0; p < 7; ++p) acc[s][p] = double4_t{0.0, 0.0, 0.0, 0.0};
+
+  double ra[8];
+  double2 rb;
+  auto load = [&](int jj0) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = tid + 256 * t;
+      const int tab = e >> 10, par = (e >> 9) & 1, kr = (e >> 6) & 7, rr = e & 63;
+      const int j = 2 * (jj0 + kr) + par, i = row0 + rr;
+      const bool ok = j < K && i < half;
+      ra[t] = ok ? (tab ? T : P)[(int64_t)j * nr + i] : 0.0;
+    }
+    const int fld = tid >> 7, par = (tid >> 6) & 1, kr = (tid >> 3) & 7, cc = tid & 7;
+    const int j = 2 * (jj0 + kr) + par, kk = kk0 + cc;
+    rb = (j < K && kk < nz) ? (fld ? ch : ps)[(int64_t)j * nz + kk] : make_double2(0.0, 0.0);
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = tid + 256 * t;
+      As[buf][e >> 10][(e >> 9) & 1][(e >> 6) & 7][e & 63] = ra[t];
+    }
+    const int fld = tid >> 7, par = (tid >> 6) & 1, kr = (tid >> 3) & 7, cc = tid & 7;
+    Bs[buf][fld][par][kr][cc] = rb.x;
+    Bs[buf][fld][par][kr][8 + cc] = rb.y;
+  };
+
+  const int nk = (KP + TP - 1) / TP;
+  if (nk > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * TP);
+#pragma unroll
+    for (int ks = 0; ks < TP; ks += 4) {
+      const int kr = ks + (lane >> 4);
+#pragma unroll
+      for (int par = 0; par < 2; ++par) {
+        const double n = (double)(m + 2 * (kt * TP + kr) + par);
+        const double Ln = n * (n + 1.0);
+        const double aP = As[buf][0][par][kr][wave * 16 + cl];
+        const double aT = As[buf][1][par][kr][wave * 16 + cl];
+        const double bp = Bs[buf][0][par][kr][cl], bc = Bs[buf][1][par][kr][cl];
+        const double lp = Ln * bp, lc = Ln * bc;
+        double4_t(&c)[7] = acc[par];
+        c[0] = MFMA(aP, bp, c[0]);  // A1 = Pbar psi
+        c[1] = MFMA(aT, bp, c[1]);  // A2 = Tbar psi
+        c[2] = MFMA(aP, lp, c[2]);  // A3 = Pbar L psi
+        c[3] = MFMA(aP, bc, c[3]);  // B1 = Pbar chi
+        c[4] = MFMA(aT, bc, c[4]);  // B2 = Tbar chi
+        c[5] = MFMA(aP, lc, c[5]);  // B3 = Pbar L chi
+        c[6] = MFMA(aT, lc, c[6]);  // B4 = Tbar L chi
+      }
+    }
+    if (kt + 1 < nk) store(buf ^ 1);
+    __syncthreads();
+  }
+  const bool hi = cl >= 8;
+  const int kk = kk0 + (cl & 7);
+  const double kap = a.kap0 * kval(kk < nz ? kk : 0, nz);
+  // Tbar-type products (A2, B2, B4) flip sign with the node
+  constexpr bool tsign[7] = {false, true, false, false, true, false, true};
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = row0 + wave * 16 + (lane >> 4) + 4 * v;
+    double2 val[7];
+#pragma unroll
+    for (int p = 0; p < 7; ++p) {
+      const double e = acc[0][p][v], o = acc[1][p][v];
+      const double e2 = __shfl_xor(e, 8), o2 = __shfl_xor(o, 8);
+      const double er = hi ? e2 : e, ei = hi ? e : e2, orr = hi ? o2 : o, oi = hi ? o : o2;
+      // the low lane writes node i (E + O), the high lane the mirror node
+      val[p] = !hi ? make_double2(er + orr, ei + oi)
+                   : (tsign[p] ? make_double2(orr - er, oi - ei) : make_double2(er - orr, ei - oi));
+    }
+    if (i < half && kk < nz) synth_write(a, m, hi ? nr - 1 - i : i, kk, kap, val);
+  }
+}
+
+struct FoldProjArgs {
+  const double* Pf;        // forward W Pbar tables, per m [i][n-m]
+  const double* Qf;        // forward W Q tables
+  const double2* in[3];    // harmonics of N_r/r, N_phi/r, N_z (mixed [m][i][kk])
+  double2* out[3];         // C, K', Zhat (packed triangular)
+  const int64_t* off;
+  int nr, nrc, nz, kmax, nkact;
+  double kap0;
+};
+
+__device__ __forceinline__ int active_kk(int a, int kmax, int nz) {
+  return (a <= kmax) ? a : nz - (2 * kmax + 1 - a);
+}
+
+// Block tile: 64 pairs of degrees (even and odd n - m) x 8 complex columns, [re | im] packed in
+// the 16 MFMA columns as in synth_fold_kernel; the low lane of a partner pair writes the even
+// degree, the high lane the odd one.
+__global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs a) {
+  const int m = blockIdx.z;
+  const int rows = a.nrc > m ? a.nrc - m : 0;
+  const int KP = (rows + 1) / 2;
+  const int row0 = blockIdx.y * TM;  // pair index
+  const int c0 = blockIdx.x * TC8;
+  if (row0 >= KP || c0 >= a.nkact) return;
+  const int nr = a.nr, nz = a.nz, half = a.nr / 2;
+  const double* __restrict__ P = a.Pf + a.off[m] * nr;
+  const double* __restrict__ Q = a.Qf + a.off[m] * nr;
+
+  __shared__ double As[2][2][2][TP][TM];  // [buf][W Pbar, W Q_A][parity][half node][pair]
+  __shared__ double Bs[2][3][2][TP][16];  // [buf][a, b, c][sum, difference][half node][re 0..7 | im 0..7]
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cl = lane & 15;
+  double4_t acc[2][5];  // [parity][Pa, Q_A a, Pb, Q_A b, Pc]
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int p = 0; p < 5; ++p) acc[s][p] = double4_t{0.0, 0.0, 0.0, 0.0};
+
+  // B staging: threads 0..191 each load one (field, half node, column) at both mirror nodes
+  const int bf = tid >> 6, bkr = (tid >> 3) & 7, bcc = tid & 7;
+  const int bca = c0 + bcc;
+  const int bkk = (tid < 192 && bca < a.nkact) ? active_kk(bca, a.kmax, nz) : -1;
+  const double2* __restrict__ Xb = (tid < 192) ? a.in[bf] + (int64_t)m * nr * nz : nullptr;
+  double ra[2][4];
+  double2 rs, rd;
+  auto load = [&](int i0) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + 256 * t;
+      const int par = e >> 9, kr = (e >> 6) & 7, rr = e & 63;
+      const int i = i0 + kr, j = 2 * (row0 + rr) + par;
+      const bool ok = i < half && j < rows;
+      const int64_t idx = (int64_t)i * rows + j;
+      ra[0][t] = ok ? P[idx] : 0.0;
+      ra[1][t] = ok ? Q[idx] : 0.0;
+    }
+    const int i = i0 + bkr;
+    double2 x = make_double2(0.0, 0.0), y = x;
+    if (bkk >= 0 && i < half) {
+      x = Xb[(int64_t)i * nz + bkk];
+      y = Xb[(int64_t)(nr - 1 - i) * nz + bkk];
+    }
+    rs = make_double2(x.x + y.x, x.y + y.y);
+    rd = make_double2(x.x - y.x, x.y - y.y);
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + 256 * t;
+      const int par = e >> 9, kr = (e >> 6) & 7, rr = e & 63;
+      As[buf][0][par][kr][rr] = ra[0][t];
+      As[buf][1][par][kr][rr] = ra[1][t] + 2.0 * ra[0][t];  // w Q_A = w Q + 2 w Pbar
+    }
+    if (tid < 192) {
+      Bs[buf][bf][0][bkr][bcc] = rs.x;
+      Bs[buf][bf][0][bkr][8 + bcc] = rs.y;
+      Bs[buf][bf][1][bkr][bcc] = rd.x;
+      Bs[buf][bf][1][bkr][8 + bcc] = rd.y;
+    }
+  };
+
+  const int nk = (half + TP - 1) / TP;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * TP);
+#pragma unroll
+    for (int ks = 0; ks < TP; ks += 4) {
+      const int kr = ks + (lane >> 4);
+#pragma unroll
+      for (int par = 0; par < 2; ++par) {
+        const int sp = par, sq = 1 - par;  // Pbar: even rows use sums; Q_A: even rows use differences
+        const double aP = As[buf][0][par][kr][wave * 16 + cl];
+        const double aQ = As[buf][1][par][kr][wave * 16 + cl];
+        double4_t(&c)[5] = acc[par];
+        c[0] = MFMA(aP, Bs[buf][0][sp][kr][cl], c[0]);  // Pa
+        c[1] = MFMA(aQ, Bs[buf][0][sq][kr][cl], c[1]);  // Q_A a
+        c[2] = MFMA(aP, Bs[buf][1][sp][kr][cl], c[2]);  // Pb
+        c[3] = MFMA(aQ, Bs[buf][1][sq][kr][cl], c[3]);  // Q_A b
+        c[4] = MFMA(aP, Bs[buf][2][sp][kr][cl], c[4]);  // Pc
+      }
+    }
+    if (kt + 1 < nk) store(buf ^ 1);
+    __syncthreads();
+  }
+  const bool hi = cl >= 8;
+  const int cidx = c0 + (cl & 7);
+  const int kk = cidx < a.nkact ? active_kk(cidx, a.kmax, nz) : 0;
+  const double kap = a.kap0 * kval(kk, nz);
+  const double fm = (double)m;
+  const int64_t tb = a.off[m];
+  const int par = hi ? 1 : 0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int jj = row0 + wave * 16 + (lane >> 4) + 4 * v;
+    double2 val[5];
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+      // partner exchange: the low lane gathers the even-degree value, the high lane the odd one
+      const double e = acc[0][p][v], o = acc[1][p][v];
+      const double send = hi ? e : o;            // what the partner needs
+      const double recv = __shfl_xor(send, 8);
+      const double mine = hi ? o : e;            // own part (re for low, im for high) of own parity
+      val[p] = hi ? make_double2(recv, mine) : make_double2(mine, recv);
+    }
+    const int r = 2 * jj + par;
+    if (r >= rows || cidx >= a.nkact) continue;
+    const double2 Pa = val[0], Pb = val[2], Pc = val[4];
+    const double2 Qa = make_double2(val[1].x - 2.0 * Pa.x, val[1].y - 2.0 * Pa.y);
+    const double2 Qb = make_double2(val[3].x - 2.0 * Pb.x, val[3].y - 2.0 * Pb.y);
+    const int64_t o = (tb + r) * nz + kk;
+    a.out[0][o] = make_double2(-Qb.x + fm * Pa.y, -Qb.y - fm * Pa.x);
+    a.out[1][o] = make_double2(kap * Qa.y - fm * kap * Pb.x, -kap * Qa.x - fm * kap * Pb.y);
+    a.out[2][o] = Pc;
+  }
+}
+
+mlg_status check(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(MLG_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return MLG_OK;
+}
+
+}  // namespace
+
+mlg_status launch_synth_fold(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,
+                             hipStream_t s) {
+  FoldSynthArgs a{};
+  a.Pb = p->d_Pb;
+  a.Tb = p->d_Tb;
+  a.psi = reinterpret_cast<const double2*>(psi);
+  a.chi = reinterpret_cast<const double2*>(chi);
+  for (int i = 0; i < 6; ++i) a.out[i] = reinterpret_cast<double2*>(out6[i]);
+  a.off = p->d_goff;
+  a.node = p->d_node;
+  a.nr = p->nr;
+  a.nrc = p->nrc;
+  a.nz = p->nz;
+  a.kap0 = 2.0 * M_PI / p->g.lz;
+  dim3 grid((unsigned)((p->nz + TC8 - 1) / TC8), (unsigned)((p->nr / 2 + TM - 1) / TM), (unsigned)p->M);
+  p->timing.begin("synth_gemm", s);
+  synth_fold_kernel<<<grid, 256, 0, s>>>(a);
+  p->timing.end(s);
+  return check("synth_fold_kernel");
+}
+
+mlg_status launch_proj_fold(const mlg_plan_s* p, double* const* in3, double* const* out3, int mmax, int kmax,
+                            hipStream_t s) {
+  FoldProjArgs a{};
+  a.Pf = p->d_Pf;
+  a.Qf = p->d_Qf;
+  for (int i = 0; i < 3; ++i) {
+    a.in[i] = reinterpret_cast<const double2*>(in3[i]);
+    a.out[i] = reinterpret_cast<double2*>(out3[i]);
+  }
+  a.off = p->d_goff;
+  a.nr = p->nr;
+  a.nrc = p->nrc;
+  a.nz = p->nz;
+  a.kmax = kmax;
+  a.nkact = (p->nz == 1) ? 1 : 2 * kmax + 1;
+  a.kap0 = 2.0 * M_PI / p->g.lz;
+  if (mmax <= 0 || a.nkact <= 0) return MLG_OK;
+  const int kp = (p->nrc + 1) / 2;
+  dim3 grid((unsigned)((a.nkact + TC8 - 1) / TC8), (unsigned)((kp + TM - 1) / TM), (unsigned)mmax);
+  p->timing.begin("proj_gemm", s);
+  proj_fold_kernel<<<grid, 256, 0, s>>>(a);
+  p->timing.end(s);
+  return check("proj_fold_kernel");
+}
+
+}  // namespace mlg

@@ -300,6 +300,7 @@ mlg_status check(const char* what) {
 
 mlg_status launch_synth_gemm(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,
                              hipStream_t s) {
+  if (p->use_fold && p->nr % 2 == 0) return launch_synth_fold(p, psi, chi, out6, s);
   SynthArgs a{};
   a.Pb = p->d_Pb;
   a.Tb = p->d_Tb;
@@ -322,6 +323,7 @@ mlg_status launch_synth_gemm(const mlg_plan_s* p, const double* psi, const doubl
 
 mlg_status launch_proj_gemm(const mlg_plan_s* p, double* const* in3, double* const* out3, int mmax, int kmax,
                             hipStream_t s) {
+  if (p->use_fold && p->nr % 2 == 0) return launch_proj_fold(p, in3, out3, mmax, kmax, s);
   ProjGemmArgs a{};
   a.Pf = p->d_Pf;
   a.Qf = p->d_Qf;

@@ -693,25 +693,31 @@ __global__ __launch_bounds__(64) void projection_kernel(ProjArgs a) {
   double2 yp1 = z0, yp2 = z0, yq1 = z0, yq2 = z0, w1 = z0, w2 = z0;
   double l1q_n1 = 0, l2q_n2 = 0, l2q_n1 = 0;
   double gpr = 0, gpi = 0;
-  for (int tb = cnt - 1; tb >= i0; tb -= PJ_D) {
-    double2 pz[PJ_D], qz[PJ_D];
-    double ql1[PJ_D], ql2[PJ_D], qr[PJ_D];
+  // the chunk below the current one is fetched while the current one is computed
+  double2 pz[PJ_D], qz[PJ_D], pzn[PJ_D], qzn[PJ_D];
+  double ql1[PJ_D], ql2[PJ_D], qr[PJ_D], ql1n[PJ_D], ql2n[PJ_D], qrn[PJ_D];
+  auto fetch2 = [&](int tb, double2 (&fp)[PJ_D], double2 (&fq)[PJ_D], double (&f1)[PJ_D], double (&f2)[PJ_D],
+                    double (&fr)[PJ_D]) {
 #pragma unroll
     for (int d = 0; d < PJ_D; ++d) {
       const int t = tb - d;
       const bool ok = t >= i0;
-      pz[d] = ok ? ps[(int64_t)t * nz] : z0;
+      fp[d] = ok ? ps[(int64_t)t * nz] : z0;
       if (k != 0) {
-        qz[d] = ok ? make_double2(scr[sidx(0, t)], scr[sidx(1, t)]) : z0;
-        ql1[d] = ok ? scr[sidx(2, t)] : 0.0;
-        ql2[d] = ok ? scr[sidx(3, t)] : 0.0;
-        qr[d] = ok ? scr[sidx(4, t)] : 1.0;
+        fq[d] = ok ? make_double2(scr[sidx(0, t)], scr[sidx(1, t)]) : z0;
+        f1[d] = ok ? scr[sidx(2, t)] : 0.0;
+        f2[d] = ok ? scr[sidx(3, t)] : 0.0;
+        fr[d] = ok ? scr[sidx(4, t)] : 1.0;
       } else {
-        qz[d] = ok ? Zc[(int64_t)t * nz] : z0;
-        ql1[d] = ql2[d] = 0.0;
-        qr[d] = 1.0;
+        fq[d] = ok ? Zc[(int64_t)t * nz] : z0;
+        f1[d] = f2[d] = 0.0;
+        fr[d] = 1.0;
       }
     }
+  };
+  fetch2(cnt - 1, pz, qz, ql1, ql2, qr);
+  for (int tb = cnt - 1; tb >= i0; tb -= PJ_D) {
+    fetch2(tb - PJ_D, pzn, qzn, ql1n, ql2n, qrn);
 #pragma unroll
     for (int d = 0; d < PJ_D; ++d) {
       const int t = tb - d;
@@ -745,15 +751,22 @@ __global__ __launch_bounds__(64) void projection_kernel(ProjArgs a) {
       w2 = w1; w1 = w;
       chv[(int64_t)t * nz] = w;
     }
+#pragma unroll
+    for (int d = 0; d < PJ_D; ++d) {
+      pz[d] = pzn[d]; qz[d] = qzn[d]; ql1[d] = ql1n[d]; ql2[d] = ql2n[d]; qr[d] = qrn[d];
+    }
   }
   if (m == 0) ps[0] = make_double2(-gpr / sgw[0], -gpi / sgw[0]);
   // ---- pass 3 (ascending): D U^T y = w
   double2 yc1 = z0, yc2 = z0;
   double gcr = 0, gci = 0;
-  for (int tb = i0; tb < cnt; tb += PJ_D) {
-    double2 wz[PJ_D];
+  // rows of the next chunk are read (not yet rewritten by this pass) while this chunk is computed
+  double2 wz[PJ_D], wzn[PJ_D];
 #pragma unroll
-    for (int d = 0; d < PJ_D; ++d) wz[d] = (tb + d < cnt) ? chv[(int64_t)(tb + d) * nz] : z0;
+  for (int d = 0; d < PJ_D; ++d) wz[d] = (i0 + d < cnt) ? chv[(int64_t)(i0 + d) * nz] : z0;
+  for (int tb = i0; tb < cnt; tb += PJ_D) {
+#pragma unroll
+    for (int d = 0; d < PJ_D; ++d) wzn[d] = (tb + PJ_D + d < cnt) ? chv[(int64_t)(tb + PJ_D + d) * nz] : z0;
 #pragma unroll
     for (int d = 0; d < PJ_D; ++d) {
       const int t = tb + d;
@@ -767,6 +780,8 @@ __global__ __launch_bounds__(64) void projection_kernel(ProjArgs a) {
       gcr += sgw[t] * v.x;
       gci += sgw[t] * v.y;
     }
+#pragma unroll
+    for (int d = 0; d < PJ_D; ++d) wz[d] = wzn[d];
   }
   if (m == 0) chv[0] = make_double2(-gcr / sgw[0], -gci / sgw[0]);
 }

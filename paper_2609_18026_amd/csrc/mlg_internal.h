@@ -114,6 +114,7 @@ struct mlg_plan_s {
   int step_q = 1;                 // p / 2 (hyperviscosity power of grad^2), 1 when nu_h = 0
   bool step_ready = false;
   bool use_fast_fft = true;   // register-resident 256-point kernels when a length is 256
+  bool use_fold = true;       // parity-folded radial products when N_r is even (MLG_RADIAL_FOLD=0 disables)
   int phi_rad[12] = {0};
   int phi_nrad = 0;
   int z_rad[12] = {0};
@@ -151,6 +152,11 @@ mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, dou
 mlg_status launch_synth_gemm(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,
                              hipStream_t s);
 mlg_status launch_proj_gemm(const mlg_plan_s* p, double* const* in3, double* const* out3, int mmax, int kmax,
+                            hipStream_t s);
+// gemm_fold.hip: the same two products folded over the node symmetry x -> -x (even N_r)
+mlg_status launch_synth_fold(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,
+                             hipStream_t s);
+mlg_status launch_proj_fold(const mlg_plan_s* p, double* const* in3, double* const* out3, int mmax, int kmax,
                             hipStream_t s);
 // gemm_split.hip: the same two products with split-bfloat16 operands and FP32 accumulation
 mlg_status launch_split_synth(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,

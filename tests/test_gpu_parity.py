@@ -183,6 +183,7 @@ TP_CASES = [
     (48, 16, 1, 1.0, 2 * np.pi, (0.1, 0.2, 0.0), 1),
     (16, 256, 256, 1.0, 8.6, (0.0, 1.0, 0.0), 1),
     (12, 256, 256, 0.7, 3.0, (0.2, -0.1, 0.3), 0),
+    (25, 12, 8, 0.8, 3.0, (0.1, 0.3, -0.2), 1),     # odd N_r: unfolded radial products
 ]
 
 
