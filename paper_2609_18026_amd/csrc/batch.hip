@@ -201,6 +201,7 @@ __device__ void phase_backward(const BatchArgs<T>& A, int b, int m, char* smem) 
         ar += (double)s[1].x * p1;
         ai += (double)s[1].y * p1;
       }
+#pragma unroll 8
       for (int t = 2; t < K; ++t) {
         const double p2 = rec[2 * t] * x * p1 - rec[2 * t + 1] * p0;
         ar += (double)s[t].x * p2;
