@@ -38,9 +38,13 @@ U_FRAME = (0.0, 1.0, 0.0)
 # the factors of a plain 256 MiB copy), per launch at 256^3; valid only while the kernel source is the
 # one that was measured.
 MEASURED_TRAFFIC = {
-    "synth_gemm": {"bytes": (493695 * 2 + 786432) * 1024, "n": 256,
-                   "source": "paper_2609_18026_amd/csrc/gemm_fused.hip",
-                   "sha256": "746af61a827db1017de16b9750f5f93047d5d20c73b6bd9b627fb1652f263728",
+    "phi_fft": {"bytes": (393626 * 2 + 393216) * 1024, "n": 256,
+                "source": "paper_2609_18026_amd/csrc/fft256.hip",
+                "sha256": "2610109167d8d47ffbd83da7fac63b94823ef4543e1348b30a28cf7055331edb",
+                "summary": "profiles/rhs_tp_256cubed_kernels.md"},
+    "synth_gemm": {"bytes": (295831 * 2 + 786432) * 1024, "n": 256,
+                   "source": "paper_2609_18026_amd/csrc/gemm_fold.hip",
+                   "sha256": "034acec060f36ac7fe583b565f3bc2c8b8a90944d1c16a8244c6db6ae0e99e4d",
                    "summary": "profiles/rhs_tp_256cubed_kernels.md"},
 }
 
