@@ -186,6 +186,54 @@ __device__ __forceinline__ void gather_pair(double2 (*Z)[16 * 17], const Phi256&
   __syncthreads();
 }
 
+// The same gather split in two, so that the loads of one pair can be in flight while another pair
+// is transformed: load_pair reads the harmonics of (fa, fb) into registers (entry it covers
+// e = t + 128 it: line e % PL, order e / PL; orders >= min(M, 128) and lines past the end read as
+// zero), store_pair writes them into Z as the Hermitian spectrum of a + i b.
+struct PairRegs {
+  double2 a[PL], b[PL];
+};
+
+__device__ __forceinline__ void load_pair(PairRegs& r, const Phi256& g, int64_t q0, const double2* __restrict__ fa,
+                                          const double2* __restrict__ fb) {
+  const int t = threadIdx.x;
+  const int mmax = g.M < 128 ? g.M : 128;
+#pragma unroll
+  for (int it = 0; it < PL; ++it) {
+    const int e = t + 128 * it;
+    const int ll = e & (PL - 1), m = e >> 3;
+    const int64_t q = q0 + ll;
+    const bool ok = m < mmax && q < g.nlines;
+    r.a[it] = ok ? fa[(int64_t)m * g.nlines + q] : make_double2(0.0, 0.0);
+    r.b[it] = (ok && fb) ? fb[(int64_t)m * g.nlines + q] : make_double2(0.0, 0.0);
+  }
+}
+
+// Starts with a barrier (earlier readers of Z are done) and ends with one.
+__device__ __forceinline__ void store_pair(const PairRegs& r, double2 (*Z)[16 * 17]) {
+  const int t = threadIdx.x;
+  __syncthreads();
+  for (int e = t; e < PL * 256; e += 128) {
+    const int ll = e & (PL - 1), p = e >> 3;
+    Z[ll][(p & 15) + 17 * (p >> 4)] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < PL; ++it) {
+    const int e = t + 128 * it;
+    const int ll = e & (PL - 1), m = e >> 3;
+    const double2 a = r.a[it], b = r.b[it];
+    if (m == 0) {
+      Z[ll][0] = make_double2(a.x, b.x);
+    } else {
+      Z[ll][(m & 15) + 17 * (m >> 4)] = make_double2(a.x - b.y, a.y + b.x);
+      const int mm = 256 - m;
+      Z[ll][(mm & 15) + 17 * (mm >> 4)] = make_double2(a.x + b.y, -a.y + b.x);
+    }
+  }
+  __syncthreads();
+}
+
 // Scatter the spectrum X (registers, X[s + 16 k]) of z = a + i b to harmonics of a and b
 // (orders m < M, scaled by 1/256; orders above mkeep written as zero).  Uses Z; contains barriers.
 __device__ __forceinline__ void scatter_pair(double2 (&v)[16], double2 (*Z)[16 * 17], const Phi256& g, int64_t q0,
@@ -344,26 +392,28 @@ __global__ __launch_bounds__(128) void phi_vec256_kernel(Phi256 g, const double2
   const int64_t q = q0 + ll;
   double2 v[16];
   double ur[16], up[16], uz[16], wr[16];
-  // pair 0: (u_r, u_phi)
-  gather_pair(Z, g, q0, fs.f[0], fs.f[1]);
+  PairRegs pr;
+  // pair 0: (u_r, u_phi); the loads of each next pair are issued before the current transform
+  load_pair(pr, g, q0, fs.f[0], fs.f[1]);
+  store_pair(pr, Z);
 #pragma unroll
   for (int j = 0; j < 16; ++j) v[j] = Z[ll][s + 17 * j];
+  load_pair(pr, g, q0, fs.f[2], fs.f[3]);
   __syncthreads();
   fft256<true>(v, Z[ll], s, tw);
 #pragma unroll
   for (int k = 0; k < 16; ++k) { ur[k] = v[k].x; up[k] = v[k].y; }
-  __syncthreads();
   // pair 1: (u_z, w_r)
-  gather_pair(Z, g, q0, fs.f[2], fs.f[3]);
+  store_pair(pr, Z);
 #pragma unroll
   for (int j = 0; j < 16; ++j) v[j] = Z[ll][s + 17 * j];
+  load_pair(pr, g, q0, fs.f[4], fs.f[5]);
   __syncthreads();
   fft256<true>(v, Z[ll], s, tw);
 #pragma unroll
   for (int k = 0; k < 16; ++k) { uz[k] = v[k].x; wr[k] = v[k].y; }
-  __syncthreads();
   // pair 2: (w_phi, w_z)
-  gather_pair(Z, g, q0, fs.f[4], fs.f[5]);
+  store_pair(pr, Z);
 #pragma unroll
   for (int j = 0; j < 16; ++j) v[j] = Z[ll][s + 17 * j];
   __syncthreads();
