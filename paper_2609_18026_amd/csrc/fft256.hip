@@ -186,54 +186,6 @@ __device__ __forceinline__ void gather_pair(double2 (*Z)[16 * 17], const Phi256&
   __syncthreads();
 }
 
-// The same gather split in two, so that the loads of one pair can be in flight while another pair
-// is transformed: load_pair reads the harmonics of (fa, fb) into registers (entry it covers
-// e = t + 128 it: line e % PL, order e / PL; orders >= min(M, 128) and lines past the end read as
-// zero), store_pair writes them into Z as the Hermitian spectrum of a + i b.
-struct PairRegs {
-  double2 a[PL], b[PL];
-};
-
-__device__ __forceinline__ void load_pair(PairRegs& r, const Phi256& g, int64_t q0, const double2* __restrict__ fa,
-                                          const double2* __restrict__ fb) {
-  const int t = threadIdx.x;
-  const int mmax = g.M < 128 ? g.M : 128;
-#pragma unroll
-  for (int it = 0; it < PL; ++it) {
-    const int e = t + 128 * it;
-    const int ll = e & (PL - 1), m = e >> 3;
-    const int64_t q = q0 + ll;
-    const bool ok = m < mmax && q < g.nlines;
-    r.a[it] = ok ? fa[(int64_t)m * g.nlines + q] : make_double2(0.0, 0.0);
-    r.b[it] = (ok && fb) ? fb[(int64_t)m * g.nlines + q] : make_double2(0.0, 0.0);
-  }
-}
-
-// Starts with a barrier (earlier readers of Z are done) and ends with one.
-__device__ __forceinline__ void store_pair(const PairRegs& r, double2 (*Z)[16 * 17]) {
-  const int t = threadIdx.x;
-  __syncthreads();
-  for (int e = t; e < PL * 256; e += 128) {
-    const int ll = e & (PL - 1), p = e >> 3;
-    Z[ll][(p & 15) + 17 * (p >> 4)] = make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int it = 0; it < PL; ++it) {
-    const int e = t + 128 * it;
-    const int ll = e & (PL - 1), m = e >> 3;
-    const double2 a = r.a[it], b = r.b[it];
-    if (m == 0) {
-      Z[ll][0] = make_double2(a.x, b.x);
-    } else {
-      Z[ll][(m & 15) + 17 * (m >> 4)] = make_double2(a.x - b.y, a.y + b.x);
-      const int mm = 256 - m;
-      Z[ll][(mm & 15) + 17 * (mm >> 4)] = make_double2(a.x + b.y, -a.y + b.x);
-    }
-  }
-  __syncthreads();
-}
-
 // Scatter the spectrum X (registers, X[s + 16 k]) of z = a + i b to harmonics of a and b
 // (orders m < M, scaled by 1/256; orders above mkeep written as zero).  Uses Z; contains barriers.
 __device__ __forceinline__ void scatter_pair(double2 (&v)[16], double2 (*Z)[16 * 17], const Phi256& g, int64_t q0,
@@ -378,54 +330,243 @@ __global__ __launch_bounds__(128) void phi_scalar256_kernel(Phi256 g, const doub
   scatter_pair(v, Z, g, q0, ll, s, mixed, nullptr);
 }
 
+// ---------------------------------------------------------------- 32-lane lines
+// The vector stage keeps four nodal fields of a line in registers while the last pair is
+// transformed; at 16 lanes per line that state allows one wavefront per SIMD.  Here a line is
+// spread over 32 lanes with 8 samples each (lane s holds x[s + 32 j]) and the 256-point DFT
+// factors as 8 x 8 x 4: a radix-8 pass over j, a twiddle, an LDS exchange, a radix-8 pass over
+// the lane's high bits, a twiddle, an exchange and two radix-4 DFTs per lane.  Taking the radix-4
+// groups (s, s + 32) returns X[s + 32 j] in v[j]: input and output share one distribution.  The
+// 32 lanes of a line lie in one wavefront, so the exchanges need only wavefront-level ordering.
+constexpr int WL = 32;       // lanes per line
+constexpr int VB = PL * WL;  // threads per block: 8 lines, 4 wavefronts
+constexpr int WROW = 288;    // LDS entries per line (harmonics at zpos(p), both exchanges)
+
+__device__ __forceinline__ int zpos(int p) { return 33 * (p >> 5) + (p & 31); }
+
+// Orders the LDS accesses of one wavefront: earlier writes are seen by later reads of other lanes
+// and earlier reads complete before later writes (LDS instructions of a wavefront execute in order).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// In-register 8-point DFT: v[n] -> V[k] = sum_n v[n] w8^(n k) (radix 2 over two 4-point DFTs).
+template <bool INV>
+__device__ __forceinline__ void dft8(double2 (&v)[8]) {
+  dft4<INV>(v[0], v[2], v[4], v[6]);  // E[k] at v[2 k]
+  dft4<INV>(v[1], v[3], v[5], v[7]);  // O[k] at v[2 k + 1]
+  const double2 o1 = tw16<INV, 2>(v[3]), o2 = tw16<INV, 4>(v[5]), o3 = tw16<INV, 6>(v[7]);
+  double2 x[8];
+  x[0] = cadd(v[0], v[1]);
+  x[4] = csub(v[0], v[1]);
+  x[1] = cadd(v[2], o1);
+  x[5] = csub(v[2], o1);
+  x[2] = cadd(v[4], o2);
+  x[6] = csub(v[4], o2);
+  x[3] = cadd(v[6], o3);
+  x[7] = csub(v[6], o3);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = x[k];
+}
+
+// v[c] *= w^(e c), c = 1..7, from the three table entries w^e, w^(2e), w^(4e) (w = exp(-2 pi i/256),
+// conjugated for the inverse); every factor is at most two roundings from the exact twiddle.
+template <bool INV>
+__device__ __forceinline__ void twiddle8(double2 (&v)[8], const double2* __restrict__ tw, int e) {
+  double2 w1 = tw[e], w2 = tw[2 * e], w4 = tw[4 * e];
+  if (INV) {
+    w1 = cconj(w1);
+    w2 = cconj(w2);
+    w4 = cconj(w4);
+  }
+  const double2 w3 = cmul(w1, w2), w6 = cmul(w4, w2);
+  v[1] = cmul(v[1], w1);
+  v[2] = cmul(v[2], w2);
+  v[3] = cmul(v[3], w3);
+  v[4] = cmul(v[4], w4);
+  v[5] = cmul(v[5], cmul(w4, w1));
+  v[6] = cmul(v[6], w6);
+  v[7] = cmul(v[7], cmul(w6, w1));
+}
+
+// 256-point DFT of one line over its 32 lanes: on entry v[j] = x[s + 32 j], on exit
+// v[j] = X[s + 32 j] (unscaled).  W is the line's LDS area (WROW entries); the caller orders any
+// later writes to W after these reads.  With n = s + 32 j, s = a + 4 b and k = k2 + 8 c + 64 d:
+// X[k] = sum_a w4^(a d) w32^(a c) sum_b w8^(b c) w256^(s k2) sum_j w8^(j k2) x[n].
+template <bool INV>
+__device__ __forceinline__ void fft256w(double2 (&v)[8], double2* W, int s, const double2* __restrict__ tw) {
+  dft8<INV>(v);            // v[k2] = sum_j w8^(j k2) x[s + 32 j]
+  twiddle8<INV>(v, tw, s);  // * w256^(s k2)
+  wave_sync();
+#pragma unroll
+  for (int k2 = 0; k2 < 8; ++k2) W[36 * k2 + s] = v[k2];
+  wave_sync();
+  const int a = s & 3, kb = s >> 2;  // this lane's (a, k2) for the second pass
+#pragma unroll
+  for (int b = 0; b < 8; ++b) v[b] = W[36 * kb + a + 4 * b];
+  dft8<INV>(v);                // v[c] = sum_b w8^(b c) (...)
+  twiddle8<INV>(v, tw, 8 * a);  // * w32^(a c)
+  wave_sync();
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int gi = 8 * c + kb;
+    W[4 * gi + a + (gi >> 2)] = v[c];
+  }
+  wave_sync();
+  // radix-4 over a for the (c, k2) groups gi = s and s + 32: outputs k = s + 64 d and s + 32 + 64 d
+  double2 p[4], r[4];
+  const int g0 = s, g1 = s + 32;
+#pragma unroll
+  for (int aa = 0; aa < 4; ++aa) {
+    p[aa] = W[4 * g0 + aa + (g0 >> 2)];
+    r[aa] = W[4 * g1 + aa + (g1 >> 2)];
+  }
+  dft4<INV>(p[0], p[1], p[2], p[3]);
+  dft4<INV>(r[0], r[1], r[2], r[3]);
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    v[2 * d] = p[d];
+    v[2 * d + 1] = r[d];
+  }
+}
+
+// Harmonics of a field pair for the block's lines, held in registers so that their loads are in
+// flight while another pair is transformed.  Entry it covers e = t + VB it: line e % PL, order
+// e / PL.  The per-lane byte offset is 32-bit (the launcher bounds the line count) and the rest of
+// the address is uniform.  GUARD (the last block, or fewer than 128 stored orders) reads orders
+// >= min(M, 128) and lines past the end as zero.
+struct PairRegs {
+  double2 a[PL * 128 / VB], b[PL * 128 / VB];
+};
+
+template <bool GUARD>
+__device__ __forceinline__ void load_pair(PairRegs& r, const Phi256& g, int64_t q0, const double2* __restrict__ fa,
+                                          const double2* __restrict__ fb) {
+  const int t = threadIdx.x;
+  const uint32_t off = (uint32_t)((t >> 3) * g.nlines + (t & 7)) * (uint32_t)sizeof(double2);
+  const int mmax = g.M < 128 ? g.M : 128;
+  const bool line_ok = q0 + (t & 7) < g.nlines;
+#pragma unroll
+  for (int it = 0; it < PL * 128 / VB; ++it) {
+    const int64_t base = q0 + (int64_t)(VB / PL) * it * g.nlines;
+    const char* pa = reinterpret_cast<const char*>(fa + base) + off;
+    const char* pb = reinterpret_cast<const char*>(fb + base) + off;
+    if (!GUARD) {
+      r.a[it] = *reinterpret_cast<const double2*>(pa);
+      r.b[it] = *reinterpret_cast<const double2*>(pb);
+    } else {
+      const bool ok = line_ok && (t >> 3) + (VB / PL) * it < mmax;
+      r.a[it] = ok ? *reinterpret_cast<const double2*>(pa) : make_double2(0.0, 0.0);
+      r.b[it] = ok ? *reinterpret_cast<const double2*>(pb) : make_double2(0.0, 0.0);
+    }
+  }
+}
+
+// Writes the pair into Z as the Hermitian spectrum of a + i b.  Orders 1..127 fill positions
+// m and 256 - m, order 0 position 0; only the Nyquist position 128 is cleared.  Starts with a
+// barrier (earlier readers of Z are done) and ends with one.
+__device__ __forceinline__ void store_pair(const PairRegs& r, double2 (*Z)[WROW]) {
+  const int t = threadIdx.x;
+  __syncthreads();
+  if (t < PL) Z[t][zpos(128)] = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int it = 0; it < PL * 128 / VB; ++it) {
+    const int e = t + VB * it;
+    const int ll = e & (PL - 1), m = e >> 3;
+    const double2 a = r.a[it], b = r.b[it];
+    if (m == 0) {
+      Z[ll][0] = make_double2(a.x, b.x);
+    } else {
+      Z[ll][zpos(m)] = make_double2(a.x - b.y, a.y + b.x);
+      Z[ll][zpos(256 - m)] = make_double2(a.x + b.y, -a.y + b.x);
+    }
+  }
+  __syncthreads();
+}
+
+// Scatters the spectrum X (v[j] = X[s + 32 j]) of z = a + i b of each line to the harmonics of a
+// and b (orders m < M, scaled by 1/256; orders above mkeep written as zero).  Barriers at both ends.
+__device__ __forceinline__ void scatter_pair_w(const double2 (&v)[8], double2 (*Z)[WROW], const Phi256& g,
+                                               int64_t q0, int ll, int s, double2* fa, double2* fb) {
+  __syncthreads();  // every line's exchange reads are complete
+#pragma unroll
+  for (int j = 0; j < 8; ++j) Z[ll][33 * j + s] = v[j];
+  __syncthreads();
+  const int t = threadIdx.x;
+  const int mmax = g.M < 128 ? g.M : 128;
+  for (int e = t; e < PL * g.M; e += VB) {
+    const int l2 = e & (PL - 1), m = e >> 3;
+    const int64_t q = q0 + l2;
+    if (q >= g.nlines) continue;
+    double2 A = make_double2(0.0, 0.0), B = A;
+    if (m < mmax && m <= g.mkeep) {
+      const double2 zm = Z[l2][zpos(m)];
+      const double2 zc = cconj(Z[l2][zpos((256 - m) & 255)]);
+      A = cscale(cadd(zm, zc), 0.5 / 256.0);
+      const double2 d = csub(zm, zc);
+      B = make_double2(0.5 / 256.0 * d.y, -0.5 / 256.0 * d.x);
+    }
+    fa[(int64_t)m * g.nlines + q] = A;
+    if (fb) fb[(int64_t)m * g.nlines + q] = B;
+  }
+  __syncthreads();
+}
+
 struct Six256 {
   double2* f[6];
 };
 
-__global__ __launch_bounds__(128) void phi_vec256_kernel(Phi256 g, const double2* __restrict__ tw, Six256 fs,
-                                                         const double* __restrict__ rinv, double Ux, double Uy,
-                                                         double Uz, double* __restrict__ taps) {
-  __shared__ double2 Z[PL][16 * 17];
-  const int t = threadIdx.x, ll = t >> 4, s = t & 15;
-  (void)t;
-  const int64_t q0 = (int64_t)blockIdx.x * PL;
+template <bool GUARD>
+__global__ __launch_bounds__(VB) void phi_vec256_kernel(Phi256 g, const double2* __restrict__ twg, Six256 fs,
+                                                        const double* __restrict__ rinv, double Ux, double Uy,
+                                                        double Uz, double* __restrict__ taps, int64_t blk0) {
+  __shared__ double2 Z[PL][WROW];
+  __shared__ double2 tw[256];  // exp(-2 pi i j / 256): twiddles and the node angles
+  const int t = threadIdx.x, ll = t / WL, s = t % WL;
+  const int64_t q0 = (blk0 + blockIdx.x) * PL;
   const int64_t q = q0 + ll;
-  double2 v[16];
-  double ur[16], up[16], uz[16], wr[16];
+  tw[t] = twg[t];  // VB == 256; visible after the first barrier of store_pair
+  double2 v[8];
+  double ur[8], up[8], uz[8], wr[8];
   PairRegs pr;
   // pair 0: (u_r, u_phi); the loads of each next pair are issued before the current transform
-  load_pair(pr, g, q0, fs.f[0], fs.f[1]);
+  load_pair<GUARD>(pr, g, q0, fs.f[0], fs.f[1]);
   store_pair(pr, Z);
 #pragma unroll
-  for (int j = 0; j < 16; ++j) v[j] = Z[ll][s + 17 * j];
-  load_pair(pr, g, q0, fs.f[2], fs.f[3]);
-  __syncthreads();
-  fft256<true>(v, Z[ll], s, tw);
+  for (int j = 0; j < 8; ++j) v[j] = Z[ll][33 * j + s];
+  load_pair<GUARD>(pr, g, q0, fs.f[2], fs.f[3]);
+  fft256w<true>(v, Z[ll], s, tw);
 #pragma unroll
-  for (int k = 0; k < 16; ++k) { ur[k] = v[k].x; up[k] = v[k].y; }
+  for (int k = 0; k < 8; ++k) {
+    ur[k] = v[k].x;
+    up[k] = v[k].y;
+  }
   // pair 1: (u_z, w_r)
   store_pair(pr, Z);
 #pragma unroll
-  for (int j = 0; j < 16; ++j) v[j] = Z[ll][s + 17 * j];
-  load_pair(pr, g, q0, fs.f[4], fs.f[5]);
-  __syncthreads();
-  fft256<true>(v, Z[ll], s, tw);
+  for (int j = 0; j < 8; ++j) v[j] = Z[ll][33 * j + s];
+  load_pair<GUARD>(pr, g, q0, fs.f[4], fs.f[5]);
+  fft256w<true>(v, Z[ll], s, tw);
 #pragma unroll
-  for (int k = 0; k < 16; ++k) { uz[k] = v[k].x; wr[k] = v[k].y; }
+  for (int k = 0; k < 8; ++k) {
+    uz[k] = v[k].x;
+    wr[k] = v[k].y;
+  }
   // pair 2: (w_phi, w_z)
   store_pair(pr, Z);
 #pragma unroll
-  for (int j = 0; j < 16; ++j) v[j] = Z[ll][s + 17 * j];
-  __syncthreads();
-  fft256<true>(v, Z[ll], s, tw);
-  // nodal cross product at phi_j, j = s + 16 k: cos(phi_j) = tw[j].x, sin(phi_j) = -tw[j].y
+  for (int j = 0; j < 8; ++j) v[j] = Z[ll][33 * j + s];
+  fft256w<true>(v, Z[ll], s, tw);
+  // nodal cross product at phi_j, j = s + 32 k: cos(phi_j) = tw[j].x, sin(phi_j) = -tw[j].y
   const bool valid = q < g.nlines;
   const double ri = valid ? rinv[q / g.nz] : 0.0;
   const int64_t pe = g.nlines * 256;
-  double2 nz_[16];
+  double nzr[8];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int j = s + 16 * k;
+  for (int k = 0; k < 8; ++k) {
+    const int j = s + 32 * k;
     const double2 c = tw[j];
     const double cphi = c.x, sphi = -c.y;
     const double wp = v[k].x, wz = v[k].y;
@@ -437,18 +578,25 @@ __global__ __launch_bounds__(128) void phi_vec256_kernel(Phi256 g, const double2
     const double Nz = Ur * wp - Up * wr[k];
     if (taps != nullptr && valid) {
       const int64_t o = phys_off(g, q) + j;
-      taps[0 * pe + o] = ur[k]; taps[1 * pe + o] = up[k]; taps[2 * pe + o] = uz[k];
-      taps[3 * pe + o] = wr[k]; taps[4 * pe + o] = wp; taps[5 * pe + o] = wz;
-      taps[6 * pe + o] = Nr; taps[7 * pe + o] = Np; taps[8 * pe + o] = Nz;
+      taps[0 * pe + o] = ur[k];
+      taps[1 * pe + o] = up[k];
+      taps[2 * pe + o] = uz[k];
+      taps[3 * pe + o] = wr[k];
+      taps[4 * pe + o] = wp;
+      taps[5 * pe + o] = wz;
+      taps[6 * pe + o] = Nr;
+      taps[7 * pe + o] = Np;
+      taps[8 * pe + o] = Nz;
     }
     v[k] = make_double2(Nr * ri, Np * ri);
-    nz_[k] = make_double2(Nz, 0.0);
+    nzr[k] = Nz;
   }
-  __syncthreads();
-  fft256<false>(v, Z[ll], s, tw);
-  scatter_pair(v, Z, g, q0, ll, s, fs.f[0], fs.f[1]);
-  fft256<false>(nz_, Z[ll], s, tw);
-  scatter_pair(nz_, Z, g, q0, ll, s, fs.f[2], nullptr);
+  fft256w<false>(v, Z[ll], s, tw);
+  scatter_pair_w(v, Z, g, q0, ll, s, fs.f[0], fs.f[1]);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = make_double2(nzr[k], 0.0);
+  fft256w<false>(v, Z[ll], s, tw);
+  scatter_pair_w(v, Z, g, q0, ll, s, fs.f[2], nullptr);
 }
 
 Phi256 phi256_geom(const mlg_plan_s* p, bool masked) {
@@ -519,12 +667,19 @@ mlg_status launch_phi256_scalar(const mlg_plan_s* p, int kind, double gamma, dou
 
 mlg_status launch_phi256_vec(const mlg_plan_s* p, const double* U, double* const* f6, double* taps, hipStream_t s) {
   Phi256 g = phi256_geom(p, p->g.dealias != 0);
-  dim3 grid((unsigned)((g.nlines + PL - 1) / PL));
   Six256 six;
   for (int i = 0; i < 6; ++i) six.f[i] = reinterpret_cast<double2*>(f6[i]);
+  const double2* tw = reinterpret_cast<const double2*>(p->d_tw_phi);
+  // interior blocks (all 8 lines present, 128 stored orders) load without guards; one more
+  // launch covers the last partial block, if any
+  const int64_t full = g.M >= 128 ? g.nlines / PL : 0;
+  const int64_t nblk = (g.nlines + PL - 1) / PL;
   p->timing.begin("phi_fft", s);
-  phi_vec256_kernel<<<grid, 128, 0, s>>>(g, reinterpret_cast<const double2*>(p->d_tw_phi), six, p->d_node, U[0], U[1],
-                                         U[2], taps);
+  if (full > 0)
+    phi_vec256_kernel<false><<<dim3((unsigned)full), VB, 0, s>>>(g, tw, six, p->d_node, U[0], U[1], U[2], taps, 0);
+  if (nblk > full)
+    phi_vec256_kernel<true><<<dim3((unsigned)(nblk - full)), VB, 0, s>>>(g, tw, six, p->d_node, U[0], U[1], U[2],
+                                                                         taps, full);
   p->timing.end(s);
   return check("phi_vec256_kernel");
 }

@@ -907,7 +907,9 @@ mlg_status launch_phi_scalar_rhs(const mlg_plan_s* p, int kind, double gamma, do
 }
 
 mlg_status launch_phi_vec_rhs(const mlg_plan_s* p, const double* U, double* const* f6, double* taps, hipStream_t s) {
-  if (p->nphi == 256 && p->use_fast_fft) return launch_phi256_vec(p, U, f6, taps, s);
+  // the 256-point kernel forms per-lane byte offsets of up to 31 lines of orders in 32 bits
+  if (p->nphi == 256 && p->use_fast_fft && (int64_t)p->nr * p->nz <= (int64_t(1) << 23))
+    return launch_phi256_vec(p, U, f6, taps, s);
   PhiGeom g = phi_geom(p, p->g.dealias != 0);
   int lb = 1024 / p->nphi;  // 4 buffers of n complex per line: 64 * lb * n bytes <= 64 KB
   if (lb < 1) lb = 1;
