@@ -552,41 +552,56 @@ __device__ __forceinline__ int active_slot(int a, int kmax, int nz) {
   return (a <= kmax) ? a : nz - (2 * kmax + 1 - a);
 }
 
-constexpr int PJ_D = 8;        // degrees fetched ahead per chunk
+constexpr int PJ_D = 8;    // degrees per chunk: the next chunk's inputs are in flight while one is computed
+constexpr int PJ_PAD = 2;  // zero entries before and after each per-m coefficient table
 
-// One block (one wave) per (m, 64 active k slots): the per-m coefficients (Gram entries,
-// reciprocal pivots, 1/(n(n+1)), gauge weights) are staged in LDS once per block.
+// One block (one wave) per (m, 64 active k slots).  Every lane walks its column's degrees in the
+// same order, so the per-m coefficients (Gram entries, factors, reciprocal pivots, 1/(n(n+1)),
+// gauge weights) are uniform: they are staged in LDS once per block, padded with zeros so that a
+// coupling that does not exist (before the first solved degree, past the last one) multiplies
+// zero instead of being tested.  The recurrences start from zero state for the same reason, and
+// the k = 0 columns (q = -Zhat) take the general path with selected operands, so the steps
+// contain no branches; only the last partial chunk of each pass tests its range.
+// Scratch per (degree, active column): the forward-swept q (complex), the factor pair (l1, l2)
+// and the reciprocal pivot.
+template <bool TAPS>
 __global__ __launch_bounds__(64) void projection_kernel(ProjArgs a) {
   extern __shared__ double sm[];
   const int m = blockIdx.y;
   const int nrc = a.nrc;
-  const int cnt = nrc - m;  // degrees n = m .. nrc-1 at index n - m
-  double* sg0 = sm;
-  double* sg1 = sg0 + cnt;
-  double* sg2 = sg1 + cnt;
-  double* srd = sg2 + cnt;
-  double* sl1 = srd + cnt;
-  double* sl2 = sl1 + cnt;
-  double* sru = sl2 + cnt;
-  double* su1 = sru + cnt;
-  double* su2 = su1 + cnt;
-  double* srL = su2 + cnt;
-  double* sgw = srL + cnt;
+  const int cnt = nrc - m;  // degrees n = m .. nrc-1 at index t = n - m
+  const int n0 = m > 0 ? m : 1;
+  const int i0 = n0 - m;  // first solved index (m = 0: n = 0 is the gauge row)
+  const int len = cnt + 2 * PJ_PAD;
+  double* sg0 = sm + PJ_PAD;
+  double* sg1 = sg0 + len;
+  double* sg2 = sg1 + len;
+  double* srd = sg2 + len;
+  double* sl1 = srd + len;
+  double* sl2 = sl1 + len;
+  double* sru = sl2 + len;
+  double* su1 = sru + len;
+  double* su2 = su1 + len;
+  double* srL = su2 + len;
+  double* sgw = srL + len;
   const int64_t gbase = a.off[m];
-  for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-    const int64_t g = gbase + t;
-    sg0[t] = a.gram[g];
-    sg1[t] = a.gram[a.ngram + g];
-    sg2[t] = a.gram[2 * a.ngram + g];
-    srd[t] = a.gram[3 * a.ngram + g];
-    sl1[t] = a.gram[4 * a.ngram + g];
-    sl2[t] = a.gram[5 * a.ngram + g];
-    sru[t] = a.gram[6 * a.ngram + g];
-    su1[t] = a.gram[7 * a.ngram + g];
-    su2[t] = a.gram[8 * a.ngram + g];
+  for (int e = threadIdx.x; e < len; e += blockDim.x) {
+    const int t = e - PJ_PAD;
+    const bool in = t >= 0 && t < cnt;
+    const int64_t g = gbase + (in ? t : 0);
+    const bool sol = in && t >= i0;
+    sg0[t] = in ? a.gram[g] : 0.0;
+    sg1[t] = in && t + 1 < cnt ? a.gram[a.ngram + g] : 0.0;
+    sg2[t] = in && t + 2 < cnt ? a.gram[2 * a.ngram + g] : 0.0;
+    srd[t] = sol ? a.gram[3 * a.ngram + g] : 0.0;
+    sl1[t] = sol && t - 1 >= i0 ? a.gram[4 * a.ngram + g] : 0.0;
+    sl2[t] = sol && t - 2 >= i0 ? a.gram[5 * a.ngram + g] : 0.0;
+    sru[t] = sol ? a.gram[6 * a.ngram + g] : 0.0;
+    su1[t] = sol && t + 1 < cnt ? a.gram[7 * a.ngram + g] : 0.0;
+    su2[t] = sol && t + 2 < cnt ? a.gram[8 * a.ngram + g] : 0.0;
     const double n = (double)(m + t);
-    srL[t] = (m + t) > 0 ? 1.0 / (n * (n + 1.0)) : 0.0;
-    sgw[t] = sqrt((2.0 * n + 1.0) * 0.5);
+    srL[t] = in && m + t > 0 ? 1.0 / (n * (n + 1.0)) : 0.0;
+    sgw[t] = in ? sqrt((2.0 * n + 1.0) * 0.5) : 0.0;
   }
   __syncthreads();
   const int ca = blockIdx.x * blockDim.x + threadIdx.x;
@@ -595,195 +610,223 @@ __global__ __launch_bounds__(64) void projection_kernel(ProjArgs a) {
   const int kk = active_slot(ca, a.kmax, a.nz);
   const int nz = a.nz;
   const int k = kval(kk, nz);
+  const bool k0 = k == 0;
   const double kap = a.kap0 * k;
-  const int n0 = m > 0 ? m : 1;
-  const int i0 = n0 - m;  // first solved index
-  const int64_t sstride = a.nact;
-  double* __restrict__ scr = a.scratch;
+  const int64_t act = a.nact;
+  double2* __restrict__ sb = reinterpret_cast<double2*>(a.scratch);              // swept q
+  double2* __restrict__ sf = sb + (int64_t)nrc * act;                              // (l1, l2)
+  double* __restrict__ sr = reinterpret_cast<double*>(sf + (int64_t)nrc * act);   // 1 / pivot
   const double2* __restrict__ Cs = a.Cs + gbase * nz + kk;
   const double2* __restrict__ Kp = a.Kp + gbase * nz + kk;
   const double2* __restrict__ Zc = a.Pc + gbase * nz + kk;
   double2* __restrict__ ps = a.psi + gbase * nz + kk;
   double2* __restrict__ chv = a.chi + gbase * nz + kk;
-  auto sidx = [&](int slot, int t) -> int64_t { return ((int64_t)slot * nrc + t) * sstride + col; };
   const double2 z0 = make_double2(0.0, 0.0);
   const double s = kap * kap * a.ell2;
   const double inv_ell2 = 1.0 / a.ell2;
   const double ell2 = a.ell2;
-
-  // ---- pass 1 (ascending index t = n - m): sources, forward substitutions for psi and q
-  double2 zpsi1 = z0, zpsi2 = z0, zq1 = z0, zq2 = z0;
-  double rq1 = 1, rq2 = 1, dq1 = 1, dq2 = 1, lq1p = 0;
-  auto LZ = [&](int t, double2 z) -> double2 { return cscale(z, t >= 0 && t < cnt ? (double)(m + t) * (m + t + 1.0) : 0.0); };
-  double2 lz_m2 = z0, lz_m1 = z0;
-  double2 lz_0 = LZ(0, cnt > 0 ? Zc[0] : z0), lz_p1 = LZ(1, cnt > 1 ? Zc[nz] : z0), lz_p2 = LZ(2, cnt > 2 ? Zc[2 * nz] : z0);
-  double2 cb[PJ_D], kb[PJ_D], zb[PJ_D];
-#pragma unroll
-  for (int d = 0; d < PJ_D; ++d) {
-    cb[d] = d < cnt ? Cs[(int64_t)d * nz] : z0;
-    kb[d] = d < cnt ? Kp[(int64_t)d * nz] : z0;
-    zb[d] = d + 3 < cnt ? Zc[(int64_t)(d + 3) * nz] : z0;
-  }
-  for (int tb = 0; tb < cnt; tb += PJ_D) {
-    double2 cn[PJ_D], kn[PJ_D], zn[PJ_D];
-#pragma unroll
-    for (int d = 0; d < PJ_D; ++d) {  // next chunk in flight while this one is computed
-      const int t = tb + PJ_D + d;
-      cn[d] = t < cnt ? Cs[(int64_t)t * nz] : z0;
-      kn[d] = t < cnt ? Kp[(int64_t)t * nz] : z0;
-      zn[d] = t + 3 < cnt ? Zc[(int64_t)(t + 3) * nz] : z0;
-    }
-#pragma unroll
-    for (int d = 0; d < PJ_D; ++d) {
-      const int t = tb + d;
-      if (t >= cnt) break;
-      const int n = m + t;
-      double2 glz = cscale(lz_0, sg0[t]);
-      if (t >= 1) glz = cadd(glz, cscale(lz_m1, sg1[t - 1]));
-      if (t >= 2) glz = cadd(glz, cscale(lz_m2, sg2[t - 2]));
-      if (t + 1 < cnt) glz = cadd(glz, cscale(lz_p1, sg1[t]));
-      if (t + 2 < cnt) glz = cadd(glz, cscale(lz_p2, sg2[t]));
-      const double2 C = cb[d];
-      const double2 K = make_double2(kb[d].x + glz.x * inv_ell2, kb[d].y + glz.y * inv_ell2);
-      if (a.taps) {
-        const int64_t idx = (gbase + t) * nz + kk;
-        a.taps[idx] = C;
-        a.taps[a.tri_elems + idx] = K;
-        a.taps[2 * a.tri_elems + idx] = Zc[(int64_t)t * nz];
-      }
-      lz_m2 = lz_m1; lz_m1 = lz_0; lz_0 = lz_p1; lz_p1 = lz_p2; lz_p2 = LZ(t + 3, zb[d]);
-      if (t < i0) continue;  // m = 0, n = 0: the gauge row
-      {
-        double2 b = cscale(C, ell2);
-        if (t - 1 >= i0) b = csub(b, cscale(zpsi1, sl1[t]));
-        if (t - 2 >= i0) b = csub(b, cscale(zpsi2, sl2[t]));
-        zpsi2 = zpsi1;
-        zpsi1 = b;
-        ps[(int64_t)t * nz] = b;
-      }
-      if (k != 0) {
-        double l2n = 0, l1n = 0;
-        if (t - 2 >= i0) l2n = sg2[t - 2] * rq2;
-        if (t - 1 >= i0) {
-          double u = sg1[t - 1];
-          if (t - 2 >= i0) u -= l2n * dq2 * lq1p;
-          l1n = u * rq1;
-        }
-        double dn = sg0[t] + s * srL[t];
-        if (t - 1 >= i0) dn -= l1n * l1n * dq1;
-        if (t - 2 >= i0) dn -= l2n * l2n * dq2;
-        const double rn = 1.0 / dn;
-        double2 b = cscale(K, -ell2);
-        if (t - 1 >= i0) b = csub(b, cscale(zq1, l1n));
-        if (t - 2 >= i0) b = csub(b, cscale(zq2, l2n));
-        zq2 = zq1; zq1 = b;
-        dq2 = dq1; dq1 = dn; rq2 = rq1; rq1 = rn; lq1p = l1n;
-        scr[sidx(0, t)] = b.x;
-        scr[sidx(1, t)] = b.y;
-        scr[sidx(2, t)] = l1n;
-        scr[sidx(3, t)] = l2n;
-        scr[sidx(4, t)] = rn;
-      }
-    }
-#pragma unroll
-    for (int d = 0; d < PJ_D; ++d) { cb[d] = cn[d]; kb[d] = kn[d]; zb[d] = zn[d]; }
-  }
-  (void)lq1p;
-  // ---- pass 2 (descending): psi and q back substitution, chi sweep U w = -ell^2 q
-  double2 yp1 = z0, yp2 = z0, yq1 = z0, yq2 = z0, w1 = z0, w2 = z0;
-  double l1q_n1 = 0, l2q_n2 = 0, l2q_n1 = 0;
-  double gpr = 0, gpi = 0;
-  // the chunk below the current one is fetched while the current one is computed
-  double2 pz[PJ_D], qz[PJ_D], pzn[PJ_D], qzn[PJ_D];
-  double ql1[PJ_D], ql2[PJ_D], qr[PJ_D], ql1n[PJ_D], ql2n[PJ_D], qrn[PJ_D];
-  auto fetch2 = [&](int tb, double2 (&fp)[PJ_D], double2 (&fq)[PJ_D], double (&f1)[PJ_D], double (&f2)[PJ_D],
-                    double (&fr)[PJ_D]) {
-#pragma unroll
-    for (int d = 0; d < PJ_D; ++d) {
-      const int t = tb - d;
-      const bool ok = t >= i0;
-      fp[d] = ok ? ps[(int64_t)t * nz] : z0;
-      if (k != 0) {
-        fq[d] = ok ? make_double2(scr[sidx(0, t)], scr[sidx(1, t)]) : z0;
-        f1[d] = ok ? scr[sidx(2, t)] : 0.0;
-        f2[d] = ok ? scr[sidx(3, t)] : 0.0;
-        fr[d] = ok ? scr[sidx(4, t)] : 1.0;
-      } else {
-        fq[d] = ok ? Zc[(int64_t)t * nz] : z0;
-        f1[d] = f2[d] = 0.0;
-        fr[d] = 1.0;
-      }
-    }
+  // loads at a uniform degree index, clamped into the column and zero outside it
+  auto at = [&](const double2* __restrict__ base, int t) -> double2 {
+    const int tc = t < 0 ? 0 : (t < cnt ? t : cnt - 1);
+    const double2 v = base[(int64_t)tc * nz];
+    return (t >= 0 && t < cnt) ? v : z0;
   };
-  fetch2(cnt - 1, pz, qz, ql1, ql2, qr);
-  for (int tb = cnt - 1; tb >= i0; tb -= PJ_D) {
-    fetch2(tb - PJ_D, pzn, qzn, ql1n, ql2n, qrn);
-#pragma unroll
-    for (int d = 0; d < PJ_D; ++d) {
-      const int t = tb - d;
-      if (t < i0) break;
-      {
-        double2 y = cscale(pz[d], srd[t]);
-        if (t + 1 < cnt) y = csub(y, cscale(yp1, sl1[t + 1]));
-        if (t + 2 < cnt) y = csub(y, cscale(yp2, sl2[t + 2]));
-        yp2 = yp1; yp1 = y;
-        const double2 v = cscale(y, srL[t]);
-        ps[(int64_t)t * nz] = v;
-        gpr += sgw[t] * v.x;
-        gpi += sgw[t] * v.y;
-      }
-      double2 qn;
-      if (k != 0) {
-        double2 y = cscale(qz[d], qr[d]);
-        if (t + 1 < cnt) y = csub(y, cscale(yq1, l1q_n1));
-        if (t + 2 < cnt) y = csub(y, cscale(yq2, l2q_n2));
-        yq2 = yq1; yq1 = y;
-        l2q_n2 = l2q_n1;
-        l1q_n1 = ql1[d];
-        l2q_n1 = ql2[d];
-        qn = cscale(y, srL[t]);
-      } else {
-        qn = cscale(qz[d], -1.0);
-      }
-      double2 w = cscale(qn, -ell2);
-      if (t + 1 < cnt) w = csub(w, cscale(w1, su1[t]));
-      if (t + 2 < cnt) w = csub(w, cscale(w2, su2[t]));
-      w2 = w1; w1 = w;
-      chv[(int64_t)t * nz] = w;
+  auto lzv = [&](int t, double2 z) -> double2 {
+    const double n = (double)(m + t);
+    return cscale(z, n * (n + 1.0));
+  };
+
+  // ---- pass 1 (ascending): sources C, K = K' + G L Zhat / ell^2; forward sweeps for psi and q
+  double2 zpsi1 = z0, zpsi2 = z0, zq1 = z0, zq2 = z0;
+  double rq1 = 0, rq2 = 0, dq1 = 0, dq2 = 0, lq1p = 0;
+  double2 lzm2 = z0, lzm1 = z0, lz0 = lzv(0, at(Zc, 0)), lzp1 = lzv(1, at(Zc, 1)), lzp2 = lzv(2, at(Zc, 2));
+  auto glz_at = [&](int t) -> double2 {
+    double2 g = cscale(lz0, sg0[t]);
+    g = cadd(g, cscale(lzm1, sg1[t - 1]));
+    g = cadd(g, cscale(lzm2, sg2[t - 2]));
+    g = cadd(g, cscale(lzp1, sg1[t]));
+    return cadd(g, cscale(lzp2, sg2[t]));
+  };
+  auto shift = [&](int t, double2 z3) {
+    lzm2 = lzm1;
+    lzm1 = lz0;
+    lz0 = lzp1;
+    lzp1 = lzp2;
+    lzp2 = (t + 3 < cnt) ? lzv(t + 3, z3) : z0;
+  };
+  auto taps_at = [&](int t, double2 C, double2 K) {
+    const int64_t idx = (gbase + t) * nz + kk;
+    a.taps[idx] = C;
+    a.taps[a.tri_elems + idx] = K;
+    a.taps[2 * a.tri_elems + idx] = Zc[(int64_t)t * nz];
+  };
+  auto step1 = [&](int t, double2 C, double2 Kq, double2 z3) {
+    const double2 g = glz_at(t);
+    const double2 K = make_double2(Kq.x + g.x * inv_ell2, Kq.y + g.y * inv_ell2);
+    if (TAPS) taps_at(t, C, K);
+    shift(t, z3);
+    // psi: G (L psi) = ell^2 C, forward sweep with the stored L D L^T
+    double2 b = cscale(C, ell2);
+    b = csub(b, cscale(zpsi1, sl1[t]));
+    b = csub(b, cscale(zpsi2, sl2[t]));
+    zpsi2 = zpsi1;
+    zpsi1 = b;
+    ps[(int64_t)t * nz] = b;
+    // q: (G + kap^2 ell^2 L^-1) (L q) = -ell^2 K, L D L^T formed on the fly
+    const double l2n = sg2[t - 2] * rq2;
+    const double l1n = (sg1[t - 1] - l2n * dq2 * lq1p) * rq1;
+    const double dn = sg0[t] + s * srL[t] - l1n * l1n * dq1 - l2n * l2n * dq2;
+    const double rn = 1.0 / dn;
+    double2 bq = cscale(K, -ell2);
+    bq = csub(bq, cscale(zq1, l1n));
+    bq = csub(bq, cscale(zq2, l2n));
+    zq2 = zq1;
+    zq1 = bq;
+    dq2 = dq1;
+    dq1 = dn;
+    rq2 = rq1;
+    rq1 = rn;
+    lq1p = l1n;
+    const int64_t o = (int64_t)t * act + col;
+    sb[o] = bq;
+    sf[o] = k0 ? z0 : make_double2(l1n, l2n);  // k = 0: q = -Zhat, read back unswept
+    sr[o] = k0 ? 1.0 : rn;
+  };
+  int t1 = 0;
+  if (i0 > 0) {  // m = 0: the gauge row n = 0 only feeds the sources of its neighbours
+    if (TAPS) {
+      const double2 g = glz_at(0);
+      const double2 Kq = at(Kp, 0);
+      taps_at(0, at(Cs, 0), make_double2(Kq.x + g.x * inv_ell2, Kq.y + g.y * inv_ell2));
     }
-#pragma unroll
-    for (int d = 0; d < PJ_D; ++d) {
-      pz[d] = pzn[d]; qz[d] = qzn[d]; ql1[d] = ql1n[d]; ql2[d] = ql2n[d]; qr[d] = qrn[d];
-    }
+    shift(0, at(Zc, 3));
+    t1 = 1;
   }
-  if (m == 0) ps[0] = make_double2(-gpr / sgw[0], -gpi / sgw[0]);
-  // ---- pass 3 (ascending): D U^T y = w
-  double2 yc1 = z0, yc2 = z0;
-  double gcr = 0, gci = 0;
-  // rows of the next chunk are read (not yet rewritten by this pass) while this chunk is computed
-  double2 wz[PJ_D], wzn[PJ_D];
-#pragma unroll
-  for (int d = 0; d < PJ_D; ++d) wz[d] = (i0 + d < cnt) ? chv[(int64_t)(i0 + d) * nz] : z0;
-  for (int tb = i0; tb < cnt; tb += PJ_D) {
-#pragma unroll
-    for (int d = 0; d < PJ_D; ++d) wzn[d] = (tb + PJ_D + d < cnt) ? chv[(int64_t)(tb + PJ_D + d) * nz] : z0;
+  {
+    double2 cb[PJ_D], kb[PJ_D], zb[PJ_D];
 #pragma unroll
     for (int d = 0; d < PJ_D; ++d) {
-      const int t = tb + d;
-      if (t >= cnt) break;
-      double2 y = cscale(wz[d], sru[t]);
-      if (t - 1 >= i0) y = csub(y, cscale(yc1, su1[t - 1]));
-      if (t - 2 >= i0) y = csub(y, cscale(yc2, su2[t - 2]));
-      yc2 = yc1; yc1 = y;
+      cb[d] = at(Cs, t1 + d);
+      kb[d] = at(Kp, t1 + d);
+      zb[d] = at(Zc, t1 + d + 3);
+    }
+    int tb = t1;
+    for (; tb + PJ_D <= cnt; tb += PJ_D) {
+      double2 cn[PJ_D], kn[PJ_D], zn[PJ_D];
+#pragma unroll
+      for (int d = 0; d < PJ_D; ++d) {
+        cn[d] = at(Cs, tb + PJ_D + d);
+        kn[d] = at(Kp, tb + PJ_D + d);
+        zn[d] = at(Zc, tb + PJ_D + d + 3);
+      }
+#pragma unroll
+      for (int d = 0; d < PJ_D; ++d) step1(tb + d, cb[d], kb[d], zb[d]);
+#pragma unroll
+      for (int d = 0; d < PJ_D; ++d) {
+        cb[d] = cn[d];
+        kb[d] = kn[d];
+        zb[d] = zn[d];
+      }
+    }
+    for (int d = 0; d < PJ_D && tb + d < cnt; ++d) step1(tb + d, cb[d], kb[d], zb[d]);
+  }
+
+  // ---- pass 2 (descending): psi and q back substitution, chi sweep U w = -ell^2 q
+  {
+    double2 yp1 = z0, yp2 = z0, yq1 = z0, yq2 = z0, w1 = z0, w2 = z0;
+    double l1q_n1 = 0, l2q_n2 = 0, l2q_n1 = 0;
+    double gpr = 0, gpi = 0;
+    const double2* __restrict__ qsrc = k0 ? Zc : nullptr;
+    auto fetch = [&](int t, double2& fp, double2& fq, double2& ff, double& fr) {
+      const int tc = t < i0 ? i0 : t;
+      const int64_t o = (int64_t)tc * act + col;
+      fp = ps[(int64_t)tc * nz];
+      fq = k0 ? qsrc[(int64_t)tc * nz] : sb[o];
+      ff = sf[o];
+      fr = sr[o];
+    };
+    auto step2 = [&](int t, double2 pz, double2 qz, double2 f, double r) {
+      double2 y = cscale(pz, srd[t]);
+      y = csub(y, cscale(yp1, sl1[t + 1]));
+      y = csub(y, cscale(yp2, sl2[t + 2]));
+      yp2 = yp1;
+      yp1 = y;
+      const double2 v = cscale(y, srL[t]);
+      ps[(int64_t)t * nz] = v;
+      gpr += sgw[t] * v.x;
+      gpi += sgw[t] * v.y;
+      double2 yq = cscale(qz, r);
+      yq = csub(yq, cscale(yq1, l1q_n1));
+      yq = csub(yq, cscale(yq2, l2q_n2));
+      yq2 = yq1;
+      yq1 = yq;
+      l2q_n2 = l2q_n1;
+      l1q_n1 = f.x;
+      l2q_n1 = f.y;
+      const double2 qn = cscale(yq, k0 ? -1.0 : srL[t]);
+      double2 w = cscale(qn, -ell2);
+      w = csub(w, cscale(w1, su1[t]));
+      w = csub(w, cscale(w2, su2[t]));
+      w2 = w1;
+      w1 = w;
+      chv[(int64_t)t * nz] = w;
+    };
+    double2 pz[PJ_D], qz[PJ_D], ff[PJ_D];
+    double rr[PJ_D];
+#pragma unroll
+    for (int d = 0; d < PJ_D; ++d) fetch(cnt - 1 - d, pz[d], qz[d], ff[d], rr[d]);
+    int tb = cnt - 1;
+    for (; tb - PJ_D + 1 >= i0; tb -= PJ_D) {
+      double2 pn[PJ_D], qn[PJ_D], fn[PJ_D];
+      double rn[PJ_D];
+#pragma unroll
+      for (int d = 0; d < PJ_D; ++d) fetch(tb - PJ_D - d, pn[d], qn[d], fn[d], rn[d]);
+#pragma unroll
+      for (int d = 0; d < PJ_D; ++d) step2(tb - d, pz[d], qz[d], ff[d], rr[d]);
+#pragma unroll
+      for (int d = 0; d < PJ_D; ++d) {
+        pz[d] = pn[d];
+        qz[d] = qn[d];
+        ff[d] = fn[d];
+        rr[d] = rn[d];
+      }
+    }
+    for (int d = 0; d < PJ_D && tb - d >= i0; ++d) step2(tb - d, pz[d], qz[d], ff[d], rr[d]);
+    if (m == 0) ps[0] = make_double2(-gpr / sgw[0], -gpi / sgw[0]);
+  }
+
+  // ---- pass 3 (ascending): D U^T y = w
+  {
+    double2 yc1 = z0, yc2 = z0;
+    double gcr = 0, gci = 0;
+    auto step3 = [&](int t, double2 wz) {
+      double2 y = cscale(wz, sru[t]);
+      y = csub(y, cscale(yc1, su1[t - 1]));
+      y = csub(y, cscale(yc2, su2[t - 2]));
+      yc2 = yc1;
+      yc1 = y;
       const double2 v = cscale(y, srL[t]);
       chv[(int64_t)t * nz] = v;
       gcr += sgw[t] * v.x;
       gci += sgw[t] * v.y;
-    }
+    };
+    // rows of the next chunk are read (not yet rewritten by this pass) while this chunk is computed
+    double2 wz[PJ_D];
 #pragma unroll
-    for (int d = 0; d < PJ_D; ++d) wz[d] = wzn[d];
+    for (int d = 0; d < PJ_D; ++d) wz[d] = at(chv, i0 + d);
+    int tb = i0;
+    for (; tb + PJ_D <= cnt; tb += PJ_D) {
+      double2 wn[PJ_D];
+#pragma unroll
+      for (int d = 0; d < PJ_D; ++d) wn[d] = at(chv, tb + PJ_D + d);
+#pragma unroll
+      for (int d = 0; d < PJ_D; ++d) step3(tb + d, wz[d]);
+#pragma unroll
+      for (int d = 0; d < PJ_D; ++d) wz[d] = wn[d];
+    }
+    for (int d = 0; d < PJ_D && tb + d < cnt; ++d) step3(tb + d, wz[d]);
+    if (m == 0) chv[0] = make_double2(-gcr / sgw[0], -gci / sgw[0]);
   }
-  if (m == 0) chv[0] = make_double2(-gcr / sgw[0], -gci / sgw[0]);
 }
 
 // Zero every entry of the packed arrays whose (m, k) column is not active.
@@ -1003,9 +1046,12 @@ mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, dou
   }
   if (a.nact > 0) {
     dim3 grid((unsigned)((a.nkact + 63) / 64), (unsigned)mmax);
-    const size_t shm = (size_t)11 * p->nrc * sizeof(double);
+    const size_t shm = (size_t)11 * (p->nrc + 2 * PJ_PAD) * sizeof(double);
     p->timing.begin("projection", s);
-    projection_kernel<<<grid, 64, shm, s>>>(a);
+    if (a.taps)
+      projection_kernel<true><<<grid, 64, shm, s>>>(a);
+    else
+      projection_kernel<false><<<grid, 64, shm, s>>>(a);
     p->timing.end(s);
   }
   return check_launch("projection_kernel");
