@@ -43,6 +43,7 @@ struct FoldSynthArgs {
   const int64_t* off;
   const double* node;      // rinv[nr], q[nr], opx[nr]
   int nr, nrc, nz;
+  int gx, gy, gz;          // tiles: column blocks, row blocks, orders
   double kap0;
 };
 
@@ -76,10 +77,12 @@ __device__ __forceinline__ void synth_write(const FoldSynthArgs& a, int m, int i
 // lanes l and l ^ 8 exchange their parts in the epilogue, then one writes node i and the other
 // its mirror.
 __global__ __launch_bounds__(256, 2) void synth_fold_kernel(FoldSynthArgs a) {
-  const int m = blockIdx.z;
+  Tile3 tl;
+  if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
+  const int m = tl.z;
   const int half = a.nr / 2;
-  const int row0 = blockIdx.y * TM;
-  const int kk0 = blockIdx.x * TC8;
+  const int row0 = tl.y * TM;
+  const int kk0 = tl.x * TC8;
   if (row0 >= half || kk0 >= a.nz) return;
   const int K = a.nrc > m ? a.nrc - m : 0;
   const int KP = (K + 1) / 2;
@@ -188,6 +191,7 @@ struct FoldProjArgs {
   double2* out[3];         // C, K', Zhat (packed triangular)
   const int64_t* off;
   int nr, nrc, nz, kmax, nkact;
+  int gx, gy, gz;          // tiles: column blocks, pair blocks, orders
   double kap0;
 };
 
@@ -199,11 +203,13 @@ __device__ __forceinline__ int active_kk(int a, int kmax, int nz) {
 // the 16 MFMA columns as in synth_fold_kernel; the low lane of a partner pair writes the even
 // degree, the high lane the odd one.
 __global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs a) {
-  const int m = blockIdx.z;
+  Tile3 tl;
+  if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
+  const int m = tl.z;
   const int rows = a.nrc > m ? a.nrc - m : 0;
   const int KP = (rows + 1) / 2;
-  const int row0 = blockIdx.y * TM;  // pair index
-  const int c0 = blockIdx.x * TC8;
+  const int row0 = tl.y * TM;  // pair index
+  const int c0 = tl.x * TC8;
   if (row0 >= KP || c0 >= a.nkact) return;
   const int nr = a.nr, nz = a.nz, half = a.nr / 2;
   const double* __restrict__ P = a.Pf + a.off[m] * nr;
@@ -343,9 +349,11 @@ mlg_status launch_synth_fold(const mlg_plan_s* p, const double* psi, const doubl
   a.nrc = p->nrc;
   a.nz = p->nz;
   a.kap0 = 2.0 * M_PI / p->g.lz;
-  dim3 grid((unsigned)((p->nz + TC8 - 1) / TC8), (unsigned)((p->nr / 2 + TM - 1) / TM), (unsigned)p->M);
+  a.gx = (p->nz + TC8 - 1) / TC8;
+  a.gy = (p->nr / 2 + TM - 1) / TM;
+  a.gz = p->M;
   p->timing.begin("synth_gemm", s);
-  synth_fold_kernel<<<grid, 256, 0, s>>>(a);
+  synth_fold_kernel<<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
   p->timing.end(s);
   return check("synth_fold_kernel");
 }
@@ -368,9 +376,11 @@ mlg_status launch_proj_fold(const mlg_plan_s* p, double* const* in3, double* con
   a.kap0 = 2.0 * M_PI / p->g.lz;
   if (mmax <= 0 || a.nkact <= 0) return MLG_OK;
   const int kp = (p->nrc + 1) / 2;
-  dim3 grid((unsigned)((a.nkact + TC8 - 1) / TC8), (unsigned)((kp + TM - 1) / TM), (unsigned)mmax);
+  a.gx = (a.nkact + TC8 - 1) / TC8;
+  a.gy = (kp + TM - 1) / TM;
+  a.gz = mmax;
   p->timing.begin("proj_gemm", s);
-  proj_fold_kernel<<<grid, 256, 0, s>>>(a);
+  proj_fold_kernel<<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
   p->timing.end(s);
   return check("proj_fold_kernel");
 }

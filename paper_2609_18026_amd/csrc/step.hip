@@ -60,6 +60,7 @@ struct StepArgs {
   const int64_t* loff;
   const int64_t* off;
   int M, nrc, nz, nzc, mode, q;   // mode 0 FE-BE, 1 AB-CN; q = p / 2 (1 without hyperviscosity)
+  int gx, gy, gz;                 // tiles: axial column blocks, row blocks, orders
   double h, nu, nuh, kap0;
 };
 
@@ -78,11 +79,13 @@ __device__ __forceinline__ double denom(const StepArgs& a, double mu) {
 
 // Z = V^{-1} [s | a] per m, then W = Phi Zs + Psi Za (and the m = 0 divided differences)
 __global__ __launch_bounds__(256) void step_fwd_kernel(StepArgs a) {
-  const int m = blockIdx.z;
+  Tile3 tl;
+  if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
+  const int m = tl.z;
   if (m >= a.M || m >= a.nrc) return;
   const int n0 = m == 0 ? 1 : 0;
   const int K = a.nrc - m - n0;
-  const int j0 = blockIdx.y * TM, kk0 = blockIdx.x * TC;
+  const int j0 = tl.y * TM, kk0 = tl.x * TC;
   if (j0 >= K || kk0 >= a.nz) return;
   const int nz = a.nz;
   const double* __restrict__ A = a.fwd + a.qoff[m];
@@ -186,11 +189,13 @@ __global__ __launch_bounds__(256) void step_fwd_kernel(StepArgs a) {
 
 // out rows n >= n0 = V W per m; inactive axial slots are zeroed
 __global__ __launch_bounds__(256) void step_bwd_kernel(StepArgs a) {
-  const int m = blockIdx.z;
+  Tile3 tl;
+  if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
+  const int m = tl.z;
   if (m >= a.M || m >= a.nrc) return;
   const int n0 = m == 0 ? 1 : 0;
   const int K = a.nrc - m - n0;
-  const int r0 = blockIdx.y * TM, kk0 = blockIdx.x * TC;
+  const int r0 = tl.y * TM, kk0 = tl.x * TC;
   if (r0 >= K || kk0 >= a.nz) return;
   const int nz = a.nz;
   const double* __restrict__ A = a.bwd + a.qoff[m];
@@ -419,7 +424,10 @@ mlg_status launch_step(const mlg_plan_s* p, int mode, int which, const double* s
   const int mz = std::min(p->M, p->nrc);
   p->timing.begin("step", st);
   if (p->step_maxk > 0) {
-    dim3 grid((unsigned)((p->nz + TC - 1) / TC), (unsigned)((p->step_maxk + TM - 1) / TM), (unsigned)mz);
+    a.gx = (p->nz + TC - 1) / TC;
+    a.gy = (p->step_maxk + TM - 1) / TM;
+    a.gz = mz;
+    const dim3 grid(xcd_blocks(a.gx, a.gy, a.gz));
     step_fwd_kernel<<<grid, 256, 0, st>>>(a);
     step_bwd_kernel<<<grid, 256, 0, st>>>(a);
   }
