@@ -103,41 +103,43 @@ __global__ __launch_bounds__(256, 2) void synth_fold_kernel(FoldSynthArgs a) {
 #pragma unroll
     for (int p = 0; p < 7; ++p) acc[s][p] = double4_t{0.0, 0.0, 0.0, 0.0};
 
-  double ra[8];
-  double2 rb;
-  auto load = [&](int jj0) {
+  // operands of the next two stages are held in registers (ra, rb: stage kt + 1; rn, rbn: kt + 2)
+  double ra[8], rn[8];
+  double2 rb, rbn;
+  auto load = [&](int jj0, double (&da)[8], double2& db) {
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int e = tid + 256 * t;
       const int tab = e >> 10, par = (e >> 9) & 1, kr = (e >> 6) & 7, rr = e & 63;
       const int j = 2 * (jj0 + kr) + par, i = row0 + rr;
       const bool ok = j < K && i < half;
-      ra[t] = ok ? (tab ? T : P)[(int64_t)j * nr + i] : 0.0;
+      da[t] = ok ? (tab ? T : P)[(int64_t)j * nr + i] : 0.0;
     }
     const int fld = tid >> 7, par = (tid >> 6) & 1, kr = (tid >> 3) & 7, cc = tid & 7;
     const int j = 2 * (jj0 + kr) + par, kk = kk0 + cc;
-    rb = (j < K && kk < nz) ? (fld ? ch : ps)[(int64_t)j * nz + kk] : make_double2(0.0, 0.0);
+    db = (j < K && kk < nz) ? (fld ? ch : ps)[(int64_t)j * nz + kk] : make_double2(0.0, 0.0);
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, const double (&da)[8], const double2& db) {
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int e = tid + 256 * t;
-      As[buf][e >> 10][(e >> 9) & 1][(e >> 6) & 7][e & 63] = ra[t];
+      As[buf][e >> 10][(e >> 9) & 1][(e >> 6) & 7][e & 63] = da[t];
     }
     const int fld = tid >> 7, par = (tid >> 6) & 1, kr = (tid >> 3) & 7, cc = tid & 7;
-    Bs[buf][fld][par][kr][cc] = rb.x;
-    Bs[buf][fld][par][kr][8 + cc] = rb.y;
+    Bs[buf][fld][par][kr][cc] = db.x;
+    Bs[buf][fld][par][kr][8 + cc] = db.y;
   };
 
   const int nk = (KP + TP - 1) / TP;
   if (nk > 0) {
-    load(0);
-    store(0);
+    load(0, ra, rb);
+    store(0, ra, rb);
   }
+  if (nk > 1) load(TP, ra, rb);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
-    if (kt + 1 < nk) load((kt + 1) * TP);
+    if (kt + 2 < nk) load((kt + 2) * TP, rn, rbn);
 #pragma unroll
     for (int ks = 0; ks < TP; ks += 4) {
       const int kr = ks + (lane >> 4);
@@ -159,7 +161,10 @@ __global__ __launch_bounds__(256, 2) void synth_fold_kernel(FoldSynthArgs a) {
         c[6] = MFMA(aT, lc, c[6]);  // B4 = Tbar L chi
       }
     }
-    if (kt + 1 < nk) store(buf ^ 1);
+    if (kt + 1 < nk) store(buf ^ 1, ra, rb);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) ra[t] = rn[t];
+    rb = rbn;
     __syncthreads();
   }
   const bool hi = cl >= 8;
@@ -231,9 +236,14 @@ __global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs a) {
   const int bca = c0 + bcc;
   const int bkk = (tid < 192 && bca < a.nkact) ? active_kk(bca, a.kmax, nz) : -1;
   const double2* __restrict__ Xb = (tid < 192) ? a.in[bf] + (int64_t)m * nr * nz : nullptr;
-  double ra[2][4];
-  double2 rs, rd;
-  auto load = [&](int i0) {
+  // operands of the next two stages in registers (raw loads; sums and differences are formed
+  // when they are written to LDS, so the loads stay in flight across the MFMAs)
+  struct Stage {
+    double p[4], q[4];
+    double2 x, y;
+  };
+  Stage ra, rn;
+  auto load = [&](int i0, Stage& d) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int e = tid + 256 * t;
@@ -241,41 +251,38 @@ __global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs a) {
       const int i = i0 + kr, j = 2 * (row0 + rr) + par;
       const bool ok = i < half && j < rows;
       const int64_t idx = (int64_t)i * rows + j;
-      ra[0][t] = ok ? P[idx] : 0.0;
-      ra[1][t] = ok ? Q[idx] : 0.0;
+      d.p[t] = ok ? P[idx] : 0.0;
+      d.q[t] = ok ? Q[idx] : 0.0;
     }
     const int i = i0 + bkr;
-    double2 x = make_double2(0.0, 0.0), y = x;
-    if (bkk >= 0 && i < half) {
-      x = Xb[(int64_t)i * nz + bkk];
-      y = Xb[(int64_t)(nr - 1 - i) * nz + bkk];
-    }
-    rs = make_double2(x.x + y.x, x.y + y.y);
-    rd = make_double2(x.x - y.x, x.y - y.y);
+    const bool ok = bkk >= 0 && i < half;
+    d.x = ok ? Xb[(int64_t)i * nz + bkk] : make_double2(0.0, 0.0);
+    d.y = ok ? Xb[(int64_t)(nr - 1 - i) * nz + bkk] : make_double2(0.0, 0.0);
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, const Stage& d) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int e = tid + 256 * t;
       const int par = e >> 9, kr = (e >> 6) & 7, rr = e & 63;
-      As[buf][0][par][kr][rr] = ra[0][t];
-      As[buf][1][par][kr][rr] = ra[1][t] + 2.0 * ra[0][t];  // w Q_A = w Q + 2 w Pbar
+      As[buf][0][par][kr][rr] = d.p[t];
+      As[buf][1][par][kr][rr] = d.q[t] + 2.0 * d.p[t];  // w Q_A = w Q + 2 w Pbar
     }
     if (tid < 192) {
-      Bs[buf][bf][0][bkr][bcc] = rs.x;
-      Bs[buf][bf][0][bkr][8 + bcc] = rs.y;
-      Bs[buf][bf][1][bkr][bcc] = rd.x;
-      Bs[buf][bf][1][bkr][8 + bcc] = rd.y;
+      Bs[buf][bf][0][bkr][bcc] = d.x.x + d.y.x;
+      Bs[buf][bf][0][bkr][8 + bcc] = d.x.y + d.y.y;
+      Bs[buf][bf][1][bkr][bcc] = d.x.x - d.y.x;
+      Bs[buf][bf][1][bkr][8 + bcc] = d.x.y - d.y.y;
     }
   };
 
   const int nk = (half + TP - 1) / TP;
-  load(0);
-  store(0);
+  load(0, ra);
+  store(0, ra);
+  if (nk > 1) load(TP, ra);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
-    if (kt + 1 < nk) load((kt + 1) * TP);
+    if (kt + 2 < nk) load((kt + 2) * TP, rn);
 #pragma unroll
     for (int ks = 0; ks < TP; ks += 4) {
       const int kr = ks + (lane >> 4);
@@ -292,7 +299,8 @@ __global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs a) {
         c[4] = MFMA(aP, Bs[buf][2][sp][kr][cl], c[4]);  // Pc
       }
     }
-    if (kt + 1 < nk) store(buf ^ 1);
+    if (kt + 1 < nk) store(buf ^ 1, ra);
+    ra = rn;
     __syncthreads();
   }
   const bool hi = cl >= 8;
