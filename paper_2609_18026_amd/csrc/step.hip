@@ -99,43 +99,48 @@ __global__ __launch_bounds__(256) void step_fwd_kernel(StepArgs a) {
   double4_t acc[2][2];
 #pragma unroll
   for (int p = 0; p < 2; ++p) acc[p][0] = acc[p][1] = double4_t{0.0, 0.0, 0.0, 0.0};
+  // raw loads with indices clamped into the operands (no branch around a load); the AB-CN
+  // combination 3 A1 - A0 and the zeros outside the operands are formed at the LDS store, so the
+  // loads of the next stage stay in flight across this stage's MFMAs
   double ra[4];
-  double2 rbv[2];
+  double2 rs, r1, r0v;
+  const double2* __restrict__ q0 = p0 ? p0 : p1;
+  const double c1 = p0 ? 3.0 : 1.0, c0 = p0 ? 1.0 : 0.0;
   auto load = [&](int k0) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int e = tid + 256 * t;
       const int kr = e >> 6, rr = e & 63;
       const int k = k0 + kr, j = j0 + rr;
-      ra[t] = (k < K && j < K) ? A[(int64_t)k * K + j] : 0.0;
+      const int kc = k < K ? k : K - 1, jc = j < K ? j : K - 1;
+      ra[t] = A[(int64_t)kc * K + jc];
     }
     const int kr = tid >> 4, cc = tid & 15;
     const int k = k0 + kr, kk = kk0 + cc;
-    const bool ok = k < K && kk < nz;
-    const int64_t i = (int64_t)k * nz + kk;
-    rbv[0] = ok ? s[i] : make_double2(0.0, 0.0);
-    double2 v = ok ? p1[i] : make_double2(0.0, 0.0);
-    if (ok && p0) {
-      const double2 w = p0[i];
-      v = make_double2(3.0 * v.x - w.x, 3.0 * v.y - w.y);
-    }
-    rbv[1] = v;
+    const int kc = k < K ? k : K - 1, kkc = kk < nz ? kk : nz - 1;
+    const int64_t i = (int64_t)kc * nz + kkc;
+    rs = s[i];
+    r1 = p1[i];
+    r0v = q0[i];
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, int k0) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int e = tid + 256 * t;
-      As[buf][e >> 6][e & 63] = ra[t];
+      const bool ok = k0 + (e >> 6) < K && j0 + (e & 63) < K;
+      As[buf][e >> 6][e & 63] = ok ? ra[t] : 0.0;
     }
     const int kr = tid >> 4, cc = tid & 15;
-    Bs[buf][0][kr][cc] = rbv[0].x;
-    Bs[buf][0][kr][TC + cc] = rbv[0].y;
-    Bs[buf][1][kr][cc] = rbv[1].x;
-    Bs[buf][1][kr][TC + cc] = rbv[1].y;
+    const bool ok = k0 + kr < K && kk0 + cc < nz;
+    const double2 v = make_double2(c1 * r1.x - c0 * r0v.x, c1 * r1.y - c0 * r0v.y);
+    Bs[buf][0][kr][cc] = ok ? rs.x : 0.0;
+    Bs[buf][0][kr][TC + cc] = ok ? rs.y : 0.0;
+    Bs[buf][1][kr][cc] = ok ? v.x : 0.0;
+    Bs[buf][1][kr][TC + cc] = ok ? v.y : 0.0;
   };
   const int nk = (K + TK - 1) / TK;
   load(0);
-  store(0);
+  store(0, 0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
@@ -149,7 +154,7 @@ __global__ __launch_bounds__(256) void step_fwd_kernel(StepArgs a) {
       acc[1][0] = MFMA(av, Bs[buf][1][kr][lane & 15], acc[1][0]);
       acc[1][1] = MFMA(av, Bs[buf][1][kr][TC + (lane & 15)], acc[1][1]);
     }
-    if (kt + 1 < nk) store(buf ^ 1);
+    if (kt + 1 < nk) store(buf ^ 1, (kt + 1) * TK);
     __syncthreads();
   }
   const int kk = kk0 + (lane & 15);
@@ -206,6 +211,7 @@ __global__ __launch_bounds__(256) void step_bwd_kernel(StepArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double4_t acc[2];
   acc[0] = acc[1] = double4_t{0.0, 0.0, 0.0, 0.0};
+  // raw loads with clamped indices, zeros applied at the LDS store (as in step_fwd_kernel)
   double ra[4];
   double2 rbv;
   auto load = [&](int k0) {
@@ -214,25 +220,29 @@ __global__ __launch_bounds__(256) void step_bwd_kernel(StepArgs a) {
       const int e = tid + 256 * t;
       const int kr = e >> 6, rr = e & 63;
       const int k = k0 + kr, r = r0 + rr;
-      ra[t] = (k < K && r < K) ? A[(int64_t)k * K + r] : 0.0;
+      const int kc = k < K ? k : K - 1, rc = r < K ? r : K - 1;
+      ra[t] = A[(int64_t)kc * K + rc];
     }
     const int kr = tid >> 4, cc = tid & 15;
     const int k = k0 + kr, kk = kk0 + cc;
-    rbv = (k < K && kk < nz) ? Wm[(int64_t)k * nz + kk] : make_double2(0.0, 0.0);
+    const int kc = k < K ? k : K - 1, kkc = kk < nz ? kk : nz - 1;
+    rbv = Wm[(int64_t)kc * nz + kkc];
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, int k0) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int e = tid + 256 * t;
-      As[buf][e >> 6][e & 63] = ra[t];
+      const bool ok = k0 + (e >> 6) < K && r0 + (e & 63) < K;
+      As[buf][e >> 6][e & 63] = ok ? ra[t] : 0.0;
     }
     const int kr = tid >> 4, cc = tid & 15;
-    Bs[buf][kr][cc] = rbv.x;
-    Bs[buf][kr][TC + cc] = rbv.y;
+    const bool ok = k0 + kr < K && kk0 + cc < nz;
+    Bs[buf][kr][cc] = ok ? rbv.x : 0.0;
+    Bs[buf][kr][TC + cc] = ok ? rbv.y : 0.0;
   };
   const int nk = (K + TK - 1) / TK;
   load(0);
-  store(0);
+  store(0, 0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
@@ -244,7 +254,7 @@ __global__ __launch_bounds__(256) void step_bwd_kernel(StepArgs a) {
       acc[0] = MFMA(av, Bs[buf][kr][lane & 15], acc[0]);
       acc[1] = MFMA(av, Bs[buf][kr][TC + (lane & 15)], acc[1]);
     }
-    if (kt + 1 < nk) store(buf ^ 1);
+    if (kt + 1 < nk) store(buf ^ 1, (kt + 1) * TK);
     __syncthreads();
   }
   const int kk = kk0 + (lane & 15);
@@ -258,13 +268,38 @@ __global__ __launch_bounds__(256) void step_bwd_kernel(StepArgs a) {
   }
 }
 
-// m = 0, n = 0: out = Phi(alpha) s0 + Psi(alpha) a0 + sum_j u_j W0[j]
-__global__ __launch_bounds__(64) void step_row0_kernel(StepArgs a) {
-  const int kk = blockIdx.x * blockDim.x + threadIdx.x;
-  if (kk >= a.nz) return;
+// m = 0, n = 0: out = Phi(alpha) s0 + Psi(alpha) a0 + sum_j u_j W0[j].  A block takes R0C axial
+// columns; the R0S lanes of a column sum every R0S-th j (their loads all in flight at once) and
+// the partial sums are added in LDS in a fixed order.
+constexpr int R0C = 16;  // columns per block
+constexpr int R0S = 16;  // partial sums per column
+
+__global__ __launch_bounds__(R0C * R0S) void step_row0_kernel(StepArgs a) {
+  __shared__ double2 part[R0S][R0C];
+  const int c = threadIdx.x % R0C, sl = threadIdx.x / R0C;
+  const int kk = blockIdx.x * R0C + c;
+  const int K = a.nrc - 1;
+  double re = 0.0, im = 0.0;
+  if (kk < a.nz) {
+#pragma unroll 8
+    for (int j = sl; j < K; j += R0S) {
+      const double2 w = a.W0[(int64_t)j * a.nz + kk];
+      re += a.u[j] * w.x;
+      im += a.u[j] * w.y;
+    }
+  }
+  part[sl][c] = make_double2(re, im);
+  __syncthreads();
+  if (sl != 0 || kk >= a.nz) return;
   if (!active_slot(kk, a.nz, a.nzc)) {
     a.out[kk] = make_double2(0.0, 0.0);
     return;
+  }
+  double sr = 0.0, si = 0.0;
+#pragma unroll
+  for (int q = 0; q < R0S; ++q) {
+    sr += part[q][c].x;
+    si += part[q][c].y;
   }
   const double kap = a.kap0 * kval(kk, a.nz);
   const double alpha = kap * kap;
@@ -274,14 +309,7 @@ __global__ __launch_bounds__(64) void step_row0_kernel(StepArgs a) {
   const double2 s0 = a.s[kk];
   double2 v = a.a1[kk];
   if (a.a0) v = make_double2(3.0 * v.x - a.a0[kk].x, 3.0 * v.y - a.a0[kk].y);
-  double re = phi * s0.x + psi * v.x, im = phi * s0.y + psi * v.y;
-  const int K = a.nrc - 1;
-  for (int j = 0; j < K; ++j) {
-    const double2 w = a.W0[(int64_t)j * a.nz + kk];
-    re += a.u[j] * w.x;
-    im += a.u[j] * w.y;
-  }
-  a.out[kk] = make_double2(re, im);
+  a.out[kk] = make_double2(phi * s0.x + psi * v.x + sr, phi * s0.y + psi * v.y + si);
 }
 
 }  // namespace
@@ -431,7 +459,7 @@ mlg_status launch_step(const mlg_plan_s* p, int mode, int which, const double* s
     step_fwd_kernel<<<grid, 256, 0, st>>>(a);
     step_bwd_kernel<<<grid, 256, 0, st>>>(a);
   }
-  step_row0_kernel<<<(unsigned)((p->nz + 63) / 64), 64, 0, st>>>(a);
+  step_row0_kernel<<<(unsigned)((p->nz + R0C - 1) / R0C), R0C * R0S, 0, st>>>(a);
   p->timing.end(st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(MLG_E_DEVICE, std::string("step kernels: ") + hipGetErrorString(e));
