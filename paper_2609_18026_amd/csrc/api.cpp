@@ -246,8 +246,7 @@ mlg_status mlg_rhs_tp(mlg_plan p, const double* U, const void* psi, const void* 
   if (st) return st;
   // 2. inverse z transforms of the six fields
   const int64_t mrows = (int64_t)p->M * p->nr;
-  for (int i = 0; i < 6; ++i)
-    if ((st = launch_zfft(p, w.X[i], w.X[i], mrows, +1, nullptr, 0, 0, s))) return st;
+  if ((st = launch_zfft_fields(p, w.X, w.X, 6, mrows, +1, nullptr, 0, 0, s))) return st;
   // 3. phi stage: nodal u, w -> N = (U + u) x w -> harmonics of N_r/r, N_phi/r, N_z
   double* tp = static_cast<double*>(taps);
   if ((st = launch_phi_vec_rhs(p, Uh, w.X, tp, s))) return st;
@@ -255,8 +254,7 @@ mlg_status mlg_rhs_tp(mlg_plan p, const double* U, const void* psi, const void* 
   int mmax, kmax;
   active_columns(p, &mmax, &kmax);
   const int64_t frows = (int64_t)mmax * p->nr;
-  for (int i = 0; i < 3; ++i)
-    if ((st = launch_zfft(p, w.X[i], w.X[i], frows, -1, nullptr, 0, 0, s))) return st;
+  if ((st = launch_zfft_fields(p, w.X, w.X, 3, frows, -1, nullptr, 0, 0, s))) return st;
   // 5. Galerkin projections onto Pbar and Q = T - 2(1+x) Pbar with the C, K', Zhat epilogue
   double* src3[3] = {w.T[0], w.T[1], w.T[2]};
   st = (p->prec == MLG_SPLIT_BF16) ? launch_split_proj(p, w.X, src3, mmax, kmax, s)

@@ -103,46 +103,6 @@ __device__ __forceinline__ bool kkept(int kk, int nz, int nzc) {
   return (k < 0 ? -k : k) < nzc;
 }
 
-constexpr int ZL = 8;  // lines per block (128 threads)
-
-template <bool INV>
-__global__ __launch_bounds__(128) void zfft256_kernel(const double2* __restrict__ tw, const double2* in,
-                                                      double2* out, int64_t rows, int nzc,
-                                                      const int32_t* __restrict__ row_m, int mask_m,
-                                                      int mask_k) {
-  __shared__ double2 Zs[ZL][16 * 17];
-  const int t = threadIdx.x, ll = t >> 4, s = t & 15;
-  const int64_t row = (int64_t)blockIdx.x * ZL + ll;
-  const bool valid = row < rows;
-  double2 v[16];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int kk = s + 16 * j;
-    double2 a = make_double2(0.0, 0.0);
-    if (valid) a = in[row * 256 + kk];
-    if (INV && !kkept(kk, 256, nzc)) a = make_double2(0.0, 0.0);
-    v[j] = a;
-  }
-  fft256<INV>(v, Zs[ll], s, tw);
-  if (!valid) return;
-  const int mrow = (!INV && row_m) ? row_m[row] : 0;
-#pragma unroll
-  for (int k1 = 0; k1 < 16; ++k1) {
-    const int kk = s + 16 * k1;
-    double2 a = v[k1];
-    if (!INV) {
-      a = cscale(a, 1.0 / 256.0);
-      bool keep = kkept(kk, 256, nzc);
-      if (row_m) {
-        const int k = kval(kk, 256);
-        keep = keep && mrow <= mask_m && (k < 0 ? -k : k) <= mask_k;
-      }
-      if (!keep) a = make_double2(0.0, 0.0);
-    }
-    out[row * 256 + kk] = a;
-  }
-}
-
 // ---------------------------------------------------------------- azimuthal stages
 // Line q = i N_z + l; physical samples at (l N_r + i) 256 + j; harmonic m at m * nlines + q.
 constexpr int PL = 8;  // lines per block (128 threads, 16 per line)
@@ -599,6 +559,56 @@ __global__ __launch_bounds__(VB) void phi_vec256_kernel(Phi256 g, const double2*
   scatter_pair_w(v, Z, g, q0, ll, s, fs.f[2], nullptr);
 }
 
+// ---------------------------------------------------------------- z transforms (32-lane lines)
+// Contiguous lines of 256 samples, up to six fields per launch (blocks field-major).  Lane s of a
+// line loads x[s + 32 j] straight into registers (32 lanes cover 512 contiguous bytes), fft256w
+// transforms the line within its wavefront and the lane stores X[s + 32 j]: the only block
+// barrier is the one after the twiddle table is staged.  In place when in == out.
+struct ZFields {
+  const double2* in[6];
+  double2* out[6];
+};
+
+template <bool INV>
+__global__ __launch_bounds__(VB) void zfft256w_kernel(const double2* __restrict__ twg, ZFields fs, int64_t rows,
+                                                      int64_t per_field, int nzc, const int32_t* __restrict__ row_m,
+                                                      int mask_m, int mask_k) {
+  __shared__ double2 Z[PL][WROW];
+  __shared__ double2 tw[256];
+  const int t = threadIdx.x, ll = t / WL, s = t % WL;
+  tw[t] = twg[t];
+  __syncthreads();
+  const int64_t f = blockIdx.x / per_field;
+  const int64_t row = (blockIdx.x - f * per_field) * PL + ll;
+  if (row >= rows) return;  // no block barrier follows
+  const double2* __restrict__ x = fs.in[f] + row * 256;
+  double2 v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int kk = s + 32 * j;
+    const double2 a = x[kk];
+    v[j] = (INV && !kkept(kk, 256, nzc)) ? make_double2(0.0, 0.0) : a;
+  }
+  fft256w<INV>(v, Z[ll], s, tw);
+  double2* __restrict__ y = fs.out[f] + row * 256;
+  const int mrow = (!INV && row_m) ? row_m[row] : 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int kk = s + 32 * j;
+    double2 a = v[j];
+    if (!INV) {
+      a = cscale(a, 1.0 / 256.0);
+      bool keep = kkept(kk, 256, nzc);
+      if (row_m) {
+        const int k = kval(kk, 256);
+        keep = keep && mrow <= mask_m && (k < 0 ? -k : k) <= mask_k;
+      }
+      if (!keep) a = make_double2(0.0, 0.0);
+    }
+    y[kk] = a;
+  }
+}
+
 Phi256 phi256_geom(const mlg_plan_s* p, bool masked) {
   Phi256 g{};
   g.nr = p->nr;
@@ -617,19 +627,24 @@ mlg_status check(const char* what) {
 
 }  // namespace
 
-mlg_status launch_zfft256(const mlg_plan_s* p, const double* in, double* out, int64_t rows, int dir,
-                          const int32_t* row_m, int mask_m, int mask_k, hipStream_t s) {
+mlg_status launch_zfft256(const mlg_plan_s* p, const double* const* in, double* const* out, int nf, int64_t rows,
+                          int dir, const int32_t* row_m, int mask_m, int mask_k, hipStream_t s) {
+  if (nf < 1 || nf > 6) return fail(MLG_E_ARG, "z transform: 1 to 6 fields per launch");
+  ZFields fs{};
+  for (int i = 0; i < nf; ++i) {
+    fs.in[i] = reinterpret_cast<const double2*>(in[i]);
+    fs.out[i] = reinterpret_cast<double2*>(out[i]);
+  }
   const double2* tw = reinterpret_cast<const double2*>(p->d_tw_z);
-  dim3 grid((unsigned)((rows + ZL - 1) / ZL));
+  const int64_t per = (rows + PL - 1) / PL;
+  dim3 grid((unsigned)(per * nf));
   p->timing.begin("z_fft", s);
   if (dir > 0)
-    zfft256_kernel<true><<<grid, 128, 0, s>>>(tw, reinterpret_cast<const double2*>(in), reinterpret_cast<double2*>(out),
-                                              rows, p->nzc, nullptr, 0, 0);
+    zfft256w_kernel<true><<<grid, VB, 0, s>>>(tw, fs, rows, per, p->nzc, nullptr, 0, 0);
   else
-    zfft256_kernel<false><<<grid, 128, 0, s>>>(tw, reinterpret_cast<const double2*>(in),
-                                               reinterpret_cast<double2*>(out), rows, p->nzc, row_m, mask_m, mask_k);
+    zfft256w_kernel<false><<<grid, VB, 0, s>>>(tw, fs, rows, per, p->nzc, row_m, mask_m, mask_k);
   p->timing.end(s);
-  return check("zfft256_kernel");
+  return check("zfft256w_kernel");
 }
 
 mlg_status launch_phi256_forward(const mlg_plan_s* p, const double* phys, double* mixed, hipStream_t s) {

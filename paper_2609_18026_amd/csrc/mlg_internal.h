@@ -144,6 +144,9 @@ mlg_status launch_phi_vec_rhs(const mlg_plan_s* p, const double* U, double* cons
 // slots outside the chop zeroed, optional dealias mask by row order m), +1 backward.
 mlg_status launch_zfft(const mlg_plan_s* p, const double* in, double* out, int64_t rows, int dir,
                        const int32_t* row_m, int mask_m, int mask_k, hipStream_t s);
+// the same transform of nf fields (1..6) of `rows` lines each, in one launch where the kernel allows
+mlg_status launch_zfft_fields(const mlg_plan_s* p, const double* const* in, double* const* out, int nf, int64_t rows,
+                              int dir, const int32_t* row_m, int mask_m, int mask_k, hipStream_t s);
 // Elliptic solves from the projection sources (C, K', Zhat); taps_src receives C, K, Zhat.
 mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, double* psi_n, double* chi_n,
                              double* scratch, double* taps_src, hipStream_t s);
@@ -178,8 +181,8 @@ const mlg_plan_s* closure_plan(const mlg_closure_s* c);
 void active_columns(const mlg_plan_s* p, int* mmax, int* kmax);
 mlg_status launch_mask_tri(const mlg_plan_s* p, double* spec, hipStream_t s);
 // fft256.hip: register-resident 256-point transforms (used when N_z or N_phi equals 256)
-mlg_status launch_zfft256(const mlg_plan_s* p, const double* in, double* out, int64_t rows, int dir,
-                          const int32_t* row_m, int mask_m, int mask_k, hipStream_t s);
+mlg_status launch_zfft256(const mlg_plan_s* p, const double* const* in, double* const* out, int nf, int64_t rows,
+                          int dir, const int32_t* row_m, int mask_m, int mask_k, hipStream_t s);
 mlg_status launch_phi256_forward(const mlg_plan_s* p, const double* phys, double* mixed, hipStream_t s);
 mlg_status launch_phi256_backward(const mlg_plan_s* p, const double* mixed, double* phys, hipStream_t s);
 mlg_status launch_phi256_scalar(const mlg_plan_s* p, int kind, double gamma, double* mixed, hipStream_t s);
