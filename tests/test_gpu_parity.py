@@ -47,6 +47,7 @@ TRANSFORM_CASES = [
     (130, 30, 6, 2.0, 1.0, 0),          # three row tiles, phi = 2*3*5
     (20, 256, 256, 1.1, 3.0, 0),        # 256-point register FFTs in phi and z
     (70, 256, 8, 0.9, 2.0, 0),          # 256-point phi with generic z
+    (9, 10, 256, 1.0, 4.0, 0),          # 256-point z over a ragged number of rows
 ]
 
 
@@ -184,6 +185,8 @@ TP_CASES = [
     (16, 256, 256, 1.0, 8.6, (0.0, 1.0, 0.0), 1),
     (12, 256, 256, 0.7, 3.0, (0.2, -0.1, 0.3), 0),
     (25, 12, 8, 0.8, 3.0, (0.1, 0.3, -0.2), 1),     # odd N_r: unfolded radial products
+    (13, 256, 6, 1.0, 2.5, (0.1, 0.4, -0.2), 1),    # 256-point phi, 78 lines: a partial last block
+    (7, 16, 256, 0.9, 4.0, (0.0, 0.5, 0.2), 1),     # 256-point z over a ragged number of rows
 ]
 
 
