@@ -625,11 +625,12 @@ __global__ __launch_bounds__(64) void projection_kernel(ProjArgs a) {
   const double s = kap * kap * a.ell2;
   const double inv_ell2 = 1.0 / a.ell2;
   const double ell2 = a.ell2;
-  // loads at a uniform degree index, clamped into the column and zero outside it
+  // loads at a uniform degree index clamped into the column: a value fetched past the end is
+  // consumed only by a step that is range-checked (the tails) or against a zero-padded
+  // coefficient, so it needs no masking
   auto at = [&](const double2* __restrict__ base, int t) -> double2 {
     const int tc = t < 0 ? 0 : (t < cnt ? t : cnt - 1);
-    const double2 v = base[(int64_t)tc * nz];
-    return (t >= 0 && t < cnt) ? v : z0;
+    return base[(int64_t)tc * nz];
   };
   auto lzv = [&](int t, double2 z) -> double2 {
     const double n = (double)(m + t);
@@ -639,6 +640,7 @@ __global__ __launch_bounds__(64) void projection_kernel(ProjArgs a) {
   // ---- pass 1 (ascending): sources C, K = K' + G L Zhat / ell^2; forward sweeps for psi and q
   double2 zpsi1 = z0, zpsi2 = z0, zq1 = z0, zq2 = z0;
   double rq1 = 0, rq2 = 0, dq1 = 0, dq2 = 0, lq1p = 0;
+  // L Zhat at t - 2 .. t + 2; entries past the column multiply zero-padded Gram couplings
   double2 lzm2 = z0, lzm1 = z0, lz0 = lzv(0, at(Zc, 0)), lzp1 = lzv(1, at(Zc, 1)), lzp2 = lzv(2, at(Zc, 2));
   auto glz_at = [&](int t) -> double2 {
     double2 g = cscale(lz0, sg0[t]);
@@ -652,7 +654,7 @@ __global__ __launch_bounds__(64) void projection_kernel(ProjArgs a) {
     lzm1 = lz0;
     lz0 = lzp1;
     lzp1 = lzp2;
-    lzp2 = (t + 3 < cnt) ? lzv(t + 3, z3) : z0;
+    lzp2 = lzv(t + 3, z3);
   };
   auto taps_at = [&](int t, double2 C, double2 K) {
     const int64_t idx = (gbase + t) * nz + kk;
