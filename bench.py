@@ -34,22 +34,32 @@ PAIR = dict(gamma=2 * np.pi, a=0.1, b=1.0, delta=0.01, lz=8.6)
 U_FRAME = (0.0, 1.0, 0.0)
 
 
-# HBM traffic of the dominant kernel from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0,
-# the factors of a plain 256 MiB copy), per launch at 256^3; valid only while the kernel source is the
-# one that was measured.
+# HBM traffic per RHS step of each kernel family from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0,
+# WRITE_SIZE x 1.0: the factors of a plain 256 MiB copy) at 256^3; a record is used only while the
+# kernel source hashes to the one that was measured (profiles/rhs_tp_256cubed_kernels.md).
+_SUMMARY = "profiles/rhs_tp_256cubed_kernels.md"
 MEASURED_TRAFFIC = {
-    "phi_fft": {"bytes": (393626 * 2 + 393216) * 1024, "n": 256,
-                "source": "paper_2609_18026_amd/csrc/fft256.hip",
-                "sha256": "2610109167d8d47ffbd83da7fac63b94823ef4543e1348b30a28cf7055331edb",
-                "summary": "profiles/rhs_tp_256cubed_kernels.md"},
-    "synth_gemm": {"bytes": (295831 * 2 + 786432) * 1024, "n": 256,
+    "synth_gemm": {"bytes": 1195224939, "launches": 1, "n": 256,
                    "source": "paper_2609_18026_amd/csrc/gemm_fold.hip",
-                   "sha256": "034acec060f36ac7fe583b565f3bc2c8b8a90944d1c16a8244c6db6ae0e99e4d",
-                   "summary": "profiles/rhs_tp_256cubed_kernels.md"},
+                   "sha256": "39370186ae76d38232939b61bc09a932dc2788bec316ed2ba7cd426fd1d61058"},
+    "proj_gemm": {"bytes": 434965752, "launches": 1, "n": 256,
+                  "source": "paper_2609_18026_amd/csrc/gemm_fold.hip",
+                  "sha256": "39370186ae76d38232939b61bc09a932dc2788bec316ed2ba7cd426fd1d61058"},
+    "phi_fft": {"bytes": 1208442650, "launches": 1, "n": 256,
+                "source": "paper_2609_18026_amd/csrc/fft256.hip",
+                "sha256": "81b5eac065760fa00828034a90ad3dcab894957323696e38466c8589c4d9ea19"},
+    "z_fft": {"bytes": 1610784768 + 541225856, "launches": 2, "n": 256,
+              "source": "paper_2609_18026_amd/csrc/fft256.hip",
+              "sha256": "81b5eac065760fa00828034a90ad3dcab894957323696e38466c8589c4d9ea19"},
+    "projection": {"bytes": 742007834 + 102792000, "launches": 2, "n": 256,
+                   "source": "paper_2609_18026_amd/csrc/kernels.hip",
+                   "sha256": "ed5ed6064113d22b5ef52ca2f5eeb63fd5f826454ad2e28d5825c29fa564fb17"},
 }
 
 
-def measured_traffic(kernel, n):
+def measured_traffic(kernel, n, per_launch=True):
+    """Measured HBM bytes of a kernel family (per launch, or per RHS step), or None when no record
+    matches the current source."""
     import hashlib
     rec = MEASURED_TRAFFIC.get(kernel)
     if not rec or rec["n"] != n:
@@ -60,7 +70,7 @@ def measured_traffic(kernel, n):
                 return None
     except OSError:
         return None
-    return rec["bytes"]
+    return rec["bytes"] / rec["launches"] if per_launch else rec["bytes"]
 
 
 def log(*a):
@@ -395,6 +405,8 @@ def main():
             ent["frac_fp64_peak"] = round(ent["tflops"] / PEAK_FP64_TFLOPS, 4)
         ent["gbs"] = round(wk["bytes"] / (step_ms / 1e3) / 1e9, 1)
         ent["frac_hbm_peak"] = round(ent["gbs"] / PEAK_HBM_GBS, 4)
+        ent["algorithmic_bytes_per_step"] = wk["bytes"]
+        ent["measured_hbm_bytes_per_step"] = measured_traffic(f, n, per_launch=False)
         per_kernel[f] = ent
     dom = max(families, key=lambda f: kern[f][0])
     d = per_kernel[dom]
