@@ -52,37 +52,44 @@ __global__ __launch_bounds__(256) void radial_gemm_f64(GemmProds prods, const Ge
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
 
+  // raw loads with indices clamped into the operands (no branch around a load); the zeros outside
+  // the operands and the n(n+1) scaling are applied at the LDS store, so the loads of the next
+  // stage stay in flight across this stage's MFMAs.  Loads run only when d.K >= 1 (nk > 0); with
+  // K == 0 (orders m >= N_r^c) the tile writes zeros.
   double ra[4], rb[4];
   auto load_tiles = [&](int k0) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int e = tid + 256 * t;
       const int kk = e >> 6, cc = e & 63;
-      const int k = k0 + kk;
-      const int row = row0 + cc;
-      ra[t] = (k < d.K && row < d.rows) ? A[(int64_t)k * d.lda + row] : 0.0;
-      const int col = col0 + cc;
-      double v = (k < d.K && col < ncol) ? B[(int64_t)k * ncol + col] : 0.0;
-      if (lscale) {
-        const double n = (double)(k + d.m);
-        v *= n * (n + 1.0);
-      }
-      rb[t] = v;
+      const int k = k0 + kk, kc = k < d.K ? k : d.K - 1;
+      const int row = row0 + cc, rc = row < d.rows ? row : d.rows - 1;
+      const int col = col0 + cc, ccl = col < ncol ? col : ncol - 1;
+      ra[t] = A[(int64_t)kc * d.lda + rc];
+      rb[t] = B[(int64_t)kc * ncol + ccl];
     }
   };
-  auto store_tiles = [&](int buf) {
+  auto store_tiles = [&](int buf, int k0) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int e = tid + 256 * t;
       const int kk = e >> 6, cc = e & 63;
-      As[buf][kk][cc] = ra[t];
-      Bs[buf][kk][cc] = rb[t];
+      const int k = k0 + kk;
+      const bool kin = k < d.K;
+      As[buf][kk][cc] = (kin && row0 + cc < d.rows) ? ra[t] : 0.0;
+      double v = rb[t];
+      if (lscale) {
+        const double n = (double)(k + d.m);
+        v *= n * (n + 1.0);
+      }
+      Bs[buf][kk][cc] = (kin && col0 + cc < ncol) ? v : 0.0;
     }
   };
-
   const int nk = (d.K + GT_K - 1) / GT_K;
-  load_tiles(0);
-  store_tiles(0);
+  if (nk > 0) {
+    load_tiles(0);
+    store_tiles(0, 0);
+  }
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
@@ -99,9 +106,7 @@ __global__ __launch_bounds__(256) void radial_gemm_f64(GemmProds prods, const Ge
       acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
       acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
-    if (kt + 1 < nk) {
-      store_tiles(buf ^ 1);
-    }
+    if (kt + 1 < nk) store_tiles(buf ^ 1, (kt + 1) * GT_K);
     __syncthreads();
   }
 #pragma unroll
