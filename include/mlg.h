@@ -169,6 +169,19 @@ mlg_status mlg_step_abcn(mlg_plan plan, const void* s, const void* A_now, const 
  * The radial products use the plan's precision. */
 mlg_status mlg_synthesize(mlg_plan plan, const void* psi, const void* chi, void* uw, void* ws, void* stream);
 
+/* Axial modal kinetic energy of a toroidal-poloidal pair: the diagnostic from which Sec. 5.3
+ * (Results and validation) reads the growth rate of the Crow instability, alpha =
+ * (pi b^2 / Gamma) d ln E_1 / dt.  For every axial FFT slot kk (signed k = kk for 2 kk < N_z,
+ * else kk - N_z):
+ *   energy[kk] = (L_z / 2) int_0^{2 pi} int_0^inf |u_k|^2 r dr dphi,
+ * u_k the axial Fourier coefficient of the velocity of (psi, chi) (Eq. tp), the area integral
+ * taken by the Gauss-Legendre rule in the mapped variable (r dr = ell^2/(1-x)^2 dx) and by
+ * Parseval in phi; the sum over kk is the kinetic energy of one axial period.  psi, chi: device,
+ * packed triangular spectra; energy: device array of N_z doubles (written); ws: the plan's
+ * workspace.  FP64 plans only (MLG_E_UNSUPPORTED otherwise); null buffers: MLG_E_ARG.
+ * Partial sums are added in a fixed order, so the result is deterministic. */
+mlg_status mlg_tp_energy(mlg_plan plan, const void* psi, const void* chi, double* energy, void* ws, void* stream);
+
 /* Optional per-kernel timing, for benchmarks and profiling (not needed for computation).
  * While enabled, every kernel launch of the plan is bracketed by two HIP events recorded on
  * the launch's stream.  mlg_timing_read waits for the recorded events, returns the summed

@@ -42,7 +42,8 @@ class mlg_layout(ctypes.Structure):
 _lib = None
 
 EXPORTS = ["mlg_plan_create", "mlg_plan_destroy", "mlg_plan_query", "mlg_plan_nodes", "mlg_forward",
-           "mlg_backward", "mlg_rhs_scalar", "mlg_rhs_tp", "mlg_synthesize", "mlg_timing_enable", "mlg_timing_read",
+           "mlg_backward", "mlg_rhs_scalar", "mlg_rhs_tp", "mlg_synthesize", "mlg_tp_energy", "mlg_timing_enable",
+           "mlg_timing_read",
            "mlg_batch_create", "mlg_batch_destroy", "mlg_batch_query", "mlg_batch_rhs_scalar", "mlg_batch_set_config",
            "mlg_batch_get_config", "mlg_batch_autotune", "mlg_step_setup", "mlg_step_febe", "mlg_step_abcn",
            "mlg_truncate", "mlg_tp_advance", "mlg_closure_param_count", "mlg_closure_create", "mlg_closure_destroy",
@@ -85,6 +86,7 @@ def lib() -> ctypes.CDLL:
     L.mlg_rhs_scalar.argtypes = [vp, i32, f64, vp, vp, vp, vp]
     L.mlg_rhs_tp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.mlg_synthesize.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.mlg_tp_energy.argtypes = [vp, vp, vp, vp, vp, vp]
     L.mlg_timing_enable.argtypes = [vp, i32]
     L.mlg_timing_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(f64), ctypes.POINTER(ctypes.c_int64)]
     L.mlg_batch_create.argtypes = [i32, ctypes.POINTER(mlg_grid), i32, i32, ctypes.POINTER(vp)]
@@ -193,6 +195,10 @@ def mlg_step_abcn(plan: int, s: int, A_now: int, A_prev: int, out: int, stream: 
 
 def mlg_synthesize(plan: int, psi: int, chi: int, uw: int, ws: int, stream: int = 0) -> None:
     _check(lib().mlg_synthesize(plan, psi, chi, uw, ws, stream))
+
+
+def mlg_tp_energy(plan: int, psi: int, chi: int, energy: int, ws: int, stream: int = 0) -> None:
+    _check(lib().mlg_tp_energy(plan, psi, chi, energy, ws, stream))
 
 
 def mlg_timing_enable(plan: int, enable: bool) -> None:
@@ -369,6 +375,14 @@ class Plan:
     def synthesize(self, psi, chi, uw):
         """uw: float64 tensor of 6 * phys_elems (u_r, u_phi, u_z, w_r, w_phi, w_z)."""
         mlg_synthesize(self.handle, psi.data_ptr(), chi.data_ptr(), uw.data_ptr(), self.ws.data_ptr(), self._stream())
+
+    def energy(self, psi, chi, out=None):
+        """Axial modal kinetic energy per FFT slot (float64 device tensor of N_z entries)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.nz, dtype=torch.float64, device=f"cuda:{self.device}")
+        mlg_tp_energy(self.handle, psi.data_ptr(), chi.data_ptr(), out.data_ptr(), self.ws.data_ptr(), self._stream())
+        return out
 
     def step_setup(self, nu, nu_h=0.0, p=8, dt=1e-2):
         mlg_step_setup(self.handle, nu, nu_h, p, dt)

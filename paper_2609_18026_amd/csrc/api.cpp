@@ -372,6 +372,18 @@ mlg_status mlg_synthesize(mlg_plan p, const void* psi, const void* chi, void* uw
   return MLG_OK;
 }
 
+mlg_status mlg_tp_energy(mlg_plan p, const void* psi, const void* chi, double* energy, void* ws, void* stream) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!psi || !chi || !energy || !ws) return fail(MLG_E_ARG, "null buffer");
+  if (p->prec != MLG_FP64) return fail(MLG_E_UNSUPPORTED, "mlg_tp_energy: FP64 plans only");
+  DeviceGuard guard(p->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Ws w = partition(p, ws);
+  if (mlg_status st = launch_synth_gemm(p, static_cast<const double*>(psi), static_cast<const double*>(chi), w.X, s))
+    return st;
+  return launch_energy(p, w.X, energy, w.T[0], s);
+}
+
 mlg_status mlg_timing_enable(mlg_plan p, int enable) {
   if (mlg_status st = check_plan(p)) return st;
   p->timing.enabled = enable != 0;

@@ -836,6 +836,52 @@ __global__ __launch_bounds__(64) void projection_kernel(ProjArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- axial modal energy
+// With the velocity harmonics f_m(i, kk) in the mixed layout [m][i][kk], a real field is
+// Re f_0 + 2 Re sum_{m>=1} f_m exp(i m phi) (the azimuthal Nyquist order is not synthesised), so
+// its axial coefficient at slot kk is f_0,kk + sum_{m>=1} (f_m,kk e^{i m phi} + conj(f_m,-kk) e^{-i m phi})
+// and, by Parseval in phi,
+//   energy[kk] = (L_z/2) 2 pi sum_i W_i (|f_0,kk|^2 + sum_{m>=1} (|f_m,kk|^2 + |f_m,-kk|^2)),
+// summed over u_r, u_phi, u_z, with W_i = w_i ell^2/(1-x_i)^2.  Stage 1: block b sums the rows
+// [b EN_ROWS, (b+1) EN_ROWS) of every axial slot into part[b][kk] (lanes over kk, coalesced);
+// stage 2 adds the parts in block order.
+constexpr int EN_ROWS = 64;
+
+__global__ __launch_bounds__(256) void energy_part_kernel(const double2* __restrict__ ur,
+                                                          const double2* __restrict__ up,
+                                                          const double2* __restrict__ uz,
+                                                          const double* __restrict__ area, int nr, int nz,
+                                                          int nphi, int64_t rows, double* __restrict__ part) {
+  const int64_t r0 = (int64_t)blockIdx.x * EN_ROWS;
+  const int64_t r1 = r0 + EN_ROWS < rows ? r0 + EN_ROWS : rows;
+  for (int kk = threadIdx.x; kk < nz; kk += blockDim.x) {
+    const int kn = kk == 0 ? 0 : nz - kk;  // slot of -k
+    double acc = 0.0;
+    for (int64_t row = r0; row < r1; ++row) {
+      const int m = (int)(row / nr), i = (int)(row - (int64_t)m * nr);
+      if (2 * m == nphi) continue;  // the Nyquist order carries no physical field
+      const int64_t o = row * nz;
+      const double2 a = ur[o + kk], b = up[o + kk], d = uz[o + kk];
+      double e = a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y + d.x * d.x + d.y * d.y;
+      if (m > 0) {
+        const double2 a2 = ur[o + kn], b2 = up[o + kn], d2 = uz[o + kn];
+        e += a2.x * a2.x + a2.y * a2.y + b2.x * b2.x + b2.y * b2.y + d2.x * d2.x + d2.y * d2.y;
+      }
+      acc += area[i] * e;
+    }
+    part[(int64_t)blockIdx.x * nz + kk] = acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void energy_sum_kernel(const double* __restrict__ part, int nparts, int nz,
+                                                         double scale, double* __restrict__ energy) {
+  const int kk = blockIdx.x * blockDim.x + threadIdx.x;
+  if (kk >= nz) return;
+  double acc = 0.0;
+  for (int b = 0; b < nparts; ++b) acc += part[(int64_t)b * nz + kk];
+  energy[kk] = scale * acc;
+}
+
 // Zero every entry of the packed arrays whose (m, k) column is not active.
 __global__ void zero_inactive_kernel(double2* __restrict__ x0, double2* __restrict__ x1, double2* __restrict__ x2,
                                      double2* __restrict__ x3, double2* __restrict__ x4,
@@ -1071,6 +1117,22 @@ mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, dou
     p->timing.end(s);
   }
   return check_launch("projection_kernel");
+}
+
+mlg_status launch_energy(const mlg_plan_s* p, double* const* u3, double* energy, double* scratch, hipStream_t s) {
+  const int64_t rows = (int64_t)p->M * p->nr;
+  const int nparts = (int)((rows + EN_ROWS - 1) / EN_ROWS);
+  if (rows <= 0) return fail(MLG_E_ARG, "energy: empty plan");
+  // the scratch (a triangular workspace array, 2 tri_elems doubles) holds nparts * nz partial sums
+  if ((int64_t)nparts * p->nz > 2 * (int64_t)p->tri_elems) return fail(MLG_E_UNSUPPORTED, "energy: scratch too small");
+  const double scale = 0.5 * p->g.lz * 2.0 * M_PI;
+  energy_part_kernel<<<nparts, 256, 0, s>>>(reinterpret_cast<const double2*>(u3[0]),
+                                            reinterpret_cast<const double2*>(u3[1]),
+                                            reinterpret_cast<const double2*>(u3[2]), p->d_node + 3 * p->nr, p->nr,
+                                            p->nz, p->nphi, rows, scratch);
+  if (mlg_status st = check_launch("energy_part_kernel")) return st;
+  energy_sum_kernel<<<(p->nz + 255) / 256, 256, 0, s>>>(scratch, nparts, p->nz, scale, energy);
+  return check_launch("energy_sum_kernel");
 }
 
 mlg_status launch_mask_tri(const mlg_plan_s* p, double* spec, hipStream_t s) {

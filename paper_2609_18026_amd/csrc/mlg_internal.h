@@ -82,7 +82,7 @@ struct mlg_plan_s {
   double* d_Pf = nullptr;   // forward w*Pbar, per m [i][n-m]
   double* d_Tb = nullptr;   // backward Tbar = (1-x^2) dPbar/dx, per m [n-m][i]
   double* d_Qf = nullptr;   // forward w*(Tbar - 2(1+x)Pbar), per m [i][n-m]
-  double* d_node = nullptr; // nodal vectors: rinv[nr], q[nr], opx[nr]
+  double* d_node = nullptr; // nodal vectors: rinv[nr], q[nr], opx[nr], area weight w ell^2/(1-x)^2 [nr]
   double* d_tw_phi = nullptr;  // exp(-2 pi i t / N_phi), interleaved
   double* d_tw_z = nullptr;    // exp(-2 pi i t / N_z), interleaved
   int32_t* d_row_m = nullptr;  // azimuthal order of every triangular row
@@ -145,6 +145,8 @@ mlg_status launch_phi_vec_rhs(const mlg_plan_s* p, const double* U, double* cons
 mlg_status launch_zfft(const mlg_plan_s* p, const double* in, double* out, int64_t rows, int dir,
                        const int32_t* row_m, int mask_m, int mask_k, hipStream_t s);
 // the same transform of nf fields (1..6) of `rows` lines each, in one launch where the kernel allows
+// axial modal kinetic energy from the velocity harmonics u_r, u_phi, u_z (mixed layout)
+mlg_status launch_energy(const mlg_plan_s* p, double* const* u3, double* energy, double* scratch, hipStream_t s);
 mlg_status launch_zfft_fields(const mlg_plan_s* p, const double* const* in, double* const* out, int nf, int64_t rows,
                               int dir, const int32_t* row_m, int mask_m, int mask_k, hipStream_t s);
 // Elliptic solves from the projection sources (C, K', Zhat); taps_src receives C, K, Zhat.

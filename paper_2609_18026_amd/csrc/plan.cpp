@@ -339,11 +339,14 @@ mlg_status build_plan(mlg_plan_s* p) {
     gram[8 * p->ngram + k] = u2[k];
   }
   // ---------------- nodal vectors, twiddles, row orders, GEMM descriptors
-  std::vector<double> node(3 * nr);
+  std::vector<double> node(4 * nr);
   for (int i = 0; i < nr; ++i) {
     node[i] = p->rinv[i];
     node[nr + i] = p->q[i];
     node[2 * nr + i] = p->one_plus_x[i];
+    // area weight: r dr = ell^2 / (1 - x)^2 dx, times the Gauss-Legendre weight
+    const ld omx = 2 * sinl(th[i] / 2) * sinl(th[i] / 2);
+    node[3 * nr + i] = (double)(wl[i] * (ld)p->g.ell * (ld)p->g.ell / (omx * omx));
   }
   auto twiddles = [](int n) {
     std::vector<double> tw(2 * n);
