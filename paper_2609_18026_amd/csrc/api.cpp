@@ -157,6 +157,19 @@ mlg_status mlg_plan_nodes(mlg_plan p, double* x, double* w, double* r) {
   return MLG_OK;
 }
 
+// Radial products of one scalar field: folded over the node symmetry for even N_r (unless the plan
+// was created with MLG_RADIAL_FOLD=0), the generic batched GEMM otherwise.
+static mlg_status scalar_radial(const mlg_plan_s* p, int dir, const double* B, double* C, hipStream_t s) {
+  if (p->use_fold && p->nr % 2 == 0) return launch_scalar_fold(p, dir, B, C, s);
+  GemmProds pr{};
+  pr.nprod = 1;
+  pr.A[0] = dir > 0 ? p->d_Pb : p->d_Pf;
+  pr.B[0] = B;
+  pr.C[0] = C;
+  return dir > 0 ? launch_gemm(p, pr, p->d_desc_bwd, p->max_rows_bwd, 2 * p->nz, s)
+                 : launch_gemm(p, pr, p->d_desc_fwd, p->max_rows_fwd, 2 * p->nz, s);
+}
+
 mlg_status mlg_forward(mlg_plan p, const void* phys, void* spec, void* ws, void* stream) {
   if (mlg_status st = check_plan(p)) return st;
   if (!phys || !spec || !ws) return fail(MLG_E_ARG, "null buffer");
@@ -165,12 +178,7 @@ mlg_status mlg_forward(mlg_plan p, const void* phys, void* spec, void* ws, void*
   Ws w = partition(p, ws);
   mlg_status st;
   if ((st = launch_phi_forward(p, static_cast<const double*>(phys), w.X[0], s))) return st;
-  GemmProds pr{};
-  pr.nprod = 1;
-  pr.A[0] = p->d_Pf;
-  pr.B[0] = w.X[0];
-  pr.C[0] = static_cast<double*>(spec);
-  if ((st = launch_gemm(p, pr, p->d_desc_fwd, p->max_rows_fwd, 2 * p->nz, s))) return st;
+  if ((st = scalar_radial(p, -1, w.X[0], static_cast<double*>(spec), s))) return st;
   return launch_zfft(p, static_cast<double*>(spec), static_cast<double*>(spec), p->tau, -1, nullptr, 0, 0, s);
 }
 
@@ -182,12 +190,7 @@ mlg_status mlg_backward(mlg_plan p, const void* spec, void* phys, void* ws, void
   Ws w = partition(p, ws);
   mlg_status st;
   if ((st = launch_zfft(p, static_cast<const double*>(spec), w.T[0], p->tau, +1, nullptr, 0, 0, s))) return st;
-  GemmProds pr{};
-  pr.nprod = 1;
-  pr.A[0] = p->d_Pb;
-  pr.B[0] = w.T[0];
-  pr.C[0] = w.X[0];
-  if ((st = launch_gemm(p, pr, p->d_desc_bwd, p->max_rows_bwd, 2 * p->nz, s))) return st;
+  if ((st = scalar_radial(p, +1, w.T[0], w.X[0], s))) return st;
   return launch_phi_backward(p, w.X[0], static_cast<double*>(phys), s);
 }
 
@@ -203,17 +206,9 @@ mlg_status mlg_rhs_scalar(mlg_plan p, int kind, double gamma, const void* spec_u
   Ws w = partition(p, ws);
   mlg_status st;
   if ((st = launch_zfft(p, static_cast<const double*>(spec_u), w.T[0], p->tau, +1, nullptr, 0, 0, s))) return st;
-  GemmProds pr{};
-  pr.nprod = 1;
-  pr.A[0] = p->d_Pb;
-  pr.B[0] = w.T[0];
-  pr.C[0] = w.X[0];
-  if ((st = launch_gemm(p, pr, p->d_desc_bwd, p->max_rows_bwd, 2 * p->nz, s))) return st;
+  if ((st = scalar_radial(p, +1, w.T[0], w.X[0], s))) return st;
   if ((st = launch_phi_scalar_rhs(p, kind, gamma, w.X[0], s))) return st;
-  pr.A[0] = p->d_Pf;
-  pr.B[0] = w.X[0];
-  pr.C[0] = static_cast<double*>(spec_out);
-  if ((st = launch_gemm(p, pr, p->d_desc_fwd, p->max_rows_fwd, 2 * p->nz, s))) return st;
+  if ((st = scalar_radial(p, -1, w.X[0], static_cast<double*>(spec_out), s))) return st;
   const bool mask = p->g.dealias != 0;
   return launch_zfft(p, static_cast<double*>(spec_out), static_cast<double*>(spec_out), p->tau, -1,
                      mask ? p->d_row_m : nullptr, p->dealias_m, p->dealias_k, s);

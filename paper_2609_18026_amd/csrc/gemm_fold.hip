@@ -335,6 +335,198 @@ __global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- scalar transforms, folded
+// The radial products of one scalar field (real columns: re and im of each axial slot).  Tiles of 64
+// rows x 64 real columns; wavefront w takes 16 rows and all four 16-column MFMA blocks, with an even
+// and an odd accumulator per block.  Loads are issued with clamped indices and zeros applied at the
+// LDS store (see synth_fold_kernel).
+constexpr int SC_N = 64;  // real columns per block
+constexpr int SC_P = 8;   // pairs (backward) or half nodes (forward) per LDS stage
+
+struct ScalarFoldArgs {
+  const double* A;   // backward: Pbar [m][n-m][i]; forward: w Pbar [m][i][n-m]
+  const double* B;   // backward: spectral rows [tau][ncol]; forward: harmonics [m][i][ncol]
+  double* C;         // backward: harmonics [m][i][ncol]; forward: spectral rows [tau][ncol]
+  const int64_t* off;
+  int nr, nrc, ncol;
+  int gx, gy, gz;
+};
+
+// backward: f(i) = E(i) + O(i), f(N-1-i) = E(i) - O(i), E / O over even / odd n - m, i < N/2
+__global__ __launch_bounds__(256) void scal_bwd_fold_kernel(ScalarFoldArgs a) {
+  Tile3 tl;
+  if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
+  const int m = tl.z;
+  const int half = a.nr / 2, nr = a.nr, ncol = a.ncol;
+  const int row0 = tl.y * TM, col0 = tl.x * SC_N;
+  if (row0 >= half || col0 >= ncol) return;
+  const int K = a.nrc > m ? a.nrc - m : 0;
+  const int KP = (K + 1) / 2;
+  const double* __restrict__ A = a.A + a.off[m] * nr;
+  const double* __restrict__ B = a.B + a.off[m] * ncol;
+  double* __restrict__ C = a.C + (int64_t)m * nr * ncol;
+  __shared__ double As[2][2][SC_P][TM];    // [buf][parity][pair][half node]
+  __shared__ double Bs[2][2][SC_P][SC_N];  // [buf][parity][pair][column]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, cl = lane & 15;
+  double4_t acc[2][4];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[q][c] = double4_t{0.0, 0.0, 0.0, 0.0};
+  double ra[4], rb[4];
+  auto load = [&](int p0) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + 256 * t;  // [parity][pair][64]
+      const int par = e >> 9, kr = (e >> 6) & 7, cc = e & 63;
+      const int j = 2 * (p0 + kr) + par, jc = j < K ? j : K - 1;
+      const int i = row0 + cc, ic = i < half ? i : half - 1;
+      const int col = col0 + cc, cc2 = col < ncol ? col : ncol - 1;
+      ra[t] = A[(int64_t)jc * nr + ic];
+      rb[t] = B[(int64_t)jc * ncol + cc2];
+    }
+  };
+  auto store = [&](int buf, int p0) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + 256 * t;
+      const int par = e >> 9, kr = (e >> 6) & 7, cc = e & 63;
+      const bool jin = 2 * (p0 + kr) + par < K;
+      As[buf][par][kr][cc] = (jin && row0 + cc < half) ? ra[t] : 0.0;
+      Bs[buf][par][kr][cc] = (jin && col0 + cc < ncol) ? rb[t] : 0.0;
+    }
+  };
+  const int nk = (KP + SC_P - 1) / SC_P;
+  if (nk > 0) {
+    load(0);
+    store(0, 0);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * SC_P);
+#pragma unroll
+    for (int ks = 0; ks < SC_P; ks += 4) {
+      const int kr = ks + (lane >> 4);
+#pragma unroll
+      for (int par = 0; par < 2; ++par) {
+        const double av = As[buf][par][kr][wave * 16 + cl];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[par][c] = MFMA(av, Bs[buf][par][kr][c * 16 + cl], acc[par][c]);
+      }
+    }
+    if (kt + 1 < nk) store(buf ^ 1, (kt + 1) * SC_P);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int col = col0 + c * 16 + cl;
+    if (col >= ncol) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = row0 + wave * 16 + (lane >> 4) + 4 * v;
+      if (i >= half) continue;
+      const double e = acc[0][c][v], o = acc[1][c][v];
+      C[(int64_t)i * ncol + col] = e + o;
+      C[(int64_t)(nr - 1 - i) * ncol + col] = e - o;
+    }
+  }
+}
+
+// forward: even n - m rows contract with X_i + X_{N-1-i}, odd rows with the difference, i < N/2
+__global__ __launch_bounds__(256) void scal_fwd_fold_kernel(ScalarFoldArgs a) {
+  Tile3 tl;
+  if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
+  const int m = tl.z;
+  const int K = a.nrc > m ? a.nrc - m : 0;
+  const int KP = (K + 1) / 2;
+  const int half = a.nr / 2, nr = a.nr, ncol = a.ncol;
+  const int row0 = tl.y * TM, col0 = tl.x * SC_N;  // row0: pair index
+  if (row0 >= KP || col0 >= ncol) return;
+  const double* __restrict__ A = a.A + a.off[m] * nr;      // [i][n-m], row length K
+  const double* __restrict__ B = a.B + (int64_t)m * nr * ncol;
+  double* __restrict__ C = a.C + a.off[m] * ncol;
+  __shared__ double As[2][2][SC_P][TM];    // [buf][parity][half node][pair]
+  __shared__ double Bs[2][2][SC_P][SC_N];  // [buf][sum, difference][half node][column]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, cl = lane & 15;
+  double4_t acc[2][4];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[q][c] = double4_t{0.0, 0.0, 0.0, 0.0};
+  double ra[4], rx[2], ry[2];
+  auto load = [&](int i0) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + 256 * t;  // [parity][half node][pair]
+      const int par = e >> 9, kr = (e >> 6) & 7, rr = e & 63;
+      const int i = i0 + kr, ic = i < half ? i : half - 1;
+      const int j = 2 * (row0 + rr) + par, jc = j < K ? j : K - 1;
+      ra[t] = A[(int64_t)ic * K + jc];
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int e = tid + 256 * t;  // [half node][column]
+      const int kr = e >> 6, cc = e & 63;
+      const int i = i0 + kr, ic = i < half ? i : half - 1;
+      const int col = col0 + cc, cc2 = col < ncol ? col : ncol - 1;
+      rx[t] = B[(int64_t)ic * ncol + cc2];
+      ry[t] = B[(int64_t)(nr - 1 - ic) * ncol + cc2];
+    }
+  };
+  auto store = [&](int buf, int i0) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + 256 * t;
+      const int par = e >> 9, kr = (e >> 6) & 7, rr = e & 63;
+      const bool ok = i0 + kr < half && 2 * (row0 + rr) + par < K;
+      As[buf][par][kr][rr] = ok ? ra[t] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int e = tid + 256 * t;
+      const int kr = e >> 6, cc = e & 63;
+      const bool ok = i0 + kr < half && col0 + cc < ncol;
+      Bs[buf][0][kr][cc] = ok ? rx[t] + ry[t] : 0.0;
+      Bs[buf][1][kr][cc] = ok ? rx[t] - ry[t] : 0.0;
+    }
+  };
+  const int nk = (half + SC_P - 1) / SC_P;
+  load(0);
+  store(0, 0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * SC_P);
+#pragma unroll
+    for (int ks = 0; ks < SC_P; ks += 4) {
+      const int kr = ks + (lane >> 4);
+#pragma unroll
+      for (int par = 0; par < 2; ++par) {
+        const double av = As[buf][par][kr][wave * 16 + cl];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[par][c] = MFMA(av, Bs[buf][par][kr][c * 16 + cl], acc[par][c]);
+      }
+    }
+    if (kt + 1 < nk) store(buf ^ 1, (kt + 1) * SC_P);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int col = col0 + c * 16 + cl;
+    if (col >= ncol) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int pr = row0 + wave * 16 + (lane >> 4) + 4 * v;
+#pragma unroll
+      for (int par = 0; par < 2; ++par) {
+        const int j = 2 * pr + par;
+        if (j < K) C[(int64_t)j * ncol + col] = acc[par][c][v];
+      }
+    }
+  }
+}
+
 mlg_status check(const char* what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(MLG_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -391,6 +583,27 @@ mlg_status launch_proj_fold(const mlg_plan_s* p, double* const* in3, double* con
   proj_fold_kernel<<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
   p->timing.end(s);
   return check("proj_fold_kernel");
+}
+
+mlg_status launch_scalar_fold(const mlg_plan_s* p, int dir, const double* B, double* C, hipStream_t s) {
+  ScalarFoldArgs a{};
+  a.A = dir > 0 ? p->d_Pb : p->d_Pf;
+  a.B = B;
+  a.C = C;
+  a.off = p->d_goff;
+  a.nr = p->nr;
+  a.nrc = p->nrc;
+  a.ncol = 2 * p->nz;
+  a.gx = (a.ncol + SC_N - 1) / SC_N;
+  a.gy = dir > 0 ? (p->nr / 2 + TM - 1) / TM : ((p->nrc + 1) / 2 + TM - 1) / TM;
+  a.gz = p->M;
+  p->timing.begin("radial_gemm", s);
+  if (dir > 0)
+    scal_bwd_fold_kernel<<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
+  else
+    scal_fwd_fold_kernel<<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
+  p->timing.end(s);
+  return check(dir > 0 ? "scal_bwd_fold_kernel" : "scal_fwd_fold_kernel");
 }
 
 }  // namespace mlg

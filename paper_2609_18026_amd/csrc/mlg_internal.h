@@ -161,6 +161,9 @@ mlg_status launch_proj_gemm(const mlg_plan_s* p, double* const* in3, double* con
 // gemm_fold.hip: the same two products folded over the node symmetry x -> -x (even N_r)
 mlg_status launch_synth_fold(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,
                              hipStream_t s);
+// parity-folded radial products of one scalar field: dir > 0 backward (spectral rows -> harmonics
+// at the nodes), dir < 0 forward; even N_r only
+mlg_status launch_scalar_fold(const mlg_plan_s* p, int dir, const double* B, double* C, hipStream_t s);
 mlg_status launch_proj_fold(const mlg_plan_s* p, double* const* in3, double* const* out3, int mmax, int kmax,
                             hipStream_t s);
 // gemm_split.hip: the same two products with split-bfloat16 operands and FP32 accumulation
