@@ -1,13 +1,15 @@
-// 256-point FFTs for gfx950 held in registers: 16 threads per line, each owning the 16 samples
-// x[s + 16 j] (s = thread index within the line, j = 0..15).  A four-step 16 x 16 factorisation
-// does a 16-point DFT in registers, a twiddle, one LDS exchange, and a second 16-point DFT,
-// which leaves X[s + 16 k] in the same registers: input and output share one distribution, so
-// inverse -> pointwise -> forward chains need no reshuffle.  LDS rows are padded to 17 so that
-// both exchange patterns are free of bank conflicts.
+// 256-point FFTs for gfx950 held in registers: a line is spread over the 32 lanes of half a
+// wavefront, lane s owning the 8 samples x[s + 32 j].  The DFT factors as 8 x 8 x 4 (fft256w):
+// a radix-8 pass in registers, a twiddle, an LDS exchange inside the wavefront, a second radix-8
+// pass, a twiddle, an exchange and two radix-4 DFTs per lane, which leaves X[s + 32 k] in the same
+// registers: input and output share one distribution, so inverse -> pointwise -> forward chains
+// need no reshuffle.
 //
-// Kernels: z transforms over contiguous lines (global loads go straight to registers, 16
-// consecutive samples per 16 lanes) and the azimuthal stages (harmonics of 8 lines are gathered
-// through LDS so that every global access covers 8 consecutive lines = 128 bytes).
+// Kernels: the z transforms over contiguous lines (loads and stores straight from registers, 512
+// contiguous bytes per 32 lanes, up to six fields per launch), and the azimuthal stages (the
+// harmonics of 8 lines are gathered through LDS so that every global access covers 8 consecutive
+// lines = 128 bytes): the scalar forward / backward transforms, the scalar nonlinear terms and the
+// fused vector stage of the toroidal-poloidal RHS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,21 +23,15 @@ namespace {
 
 using namespace ::mlg::dev;
 
-constexpr double kC1 = 0.92387953251128674;   // cos(pi/8)
-constexpr double kS1 = 0.38268343236508976;   // sin(pi/8)
 constexpr double kR2 = 0.70710678118654752;   // sqrt(2)/2
 
-// multiply by w16^j, w16 = exp(-+ 2 pi i / 16) (forward: minus), for the j used by dft16
+// multiply by w8^J, w8 = exp(-+ 2 pi i / 8) (forward: minus), J = 1, 2, 3
 template <bool INV, int J>
-__device__ __forceinline__ double2 tw16(double2 a) {
+__device__ __forceinline__ double2 tw8(double2 a) {
   constexpr double sg = INV ? 1.0 : -1.0;
-  if constexpr (J == 0) return a;
-  else if constexpr (J == 1) return cmul(a, make_double2(kC1, sg * kS1));
-  else if constexpr (J == 2) return cmul(a, make_double2(kR2, sg * kR2));
-  else if constexpr (J == 3) return cmul(a, make_double2(kS1, sg * kC1));
-  else if constexpr (J == 4) return cmul_mi(a, INV);
-  else if constexpr (J == 6) return cmul(a, make_double2(-kR2, sg * kR2));
-  else return cmul(a, make_double2(-kC1, -sg * kS1));  // J == 9
+  if constexpr (J == 1) return cmul(a, make_double2(kR2, sg * kR2));
+  else if constexpr (J == 2) return cmul_mi(a, INV);
+  else return cmul(a, make_double2(-kR2, sg * kR2));  // J == 3
 }
 
 template <bool INV>
@@ -46,54 +42,6 @@ __device__ __forceinline__ void dft4(double2& a, double2& b, double2& c, double2
   b = cadd(t1, t3);
   c = csub(t0, t2);
   d = csub(t1, t3);
-}
-
-// In-register 16-point DFT: v[n] -> V[k] = sum_n v[n] w16^(n k).
-template <bool INV>
-__device__ __forceinline__ void dft16(double2 (&v)[16]) {
-  // n = n1 + 4 n2: DFT4 over n2 for each n1 -> Y[n1][k2] at v[n1 + 4 k2]
-#pragma unroll
-  for (int n1 = 0; n1 < 4; ++n1) dft4<INV>(v[n1], v[n1 + 4], v[n1 + 8], v[n1 + 12]);
-  // twiddles w16^(n1 k2)
-  v[1 + 4 * 1] = tw16<INV, 1>(v[1 + 4 * 1]);
-  v[1 + 4 * 2] = tw16<INV, 2>(v[1 + 4 * 2]);
-  v[1 + 4 * 3] = tw16<INV, 3>(v[1 + 4 * 3]);
-  v[2 + 4 * 1] = tw16<INV, 2>(v[2 + 4 * 1]);
-  v[2 + 4 * 2] = tw16<INV, 4>(v[2 + 4 * 2]);
-  v[2 + 4 * 3] = tw16<INV, 6>(v[2 + 4 * 3]);
-  v[3 + 4 * 1] = tw16<INV, 3>(v[3 + 4 * 1]);
-  v[3 + 4 * 2] = tw16<INV, 6>(v[3 + 4 * 2]);
-  v[3 + 4 * 3] = tw16<INV, 9>(v[3 + 4 * 3]);
-  // DFT4 over n1 for each k2 -> X[k2 + 4 k1] at v[4 k2 + k1]
-#pragma unroll
-  for (int k2 = 0; k2 < 4; ++k2) dft4<INV>(v[4 * k2], v[4 * k2 + 1], v[4 * k2 + 2], v[4 * k2 + 3]);
-  double2 o[16];
-#pragma unroll
-  for (int k2 = 0; k2 < 4; ++k2)
-#pragma unroll
-    for (int k1 = 0; k1 < 4; ++k1) o[k2 + 4 * k1] = v[4 * k2 + k1];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) v[k] = o[k];
-}
-
-// 256-point DFT of one line spread over 16 threads.  On entry v[j] = x[s + 16 j]; on exit
-// v[k] = X[s + 16 k] (unscaled).  Z is this line's LDS row block (16 x 17 complex).  Contains
-// one barrier: all threads of the block must call it.
-template <bool INV>
-__device__ __forceinline__ void fft256(double2 (&v)[16], double2* Z, int s, const double2* __restrict__ tw) {
-  dft16<INV>(v);  // over j: v[k2] = Y[s][k2]
-#pragma unroll
-  for (int k2 = 1; k2 < 16; ++k2) {
-    double2 w = tw[s * k2];
-    if (INV) w = cconj(w);
-    v[k2] = cmul(v[k2], w);
-  }
-#pragma unroll
-  for (int k2 = 0; k2 < 16; ++k2) Z[s + 17 * k2] = v[k2];
-  __syncthreads();
-#pragma unroll
-  for (int n1 = 0; n1 < 16; ++n1) v[n1] = Z[n1 + 17 * s];
-  dft16<INV>(v);
 }
 
 __device__ __forceinline__ int kval(int kk, int nz) { return (2 * kk < nz) ? kk : kk - nz; }
@@ -116,178 +64,6 @@ __device__ __forceinline__ int64_t phys_off(const Phi256& g, int64_t q) {
   const int64_t i = q / g.nz;
   const int64_t l = q - i * g.nz;
   return (l * g.nr + i) * 256;
-}
-
-// Gather the harmonics of fields (fa, fb) for the block's lines into Z as the Hermitian
-// spectrum of z = a + i b (orders m < M, the rest zero).  Ends with a barrier.
-__device__ __forceinline__ void gather_pair(double2 (*Z)[16 * 17], const Phi256& g, int64_t q0,
-                                            const double2* __restrict__ fa, const double2* __restrict__ fb) {
-  const int t = threadIdx.x;
-  for (int e = t; e < PL * 256; e += 128) {
-    const int ll = e & (PL - 1), p = e >> 3;  // zero-fill all 256 positions
-    Z[ll][(p & 15) + 17 * (p >> 4)] = make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  const int mmax = g.M < 128 ? g.M : 128;
-  for (int e = t; e < PL * mmax; e += 128) {
-    const int ll = e & (PL - 1), m = e >> 3;
-    const int64_t q = q0 + ll;
-    if (q >= g.nlines) continue;
-    const double2 a = fa[(int64_t)m * g.nlines + q];
-    const double2 b = fb ? fb[(int64_t)m * g.nlines + q] : make_double2(0.0, 0.0);
-    if (m == 0) {
-      Z[ll][0] = make_double2(a.x, b.x);
-    } else {
-      Z[ll][(m & 15) + 17 * (m >> 4)] = make_double2(a.x - b.y, a.y + b.x);
-      const int mm = 256 - m;
-      Z[ll][(mm & 15) + 17 * (mm >> 4)] = make_double2(a.x + b.y, -a.y + b.x);
-    }
-  }
-  __syncthreads();
-}
-
-// Scatter the spectrum X (registers, X[s + 16 k]) of z = a + i b to harmonics of a and b
-// (orders m < M, scaled by 1/256; orders above mkeep written as zero).  Uses Z; contains barriers.
-__device__ __forceinline__ void scatter_pair(double2 (&v)[16], double2 (*Z)[16 * 17], const Phi256& g, int64_t q0,
-                                             int ll, int s, double2* fa, double2* fb) {
-  __syncthreads();  // the fft's LDS reads are complete
-#pragma unroll
-  for (int k1 = 0; k1 < 16; ++k1) Z[ll][s + 17 * k1] = v[k1];
-  __syncthreads();
-  const int t = threadIdx.x;
-  const int mmax = g.M < 128 ? g.M : 128;
-  for (int e = t; e < PL * g.M; e += 128) {
-    const int l2 = e & (PL - 1), m = e >> 3;
-    const int64_t q = q0 + l2;
-    if (q >= g.nlines) continue;
-    double2 A = make_double2(0.0, 0.0), B = A;
-    if (m < mmax && m <= g.mkeep) {
-      const double2 zm = Z[l2][(m & 15) + 17 * (m >> 4)];
-      const int mm = (256 - m) & 255;
-      const double2 zc = cconj(Z[l2][(mm & 15) + 17 * (mm >> 4)]);
-      A = cscale(cadd(zm, zc), 0.5 / 256.0);
-      const double2 d = csub(zm, zc);
-      B = make_double2(0.5 / 256.0 * d.y, -0.5 / 256.0 * d.x);
-    }
-    fa[(int64_t)m * g.nlines + q] = A;
-    if (fb) fb[(int64_t)m * g.nlines + q] = B;
-  }
-  __syncthreads();
-}
-
-__global__ __launch_bounds__(128) void phi_fwd256_kernel(Phi256 g, const double2* __restrict__ tw,
-                                                         const double* __restrict__ phys, double2* mixed) {
-  __shared__ double2 Z[PL][16 * 17];
-  const int t = threadIdx.x, ll = t >> 4, s = t & 15;
-  const int64_t q0 = (int64_t)blockIdx.x * PL;
-  // pairs of lines: line 2p in the real part, 2p+1 in the imaginary part; thread group ll
-  // handles the pair (ll & ~1, ll | 1) as one complex line only for even ll
-  const int64_t qa = q0 + (ll & ~1), qb = qa + 1;
-  double2 v[16];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const double a = (qa < g.nlines) ? phys[phys_off(g, qa) + s + 16 * j] : 0.0;
-    const double b = (qb < g.nlines) ? phys[phys_off(g, qb) + s + 16 * j] : 0.0;
-    v[j] = make_double2(a, b);
-  }
-  fft256<false>(v, Z[ll], s, tw);
-  // groups with odd ll computed the same pair; only even groups write their spectra
-  __syncthreads();
-  if ((ll & 1) == 0) {
-#pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) Z[ll][s + 17 * k1] = v[k1];
-  }
-  __syncthreads();
-  for (int e = t; e < PL * g.M; e += 128) {
-    const int l2 = e & (PL - 1), m = e >> 3;
-    const int64_t q = q0 + l2;
-    if (q >= g.nlines) continue;
-    double2 r = make_double2(0.0, 0.0);
-    if (m < 128 && m <= g.mkeep) {
-      const double2* Zp = Z[l2 & ~1];
-      const double2 zm = Zp[(m & 15) + 17 * (m >> 4)];
-      const int mm = (256 - m) & 255;
-      const double2 zc = cconj(Zp[(mm & 15) + 17 * (mm >> 4)]);
-      if ((l2 & 1) == 0) {
-        r = cscale(cadd(zm, zc), 0.5 / 256.0);
-      } else {
-        const double2 d = csub(zm, zc);
-        r = make_double2(0.5 / 256.0 * d.y, -0.5 / 256.0 * d.x);
-      }
-    }
-    mixed[(int64_t)m * g.nlines + q] = r;
-  }
-}
-
-__global__ __launch_bounds__(128) void phi_bwd256_kernel(Phi256 g, const double2* __restrict__ tw,
-                                                         const double2* __restrict__ mixed, double* phys) {
-  __shared__ double2 Z[PL][16 * 17];
-  const int t = threadIdx.x, ll = t >> 4, s = t & 15;
-  const int64_t q0 = (int64_t)blockIdx.x * PL;
-  // pack line pairs (2p, 2p+1) into one complex spectrum stored at Z[2p]
-  for (int e = t; e < PL * 256; e += 128) {
-    const int l2 = e & (PL - 1), p = e >> 3;
-    Z[l2][(p & 15) + 17 * (p >> 4)] = make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  const int mmax = g.M < 128 ? g.M : 128;
-  for (int e = t; e < (PL / 2) * mmax; e += 128) {
-    const int pr = e & (PL / 2 - 1), m = e >> 2;
-    const int64_t qa = q0 + 2 * pr, qb = qa + 1;
-    const double2 a = (qa < g.nlines) ? mixed[(int64_t)m * g.nlines + qa] : make_double2(0.0, 0.0);
-    const double2 b = (qb < g.nlines) ? mixed[(int64_t)m * g.nlines + qb] : make_double2(0.0, 0.0);
-    double2* Zp = Z[2 * pr];
-    if (m == 0) {
-      Zp[0] = make_double2(a.x, b.x);
-    } else {
-      Zp[(m & 15) + 17 * (m >> 4)] = make_double2(a.x - b.y, a.y + b.x);
-      const int mm = 256 - m;
-      Zp[(mm & 15) + 17 * (mm >> 4)] = make_double2(a.x + b.y, -a.y + b.x);
-    }
-  }
-  __syncthreads();
-  double2 v[16];
-  const double2* Zsrc = Z[ll & ~1];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) v[j] = Zsrc[s + 17 * j];
-  __syncthreads();  // odd groups read the even row before any group overwrites its own row
-  fft256<true>(v, Z[ll], s, tw);
-  const int64_t q = q0 + ll;
-  if (q < g.nlines) {
-    const bool imag = (ll & 1) != 0;
-#pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) {
-      // select values, not addresses, so that v stays in registers
-      const double re = v[k1].x, im = v[k1].y;
-      phys[phys_off(g, q) + s + 16 * k1] = imag ? im : re;
-    }
-  }
-}
-
-template <int MODE>
-__global__ __launch_bounds__(128) void phi_scalar256_kernel(Phi256 g, const double2* __restrict__ tw, double2* mixed,
-                                                            double gamma) {
-  __shared__ double2 Z[PL][16 * 17];
-  const int t = threadIdx.x, ll = t >> 4, s = t & 15;
-  const int64_t q0 = (int64_t)blockIdx.x * PL;
-  (void)t;
-  // each line is transformed on its own (imaginary part zero): u = B(u_hat), g(u), F(g)
-  gather_pair(Z, g, q0, mixed, nullptr);  // fb == null -> b = 0
-  // gather_pair packed each line ll into Z[ll] as a + i*0 -- with fb null the layout per line is correct
-  double2 v[16];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) v[j] = Z[ll][s + 17 * j];
-  __syncthreads();
-  fft256<true>(v, Z[ll], s, tw);
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const double u = v[k].x;
-    const double r = (MODE == MLG_RHS_U2) ? u * u : gamma * u * (1.0 - u);
-    v[k] = make_double2(r, 0.0);
-  }
-  __syncthreads();
-  fft256<false>(v, Z[ll], s, tw);
-  scatter_pair(v, Z, g, q0, ll, s, mixed, nullptr);
 }
 
 // ---------------------------------------------------------------- 32-lane lines
@@ -317,7 +93,7 @@ template <bool INV>
 __device__ __forceinline__ void dft8(double2 (&v)[8]) {
   dft4<INV>(v[0], v[2], v[4], v[6]);  // E[k] at v[2 k]
   dft4<INV>(v[1], v[3], v[5], v[7]);  // O[k] at v[2 k + 1]
-  const double2 o1 = tw16<INV, 2>(v[3]), o2 = tw16<INV, 4>(v[5]), o3 = tw16<INV, 6>(v[7]);
+  const double2 o1 = tw8<INV, 1>(v[3]), o2 = tw8<INV, 2>(v[5]), o3 = tw8<INV, 3>(v[7]);
   double2 x[8];
   x[0] = cadd(v[0], v[1]);
   x[4] = csub(v[0], v[1]);
@@ -559,6 +335,136 @@ __global__ __launch_bounds__(VB) void phi_vec256_kernel(Phi256 g, const double2*
   scatter_pair_w(v, Z, g, q0, ll, s, fs.f[2], nullptr);
 }
 
+// ---------------------------------------------------------------- scalar phi stages (32-lane lines)
+// Two real lines (2p, 2p+1) travel as one complex line z = a + i b: the backward stage packs their
+// harmonics as the Hermitian pair spectrum in row 2p of Z, both line groups transform it and each
+// keeps its part; the forward stage transforms the pair, the even group stores the spectrum and the
+// harmonics of both lines are separated from it.  The twiddles are staged in LDS as in the vector
+// stage; the block barrier of the gather also publishes them.
+__global__ __launch_bounds__(VB) void phi_bwd256_kernel(Phi256 g, const double2* __restrict__ twg,
+                                                        const double2* __restrict__ mixed, double* __restrict__ phys) {
+  __shared__ double2 Z[PL][WROW];
+  __shared__ double2 tw[256];
+  const int t = threadIdx.x, ll = t / WL, s = t % WL;
+  const int64_t q0 = (int64_t)blockIdx.x * PL;
+  tw[t] = twg[t];
+  if (t < PL / 2) Z[2 * t][zpos(128)] = make_double2(0.0, 0.0);
+  const int mmax = g.M < 128 ? g.M : 128;
+#pragma unroll
+  for (int it = 0; it < (PL / 2) * 128 / VB; ++it) {
+    const int e = t + VB * it;
+    const int pr = e & (PL / 2 - 1), m = e / (PL / 2);
+    const int64_t qa = q0 + 2 * pr, qb = qa + 1;
+    const double2 a = (m < mmax && qa < g.nlines) ? mixed[(int64_t)m * g.nlines + qa] : make_double2(0.0, 0.0);
+    const double2 b = (m < mmax && qb < g.nlines) ? mixed[(int64_t)m * g.nlines + qb] : make_double2(0.0, 0.0);
+    double2* Zp = Z[2 * pr];
+    if (m == 0) {
+      Zp[0] = make_double2(a.x, b.x);
+    } else {
+      Zp[zpos(m)] = make_double2(a.x - b.y, a.y + b.x);
+      Zp[zpos(256 - m)] = make_double2(a.x + b.y, -a.y + b.x);
+    }
+  }
+  __syncthreads();
+  double2 v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = Z[ll & ~1][33 * j + s];
+  __syncthreads();  // the odd line reads the even row before any line overwrites its own row
+  fft256w<true>(v, Z[ll], s, tw);
+  const int64_t q = q0 + ll;
+  if (q < g.nlines) {
+    const bool imag = (ll & 1) != 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      // select values, not addresses, so that v stays in registers
+      const double re = v[k].x, im = v[k].y;
+      phys[phys_off(g, q) + s + 32 * k] = imag ? im : re;
+    }
+  }
+}
+
+__global__ __launch_bounds__(VB) void phi_fwd256_kernel(Phi256 g, const double2* __restrict__ twg,
+                                                        const double* __restrict__ phys, double2* __restrict__ mixed) {
+  __shared__ double2 Z[PL][WROW];
+  __shared__ double2 tw[256];
+  const int t = threadIdx.x, ll = t / WL, s = t % WL;
+  const int64_t q0 = (int64_t)blockIdx.x * PL;
+  tw[t] = twg[t];
+  const int64_t qa = q0 + (ll & ~1), qb = qa + 1;
+  double2 v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const double a = (qa < g.nlines) ? phys[phys_off(g, qa) + s + 32 * j] : 0.0;
+    const double b = (qb < g.nlines) ? phys[phys_off(g, qb) + s + 32 * j] : 0.0;
+    v[j] = make_double2(a, b);
+  }
+  __syncthreads();  // the twiddle table is staged
+  fft256w<false>(v, Z[ll], s, tw);
+  __syncthreads();  // every line's exchange reads are complete
+  if ((ll & 1) == 0) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) Z[ll][33 * k + s] = v[k];
+  }
+  __syncthreads();
+  for (int e = t; e < PL * g.M; e += VB) {
+    const int l2 = e & (PL - 1), m = e >> 3;
+    const int64_t q = q0 + l2;
+    if (q >= g.nlines) continue;
+    double2 r = make_double2(0.0, 0.0);
+    if (m < 128 && m <= g.mkeep) {
+      const double2* Zp = Z[l2 & ~1];
+      const double2 zm = Zp[zpos(m)];
+      const double2 zc = cconj(Zp[zpos((256 - m) & 255)]);
+      if ((l2 & 1) == 0) {
+        r = cscale(cadd(zm, zc), 0.5 / 256.0);
+      } else {
+        const double2 d = csub(zm, zc);
+        r = make_double2(0.5 / 256.0 * d.y, -0.5 / 256.0 * d.x);
+      }
+    }
+    mixed[(int64_t)m * g.nlines + q] = r;
+  }
+}
+
+// u = B(u_hat), g(u) = u^2 or gamma u (1 - u), back to harmonics; one real line per 32 lanes
+template <int MODE>
+__global__ __launch_bounds__(VB) void phi_scalar256_kernel(Phi256 g, const double2* __restrict__ twg, double2* mixed,
+                                                           double gamma) {
+  __shared__ double2 Z[PL][WROW];
+  __shared__ double2 tw[256];
+  const int t = threadIdx.x, ll = t / WL, s = t % WL;
+  const int64_t q0 = (int64_t)blockIdx.x * PL;
+  tw[t] = twg[t];
+  if (t < PL) Z[t][zpos(128)] = make_double2(0.0, 0.0);
+  const int mmax = g.M < 128 ? g.M : 128;
+#pragma unroll
+  for (int it = 0; it < PL * 128 / VB; ++it) {
+    const int e = t + VB * it;
+    const int l2 = e & (PL - 1), m = e >> 3;
+    const int64_t q = q0 + l2;
+    const double2 a = (m < mmax && q < g.nlines) ? mixed[(int64_t)m * g.nlines + q] : make_double2(0.0, 0.0);
+    if (m == 0) {
+      Z[l2][0] = make_double2(a.x, 0.0);
+    } else {
+      Z[l2][zpos(m)] = a;
+      Z[l2][zpos(256 - m)] = cconj(a);
+    }
+  }
+  __syncthreads();
+  double2 v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = Z[ll][33 * j + s];
+  fft256w<true>(v, Z[ll], s, tw);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const double u = v[k].x;
+    const double r = (MODE == MLG_RHS_U2) ? u * u : gamma * u * (1.0 - u);
+    v[k] = make_double2(r, 0.0);
+  }
+  fft256w<false>(v, Z[ll], s, tw);
+  scatter_pair_w(v, Z, g, q0, ll, s, mixed, nullptr);
+}
+
 // ---------------------------------------------------------------- z transforms (32-lane lines)
 // Contiguous lines of 256 samples, up to six fields per launch (blocks field-major).  Lane s of a
 // line loads x[s + 32 j] straight into registers (32 lanes cover 512 contiguous bytes), fft256w
@@ -651,8 +557,8 @@ mlg_status launch_phi256_forward(const mlg_plan_s* p, const double* phys, double
   Phi256 g = phi256_geom(p, false);
   dim3 grid((unsigned)((g.nlines + PL - 1) / PL));
   p->timing.begin("phi_fft", s);
-  phi_fwd256_kernel<<<grid, 128, 0, s>>>(g, reinterpret_cast<const double2*>(p->d_tw_phi), phys,
-                                         reinterpret_cast<double2*>(mixed));
+  phi_fwd256_kernel<<<grid, VB, 0, s>>>(g, reinterpret_cast<const double2*>(p->d_tw_phi), phys,
+                                        reinterpret_cast<double2*>(mixed));
   p->timing.end(s);
   return check("phi_fwd256_kernel");
 }
@@ -661,8 +567,8 @@ mlg_status launch_phi256_backward(const mlg_plan_s* p, const double* mixed, doub
   Phi256 g = phi256_geom(p, false);
   dim3 grid((unsigned)((g.nlines + PL - 1) / PL));
   p->timing.begin("phi_fft", s);
-  phi_bwd256_kernel<<<grid, 128, 0, s>>>(g, reinterpret_cast<const double2*>(p->d_tw_phi),
-                                         reinterpret_cast<const double2*>(mixed), phys);
+  phi_bwd256_kernel<<<grid, VB, 0, s>>>(g, reinterpret_cast<const double2*>(p->d_tw_phi),
+                                        reinterpret_cast<const double2*>(mixed), phys);
   p->timing.end(s);
   return check("phi_bwd256_kernel");
 }
@@ -673,9 +579,9 @@ mlg_status launch_phi256_scalar(const mlg_plan_s* p, int kind, double gamma, dou
   const double2* tw = reinterpret_cast<const double2*>(p->d_tw_phi);
   p->timing.begin("phi_fft", s);
   if (kind == MLG_RHS_U2)
-    phi_scalar256_kernel<MLG_RHS_U2><<<grid, 128, 0, s>>>(g, tw, reinterpret_cast<double2*>(mixed), gamma);
+    phi_scalar256_kernel<MLG_RHS_U2><<<grid, VB, 0, s>>>(g, tw, reinterpret_cast<double2*>(mixed), gamma);
   else
-    phi_scalar256_kernel<MLG_RHS_KPP><<<grid, 128, 0, s>>>(g, tw, reinterpret_cast<double2*>(mixed), gamma);
+    phi_scalar256_kernel<MLG_RHS_KPP><<<grid, VB, 0, s>>>(g, tw, reinterpret_cast<double2*>(mixed), gamma);
   p->timing.end(s);
   return check("phi_scalar256_kernel");
 }
