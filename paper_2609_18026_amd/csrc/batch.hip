@@ -98,9 +98,54 @@ __device__ __forceinline__ Cx<T> conjc(Cx<T> a) { return cx(a.x, -a.y); }
 template <typename T>
 __device__ __forceinline__ Cx<T> scl(Cx<T> a, T s) { return cx(a.x * s, a.y * s); }
 
-// Stockham pass (radix R, span Ns) over 'nl' lines of length n in LDS.
+// multiply by -i (forward) or +i (inverse)
+template <typename T>
+__device__ __forceinline__ Cx<T> mul_mi(Cx<T> a, bool inv) {
+  return inv ? cx(-a.y, a.x) : cx(a.y, -a.x);
+}
+
+// In-register DFT of length R (2, 3, 4, 5) with exp(-+ 2 pi i / R) (forward: minus), written out.
 template <typename T, int R>
-__device__ __forceinline__ void bpass(const Cx<T>* in, Cx<T>* out, int n, int Ns, const double* __restrict__ tw, bool inv,
+__device__ __forceinline__ void small_dft(Cx<T> (&v)[R], bool inv) {
+  if constexpr (R == 2) {
+    const Cx<T> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+  } else if constexpr (R == 3) {
+    constexpr double h = 0.86602540378443864676;  // sqrt(3)/2
+    const Cx<T> t1 = v[1] + v[2];
+    const Cx<T> t2 = v[0] - scl(t1, (T)0.5);
+    const Cx<T> t3 = mul_mi(scl(v[1] - v[2], (T)h), inv);
+    v[0] = v[0] + t1;
+    v[1] = t2 + t3;
+    v[2] = t2 - t3;
+  } else if constexpr (R == 4) {
+    const Cx<T> t0 = v[0] + v[2], t1 = v[0] - v[2];
+    const Cx<T> t2 = v[1] + v[3], t3 = mul_mi(v[1] - v[3], inv);
+    v[0] = t0 + t2;
+    v[1] = t1 + t3;
+    v[2] = t0 - t2;
+    v[3] = t1 - t3;
+  } else {
+    constexpr double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;  // cos 2pi/5, cos 4pi/5
+    constexpr double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;   // sin 2pi/5, sin 4pi/5
+    const Cx<T> t1 = v[1] + v[4], t2 = v[2] + v[3], t3 = v[1] - v[4], t4 = v[2] - v[3];
+    const Cx<T> r1 = v[0] + scl(t1, (T)c1) + scl(t2, (T)c2);
+    const Cx<T> r2 = v[0] + scl(t1, (T)c2) + scl(t2, (T)c1);
+    const Cx<T> i1 = mul_mi(scl(t3, (T)s1) + scl(t4, (T)s2), inv);
+    const Cx<T> i2 = mul_mi(scl(t3, (T)s2) - scl(t4, (T)s1), inv);
+    v[0] = v[0] + t1 + t2;
+    v[1] = r1 + i1;
+    v[4] = r1 - i1;
+    v[2] = r2 + i2;
+    v[3] = r2 - i2;
+  }
+}
+
+// Stockham pass (radix R, span Ns) over 'nl' lines of length n in LDS; tw is the line's table
+// exp(-2 pi i t / n) staged in LDS.  The stage twiddle index j_mod_Ns r n / (Ns R) is below n.
+template <typename T, int R>
+__device__ __forceinline__ void bpass(const Cx<T>* in, Cx<T>* out, int n, int Ns, const Cx<double>* tw, bool inv,
                                       int nl, int tid, int nth) {
   const int nb = n / R;
   const int tfac = n / (Ns * R);
@@ -114,30 +159,18 @@ __device__ __forceinline__ void bpass(const Cx<T>* in, Cx<T>* out, int n, int Ns
     for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
 #pragma unroll
     for (int r = 1; r < R; ++r) {
-      const int t = (jm * r * tfac) % n;
-      Cx<T> w = cx((T)tw[2 * t], (T)(inv ? -tw[2 * t + 1] : tw[2 * t + 1]));
-      v[r] = v[r] * w;
+      const Cx<double> w = tw[jm * r * tfac];
+      v[r] = v[r] * cx((T)w.x, (T)(inv ? -w.y : w.y));
     }
-    Cx<T> o[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      Cx<T> s = v[0];
-#pragma unroll
-      for (int r = 1; r < R; ++r) {
-        const int t = ((r * q) % R) * (n / R);
-        Cx<T> w = cx((T)tw[2 * t], (T)(inv ? -tw[2 * t + 1] : tw[2 * t + 1]));
-        s = s + v[r] * w;
-      }
-      o[q] = s;
-    }
+    small_dft<T, R>(v, inv);
     const int od = (j / Ns) * Ns * R + jm;
 #pragma unroll
-    for (int r = 0; r < R; ++r) dst[od + r * Ns] = o[r];
+    for (int r = 0; r < R; ++r) dst[od + r * Ns] = v[r];
   }
 }
 
 template <typename T>
-__device__ __forceinline__ Cx<T>* bfft(Cx<T>* x, Cx<T>* y, const BatchInst& I, const double* __restrict__ tw, bool inv, int nl) {
+__device__ __forceinline__ Cx<T>* bfft(Cx<T>* x, Cx<T>* y, const BatchInst& I, const Cx<double>* tw, bool inv, int nl) {
   const int tid = threadIdx.x, nth = blockDim.x;
   int Ns = 1;
   Cx<T>* a = x;
@@ -237,7 +270,10 @@ __device__ void phase_phi(const BatchArgs<T>& A, int b, int q0, char* smem) {
   const int n = I.nphi, L = A.lines, np = L / 2;
   Cx<T>* X = reinterpret_cast<Cx<T>*>(smem);
   Cx<T>* Y = X + np * n;
-  const double* tw = A.tab + I.tw_off;
+  // the twiddle table follows the two line buffers (2 np n complex of T: a multiple of 16 bytes)
+  Cx<double>* tw = reinterpret_cast<Cx<double>*>(smem + (size_t)2 * np * n * sizeof(Cx<T>));
+  const double* twg = A.tab + I.tw_off;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) tw[e] = Cx<double>{twg[2 * e], twg[2 * e + 1]};
   Cx<T>* mix = A.mix + I.mix_off;
   for (int e = threadIdx.x; e < np * n; e += blockDim.x) X[e] = cx<T>(0, 0);
   __syncthreads();
@@ -341,7 +377,9 @@ __global__ void batch_kernel(BatchArgs<T> A) {
 size_t smem_bytes(const mlg_batch_s* bt, int lines) {
   size_t mx = 256 * sizeof(Cx<double>) + 512 * sizeof(double);
   const size_t cs = bt->prec == MLG_FP32 ? sizeof(Cx<float>) : sizeof(Cx<double>);
-  for (const auto& I : bt->inst) mx = std::max(mx, (size_t)2 * (lines / 2) * I.nphi * cs);
+  // phase 2: two buffers of lines / 2 complex lines, then the twiddle table (nphi complex FP64)
+  for (const auto& I : bt->inst)
+    mx = std::max(mx, (size_t)2 * (lines / 2) * I.nphi * cs + (size_t)I.nphi * sizeof(Cx<double>));
   return mx;
 }
 
