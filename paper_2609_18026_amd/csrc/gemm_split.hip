@@ -66,14 +66,21 @@ struct SplitSynthArgs {
   const int64_t* off;
   const double* node;
   int nr, nrc, nz;
+  int gx, gy, gz;                // tiles: column blocks, row blocks, orders
   double kap0;
 };
 
-// B staging: [buf][var][col][k] with var = input(psi, chi) x scaled(1, L) x part(re, im) x (hi, lo)
-__global__ __launch_bounds__(256) void split_synth_kernel(SplitSynthArgs a) {
-  const int m = blockIdx.z;
-  const int row0 = blockIdx.y * TM;
-  const int kk0 = blockIdx.x * TC;
+// B staging: [buf][var][col][k] with var = input(psi, chi) x scaled(1, L) x part(re, im) x (hi, lo).
+// The FP64 operands of the next two K stages and the table fragments of the next one are held in
+// registers as raw loads; the scaling by L and the bf16 split happen when they are written to LDS,
+// after the MFMAs of the current stage, so the loads stay in flight across them.  At 3 waves per
+// SIMD (156 VGPRs, the accumulators leave the AGPRs) the latency of the next stage is better hidden.
+__global__ __launch_bounds__(256, 3) void split_synth_kernel(SplitSynthArgs a) {
+  Tile3 tl;
+  if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
+  const int m = tl.z;
+  const int row0 = tl.y * TM;
+  const int kk0 = tl.x * TC;
   if (row0 >= a.nr || kk0 >= a.nz) return;
   const int K = a.nrc > m ? a.nrc - m : 0;
   const int nr = a.nr, nz = a.nz;
@@ -94,17 +101,27 @@ __global__ __launch_bounds__(256) void split_synth_kernel(SplitSynthArgs a) {
   for (int p = 0; p < 7; ++p) acc[p][0] = acc[p][1] = floatx4{0.f, 0.f, 0.f, 0.f};
 
   // each thread stages 2 (k, col) entries of psi and chi per chunk
-  auto stage = [&](int buf, int k0) {
+  struct Stage {
+    double2 p[2], c[2];
+  };
+  auto load = [&](int k0, Stage& d) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = tid + 256 * h;
+      const int k = k0 + (e >> 4), kk = kk0 + (e & 15);
+      const bool ok = k < K && kk < nz;
+      d.p[h] = ok ? ps[(int64_t)k * nz + kk] : make_double2(0.0, 0.0);
+      d.c[h] = ok ? ch[(int64_t)k * nz + kk] : make_double2(0.0, 0.0);
+    }
+  };
+  auto store = [&](int buf, int k0, const Stage& d) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int e = tid + 256 * h;
       const int kr = e >> 4, c = e & 15;
-      const int k = k0 + kr, kk = kk0 + c;
-      const bool ok = k < K && kk < nz;
-      const double Ln = (double)(k + m) * (k + m + 1.0);
-      const double2 vp = ok ? ps[(int64_t)k * nz + kk] : make_double2(0.0, 0.0);
-      const double2 vc = ok ? ch[(int64_t)k * nz + kk] : make_double2(0.0, 0.0);
-      const double vals[8] = {vp.x, vp.y, Ln * vp.x, Ln * vp.y, vc.x, vc.y, Ln * vc.x, Ln * vc.y};
+      const double Ln = (double)(k0 + kr + m) * (k0 + kr + m + 1.0);
+      const double vals[8] = {d.p[h].x,      d.p[h].y, Ln * d.p[h].x, Ln * d.p[h].y,
+                              d.c[h].x,      d.c[h].y, Ln * d.c[h].x, Ln * d.c[h].y};
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         unsigned short hi, lo;
@@ -114,15 +131,26 @@ __global__ __launch_bounds__(256) void split_synth_kernel(SplitSynthArgs a) {
       }
     }
   };
+  auto frags = [&](int kt, bf16x8 (&f)[4]) {
+    const int64_t ko = (int64_t)kt * TK;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) f[t] = ldfrag(tp[t] + ko);
+  };
+
   const int nk = (K + TK - 1) / TK;
-  stage(0, 0);
+  Stage ra, rn;
+  bf16x8 fa[4], fn[4];
+  if (nk > 0) {
+    frags(0, fa);  // issued first, so that the wait for the staged operands covers it
+    load(0, ra);
+    store(0, 0, ra);
+  }
+  if (nk > 1) load(TK, ra);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
-    const int64_t ko = (int64_t)kt * TK;
-    const bf16x8 pH = ldfrag(tp[0] + ko), pL = ldfrag(tp[1] + ko);
-    const bf16x8 tH = ldfrag(tp[2] + ko), tL = ldfrag(tp[3] + ko);
-    if (kt + 1 < nk) stage(buf ^ 1, (kt + 1) * TK);
+    if (kt + 2 < nk) load((kt + 2) * TK, rn);
+    if (kt + 1 < nk) frags(kt + 1, fn);
     const int c = lane & 15;
     // var index: q = 0 psi re, 1 psi im, 2 Lpsi re, 3 Lpsi im, 4 chi re, 5 chi im, 6 Lchi re, 7 Lchi im
     bf16x8 bh[8], bl[8];
@@ -133,14 +161,18 @@ __global__ __launch_bounds__(256) void split_synth_kernel(SplitSynthArgs a) {
     }
 #pragma unroll
     for (int ri = 0; ri < 2; ++ri) {
-      acc[0][ri] = mfma3(pH, pL, bh[0 + ri], bl[0 + ri], acc[0][ri]);  // A1 = P psi
-      acc[1][ri] = mfma3(tH, tL, bh[0 + ri], bl[0 + ri], acc[1][ri]);  // A2 = T psi
-      acc[2][ri] = mfma3(pH, pL, bh[2 + ri], bl[2 + ri], acc[2][ri]);  // A3 = P L psi
-      acc[3][ri] = mfma3(pH, pL, bh[4 + ri], bl[4 + ri], acc[3][ri]);  // B1 = P chi
-      acc[4][ri] = mfma3(tH, tL, bh[4 + ri], bl[4 + ri], acc[4][ri]);  // B2 = T chi
-      acc[5][ri] = mfma3(pH, pL, bh[6 + ri], bl[6 + ri], acc[5][ri]);  // B3 = P L chi
-      acc[6][ri] = mfma3(tH, tL, bh[6 + ri], bl[6 + ri], acc[6][ri]);  // B4 = T L chi
+      acc[0][ri] = mfma3(fa[0], fa[1], bh[0 + ri], bl[0 + ri], acc[0][ri]);  // A1 = P psi
+      acc[1][ri] = mfma3(fa[2], fa[3], bh[0 + ri], bl[0 + ri], acc[1][ri]);  // A2 = T psi
+      acc[2][ri] = mfma3(fa[0], fa[1], bh[2 + ri], bl[2 + ri], acc[2][ri]);  // A3 = P L psi
+      acc[3][ri] = mfma3(fa[0], fa[1], bh[4 + ri], bl[4 + ri], acc[3][ri]);  // B1 = P chi
+      acc[4][ri] = mfma3(fa[2], fa[3], bh[4 + ri], bl[4 + ri], acc[4][ri]);  // B2 = T chi
+      acc[5][ri] = mfma3(fa[0], fa[1], bh[6 + ri], bl[6 + ri], acc[5][ri]);  // B3 = P L chi
+      acc[6][ri] = mfma3(fa[2], fa[3], bh[6 + ri], bl[6 + ri], acc[6][ri]);  // B4 = T L chi
     }
+    if (kt + 1 < nk) store(buf ^ 1, (kt + 1) * TK, ra);
+    ra = rn;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) fa[t] = fn[t];
     __syncthreads();
   }
   const int kk = kk0 + (lane & 15);
@@ -186,6 +218,7 @@ struct SplitProjArgs {
   double2* out[3];
   const int64_t* off;
   int nr, nrc, nz, kmax, nkact;
+  int gx, gy, gz;                // tiles: column blocks, row blocks, orders
   double kap0;
 };
 
@@ -193,10 +226,14 @@ __device__ __forceinline__ int active_kk(int a, int kmax, int nz) {
   return (a <= kmax) ? a : nz - (2 * kmax + 1 - a);
 }
 
+// Staging as in split_synth_kernel: raw loads of the next two node stages and the next table
+// fragments in registers, split into bf16 at the LDS store.
 __global__ __launch_bounds__(256) void split_proj_kernel(SplitProjArgs a) {
-  const int m = blockIdx.z;
-  const int row0 = blockIdx.y * TM;
-  const int c0 = blockIdx.x * TC;
+  Tile3 tl;
+  if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
+  const int m = tl.z;
+  const int row0 = tl.y * TM;
+  const int c0 = tl.x * TC;
   const int rows = a.nrc > m ? a.nrc - m : 0;
   if (row0 >= rows || c0 >= a.nkact) return;
   const int nr = a.nr, nz = a.nz;
@@ -214,19 +251,33 @@ __global__ __launch_bounds__(256) void split_proj_kernel(SplitProjArgs a) {
   floatx4 acc[5][2];
 #pragma unroll
   for (int p = 0; p < 5; ++p) acc[p][0] = acc[p][1] = floatx4{0.f, 0.f, 0.f, 0.f};
-  auto stage = [&](int buf, int k0) {
+  // the (node, column) entries of a thread do not change their column between stages
+  int skk[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int ca = c0 + ((tid + 256 * h) & 15);
+    skk[h] = ca < a.nkact ? active_kk(ca, a.kmax, nz) : -1;
+  }
+  struct Stage {
+    double2 v[2][3];
+  };
+  auto load = [&](int k0, Stage& d) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = k0 + ((tid + 256 * h) >> 4);
+      const bool ok = k < nr && skk[h] >= 0;
+      const int64_t idx = (int64_t)k * nz + skk[h];
+      d.v[h][0] = ok ? X0[idx] : make_double2(0.0, 0.0);
+      d.v[h][1] = ok ? X1[idx] : make_double2(0.0, 0.0);
+      d.v[h][2] = ok ? X2[idx] : make_double2(0.0, 0.0);
+    }
+  };
+  auto store = [&](int buf, const Stage& d) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int e = tid + 256 * h;
       const int kr = e >> 4, c = e & 15;
-      const int k = k0 + kr, ca = c0 + c;
-      const bool ok = k < nr && ca < a.nkact;
-      const int kk = ok ? active_kk(ca, a.kmax, nz) : 0;
-      const int64_t idx = (int64_t)k * nz + kk;
-      const double2 v0 = ok ? X0[idx] : make_double2(0.0, 0.0);
-      const double2 v1 = ok ? X1[idx] : make_double2(0.0, 0.0);
-      const double2 v2 = ok ? X2[idx] : make_double2(0.0, 0.0);
-      const double vals[6] = {v0.x, v0.y, v1.x, v1.y, v2.x, v2.y};
+      const double vals[6] = {d.v[h][0].x, d.v[h][0].y, d.v[h][1].x, d.v[h][1].y, d.v[h][2].x, d.v[h][2].y};
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
         unsigned short hi, lo;
@@ -236,15 +287,23 @@ __global__ __launch_bounds__(256) void split_proj_kernel(SplitProjArgs a) {
       }
     }
   };
+  auto frags = [&](int kt, bf16x8 (&f)[4]) {
+    const int64_t ko = (int64_t)kt * TK;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) f[t] = ldfrag(tp[t] + ko);
+  };
   const int nk = (nr + TK - 1) / TK;
-  stage(0, 0);
+  Stage ra, rn;
+  bf16x8 fa[4], fn[4];
+  frags(0, fa);  // issued first, so that the wait for the staged operands covers it
+  load(0, ra);
+  store(0, ra);
+  if (nk > 1) load(TK, ra);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
-    const int64_t ko = (int64_t)kt * TK;
-    const bf16x8 pH = ldfrag(tp[0] + ko), pL = ldfrag(tp[1] + ko);
-    const bf16x8 qH = ldfrag(tp[2] + ko), qL = ldfrag(tp[3] + ko);
-    if (kt + 1 < nk) stage(buf ^ 1, (kt + 1) * TK);
+    if (kt + 2 < nk) load((kt + 2) * TK, rn);
+    if (kt + 1 < nk) frags(kt + 1, fn);
     const int c = lane & 15;
     bf16x8 bh[6], bl[6];
 #pragma unroll
@@ -254,12 +313,16 @@ __global__ __launch_bounds__(256) void split_proj_kernel(SplitProjArgs a) {
     }
 #pragma unroll
     for (int ri = 0; ri < 2; ++ri) {
-      acc[0][ri] = mfma3(pH, pL, bh[0 + ri], bl[0 + ri], acc[0][ri]);  // Pa
-      acc[1][ri] = mfma3(qH, qL, bh[0 + ri], bl[0 + ri], acc[1][ri]);  // Qa
-      acc[2][ri] = mfma3(pH, pL, bh[2 + ri], bl[2 + ri], acc[2][ri]);  // Pb
-      acc[3][ri] = mfma3(qH, qL, bh[2 + ri], bl[2 + ri], acc[3][ri]);  // Qb
-      acc[4][ri] = mfma3(pH, pL, bh[4 + ri], bl[4 + ri], acc[4][ri]);  // Pc
+      acc[0][ri] = mfma3(fa[0], fa[1], bh[0 + ri], bl[0 + ri], acc[0][ri]);  // Pa
+      acc[1][ri] = mfma3(fa[2], fa[3], bh[0 + ri], bl[0 + ri], acc[1][ri]);  // Qa
+      acc[2][ri] = mfma3(fa[0], fa[1], bh[2 + ri], bl[2 + ri], acc[2][ri]);  // Pb
+      acc[3][ri] = mfma3(fa[2], fa[3], bh[2 + ri], bl[2 + ri], acc[3][ri]);  // Qb
+      acc[4][ri] = mfma3(fa[0], fa[1], bh[4 + ri], bl[4 + ri], acc[4][ri]);  // Pc
     }
+    if (kt + 1 < nk) store(buf ^ 1, ra);
+    ra = rn;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) fa[t] = fn[t];
     __syncthreads();
   }
   const int cidx = c0 + (lane & 15);
@@ -307,9 +370,11 @@ mlg_status launch_split_synth(const mlg_plan_s* p, const double* psi, const doub
   a.nrc = p->nrc;
   a.nz = p->nz;
   a.kap0 = 2.0 * M_PI / p->g.lz;
-  dim3 grid((unsigned)((p->nz + TC - 1) / TC), (unsigned)((p->nr + TM - 1) / TM), (unsigned)p->M);
+  a.gx = (p->nz + TC - 1) / TC;
+  a.gy = (p->nr + TM - 1) / TM;
+  a.gz = p->M;
   p->timing.begin("synth_gemm", s);
-  split_synth_kernel<<<grid, 256, 0, s>>>(a);
+  split_synth_kernel<<<xcd_blocks(a.gx, a.gy, a.gz), 256, 0, s>>>(a);
   p->timing.end(s);
   return check("split_synth_kernel");
 }
@@ -332,9 +397,11 @@ mlg_status launch_split_proj(const mlg_plan_s* p, double* const* in3, double* co
   a.nkact = (p->nz == 1) ? 1 : 2 * kmax + 1;
   a.kap0 = 2.0 * M_PI / p->g.lz;
   if (mmax <= 0 || a.nkact <= 0) return MLG_OK;
-  dim3 grid((unsigned)((a.nkact + TC - 1) / TC), (unsigned)((p->nrc + TM - 1) / TM), (unsigned)mmax);
+  a.gx = (a.nkact + TC - 1) / TC;
+  a.gy = (p->nrc + TM - 1) / TM;
+  a.gz = mmax;
   p->timing.begin("proj_gemm", s);
-  split_proj_kernel<<<grid, 256, 0, s>>>(a);
+  split_proj_kernel<<<xcd_blocks(a.gx, a.gy, a.gz), 256, 0, s>>>(a);
   p->timing.end(s);
   return check("split_proj_kernel");
 }
