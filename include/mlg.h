@@ -57,9 +57,12 @@ typedef enum {
 
 typedef enum {
   MLG_FP64 = 0,        /* double data, FP64 arithmetic (MFMA f64 for the radial products)    */
-  MLG_FP32 = 1,        /* float data, FP32 arithmetic                                        */
-  MLG_SPLIT_BF16 = 2   /* float data; radial products as hi/lo bfloat16 splits on MFMA with  */
-                       /* FP32 accumulation (a_hi b_hi + a_hi b_lo + a_lo b_hi)              */
+  MLG_FP32 = 1,        /* batches only: float data and streamed tables (built in FP64),       */
+                       /* FP32 arithmetic                                                    */
+  MLG_SPLIT_BF16 = 2   /* plans only: double data; the radial products of the vector RHS as   */
+                       /* hi/lo bfloat16 splits on MFMA with FP32 accumulation                */
+                       /* (a_hi b_hi + a_hi b_lo + a_lo b_hi); FFTs, pointwise products and   */
+                       /* solves stay FP64                                                    */
 } mlg_precision;
 
 enum { MLG_RHS_U2 = 0, MLG_RHS_KPP = 1 };
@@ -95,7 +98,8 @@ typedef struct mlg_plan_s* mlg_plan;
  * r d/dr Pbar, the horizontal-Laplacian Gram factors of Eq. del2h-entries and the FFT
  * twiddles, then copies them to 'device'.  Errors: MLG_E_ARG for bad sizes/chops/ell,
  * MLG_E_NONFINITE for non-finite ell or L_z, MLG_E_UNSUPPORTED for N_phi or N_z whose
- * factors are not all 2, 3 or 5, or N_phi, N_z above 1024; MLG_E_ALLOC/DEVICE on HIP failure.
+ * factors are not all 2, 3 or 5, or N_phi, N_z above 1024, or a precision other than MLG_FP64
+ * and MLG_SPLIT_BF16 (the data of both are double); MLG_E_ALLOC/DEVICE on HIP failure.
  * On failure *out is NULL and nothing is leaked.  For even N_r the FP64 radial products of the
  * vector RHS use the node symmetry x -> -x and the parity of Pbar_n^m (half the flops); the
  * environment variable MLG_RADIAL_FOLD=0, read at creation, selects the unfolded products. */

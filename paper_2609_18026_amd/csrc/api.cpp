@@ -160,6 +160,7 @@ mlg_status mlg_plan_nodes(mlg_plan p, double* x, double* w, double* r) {
 // Radial products of one scalar field: folded over the node symmetry for even N_r (unless the plan
 // was created with MLG_RADIAL_FOLD=0), the generic batched GEMM otherwise.
 static mlg_status scalar_radial(const mlg_plan_s* p, int dir, const double* B, double* C, hipStream_t s) {
+  if (p->prec == MLG_SPLIT_BF16) return launch_split_scalar(p, dir, B, C, s);
   if (p->use_fold && p->nr % 2 == 0) return launch_scalar_fold(p, dir, B, C, s);
   GemmProds pr{};
   pr.nprod = 1;

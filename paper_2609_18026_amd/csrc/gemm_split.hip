@@ -347,6 +347,111 @@ __global__ __launch_bounds__(256) void split_proj_kernel(SplitProjArgs a) {
   }
 }
 
+struct SplitScalarArgs {
+  const unsigned short* tab[2];  // hi, lo: backward Pbar [i][kpad] (split synthesis tables),
+                                 // forward W Pbar [n-m][ipad] (split projection tables)
+  const int64_t* toff;           // per m element offset of the tables
+  const int32_t* kpad;           // backward: per m row stride
+  int ipad;                      // forward: row stride
+  const double2* in;             // backward: spectrum [tau][nz]; forward: harmonics [m][i][nz]
+  double2* out;                  // backward: harmonics [m][i][nz]; forward: spectrum [tau][nz]
+  const int64_t* off;            // packed offset of each order
+  int nr, nrc, nz;
+  int gx, gy, gz;                // tiles: column blocks, row blocks, orders
+};
+
+// Radial products of the scalar transform pair (Sec. 4.1) with split-bfloat16 operands:
+// backward f_m[i][kk] = sum_n Pbar_n^m(x_i) s[n][kk], forward s[n][kk] = sum_i w_i Pbar_n^m(x_i)
+// f_m[i][kk].  The real table is the MFMA A operand; the re and im parts of the complex data are
+// two B operands.  Staging and pipelining as in split_proj_kernel.
+template <bool FWD>
+__global__ __launch_bounds__(256) void split_scalar_kernel(SplitScalarArgs a) {
+  Tile3 tl;
+  if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
+  const int m = tl.z;
+  const int K = a.nrc > m ? a.nrc - m : 0;
+  const int rows = FWD ? K : a.nr;  // output rows of this order
+  const int kdim = FWD ? a.nr : K;  // contraction length
+  const int row0 = tl.y * TM;
+  const int kk0 = tl.x * TC;
+  if (row0 >= rows || kk0 >= a.nz) return;
+  const int nz = a.nz;
+  const int ld = FWD ? a.ipad : a.kpad[m];
+  const double2* __restrict__ X = a.in + (FWD ? (int64_t)m * a.nr : a.off[m]) * nz;
+  double2* __restrict__ Y = a.out + (FWD ? a.off[m] : (int64_t)m * a.nr) * nz;
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][4][TC][TK];  // [buf][re hi, re lo, im hi, im lo]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rowl = row0 + wave * 16 + (lane & 15);
+  const int kg = 8 * (lane >> 4);
+  const bool rowok = rowl < rows;
+  const unsigned short* tp[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) tp[t] = a.tab[t] + a.toff[m] + (int64_t)(rowok ? rowl : 0) * ld + kg;
+  floatx4 acc[2] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
+  struct Stage {
+    double2 v[2];
+  };
+  auto load = [&](int k0, Stage& d) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = tid + 256 * h;
+      const int k = k0 + (e >> 4), kk = kk0 + (e & 15);
+      d.v[h] = (k < kdim && kk < nz) ? X[(int64_t)k * nz + kk] : make_double2(0.0, 0.0);
+    }
+  };
+  auto store = [&](int buf, const Stage& d) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = tid + 256 * h;
+      const int kr = e >> 4, c = e & 15;
+      unsigned short hi, lo;
+      split2(d.v[h].x, hi, lo);
+      Bs[buf][0][c][kr] = hi;
+      Bs[buf][1][c][kr] = lo;
+      split2(d.v[h].y, hi, lo);
+      Bs[buf][2][c][kr] = hi;
+      Bs[buf][3][c][kr] = lo;
+    }
+  };
+  auto frags = [&](int kt, bf16x8 (&f)[2]) {
+    const int64_t ko = (int64_t)kt * TK;
+    f[0] = ldfrag(tp[0] + ko);
+    f[1] = ldfrag(tp[1] + ko);
+  };
+  const int nk = (kdim + TK - 1) / TK;
+  Stage ra, rn;
+  bf16x8 fa[2], fn[2];
+  if (nk > 0) {
+    frags(0, fa);  // issued first, so that the wait for the staged operands covers it
+    load(0, ra);
+    store(0, ra);
+  }
+  if (nk > 1) load(TK, ra);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 2 < nk) load((kt + 2) * TK, rn);
+    if (kt + 1 < nk) frags(kt + 1, fn);
+    const int c = lane & 15;
+    const bf16x8 rh = ldfrag(&Bs[buf][0][c][kg]), rl = ldfrag(&Bs[buf][1][c][kg]);
+    const bf16x8 ih = ldfrag(&Bs[buf][2][c][kg]), il = ldfrag(&Bs[buf][3][c][kg]);
+    acc[0] = mfma3(fa[0], fa[1], rh, rl, acc[0]);
+    acc[1] = mfma3(fa[0], fa[1], ih, il, acc[1]);
+    if (kt + 1 < nk) store(buf ^ 1, ra);
+    ra = rn;
+    fa[0] = fn[0];
+    fa[1] = fn[1];
+    __syncthreads();
+  }
+  const int kk = kk0 + (lane & 15);
+  if (kk >= nz) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = row0 + wave * 16 + 4 * (lane >> 4) + v;
+    if (r < rows) Y[(int64_t)r * nz + kk] = make_double2(acc[0][v], acc[1][v]);
+  }
+}
+
 mlg_status check(const char* what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(MLG_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -404,6 +509,31 @@ mlg_status launch_split_proj(const mlg_plan_s* p, double* const* in3, double* co
   split_proj_kernel<<<xcd_blocks(a.gx, a.gy, a.gz), 256, 0, s>>>(a);
   p->timing.end(s);
   return check("split_proj_kernel");
+}
+
+mlg_status launch_split_scalar(const mlg_plan_s* p, int dir, const double* in, double* out, hipStream_t s) {
+  const bool fwd = dir < 0;
+  SplitScalarArgs a{};
+  for (int t = 0; t < 2; ++t) a.tab[t] = fwd ? p->d_split_prj[t] : p->d_split_syn[t];
+  a.toff = fwd ? p->d_split_prj_off : p->d_split_syn_off;
+  a.kpad = p->d_split_syn_kpad;
+  a.ipad = p->split_ipad;
+  a.in = reinterpret_cast<const double2*>(in);
+  a.out = reinterpret_cast<double2*>(out);
+  a.off = p->d_goff;
+  a.nr = p->nr;
+  a.nrc = p->nrc;
+  a.nz = p->nz;
+  a.gx = (p->nz + TC - 1) / TC;
+  a.gy = ((fwd ? p->nrc : p->nr) + TM - 1) / TM;
+  a.gz = p->M;
+  p->timing.begin("radial_gemm", s);
+  if (fwd)
+    split_scalar_kernel<true><<<xcd_blocks(a.gx, a.gy, a.gz), 256, 0, s>>>(a);
+  else
+    split_scalar_kernel<false><<<xcd_blocks(a.gx, a.gy, a.gz), 256, 0, s>>>(a);
+  p->timing.end(s);
+  return check("split_scalar_kernel");
 }
 
 }  // namespace mlg

@@ -171,6 +171,8 @@ mlg_status launch_split_synth(const mlg_plan_s* p, const double* psi, const doub
                               hipStream_t s);
 mlg_status launch_split_proj(const mlg_plan_s* p, double* const* in3, double* const* out3, int mmax, int kmax,
                              hipStream_t s);
+// split-bfloat16 radial products of the scalar transform pair: dir > 0 backward, dir < 0 forward
+mlg_status launch_split_scalar(const mlg_plan_s* p, int dir, const double* in, double* out, hipStream_t s);
 // step.hip: semi-implicit operators and the step kernel (mode 0 FE-BE, 1 AB-CN; which 0: h = dt/2, 1: h = dt)
 mlg_status step_setup(mlg_plan_s* p, const mlg_dissip* d);
 mlg_status launch_step(const mlg_plan_s* p, int mode, int which, const double* s, const double* a1, const double* a0,

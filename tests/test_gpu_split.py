@@ -2,7 +2,8 @@
 
 The split mode computes every radial product as hi_a hi_b + hi_a lo_b + lo_a hi_b of bfloat16
 parts with FP32 accumulation (relative error ~2^-17 per term); FFTs, the cross product and the
-elliptic solves stay FP64.  The errors are measured normwise at each tap point and must stay
+elliptic solves stay FP64.  The scalar transform pair and the scalar nonlinear term use split
+radial products too and must stay within 5e-5 of the oracle.  The errors are measured normwise at each tap point and must stay
 within 5e-5 for the nodal fields and sources.  The solved potentials inherit the conditioning of
 the discrete projection (the Laplacian solves have cond ~1e9 at N_r = 256): the ~5e-6 errors of
 N are amplified, in the coefficients of (psi_N, chi_N) and in the velocity V(psi_N, chi_N) they
@@ -15,7 +16,8 @@ import pytest
 import synth
 from helpers import from_lib, rel, to_lib
 from oracle.grid import Grid
-from oracle.rhs import VecTables, rhs_tp, synthesize
+from oracle.rhs import VecTables, rhs_scalar, rhs_tp, synthesize
+from oracle.transform import Tables, backward, forward
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -66,3 +68,47 @@ def test_split_rhs_tp_error(case):
     for nm in names + ["C", "K", "Z"]:
         assert errs[nm] < 5e-5, (nm, errs[nm])
     assert errs["V(psi_N,chi_N)"] < 2e-2 and errs["psi_N"] < 1e-1 and errs["chi_N"] < 1e-1
+
+
+SCALAR_CASES = [
+    # nr, nphi, nz, ell, lz, nrc, dealias, kind
+    (32, 16, 1, 1.0, 2 * np.pi, 0, 1, "kpp"),   # 2D polar, N_z = 1
+    (80, 24, 12, 1.3, 2.0, 0, 0, "u2"),          # two 64-row tiles, ragged; contraction over 3 k steps
+    (100, 20, 40, 0.7, 5.0, 90, 1, "kpp"),       # radial chop N_r^c = 90 < N_r, factors 5
+    (20, 256, 256, 1.1, 3.0, 0, 1, "u2"),        # 256-point FFTs in phi and z
+    (32, 32, 4, 1.0, 2.0, 8, 0, "u2"),           # N_r^c = 8 < M = 16: orders m >= 8 have no degrees
+]
+
+
+@pytest.mark.parametrize("case", SCALAR_CASES)
+def test_split_scalar_error(case):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_18026_amd import MLG_RHS_KPP, MLG_RHS_U2, MLG_SPLIT_BF16, Plan
+    nr, nphi, nz, ell, lz, nrc, dealias, kind = case
+    print("split scalar", case, flush=True)
+    g = Grid(nr, nphi, nz, ell, lz=lz, nrc=nrc)
+    t = Tables(g)
+    plan = Plan(nr, nphi, nz, ell, lz, nrc=nrc, dealias=dealias, prec=MLG_SPLIT_BF16)
+    errs = {}
+    s = np.random.default_rng(200 + nr).standard_normal((nz, nr, nphi))
+    spec = plan.empty_spec()
+    plan.forward(torch.from_numpy(s).cuda(), spec)
+    torch.cuda.synchronize()
+    errs["forward"] = rel(from_lib(spec.cpu().numpy(), g.M, g.nrc), forward(s, g, t))
+    C = synth.geometric_spectrum(g.M, g.nrc, nz, g.nzc, seed=8, a=0.9, b=0.9, c=0.9)
+    Cd = torch.from_numpy(to_lib(C)).cuda()
+    phys = plan.empty_phys()
+    plan.backward(Cd, phys)
+    torch.cuda.synchronize()
+    errs["backward"] = rel(phys.cpu().numpy(), backward(C, g, t))
+    out = plan.empty_spec()
+    plan.rhs_scalar(MLG_RHS_U2 if kind == "u2" else MLG_RHS_KPP, 0.25, Cd, out)
+    torch.cuda.synchronize()
+    got = from_lib(out.cpu().numpy(), g.M, g.nrc)
+    errs["rhs_scalar"] = rel(got, rhs_scalar(C, g, t, kind, 0.25, dealias=bool(dealias)))
+    print("  split-bf16 relative errors:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v < 5e-5, (k, v)
+    if dealias:
+        assert np.all(got[g.dealias_m() + 1:] == 0)
