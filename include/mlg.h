@@ -59,10 +59,11 @@ typedef enum {
   MLG_FP64 = 0,        /* double data, FP64 arithmetic (MFMA f64 for the radial products)    */
   MLG_FP32 = 1,        /* batches only: float data and streamed tables (built in FP64),       */
                        /* FP32 arithmetic                                                    */
-  MLG_SPLIT_BF16 = 2   /* plans only: double data; the radial products of the vector RHS as   */
-                       /* hi/lo bfloat16 splits on MFMA with FP32 accumulation                */
-                       /* (a_hi b_hi + a_hi b_lo + a_lo b_hi); FFTs, pointwise products and   */
-                       /* solves stay FP64                                                    */
+  MLG_SPLIT_BF16 = 2   /* plans only: double data; every radial product (transform pair,      */
+                       /* scalar and vector RHS) and, for N_z = 256, the z transforms as two  */
+                       /* radix-16 DFT products, on MFMA with hi/lo bfloat16 operands and FP32 */
+                       /* accumulation (a_hi b_hi + a_hi b_lo + a_lo b_hi); the phi FFTs,     */
+                       /* pointwise products and solves stay FP64                             */
 } mlg_precision;
 
 enum { MLG_RHS_U2 = 0, MLG_RHS_KPP = 1 };

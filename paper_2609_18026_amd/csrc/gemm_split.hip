@@ -452,6 +452,115 @@ __global__ __launch_bounds__(256) void split_scalar_kernel(SplitScalarArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- z transforms as DFT products
+// N_z = 256 = 16 x 16 (Cooley-Tukey): with n = 16 n1 + n2 and k = k1 + 16 k2,
+//   X[k1 + 16 k2] = sum_n2 W16^(n2 k2) W256^(n2 k1) sum_n1 W16^(n1 k1) x[16 n1 + n2],
+// W_N = exp(+-2 pi i / N).  Both radix-16 stages are 16 x 16 complex matrix products on MFMA in the
+// real form [[Fr, -Fi], [Fi, Fr]] with split-bfloat16 operands and FP32 accumulation.  Stage 1
+// takes the line as its A operand: lane l = 16 g + n2 supplies x[l + 64 j], j = 0..3 (n1 = g + 4 j,
+// re and im interleaved along the contraction), so the loads are coalesced.  Its accumulators hold
+// Y[k1 = l % 16][n2 = 4 g + v], v = 0..3, which after the twiddle W256^(n2 k1) are exactly the
+// lane's B operand of stage 2 (contraction over n2 = 4 g + v); stage 2 leaves X[l % 16 + 16 (4 g + v)]
+// in the lane.  No LDS and no lane exchange; the per-lane constants come from a plan table.
+struct ZdftArgs {
+  const uint4* tab;     // [dir][lane][10] (40 words, see plan construction)
+  const double2* in[6];
+  double2* out[6];
+  int64_t rows;         // lines per field
+  int64_t lines;        // rows x fields
+  int nzc;
+  const int32_t* row_m;
+  int mask_m, mask_k;
+};
+constexpr int ZD_LPW = 4;  // lines per wave, loaded together
+
+__device__ __forceinline__ bool zkept(int kk, int nzc) {
+  const int k = (kk < 128) ? kk : kk - 256;
+  return k != -128 && (k < 0 ? -k : k) < nzc;
+}
+
+template <bool INV>
+__global__ __launch_bounds__(256) void split_zdft_kernel(ZdftArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t L0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * ZD_LPW;
+  if (L0 >= a.lines) return;
+  const int g = lane >> 4, c = lane & 15;
+  double2 d[ZD_LPW][4];
+#pragma unroll
+  for (int t = 0; t < ZD_LPW; ++t) {
+    const int64_t L = L0 + t < a.lines ? L0 + t : L0;  // the last wave may hold fewer lines
+    const int64_t f = L / a.rows, row = L - f * a.rows;
+    const double2* __restrict__ x = a.in[f] + row * 256;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) d[t][j] = x[lane + 64 * j];
+  }
+  const uint4* __restrict__ T = a.tab + ((INV ? 0 : 1) * 64 + lane) * 10;
+  const bf16x8 b1rh = __builtin_bit_cast(bf16x8, T[0]), b1rl = __builtin_bit_cast(bf16x8, T[1]);
+  const bf16x8 b1ih = __builtin_bit_cast(bf16x8, T[2]), b1il = __builtin_bit_cast(bf16x8, T[3]);
+  const bf16x8 a2rh = __builtin_bit_cast(bf16x8, T[4]), a2rl = __builtin_bit_cast(bf16x8, T[5]);
+  const bf16x8 a2ih = __builtin_bit_cast(bf16x8, T[6]), a2il = __builtin_bit_cast(bf16x8, T[7]);
+  const float4 t01 = __builtin_bit_cast(float4, T[8]), t23 = __builtin_bit_cast(float4, T[9]);
+  const float twr[4] = {t01.x, t01.z, t23.x, t23.z}, twi[4] = {t01.y, t01.w, t23.y, t23.w};
+  const floatx4 zero = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < ZD_LPW; ++t) {
+    const int64_t L = L0 + t;
+    if (L >= a.lines) break;
+    // stage 1: A operand (re, im of x[l + 64 j]); the inverse transform drops the unkept slots
+    u16x8 ah, al;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      double2 v = d[t][j];
+      if (INV && !zkept(lane + 64 * j, a.nzc)) v = make_double2(0.0, 0.0);
+      unsigned short h, l;
+      split2(v.x, h, l);
+      ah[2 * j] = h;
+      al[2 * j] = l;
+      split2(v.y, h, l);
+      ah[2 * j + 1] = h;
+      al[2 * j + 1] = l;
+    }
+    const bf16x8 xh = __builtin_bit_cast(bf16x8, ah), xl = __builtin_bit_cast(bf16x8, al);
+    const floatx4 yr = mfma3(xh, xl, b1rh, b1rl, zero);
+    const floatx4 yi = mfma3(xh, xl, b1ih, b1il, zero);
+    // twiddle, then the stage-2 B operand (re, im of Y'[k1][4 g + v])
+    u16x8 bh, bl;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float re = yr[v] * twr[v] - yi[v] * twi[v];
+      const float im = yr[v] * twi[v] + yi[v] * twr[v];
+      unsigned short h, l;
+      split2(re, h, l);
+      bh[2 * v] = h;
+      bl[2 * v] = l;
+      split2(im, h, l);
+      bh[2 * v + 1] = h;
+      bl[2 * v + 1] = l;
+    }
+    const bf16x8 yh = __builtin_bit_cast(bf16x8, bh), yl = __builtin_bit_cast(bf16x8, bl);
+    const floatx4 zr = mfma3(a2rh, a2rl, yh, yl, zero);
+    const floatx4 zi = mfma3(a2ih, a2il, yh, yl, zero);
+    const int64_t f = L / a.rows, row = L - f * a.rows;
+    double2* __restrict__ y = a.out[f] + row * 256;
+    const int mrow = (!INV && a.row_m) ? a.row_m[row] : 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int kk = c + 16 * (4 * g + v);
+      double2 o = make_double2((double)zr[v], (double)zi[v]);
+      if (!INV) {
+        o = make_double2(o.x * (1.0 / 256.0), o.y * (1.0 / 256.0));
+        bool keep = zkept(kk, a.nzc);
+        if (a.row_m) {
+          const int k = (kk < 128) ? kk : kk - 256;
+          keep = keep && mrow <= a.mask_m && (k < 0 ? -k : k) <= a.mask_k;
+        }
+        if (!keep) o = make_double2(0.0, 0.0);
+      }
+      y[kk] = o;
+    }
+  }
+}
+
 mlg_status check(const char* what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(MLG_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -534,6 +643,34 @@ mlg_status launch_split_scalar(const mlg_plan_s* p, int dir, const double* in, d
     split_scalar_kernel<false><<<xcd_blocks(a.gx, a.gy, a.gz), 256, 0, s>>>(a);
   p->timing.end(s);
   return check("split_scalar_kernel");
+}
+
+mlg_status launch_split_zdft(const mlg_plan_s* p, const double* const* in, double* const* out, int nf, int64_t rows,
+                             int dir, const int32_t* row_m, int mask_m, int mask_k, hipStream_t s) {
+  if (rows <= 0 || nf <= 0) return MLG_OK;
+  if (nf > 6) return fail(MLG_E_ARG, "z transform: 1 to 6 fields per launch");
+  if (p->nz != 256 || !p->d_split_zdft) return fail(MLG_E_UNSUPPORTED, "split z transform: N_z = 256 split plans only");
+  ZdftArgs a{};
+  a.tab = reinterpret_cast<const uint4*>(p->d_split_zdft);
+  for (int i = 0; i < nf; ++i) {
+    a.in[i] = reinterpret_cast<const double2*>(in[i]);
+    a.out[i] = reinterpret_cast<double2*>(out[i]);
+  }
+  a.rows = rows;
+  a.lines = rows * nf;
+  a.nzc = p->nzc;
+  a.row_m = row_m;
+  a.mask_m = mask_m;
+  a.mask_k = mask_k;
+  const int64_t waves = (a.lines + ZD_LPW - 1) / ZD_LPW;
+  const unsigned blocks = (unsigned)((waves + 3) / 4);
+  p->timing.begin("z_fft", s);
+  if (dir > 0)
+    split_zdft_kernel<true><<<blocks, 256, 0, s>>>(a);
+  else
+    split_zdft_kernel<false><<<blocks, 256, 0, s>>>(a);
+  p->timing.end(s);
+  return check("split_zdft_kernel");
 }
 
 }  // namespace mlg

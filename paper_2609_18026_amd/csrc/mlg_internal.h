@@ -99,6 +99,7 @@ struct mlg_plan_s {
   unsigned short* d_split_prj[4] = {nullptr, nullptr, nullptr, nullptr};  // W Pbar hi/lo, W Q hi/lo [n-m][ipad]
   int64_t* d_split_prj_off = nullptr;
   int split_ipad = 0;
+  uint32_t* d_split_zdft = nullptr;  // N_z = 256 split plans: DFT-product constants [dir][lane][40 words]
   // semi-implicit step operators (mlg_step_setup): per m, X_m = G_m L / ell^2 restricted to
   // n >= max(m, 1) is L^{-1/2} Q diag(lam) Q^T L^{1/2}; the step applies scalar functions of
   // lam + kappa^2 between the two products
@@ -173,6 +174,10 @@ mlg_status launch_split_proj(const mlg_plan_s* p, double* const* in3, double* co
                              hipStream_t s);
 // split-bfloat16 radial products of the scalar transform pair: dir > 0 backward, dir < 0 forward
 mlg_status launch_split_scalar(const mlg_plan_s* p, int dir, const double* in, double* out, hipStream_t s);
+// split-bfloat16 z transforms of N_z = 256 as two radix-16 DFT products on MFMA (same arguments
+// and masks as launch_zfft256)
+mlg_status launch_split_zdft(const mlg_plan_s* p, const double* const* in, double* const* out, int nf, int64_t rows,
+                             int dir, const int32_t* row_m, int mask_m, int mask_k, hipStream_t s);
 // step.hip: semi-implicit operators and the step kernel (mode 0 FE-BE, 1 AB-CN; which 0: h = dt/2, 1: h = dt)
 mlg_status step_setup(mlg_plan_s* p, const mlg_dissip* d);
 mlg_status launch_step(const mlg_plan_s* p, int mode, int which, const double* s, const double* a1, const double* a0,

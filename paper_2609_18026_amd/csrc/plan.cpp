@@ -150,7 +150,7 @@ void free_plan_device(mlg_plan_s* p) {
                   p->d_row_m, p->d_desc_fwd, p->d_desc_bwd, p->d_gram, p->d_goff,
                   p->d_split_syn[0], p->d_split_syn[1], p->d_split_syn[2], p->d_split_syn[3],
                   p->d_split_syn_off, p->d_split_syn_kpad, p->d_split_prj[0], p->d_split_prj[1],
-                  p->d_split_prj[2], p->d_split_prj[3], p->d_split_prj_off, p->d_step_fwd,
+                  p->d_split_prj[2], p->d_split_prj[3], p->d_split_prj_off, p->d_split_zdft, p->d_step_fwd,
                   p->d_step_bwd, p->d_step_lam, p->d_step_u, p->d_step_qoff, p->d_step_loff, p->d_step_w};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -270,6 +270,43 @@ mlg_status build_plan(mlg_plan_s* p) {
     if ((st2 = upload(&p->d_split_syn_off, soff)) || (st2 = upload(&p->d_split_syn_kpad, kpad)) ||
         (st2 = upload(&p->d_split_prj_off, poff)))
       return st2;
+    if (nz == 256) {
+      // z transforms as two radix-16 DFT products (n = 16 n1 + n2, k = k1 + 16 k2).  Per direction
+      // (0: inverse, exp(+i ...); 1: forward, exp(-i ...)) and lane l = 16 g + c, 40 words: the
+      // stage-1 B operands (column k1 = c, contraction rows n1 = g + 4 j, re / im interleaved) of
+      // the real and imaginary outputs, the stage-2 A operands (row k2 = c, contraction n2 = 4 g + j),
+      // each as bfloat16 hi and lo, then the FP32 twiddles W_256^(n2 k1), n2 = 4 g + j, k1 = c.
+      std::vector<uint32_t> zt((size_t)2 * 64 * 40, 0);
+      const ld pi2 = 2 * acosl(-1.0L);
+      for (int d = 0; d < 2; ++d) {
+        const ld sg = d == 0 ? 1.0L : -1.0L;
+        for (int l = 0; l < 64; ++l) {
+          const int gg = l >> 4, c = l & 15;
+          uint16_t h[8][8], lo[8][8];  // [operand][element]: B1re, B1im, A2re, A2im (hi / lo)
+          float tw[8];
+          for (int j = 0; j < 4; ++j) {
+            const ld a1 = pi2 * (ld)(((gg + 4 * j) * c) & 15) / 16.0L;
+            const ld a2 = pi2 * (ld)((c * (4 * gg + j)) & 15) / 16.0L;
+            const ld a3 = pi2 * (ld)(((4 * gg + j) * c) & 255) / 256.0L;
+            const double c1 = (double)cosl(a1), s1 = (double)(sg * sinl(a1));
+            const double c2 = (double)cosl(a2), s2 = (double)(sg * sinl(a2));
+            const double vals[4][2] = {{c1, -s1}, {s1, c1}, {c2, -s2}, {s2, c2}};
+            for (int o = 0; o < 4; ++o)
+              for (int q = 0; q < 2; ++q) split_into(vals[o][q], &h[o][2 * j + q], &lo[o][2 * j + q]);
+            tw[2 * j] = (float)cosl(a3);
+            tw[2 * j + 1] = (float)(sg * sinl(a3));
+          }
+          uint32_t* w = &zt[((size_t)d * 64 + l) * 40];
+          for (int o = 0; o < 4; ++o)
+            for (int e = 0; e < 4; ++e) {
+              w[8 * o + e] = (uint32_t)h[o][2 * e] | ((uint32_t)h[o][2 * e + 1] << 16);
+              w[8 * o + 4 + e] = (uint32_t)lo[o][2 * e] | ((uint32_t)lo[o][2 * e + 1] << 16);
+            }
+          std::memcpy(&w[32], tw, sizeof(tw));
+        }
+      }
+      if ((st2 = upload(&p->d_split_zdft, zt))) return st2;
+    }
   }
   // ---------------- Gram factors for the elliptic solves
   GramFactors gf;

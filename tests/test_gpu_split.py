@@ -1,9 +1,10 @@
 """Split-bfloat16 radial products (MLG_SPLIT_BF16 plans) against the FP64 oracle.
 
 The split mode computes every radial product as hi_a hi_b + hi_a lo_b + lo_a hi_b of bfloat16
-parts with FP32 accumulation (relative error ~2^-17 per term); FFTs, the cross product and the
+parts with FP32 accumulation (relative error ~2^-17 per term); for N_z = 256 the z transforms are
+two radix-16 DFT products in the same arithmetic.  The phi FFTs, the cross product and the
 elliptic solves stay FP64.  The scalar transform pair and the scalar nonlinear term use split
-radial products too and must stay within 5e-5 of the oracle.  The errors are measured normwise at each tap point and must stay
+products too and must stay within 5e-5 of the oracle.  The errors are measured normwise at each tap point and must stay
 within 5e-5 for the nodal fields and sources.  The solved potentials inherit the conditioning of
 the discrete projection (the Laplacian solves have cond ~1e9 at N_r = 256): the ~5e-6 errors of
 N are amplified, in the coefficients of (psi_N, chi_N) and in the velocity V(psi_N, chi_N) they
