@@ -39,21 +39,21 @@ U_FRAME = (0.0, 1.0, 0.0)
 # kernel source hashes to the one that was measured (profiles/rhs_tp_256cubed_kernels.md).
 _SUMMARY = "profiles/rhs_tp_256cubed_kernels.md"
 MEASURED_TRAFFIC = {
-    "synth_gemm": {"bytes": 1195224939, "launches": 1, "n": 256,
+    "synth_gemm": {"bytes": 1193291776, "launches": 1, "n": 256,
                    "source": "paper_2609_18026_amd/csrc/gemm_fold.hip",
-                   "sha256": "39370186ae76d38232939b61bc09a932dc2788bec316ed2ba7cd426fd1d61058"},
-    "proj_gemm": {"bytes": 434965752, "launches": 1, "n": 256,
+                   "sha256": "6e1cbf1744dd152785f555bb7a6064158993c072d8ab9d7eaa6db1d68bd81fcf"},
+    "proj_gemm": {"bytes": 435937280, "launches": 1, "n": 256,
                   "source": "paper_2609_18026_amd/csrc/gemm_fold.hip",
-                  "sha256": "39370186ae76d38232939b61bc09a932dc2788bec316ed2ba7cd426fd1d61058"},
-    "phi_fft": {"bytes": 1208442650, "launches": 1, "n": 256,
+                  "sha256": "6e1cbf1744dd152785f555bb7a6064158993c072d8ab9d7eaa6db1d68bd81fcf"},
+    "phi_fft": {"bytes": 1208442880, "launches": 1, "n": 256,
                 "source": "paper_2609_18026_amd/csrc/fft256.hip",
-                "sha256": "81b5eac065760fa00828034a90ad3dcab894957323696e38466c8589c4d9ea19"},
-    "z_fft": {"bytes": 1610784768 + 541225856, "launches": 2, "n": 256,
+                "sha256": "93a06b07484b790647c3f80faaeb11a12efd4b135ae8bd5e55a626eb1f9e92f9"},
+    "z_fft": {"bytes": 1610766336 + 541227008, "launches": 2, "n": 256,
               "source": "paper_2609_18026_amd/csrc/fft256.hip",
-              "sha256": "81b5eac065760fa00828034a90ad3dcab894957323696e38466c8589c4d9ea19"},
-    "projection": {"bytes": 742007834 + 102792000, "launches": 2, "n": 256,
+              "sha256": "93a06b07484b790647c3f80faaeb11a12efd4b135ae8bd5e55a626eb1f9e92f9"},
+    "projection": {"bytes": 741985280 + 102808576, "launches": 2, "n": 256,
                    "source": "paper_2609_18026_amd/csrc/kernels.hip",
-                   "sha256": "ed5ed6064113d22b5ef52ca2f5eeb63fd5f826454ad2e28d5825c29fa564fb17"},
+                   "sha256": "9edd59ed0753de21a9839094ec5436091a62696e64b9a5620426e523d50595b7"},
 }
 
 
@@ -356,13 +356,28 @@ def main():
         sys.exit(2)
     import torch
     from paper_2609_18026_amd import Plan, mlg_timing_enable, mlg_timing_read
+    # a plain 256 MiB device copy: the HBM counter reference (--calibrate-copy) and the practical
+    # read + write rate the streaming kernels are compared with
+    src = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
     if args.calibrate_copy:
-        src = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")  # 256 MiB
-        dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
         log("bench: calibration copy of 268435456 bytes x3 done")
+    dst.copy_(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_ms = c0.elapsed_time(c1) / 10
+    copy_ref = {"bytes_read_plus_written": 2 * 2 ** 28, "ms": round(copy_ms, 4),
+                "gbs": round(2 * 2 ** 28 / (copy_ms / 1e3) / 1e9, 1),
+                "frac_hbm_peak": round(2 * 2 ** 28 / (copy_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+    log(f"bench: plain 256 MiB device copy {copy_ref['gbs']:.0f} GB/s (read + write)")
+    del src, dst
     n = args.n
     plan = Plan(n, n, n, 1.0, PAIR["lz"], dealias=1)
     log(f"bench: plan {n}^3 ready, workspace {plan.layout.workspace_bytes / 2**30:.2f} GiB")
@@ -443,6 +458,7 @@ def main():
         "roofline": roofline,
         "kernels": per_kernel,
         "transform_pair": {"ms": round(pair_ms, 4), "gdofs": round(n ** 3 / (pair_ms / 1e3) / 1e9, 4)},
+        "hbm_copy_reference": copy_ref,
     }
     # split-bfloat16 radial products on the same state: time, and the error against the FP64 result
     # at the tap that is well conditioned: the velocity V(psi_N, chi_N) the potentials represent
@@ -459,7 +475,21 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     sms = e0.elapsed_time(e1) / args.steps
-    del splan
+    # the split transform pair (radial products and z transforms as split-bf16 DFT products) against
+    # the FP64 pair on the same field
+    sphys, sspec = splan.empty_phys(), splan.empty_spec()
+    splan.backward(psi, sphys)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        splan.backward(psi, sphys)
+        splan.forward(sphys, sspec)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    spair_ms = e0.elapsed_time(e1) / args.steps
+    perr = float(torch.linalg.vector_norm(sphys - phys) / torch.linalg.vector_norm(phys))
+    serr = float(torch.linalg.vector_norm(sspec - spec) / torch.linalg.vector_norm(spec))
+    del splan, sphys, sspec
     uw_ref = torch.empty(6 * plan.layout.phys_elems, dtype=torch.float64, device="cuda")
     uw_spl = torch.empty_like(uw_ref)
     plan.synthesize(ref_p, ref_c, uw_ref)
@@ -469,8 +499,12 @@ def main():
     verr = float(torch.linalg.vector_norm(uw_spl[:3 * pe] - uw_ref[:3 * pe]) / torch.linalg.vector_norm(uw_ref[:3 * pe]))
     cerr = float(torch.linalg.vector_norm(sp - ref_p) / torch.linalg.vector_norm(ref_p))
     out["split_bf16"] = {"ms_per_step": round(sms, 4), "gdofs": round(n ** 3 / (sms / 1e3) / 1e9, 4),
-                         "rel_err_velocity_of_output_vs_fp64": verr, "rel_err_psi_coefficients_vs_fp64": cerr}
-    log(f"bench: split-bf16 {sms:.3f} ms/step, velocity rel err {verr:.2e} (coefficients {cerr:.2e})")
+                         "rel_err_velocity_of_output_vs_fp64": verr, "rel_err_psi_coefficients_vs_fp64": cerr,
+                         "transform_pair_ms": round(spair_ms, 4),
+                         "transform_pair_gdofs": round(n ** 3 / (spair_ms / 1e3) / 1e9, 4),
+                         "rel_err_pair_backward_vs_fp64": perr, "rel_err_pair_forward_vs_fp64": serr}
+    log(f"bench: split-bf16 {sms:.3f} ms/step, velocity rel err {verr:.2e} (coefficients {cerr:.2e}); "
+        f"pair {spair_ms:.3f} ms, rel err {perr:.2e} / {serr:.2e}")
     out["batched_2d"] = bench_batched(torch, args, stream, e0, e1)
     out["time_step"] = bench_time_step(torch, plan, psi, chi, args, stream, e0, e1)
     if not args.no_closure:

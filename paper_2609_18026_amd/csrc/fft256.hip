@@ -53,7 +53,7 @@ __device__ __forceinline__ bool kkept(int kk, int nz, int nzc) {
 
 // ---------------------------------------------------------------- azimuthal stages
 // Line q = i N_z + l; physical samples at (l N_r + i) 256 + j; harmonic m at m * nlines + q.
-constexpr int PL = 8;  // lines per block (128 threads, 16 per line)
+constexpr int PL = 8;  // lines per block
 
 struct Phi256 {
   int nr, nz, M, mkeep;
