@@ -168,6 +168,34 @@ mlg_status mlg_step_febe(mlg_plan plan, int half, const void* s, const void* A, 
  * share its step scratch and must not overlap. */
 mlg_status mlg_step_abcn(mlg_plan plan, const void* s, const void* A_now, const void* A_prev, void* out, void* stream);
 
+/* Adaptive modal filter (Sec. 3.3, the paragraph on aliasing and dissipation), applied between
+ * steps.  Every stored coefficient s_{n m k} of a field whose normalised index
+ *   zeta = max(n / N_r^c, m / N_phi^c, |k| / N_z^c)
+ * exceeds zeta_c is multiplied by exp(-eps ((zeta - zeta_c) / (1 - zeta_c))^8).  The amplitude eps
+ * follows the fraction f of the field's coefficient energy (sum of |s|^2 over the stored
+ * coefficients) held above zeta_c: each application measures f, moves eps towards
+ * eps_max * clip((f - tau) / tau, 0, 1) by the fraction 'relax', then filters with the new eps.
+ * eps starts at 0, so the filter stays inactive while f < tau; it is bounded by eps_max and each
+ * field (slot 0: psi, slot 1: chi) keeps its own state on the device. */
+typedef struct {
+  double zeta_c;   /* cutoff, 0 <= zeta_c < 1 (2/3 is the value this library's driver uses)     */
+  double tau;      /* target tail fraction, > 0 (the paper's default 2e-2)                      */
+  double eps_max;  /* saturation amplitude, >= 0 (36: exp(-36) ~ 2e-16 at the last index)      */
+  double relax;    /* relaxation per application, 0 < relax <= 1                               */
+} mlg_filter_cfg;
+
+/* Enable the filter with 'cfg' and reset both states to eps = 0, f = 0 (cfg NULL disables it).
+ * While enabled, mlg_tp_advance filters psi (slot 0) and chi (slot 1) after every step.
+ * Allocates the state on the first call; synchronises the device.  Errors: MLG_E_ARG for a
+ * parameter out of range or non-finite, MLG_E_ALLOC. */
+mlg_status mlg_filter_setup(mlg_plan plan, const mlg_filter_cfg* cfg);
+/* One application to the packed spectral field 'spec' (device, modified in place) with state
+ * slot 0 or 1; asynchronous on 'stream'.  Errors: MLG_E_ARG (filter not enabled, bad slot, NULL). */
+mlg_status mlg_filter_apply(mlg_plan plan, int32_t slot, void* spec, void* stream);
+/* Host copy of the state {eps_0, eps_1, f_0, f_1} (f: the tail fraction the last application
+ * measured).  Synchronises the device.  Errors: MLG_E_ARG (filter never enabled), MLG_E_DEVICE. */
+mlg_status mlg_filter_state(mlg_plan plan, double* out4);
+
 /* Nodal velocity and vorticity of a toroidal-poloidal pair (Sec. 3.2, Eq. tp):
  * u = curl(psi z) + curl curl(chi z), omega = curl u.  'uw' is a device buffer of
  * 6 * phys_elems reals receiving u_r, u_phi, u_z, w_r, w_phi, w_z (physical layout each).
@@ -309,7 +337,8 @@ mlg_status mlg_closure_stats(mlg_closure closure, int64_t* calls, int64_t* fallb
  * been called), with A = mlg_rhs_tp(U, psi, chi), corrected by 'closure' when non-NULL (its
  * plan must be 'plan').  start = 1: the first step is the Richardson start-up of Sec. 3.3 and
  * (hist_psi, hist_chi) are outputs; start = 0: they hold A^{j-1} from the previous call.  On
- * return they hold A of the last state a step started from.  psi, chi are advanced in place.
+ * return they hold A of the last state a step started from.  psi, chi are advanced in place and,
+ * when mlg_filter_setup has enabled the filter, filtered after every step.
  * tmp: device buffer of 6 * spec_elems complex128; ws: the plan workspace. */
 mlg_status mlg_tp_advance(mlg_plan plan, const double* U, void* psi, void* chi, void* hist_psi, void* hist_chi,
                           int32_t nsteps, int32_t start, mlg_closure closure, void* tmp, void* ws, void* stream);

@@ -46,7 +46,8 @@ EXPORTS = ["mlg_plan_create", "mlg_plan_destroy", "mlg_plan_query", "mlg_plan_no
            "mlg_timing_read",
            "mlg_batch_create", "mlg_batch_destroy", "mlg_batch_query", "mlg_batch_rhs_scalar", "mlg_batch_set_config",
            "mlg_batch_get_config", "mlg_batch_autotune", "mlg_step_setup", "mlg_step_febe", "mlg_step_abcn",
-           "mlg_truncate", "mlg_tp_advance", "mlg_closure_param_count", "mlg_closure_create", "mlg_closure_destroy",
+           "mlg_truncate", "mlg_tp_advance", "mlg_filter_setup", "mlg_filter_apply", "mlg_filter_state",
+           "mlg_closure_param_count", "mlg_closure_create", "mlg_closure_destroy",
            "mlg_closure_columns", "mlg_closure_set_params", "mlg_closure_get_params", "mlg_closure_get_grads",
            "mlg_closure_set_scales", "mlg_closure_get_scales", "mlg_closure_features", "mlg_closure_targets",
            "mlg_closure_forward", "mlg_closure_train_step", "mlg_closure_infer", "mlg_closure_stats",
@@ -61,6 +62,11 @@ class mlg_closure_cfg(ctypes.Structure):
 
 class mlg_dissip(ctypes.Structure):
     _fields_ = [("nu", ctypes.c_double), ("nu_h", ctypes.c_double), ("p", ctypes.c_int32), ("dt", ctypes.c_double)]
+
+
+class mlg_filter_cfg(ctypes.Structure):
+    _fields_ = [("zeta_c", ctypes.c_double), ("tau", ctypes.c_double), ("eps_max", ctypes.c_double),
+                ("relax", ctypes.c_double)]
 
 
 class mlg_batch_config(ctypes.Structure):
@@ -103,6 +109,9 @@ def lib() -> ctypes.CDLL:
     i64, f32 = ctypes.c_int64, ctypes.c_float
     L.mlg_truncate.argtypes = [vp, vp, vp, vp, vp]
     L.mlg_tp_advance.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp]
+    L.mlg_filter_setup.argtypes = [vp, ctypes.POINTER(mlg_filter_cfg)]
+    L.mlg_filter_apply.argtypes = [vp, i32, vp, vp]
+    L.mlg_filter_state.argtypes = [vp, ctypes.POINTER(f64)]
     L.mlg_closure_param_count.argtypes = []
     L.mlg_closure_create.argtypes = [ctypes.POINTER(mlg_closure_cfg), vp, ctypes.POINTER(vp)]
     L.mlg_closure_destroy.argtypes = [vp]
@@ -183,6 +192,25 @@ def mlg_rhs_tp(plan: int, U, psi: int, chi: int, psi_n: int, chi_n: int, taps: i
 def mlg_step_setup(plan: int, nu: float, nu_h: float, p: int, dt: float) -> None:
     d = mlg_dissip(nu, nu_h, p, dt)
     _check(lib().mlg_step_setup(plan, ctypes.byref(d)))
+
+
+def mlg_filter_setup(plan: int, zeta_c: float, tau: float, eps_max: float, relax: float) -> None:
+    c = mlg_filter_cfg(zeta_c, tau, eps_max, relax)
+    _check(lib().mlg_filter_setup(plan, ctypes.byref(c)))
+
+
+def mlg_filter_disable(plan: int) -> None:
+    _check(lib().mlg_filter_setup(plan, None))
+
+
+def mlg_filter_apply(plan: int, slot: int, spec: int, stream: int = 0) -> None:
+    _check(lib().mlg_filter_apply(plan, slot, spec, stream))
+
+
+def mlg_filter_state(plan: int):
+    out = (ctypes.c_double * 4)()
+    _check(lib().mlg_filter_state(plan, out))
+    return tuple(out)
 
 
 def mlg_step_febe(plan: int, half: int, s: int, A: int, out: int, stream: int = 0) -> None:
@@ -386,6 +414,20 @@ class Plan:
 
     def step_setup(self, nu, nu_h=0.0, p=8, dt=1e-2):
         mlg_step_setup(self.handle, nu, nu_h, p, dt)
+
+    def filter_setup(self, zeta_c=2.0 / 3.0, tau=2e-2, eps_max=36.0, relax=0.1):
+        """Enable the adaptive modal filter (both states reset); mlg_tp_advance then filters every step."""
+        mlg_filter_setup(self.handle, zeta_c, tau, eps_max, relax)
+
+    def filter_disable(self):
+        mlg_filter_disable(self.handle)
+
+    def filter_apply(self, slot, spec):
+        mlg_filter_apply(self.handle, slot, spec.data_ptr(), self._stream())
+
+    def filter_state(self):
+        """(eps_psi, eps_chi, f_psi, f_chi) after the last application (synchronises)."""
+        return mlg_filter_state(self.handle)
 
     def step_febe(self, half, s, A, out):
         mlg_step_febe(self.handle, half, s.data_ptr(), A.data_ptr(), out.data_ptr(), self._stream())

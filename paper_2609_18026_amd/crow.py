@@ -9,7 +9,9 @@ the dissipation of Eq. dissipation (nu, nu_h, order p).  The axial modal energie
 mlg_tp_energy, and the growth rate of the seeded fundamental is reported in units of
 Gamma / (2 pi b^2): alpha = (pi b^2 / Gamma) d ln E_1 / dt, with E_1 the energy of k = +1 and -1.
 
-Every step runs in the library's kernels; this module only sequences the calls and fits rates.
+With --filter 1 the adaptive modal filter of Sec. 3.3 (mlg_filter_setup) runs between steps, as in
+the paper's runs.  Every step runs in the library's kernels; this module only sequences the calls
+and fits rates.
 
     python -m paper_2609_18026_amd.crow --nr 96 --nphi 64 --nz 32 --dt 2e-3 --t-end 50
 """
@@ -44,6 +46,9 @@ class CrowSpec:
     sample_every: float = 0.5   # time between energy samples
     dealias: int = 1
     nrc: int = 0                # radial chop N_r^c (0: N_r, no radial margin)
+    filter: int = 0             # 1: the adaptive modal filter of Sec. 3.3 between steps
+    filter_zc: float = 2.0 / 3.0
+    filter_tau: float = 2e-2
 
 
 def _fit_rate(t: np.ndarray, lnE: np.ndarray, lo: float, hi: float):
@@ -63,6 +68,8 @@ def run(spec: CrowSpec, log=None) -> dict:
     lz = spec.lz_over_b * spec.b
     plan = Plan(spec.nr, spec.nphi, spec.nz, spec.ell, lz, nrc=spec.nrc, dealias=spec.dealias)
     plan.step_setup(spec.nu, spec.nu_h, spec.p, spec.dt)
+    if spec.filter:
+        plan.filter_setup(spec.filter_zc, spec.filter_tau)
     x, w, r = plan.nodes()
     phi = 2 * np.pi * np.arange(spec.nphi) / spec.nphi
     z = lz * np.arange(spec.nz) / spec.nz
@@ -74,12 +81,14 @@ def run(spec: CrowSpec, log=None) -> dict:
     U = (0.0, spec.gamma / (2 * math.pi * spec.b), 0.0)
     every = max(1, int(round(spec.sample_every / spec.dt)))
     nsteps = int(round(spec.t_end / spec.dt))
-    times, E = [], []
+    times, E, filt = [], [], []
 
     def sample(t):
         e = plan.energy(psi, chi).cpu().numpy()
         times.append(t)
         E.append(e)
+        if spec.filter:
+            filt.append(plan.filter_state())
         return e
 
     sample(0.0)
@@ -120,6 +129,7 @@ def run(spec: CrowSpec, log=None) -> dict:
         "E0": En[:, 0].tolist(),
         "E2": (En[:, 2] + En[:, -2]).tolist() if spec.nz > 4 else None,
         "alpha_local": local.tolist(),
+        "filter_state": filt if spec.filter else None,   # (eps_psi, eps_chi, f_psi, f_chi) per sample
     }
     for lo, hi in ((10.0, 18.0), (28.0, 38.0), (33.0, 50.0), (33.0, 60.0)):
         if hi > t[-1] + 1e-9:
@@ -138,7 +148,10 @@ def main(argv=None) -> int:
     args = ap.parse_args(argv)
     spec = CrowSpec(**{k: getattr(args, k) for k in asdict(d)})
     res = run(spec, log=lambda *a: print(*a, file=sys.stderr, flush=True))
-    brief = {k: v for k, v in res.items() if k not in ("t", "E1", "E0", "E2", "alpha_local")}
+    brief = {k: v for k, v in res.items() if k not in ("t", "E1", "E0", "E2", "alpha_local", "filter_state")}
+    if res.get("filter_state"):
+        brief["filter_eps_max_seen"] = [max(s[0] for s in res["filter_state"]), max(s[1] for s in res["filter_state"])]
+        brief["filter_tail_max_seen"] = [max(s[2] for s in res["filter_state"]), max(s[3] for s in res["filter_state"])]
     print(json.dumps(brief), flush=True)
     if args.out:
         with open(args.out, "w") as f:

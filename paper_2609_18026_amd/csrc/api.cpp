@@ -293,6 +293,58 @@ mlg_status mlg_step_abcn(mlg_plan p, const void* s, const void* A_now, const voi
                      static_cast<const double*>(A_prev), static_cast<double*>(out), static_cast<hipStream_t>(stream));
 }
 
+mlg_status mlg_filter_setup(mlg_plan p, const mlg_filter_cfg* cfg) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!cfg) {
+    p->filter_on = false;
+    return MLG_OK;
+  }
+  const double v[4] = {cfg->zeta_c, cfg->tau, cfg->eps_max, cfg->relax};
+  for (double x : v)
+    if (!std::isfinite(x)) return fail(MLG_E_ARG, "filter parameters must be finite");
+  if (cfg->zeta_c < 0.0 || cfg->zeta_c >= 1.0) return fail(MLG_E_ARG, "filter: 0 <= zeta_c < 1");
+  if (cfg->tau <= 0.0) return fail(MLG_E_ARG, "filter: tau must be > 0");
+  if (cfg->eps_max < 0.0) return fail(MLG_E_ARG, "filter: eps_max must be >= 0");
+  if (cfg->relax <= 0.0 || cfg->relax > 1.0) return fail(MLG_E_ARG, "filter: 0 < relax <= 1");
+  DeviceGuard guard(p->device);
+  const size_t bytes = (size_t)(4 + 2 * FILTER_BLOCKS) * sizeof(double);
+  if (!p->d_filter) {
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->d_filter), bytes);
+    if (e != hipSuccess) {
+      p->d_filter = nullptr;
+      return fail(MLG_E_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+  }
+  const double zero[4] = {0.0, 0.0, 0.0, 0.0};
+  MLG_HIP_TRY(hipDeviceSynchronize());
+  MLG_HIP_TRY(hipMemcpy(p->d_filter, zero, sizeof(zero), hipMemcpyHostToDevice));
+  p->filter_zc = cfg->zeta_c;
+  p->filter_tau = cfg->tau;
+  p->filter_epsmax = cfg->eps_max;
+  p->filter_relax = cfg->relax;
+  p->filter_on = true;
+  return MLG_OK;
+}
+
+mlg_status mlg_filter_apply(mlg_plan p, int32_t slot, void* spec, void* stream) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!p->filter_on) return fail(MLG_E_ARG, "mlg_filter_setup has not enabled the filter");
+  if (slot != 0 && slot != 1) return fail(MLG_E_ARG, "filter slot must be 0 or 1");
+  if (!spec) return fail(MLG_E_ARG, "null buffer");
+  DeviceGuard guard(p->device);
+  return launch_filter(p, slot, static_cast<double*>(spec), static_cast<hipStream_t>(stream));
+}
+
+mlg_status mlg_filter_state(mlg_plan p, double* out4) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!out4) return fail(MLG_E_ARG, "null buffer");
+  if (!p->d_filter) return fail(MLG_E_ARG, "mlg_filter_setup has never been called");
+  DeviceGuard guard(p->device);
+  MLG_HIP_TRY(hipDeviceSynchronize());
+  MLG_HIP_TRY(hipMemcpy(out4, p->d_filter, 4 * sizeof(double), hipMemcpyDeviceToHost));
+  return MLG_OK;
+}
+
 mlg_status mlg_tp_advance(mlg_plan p, const double* U, void* psi, void* chi, void* hist_psi, void* hist_chi,
                           int32_t nsteps, int32_t start, mlg_closure closure, void* tmp, void* ws, void* stream) {
   if (mlg_status st = check_plan(p)) return st;
@@ -315,6 +367,12 @@ mlg_status mlg_tp_advance(mlg_plan p, const double* U, void* psi, void* chi, voi
     if (mlg_status e = mlg_rhs_tp(p, U, a, b, ra, rb, nullptr, ws, stream)) return e;
     return closure ? closure_correct(closure, a, b, ra, rb, s) : MLG_OK;
   };
+  // the adaptive modal filter between steps (Sec. 3.3), when enabled
+  auto filter = [&]() -> mlg_status {
+    if (!p->filter_on) return MLG_OK;
+    if (mlg_status e = launch_filter(p, 0, sp, s)) return e;
+    return launch_filter(p, 1, sc, s);
+  };
   int done = 0;
   if (start) {
     // s1 = 2 S_{dt/2}(S_{dt/2}(s0)) - S_dt(s0), S_h(s) = (I - h L)^{-1} (s + h A(s))
@@ -328,6 +386,7 @@ mlg_status mlg_tp_advance(mlg_plan p, const double* U, void* psi, void* chi, voi
         (st = launch_step(p, 0, 0, t[5], t[1], nullptr, t[5], s)))
       return st;
     if ((st = launch_richardson(p, t[4], t[2], sp, s)) || (st = launch_richardson(p, t[5], t[3], sc, s))) return st;
+    if ((st = filter())) return st;
     done = 1;
   }
   // AB-CN: the nonlinear terms alternate between (hist) and (t0, t1); the step runs in place
@@ -337,6 +396,7 @@ mlg_status mlg_tp_advance(mlg_plan p, const double* U, void* psi, void* chi, voi
     if ((st = rhs(sp, sc, now[0], now[1]))) return st;
     if ((st = launch_step(p, 1, 0, sp, now[0], prev[0], sp, s)) || (st = launch_step(p, 1, 0, sc, now[1], prev[1], sc, s)))
       return st;
+    if ((st = filter())) return st;
     prev[0] = now[0];
     prev[1] = now[1];
   }

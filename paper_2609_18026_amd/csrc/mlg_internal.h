@@ -114,6 +114,11 @@ struct mlg_plan_s {
   double step_dt = 0, step_nu = 0, step_nuh = 0;
   int step_q = 1;                 // p / 2 (hyperviscosity power of grad^2), 1 when nu_h = 0
   bool step_ready = false;
+  // adaptive modal filter (mlg_filter_setup): d_filter holds [eps_psi, eps_chi, f_psi, f_chi] and
+  // then 2 * FILTER_BLOCKS partial sums
+  double* d_filter = nullptr;
+  bool filter_on = false;
+  double filter_zc = 0, filter_tau = 0, filter_epsmax = 0, filter_relax = 0;
   bool use_fast_fft = true;   // register-resident 256-point kernels when a length is 256
   bool use_fold = true;       // parity-folded radial products when N_r is even (MLG_RADIAL_FOLD=0 disables)
   int phi_rad[12] = {0};
@@ -185,6 +190,9 @@ mlg_status launch_step(const mlg_plan_s* p, int mode, int which, const double* s
 // s1 = 2 half - full over all spectral elements (the Richardson start-up of Sec. 3.3)
 mlg_status launch_richardson(const mlg_plan_s* p, const double* half, const double* full, double* out,
                              hipStream_t st);
+// adaptive modal filter of Sec. 3.3 on one packed spectral field with state slot 'slot' (0, 1)
+constexpr int FILTER_BLOCKS = 256;
+mlg_status launch_filter(const mlg_plan_s* p, int slot, double* spec, hipStream_t s);
 // closure.hip: features -> network -> judge -> corrected (rpsi, rchi), all on 'st'
 mlg_status closure_correct(mlg_closure_s* c, const double* psi, const double* chi, double* rpsi, double* rchi,
                            hipStream_t st);

@@ -151,7 +151,8 @@ void free_plan_device(mlg_plan_s* p) {
                   p->d_split_syn[0], p->d_split_syn[1], p->d_split_syn[2], p->d_split_syn[3],
                   p->d_split_syn_off, p->d_split_syn_kpad, p->d_split_prj[0], p->d_split_prj[1],
                   p->d_split_prj[2], p->d_split_prj[3], p->d_split_prj_off, p->d_split_zdft, p->d_step_fwd,
-                  p->d_step_bwd, p->d_step_lam, p->d_step_u, p->d_step_qoff, p->d_step_loff, p->d_step_w};
+                  p->d_step_bwd, p->d_step_lam, p->d_step_u, p->d_step_qoff, p->d_step_loff, p->d_step_w,
+                  p->d_filter};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }

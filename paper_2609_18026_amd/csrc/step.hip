@@ -312,6 +312,102 @@ __global__ __launch_bounds__(R0C * R0S) void step_row0_kernel(StepArgs a) {
   a.out[kk] = make_double2(phi * s0.x + psi * v.x + sr, phi * s0.y + psi * v.y + si);
 }
 
+
+// ---------------------------------------------------------------- adaptive modal filter
+// Sec. 3.3: every coefficient whose normalised index zeta = max(n / N_r^c, m / N_phi^c,
+// |k| / N_z^c) exceeds zeta_c is multiplied by exp(-eps ((zeta - zeta_c) / (1 - zeta_c))^8); eps
+// follows the fraction f of sum |s|^2 held above zeta_c: target eps_max clip((f - tau) / tau, 0, 1),
+// relaxed as eps <- eps + r (target - eps), one state per field.  Three launches: partial sums over
+// a fixed number of blocks (so the reduction order never depends on the device), the state update
+// in one block, and the scaling.  The state stays on the device: a time loop never waits for it.
+struct FilterArgs {
+  double2* spec;
+  const int32_t* row_m;
+  const int64_t* off;
+  int64_t rows;
+  int nz, nzc, nrc, M;
+  double zc, tau, eps_max, relax;
+  double* state;  // [eps_0, eps_1, f_0, f_1]
+  double* part;   // FILTER_BLOCKS x (tail, total)
+  int slot;
+};
+
+__device__ __forceinline__ double filter_zeta(const FilterArgs& a, int64_t row, int kk) {
+  const int m = a.row_m[row];
+  const int n = m + (int)(row - a.off[m]);
+  const int k = (2 * kk < a.nz) ? kk : kk - a.nz;
+  const double zr = (double)n / a.nrc, zp = (double)m / a.M, zz = (double)(k < 0 ? -k : k) / a.nzc;
+  return fmax(fmax(zr, zp), zz);
+}
+
+__global__ __launch_bounds__(256) void filter_sums_kernel(FilterArgs a) {
+  __shared__ double st[256], sa[256];
+  const int t = threadIdx.x;
+  double tail = 0.0, total = 0.0;
+  const int64_t n = a.rows * a.nz;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + t; e < n; e += (int64_t)FILTER_BLOCKS * 256) {
+    const int64_t row = e / a.nz;
+    const int kk = (int)(e - row * a.nz);
+    const double2 v = a.spec[e];
+    const double w = v.x * v.x + v.y * v.y;
+    total += w;
+    if (filter_zeta(a, row, kk) > a.zc) tail += w;
+  }
+  st[t] = tail;
+  sa[t] = total;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+      st[t] += st[t + h];
+      sa[t] += sa[t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    a.part[2 * blockIdx.x] = st[0];
+    a.part[2 * blockIdx.x + 1] = sa[0];
+  }
+}
+
+__global__ __launch_bounds__(FILTER_BLOCKS) void filter_update_kernel(FilterArgs a) {
+  __shared__ double st[FILTER_BLOCKS], sa[FILTER_BLOCKS];
+  const int t = threadIdx.x;
+  st[t] = a.part[2 * t];
+  sa[t] = a.part[2 * t + 1];
+  __syncthreads();
+  for (int h = FILTER_BLOCKS / 2; h > 0; h >>= 1) {
+    if (t < h) {
+      st[t] += st[t + h];
+      sa[t] += sa[t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double f = sa[0] > 0.0 ? st[0] / sa[0] : 0.0;
+    const double target = a.eps_max * fmin(fmax((f - a.tau) / a.tau, 0.0), 1.0);
+    const double e0 = a.state[a.slot];
+    a.state[a.slot] = e0 + a.relax * (target - e0);
+    a.state[2 + a.slot] = f;
+  }
+}
+
+__global__ __launch_bounds__(256) void filter_apply_kernel(FilterArgs a) {
+  const double eps = a.state[a.slot];
+  const int64_t n = a.rows * a.nz;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    const int64_t row = e / a.nz;
+    const int kk = (int)(e - row * a.nz);
+    const double zeta = filter_zeta(a, row, kk);
+    if (zeta > a.zc) {
+      const double x = (zeta - a.zc) / (1.0 - a.zc);
+      const double x2 = x * x, x4 = x2 * x2;
+      const double sg = exp(-eps * (x4 * x4));
+      const double2 v = a.spec[e];
+      a.spec[e] = make_double2(v.x * sg, v.y * sg);
+    }
+  }
+}
+
 }  // namespace
 
 mlg_status step_setup(mlg_plan_s* p, const mlg_dissip* d) {
@@ -480,6 +576,35 @@ mlg_status launch_richardson(const mlg_plan_s* p, const double* half, const doub
   p->timing.end(st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(MLG_E_DEVICE, std::string("richardson_kernel: ") + hipGetErrorString(e));
+  return MLG_OK;
+}
+
+mlg_status launch_filter(const mlg_plan_s* p, int slot, double* spec, hipStream_t st) {
+  FilterArgs a{};
+  a.spec = reinterpret_cast<double2*>(spec);
+  a.row_m = p->d_row_m;
+  a.off = p->d_goff;
+  a.rows = p->tau;
+  a.nz = p->nz;
+  a.nzc = p->nzc;
+  a.nrc = p->nrc;
+  a.M = p->M;
+  a.zc = p->filter_zc;
+  a.tau = p->filter_tau;
+  a.eps_max = p->filter_epsmax;
+  a.relax = p->filter_relax;
+  a.state = p->d_filter;
+  a.part = p->d_filter + 4;
+  a.slot = slot;
+  const int64_t n = a.rows * a.nz;
+  const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+  p->timing.begin("filter", st);
+  filter_sums_kernel<<<FILTER_BLOCKS, 256, 0, st>>>(a);
+  filter_update_kernel<<<1, FILTER_BLOCKS, 0, st>>>(a);
+  filter_apply_kernel<<<blocks, 256, 0, st>>>(a);
+  p->timing.end(st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(MLG_E_DEVICE, std::string("filter kernels: ") + hipGetErrorString(e));
   return MLG_OK;
 }
 

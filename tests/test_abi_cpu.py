@@ -61,3 +61,6 @@ def test_null_arguments_rejected(L):
     assert L.mlg_forward(None, None, None, None, None) == 1
     assert L.mlg_rhs_tp(None, None, None, None, None, None, None, None, None) == 1
     assert L.mlg_plan_destroy(None) == 0
+    assert L.mlg_filter_setup(None, None) == 1
+    assert L.mlg_filter_apply(None, 0, None, None) == 1
+    assert L.mlg_filter_state(None, None) == 1
