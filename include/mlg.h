@@ -138,7 +138,8 @@ mlg_status mlg_rhs_scalar(mlg_plan plan, int kind, double gamma, const void* spe
  * supported).  'taps' may be NULL; otherwise a device buffer of
  * 9 * phys_elems + 3 * spec_elems values (reals, then complex) receiving nodal
  * u_r, u_phi, u_z, w_r, w_phi, w_z, N_r, N_phi, N_z and the sources C, K, Zhat.
- * Requires N_r^c = N_r <= 512 (MLG_E_UNSUPPORTED otherwise). */
+ * A radial margin N_r^c < N_r (Sec. 3.3) is allowed: the products are formed on the N_r nodes and
+ * projected onto the degrees below N_r^c.  Requires N_r^c <= 512 (MLG_E_UNSUPPORTED otherwise). */
 mlg_status mlg_rhs_tp(mlg_plan plan, const double* U, const void* psi, const void* chi,
                       void* psi_n, void* chi_n, void* taps, void* ws, void* stream);
 

@@ -13,7 +13,7 @@ With --filter 1 the adaptive modal filter of Sec. 3.3 (mlg_filter_setup) runs be
 the paper's runs.  Every step runs in the library's kernels; this module only sequences the calls
 and fits rates.
 
-    python -m paper_2609_18026_amd.crow --nr 96 --nphi 64 --nz 32 --dt 2e-3 --t-end 50
+    python -m paper_2609_18026_amd.crow --nr 128 --nrc 96 --nphi 64 --nz 32 --dt 2e-3 --t-end 60
 """
 from __future__ import annotations
 
@@ -29,7 +29,7 @@ import numpy as np
 
 @dataclass
 class CrowSpec:
-    nr: int = 96
+    nr: int = 128
     nphi: int = 64
     nz: int = 32
     ell: float = 4.0        # map scale (the paper's vortex-pair runs use ell = 4)
@@ -42,10 +42,12 @@ class CrowSpec:
     nu_h: float = 5e-8
     p: int = 8
     dt: float = 2e-3
-    t_end: float = 50.0
+    t_end: float = 60.0
     sample_every: float = 0.5   # time between energy samples
     dealias: int = 1
-    nrc: int = 0                # radial chop N_r^c (0: N_r, no radial margin)
+    nrc: int = 96               # radial chop N_r^c (0: N_r, no radial margin); 96 degrees on 128
+                                # nodes keep the radial aliasing of the products out of the retained
+                                # degrees (without a margin the runs break down after t ~ 27..52)
     filter: int = 0             # 1: the adaptive modal filter of Sec. 3.3 between steps
     filter_zc: float = 2.0 / 3.0
     filter_tau: float = 2e-2

@@ -221,8 +221,7 @@ mlg_status mlg_rhs_tp(mlg_plan p, const double* U, const void* psi, const void* 
   if (!psi || !chi || !psi_n || !chi_n || !ws) return fail(MLG_E_ARG, "null buffer");
   if (psi_n == chi_n || psi_n == psi || psi_n == chi || chi_n == psi || chi_n == chi)
     return fail(MLG_E_ARG, "outputs must not alias each other or the inputs");
-  if (p->nrc != p->nr) return fail(MLG_E_UNSUPPORTED, "mlg_rhs_tp requires N_r^c = N_r");
-  if (p->nrc > 512) return fail(MLG_E_UNSUPPORTED, "mlg_rhs_tp supports N_r up to 512");
+  if (p->nrc > 512) return fail(MLG_E_UNSUPPORTED, "mlg_rhs_tp supports N_r^c up to 512");
   double Uh[3] = {0.0, 0.0, 0.0};
   if (U) {
     for (int i = 0; i < 3; ++i) {

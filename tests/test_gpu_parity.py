@@ -124,16 +124,16 @@ def test_rhs_scalar_parity(case):
         assert np.all(got[g.dealias_m() + 1:] == 0)
 
 
-def _tp_case(nr, nphi, nz, ell, lz, U, dealias, seeds=(2, 3), rates=(0.9, 0.85, 0.85)):
+def _tp_case(nr, nphi, nz, ell, lz, U, dealias, seeds=(2, 3), rates=(0.9, 0.85, 0.85), nrc=0):
     Plan = _gpu()
-    g = Grid(nr, nphi, nz, ell, lz=lz)
+    g = Grid(nr, nphi, nz, ell, lz=lz, nrc=nrc)
     vt = VecTables(g)
     a, b, c = rates
     psi = synth.geometric_spectrum(g.M, g.nrc, nz, g.nzc, seed=seeds[0], a=a, b=b, c=c)
     chi = synth.geometric_spectrum(g.M, g.nrc, nz, g.nzc, seed=seeds[1], a=a, b=b, c=c)
     taps = {}
     ref_psi, ref_chi = rhs_tp(psi, chi, g, vt, U=U, dealias=bool(dealias), taps=taps)
-    plan = Plan(nr, nphi, nz, ell, lz, dealias=dealias)
+    plan = Plan(nr, nphi, nz, ell, lz, nrc=nrc, dealias=dealias)
     tp = plan.taps_buffer()
     po, co = plan.empty_spec(), plan.empty_spec()
     plan.rhs_tp(torch.from_numpy(to_lib(psi)).cuda(), torch.from_numpy(to_lib(chi)).cuda(), po, co, U=U, taps=tp)
@@ -190,11 +190,21 @@ TP_CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", TP_CASES)
+TP_CHOP_CASES = [
+    # nr, nphi, nz, ell, lz, U, dealias, nrc: a radial margin N_r^c < N_r
+    (40, 16, 8, 1.0, 3.0, (0.0, 1.0, 0.0), 1, 30),        # even N_r: folded products
+    (33, 12, 6, 0.8, 3.0, (0.1, 0.3, -0.2), 1, 25),       # odd N_r: unfolded products
+    (24, 64, 8, 1.1, 2.0, (0.2, 0.0, 0.1), 0, 12),        # M = 32 > N_r^c: orders m >= 12 have no degrees
+    (20, 256, 256, 1.0, 8.6, (0.0, 1.0, 0.0), 1, 16),     # 256-point phi and z
+]
+
+
+@pytest.mark.parametrize("case", TP_CASES + TP_CHOP_CASES)
 def test_rhs_tp_parity_taps(case):
-    nr, nphi, nz, ell, lz, U, dealias = case
+    nr, nphi, nz, ell, lz, U, dealias = case[:7]
+    nrc = case[7] if len(case) > 7 else 0
     _say("rhs_tp parity", case)
-    g, taps, ref_psi, ref_chi, got = _tp_case(nr, nphi, nz, ell, lz, U, dealias)
+    g, taps, ref_psi, ref_chi, got = _tp_case(nr, nphi, nz, ell, lz, U, dealias, nrc=nrc)
     names = ["u_r", "u_phi", "u_z", "w_r", "w_phi", "w_z"]
     for i, nm in enumerate(names):
         ref = (taps["u"] + taps["w"])[i]
