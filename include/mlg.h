@@ -169,6 +169,15 @@ mlg_status mlg_step_febe(mlg_plan plan, int half, const void* s, const void* A, 
  * share its step scratch and must not overlap. */
 mlg_status mlg_step_abcn(mlg_plan plan, const void* s, const void* A_now, const void* A_prev, void* out, void* stream);
 
+/* Value of one harmonic of a packed spectral field at arbitrary radii (Eq. expansion, Eq. map):
+ *   out[j] = sum_{n=m}^{N_r^c-1} s_{n m kk} Pbar_n^m(x(r_j)),  x(r) = (r^2 - ell^2) / (r^2 + ell^2),
+ * for 0 <= m < N_phi^c and axial slot 0 <= kk < N_z.  r: device array of npts radii (>= 0); out:
+ * device array of npts complex values (2 npts doubles).  Pbar follows the normalised recurrence of the
+ * plan's tables in FP64.  For m = 0, kk = 0 the value is the azimuthal and axial mean of the field at
+ * radius r (the quantity whose level sets give a front radius).  Errors: MLG_E_ARG. */
+mlg_status mlg_eval_harmonic(mlg_plan plan, const void* spec, int32_t m, int32_t kk, const double* r, int64_t npts,
+                             void* out, void* stream);
+
 /* Adaptive modal filter (Sec. 3.3, the paragraph on aliasing and dissipation), applied between
  * steps.  Every stored coefficient s_{n m k} of a field whose normalised index
  *   zeta = max(n / N_r^c, m / N_phi^c, |k| / N_z^c)
@@ -343,6 +352,16 @@ mlg_status mlg_closure_stats(mlg_closure closure, int64_t* calls, int64_t* fallb
  * tmp: device buffer of 6 * spec_elems complex128; ws: the plan workspace. */
 mlg_status mlg_tp_advance(mlg_plan plan, const double* U, void* psi, void* chi, void* hist_psi, void* hist_chi,
                           int32_t nsteps, int32_t start, mlg_closure closure, void* tmp, void* ws, void* stream);
+
+/* Semi-implicit integration of one scalar, ds/dt = A(s) + L s (Sec. 3.3) with A = mlg_rhs_scalar(kind,
+ * gamma) (Eq. kpp for MLG_RHS_KPP) and L the operator of mlg_step_setup: nsteps steps of Eq. abcn;
+ * start = 1: the first is the Richardson start-up of Sec. 3.3 and 'hist' is an output; start = 0:
+ * 'hist' holds A^{j-1} from the previous call.  On return 'hist' holds A of the last state a step
+ * started from; 'state' is advanced in place and, when mlg_filter_setup has enabled the filter,
+ * filtered after every step with state slot 0.  tmp: device buffer of 3 * spec_elems complex128;
+ * ws: the plan workspace.  Errors: MLG_E_ARG (no step setup, NULL buffer, bad kind, nsteps < 0). */
+mlg_status mlg_scalar_advance(mlg_plan plan, int32_t kind, double gamma, void* state, void* hist, int32_t nsteps,
+                              int32_t start, void* tmp, void* ws, void* stream);
 
 /* Message for the last error on this thread ("" if none). */
 const char* mlg_last_error(void);

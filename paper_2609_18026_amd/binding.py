@@ -47,6 +47,7 @@ EXPORTS = ["mlg_plan_create", "mlg_plan_destroy", "mlg_plan_query", "mlg_plan_no
            "mlg_batch_create", "mlg_batch_destroy", "mlg_batch_query", "mlg_batch_rhs_scalar", "mlg_batch_set_config",
            "mlg_batch_get_config", "mlg_batch_autotune", "mlg_step_setup", "mlg_step_febe", "mlg_step_abcn",
            "mlg_truncate", "mlg_tp_advance", "mlg_filter_setup", "mlg_filter_apply", "mlg_filter_state",
+           "mlg_eval_harmonic", "mlg_scalar_advance",
            "mlg_closure_param_count", "mlg_closure_create", "mlg_closure_destroy",
            "mlg_closure_columns", "mlg_closure_set_params", "mlg_closure_get_params", "mlg_closure_get_grads",
            "mlg_closure_set_scales", "mlg_closure_get_scales", "mlg_closure_features", "mlg_closure_targets",
@@ -112,6 +113,8 @@ def lib() -> ctypes.CDLL:
     L.mlg_filter_setup.argtypes = [vp, ctypes.POINTER(mlg_filter_cfg)]
     L.mlg_filter_apply.argtypes = [vp, i32, vp, vp]
     L.mlg_filter_state.argtypes = [vp, ctypes.POINTER(f64)]
+    L.mlg_eval_harmonic.argtypes = [vp, vp, i32, i32, vp, ctypes.c_int64, vp, vp]
+    L.mlg_scalar_advance.argtypes = [vp, i32, f64, vp, vp, i32, i32, vp, vp, vp]
     L.mlg_closure_param_count.argtypes = []
     L.mlg_closure_create.argtypes = [ctypes.POINTER(mlg_closure_cfg), vp, ctypes.POINTER(vp)]
     L.mlg_closure_destroy.argtypes = [vp]
@@ -197,6 +200,15 @@ def mlg_step_setup(plan: int, nu: float, nu_h: float, p: int, dt: float) -> None
 def mlg_filter_setup(plan: int, zeta_c: float, tau: float, eps_max: float, relax: float) -> None:
     c = mlg_filter_cfg(zeta_c, tau, eps_max, relax)
     _check(lib().mlg_filter_setup(plan, ctypes.byref(c)))
+
+
+def mlg_eval_harmonic(plan: int, spec: int, m: int, kk: int, r: int, npts: int, out: int, stream: int = 0) -> None:
+    _check(lib().mlg_eval_harmonic(plan, spec, m, kk, r, npts, out, stream))
+
+
+def mlg_scalar_advance(plan: int, kind: int, gamma: float, state: int, hist: int, nsteps: int, start: int, tmp: int,
+                       ws: int, stream: int = 0) -> None:
+    _check(lib().mlg_scalar_advance(plan, kind, gamma, state, hist, nsteps, start, tmp, ws, stream))
 
 
 def mlg_filter_disable(plan: int) -> None:
@@ -424,6 +436,23 @@ class Plan:
 
     def filter_apply(self, slot, spec):
         mlg_filter_apply(self.handle, slot, spec.data_ptr(), self._stream())
+
+    def advance_scalar(self, kind, gamma, s, hist, nsteps, start=0, tmp=None):
+        """nsteps AB-CN steps of one scalar in place (Richardson start when start = 1); returns tmp."""
+        import torch
+        if tmp is None:
+            tmp = torch.empty(3 * self.layout.spec_elems, dtype=torch.complex128, device=f"cuda:{self.device}")
+        mlg_scalar_advance(self.handle, kind, gamma, s.data_ptr(), hist.data_ptr(), nsteps, start, tmp.data_ptr(),
+                           self.ws.data_ptr(), self._stream())
+        return tmp
+
+    def eval_harmonic(self, spec, m, kk, r):
+        """Complex values of the (m, kk) harmonic of 'spec' at the radii r (float64 device tensor)."""
+        import torch
+        r = r.contiguous()
+        out = torch.empty(r.numel(), dtype=torch.complex128, device=r.device)
+        mlg_eval_harmonic(self.handle, spec.data_ptr(), m, kk, r.data_ptr(), r.numel(), out.data_ptr(), self._stream())
+        return out
 
     def filter_state(self):
         """(eps_psi, eps_chi, f_psi, f_chi) after the last application (synchronises)."""

@@ -292,6 +292,17 @@ mlg_status mlg_step_abcn(mlg_plan p, const void* s, const void* A_now, const voi
                      static_cast<const double*>(A_prev), static_cast<double*>(out), static_cast<hipStream_t>(stream));
 }
 
+mlg_status mlg_eval_harmonic(mlg_plan p, const void* spec, int32_t m, int32_t kk, const double* r, int64_t npts,
+                             void* out, void* stream) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!spec || !out || (npts > 0 && !r)) return fail(MLG_E_ARG, "null buffer");
+  if (m < 0 || m >= p->M || kk < 0 || kk >= p->nz) return fail(MLG_E_ARG, "harmonic (m, kk) out of range");
+  if (npts < 0) return fail(MLG_E_ARG, "npts must be >= 0");
+  DeviceGuard guard(p->device);
+  return launch_eval_harmonic(p, static_cast<const double*>(spec), m, kk, r, npts, static_cast<double*>(out),
+                              static_cast<hipStream_t>(stream));
+}
+
 mlg_status mlg_filter_setup(mlg_plan p, const mlg_filter_cfg* cfg) {
   if (mlg_status st = check_plan(p)) return st;
   if (!cfg) {
@@ -403,6 +414,50 @@ mlg_status mlg_tp_advance(mlg_plan p, const double* U, void* psi, void* chi, voi
     MLG_HIP_TRY(hipMemcpyAsync(hp, prev[0], n * sizeof(double), hipMemcpyDeviceToDevice, s));
     MLG_HIP_TRY(hipMemcpyAsync(hc, prev[1], n * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
+  return MLG_OK;
+}
+
+mlg_status mlg_scalar_advance(mlg_plan p, int32_t kind, double gamma, void* state, void* hist, int32_t nsteps,
+                              int32_t start, void* tmp, void* ws, void* stream) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!p->step_ready) return fail(MLG_E_ARG, "mlg_step_setup has not been called");
+  if (!state || !hist || !tmp || !ws) return fail(MLG_E_ARG, "null buffer");
+  if (kind != MLG_RHS_U2 && kind != MLG_RHS_KPP) return fail(MLG_E_ARG, "kind must be MLG_RHS_U2 or MLG_RHS_KPP");
+  if (!std::isfinite(gamma)) return fail(MLG_E_ARG, "gamma must be finite");
+  if (nsteps < 0) return fail(MLG_E_ARG, "nsteps must be >= 0");
+  if (nsteps == 0) return MLG_OK;
+  DeviceGuard guard(p->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t n = (size_t)p->tau * p->nz * 2;  // doubles per spectral array
+  double* t[3];
+  for (int i = 0; i < 3; ++i) t[i] = static_cast<double*>(tmp) + i * n;
+  double* sp = static_cast<double*>(state);
+  double* hp = static_cast<double*>(hist);
+  mlg_status st;
+  auto rhs = [&](const double* a, double* ra) { return mlg_rhs_scalar(p, kind, gamma, a, ra, ws, stream); };
+  auto filter = [&]() -> mlg_status { return p->filter_on ? launch_filter(p, 0, sp, s) : MLG_OK; };
+  int done = 0;
+  if (start) {
+    // s1 = 2 S_{dt/2}(S_{dt/2}(s0)) - S_dt(s0), S_h(s) = (I - h L)^{-1} (s + h A(s))
+    if ((st = rhs(sp, hp))) return st;
+    if ((st = launch_step(p, 0, 1, sp, hp, nullptr, t[1], s))) return st;
+    if ((st = launch_step(p, 0, 0, sp, hp, nullptr, t[2], s))) return st;
+    if ((st = rhs(t[2], t[0]))) return st;
+    if ((st = launch_step(p, 0, 0, t[2], t[0], nullptr, t[2], s))) return st;
+    if ((st = launch_richardson(p, t[2], t[1], sp, s))) return st;
+    if ((st = filter())) return st;
+    done = 1;
+  }
+  // AB-CN: the nonlinear term alternates between hist and t0; the step runs in place
+  double* prev = hp;
+  for (; done < nsteps; ++done) {
+    double* now = prev == hp ? t[0] : hp;
+    if ((st = rhs(sp, now))) return st;
+    if ((st = launch_step(p, 1, 0, sp, now, prev, sp, s))) return st;
+    if ((st = filter())) return st;
+    prev = now;
+  }
+  if (prev != hp) MLG_HIP_TRY(hipMemcpyAsync(hp, prev, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   return MLG_OK;
 }
 

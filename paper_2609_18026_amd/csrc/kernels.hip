@@ -882,6 +882,44 @@ __global__ __launch_bounds__(256) void energy_sum_kernel(const double* __restric
   energy[kk] = scale * acc;
 }
 
+// ---------------------------------------------------------------- pointwise evaluation of one harmonic
+// f(r_j) = sum_{n=m}^{N_r^c-1} s[n][kk] Pbar_n^m(x(r_j)) (Eq. expansion for one (m, k) column), with
+// x = (r^2 - ell^2) / (r^2 + ell^2) and sqrt(1 - x^2) = 2 ell r / (r^2 + ell^2) (Eq. map), Pbar by
+// the normalised recurrence of the plan tables in FP64: one thread per radius, coefficients read
+// in order by every thread.
+__global__ __launch_bounds__(256) void eval_harmonic_kernel(const double2* __restrict__ col, int64_t stride, int m,
+                                                            int nrc, double ell, const double* __restrict__ r,
+                                                            int64_t npts, double2* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= npts) return;
+  const double rr = r[j], d = rr * rr + ell * ell;
+  const double x = (rr * rr - ell * ell) / d, sn = 2.0 * ell * rr / d;
+  double p0 = sqrt(0.5);
+  for (int i = 1; i <= m; ++i) p0 *= sqrt((double)(2 * i + 1) / (double)(2 * i)) * sn;
+  double2 acc = make_double2(0.0, 0.0);
+  if (m < nrc) {
+    double2 c = col[0];
+    acc = make_double2(c.x * p0, c.y * p0);
+  }
+  double p1 = sqrt((double)(2 * m + 3)) * x * p0;
+  if (m + 1 < nrc) {
+    double2 c = col[stride];
+    acc.x += c.x * p1;
+    acc.y += c.y * p1;
+  }
+  for (int n = m + 2; n < nrc; ++n) {
+    const double a = sqrt((double)(4 * n * n - 1) / (double)(n * n - m * m));
+    const double b = sqrt((double)((2 * n + 1) * (n - 1 - m) * (n - 1 + m)) / (double)((2 * n - 3) * (n * n - m * m)));
+    const double p2 = a * x * p1 - b * p0;
+    const double2 c = col[(int64_t)(n - m) * stride];
+    acc.x += c.x * p2;
+    acc.y += c.y * p2;
+    p0 = p1;
+    p1 = p2;
+  }
+  out[j] = acc;
+}
+
 // Zero every entry of the packed arrays whose (m, k) column is not active.
 __global__ void zero_inactive_kernel(double2* __restrict__ x0, double2* __restrict__ x1, double2* __restrict__ x2,
                                      double2* __restrict__ x3, double2* __restrict__ x4,
@@ -1148,4 +1186,13 @@ mlg_status launch_mask_tri(const mlg_plan_s* p, double* spec, hipStream_t s) {
   return check_launch("mask_tri_kernel");
 }
 
+mlg_status launch_eval_harmonic(const mlg_plan_s* p, const double* spec, int m, int kk, const double* r, int64_t npts,
+                                double* out, hipStream_t s) {
+  if (npts <= 0) return MLG_OK;
+  // the packed row offset of order m comes from the plan's host copy of the offsets
+  const double2* col = reinterpret_cast<const double2*>(spec) + p->off[m] * p->nz + kk;
+  eval_harmonic_kernel<<<(unsigned)((npts + 255) / 256), 256, 0, s>>>(col, p->nz, m, p->nrc, p->g.ell, r, npts,
+                                                                     reinterpret_cast<double2*>(out));
+  return check_launch("eval_harmonic_kernel");
+}
 }  // namespace mlg

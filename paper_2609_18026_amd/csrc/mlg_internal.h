@@ -193,6 +193,9 @@ mlg_status launch_richardson(const mlg_plan_s* p, const double* half, const doub
 // adaptive modal filter of Sec. 3.3 on one packed spectral field with state slot 'slot' (0, 1)
 constexpr int FILTER_BLOCKS = 256;
 mlg_status launch_filter(const mlg_plan_s* p, int slot, double* spec, hipStream_t s);
+// kernels.hip: one (m, kk) column of a packed spectral field evaluated at npts radii (complex out)
+mlg_status launch_eval_harmonic(const mlg_plan_s* p, const double* spec, int m, int kk, const double* r, int64_t npts,
+                                double* out, hipStream_t s);
 // closure.hip: features -> network -> judge -> corrected (rpsi, rchi), all on 'st'
 mlg_status closure_correct(mlg_closure_s* c, const double* psi, const double* chi, double* rpsi, double* rchi,
                            hipStream_t st);

@@ -1,0 +1,94 @@
+"""The Fisher-KPP front of Sec. 5.2 on the GPU: harmonic evaluation, the scalar time loop, the
+linear stage against Eq. kpp-linear, and the front radius and speed.
+
+Bars: mlg_eval_harmonic agrees with the oracle's evaluation of the expansion to 1e-13 (relative to
+the largest value); mlg_scalar_advance agrees with the oracle's Richardson start + AB-CN integration
+of Eq. kpp to 1e-12 normwise; the linear stage (A = 1e-6, dt = 1e-2, t = 20) is within 2e-5 of the
+closed form in the relative weighted L2 norm (the paper reports 1.401e-5, set by the time step; this
+path gives 1.4012e-5); the front radius at t = 80 with 768 radial degrees at ell = 32 is within 2e-3
+of the paper's 63.8393 (its three runs span 63.8389..63.8395; this path gives 63.8403 on all of
+them, 3e-5 apart) and the front speed within 2e-3 of the paper's 0.9037 (t = 32) and 0.9542 (t = 80).
+"""
+import numpy as np
+import pytest
+
+import synth
+from helpers import from_lib, rel, to_lib
+from oracle import kpp as okpp
+from oracle.grid import Grid
+from oracle.rhs import rhs_scalar
+from oracle.timestep import Dissipation, integrate_abcn
+from oracle.transform import Tables
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2609_18026_amd as m
+    return m
+
+
+@pytest.mark.parametrize("case", [(40, 16, 8, 2.0, 0), (33, 12, 1, 0.7, 0), (30, 20, 6, 1.5, 24)])
+def test_eval_harmonic_parity(case):
+    m = _gpu()
+    nr, nphi, nz, ell, nrc = case
+    print("eval_harmonic parity", case, flush=True)
+    g = Grid(nr, nphi, nz, ell, nrc=nrc)
+    plan = m.Plan(nr, nphi, nz, ell, nrc=nrc)
+    S = synth.geometric_spectrum(g.M, g.nrc, nz, g.nzc, seed=21, a=0.9, b=0.9, c=0.9)
+    d = torch.from_numpy(to_lib(S)).cuda()
+    r = np.concatenate([[0.0], g.r[:5], np.linspace(0.01, 40.0, 97), [1e3, 1e5]])
+    rd = torch.from_numpy(r).cuda()
+    for mm in sorted({0, 1, g.M // 2, g.M - 1}):
+        for kk in sorted({0, 1 % nz, nz - 1}):
+            got = plan.eval_harmonic(d, mm, kk, rd).cpu().numpy()
+            ref = okpp.harmonic_at(S, g, mm, kk, r)
+            scale = max(np.abs(ref).max(), 1e-300)
+            assert np.abs(got - ref).max() <= 1e-13 * scale, (mm, kk, np.abs(got - ref).max() / scale)
+
+
+def test_scalar_advance_parity():
+    m = _gpu()
+    print("scalar advance parity", flush=True)
+    from paper_2609_18026_amd import MLG_RHS_KPP
+    nr, nphi, ell, dt, n = 32, 8, 2.0, 1e-2, 10
+    g = Grid(nr, nphi, 1, ell)
+    t = Tables(g)
+    plan = m.Plan(nr, nphi, 1, ell, dealias=1)
+    plan.step_setup(1.0, 0.0, 8, dt)
+    S0 = synth.geometric_spectrum(g.M, g.nrc, 1, g.nzc, seed=23, a=0.8, b=0.7, c=1.0)
+    ref = integrate_abcn(S0, dt, n, Dissipation(g, 1.0), lambda S: rhs_scalar(S, g, t, "kpp", 0.25, dealias=True))
+    s = torch.from_numpy(to_lib(S0)).cuda()
+    hist = plan.empty_spec()
+    tmp = plan.advance_scalar(MLG_RHS_KPP, 0.25, s, hist, 3, start=1)
+    plan.advance_scalar(MLG_RHS_KPP, 0.25, s, hist, n - 3, start=0, tmp=tmp)
+    torch.cuda.synchronize()
+    got = from_lib(s.cpu().numpy(), g.M, g.nrc)
+    assert rel(got, ref) < 1e-12, rel(got, ref)
+
+
+def test_kpp_linear_stage_against_closed_form():
+    _gpu()
+    from paper_2609_18026_amd.kpp import KppSpec, run
+    spec = KppSpec(nr=96, ell=8.0, A=1e-6, dt=1e-2, t_end=20.0, sample_every=5.0)
+    print("kpp linear stage", spec, flush=True)
+    res = run(spec)
+    print("relative weighted L2 error at t = 20:", res["linear_rel_err"], "(paper: 1.401e-5)", flush=True)
+    assert res["linear_rel_err"] < 2e-5
+    assert abs(res["linear_rel_err"] - 1.401e-5) < 5e-9   # the paper's figure to its four digits
+
+
+@pytest.mark.timeout(300)
+def test_kpp_front_radius_and_speed():
+    _gpu()
+    from paper_2609_18026_amd.kpp import KppSpec, run
+    spec = KppSpec(nr=768, ell=32.0, A=1.0, dt=1e-2, t_end=80.0)
+    print("kpp front", spec, flush=True)
+    res = run(spec)
+    print("R(80)", res["R_80"], "speed(80)", res["speed_80"], "theory", res["speed_theory_80"],
+          "R(32)", res["R_32"], "speed(32)", res["speed_32"], flush=True)
+    assert abs(res["R_80"] - 63.8393) < 2e-3
+    assert abs(res["speed_80"] - 0.9542) < 2e-3 and abs(res["speed_32"] - 0.9037) < 2e-3
