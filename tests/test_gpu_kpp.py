@@ -81,6 +81,16 @@ def test_kpp_linear_stage_against_closed_form():
     assert abs(res["linear_rel_err"] - 1.401e-5) < 5e-9   # the paper's figure to its four digits
 
 
+@pytest.mark.parametrize("dt,paper", [(2e-2, 4.71e-5), (5e-3, 5.80e-6), (2.5e-3, 3.81e-6)])
+def test_kpp_linear_stage_time_refinement(dt, paper):
+    """The paper's refinement series (printed to three digits), floor near 4e-6 included."""
+    _gpu()
+    from paper_2609_18026_amd.kpp import KppSpec, run
+    res = run(KppSpec(nr=96, ell=8.0, A=1e-6, dt=dt, t_end=20.0, sample_every=5.0))
+    print("dt", dt, "error", res["linear_rel_err"], "paper", paper, flush=True)
+    assert abs(res["linear_rel_err"] / paper - 1) < 0.01
+
+
 @pytest.mark.timeout(300)
 def test_kpp_front_radius_and_speed():
     _gpu()
