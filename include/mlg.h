@@ -134,8 +134,9 @@ mlg_status mlg_rhs_scalar(mlg_plan plan, int kind, double gamma, const void* spe
  * omega = curl u and U = (U[0], U[1], U[2]) a uniform Cartesian background (host array;
  * NULL = 0).  P takes the gradient-free part through the axial curl and curl-curl
  * (Eq. tp-poisson); the m = 0 blocks use the decay gauge psi, chi -> 0 as r -> infinity.
- * Inputs must have zero net circulation (the logarithmic proxy of Eq. logproxy is not
- * supported).  'taps' may be NULL; otherwise a device buffer of
+ * psi and chi are the regular parts of the potentials: a net circulation or axial volume flux
+ * is carried by the logarithmic proxy amplitudes of mlg_set_log_proxy (Eq. logproxy), whose
+ * velocity and vorticity enter u and omega here.  'taps' may be NULL; otherwise a device buffer of
  * 9 * phys_elems + 3 * spec_elems values (reals, then complex) receiving nodal
  * u_r, u_phi, u_z, w_r, w_phi, w_z, N_r, N_phi, N_z and the sources C, K, Zhat.
  * A radial margin N_r^c < N_r (Sec. 3.3) is allowed: the products are formed on the N_r nodes and
@@ -168,6 +169,25 @@ mlg_status mlg_step_febe(mlg_plan plan, int half, const void* s, const void* A, 
  * All arrays spectral (packed triangular); out must not alias the inputs.  Calls on one plan
  * share its step scratch and must not overlap. */
 mlg_status mlg_step_abcn(mlg_plan plan, const void* s, const void* A_now, const void* A_prev, void* out, void* stream);
+
+/* Logarithmic proxies (Sec. 3.1, Eq. logproxy): the potentials are psi~ + c_psi Lambda and
+ * chi~ + c_chi Lambda with Lambda(r) = ln(r^2 + ell^2), the spectral arrays holding the regular parts
+ * psi~, chi~.  The proxy parts add u_phi = -2 c_psi r / (r^2 + ell^2), u_z = -c_chi grad_h^2 Lambda,
+ * w_phi = c_chi d(grad_h^2 Lambda)/dr and w_z = -c_psi grad_h^2 Lambda (grad_h^2 Lambda =
+ * 4 ell^2 / (r^2 + ell^2)^2) to the velocity and vorticity of mlg_rhs_tp, mlg_synthesize,
+ * mlg_tp_energy and mlg_tp_enstrophy: a circulation -4 pi c_psi and an axial volume flux
+ * -4 pi c_chi at infinity.  Both are constants of the motion, so mlg_tp_advance keeps them and adds
+ * the dissipation of the proxy parts, c L Lambda (a fixed vector on the m = 0, k = 0 degrees, built
+ * by mlg_step_setup), to the nonlinear terms of the regular parts.  Default 0 and 0.
+ * Errors: MLG_E_ARG (non-finite amplitude). */
+mlg_status mlg_set_log_proxy(mlg_plan plan, double c_psi, double c_chi);
+
+/* Enstrophy per axial slot: the quadrature of mlg_tp_energy applied to the vorticity,
+ *   enstrophy[kk] = (L_z / 2) int_0^{2 pi} int_0^inf |omega_k|^2 r dr dphi,
+ * so that the sum over the slots is (1/2) int |omega|^2 dV over one axial period.  Same buffers
+ * and errors as mlg_tp_energy (FP64 plans). */
+mlg_status mlg_tp_enstrophy(mlg_plan plan, const void* psi, const void* chi, double* enstrophy, void* ws,
+                            void* stream);
 
 /* Value of one harmonic of a packed spectral field at arbitrary radii (Eq. expansion, Eq. map):
  *   out[j] = sum_{n=m}^{N_r^c-1} s_{n m kk} Pbar_n^m(x(r_j)),  x(r) = (r^2 - ell^2) / (r^2 + ell^2),

@@ -47,7 +47,7 @@ EXPORTS = ["mlg_plan_create", "mlg_plan_destroy", "mlg_plan_query", "mlg_plan_no
            "mlg_batch_create", "mlg_batch_destroy", "mlg_batch_query", "mlg_batch_rhs_scalar", "mlg_batch_set_config",
            "mlg_batch_get_config", "mlg_batch_autotune", "mlg_step_setup", "mlg_step_febe", "mlg_step_abcn",
            "mlg_truncate", "mlg_tp_advance", "mlg_filter_setup", "mlg_filter_apply", "mlg_filter_state",
-           "mlg_eval_harmonic", "mlg_scalar_advance",
+           "mlg_eval_harmonic", "mlg_scalar_advance", "mlg_set_log_proxy", "mlg_tp_enstrophy",
            "mlg_closure_param_count", "mlg_closure_create", "mlg_closure_destroy",
            "mlg_closure_columns", "mlg_closure_set_params", "mlg_closure_get_params", "mlg_closure_get_grads",
            "mlg_closure_set_scales", "mlg_closure_get_scales", "mlg_closure_features", "mlg_closure_targets",
@@ -115,6 +115,8 @@ def lib() -> ctypes.CDLL:
     L.mlg_filter_state.argtypes = [vp, ctypes.POINTER(f64)]
     L.mlg_eval_harmonic.argtypes = [vp, vp, i32, i32, vp, ctypes.c_int64, vp, vp]
     L.mlg_scalar_advance.argtypes = [vp, i32, f64, vp, vp, i32, i32, vp, vp, vp]
+    L.mlg_set_log_proxy.argtypes = [vp, f64, f64]
+    L.mlg_tp_enstrophy.argtypes = [vp, vp, vp, vp, vp, vp]
     L.mlg_closure_param_count.argtypes = []
     L.mlg_closure_create.argtypes = [ctypes.POINTER(mlg_closure_cfg), vp, ctypes.POINTER(vp)]
     L.mlg_closure_destroy.argtypes = [vp]
@@ -209,6 +211,14 @@ def mlg_eval_harmonic(plan: int, spec: int, m: int, kk: int, r: int, npts: int, 
 def mlg_scalar_advance(plan: int, kind: int, gamma: float, state: int, hist: int, nsteps: int, start: int, tmp: int,
                        ws: int, stream: int = 0) -> None:
     _check(lib().mlg_scalar_advance(plan, kind, gamma, state, hist, nsteps, start, tmp, ws, stream))
+
+
+def mlg_set_log_proxy(plan: int, c_psi: float, c_chi: float) -> None:
+    _check(lib().mlg_set_log_proxy(plan, c_psi, c_chi))
+
+
+def mlg_tp_enstrophy(plan: int, psi: int, chi: int, out: int, ws: int, stream: int = 0) -> None:
+    _check(lib().mlg_tp_enstrophy(plan, psi, chi, out, ws, stream))
 
 
 def mlg_filter_disable(plan: int) -> None:
@@ -445,6 +455,18 @@ class Plan:
         mlg_scalar_advance(self.handle, kind, gamma, s.data_ptr(), hist.data_ptr(), nsteps, start, tmp.data_ptr(),
                            self.ws.data_ptr(), self._stream())
         return tmp
+
+    def set_log_proxy(self, c_psi=0.0, c_chi=0.0):
+        """Amplitudes of ln(r^2 + ell^2) carried by psi and chi beyond their regular parts."""
+        mlg_set_log_proxy(self.handle, c_psi, c_chi)
+
+    def enstrophy(self, psi, chi, out=None):
+        """Enstrophy per axial FFT slot (float64 device tensor of N_z entries; the sum is (1/2) int |w|^2 dV)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.nz, dtype=torch.float64, device=f"cuda:{self.device}")
+        mlg_tp_enstrophy(self.handle, psi.data_ptr(), chi.data_ptr(), out.data_ptr(), self.ws.data_ptr(), self._stream())
+        return out
 
     def eval_harmonic(self, spec, m, kk, r):
         """Complex values of the (m, kk) harmonic of 'spec' at the radii r (float64 device tensor)."""

@@ -239,6 +239,8 @@ mlg_status mlg_rhs_tp(mlg_plan p, const double* U, const void* psi, const void* 
   else
     st = launch_synth_gemm(p, static_cast<const double*>(psi), static_cast<const double*>(chi), w.X, s);
   if (st) return st;
+  // the logarithmic proxy parts of the potentials, when they carry amplitudes (Eq. logproxy)
+  if ((st = launch_proxy_fields(p, w.X, s))) return st;
   // 2. inverse z transforms of the six fields
   const int64_t mrows = (int64_t)p->M * p->nr;
   if ((st = launch_zfft_fields(p, w.X, w.X, 6, mrows, +1, nullptr, 0, 0, s))) return st;
@@ -375,6 +377,7 @@ mlg_status mlg_tp_advance(mlg_plan p, const double* U, void* psi, void* chi, voi
   mlg_status st;
   auto rhs = [&](const double* a, const double* b, double* ra, double* rb) -> mlg_status {
     if (mlg_status e = mlg_rhs_tp(p, U, a, b, ra, rb, nullptr, ws, stream)) return e;
+    if (mlg_status e = launch_proxy_force(p, ra, rb, s)) return e;   // dissipation of the proxy parts
     return closure ? closure_correct(closure, a, b, ra, rb, s) : MLG_OK;
   };
   // the adaptive modal filter between steps (Sec. 3.3), when enabled
@@ -473,6 +476,7 @@ mlg_status mlg_synthesize(mlg_plan p, const void* psi, const void* chi, void* uw
   else
     st = launch_synth_gemm(p, static_cast<const double*>(psi), static_cast<const double*>(chi), w.X, s);
   if (st) return st;
+  if ((st = launch_proxy_fields(p, w.X, s))) return st;
   const int64_t mrows = (int64_t)p->M * p->nr;
   const size_t pe = (size_t)p->nz * p->nr * p->nphi;
   for (int i = 0; i < 6; ++i) {
@@ -491,7 +495,29 @@ mlg_status mlg_tp_energy(mlg_plan p, const void* psi, const void* chi, double* e
   Ws w = partition(p, ws);
   if (mlg_status st = launch_synth_gemm(p, static_cast<const double*>(psi), static_cast<const double*>(chi), w.X, s))
     return st;
+  if (mlg_status st = launch_proxy_fields(p, w.X, s)) return st;
   return launch_energy(p, w.X, energy, w.T[0], s);
+}
+
+mlg_status mlg_tp_enstrophy(mlg_plan p, const void* psi, const void* chi, double* enstrophy, void* ws, void* stream) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!psi || !chi || !enstrophy || !ws) return fail(MLG_E_ARG, "null buffer");
+  if (p->prec != MLG_FP64) return fail(MLG_E_UNSUPPORTED, "mlg_tp_enstrophy: FP64 plans only");
+  DeviceGuard guard(p->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Ws w = partition(p, ws);
+  if (mlg_status st = launch_synth_gemm(p, static_cast<const double*>(psi), static_cast<const double*>(chi), w.X, s))
+    return st;
+  if (mlg_status st = launch_proxy_fields(p, w.X, s)) return st;
+  return launch_energy(p, w.X + 3, enstrophy, w.T[0], s);   // the same quadrature on the vorticity
+}
+
+mlg_status mlg_set_log_proxy(mlg_plan p, double c_psi, double c_chi) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!std::isfinite(c_psi) || !std::isfinite(c_chi)) return fail(MLG_E_ARG, "proxy amplitudes must be finite");
+  p->log_cpsi = c_psi;
+  p->log_cchi = c_chi;
+  return MLG_OK;
 }
 
 mlg_status mlg_timing_enable(mlg_plan p, int enable) {

@@ -920,6 +920,33 @@ __global__ __launch_bounds__(256) void eval_harmonic_kernel(const double2* __res
   out[j] = acc;
 }
 
+// ---------------------------------------------------------------- logarithmic proxy (Eq. logproxy)
+// Potentials psi~ + c_psi Lambda, chi~ + c_chi Lambda with Lambda = ln(r^2 + ell^2): at node i, with
+// q = (1 - x)^2 / ell^2 = grad_h^2 Lambda and r (1 - x) / ell^2 = 2 r / (r^2 + ell^2), the proxy parts
+// add u_phi = -c_psi r sqrt(q) / ell, u_z = -c_chi q, w_phi = -2 c_chi r q^{3/2} / ell, w_z = -c_psi q
+// to the m = 0, k = 0 harmonics (mixed layout, before the inverse z transforms).
+__global__ void proxy_fields_kernel(double2* __restrict__ up, double2* __restrict__ uz, double2* __restrict__ wp,
+                                    double2* __restrict__ wz, const double* __restrict__ node, int nr, int nz,
+                                    double cpsi, double cchi, double ell) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nr) return;
+  const double r = 1.0 / node[i], q = node[nr + i], sq = sqrt(q);
+  const int64_t o = (int64_t)i * nz;  // order 0, node i, axial slot 0
+  up[o].x += -cpsi * r * sq / ell;
+  uz[o].x += -cchi * q;
+  wp[o].x += -2.0 * cchi * r * q * sq / ell;
+  wz[o].x += -cpsi * q;
+}
+
+// The regular parts evolve with the constant forcing c L Lambda on the m = 0, k = 0 column.
+__global__ void proxy_force_kernel(double2* __restrict__ psi_n, double2* __restrict__ chi_n,
+                                   const double* __restrict__ f, int nrc, int nz, double cpsi, double cchi) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nrc) return;
+  psi_n[(int64_t)n * nz].x += cpsi * f[n];
+  chi_n[(int64_t)n * nz].x += cchi * f[n];
+}
+
 // Zero every entry of the packed arrays whose (m, k) column is not active.
 __global__ void zero_inactive_kernel(double2* __restrict__ x0, double2* __restrict__ x1, double2* __restrict__ x2,
                                      double2* __restrict__ x3, double2* __restrict__ x4,
@@ -1195,4 +1222,21 @@ mlg_status launch_eval_harmonic(const mlg_plan_s* p, const double* spec, int m, 
                                                                      reinterpret_cast<double2*>(out));
   return check_launch("eval_harmonic_kernel");
 }
+
+mlg_status launch_proxy_fields(const mlg_plan_s* p, double* const* f6, hipStream_t s) {
+  if (p->log_cpsi == 0.0 && p->log_cchi == 0.0) return MLG_OK;
+  proxy_fields_kernel<<<(p->nr + 255) / 256, 256, 0, s>>>(
+      reinterpret_cast<double2*>(f6[1]), reinterpret_cast<double2*>(f6[2]), reinterpret_cast<double2*>(f6[4]),
+      reinterpret_cast<double2*>(f6[5]), p->d_node, p->nr, p->nz, p->log_cpsi, p->log_cchi, p->g.ell);
+  return check_launch("proxy_fields_kernel");
+}
+
+mlg_status launch_proxy_force(const mlg_plan_s* p, double* psi_n, double* chi_n, hipStream_t s) {
+  if ((p->log_cpsi == 0.0 && p->log_cchi == 0.0) || !p->d_logf) return MLG_OK;
+  proxy_force_kernel<<<(p->nrc + 255) / 256, 256, 0, s>>>(reinterpret_cast<double2*>(psi_n),
+                                                           reinterpret_cast<double2*>(chi_n), p->d_logf, p->nrc,
+                                                           p->nz, p->log_cpsi, p->log_cchi);
+  return check_launch("proxy_force_kernel");
+}
 }  // namespace mlg
+

@@ -119,6 +119,10 @@ struct mlg_plan_s {
   double* d_filter = nullptr;
   bool filter_on = false;
   double filter_zc = 0, filter_tau = 0, filter_epsmax = 0, filter_relax = 0;
+  // logarithmic proxy amplitudes of the potentials (mlg_set_log_proxy) and, once the step is set
+  // up, the forcing L Lambda of the regular parts on the m = 0, k = 0 column (N_r^c reals)
+  double log_cpsi = 0, log_cchi = 0;
+  double* d_logf = nullptr;
   bool use_fast_fft = true;   // register-resident 256-point kernels when a length is 256
   bool use_fold = true;       // parity-folded radial products when N_r is even (MLG_RADIAL_FOLD=0 disables)
   int phi_rad[12] = {0};
@@ -193,6 +197,13 @@ mlg_status launch_richardson(const mlg_plan_s* p, const double* half, const doub
 // adaptive modal filter of Sec. 3.3 on one packed spectral field with state slot 'slot' (0, 1)
 constexpr int FILTER_BLOCKS = 256;
 mlg_status launch_filter(const mlg_plan_s* p, int slot, double* spec, hipStream_t s);
+// plan.cpp: L Lambda = nu g + nu_h (-Dbar_0)^{q-1} g on the m = 0 degrees (g: the image of
+// grad_h^2 Lambda, Eq. logproxy), in long double
+void proxy_forcing(const mlg_plan_s* p, double nu, double nuh, int q, std::vector<double>& out);
+// kernels.hip: the proxy parts of u_phi, u_z, w_phi, w_z added to the m = 0, k = 0 harmonics of the
+// six synthesised fields (mixed layout), and the forcing added to the m = 0, k = 0 column of the RHS
+mlg_status launch_proxy_fields(const mlg_plan_s* p, double* const* f6, hipStream_t s);
+mlg_status launch_proxy_force(const mlg_plan_s* p, double* psi_n, double* chi_n, hipStream_t s);
 // kernels.hip: one (m, kk) column of a packed spectral field evaluated at npts radii (complex out)
 mlg_status launch_eval_harmonic(const mlg_plan_s* p, const double* spec, int m, int kk, const double* r, int64_t npts,
                                 double* out, hipStream_t s);

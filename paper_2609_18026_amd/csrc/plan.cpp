@@ -152,7 +152,7 @@ void free_plan_device(mlg_plan_s* p) {
                   p->d_split_syn_off, p->d_split_syn_kpad, p->d_split_prj[0], p->d_split_prj[1],
                   p->d_split_prj[2], p->d_split_prj[3], p->d_split_prj_off, p->d_split_zdft, p->d_step_fwd,
                   p->d_step_bwd, p->d_step_lam, p->d_step_u, p->d_step_qoff, p->d_step_loff, p->d_step_w,
-                  p->d_filter};
+                  p->d_filter, p->d_logf};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }
@@ -177,6 +177,38 @@ void split_into(double x, uint16_t* hi, uint16_t* lo) {
 }
 
 }  // namespace
+
+void proxy_forcing(const mlg_plan_s* p, double nu, double nuh, int q, std::vector<double>& out) {
+  const int nrc = p->nrc;
+  const ld ell2 = (ld)p->g.ell * (ld)p->g.ell;
+  // g: (1/ell^2)(4/3 P_0 - 2 P_1 + 2/3 P_2) on the normalised Pbar_n^0 = sqrt((2n+1)/2) P_n
+  std::vector<ld> g(nrc, 0), v(nrc, 0), w(nrc, 0);
+  const ld un[3] = {4.0L / 3.0L, -2.0L, 2.0L / 3.0L};
+  for (int n = 0; n < 3 && n < nrc; ++n) g[n] = un[n] / sqrtl((ld)(2 * n + 1) / 2.0L) / ell2;
+  // -Dbar_0 v = G diag(n(n+1)) v / ell^2 with the exact Gram matrix G of the m = 0 block
+  auto minus_dbar = [&](const std::vector<ld>& a, std::vector<ld>& b) {
+    for (int n = 0; n < nrc; ++n) {
+      ld acc = 0;
+      for (int j = std::max(0, n - 2); j <= std::min(nrc - 1, n + 2); ++j) {
+        ld G = 0;
+        const int lo = std::min(n, j), d = std::abs(n - j);
+        const ld e1 = eps_nm(lo + 1, 0), e2 = eps_nm(lo + 2, 0);
+        if (d == 0) G = 1 + eps_nm(lo, 0) * eps_nm(lo, 0) + e1 * e1;
+        else if (d == 1) G = -2 * e1;
+        else G = e1 * e2;
+        acc += G * (ld)j * (ld)(j + 1) * a[j];
+      }
+      b[n] = acc / ell2;
+    }
+  };
+  v = g;
+  for (int i = 1; i < q; ++i) {
+    minus_dbar(v, w);
+    v.swap(w);
+  }
+  out.assign(nrc, 0.0);
+  for (int n = 0; n < nrc; ++n) out[n] = (double)((ld)nu * g[n] + (q >= 1 && nuh != 0.0 ? (ld)nuh * v[n] : 0.0L));
+}
 
 void gl_theta(int N, std::vector<long double>& theta, std::vector<long double>& w) { gauss_legendre_theta(N, theta, w); }
 void pbar_col(int m, int nmax, long double t, long double* out) { pbar_column(m, nmax, t, out); }

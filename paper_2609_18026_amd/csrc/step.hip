@@ -487,6 +487,8 @@ mlg_status step_setup(mlg_plan_s* p, const mlg_dissip* d) {
     if (*q) (void)hipFree(*q);
   if (p->d_step_qoff) (void)hipFree(p->d_step_qoff);
   if (p->d_step_loff) (void)hipFree(p->d_step_loff);
+  if (p->d_logf) (void)hipFree(p->d_logf);
+  p->d_logf = nullptr;
   p->d_step_fwd = p->d_step_bwd = p->d_step_lam = p->d_step_u = p->d_step_w = nullptr;
   p->d_step_qoff = p->d_step_loff = nullptr;
   p->step_ready = false;
@@ -515,6 +517,10 @@ mlg_status step_setup(mlg_plan_s* p, const mlg_dissip* d) {
   p->step_nu = d->nu;
   p->step_nuh = d->nu_h;
   p->step_q = d->nu_h > 0 ? d->p / 2 : 1;
+  // the dissipation of the logarithmic proxies, a constant forcing of the regular parts (Eq. logproxy)
+  std::vector<double> lf;
+  proxy_forcing(p, d->nu, d->nu_h, p->step_q, lf);
+  if ((st = upl(&p->d_logf, lf))) return st;
   p->step_ready = true;
   return MLG_OK;
 }
