@@ -103,43 +103,43 @@ __global__ __launch_bounds__(256, 2) void synth_fold_kernel(FoldSynthArgs a) {
 #pragma unroll
     for (int p = 0; p < 7; ++p) acc[s][p] = double4_t{0.0, 0.0, 0.0, 0.0};
 
-  // operands of the next two stages are held in registers (ra, rb: stage kt + 1; rn, rbn: kt + 2)
-  double ra[8], rn[8];
-  double2 rb, rbn;
-  auto load = [&](int jj0, double (&da)[8], double2& db) {
+  // Operands of the next two stages alternate between two register sets.  Every load is
+  // unconditional (indices clamped into the table; entries outside it are zeroed when written to
+  // LDS), so writing one set waits only for that set while the other set's loads stay in flight
+  // across the MFMAs of the current stage.
+  struct Stage {
+    double a[8];
+    double2 b;
+  };
+  Stage sx, sy;
+  const int Kc = K > 0 ? K - 1 : 0;
+  const int fld = tid >> 7, bpar = (tid >> 6) & 1, bkr = (tid >> 3) & 7, bcc = tid & 7;
+  const int bkk = kk0 + bcc;
+  const double2* __restrict__ Bsrc = (fld ? ch : ps) + (bkk < nz ? bkk : nz - 1);
+  auto load = [&](int jj0, Stage& d) {
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int e = tid + 256 * t;
-      const int tab = e >> 10, par = (e >> 9) & 1, kr = (e >> 6) & 7, rr = e & 63;
-      const int j = 2 * (jj0 + kr) + par, i = row0 + rr;
-      const bool ok = j < K && i < half;
-      da[t] = ok ? (tab ? T : P)[(int64_t)j * nr + i] : 0.0;
+      const int par = (e >> 9) & 1, kr = (e >> 6) & 7, rr = e & 63;
+      const int j = min(2 * (jj0 + kr) + par, Kc), i = min(row0 + rr, half - 1);
+      d.a[t] = ((t >> 2) ? T : P)[(int64_t)j * nr + i];
     }
-    const int fld = tid >> 7, par = (tid >> 6) & 1, kr = (tid >> 3) & 7, cc = tid & 7;
-    const int j = 2 * (jj0 + kr) + par, kk = kk0 + cc;
-    db = (j < K && kk < nz) ? (fld ? ch : ps)[(int64_t)j * nz + kk] : make_double2(0.0, 0.0);
+    const int j = min(2 * (jj0 + bkr) + bpar, Kc);
+    d.b = Bsrc[(int64_t)j * nz];
   };
-  auto store = [&](int buf, const double (&da)[8], const double2& db) {
+  auto store = [&](int buf, int jj0, const Stage& d) {
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int e = tid + 256 * t;
-      As[buf][e >> 10][(e >> 9) & 1][(e >> 6) & 7][e & 63] = da[t];
+      const int par = (e >> 9) & 1, kr = (e >> 6) & 7, rr = e & 63;
+      const bool ok = 2 * (jj0 + kr) + par < K && row0 + rr < half;
+      As[buf][t >> 2][par][kr][rr] = ok ? d.a[t] : 0.0;
     }
-    const int fld = tid >> 7, par = (tid >> 6) & 1, kr = (tid >> 3) & 7, cc = tid & 7;
-    Bs[buf][fld][par][kr][cc] = db.x;
-    Bs[buf][fld][par][kr][8 + cc] = db.y;
+    const bool ok = 2 * (jj0 + bkr) + bpar < K && bkk < nz;
+    Bs[buf][fld][bpar][bkr][bcc] = ok ? d.b.x : 0.0;
+    Bs[buf][fld][bpar][bkr][8 + bcc] = ok ? d.b.y : 0.0;
   };
-
-  const int nk = (KP + TP - 1) / TP;
-  if (nk > 0) {
-    load(0, ra, rb);
-    store(0, ra, rb);
-  }
-  if (nk > 1) load(TP, ra, rb);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 2 < nk) load((kt + 2) * TP, rn, rbn);
+  auto compute = [&](int buf, int kt) {
 #pragma unroll
     for (int ks = 0; ks < TP; ks += 4) {
       const int kr = ks + (lane >> 4);
@@ -161,11 +161,32 @@ __global__ __launch_bounds__(256, 2) void synth_fold_kernel(FoldSynthArgs a) {
         c[6] = MFMA(aT, lc, c[6]);  // B4 = Tbar L chi
       }
     }
-    if (kt + 1 < nk) store(buf ^ 1, ra, rb);
-#pragma unroll
-    for (int t = 0; t < 8; ++t) ra[t] = rn[t];
-    rb = rbn;
+  };
+
+  const int nk = (KP + TP - 1) / TP;
+  if (nk > 0) {
+    load(0, sx);
+    store(0, 0, sx);
+    load(TP, sy);
     __syncthreads();
+    // stages in pairs (LDS buffer 0, then 1); a stage past the last is loaded from clamped
+    // addresses and written as zeros, and an odd last stage is multiplied after the loop
+    int kt = 0;
+    for (; kt + 1 < nk; kt += 2) {
+      load((kt + 2) * TP, sx);
+      __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
+      compute(0, kt);
+      __builtin_amdgcn_sched_barrier(0);  // and the LDS writes (which wait for their set) after them
+      store(1, (kt + 1) * TP, sy);
+      __syncthreads();
+      load((kt + 3) * TP, sy);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(1, kt + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      store(0, (kt + 2) * TP, sx);
+      __syncthreads();
+    }
+    if (kt < nk) compute(0, kt);
   }
   const bool hi = cl >= 8;
   const int kk = kk0 + (cl & 7);
