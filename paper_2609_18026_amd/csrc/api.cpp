@@ -32,11 +32,10 @@ bool factorable(int n) {
   return n >= 1 && n <= 1024 && factor_radices(n, r) >= 0;
 }
 
-// Workspace partition for FP64 plans: 7 mixed arrays, 5 triangular arrays, solve scratch.
+// Workspace partition for FP64 plans: 7 mixed arrays, 5 triangular arrays.
 struct Ws {
   double* X[7];
   double* T[5];
-  double* scratch;
 };
 
 Ws partition(const mlg_plan_s* p, void* ws) {
@@ -51,7 +50,6 @@ Ws partition(const mlg_plan_s* p, void* ws) {
     w.T[i] = reinterpret_cast<double*>(b + o);
     o += p->tri_elems * 2 * sizeof(double);
   }
-  w.scratch = reinterpret_cast<double*>(b + o);
   return w;
 }
 
@@ -260,7 +258,7 @@ mlg_status mlg_rhs_tp(mlg_plan p, const double* U, const void* psi, const void* 
   // 6. elliptic solves per (m, k)
   const double* csrc[3] = {w.T[0], w.T[1], w.T[2]};
   double* tsrc = tp ? tp + (size_t)9 * p->nz * p->nr * p->nphi : nullptr;
-  return launch_projection(p, csrc, static_cast<double*>(psi_n), static_cast<double*>(chi_n), w.scratch, tsrc, s);
+  return launch_projection(p, csrc, static_cast<double*>(psi_n), static_cast<double*>(chi_n), tsrc, s);
 }
 
 mlg_status mlg_step_setup(mlg_plan p, const mlg_dissip* d) {

@@ -525,30 +525,38 @@ __global__ __launch_bounds__(256) void zfft_kernel(ZGeom g, FftRadices fr, const
 }
 
 // ---------------------------------------------------------------- projection solves
-// One thread per active (m, k slot) column (kept by the axial chop and, with dealiasing, by the
-// two-thirds mask).  Inputs (triangular, k spectral) from the fused projection GEMM: the curl
-// source C = [z . curl N]^, K' = -i kap [(1/r) d_r(r N_r)]^ - m kap [N_phi/r]^ and Zhat = [N_z]^.
+// Per active (m, k slot) column (kept by the axial chop and, with dealiasing, by the two-thirds
+// mask).  Inputs (triangular, k spectral) from the projection products: the curl source
+// C = [z . curl N]^, K' = -i kap [(1/r) d_r(r N_r)]^ - m kap [N_phi/r]^ and Zhat = [N_z]^.
 //   K = K' - Dbar Zhat,  Dbar = -G L / ell^2.
-//   psi: G (L psi) = ell^2 C              (precomputed L D L^T of G)
-//   q:   q = -Zhat at k = 0, else (G + kap^2 ell^2 L^-1)(L q) = -ell^2 K   (L D L^T on the fly)
-//   chi: G (L chi) = -ell^2 q             (precomputed U D U^T of G, started from the top degree)
+//   psi: G (L psi) = ell^2 C              (L D L^T of G, per order)
+//   q:   q = -Zhat at k = 0, else (G + kap^2 ell^2 L^-1)(L q) = -ell^2 K   (L D L^T per column,
+//        a plan constant)
+//   chi: G (L chi) = -ell^2 q             (U D U^T of G, started from the top degree)
 // For m = 0 the unknowns n >= 1 use G restricted to n >= 1 and n = 0 follows from the decay
-// gauge sum_n sqrt((2n+1)/2) s_n = 0.  Three passes over n: ascending (sources, forward
-// substitutions), descending (psi and q back substitution, first chi sweep), ascending (chi).
-// Inputs of each pass are fetched D degrees ahead so that a thread keeps several loads in flight.
+// gauge sum_n sqrt((2n+1)/2) s_n = 0.
+//
+// Every substitution is a linear recurrence of order two, y_t = a_t - al_t y_(t-+1) - be_t y_(t-+2),
+// so its value on a run of degrees is affine in the two values entering the run.  A column is
+// solved by PS_SEG threads, each owning a run of at most SMAX consecutive degrees: a thread sweeps
+// its run from a zero entering state while carrying the two homogeneous solutions (the 2 x 2 map
+// of the entering state), the entering states follow from composing the maps of the runs before
+// it (read from LDS), and the thread adds the homogeneous part.  Four such rounds: the forward
+// substitutions of psi and q, their back substitutions (then psi and q are final), the chi sweep
+// U w = -ell^2 q, and its back substitution.  Every intermediate stays in registers.
 struct ProjArgs {
   const double2* __restrict__ Cs;
   const double2* __restrict__ Kp;
   const double2* __restrict__ Pc;
   double2* __restrict__ psi;
   double2* __restrict__ chi;
-  double* __restrict__ scratch;  // 5 reals per (active column, degree)
   double2* __restrict__ taps;    // C, K, Zhat (triangular) or null
   const double* __restrict__ gram;
   const int64_t* __restrict__ off;
-  int64_t ngram, tri_elems, nact;
-  int M, nz, nrc, nzc, kmax, mmax;  // active: m < mmax, |k| <= kmax and kept
-  int nkact;                        // active k slots per m
+  const double2* __restrict__ qfl;  // q-operator factors (l1, l2), [m][t][slot], nrc + 2 rows per m
+  const double* __restrict__ qfr;   // and reciprocal pivots
+  int64_t ngram, tri_elems;
+  int nz, nrc, kmax, nkact;
   double ell2, kap0;
 };
 
@@ -557,40 +565,104 @@ __device__ __forceinline__ int active_slot(int a, int kmax, int nz) {
   return (a <= kmax) ? a : nz - (2 * kmax + 1 - a);
 }
 
-constexpr int PJ_D = 8;    // degrees per chunk: the next chunk's inputs are in flight while one is computed
-constexpr int PJ_PAD = 2;  // zero entries before and after each per-m coefficient table
+constexpr int PS_SEG = 32;  // threads (runs of degrees) per column
+constexpr int PS_COL = 8;   // columns per block
+constexpr int PJ_PAD = 2;   // zero entries before and after each per-m coefficient table
 
-// One block (one wave) per (m, 64 active k slots).  Every lane walks its column's degrees in the
-// same order, so the per-m coefficients (Gram entries, factors, reciprocal pivots, 1/(n(n+1)),
-// gauge weights) are uniform: they are staged in LDS once per block, padded with zeros so that a
-// coupling that does not exist (before the first solved degree, past the last one) multiplies
-// zero instead of being tested.  The recurrences start from zero state for the same reason, and
-// the k = 0 columns (q = -Zhat) take the general path with selected operands, so the steps
-// contain no branches; only the last partial chunk of each pass tests its range.
-// Scratch per (degree, active column): the forward-swept q (complex), the factor pair (l1, l2)
-// and the reciprocal pivot.
-template <bool TAPS>
-__global__ __launch_bounds__(64) void projection_kernel(ProjArgs a) {
+// LDS: 11 per-m tables of nrc + 2 PJ_PAD entries, then the run maps (16-byte aligned)
+__host__ __device__ constexpr size_t proj_maps_at(int nrc) { return (11 * ((size_t)nrc + 2 * PJ_PAD) + 1) & ~(size_t)1; }
+
+// The affine map of a run: (y_last, y_before) = (c, p) + [h0 h1; h2 h3] (entering y_1, y_2)
+struct RunMap {
+  double2 c, p;
+  double h0, h1, h2, h3;
+};
+
+__device__ __forceinline__ double2 fms2(double2 a, double al, double2 y1, double be, double2 y2) {
+  return make_double2(a.x - al * y1.x - be * y2.x, a.y - al * y1.y - be * y2.y);
+}
+
+// Sweep of one run, in storage order j = 0..len-1 (UP) or len-1..0 (down), from a zero entering
+// state; coef(j, al, be) gives the recurrence coefficients of entry j.
+template <int SMAX, bool UP, class Coef>
+__device__ __forceinline__ RunMap sweep_run(double2 (&y)[SMAX], const double2 (&a)[SMAX], int len, Coef coef) {
+  double2 yc = make_double2(0.0, 0.0), yp = yc;
+  double e1c = 1.0, e1p = 0.0, e2c = 0.0, e2p = 1.0;
+#pragma unroll
+  for (int jj = 0; jj < SMAX; ++jj) {
+    const int j = UP ? jj : SMAX - 1 - jj;
+    if (j < len) {
+      double al, be;
+      coef(j, al, be);
+      const double2 v = fms2(a[j], al, yc, be, yp);
+      yp = yc;
+      yc = v;
+      y[j] = v;
+      const double n1 = -al * e1c - be * e1p, n2 = -al * e2c - be * e2p;
+      e1p = e1c;
+      e1c = n1;
+      e2p = e2c;
+      e2c = n2;
+    }
+  }
+  return RunMap{yc, yp, e1c, e2c, e1p, e2p};
+}
+
+// Entering state of run r from the maps of the runs before it (UP: runs 0..r-1, else PS_SEG-1..r+1)
+template <bool UP>
+__device__ __forceinline__ void enter_state(const RunMap* __restrict__ maps, int r, int c, double2& in1,
+                                            double2& in2) {
+  in1 = make_double2(0.0, 0.0);
+  in2 = in1;
+  const int n = UP ? r : PS_SEG - 1 - r;
+  for (int i = 0; i < n; ++i) {
+    const RunMap q = maps[(UP ? i : PS_SEG - 1 - i) * PS_COL + c];
+    const double2 o1 = make_double2(q.c.x + q.h0 * in1.x + q.h1 * in2.x, q.c.y + q.h0 * in1.y + q.h1 * in2.y);
+    const double2 o2 = make_double2(q.p.x + q.h2 * in1.x + q.h3 * in2.x, q.p.y + q.h2 * in1.y + q.h3 * in2.y);
+    in1 = o1;
+    in2 = o2;
+  }
+}
+
+// Adds the homogeneous solution started from the entering state (in1, in2)
+template <int SMAX, bool UP, class Coef>
+__device__ __forceinline__ void add_entering(double2 (&y)[SMAX], int len, double2 in1, double2 in2, Coef coef) {
+#pragma unroll
+  for (int jj = 0; jj < SMAX; ++jj) {
+    const int j = UP ? jj : SMAX - 1 - jj;
+    if (j < len) {
+      double al, be;
+      coef(j, al, be);
+      const double2 d = make_double2(-al * in1.x - be * in2.x, -al * in1.y - be * in2.y);
+      in2 = in1;
+      in1 = d;
+      y[j] = cadd(y[j], d);
+    }
+  }
+}
+
+template <bool TAPS, int SMAX>
+__global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a) {
   extern __shared__ double sm[];
   const int m = blockIdx.y;
   const int nrc = a.nrc;
   const int cnt = nrc - m;  // degrees n = m .. nrc-1 at index t = n - m
-  const int n0 = m > 0 ? m : 1;
-  const int i0 = n0 - m;  // first solved index (m = 0: n = 0 is the gauge row)
-  const int len = cnt + 2 * PJ_PAD;
+  const int i0 = (m > 0 ? m : 1) - m;  // first solved index (m = 0: n = 0 is the gauge row)
+  const int len_t = cnt + 2 * PJ_PAD;
   double* sg0 = sm + PJ_PAD;
-  double* sg1 = sg0 + len;
-  double* sg2 = sg1 + len;
-  double* srd = sg2 + len;
-  double* sl1 = srd + len;
-  double* sl2 = sl1 + len;
-  double* sru = sl2 + len;
-  double* su1 = sru + len;
-  double* su2 = su1 + len;
-  double* srL = su2 + len;
-  double* sgw = srL + len;
+  double* sg1 = sg0 + len_t;
+  double* sg2 = sg1 + len_t;
+  double* srd = sg2 + len_t;
+  double* sl1 = srd + len_t;
+  double* sl2 = sl1 + len_t;
+  double* sru = sl2 + len_t;
+  double* su1 = sru + len_t;
+  double* su2 = su1 + len_t;
+  double* srL = su2 + len_t;
+  double* sgw = srL + len_t;
+  RunMap* maps = reinterpret_cast<RunMap*>(sm + proj_maps_at(nrc));  // [2][PS_SEG][PS_COL]
   const int64_t gbase = a.off[m];
-  for (int e = threadIdx.x; e < len; e += blockDim.x) {
+  for (int e = threadIdx.x; e < len_t; e += blockDim.x) {
     const int t = e - PJ_PAD;
     const bool in = t >= 0 && t < cnt;
     const int64_t g = gbase + (in ? t : 0);
@@ -609,230 +681,211 @@ __global__ __launch_bounds__(64) void projection_kernel(ProjArgs a) {
     sgw[t] = in ? sqrt((2.0 * n + 1.0) * 0.5) : 0.0;
   }
   __syncthreads();
-  const int ca = blockIdx.x * blockDim.x + threadIdx.x;
-  if (ca >= a.nkact) return;
-  const int64_t col = (int64_t)m * a.nkact + ca;
-  const int kk = active_slot(ca, a.kmax, a.nz);
+
+  const int c = threadIdx.x % PS_COL, r = threadIdx.x / PS_COL;
+  const int ca = blockIdx.x * PS_COL + c;
+  const bool active = ca < a.nkact;
+  const int slot = active ? ca : 0;  // inactive threads load column 0 and store nothing
   const int nz = a.nz;
+  const int kk = active_slot(slot, a.kmax, nz);
   const int k = kval(kk, nz);
   const bool k0 = k == 0;
-  const double kap = a.kap0 * k;
-  const int64_t act = a.nact;
-  double2* __restrict__ sb = reinterpret_cast<double2*>(a.scratch);              // swept q
-  double2* __restrict__ sf = sb + (int64_t)nrc * act;                              // (l1, l2)
-  double* __restrict__ sr = reinterpret_cast<double*>(sf + (int64_t)nrc * act);   // 1 / pivot
+  const int nsol = cnt - i0;
+  const int S = (nsol + PS_SEG - 1) / PS_SEG;
+  const int s0 = i0 + r * S;
+  const int len = max(0, min(s0 + S, cnt) - s0);
+  const double2 z0 = make_double2(0.0, 0.0);
+  const double ell2 = a.ell2, inv_ell2 = 1.0 / a.ell2;
   const double2* __restrict__ Cs = a.Cs + gbase * nz + kk;
   const double2* __restrict__ Kp = a.Kp + gbase * nz + kk;
   const double2* __restrict__ Zc = a.Pc + gbase * nz + kk;
   double2* __restrict__ ps = a.psi + gbase * nz + kk;
   double2* __restrict__ chv = a.chi + gbase * nz + kk;
-  const double2 z0 = make_double2(0.0, 0.0);
-  const double s = kap * kap * a.ell2;
-  const double inv_ell2 = 1.0 / a.ell2;
-  const double ell2 = a.ell2;
-  // loads at a uniform degree index clamped into the column: a value fetched past the end is
-  // consumed only by a step that is range-checked (the tails) or against a zero-padded
-  // coefficient, so it needs no masking
-  auto at = [&](const double2* __restrict__ base, int t) -> double2 {
-    const int tc = t < 0 ? 0 : (t < cnt ? t : cnt - 1);
-    return base[(int64_t)tc * nz];
-  };
-  auto lzv = [&](int t, double2 z) -> double2 {
+  const int qrows = nrc + 2;
+  const double2* __restrict__ qfl = a.qfl + (int64_t)m * qrows * a.nkact + slot;
+  const double* __restrict__ qfr = a.qfr + (int64_t)m * qrows * a.nkact + slot;
+  auto tcl = [&](int t) { return t < 0 ? 0 : (t < cnt ? t : cnt - 1); };  // clamped into the column
+  auto lzv = [&](int t, double2 z) {
     const double n = (double)(m + t);
     return cscale(z, n * (n + 1.0));
   };
+  // (G L Zhat)_t from L Zhat at t-2..t+2 (entries outside the column meet zero-padded couplings)
+  auto glz = [&](int t, double2 zm2, double2 zm1, double2 zc, double2 zp1, double2 zp2) {
+    double2 g = cscale(zc, sg0[t]);
+    g = cadd(g, cscale(zm1, sg1[t - 1]));
+    g = cadd(g, cscale(zm2, sg2[t - 2]));
+    g = cadd(g, cscale(zp1, sg1[t]));
+    return cadd(g, cscale(zp2, sg2[t]));
+  };
 
-  // ---- pass 1 (ascending): sources C, K = K' + G L Zhat / ell^2; forward sweeps for psi and q
-  double2 zpsi1 = z0, zpsi2 = z0, zq1 = z0, zq2 = z0;
-  double rq1 = 0, rq2 = 0, dq1 = 0, dq2 = 0, lq1p = 0;
-  // L Zhat at t - 2 .. t + 2; entries past the column multiply zero-padded Gram couplings
-  double2 lzm2 = z0, lzm1 = z0, lz0 = lzv(0, at(Zc, 0)), lzp1 = lzv(1, at(Zc, 1)), lzp2 = lzv(2, at(Zc, 2));
-  auto glz_at = [&](int t) -> double2 {
-    double2 g = cscale(lz0, sg0[t]);
-    g = cadd(g, cscale(lzm1, sg1[t - 1]));
-    g = cadd(g, cscale(lzm2, sg2[t - 2]));
-    g = cadd(g, cscale(lzp1, sg1[t]));
-    return cadd(g, cscale(lzp2, sg2[t]));
-  };
-  auto shift = [&](int t, double2 z3) {
-    lzm2 = lzm1;
-    lzm1 = lz0;
-    lz0 = lzp1;
-    lzp1 = lzp2;
-    lzp2 = lzv(t + 3, z3);
-  };
-  auto taps_at = [&](int t, double2 C, double2 K) {
-    const int64_t idx = (gbase + t) * nz + kk;
-    a.taps[idx] = C;
-    a.taps[a.tri_elems + idx] = K;
-    a.taps[2 * a.tri_elems + idx] = Zc[(int64_t)t * nz];
-  };
-  auto step1 = [&](int t, double2 C, double2 Kq, double2 z3) {
-    const double2 g = glz_at(t);
-    const double2 K = make_double2(Kq.x + g.x * inv_ell2, Kq.y + g.y * inv_ell2);
-    if (TAPS) taps_at(t, C, K);
-    shift(t, z3);
-    // psi: G (L psi) = ell^2 C, forward sweep with the stored L D L^T
-    double2 b = cscale(C, ell2);
-    b = csub(b, cscale(zpsi1, sl1[t]));
-    b = csub(b, cscale(zpsi2, sl2[t]));
-    zpsi2 = zpsi1;
-    zpsi1 = b;
-    ps[(int64_t)t * nz] = b;
-    // q: (G + kap^2 ell^2 L^-1) (L q) = -ell^2 K, L D L^T formed on the fly
-    const double l2n = sg2[t - 2] * rq2;
-    const double l1n = (sg1[t - 1] - l2n * dq2 * lq1p) * rq1;
-    const double dn = sg0[t] + s * srL[t] - l1n * l1n * dq1 - l2n * l2n * dq2;
-    const double rn = 1.0 / dn;
-    double2 bq = cscale(K, -ell2);
-    bq = csub(bq, cscale(zq1, l1n));
-    bq = csub(bq, cscale(zq2, l2n));
-    zq2 = zq1;
-    zq1 = bq;
-    dq2 = dq1;
-    dq1 = dn;
-    rq2 = rq1;
-    rq1 = rn;
-    lq1p = l1n;
-    const int64_t o = (int64_t)t * act + col;
-    sb[o] = bq;
-    sf[o] = k0 ? z0 : make_double2(l1n, l2n);  // k = 0: q = -Zhat, read back unswept
-    sr[o] = k0 ? 1.0 : rn;
-  };
-  int t1 = 0;
-  if (i0 > 0) {  // m = 0: the gauge row n = 0 only feeds the sources of its neighbours
-    if (TAPS) {
-      const double2 g = glz_at(0);
-      const double2 Kq = at(Kp, 0);
-      taps_at(0, at(Cs, 0), make_double2(Kq.x + g.x * inv_ell2, Kq.y + g.y * inv_ell2));
-    }
-    shift(0, at(Zc, 3));
-    t1 = 1;
-  }
+  // ---- round 1 (ascending): sources, forward substitutions of psi and q
+  double2 yp[SMAX], yq[SMAX];
+  double2 qf[SMAX];
   {
-    double2 cb[PJ_D], kb[PJ_D], zb[PJ_D];
+    double2 ap[SMAX], aq[SMAX];
+    double2 zw[SMAX + 4];  // Zhat at t = s0 - 2 + i
 #pragma unroll
-    for (int d = 0; d < PJ_D; ++d) {
-      cb[d] = at(Cs, t1 + d);
-      kb[d] = at(Kp, t1 + d);
-      zb[d] = at(Zc, t1 + d + 3);
+    for (int i = 0; i < SMAX + 4; ++i) zw[i] = Zc[(int64_t)tcl(s0 - 2 + i) * nz];
+#pragma unroll
+    for (int j = 0; j < SMAX; ++j) {
+      const int t = tcl(s0 + j);
+      ap[j] = Cs[(int64_t)t * nz];
+      aq[j] = Kp[(int64_t)t * nz];
+      qf[j] = qfl[(int64_t)(s0 + j < qrows ? s0 + j : 0) * a.nkact];
     }
-    int tb = t1;
-    for (; tb + PJ_D <= cnt; tb += PJ_D) {
-      double2 cn[PJ_D], kn[PJ_D], zn[PJ_D];
 #pragma unroll
-      for (int d = 0; d < PJ_D; ++d) {
-        cn[d] = at(Cs, tb + PJ_D + d);
-        kn[d] = at(Kp, tb + PJ_D + d);
-        zn[d] = at(Zc, tb + PJ_D + d + 3);
-      }
-#pragma unroll
-      for (int d = 0; d < PJ_D; ++d) step1(tb + d, cb[d], kb[d], zb[d]);
-#pragma unroll
-      for (int d = 0; d < PJ_D; ++d) {
-        cb[d] = cn[d];
-        kb[d] = kn[d];
-        zb[d] = zn[d];
+    for (int j = 0; j < SMAX; ++j) {
+      if (j < len) {
+        const int t = s0 + j;
+        const double2 g = glz(t, lzv(t - 2, zw[j]), lzv(t - 1, zw[j + 1]), lzv(t, zw[j + 2]), lzv(t + 1, zw[j + 3]),
+                              lzv(t + 2, zw[j + 4]));
+        const double2 K = make_double2(aq[j].x + g.x * inv_ell2, aq[j].y + g.y * inv_ell2);
+        if (TAPS && active) {
+          const int64_t idx = (gbase + t) * nz + kk;
+          a.taps[idx] = ap[j];
+          a.taps[a.tri_elems + idx] = K;
+          a.taps[2 * a.tri_elems + idx] = zw[j + 2];
+        }
+        ap[j] = cscale(ap[j], ell2);
+        aq[j] = k0 ? zw[j + 2] : cscale(K, -ell2);  // k = 0: the identity solve keeps Zhat
       }
     }
-    for (int d = 0; d < PJ_D && tb + d < cnt; ++d) step1(tb + d, cb[d], kb[d], zb[d]);
+    if (TAPS && active && r == 0 && i0 > 0) {  // m = 0: the gauge row's sources
+      const double2 za = Zc[0], zb = Zc[(int64_t)tcl(1) * nz], zc2 = Zc[(int64_t)tcl(2) * nz];
+      const double2 g = glz(0, z0, z0, lzv(0, za), lzv(1, zb), lzv(2, zc2));
+      const double2 Kq = Kp[0];
+      a.taps[gbase * nz + kk] = Cs[0];
+      a.taps[a.tri_elems + gbase * nz + kk] = make_double2(Kq.x + g.x * inv_ell2, Kq.y + g.y * inv_ell2);
+      a.taps[2 * a.tri_elems + gbase * nz + kk] = za;
+    }
+    auto cp = [&](int j, double& al, double& be) {
+      al = sl1[s0 + j];
+      be = sl2[s0 + j];
+    };
+    auto cq = [&](int j, double& al, double& be) {
+      al = qf[j].x;
+      be = qf[j].y;
+    };
+    maps[r * PS_COL + c] = sweep_run<SMAX, true>(yp, ap, len, cp);
+    maps[(PS_SEG + r) * PS_COL + c] = sweep_run<SMAX, true>(yq, aq, len, cq);
+    __syncthreads();
+    double2 p1, p2, q1, q2;
+    enter_state<true>(maps, r, c, p1, p2);
+    enter_state<true>(maps + PS_SEG * PS_COL, r, c, q1, q2);
+    add_entering<SMAX, true>(yp, len, p1, p2, cp);
+    add_entering<SMAX, true>(yq, len, q1, q2, cq);
+    __syncthreads();
   }
 
-  // ---- pass 2 (descending): psi and q back substitution, chi sweep U w = -ell^2 q
+  // ---- round 2 (descending): back substitutions of psi and q; psi is final
+  double gpr = 0.0, gpi = 0.0;
   {
-    double2 yp1 = z0, yp2 = z0, yq1 = z0, yq2 = z0, w1 = z0, w2 = z0;
-    double l1q_n1 = 0, l2q_n2 = 0, l2q_n1 = 0;
-    double gpr = 0, gpi = 0;
-    const double2* __restrict__ qsrc = k0 ? Zc : nullptr;
-    auto fetch = [&](int t, double2& fp, double2& fq, double2& ff, double& fr) {
-      const int tc = t < i0 ? i0 : t;
-      const int64_t o = (int64_t)tc * act + col;
-      fp = ps[(int64_t)tc * nz];
-      fq = k0 ? qsrc[(int64_t)tc * nz] : sb[o];
-      ff = sf[o];
-      fr = sr[o];
-    };
-    auto step2 = [&](int t, double2 pz, double2 qz, double2 f, double r) {
-      double2 y = cscale(pz, srd[t]);
-      y = csub(y, cscale(yp1, sl1[t + 1]));
-      y = csub(y, cscale(yp2, sl2[t + 2]));
-      yp2 = yp1;
-      yp1 = y;
-      const double2 v = cscale(y, srL[t]);
-      ps[(int64_t)t * nz] = v;
-      gpr += sgw[t] * v.x;
-      gpi += sgw[t] * v.y;
-      double2 yq = cscale(qz, r);
-      yq = csub(yq, cscale(yq1, l1q_n1));
-      yq = csub(yq, cscale(yq2, l2q_n2));
-      yq2 = yq1;
-      yq1 = yq;
-      l2q_n2 = l2q_n1;
-      l1q_n1 = f.x;
-      l2q_n1 = f.y;
-      const double2 qn = cscale(yq, k0 ? -1.0 : srL[t]);
-      double2 w = cscale(qn, -ell2);
-      w = csub(w, cscale(w1, su1[t]));
-      w = csub(w, cscale(w2, su2[t]));
-      w2 = w1;
-      w1 = w;
-      chv[(int64_t)t * nz] = w;
-    };
-    double2 pz[PJ_D], qz[PJ_D], ff[PJ_D];
-    double rr[PJ_D];
+    double qr[SMAX];
 #pragma unroll
-    for (int d = 0; d < PJ_D; ++d) fetch(cnt - 1 - d, pz[d], qz[d], ff[d], rr[d]);
-    int tb = cnt - 1;
-    for (; tb - PJ_D + 1 >= i0; tb -= PJ_D) {
-      double2 pn[PJ_D], qn[PJ_D], fn[PJ_D];
-      double rn[PJ_D];
+    for (int j = 0; j < SMAX; ++j) {
+      const int t = s0 + j;
+      // couplings to t + 1 and t + 2 (rows past the column hold zeros)
+      const double2 f1 = qfl[(int64_t)(t + 1 < qrows ? t + 1 : 0) * a.nkact];
+      const double2 f2 = qfl[(int64_t)(t + 2 < qrows ? t + 2 : 0) * a.nkact];
+      qf[j] = make_double2(f1.x, f2.y);
+      qr[j] = qfr[(int64_t)(t < qrows ? t : 0) * a.nkact];
+    }
 #pragma unroll
-      for (int d = 0; d < PJ_D; ++d) fetch(tb - PJ_D - d, pn[d], qn[d], fn[d], rn[d]);
-#pragma unroll
-      for (int d = 0; d < PJ_D; ++d) step2(tb - d, pz[d], qz[d], ff[d], rr[d]);
-#pragma unroll
-      for (int d = 0; d < PJ_D; ++d) {
-        pz[d] = pn[d];
-        qz[d] = qn[d];
-        ff[d] = fn[d];
-        rr[d] = rn[d];
+    for (int j = 0; j < SMAX; ++j) {
+      if (j < len) {
+        yp[j] = cscale(yp[j], srd[s0 + j]);
+        yq[j] = cscale(yq[j], qr[j]);
       }
     }
-    for (int d = 0; d < PJ_D && tb - d >= i0; ++d) step2(tb - d, pz[d], qz[d], ff[d], rr[d]);
-    if (m == 0) ps[0] = make_double2(-gpr / sgw[0], -gpi / sgw[0]);
+    auto cp = [&](int j, double& al, double& be) {
+      al = sl1[s0 + j + 1];
+      be = sl2[s0 + j + 2];
+    };
+    auto cq = [&](int j, double& al, double& be) {
+      al = qf[j].x;
+      be = qf[j].y;
+    };
+    double2 bp[SMAX], bq[SMAX];
+    maps[r * PS_COL + c] = sweep_run<SMAX, false>(bp, yp, len, cp);
+    maps[(PS_SEG + r) * PS_COL + c] = sweep_run<SMAX, false>(bq, yq, len, cq);
+    __syncthreads();
+    double2 p1, p2, q1, q2;
+    enter_state<false>(maps, r, c, p1, p2);
+    enter_state<false>(maps + PS_SEG * PS_COL, r, c, q1, q2);
+    add_entering<SMAX, false>(bp, len, p1, p2, cp);
+    add_entering<SMAX, false>(bq, len, q1, q2, cq);
+#pragma unroll
+    for (int j = 0; j < SMAX; ++j) {
+      if (j < len) {
+        const int t = s0 + j;
+        const double2 v = cscale(bp[j], srL[t]);
+        if (active) ps[(int64_t)t * nz] = v;
+        gpr += sgw[t] * v.x;
+        gpi += sgw[t] * v.y;
+        yq[j] = cscale(cscale(bq[j], k0 ? -1.0 : srL[t]), -ell2);  // the chi source -ell^2 q
+      }
+    }
+    __syncthreads();
   }
 
-  // ---- pass 3 (ascending): D U^T y = w
+  // ---- round 3 (descending): U w = -ell^2 q
   {
-    double2 yc1 = z0, yc2 = z0;
-    double gcr = 0, gci = 0;
-    auto step3 = [&](int t, double2 wz) {
-      double2 y = cscale(wz, sru[t]);
-      y = csub(y, cscale(yc1, su1[t - 1]));
-      y = csub(y, cscale(yc2, su2[t - 2]));
-      yc2 = yc1;
-      yc1 = y;
-      const double2 v = cscale(y, srL[t]);
-      chv[(int64_t)t * nz] = v;
-      gcr += sgw[t] * v.x;
-      gci += sgw[t] * v.y;
+    auto cw = [&](int j, double& al, double& be) {
+      al = su1[s0 + j];
+      be = su2[s0 + j];
     };
-    // rows of the next chunk are read (not yet rewritten by this pass) while this chunk is computed
-    double2 wz[PJ_D];
+    maps[r * PS_COL + c] = sweep_run<SMAX, false>(yp, yq, len, cw);
+    __syncthreads();
+    double2 w1, w2;
+    enter_state<false>(maps, r, c, w1, w2);
+    add_entering<SMAX, false>(yp, len, w1, w2, cw);
 #pragma unroll
-    for (int d = 0; d < PJ_D; ++d) wz[d] = at(chv, i0 + d);
-    int tb = i0;
-    for (; tb + PJ_D <= cnt; tb += PJ_D) {
-      double2 wn[PJ_D];
+    for (int j = 0; j < SMAX; ++j)
+      if (j < len) yp[j] = cscale(yp[j], sru[s0 + j]);
+    __syncthreads();
+  }
+
+  // ---- round 4 (ascending): D U^T y = w; chi is final
+  double gcr = 0.0, gci = 0.0;
+  {
+    auto cu = [&](int j, double& al, double& be) {
+      al = su1[s0 + j - 1];
+      be = su2[s0 + j - 2];
+    };
+    maps[r * PS_COL + c] = sweep_run<SMAX, true>(yq, yp, len, cu);
+    __syncthreads();
+    double2 c1, c2;
+    enter_state<true>(maps, r, c, c1, c2);
+    add_entering<SMAX, true>(yq, len, c1, c2, cu);
 #pragma unroll
-      for (int d = 0; d < PJ_D; ++d) wn[d] = at(chv, tb + PJ_D + d);
-#pragma unroll
-      for (int d = 0; d < PJ_D; ++d) step3(tb + d, wz[d]);
-#pragma unroll
-      for (int d = 0; d < PJ_D; ++d) wz[d] = wn[d];
+    for (int j = 0; j < SMAX; ++j) {
+      if (j < len) {
+        const int t = s0 + j;
+        const double2 v = cscale(yq[j], srL[t]);
+        if (active) chv[(int64_t)t * nz] = v;
+        gcr += sgw[t] * v.x;
+        gci += sgw[t] * v.y;
+      }
     }
-    for (int d = 0; d < PJ_D && tb + d < cnt; ++d) step3(tb + d, wz[d]);
-    if (m == 0) chv[0] = make_double2(-gcr / sgw[0], -gci / sgw[0]);
+  }
+
+  // ---- m = 0: the gauge row n = 0 from the sums over the column
+  if (m == 0) {
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(maps);
+    const int e = r * PS_COL + c;
+    red[4 * e + 0] = gpr;
+    red[4 * e + 1] = gpi;
+    red[4 * e + 2] = gcr;
+    red[4 * e + 3] = gci;
+    __syncthreads();
+    if (r == 0 && active) {
+      double s[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int i = 0; i < PS_SEG; ++i)
+        for (int v = 0; v < 4; ++v) s[v] += red[4 * (i * PS_COL + c) + v];
+      ps[0] = make_double2(-s[0] / sgw[0], -s[1] / sgw[0]);
+      chv[0] = make_double2(-s[2] / sgw[0], -s[3] / sgw[0]);
+    }
   }
 }
 
@@ -1136,32 +1189,30 @@ void active_columns(const mlg_plan_s* p, int* mmax_out, int* kmax_out) {
 }
 
 mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, double* psi_n, double* chi_n,
-                             double* scratch, double* taps_src, hipStream_t s) {
+                             double* taps_src, hipStream_t s) {
   ProjArgs a{};
   a.Cs = reinterpret_cast<const double2*>(src3[0]);
   a.Kp = reinterpret_cast<const double2*>(src3[1]);
   a.Pc = reinterpret_cast<const double2*>(src3[2]);
   a.psi = reinterpret_cast<double2*>(psi_n);
   a.chi = reinterpret_cast<double2*>(chi_n);
-  a.scratch = scratch;
   a.taps = reinterpret_cast<double2*>(taps_src);
   a.gram = p->d_gram;
   a.off = p->d_goff;  // the Gram offsets coincide with the triangular row offsets
+  a.qfl = p->d_qfl;
+  a.qfr = p->d_qfr;
   a.ngram = p->ngram;
   a.tri_elems = (int64_t)p->tri_elems;
-  a.M = p->M;
   a.nz = p->nz;
   a.nrc = p->nrc;
-  a.nzc = p->nzc;
   int mmax, kmax;
   active_columns(p, &mmax, &kmax);
   a.kmax = kmax;
-  a.mmax = mmax;
-  a.nkact = 2 * kmax + 1;
-  if (p->nz == 1) a.nkact = 1;
-  a.nact = (int64_t)mmax * a.nkact;
+  a.nkact = p->nz == 1 ? 1 : 2 * kmax + 1;
   a.ell2 = p->g.ell * p->g.ell;
   a.kap0 = 2.0 * M_PI / p->g.lz;
+  // runs of at most SMAX degrees: ceil((nrc - 1) / PS_SEG) for the longest column (m = 0)
+  if (p->nrc - 1 > 16 * PS_SEG) return fail(MLG_E_UNSUPPORTED, "projection solves: nrc above 513");
   const int64_t total = p->tau * p->nz;
   if (total > 0) {
     int blocks = (int)std::min<int64_t>((total + 255) / 256, 65536);
@@ -1173,14 +1224,19 @@ mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, dou
     p->timing.end(s);
     if (mlg_status st = check_launch("zero_inactive_kernel")) return st;
   }
-  if (a.nact > 0) {
-    dim3 grid((unsigned)((a.nkact + 63) / 64), (unsigned)mmax);
-    const size_t shm = (size_t)11 * (p->nrc + 2 * PJ_PAD) * sizeof(double);
+  if (mmax > 0 && a.nkact > 0) {
+    dim3 grid((unsigned)((a.nkact + PS_COL - 1) / PS_COL), (unsigned)mmax);
+    const size_t shm = (proj_maps_at(p->nrc) + (size_t)2 * PS_SEG * PS_COL * (sizeof(RunMap) / sizeof(double))) *
+                       sizeof(double);
+    const bool wide = p->nrc - 1 > 8 * PS_SEG;
     p->timing.begin("projection", s);
-    if (a.taps)
-      projection_kernel<true><<<grid, 64, shm, s>>>(a);
-    else
-      projection_kernel<false><<<grid, 64, shm, s>>>(a);
+    if (a.taps) {
+      if (wide) projection_kernel<true, 16><<<grid, PS_SEG * PS_COL, shm, s>>>(a);
+      else projection_kernel<true, 8><<<grid, PS_SEG * PS_COL, shm, s>>>(a);
+    } else {
+      if (wide) projection_kernel<false, 16><<<grid, PS_SEG * PS_COL, shm, s>>>(a);
+      else projection_kernel<false, 8><<<grid, PS_SEG * PS_COL, shm, s>>>(a);
+    }
     p->timing.end(s);
   }
   return check_launch("projection_kernel");

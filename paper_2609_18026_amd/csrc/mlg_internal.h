@@ -91,6 +91,11 @@ struct mlg_plan_s {
   double* d_gram = nullptr;    // packed g0,g1,g2 | LDL^T 1/d,l1,l2 | UDU^T 1/d,u1,u2 (9 * ngram)
   int64_t* d_goff = nullptr;
   int64_t ngram = 0;
+  // L D L^T factors of G + kap^2 ell^2 L^-1 for every active (m, k) column of the projection:
+  // (l1, l2) and 1 / pivot at [m][n - m][active k slot], nrc + 2 rows per order (rows past the
+  // column are zero); the identity for k = 0
+  double2* d_qfl = nullptr;
+  double* d_qfr = nullptr;
   int max_rows_fwd = 0, max_rows_bwd = 0;
   // split-bfloat16 tables (MLG_SPLIT_BF16 plans): hi / lo parts, rows padded to 32 entries
   unsigned short* d_split_syn[4] = {nullptr, nullptr, nullptr, nullptr};  // Pbar^T hi/lo, Tbar^T hi/lo [i][kpad]
@@ -161,7 +166,7 @@ mlg_status launch_zfft_fields(const mlg_plan_s* p, const double* const* in, doub
                               int dir, const int32_t* row_m, int mask_m, int mask_k, hipStream_t s);
 // Elliptic solves from the projection sources (C, K', Zhat); taps_src receives C, K, Zhat.
 mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, double* psi_n, double* chi_n,
-                             double* scratch, double* taps_src, hipStream_t s);
+                             double* taps_src, hipStream_t s);
 // gemm_fused.hip: synthesis of the six velocity / vorticity harmonics from (psi, chi), and the five
 // projection products with the C, K', Zhat epilogue on the active (m < mmax, |k| <= kmax) columns.
 mlg_status launch_synth_gemm(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,

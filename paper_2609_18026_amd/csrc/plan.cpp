@@ -152,7 +152,7 @@ void free_plan_device(mlg_plan_s* p) {
                   p->d_split_syn_off, p->d_split_syn_kpad, p->d_split_prj[0], p->d_split_prj[1],
                   p->d_split_prj[2], p->d_split_prj[3], p->d_split_prj_off, p->d_split_zdft, p->d_step_fwd,
                   p->d_step_bwd, p->d_step_lam, p->d_step_u, p->d_step_qoff, p->d_step_loff, p->d_step_w,
-                  p->d_filter, p->d_logf};
+                  p->d_filter, p->d_logf, p->d_qfl, p->d_qfr};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }
@@ -408,6 +408,52 @@ mlg_status build_plan(mlg_plan_s* p) {
     gram[7 * p->ngram + k] = u1[k];
     gram[8 * p->ngram + k] = u2[k];
   }
+  // ---------------- factors of the q operator of the projection, G + kap^2 ell^2 L^-1 (L =
+  // diag(n (n + 1))), per active (m, k) column: L D L^T over the solved degrees (m = 0: n >= 1)
+  {
+    int mmax = 0, kmax = 0;
+    active_columns(p, &mmax, &kmax);
+    const int nkact = nz == 1 ? 1 : 2 * kmax + 1;
+    const int rows = nrc + 2;
+    const size_t cells = (size_t)std::max(mmax, 0) * rows * nkact;
+    std::vector<double2> qfl(std::max<size_t>(cells, 1), make_double2(0.0, 0.0));
+    std::vector<double> qfr(std::max<size_t>(cells, 1), 0.0);
+    const ld kap0 = 2 * acosl(-1.0L) / (ld)p->g.lz, ell2 = (ld)p->g.ell * (ld)p->g.ell;
+    std::vector<ld> d(rows), l1(rows);
+    for (int m = 0; m < mmax; ++m) {
+      const int cnt = nrc - m, i0 = std::max(m, 1) - m;
+      const int64_t gb = gf.goff[m];
+      for (int a = 0; a < nkact; ++a) {
+        const int kk = (a <= kmax) ? a : nz - (2 * kmax + 1 - a);
+        const int k = (2 * kk < nz) ? kk : kk - nz;
+        const ld sk = kap0 * kap0 * (ld)k * (ld)k * ell2;
+        for (int t = i0; t < cnt; ++t) {
+          const size_t o = ((size_t)m * rows + t) * nkact + a;
+          if (k == 0) {  // q = -Zhat: no solve
+            qfr[o] = 1.0;
+            continue;
+          }
+          const ld n = (ld)(m + t);
+          ld l2 = 0, l1t = 0;
+          if (t - 2 >= i0) l2 = (ld)gf.g2[gb + t - 2] / d[t - 2];
+          if (t - 1 >= i0) {
+            ld c = gf.g1[gb + t - 1];
+            if (t - 2 >= i0) c -= l2 * d[t - 2] * l1[t - 1];
+            l1t = c / d[t - 1];
+          }
+          ld dt = (ld)gf.g0[gb + t] + sk / (n * (n + 1));
+          if (t - 1 >= i0) dt -= l1t * l1t * d[t - 1];
+          if (t - 2 >= i0) dt -= l2 * l2 * d[t - 2];
+          d[t] = dt;
+          l1[t] = l1t;
+          qfl[o] = make_double2((double)l1t, (double)l2);
+          qfr[o] = (double)(1.0L / dt);
+        }
+      }
+    }
+    mlg_status st2;
+    if ((st2 = upload(&p->d_qfl, qfl)) || (st2 = upload(&p->d_qfr, qfr))) return st2;
+  }
   // ---------------- nodal vectors, twiddles, row orders, GEMM descriptors
   std::vector<double> node(4 * nr);
   for (int i = 0; i < nr; ++i) {
@@ -456,11 +502,10 @@ mlg_status build_plan(mlg_plan_s* p) {
       (st = upload(&p->d_desc_fwd, dfwd)) || (st = upload(&p->d_desc_bwd, dbwd)) ||
       (st = upload(&p->d_gram, gram)) || (st = upload(&p->d_goff, gf.goff)))
     return st;
-  // ---------------- workspace: 7 mixed + 5 triangular + solve scratch (5 reals per column and degree)
+  // ---------------- workspace: 7 mixed + 5 triangular arrays
   p->mixed_elems = (size_t)M * nr * nz;
   p->tri_elems = (size_t)p->tau * nz;
-  const size_t scratch = (size_t)5 * nrc * M * nz;
-  p->ws_bytes = (7 * p->mixed_elems * 2 + 5 * p->tri_elems * 2 + scratch) * sizeof(double) + 1024;
+  p->ws_bytes = (7 * p->mixed_elems * 2 + 5 * p->tri_elems * 2) * sizeof(double) + 1024;
   return MLG_OK;
 }
 
