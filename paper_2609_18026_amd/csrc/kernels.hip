@@ -555,8 +555,9 @@ struct ProjArgs {
   const int64_t* __restrict__ off;
   const double2* __restrict__ qfl;  // q-operator factors (l1, l2), [m][t][slot], nrc + 2 rows per m
   const double* __restrict__ qfr;   // and reciprocal pivots
-  int64_t ngram, tri_elems;
-  int nz, nrc, kmax, nkact;
+  const int32_t* __restrict__ row_m;  // order of each triangular row
+  int64_t ngram, tri_elems, rows;
+  int nz, nrc, kmax, nkact, mmax;
   double ell2, kap0;
 };
 
@@ -645,6 +646,27 @@ template <bool TAPS, int SMAX>
 __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a) {
   extern __shared__ double sm[];
   const int m = blockIdx.y;
+  {
+    // every block first clears its share of the entries whose (m, k) column is not solved (the
+    // stores drain while the solves wait on their loads)
+    const int64_t total = a.rows * a.nz;
+    const int64_t nb = (int64_t)gridDim.x * gridDim.y, b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const int64_t per = (total + nb - 1) / nb;
+    const int64_t e1 = min(total, (b + 1) * per);
+    const double2 z = make_double2(0.0, 0.0);
+    for (int64_t e = b * per + threadIdx.x; e < e1; e += blockDim.x) {
+      const int64_t row = e / a.nz;
+      const int k = kval((int)(e - row * a.nz), a.nz);
+      if (a.row_m[row] < a.mmax && (k < 0 ? -k : k) <= a.kmax) continue;
+      a.psi[e] = z;
+      a.chi[e] = z;
+      if (TAPS) {
+        a.taps[e] = z;
+        a.taps[a.tri_elems + e] = z;
+        a.taps[2 * a.tri_elems + e] = z;
+      }
+    }
+  }
   const int nrc = a.nrc;
   const int cnt = nrc - m;  // degrees n = m .. nrc-1 at index t = n - m
   const int i0 = (m > 0 ? m : 1) - m;  // first solved index (m = 0: n = 0 is the gauge row)
@@ -660,7 +682,7 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
   double* su2 = su1 + len_t;
   double* srL = su2 + len_t;
   double* sgw = srL + len_t;
-  RunMap* maps = reinterpret_cast<RunMap*>(sm + proj_maps_at(nrc));  // [2][PS_SEG][PS_COL]
+  RunMap* maps = reinterpret_cast<RunMap*>(sm + proj_maps_at(nrc));  // [PS_SEG][PS_COL]
   const int64_t gbase = a.off[m];
   for (int e = threadIdx.x; e < len_t; e += blockDim.x) {
     const int t = e - PJ_PAD;
@@ -766,12 +788,15 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
       al = qf[j].x;
       be = qf[j].y;
     };
+    const RunMap mq = sweep_run<SMAX, true>(yq, aq, len, cq);
     maps[r * PS_COL + c] = sweep_run<SMAX, true>(yp, ap, len, cp);
-    maps[(PS_SEG + r) * PS_COL + c] = sweep_run<SMAX, true>(yq, aq, len, cq);
     __syncthreads();
     double2 p1, p2, q1, q2;
     enter_state<true>(maps, r, c, p1, p2);
-    enter_state<true>(maps + PS_SEG * PS_COL, r, c, q1, q2);
+    __syncthreads();
+    maps[r * PS_COL + c] = mq;
+    __syncthreads();
+    enter_state<true>(maps, r, c, q1, q2);
     add_entering<SMAX, true>(yp, len, p1, p2, cp);
     add_entering<SMAX, true>(yq, len, q1, q2, cq);
     __syncthreads();
@@ -806,12 +831,15 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
       be = qf[j].y;
     };
     double2 bp[SMAX], bq[SMAX];
+    const RunMap mq = sweep_run<SMAX, false>(bq, yq, len, cq);
     maps[r * PS_COL + c] = sweep_run<SMAX, false>(bp, yp, len, cp);
-    maps[(PS_SEG + r) * PS_COL + c] = sweep_run<SMAX, false>(bq, yq, len, cq);
     __syncthreads();
     double2 p1, p2, q1, q2;
     enter_state<false>(maps, r, c, p1, p2);
-    enter_state<false>(maps + PS_SEG * PS_COL, r, c, q1, q2);
+    __syncthreads();
+    maps[r * PS_COL + c] = mq;
+    __syncthreads();
+    enter_state<false>(maps, r, c, q1, q2);
     add_entering<SMAX, false>(bp, len, p1, p2, cp);
     add_entering<SMAX, false>(bq, len, q1, q2, cq);
 #pragma unroll
@@ -1201,6 +1229,8 @@ mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, dou
   a.off = p->d_goff;  // the Gram offsets coincide with the triangular row offsets
   a.qfl = p->d_qfl;
   a.qfr = p->d_qfr;
+  a.row_m = p->d_row_m;
+  a.rows = p->tau;
   a.ngram = p->ngram;
   a.tri_elems = (int64_t)p->tri_elems;
   a.nz = p->nz;
@@ -1209,12 +1239,14 @@ mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, dou
   active_columns(p, &mmax, &kmax);
   a.kmax = kmax;
   a.nkact = p->nz == 1 ? 1 : 2 * kmax + 1;
+  a.mmax = mmax;
   a.ell2 = p->g.ell * p->g.ell;
   a.kap0 = 2.0 * M_PI / p->g.lz;
   // runs of at most SMAX degrees: ceil((nrc - 1) / PS_SEG) for the longest column (m = 0)
   if (p->nrc - 1 > 16 * PS_SEG) return fail(MLG_E_UNSUPPORTED, "projection solves: nrc above 513");
   const int64_t total = p->tau * p->nz;
-  if (total > 0) {
+  const bool solve = mmax > 0 && a.nkact > 0;
+  if (total > 0 && !solve) {  // otherwise the solve blocks clear the inactive entries
     int blocks = (int)std::min<int64_t>((total + 255) / 256, 65536);
     double2* t0 = a.taps;
     p->timing.begin("projection", s);
@@ -1224,9 +1256,9 @@ mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, dou
     p->timing.end(s);
     if (mlg_status st = check_launch("zero_inactive_kernel")) return st;
   }
-  if (mmax > 0 && a.nkact > 0) {
+  if (solve) {
     dim3 grid((unsigned)((a.nkact + PS_COL - 1) / PS_COL), (unsigned)mmax);
-    const size_t shm = (proj_maps_at(p->nrc) + (size_t)2 * PS_SEG * PS_COL * (sizeof(RunMap) / sizeof(double))) *
+    const size_t shm = (proj_maps_at(p->nrc) + (size_t)PS_SEG * PS_COL * (sizeof(RunMap) / sizeof(double))) *
                        sizeof(double);
     const bool wide = p->nrc - 1 > 8 * PS_SEG;
     p->timing.begin("projection", s);
