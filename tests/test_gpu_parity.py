@@ -196,6 +196,8 @@ TP_CHOP_CASES = [
     (33, 12, 6, 0.8, 3.0, (0.1, 0.3, -0.2), 1, 25),       # odd N_r: unfolded products
     (24, 64, 8, 1.1, 2.0, (0.2, 0.0, 0.1), 0, 12),        # M = 32 > N_r^c: orders m >= 12 have no degrees
     (20, 256, 256, 1.0, 8.6, (0.0, 1.0, 0.0), 1, 16),     # 256-point phi and z
+    (300, 8, 4, 1.0, 3.0, (0.1, 0.0, 0.2), 1, 0),         # N_r^c above 257: runs of 16 degrees in the solves
+    (301, 6, 6, 0.9, 2.5, (0.0, 0.2, 0.3), 0, 280),       # the same, odd N_r with a margin
 ]
 
 
@@ -216,6 +218,13 @@ def test_rhs_tp_parity_taps(case):
     # backward error of the library's solve in its own equations (its sources were checked above)
     be = _backward_error(g, got["psi"], got["chi"], got["C"], got["K"], got["Z"], dealias)
     assert be < 1e-14, be
-    # forward difference: bounded by conditioning; at these sizes it stays small
-    _say("  psi/chi forward rel diff", rel(got["psi"], ref_psi), rel(got["chi"], ref_chi), "backward err", be)
-    assert rel(got["psi"], ref_psi) < 1e-9 and rel(got["chi"], ref_chi) < 1e-9
+    # forward difference: bounded by conditioning.  Up to N_r^c = 256 it stays below 1e-9; above,
+    # cond(Dbar_1) (5.5e9 at N_r^c = 300) times the last digits of the sources sets it for any
+    # backward-stable solver (sequential substitution gives the same psi 3.9e-8, chi 6e-7 there),
+    # so the bar becomes 4 eps cond(Dbar_1) while the backward error above stays the binding check
+    fwd = 1e-9
+    if g.nrc > 256:
+        fwd = 4 * np.finfo(float).eps * np.linalg.cond(laplacian_matrix(1, g.nrc, g.ell))
+    _say("  psi/chi forward rel diff", rel(got["psi"], ref_psi), rel(got["chi"], ref_chi), "backward err", be,
+         "bar", fwd)
+    assert rel(got["psi"], ref_psi) < fwd and rel(got["chi"], ref_chi) < fwd
