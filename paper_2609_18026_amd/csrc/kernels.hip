@@ -744,7 +744,9 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
   double2 yp[SMAX], yq[SMAX];
   double2 qf[SMAX];
   {
-    double2 ap[SMAX], aq[SMAX];
+    // the sweeps overwrite their sources in place (entry j is read before it is written)
+    double2 (&ap)[SMAX] = yp;
+    double2 (&aq)[SMAX] = yq;
     double2 zw[SMAX + 4];  // Zhat at t = s0 - 2 + i
 #pragma unroll
     for (int i = 0; i < SMAX + 4; ++i) zw[i] = Zc[(int64_t)tcl(s0 - 2 + i) * nz];
@@ -830,7 +832,8 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
       al = qf[j].x;
       be = qf[j].y;
     };
-    double2 bp[SMAX], bq[SMAX];
+    double2 (&bp)[SMAX] = yp;  // in place, as in round 1
+    double2 (&bq)[SMAX] = yq;
     const RunMap mq = sweep_run<SMAX, false>(bq, yq, len, cq);
     maps[r * PS_COL + c] = sweep_run<SMAX, false>(bp, yp, len, cp);
     __syncthreads();
