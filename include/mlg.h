@@ -255,8 +255,9 @@ mlg_status mlg_timing_enable(mlg_plan plan, int enable);
 mlg_status mlg_timing_read(mlg_plan plan, const char* kernel, double* total_ms, int64_t* launches);
 
 /* ---------------------------------------------------------------- batched 2D instances
- * Many independent 2D fields (N_z = 1) of uneven sizes, each with its own grid, advanced by one
- * persistent (cooperative) kernel launch: the pseudospectral KPP term
+ * Many independent 2D fields (N_z = 1) of uneven sizes, each with its own grid, advanced by three
+ * persistent launches (backward transforms, azimuthal stage, forward projections, each block walking
+ * its share of the phase's cost-sorted work list): the pseudospectral KPP term
  * R_b = Mask(F(gamma u (1 - u))), u = B(u_hat_b), of Sec. 3.3 and Sec. 5.2 (Eq. kpp), for every
  * instance b.  Spectra of all instances are packed in one device buffer: instance b occupies the
  * complex elements [spec_offsets[b], spec_offsets[b+1]) in the packed triangular layout of a
@@ -264,7 +265,7 @@ mlg_status mlg_timing_read(mlg_plan plan, const char* kernel, double* total_ms, 
  * Legendre recurrence are built in FP64. */
 typedef struct mlg_batch_s* mlg_batch;
 
-/* Launch shape of the persistent kernel: regenerate Pbar by its recurrence in the backward
+/* Launch shape of the persistent kernels: regenerate Pbar by its recurrence in the backward
  * phase (1) or stream tables (0); threads per block (64, 128, 256); blocks per compute unit
  * (1..8, capped by occupancy); azimuthal lines per work item (even, 2..32). */
 typedef struct {
@@ -278,12 +279,12 @@ mlg_status mlg_batch_create(int count, const mlg_grid* grids, mlg_precision prec
 mlg_status mlg_batch_destroy(mlg_batch batch);
 /* spec_offsets: host array of count + 1 entries (may be NULL); workspace_bytes may be NULL. */
 mlg_status mlg_batch_query(mlg_batch batch, int64_t* spec_offsets, int64_t* workspace_bytes);
-/* One persistent launch over all instances.  spec_in and spec_out must not alias. */
+/* The three launches over all instances, in stream order.  spec_in and spec_out must not alias. */
 mlg_status mlg_batch_rhs_scalar(mlg_batch batch, double gamma, const void* spec_in, void* spec_out, void* ws,
                                 void* stream);
 mlg_status mlg_batch_set_config(mlg_batch batch, const mlg_batch_config* config);
 mlg_status mlg_batch_get_config(mlg_batch batch, mlg_batch_config* config);
-/* Autotuner: times every candidate launch shape (recurrence or tables x 128/256 threads x 1, 2, 4
+/* Autotuner: times every candidate launch shape (recurrence or tables x 128/256 threads x 1, 2, 4, 8
  * blocks per CU x 4, 8, 16 lines per item) on the given buffers with HIP events, keeps the fastest
  * for later calls and returns it (chosen, best_ms may be NULL).  Overwrites spec_out. */
 mlg_status mlg_batch_autotune(mlg_batch batch, double gamma, const void* spec_in, void* spec_out, void* ws,

@@ -1,8 +1,10 @@
-// Batched pseudospectral KPP term for many uneven 2D instances in one persistent launch.
+// Batched pseudospectral KPP term for many uneven 2D instances.
 //
 // For each instance b (N_z = 1): R_b = Mask(F(gamma u (1 - u))), u = B(u_hat_b) (Sec. 3.3;
-// Sec. 5.2, Eq. kpp).  A cooperative kernel, sized to be co-resident, walks three phases
-// separated by grid barriers:
+// Sec. 5.2, Eq. kpp).  Three persistent launches (a fixed number of blocks per CU, each block
+// walking its share of the phase's work list) run the phases; the kernel boundaries order them
+// (a grid-wide barrier inside one cooperative launch costs about 50 us on this part, against a few
+// microseconds for a launch boundary):
 //   1. backward radial transform per (instance, m): f_m(r_i) = sum_n Pbar_n^m(x_i) u_hat_n^m;
 //      Pbar either streamed from per-instance tables or regenerated in the kernel by the
 //      normalised three-term recurrence (FP64) from Pbar_m^m(x_i);
@@ -11,7 +13,6 @@
 //   3. forward radial projection per (instance, m): u_hat_n^m = sum_i w_i Pbar_n^m(x_i) g_m(r_i).
 // Work lists of each phase are sorted by cost (largest first) and dealt round-robin to the
 // blocks.  Data may be FP64 or FP32 (template T); recurrences and tables are built in FP64.
-#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,8 +26,6 @@
 #include <vector>
 
 #include "mlg_internal.h"
-
-namespace cg = cooperative_groups;
 
 namespace mlg {
 
@@ -354,23 +353,14 @@ __device__ void phase_forward(const BatchArgs<T>& A, int b, int m, char* smem) {
   __syncthreads();
 }
 
-template <typename T>
+template <typename T, int PHASE>
 __global__ void batch_kernel(BatchArgs<T> A) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  cg::grid_group grid = cg::this_grid();
-  for (int it = blockIdx.x; it < A.nitems[0]; it += gridDim.x) {
-    const int w = A.items[0][it];
-    phase_backward<T>(A, w >> 16, w & 0xffff, smem);
-  }
-  grid.sync();
-  for (int it = blockIdx.x; it < A.nitems[1]; it += gridDim.x) {
-    const int w = A.items[1][it];
-    phase_phi<T>(A, w >> 16, w & 0xffff, smem);
-  }
-  grid.sync();
-  for (int it = blockIdx.x; it < A.nitems[2]; it += gridDim.x) {
-    const int w = A.items[2][it];
-    phase_forward<T>(A, w >> 16, w & 0xffff, smem);
+  for (int it = blockIdx.x; it < A.nitems[PHASE]; it += gridDim.x) {
+    const int w = A.items[PHASE][it];
+    if constexpr (PHASE == 0) phase_backward<T>(A, w >> 16, w & 0xffff, smem);
+    else if constexpr (PHASE == 1) phase_phi<T>(A, w >> 16, w & 0xffff, smem);
+    else phase_forward<T>(A, w >> 16, w & 0xffff, smem);
   }
 }
 
@@ -405,14 +395,21 @@ mlg_status run_batch(const mlg_batch_s* bt, double gamma, const void* in, void* 
   A.lines = c.lines;
   A.gamma = (T)gamma;
   const size_t shm = smem_bytes(bt, c.lines);
-  int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<T>, c.threads, shm);
-  if (e != hipSuccess || per_cu <= 0) return fail(MLG_E_DEVICE, "batch kernel does not fit on a CU");
+  // blocks per CU: the configured count, capped by what the phase kernels' registers and LDS allow
+  int per_cu = 1 << 30;
+  for (const void* k : {reinterpret_cast<const void*>(batch_kernel<T, 0>), reinterpret_cast<const void*>(batch_kernel<T, 1>),
+                        reinterpret_cast<const void*>(batch_kernel<T, 2>)}) {
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, c.threads, shm);
+    if (e != hipSuccess || n <= 0) return fail(MLG_E_DEVICE, "batch kernel does not fit on a CU");
+    per_cu = std::min(per_cu, n);
+  }
   const int blocks = std::max(1, std::min(per_cu, c.blocks_per_cu) * bt->cus);
-  void* args[] = {&A};
-  e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(batch_kernel<T>), dim3(blocks), dim3(c.threads),
-                                 args, (unsigned)shm, s);
-  if (e != hipSuccess) return fail(MLG_E_DEVICE, std::string("hipLaunchCooperativeKernel: ") + hipGetErrorString(e));
+  batch_kernel<T, 0><<<dim3(blocks), dim3(c.threads), shm, s>>>(A);
+  batch_kernel<T, 1><<<dim3(blocks), dim3(c.threads), shm, s>>>(A);
+  batch_kernel<T, 2><<<dim3(blocks), dim3(c.threads), shm, s>>>(A);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(MLG_E_DEVICE, std::string("batch kernel launch: ") + hipGetErrorString(e));
   return MLG_OK;
 }
 
@@ -686,7 +683,7 @@ mlg_status mlg_batch_autotune(mlg_batch b, double gamma, const void* spec_in, vo
     return fail(MLG_E_DEVICE, "hipEventCreate failed");
   const int lines_c[] = {4, 8, 16};
   const int thr_c[] = {128, 256};
-  const int bpc_c[] = {1, 2, 4};
+  const int bpc_c[] = {1, 2, 4, 8};
   BatchConfig best = b->cfg;
   float best_t = 1e30f;
   mlg_status st = MLG_OK;
