@@ -13,6 +13,11 @@ Test infrastructure only (see the package header).
 
 Spectral states use the oracle layout (M, N_r^c, N_z); each (m, k) column is
 advanced with dense matrices.
+
+Pins: the printed Table tab:oseen and the manufactured mode (nu only, no axial
+dependence); the -kappa^2 shift and the hyperviscous power against symbolic
+(-grad^2)^{p/2} of fields in the retained span, and AB-CN with kappa != 0 against
+the three-dimensional heat kernel (tests/test_oracle_dissipation_pins.py).
 """
 from __future__ import annotations
 
