@@ -335,6 +335,9 @@ def bench_closure(torch, args, stream, e0, e1):
                      "nu_h=1e-14, p=8, dt=5e-4, 12 snapshots 40 steps apart; runs 0-5 train, 6-7 held out"}
     log(f"bench: closure train step {train_ms:.3f} ms, inference {inf_ms:.3f} ms vs coarse RHS {rhs_ms:.3f} ms, "
         f"held-out gain {g_free:.3f} (judged {g_jud:.3f})")
+    torch.cuda.synchronize()
+    for h in (free, cl, fine, coarse):
+        h.close()
     return res
 
 
@@ -489,7 +492,9 @@ def main():
     spair_ms = e0.elapsed_time(e1) / args.steps
     perr = float(torch.linalg.vector_norm(sphys - phys) / torch.linalg.vector_norm(phys))
     serr = float(torch.linalg.vector_norm(sspec - spec) / torch.linalg.vector_norm(spec))
-    del splan, sphys, sspec
+    torch.cuda.synchronize()
+    splan.close()
+    del sphys, sspec
     uw_ref = torch.empty(6 * plan.layout.phys_elems, dtype=torch.float64, device="cuda")
     uw_spl = torch.empty_like(uw_ref)
     plan.synthesize(ref_p, ref_c, uw_ref)
@@ -509,6 +514,8 @@ def main():
     out["time_step"] = bench_time_step(torch, plan, psi, chi, args, stream, e0, e1)
     if not args.no_closure:
         out["closure"] = bench_closure(torch, args, stream, e0, e1)
+    torch.cuda.synchronize()
+    plan.close()                 # every native handle is released before the interpreter shuts down
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)

@@ -149,6 +149,33 @@ def _check(status: int) -> None:
         raise MlgError(status, mlg_last_error())
 
 
+_DEVICE_TYPE = "cuda"        # where the library's buffers live (the CPU tests of the checks substitute "cpu")
+
+
+def _ptr(t, name: str, dtypes, numel: int, device: int) -> int:
+    """data_ptr() of a tensor the library will read or write, after checking it against what the
+    entry point assumes: one of 'dtypes', contiguous, on cuda:'device', at least 'numel' elements.
+    A mismatch raises ValueError before any native call (a wrong buffer would make the kernels
+    access memory outside it)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {' or '.join(str(d) for d in dtypes)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name}: {t.numel()} elements, need at least {numel}")
+    if t.device.type != _DEVICE_TYPE or (t.device.index if t.device.index is not None else 0) != device:
+        raise ValueError(f"{name}: tensor on {t.device}, expected {_DEVICE_TYPE}:{device}")
+    return t.data_ptr()
+
+
+def _finalizing() -> bool:
+    import sys
+    return sys.is_finalizing()
+
+
 def mlg_plan_create(grid: mlg_grid, prec: int = MLG_FP64, device: int = 0) -> int:
     h = ctypes.c_void_p()
     _check(lib().mlg_plan_create(ctypes.byref(grid), prec, device, ctypes.byref(h)))
@@ -386,7 +413,24 @@ class Plan:
         self.handle = mlg_plan_create(self.grid, prec, device)
         self.layout = mlg_plan_query(self.handle)
         self.nr, self.nphi, self.nz = nr, nphi, nz
+        self.rdtype = torch.float32 if self.layout.real_bytes == 4 else torch.float64
+        self.cdtype = torch.complex64 if self.layout.real_bytes == 4 else torch.complex128
         self.ws = torch.empty(max(self.layout.workspace_bytes, 8), dtype=torch.uint8, device=f"cuda:{device}")
+
+    # checked device pointers (see _ptr)
+    def _phys(self, t, name="phys", count=1):
+        return _ptr(t, name, (self.rdtype,), count * self.layout.phys_elems, self.device)
+
+    def _spec(self, t, name="spec", count=1):
+        return _ptr(t, name, (self.cdtype,), count * self.layout.spec_elems, self.device)
+
+    def _f64(self, t, name, numel):
+        import torch
+        return _ptr(t, name, (torch.float64,), numel, self.device)
+
+    def _ws(self):
+        import torch
+        return _ptr(self.ws, "workspace", (torch.uint8,), self.layout.workspace_bytes, self.device)
 
     @property
     def tau(self) -> int:
@@ -397,11 +441,11 @@ class Plan:
 
     def empty_phys(self):
         import torch
-        return torch.empty((self.nz, self.nr, self.nphi), dtype=torch.float64, device=f"cuda:{self.device}")
+        return torch.empty((self.nz, self.nr, self.nphi), dtype=self.rdtype, device=f"cuda:{self.device}")
 
     def empty_spec(self):
         import torch
-        return torch.empty((self.tau, self.nz), dtype=torch.complex128, device=f"cuda:{self.device}")
+        return torch.empty((self.tau, self.nz), dtype=self.cdtype, device=f"cuda:{self.device}")
 
     @staticmethod
     def _stream():
@@ -409,29 +453,32 @@ class Plan:
         return torch.cuda.current_stream().cuda_stream
 
     def forward(self, phys, spec):
-        mlg_forward(self.handle, phys.data_ptr(), spec.data_ptr(), self.ws.data_ptr(), self._stream())
+        mlg_forward(self.handle, self._phys(phys), self._spec(spec), self._ws(), self._stream())
 
     def backward(self, spec, phys):
-        mlg_backward(self.handle, spec.data_ptr(), phys.data_ptr(), self.ws.data_ptr(), self._stream())
+        mlg_backward(self.handle, self._spec(spec), self._phys(phys), self._ws(), self._stream())
 
     def rhs_scalar(self, kind, gamma, spec_u, spec_out):
-        mlg_rhs_scalar(self.handle, kind, gamma, spec_u.data_ptr(), spec_out.data_ptr(), self.ws.data_ptr(),
-                       self._stream())
+        mlg_rhs_scalar(self.handle, kind, gamma, self._spec(spec_u, "spec_u"), self._spec(spec_out, "spec_out"),
+                       self._ws(), self._stream())
 
     def rhs_tp(self, psi, chi, psi_n, chi_n, U=None, taps=None):
-        mlg_rhs_tp(self.handle, U, psi.data_ptr(), chi.data_ptr(), psi_n.data_ptr(), chi_n.data_ptr(),
-                   0 if taps is None else taps.data_ptr(), self.ws.data_ptr(), self._stream())
+        tp = 0 if taps is None else self._f64(taps, "taps", 9 * self.layout.phys_elems + 6 * self.layout.spec_elems)
+        mlg_rhs_tp(self.handle, U, self._spec(psi, "psi"), self._spec(chi, "chi"), self._spec(psi_n, "psi_n"),
+                   self._spec(chi_n, "chi_n"), tp, self._ws(), self._stream())
 
     def synthesize(self, psi, chi, uw):
         """uw: float64 tensor of 6 * phys_elems (u_r, u_phi, u_z, w_r, w_phi, w_z)."""
-        mlg_synthesize(self.handle, psi.data_ptr(), chi.data_ptr(), uw.data_ptr(), self.ws.data_ptr(), self._stream())
+        mlg_synthesize(self.handle, self._spec(psi, "psi"), self._spec(chi, "chi"),
+                       self._f64(uw, "uw", 6 * self.layout.phys_elems), self._ws(), self._stream())
 
     def energy(self, psi, chi, out=None):
         """Axial modal kinetic energy per FFT slot (float64 device tensor of N_z entries)."""
         import torch
         if out is None:
             out = torch.empty(self.nz, dtype=torch.float64, device=f"cuda:{self.device}")
-        mlg_tp_energy(self.handle, psi.data_ptr(), chi.data_ptr(), out.data_ptr(), self.ws.data_ptr(), self._stream())
+        mlg_tp_energy(self.handle, self._spec(psi, "psi"), self._spec(chi, "chi"), self._f64(out, "out", self.nz),
+                      self._ws(), self._stream())
         return out
 
     def step_setup(self, nu, nu_h=0.0, p=8, dt=1e-2):
@@ -445,15 +492,15 @@ class Plan:
         mlg_filter_disable(self.handle)
 
     def filter_apply(self, slot, spec):
-        mlg_filter_apply(self.handle, slot, spec.data_ptr(), self._stream())
+        mlg_filter_apply(self.handle, slot, self._spec(spec), self._stream())
 
     def advance_scalar(self, kind, gamma, s, hist, nsteps, start=0, tmp=None):
         """nsteps AB-CN steps of one scalar in place (Richardson start when start = 1); returns tmp."""
         import torch
         if tmp is None:
             tmp = torch.empty(3 * self.layout.spec_elems, dtype=torch.complex128, device=f"cuda:{self.device}")
-        mlg_scalar_advance(self.handle, kind, gamma, s.data_ptr(), hist.data_ptr(), nsteps, start, tmp.data_ptr(),
-                           self.ws.data_ptr(), self._stream())
+        mlg_scalar_advance(self.handle, kind, gamma, self._spec(s, "state"), self._spec(hist, "hist"), nsteps, start,
+                           self._spec(tmp, "tmp", 3), self._ws(), self._stream())
         return tmp
 
     def set_log_proxy(self, c_psi=0.0, c_chi=0.0):
@@ -465,7 +512,8 @@ class Plan:
         import torch
         if out is None:
             out = torch.empty(self.nz, dtype=torch.float64, device=f"cuda:{self.device}")
-        mlg_tp_enstrophy(self.handle, psi.data_ptr(), chi.data_ptr(), out.data_ptr(), self.ws.data_ptr(), self._stream())
+        mlg_tp_enstrophy(self.handle, self._spec(psi, "psi"), self._spec(chi, "chi"), self._f64(out, "out", self.nz),
+                         self._ws(), self._stream())
         return out
 
     def eval_harmonic(self, spec, m, kk, r):
@@ -473,7 +521,8 @@ class Plan:
         import torch
         r = r.contiguous()
         out = torch.empty(r.numel(), dtype=torch.complex128, device=r.device)
-        mlg_eval_harmonic(self.handle, spec.data_ptr(), m, kk, r.data_ptr(), r.numel(), out.data_ptr(), self._stream())
+        mlg_eval_harmonic(self.handle, self._spec(spec), m, kk, self._f64(r, "r", r.numel()), r.numel(),
+                          _ptr(out, "out", (torch.complex128,), r.numel(), self.device), self._stream())
         return out
 
     def filter_state(self):
@@ -481,23 +530,26 @@ class Plan:
         return mlg_filter_state(self.handle)
 
     def step_febe(self, half, s, A, out):
-        mlg_step_febe(self.handle, half, s.data_ptr(), A.data_ptr(), out.data_ptr(), self._stream())
+        mlg_step_febe(self.handle, half, self._spec(s, "s"), self._spec(A, "A"), self._spec(out, "out"),
+                      self._stream())
 
     def step_abcn(self, s, A_now, A_prev, out):
-        mlg_step_abcn(self.handle, s.data_ptr(), A_now.data_ptr(), A_prev.data_ptr(), out.data_ptr(), self._stream())
+        mlg_step_abcn(self.handle, self._spec(s, "s"), self._spec(A_now, "A_now"), self._spec(A_prev, "A_prev"),
+                      self._spec(out, "out"), self._stream())
 
     def truncate_to(self, other: "Plan", src, dst):
         """dst (spectral of 'other') = src (spectral of this plan) moved to the other grid."""
-        mlg_truncate(self.handle, other.handle, src.data_ptr(), dst.data_ptr(), self._stream())
+        mlg_truncate(self.handle, other.handle, self._spec(src, "src"), other._spec(dst, "dst"), self._stream())
 
     def advance(self, psi, chi, hist_psi, hist_chi, nsteps, start, U=None, closure=None, tmp=None):
         """nsteps AB-CN steps of (psi, chi) in place; tmp: complex128 tensor of 6 * spec_elems."""
         import torch
         if tmp is None:
             tmp = torch.empty(6 * self.layout.spec_elems, dtype=torch.complex128, device=f"cuda:{self.device}")
-        mlg_tp_advance(self.handle, U, psi.data_ptr(), chi.data_ptr(), hist_psi.data_ptr(), hist_chi.data_ptr(),
-                       int(nsteps), int(start), closure.handle if closure is not None else 0, tmp.data_ptr(),
-                       self.ws.data_ptr(), self._stream())
+        mlg_tp_advance(self.handle, U, self._spec(psi, "psi"), self._spec(chi, "chi"),
+                       self._spec(hist_psi, "hist_psi"), self._spec(hist_chi, "hist_chi"),
+                       int(nsteps), int(start), closure.handle if closure is not None else 0,
+                       self._spec(tmp, "tmp", 6), self._ws(), self._stream())
         return tmp
 
     def taps_buffer(self):
@@ -510,7 +562,17 @@ class Plan:
             mlg_plan_destroy(self.handle)
             self.handle = 0
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
     def __del__(self):
+        # at interpreter shutdown the HIP runtime may already be torn down: leave the handle to
+        # the process exit rather than call into the library
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -574,15 +636,22 @@ class Batch:
         import torch
         return torch.zeros(int(self.offsets[-1]), dtype=self.cdtype, device=f"cuda:{self.device}")
 
+    def _spec(self, t, name):
+        return _ptr(t, name, (self.cdtype,), int(self.offsets[-1]), self.device)
+
+    def _ws(self):
+        import torch
+        return _ptr(self.ws, "workspace", (torch.uint8,), 1, self.device)
+
     def rhs_kpp(self, gamma, spec_in, spec_out):
         import torch
-        mlg_batch_rhs_scalar(self.handle, gamma, spec_in.data_ptr(), spec_out.data_ptr(), self.ws.data_ptr(),
-                             torch.cuda.current_stream().cuda_stream)
+        mlg_batch_rhs_scalar(self.handle, gamma, self._spec(spec_in, "spec_in"), self._spec(spec_out, "spec_out"),
+                             self._ws(), torch.cuda.current_stream().cuda_stream)
 
     def autotune(self, gamma, spec_in, spec_out):
         import torch
-        return mlg_batch_autotune(self.handle, gamma, spec_in.data_ptr(), spec_out.data_ptr(), self.ws.data_ptr(),
-                                  torch.cuda.current_stream().cuda_stream)
+        return mlg_batch_autotune(self.handle, gamma, self._spec(spec_in, "spec_in"), self._spec(spec_out, "spec_out"),
+                                  self._ws(), torch.cuda.current_stream().cuda_stream)
 
     def set_config(self, recurrence, threads, blocks_per_cu, lines):
         mlg_batch_set_config(self.handle, mlg_batch_config(recurrence, threads, blocks_per_cu, lines))
@@ -596,7 +665,15 @@ class Batch:
             mlg_batch_destroy(self.handle)
             self.handle = 0
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
     def __del__(self):
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -632,24 +709,38 @@ class Closure:
     def get_scales(self):
         return mlg_closure_get_scales(self.handle)
 
+    def _f32(self, t, name, numel):
+        import torch
+        return _ptr(t, name, (torch.float32,), numel, self.plan.device)
+
     def features(self, psi, chi, x_out):
-        mlg_closure_features(self.handle, psi.data_ptr(), chi.data_ptr(), x_out.data_ptr(), self._stream())
+        p = self.plan
+        mlg_closure_features(self.handle, p._spec(psi, "psi"), p._spec(chi, "chi"),
+                             self._f32(x_out, "x_out", self.ncols * MLG_CLOSURE_NIN), self._stream())
 
     def targets(self, ref_psi, ref_chi, psi_n, chi_n, y_out):
-        mlg_closure_targets(self.handle, ref_psi.data_ptr(), ref_chi.data_ptr(), psi_n.data_ptr(), chi_n.data_ptr(),
-                            y_out.data_ptr(), self._stream())
+        p = self.plan
+        mlg_closure_targets(self.handle, p._spec(ref_psi, "ref_psi"), p._spec(ref_chi, "ref_chi"),
+                            p._spec(psi_n, "psi_n"), p._spec(chi_n, "chi_n"),
+                            self._f32(y_out, "y_out", self.ncols * MLG_CLOSURE_NOUT), self._stream())
 
     def forward(self, x, y):
-        mlg_closure_forward(self.handle, x.data_ptr(), int(x.shape[0]), y.data_ptr(), self._stream())
+        nb = int(x.shape[0])
+        mlg_closure_forward(self.handle, self._f32(x, "x", nb * MLG_CLOSURE_NIN), nb,
+                            self._f32(y, "y", nb * MLG_CLOSURE_NOUT), self._stream())
 
     def train_step(self, data_x, data_y, idx, nb, lr, want_loss=False):
-        return mlg_closure_train_step(self.handle, data_x.data_ptr(), data_y.data_ptr(),
-                                      0 if idx is None else idx.data_ptr(), int(data_x.shape[0]), int(nb), float(lr),
-                                      want_loss, self._stream())
+        import torch
+        count = int(data_x.shape[0])
+        ip = 0 if idx is None else _ptr(idx, "idx", (torch.int32,), int(nb), self.plan.device)
+        return mlg_closure_train_step(self.handle, self._f32(data_x, "data_x", count * MLG_CLOSURE_NIN),
+                                      self._f32(data_y, "data_y", count * MLG_CLOSURE_NOUT),
+                                      ip, count, int(nb), float(lr), want_loss, self._stream())
 
     def infer(self, psi, chi, rhs_psi, rhs_chi, want_flag=False):
-        return mlg_closure_infer(self.handle, psi.data_ptr(), chi.data_ptr(), rhs_psi.data_ptr(), rhs_chi.data_ptr(),
-                                 want_flag, self._stream())
+        p = self.plan
+        return mlg_closure_infer(self.handle, p._spec(psi, "psi"), p._spec(chi, "chi"), p._spec(rhs_psi, "rhs_psi"),
+                                 p._spec(rhs_chi, "rhs_chi"), want_flag, self._stream())
 
     def stats(self):
         return mlg_closure_stats(self.handle)
@@ -659,7 +750,15 @@ class Closure:
             mlg_closure_destroy(self.handle)
             self.handle = 0
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
     def __del__(self):
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:
