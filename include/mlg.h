@@ -144,6 +144,19 @@ mlg_status mlg_rhs_scalar(mlg_plan plan, int kind, double gamma, const void* spe
 mlg_status mlg_rhs_tp(mlg_plan plan, const double* U, const void* psi, const void* chi,
                       void* psi_n, void* chi_n, void* taps, void* ws, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): mlg_rhs_tp without the 'ws' argument.  The workspace is a
+ * fixed array of 192 MiB (201326592 bytes) in the library's device memory, one copy per GPU, which
+ * each GPU holds from the library's first use there until the process ends; the call allocates
+ * nothing and launches the same kernels as mlg_rhs_tp, so the outputs are identical.  Plans whose
+ * mlg_layout.workspace_bytes exceed the array get MLG_E_UNSUPPORTED (128^3 at the default chops fits);
+ * a plan with timing hooks enabled gets MLG_E_ARG (they create events).  The array keeps the last
+ * call's contents; no kernel relies on it starting at zero.  All calls on one GPU share the array:
+ * calls that overlap in time on the same GPU (other streams, other threads) race and must be
+ * serialised by the caller. */
+mlg_status mlg_rhs_tp_noalloc(mlg_plan plan, const double* U, const void* psi, const void* chi,
+                              void* psi_n, void* chi_n, void* taps, void* stream);
+
 /* ---------------------------------------------------------------- semi-implicit time stepping
  * ds/dt = A(s) + L s (Sec. 3.3, Eq. split) with L = nu grad^2 - nu_h (-grad^2)^{p/2}
  * (Eq. dissipation), composed per (m, k) from the truncated horizontal Laplacian of

@@ -42,7 +42,7 @@ class mlg_layout(ctypes.Structure):
 _lib = None
 
 EXPORTS = ["mlg_plan_create", "mlg_plan_destroy", "mlg_plan_query", "mlg_plan_nodes", "mlg_forward",
-           "mlg_backward", "mlg_rhs_scalar", "mlg_rhs_tp", "mlg_synthesize", "mlg_tp_energy", "mlg_timing_enable",
+           "mlg_backward", "mlg_rhs_scalar", "mlg_rhs_tp", "mlg_rhs_tp_noalloc", "mlg_synthesize", "mlg_tp_energy", "mlg_timing_enable",
            "mlg_timing_read",
            "mlg_batch_create", "mlg_batch_destroy", "mlg_batch_query", "mlg_batch_rhs_scalar", "mlg_batch_set_config",
            "mlg_batch_get_config", "mlg_batch_autotune", "mlg_step_setup", "mlg_step_febe", "mlg_step_abcn",
@@ -92,6 +92,7 @@ def lib() -> ctypes.CDLL:
     L.mlg_backward.argtypes = [vp, vp, vp, vp, vp]
     L.mlg_rhs_scalar.argtypes = [vp, i32, f64, vp, vp, vp, vp]
     L.mlg_rhs_tp.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.mlg_rhs_tp_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.mlg_synthesize.argtypes = [vp, vp, vp, vp, vp, vp]
     L.mlg_tp_energy.argtypes = [vp, vp, vp, vp, vp, vp]
     L.mlg_timing_enable.argtypes = [vp, i32]
@@ -219,6 +220,13 @@ def mlg_rhs_tp(plan: int, U, psi: int, chi: int, psi_n: int, chi_n: int, taps: i
     if U is not None:
         Uarr = (ctypes.c_double * 3)(*[float(u) for u in U])
     _check(lib().mlg_rhs_tp(plan, Uarr, psi, chi, psi_n, chi_n, taps, ws, stream))
+
+
+def mlg_rhs_tp_noalloc(plan: int, U, psi: int, chi: int, psi_n: int, chi_n: int, taps: int, stream: int = 0) -> None:
+    Uarr = None
+    if U is not None:
+        Uarr = (ctypes.c_double * 3)(*[float(u) for u in U])
+    _check(lib().mlg_rhs_tp_noalloc(plan, Uarr, psi, chi, psi_n, chi_n, taps, stream))
 
 
 def mlg_step_setup(plan: int, nu: float, nu_h: float, p: int, dt: float) -> None:

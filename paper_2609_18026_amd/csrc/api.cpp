@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -58,6 +59,33 @@ mlg_status check_plan(mlg_plan p) {
   return MLG_OK;
 }
 
+// Device-resident workspace of mlg_rhs_tp_noalloc: one copy per GPU, held from the first use of the
+// library on that GPU until the process ends.  Host code never uses the array's name as an
+// address: the device address of each GPU's copy comes from hipGetSymbolAddress.
+constexpr size_t kScratchBytes = size_t(192) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// With 'device' current: look up (once) the address of that GPU's copy of the array.
+mlg_status scratch_setup(int device) {
+  if (device < 0 || device >= kScratchDevices) return fail(MLG_E_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return MLG_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(MLG_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[device] = ptr;
+  return MLG_OK;
+}
+
+void* scratch_address(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (device >= 0 && device < kScratchDevices) ? g_scratch_ptr[device] : nullptr;
+}
+
 }  // namespace
 }  // namespace mlg
 
@@ -95,6 +123,9 @@ mlg_status mlg_plan_create(const mlg_grid* grid, mlg_precision prec, int device,
     return fail(MLG_E_ARG, "device index out of range or no HIP device");
   DeviceGuard guard(device);
   if (!guard.ok) return fail(MLG_E_DEVICE, "hipSetDevice failed");
+  // the no-allocation entry point's workspace on this GPU (a failure here is reported by that
+  // entry point, which retries the lookup; plans themselves do not need it)
+  if (scratch_setup(device) != MLG_OK) set_error("");
   mlg_plan_s* p = new (std::nothrow) mlg_plan_s();
   if (!p) return fail(MLG_E_ALLOC, "host allocation failed");
   p->g = g;
@@ -213,8 +244,12 @@ mlg_status mlg_rhs_scalar(mlg_plan p, int kind, double gamma, const void* spec_u
                      mask ? p->d_row_m : nullptr, p->dealias_m, p->dealias_k, s);
 }
 
-mlg_status mlg_rhs_tp(mlg_plan p, const double* U, const void* psi, const void* chi, void* psi_n, void* chi_n,
-                      void* taps, void* ws, void* stream) {
+}  // extern "C"
+
+// The kernel sequence of mlg_rhs_tp on the workspace 'ws' (caller-provided, or the per-GPU array of
+// mlg_rhs_tp_noalloc).
+static mlg_status rhs_tp_run(mlg_plan p, const double* U, const void* psi, const void* chi, void* psi_n, void* chi_n,
+                             void* taps, void* ws, void* stream) {
   if (mlg_status st = check_plan(p)) return st;
   if (!psi || !chi || !psi_n || !chi_n || !ws) return fail(MLG_E_ARG, "null buffer");
   if (psi_n == chi_n || psi_n == psi || psi_n == chi || chi_n == psi || chi_n == chi)
@@ -259,6 +294,30 @@ mlg_status mlg_rhs_tp(mlg_plan p, const double* U, const void* psi, const void* 
   const double* csrc[3] = {w.T[0], w.T[1], w.T[2]};
   double* tsrc = tp ? tp + (size_t)9 * p->nz * p->nr * p->nphi : nullptr;
   return launch_projection(p, csrc, static_cast<double*>(psi_n), static_cast<double*>(chi_n), tsrc, s);
+}
+
+extern "C" {
+
+mlg_status mlg_rhs_tp(mlg_plan p, const double* U, const void* psi, const void* chi, void* psi_n, void* chi_n,
+                      void* taps, void* ws, void* stream) {
+  return rhs_tp_run(p, U, psi, chi, psi_n, chi_n, taps, ws, stream);
+}
+
+mlg_status mlg_rhs_tp_noalloc(mlg_plan p, const double* U, const void* psi, const void* chi, void* psi_n,
+                              void* chi_n, void* taps, void* stream) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (p->ws_bytes > kScratchBytes)
+    return fail(MLG_E_UNSUPPORTED, "mlg_rhs_tp_noalloc: the plan needs " + std::to_string(p->ws_bytes) +
+                                       " workspace bytes, above the fixed " + std::to_string(kScratchBytes));
+  if (p->timing.enabled) return fail(MLG_E_ARG, "mlg_rhs_tp_noalloc: timing hooks are enabled (they create events)");
+  DeviceGuard guard(p->device);
+  if (!guard.ok) return fail(MLG_E_DEVICE, "hipSetDevice failed");
+  void* ws = scratch_address(p->device);
+  if (!ws) {
+    if (mlg_status st = scratch_setup(p->device)) return st;
+    ws = scratch_address(p->device);
+  }
+  return rhs_tp_run(p, U, psi, chi, psi_n, chi_n, taps, ws, stream);
 }
 
 mlg_status mlg_step_setup(mlg_plan p, const mlg_dissip* d) {
