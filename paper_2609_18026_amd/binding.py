@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmlg.so")
@@ -173,7 +174,6 @@ def _ptr(t, name: str, dtypes, numel: int, device: int) -> int:
 
 
 def _finalizing() -> bool:
-    import sys
     return sys.is_finalizing()
 
 
@@ -579,7 +579,7 @@ class Plan:
     def __del__(self):
         # at interpreter shutdown the HIP runtime may already be torn down: leave the handle to
         # the process exit rather than call into the library
-        if _finalizing():
+        if not getattr(self, "handle", 0) or _finalizing():
             return
         try:
             self.close()
@@ -680,7 +680,7 @@ class Batch:
         self.close()
 
     def __del__(self):
-        if _finalizing():
+        if not getattr(self, "handle", 0) or _finalizing():
             return
         try:
             self.close()
@@ -765,7 +765,7 @@ class Closure:
         self.close()
 
     def __del__(self):
-        if _finalizing():
+        if not getattr(self, "handle", 0) or _finalizing():
             return
         try:
             self.close()
