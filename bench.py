@@ -189,6 +189,81 @@ def bench_batched(torch, args, stream, e0, e1, count=64, seed=3):
     return res
 
 
+def bench_split(torch, plan, psi, chi, po, co, phys, spec, args, stream, e0, e1):
+    """MLG_SPLIT_BF16 plan on the same state: RHS and transform-pair times beside FP64, and the errors
+    against the FP64 library result (itself within 1e-12 of the oracle): the nodal taps u, omega, N
+    and the sources C, K, Zhat, the output coefficients, and the velocity V(psi_N, chi_N) they
+    represent (plain and area-weighted node norms, and relative to the nodal N)."""
+    from paper_2609_18026_amd import MLG_SPLIT_BF16, Plan
+    n = plan.nr
+    pe = plan.layout.phys_elems
+    se = plan.layout.spec_elems
+    splan = Plan(n, n, n, 1.0, PAIR["lz"], dealias=1, prec=MLG_SPLIT_BF16)
+    sp, sc = splan.empty_spec(), splan.empty_spec()
+    for _ in range(args.warmup):
+        splan.rhs_tp(psi, chi, sp, sc, U=U_FRAME)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        splan.rhs_tp(psi, chi, sp, sc, U=U_FRAME)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sms = e0.elapsed_time(e1) / args.steps
+    sphys, sspec = splan.empty_phys(), splan.empty_spec()
+    splan.backward(psi, sphys)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        splan.backward(psi, sphys)
+        splan.forward(sphys, sspec)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    spair_ms = e0.elapsed_time(e1) / args.steps
+    perr = float(torch.linalg.vector_norm(sphys - phys) / torch.linalg.vector_norm(phys))
+    serr = float(torch.linalg.vector_norm(sspec - spec) / torch.linalg.vector_norm(spec))
+    del sphys, sspec
+    # taps of both plans
+    t64, tsp = plan.taps_buffer(), splan.taps_buffer()
+    a, b = plan.empty_spec(), plan.empty_spec()
+    plan.rhs_tp(psi, chi, a, b, U=U_FRAME, taps=t64)
+    splan.rhs_tp(psi, chi, sp, sc, U=U_FRAME, taps=tsp)
+    torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    splan.close()
+    rel = lambda x, y: float(torch.linalg.vector_norm(x - y) / torch.linalg.vector_norm(y))
+    taps = {"u": rel(tsp[:3 * pe], t64[:3 * pe]), "omega": rel(tsp[3 * pe:6 * pe], t64[3 * pe:6 * pe]),
+            "N": rel(tsp[6 * pe:9 * pe], t64[6 * pe:9 * pe])}
+    for j, nm in enumerate(("C", "K", "Zhat")):
+        o = 9 * pe + 2 * j * se
+        taps[nm] = rel(tsp[o:o + 2 * se], t64[o:o + 2 * se])
+    uw_ref = torch.empty(6 * pe, dtype=torch.float64, device="cuda")
+    uw_spl = torch.empty_like(uw_ref)
+    plan.synthesize(po, co, uw_ref)
+    plan.synthesize(sp, sc, uw_spl)
+    torch.cuda.synchronize()
+    x, w, r = plan.nodes()
+    area = torch.from_numpy(w / (1 - x) ** 2).cuda()
+    vr = uw_ref[:3 * pe].view(3, n, n, n)
+    vs = uw_spl[:3 * pe].view(3, n, n, n)
+    d2 = ((vs - vr) ** 2).sum(dim=(0, 1, 3))
+    r2 = (vr ** 2).sum(dim=(0, 1, 3))
+    Nn = t64[6 * pe:9 * pe].view(3, n, n, n)
+    n2 = (Nn ** 2).sum(dim=(0, 1, 3))
+    vel = {"plain": rel(vs, vr), "area_weighted": float(torch.sqrt((d2 * area).sum() / (r2 * area).sum())),
+           "plain_rel_to_N": float(torch.sqrt(d2.sum() / n2.sum())),
+           "area_weighted_rel_to_N": float(torch.sqrt((d2 * area).sum() / (n2 * area).sum()))}
+    res = {"ms_per_step": round(sms, 4), "fp64_ms_per_step": None, "gdofs": round(n ** 3 / (sms / 1e3) / 1e9, 4),
+           "stages": "split: synthesis products, inverse z DFT products, transform-pair products; FP64: phi FFTs, "
+                     "cross product, forward z, projection sources, solves",
+           "rel_err_vs_fp64": {"velocity_of_output": vel, "psi_coefficients": rel(sp, po), "chi_coefficients": rel(sc, co),
+                               "taps": taps},
+           "transform_pair_ms": round(spair_ms, 4), "transform_pair_gdofs": round(n ** 3 / (spair_ms / 1e3) / 1e9, 4),
+           "rel_err_pair_backward_vs_fp64": perr, "rel_err_pair_forward_vs_fp64": serr}
+    log(f"bench: split-bf16 {sms:.3f} ms/step, velocity rel err {vel['plain']:.2e} (area {vel['area_weighted']:.2e}, "
+        f"vs |N| {vel['plain_rel_to_N']:.2e}); taps {taps}; pair {spair_ms:.3f} ms, rel err {perr:.2e} / {serr:.2e}")
+    return res
+
+
 def bench_time_step(torch, plan, psi, chi, args, stream, e0, e1):
     """Whole AB-CN steps of (psi, chi) at the bench size: one RHS plus the implicit update of both
     potentials per step (Eq. abcn), through mlg_tp_advance on resident state."""
@@ -463,53 +538,9 @@ def main():
         "transform_pair": {"ms": round(pair_ms, 4), "gdofs": round(n ** 3 / (pair_ms / 1e3) / 1e9, 4)},
         "hbm_copy_reference": copy_ref,
     }
-    # split-bfloat16 radial products on the same state: time, and the error against the FP64 result
-    # at the tap that is well conditioned: the velocity V(psi_N, chi_N) the potentials represent
-    from paper_2609_18026_amd import MLG_SPLIT_BF16
-    ref_p, ref_c = po.clone(), co.clone()
-    splan = Plan(n, n, n, 1.0, PAIR["lz"], dealias=1, prec=MLG_SPLIT_BF16)
-    sp, sc = splan.empty_spec(), splan.empty_spec()
-    for _ in range(args.warmup):
-        splan.rhs_tp(psi, chi, sp, sc, U=U_FRAME)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        splan.rhs_tp(psi, chi, sp, sc, U=U_FRAME)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    sms = e0.elapsed_time(e1) / args.steps
-    # the split transform pair (radial products and z transforms as split-bf16 DFT products) against
-    # the FP64 pair on the same field
-    sphys, sspec = splan.empty_phys(), splan.empty_spec()
-    splan.backward(psi, sphys)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        splan.backward(psi, sphys)
-        splan.forward(sphys, sspec)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    spair_ms = e0.elapsed_time(e1) / args.steps
-    perr = float(torch.linalg.vector_norm(sphys - phys) / torch.linalg.vector_norm(phys))
-    serr = float(torch.linalg.vector_norm(sspec - spec) / torch.linalg.vector_norm(spec))
-    torch.cuda.synchronize()
-    splan.close()
-    del sphys, sspec
-    uw_ref = torch.empty(6 * plan.layout.phys_elems, dtype=torch.float64, device="cuda")
-    uw_spl = torch.empty_like(uw_ref)
-    plan.synthesize(ref_p, ref_c, uw_ref)
-    plan.synthesize(sp, sc, uw_spl)
-    torch.cuda.synchronize()
-    pe = plan.layout.phys_elems
-    verr = float(torch.linalg.vector_norm(uw_spl[:3 * pe] - uw_ref[:3 * pe]) / torch.linalg.vector_norm(uw_ref[:3 * pe]))
-    cerr = float(torch.linalg.vector_norm(sp - ref_p) / torch.linalg.vector_norm(ref_p))
-    out["split_bf16"] = {"ms_per_step": round(sms, 4), "gdofs": round(n ** 3 / (sms / 1e3) / 1e9, 4),
-                         "rel_err_velocity_of_output_vs_fp64": verr, "rel_err_psi_coefficients_vs_fp64": cerr,
-                         "transform_pair_ms": round(spair_ms, 4),
-                         "transform_pair_gdofs": round(n ** 3 / (spair_ms / 1e3) / 1e9, 4),
-                         "rel_err_pair_backward_vs_fp64": perr, "rel_err_pair_forward_vs_fp64": serr}
-    log(f"bench: split-bf16 {sms:.3f} ms/step, velocity rel err {verr:.2e} (coefficients {cerr:.2e}); "
-        f"pair {spair_ms:.3f} ms, rel err {perr:.2e} / {serr:.2e}")
+    # split-bfloat16 products on the same state: time, and the errors against the FP64 result
+    out["split_bf16"] = bench_split(torch, plan, psi, chi, po, co, phys, spec, args, stream, e0, e1)
+    out["split_bf16"]["fp64_ms_per_step"] = round(ms, 4)
     out["batched_2d"] = bench_batched(torch, args, stream, e0, e1)
     out["time_step"] = bench_time_step(torch, plan, psi, chi, args, stream, e0, e1)
     if not args.no_closure:

@@ -20,8 +20,8 @@
  *  - One plan may be used from one stream at a time; concurrent streams need their
  *    own workspace buffers.
  *
- * Data layouts (FP64 plans: real = double, complex = interleaved double pair;
- * FP32 and split-BF16 plans: float / interleaved float pair)
+ * Data layouts (plans: real = double, complex = interleaved double pair; FP32 batches:
+ * float / interleaved float pair)
  *  - physical field: real [N_z][N_r][N_phi], element (l, i, j) = s(r_i, phi_j, z_l),
  *    r_i ascending (x_i the Gauss-Legendre nodes, r = ell sqrt((1+x)/(1-x)), Eq. map),
  *    phi_j = 2 pi j / N_phi, z_l = L_z l / N_z.
@@ -59,11 +59,14 @@ typedef enum {
   MLG_FP64 = 0,        /* double data, FP64 arithmetic (MFMA f64 for the radial products)    */
   MLG_FP32 = 1,        /* batches only: float data and streamed tables (built in FP64),       */
                        /* FP32 arithmetic                                                    */
-  MLG_SPLIT_BF16 = 2   /* plans only: double data; every radial product (transform pair,      */
-                       /* scalar and vector RHS) and, for N_z = 256, the z transforms as two  */
-                       /* radix-16 DFT products, on MFMA with hi/lo bfloat16 operands and FP32 */
-                       /* accumulation (a_hi b_hi + a_hi b_lo + a_lo b_hi); the phi FFTs,     */
-                       /* pointwise products and solves stay FP64                             */
+  MLG_SPLIT_BF16 = 2   /* plans only: double data; the radial products of the transform pair, */
+                       /* the scalar RHS and the vector synthesis, and for N_z = 256 their    */
+                       /* z transforms as two radix-16 DFT products, on MFMA with hi/lo       */
+                       /* bfloat16 operands and FP32 accumulation (a_hi b_hi + a_hi b_lo +    */
+                       /* a_lo b_hi); the phi FFTs, pointwise products, the projection's      */
+                       /* forward z transforms, source products and solves stay FP64 (the   */
+                       /* solves are ill-conditioned along far-field directions and would     */
+                       /* amplify reduced-precision source errors)                            */
 } mlg_precision;
 
 enum { MLG_RHS_U2 = 0, MLG_RHS_KPP = 1 };
@@ -88,7 +91,7 @@ typedef struct {
   int64_t workspace_bytes;  /* bytes of device workspace every call of this plan needs  */
   int32_t M;                /* stored azimuthal orders                                   */
   int32_t nrc, nzc;         /* resolved radial and axial chops                           */
-  int32_t real_bytes;       /* 8 (FP64) or 4 (FP32, split-BF16)                          */
+  int32_t real_bytes;       /* bytes of one real of the data arrays (8 for plans)        */
   int32_t dealias_m, dealias_k;  /* largest kept m and |k| under the two-thirds mask     */
 } mlg_layout;
 

@@ -280,16 +280,18 @@ static mlg_status rhs_tp_run(mlg_plan p, const double* U, const void* psi, const
   // 3. phi stage: nodal u, w -> N = (U + u) x w -> harmonics of N_r/r, N_phi/r, N_z
   double* tp = static_cast<double*>(taps);
   if ((st = launch_phi_vec_rhs(p, Uh, w.X, tp, s))) return st;
-  // 4. forward z transforms of the orders the projection uses
+  // 4. forward z transforms of the orders the projection uses.  From here on every plan computes in
+  // FP64: the solves of step 6 are ill-conditioned along the far-field directions of the Gram
+  // matrices (cond(Dbar_1) ~ 1e9 at N_r = 256), and the curl-type sources are a small residual of
+  // N for flows near a steady state, so reduced-precision source products would be amplified there
+  const int fp64_only = 1;
   int mmax, kmax;
   active_columns(p, &mmax, &kmax);
   const int64_t frows = (int64_t)mmax * p->nr;
-  if ((st = launch_zfft_fields(p, w.X, w.X, 3, frows, -1, nullptr, 0, 0, s))) return st;
+  if ((st = launch_zfft_fields(p, w.X, w.X, 3, frows, -1, nullptr, 0, 0, s, fp64_only))) return st;
   // 5. Galerkin projections onto Pbar and Q = T - 2(1+x) Pbar with the C, K', Zhat epilogue
   double* src3[3] = {w.T[0], w.T[1], w.T[2]};
-  st = (p->prec == MLG_SPLIT_BF16) ? launch_split_proj(p, w.X, src3, mmax, kmax, s)
-                                   : launch_proj_gemm(p, w.X, src3, mmax, kmax, s);
-  if (st) return st;
+  if ((st = launch_proj_gemm(p, w.X, src3, mmax, kmax, s))) return st;
   // 6. elliptic solves per (m, k)
   const double* csrc[3] = {w.T[0], w.T[1], w.T[2]};
   double* tsrc = tp ? tp + (size_t)9 * p->nz * p->nr * p->nphi : nullptr;

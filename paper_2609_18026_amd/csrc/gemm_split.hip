@@ -210,143 +210,6 @@ __global__ __launch_bounds__(256, 3) void split_synth_kernel(SplitSynthArgs a) {
   }
 }
 
-struct SplitProjArgs {
-  const unsigned short* tab[4];  // W Pbar hi, lo, W Q hi, lo: per m [n-m][ipad], k = i
-  const int64_t* toff;
-  int ipad;
-  const double2* in[3];
-  double2* out[3];
-  const int64_t* off;
-  int nr, nrc, nz, kmax, nkact;
-  int gx, gy, gz;                // tiles: column blocks, row blocks, orders
-  double kap0;
-};
-
-__device__ __forceinline__ int active_kk(int a, int kmax, int nz) {
-  return (a <= kmax) ? a : nz - (2 * kmax + 1 - a);
-}
-
-// Staging as in split_synth_kernel: raw loads of the next two node stages and the next table
-// fragments in registers, split into bf16 at the LDS store.
-__global__ __launch_bounds__(256) void split_proj_kernel(SplitProjArgs a) {
-  Tile3 tl;
-  if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
-  const int m = tl.z;
-  const int row0 = tl.y * TM;
-  const int c0 = tl.x * TC;
-  const int rows = a.nrc > m ? a.nrc - m : 0;
-  if (row0 >= rows || c0 >= a.nkact) return;
-  const int nr = a.nr, nz = a.nz;
-  const double2* __restrict__ X0 = a.in[0] + (int64_t)m * nr * nz;
-  const double2* __restrict__ X1 = a.in[1] + (int64_t)m * nr * nz;
-  const double2* __restrict__ X2 = a.in[2] + (int64_t)m * nr * nz;
-  __shared__ __attribute__((aligned(16))) unsigned short Bs[2][12][TC][TK];  // 24 KB
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int rowl = row0 + wave * 16 + (lane & 15);
-  const int kg = 8 * (lane >> 4);
-  const bool rowok = rowl < rows;
-  const unsigned short* tp[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) tp[t] = a.tab[t] + a.toff[m] + (int64_t)(rowok ? rowl : 0) * a.ipad + kg;
-  floatx4 acc[5][2];
-#pragma unroll
-  for (int p = 0; p < 5; ++p) acc[p][0] = acc[p][1] = floatx4{0.f, 0.f, 0.f, 0.f};
-  // the (node, column) entries of a thread do not change their column between stages
-  int skk[2];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int ca = c0 + ((tid + 256 * h) & 15);
-    skk[h] = ca < a.nkact ? active_kk(ca, a.kmax, nz) : -1;
-  }
-  struct Stage {
-    double2 v[2][3];
-  };
-  auto load = [&](int k0, Stage& d) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k = k0 + ((tid + 256 * h) >> 4);
-      const bool ok = k < nr && skk[h] >= 0;
-      const int64_t idx = (int64_t)k * nz + skk[h];
-      d.v[h][0] = ok ? X0[idx] : make_double2(0.0, 0.0);
-      d.v[h][1] = ok ? X1[idx] : make_double2(0.0, 0.0);
-      d.v[h][2] = ok ? X2[idx] : make_double2(0.0, 0.0);
-    }
-  };
-  auto store = [&](int buf, const Stage& d) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int e = tid + 256 * h;
-      const int kr = e >> 4, c = e & 15;
-      const double vals[6] = {d.v[h][0].x, d.v[h][0].y, d.v[h][1].x, d.v[h][1].y, d.v[h][2].x, d.v[h][2].y};
-#pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        unsigned short hi, lo;
-        split2(vals[q], hi, lo);
-        Bs[buf][2 * q][c][kr] = hi;
-        Bs[buf][2 * q + 1][c][kr] = lo;
-      }
-    }
-  };
-  auto frags = [&](int kt, bf16x8 (&f)[4]) {
-    const int64_t ko = (int64_t)kt * TK;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) f[t] = ldfrag(tp[t] + ko);
-  };
-  const int nk = (nr + TK - 1) / TK;
-  Stage ra, rn;
-  bf16x8 fa[4], fn[4];
-  frags(0, fa);  // issued first, so that the wait for the staged operands covers it
-  load(0, ra);
-  store(0, ra);
-  if (nk > 1) load(TK, ra);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 2 < nk) load((kt + 2) * TK, rn);
-    if (kt + 1 < nk) frags(kt + 1, fn);
-    const int c = lane & 15;
-    bf16x8 bh[6], bl[6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      bh[q] = ldfrag(&Bs[buf][2 * q][c][kg]);
-      bl[q] = ldfrag(&Bs[buf][2 * q + 1][c][kg]);
-    }
-#pragma unroll
-    for (int ri = 0; ri < 2; ++ri) {
-      acc[0][ri] = mfma3(fa[0], fa[1], bh[0 + ri], bl[0 + ri], acc[0][ri]);  // Pa
-      acc[1][ri] = mfma3(fa[2], fa[3], bh[0 + ri], bl[0 + ri], acc[1][ri]);  // Qa
-      acc[2][ri] = mfma3(fa[0], fa[1], bh[2 + ri], bl[2 + ri], acc[2][ri]);  // Pb
-      acc[3][ri] = mfma3(fa[2], fa[3], bh[2 + ri], bl[2 + ri], acc[3][ri]);  // Qb
-      acc[4][ri] = mfma3(fa[0], fa[1], bh[4 + ri], bl[4 + ri], acc[4][ri]);  // Pc
-    }
-    if (kt + 1 < nk) store(buf ^ 1, ra);
-    ra = rn;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) fa[t] = fn[t];
-    __syncthreads();
-  }
-  const int cidx = c0 + (lane & 15);
-  if (cidx >= a.nkact) return;
-  const int kk = active_kk(cidx, a.kmax, nz);
-  const double kap = a.kap0 * kval(kk, nz);
-  const double fm = (double)m;
-  const int64_t tb = a.off[m];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int r = row0 + wave * 16 + 4 * (lane >> 4) + v;
-    if (r >= rows) continue;
-    const double2 Pa = make_double2(acc[0][0][v], acc[0][1][v]);
-    const double2 Qa = make_double2(acc[1][0][v], acc[1][1][v]);
-    const double2 Pb = make_double2(acc[2][0][v], acc[2][1][v]);
-    const double2 Qb = make_double2(acc[3][0][v], acc[3][1][v]);
-    const double2 Pc = make_double2(acc[4][0][v], acc[4][1][v]);
-    const int64_t o = (tb + r) * nz + kk;
-    a.out[0][o] = make_double2(-Qb.x + fm * Pa.y, -Qb.y - fm * Pa.x);
-    a.out[1][o] = make_double2(kap * Qa.y - fm * kap * Pb.x, -kap * Qa.x - fm * kap * Pb.y);
-    a.out[2][o] = Pc;
-  }
-}
-
 struct SplitScalarArgs {
   const unsigned short* tab[2];  // hi, lo: backward Pbar [i][kpad] (split synthesis tables),
                                  // forward W Pbar [n-m][ipad] (split projection tables)
@@ -363,7 +226,8 @@ struct SplitScalarArgs {
 // Radial products of the scalar transform pair (Sec. 4.1) with split-bfloat16 operands:
 // backward f_m[i][kk] = sum_n Pbar_n^m(x_i) s[n][kk], forward s[n][kk] = sum_i w_i Pbar_n^m(x_i)
 // f_m[i][kk].  The real table is the MFMA A operand; the re and im parts of the complex data are
-// two B operands.  Staging and pipelining as in split_proj_kernel.
+// two B operands.  The FP64 operands of the next two K stages and the table fragments of the next one
+// are held in registers as raw loads and split into bf16 at the LDS store (as in split_synth_kernel).
 template <bool FWD>
 __global__ __launch_bounds__(256) void split_scalar_kernel(SplitScalarArgs a) {
   Tile3 tl;
@@ -591,33 +455,6 @@ mlg_status launch_split_synth(const mlg_plan_s* p, const double* psi, const doub
   split_synth_kernel<<<xcd_blocks(a.gx, a.gy, a.gz), 256, 0, s>>>(a);
   p->timing.end(s);
   return check("split_synth_kernel");
-}
-
-mlg_status launch_split_proj(const mlg_plan_s* p, double* const* in3, double* const* out3, int mmax, int kmax,
-                             hipStream_t s) {
-  SplitProjArgs a{};
-  for (int t = 0; t < 4; ++t) a.tab[t] = p->d_split_prj[t];
-  a.toff = p->d_split_prj_off;
-  a.ipad = p->split_ipad;
-  for (int i = 0; i < 3; ++i) {
-    a.in[i] = reinterpret_cast<const double2*>(in3[i]);
-    a.out[i] = reinterpret_cast<double2*>(out3[i]);
-  }
-  a.off = p->d_goff;
-  a.nr = p->nr;
-  a.nrc = p->nrc;
-  a.nz = p->nz;
-  a.kmax = kmax;
-  a.nkact = (p->nz == 1) ? 1 : 2 * kmax + 1;
-  a.kap0 = 2.0 * M_PI / p->g.lz;
-  if (mmax <= 0 || a.nkact <= 0) return MLG_OK;
-  a.gx = (a.nkact + TC - 1) / TC;
-  a.gy = (p->nrc + TM - 1) / TM;
-  a.gz = mmax;
-  p->timing.begin("proj_gemm", s);
-  split_proj_kernel<<<xcd_blocks(a.gx, a.gy, a.gz), 256, 0, s>>>(a);
-  p->timing.end(s);
-  return check("split_proj_kernel");
 }
 
 mlg_status launch_split_scalar(const mlg_plan_s* p, int dir, const double* in, double* out, hipStream_t s) {

@@ -101,7 +101,7 @@ struct mlg_plan_s {
   unsigned short* d_split_syn[4] = {nullptr, nullptr, nullptr, nullptr};  // Pbar^T hi/lo, Tbar^T hi/lo [i][kpad]
   int64_t* d_split_syn_off = nullptr;
   int32_t* d_split_syn_kpad = nullptr;
-  unsigned short* d_split_prj[4] = {nullptr, nullptr, nullptr, nullptr};  // W Pbar hi/lo, W Q hi/lo [n-m][ipad]
+  unsigned short* d_split_prj[2] = {nullptr, nullptr};  // W Pbar hi/lo [n-m][ipad] (scalar forward products)
   int64_t* d_split_prj_off = nullptr;
   int split_ipad = 0;
   uint32_t* d_split_zdft = nullptr;  // N_z = 256 split plans: DFT-product constants [dir][lane][40 words]
@@ -162,8 +162,10 @@ mlg_status launch_zfft(const mlg_plan_s* p, const double* in, double* out, int64
 // the same transform of nf fields (1..6) of `rows` lines each, in one launch where the kernel allows
 // axial modal kinetic energy from the velocity harmonics u_r, u_phi, u_z (mixed layout)
 mlg_status launch_energy(const mlg_plan_s* p, double* const* u3, double* energy, double* scratch, hipStream_t s);
+// (fp64_only: the FP64 transforms also on a split-bfloat16 plan)
 mlg_status launch_zfft_fields(const mlg_plan_s* p, const double* const* in, double* const* out, int nf, int64_t rows,
-                              int dir, const int32_t* row_m, int mask_m, int mask_k, hipStream_t s);
+                              int dir, const int32_t* row_m, int mask_m, int mask_k, hipStream_t s,
+                              bool fp64_only = false);
 // Elliptic solves from the projection sources (C, K', Zhat); taps_src receives C, K, Zhat.
 mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, double* psi_n, double* chi_n,
                              double* taps_src, hipStream_t s);
@@ -184,8 +186,6 @@ mlg_status launch_proj_fold(const mlg_plan_s* p, double* const* in3, double* con
 // gemm_split.hip: the same two products with split-bfloat16 operands and FP32 accumulation
 mlg_status launch_split_synth(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,
                               hipStream_t s);
-mlg_status launch_split_proj(const mlg_plan_s* p, double* const* in3, double* const* out3, int mmax, int kmax,
-                             hipStream_t s);
 // split-bfloat16 radial products of the scalar transform pair: dir > 0 backward, dir < 0 forward
 mlg_status launch_split_scalar(const mlg_plan_s* p, int dir, const double* in, double* out, hipStream_t s);
 // split-bfloat16 z transforms of N_z = 256 as two radix-16 DFT products on MFMA (same arguments

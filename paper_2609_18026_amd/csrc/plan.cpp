@@ -150,7 +150,7 @@ void free_plan_device(mlg_plan_s* p) {
                   p->d_row_m, p->d_desc_fwd, p->d_desc_bwd, p->d_gram, p->d_goff,
                   p->d_split_syn[0], p->d_split_syn[1], p->d_split_syn[2], p->d_split_syn[3],
                   p->d_split_syn_off, p->d_split_syn_kpad, p->d_split_prj[0], p->d_split_prj[1],
-                  p->d_split_prj[2], p->d_split_prj[3], p->d_split_prj_off, p->d_split_zdft, p->d_step_fwd,
+                  p->d_split_prj_off, p->d_split_zdft, p->d_step_fwd,
                   p->d_step_bwd, p->d_step_lam, p->d_step_u, p->d_step_qoff, p->d_step_loff, p->d_step_w,
                   p->d_filter, p->d_logf, p->d_qfl, p->d_qfr};
   for (void* q : ptrs)
@@ -274,11 +274,9 @@ mlg_status build_plan(mlg_plan_s* p) {
       soff[m + 1] = soff[m] + (int64_t)nr * kpad[m];
       poff[m + 1] = poff[m] + (int64_t)K * ipad;
     }
-    std::vector<uint16_t> sy[4], pj[4];
-    for (int t = 0; t < 4; ++t) {
-      sy[t].assign(std::max<int64_t>(soff[M], 1), 0);
-      pj[t].assign(std::max<int64_t>(poff[M], 1), 0);
-    }
+    std::vector<uint16_t> sy[4], pj[2];
+    for (int t = 0; t < 4; ++t) sy[t].assign(std::max<int64_t>(soff[M], 1), 0);
+    for (int t = 0; t < 2; ++t) pj[t].assign(std::max<int64_t>(poff[M], 1), 0);
     for (int m = 0; m < M; ++m) {
       const int K = std::max(nrc - m, 0);
       const size_t base = (size_t)p->off[m] * nr;
@@ -287,19 +285,18 @@ mlg_status build_plan(mlg_plan_s* p) {
           const double P = Pb[base + (size_t)kk * nr + i];
           const double T = Tb[base + (size_t)kk * nr + i];
           const double WP = Pf[base + (size_t)i * K + kk];
-          const double WQ = Qf[base + (size_t)i * K + kk];
           const int64_t s1 = soff[m] + (int64_t)i * kpad[m] + kk;  // [i][n - m]
           const int64_t s2 = poff[m] + (int64_t)kk * ipad + i;     // [n - m][i]
           split_into(P, &sy[0][s1], &sy[1][s1]);
           split_into(T, &sy[2][s1], &sy[3][s1]);
           split_into(WP, &pj[0][s2], &pj[1][s2]);
-          split_into(WQ, &pj[2][s2], &pj[3][s2]);
         }
     }
     mlg_status st2;
-    for (int t = 0; t < 4; ++t) {
-      if ((st2 = upload(&p->d_split_syn[t], sy[t])) || (st2 = upload(&p->d_split_prj[t], pj[t]))) return st2;
-    }
+    for (int t = 0; t < 4; ++t)
+      if ((st2 = upload(&p->d_split_syn[t], sy[t]))) return st2;
+    for (int t = 0; t < 2; ++t)
+      if ((st2 = upload(&p->d_split_prj[t], pj[t]))) return st2;
     if ((st2 = upload(&p->d_split_syn_off, soff)) || (st2 = upload(&p->d_split_syn_kpad, kpad)) ||
         (st2 = upload(&p->d_split_prj_off, poff)))
       return st2;

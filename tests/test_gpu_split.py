@@ -1,15 +1,16 @@
 """Split-bfloat16 radial products (MLG_SPLIT_BF16 plans) against the FP64 oracle.
 
-The split mode computes every radial product as hi_a hi_b + hi_a lo_b + lo_a hi_b of bfloat16
-parts with FP32 accumulation (relative error ~2^-17 per term); for N_z = 256 the z transforms are
-two radix-16 DFT products in the same arithmetic.  The phi FFTs, the cross product and the
-elliptic solves stay FP64.  The scalar transform pair and the scalar nonlinear term use split
-products too and must stay within 5e-5 of the oracle.  The errors are measured normwise at each tap point and must stay
-within 5e-5 for the nodal fields and sources.  The solved potentials inherit the conditioning of
-the discrete projection (the Laplacian solves have cond ~1e9 at N_r = 256): the ~5e-6 errors of
-N are amplified, in the coefficients of (psi_N, chi_N) and in the velocity V(psi_N, chi_N) they
-represent.  Those output errors are measured and printed here (and by bench.py at 256^3) and only
-checked against a loose bound at these sizes.
+The split mode computes the radial products of the transform pair, the scalar term and the vector
+synthesis as hi_a hi_b + hi_a lo_b + lo_a hi_b of bfloat16 parts with FP32 accumulation (relative
+error ~2^-17 per term); for N_z = 256 their z transforms are two radix-16 DFT products in the same
+arithmetic.  The phi FFTs, the cross product, the projection's forward z transforms, its source
+products and its elliptic solves stay FP64: the solves are ill-conditioned along the far-field
+directions of the Gram matrices (cond ~1e9 at N_r = 256) and split source products were amplified
+there into O(1) errors of the output.  With FP64 sources the output error follows the error of the
+nodal N, which the projection does not enlarge: the velocity V(psi_N, chi_N) the output represents
+is checked relative to the nodal N (the projection is a contraction in the continuous L2 norm) and
+relative to itself.  The scalar transform pair and the scalar nonlinear term must stay within 5e-5
+of the oracle; the nodal taps within 5e-5.
 """
 import numpy as np
 import pytest
@@ -27,6 +28,8 @@ CASES = [
     (24, 12, 8, 0.9, 3.0, (0.3, -0.2, 0.5), 1),
     (70, 20, 10, 1.2, 4.0, (0.0, 1.0, 0.0), 0),
     (40, 256, 256, 1.0, 8.6, (0.0, 1.0, 0.0), 1),
+    (256, 16, 16, 1.0, 8.6, (0.0, 1.0, 0.0), 1),     # the headline radial size: cond(Dbar_1) ~ 1e9
+    (256, 24, 8, 1.5, 5.0, (0.2, -0.4, 0.1), 0),
 ]
 
 
@@ -65,10 +68,15 @@ def test_split_rhs_tp_error(case):
     v_got, _ = synthesize(gp, gc, g, vt)
     v_ref, _ = synthesize(ref_psi, ref_chi, g, vt)
     errs["V(psi_N,chi_N)"] = rel(np.stack(v_got), np.stack(v_ref))
+    nN = np.linalg.norm(np.stack(list(taps["N"])).ravel())
+    errs["V err / |N|"] = np.linalg.norm((np.stack(v_got) - np.stack(v_ref)).ravel()) / nN
     print("  split-bf16 relative errors:", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    for nm in names + ["C", "K", "Z"]:
+    for nm in names:
         assert errs[nm] < 5e-5, (nm, errs[nm])
-    assert errs["V(psi_N,chi_N)"] < 2e-2 and errs["psi_N"] < 1e-1 and errs["chi_N"] < 1e-1
+    # the projection does not enlarge the nodal error of N (measured <= 4.3e-6 on these cases)
+    assert errs["V err / |N|"] < 1e-5, errs["V err / |N|"]
+    # relative to the output itself the error grows by |N| / |P N| (measured <= 4.7e-5 here, at 256 nodes)
+    assert errs["V(psi_N,chi_N)"] < 2e-4, errs["V(psi_N,chi_N)"]
 
 
 SCALAR_CASES = [
