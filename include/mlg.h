@@ -186,6 +186,33 @@ mlg_status mlg_step_febe(mlg_plan plan, int half, const void* s, const void* A, 
  * share its step scratch and must not overlap. */
 mlg_status mlg_step_abcn(mlg_plan plan, const void* s, const void* A_now, const void* A_prev, void* out, void* stream);
 
+/* Inverse Laplacian of a scalar (Sec. 3.1, Eq. laplacian, Eq. logproxy): s = (grad^2)^{-1} f per
+ * harmonic, (Dbar_m - kappa_k^2) shat = fhat with the truncated Dbar_m of Eq. del2h-entries, for
+ * every stored (m, k) other than m = k = 0 (slots outside the axial chop are written as zero).  The
+ * m = k = 0 block is singular (Dbar_0 annihilates the constant Pbar_0^0); the potential carries one
+ * extra real amplitude c of Lambda = ln(r^2 + ell^2), s = c Lambda + sum shat_n Pbar_n^0, and the
+ * paper's two variants differ only in that block:
+ *  MLG_LOG_PRESCRIBE: c is read from *c; Dbar_0 shat = fhat - c g with its first row replaced by
+ *    the decay gauge sum_n Pbar_n^0(1) shat_n = 0 (g: the coefficients of grad_h^2 Lambda);
+ *  MLG_LOG_SOLVE: the first column of Dbar_0 is replaced by g, so that the unknown of Pbar_0^0
+ *    becomes c: [g | Dbar_0[:, 1:]] (c, shat_1, ...) = fhat; c is written to *c, and the constant
+ *    shat_0, which the Laplacian does not see, is fixed by the same decay gauge.
+ * The m = k = 0 column is that of a real field: the real part of fhat is used and the column of s
+ * is real.  f, s: packed spectral arrays (no aliasing); c: device pointer to one double; ws: the
+ * plan workspace.  Each (m, k) column is one thread's L D L^T sweep of the SPD system
+ * (G_m + kappa^2 ell^2 L^-1) y = -ell^2 fhat, y = diag(n(n+1)) shat (Dbar_m = -G_m L / ell^2 with G_m the
+ * pentadiagonal Gram matrix).  Errors: MLG_E_ARG (null or aliased buffers, unknown variant). */
+enum { MLG_LOG_PRESCRIBE = 0, MLG_LOG_SOLVE = 1 };
+mlg_status mlg_laplacian_solve(mlg_plan plan, int variant, const void* f, void* s, double* c, void* ws, void* stream);
+
+/* Removal of the free far-field level of the axisymmetric components (Sec. 3.1): Pbar_n^0 tends to
+ * Pbar_n^0(1) = sqrt((2n + 1)/2) as r -> infinity, so every m = 0 harmonic has the level
+ * sum_n Pbar_n^0(1) shat_{n,0,k} at infinity.  For every axial slot it is removed through the
+ * constant basis function: shat_{0,0,k} -= level / Pbar_0^0(1), i.e. the constant at infinity is
+ * subtracted from the component everywhere and every derivative is unchanged.  In place on a
+ * packed spectral array. */
+mlg_status mlg_remove_far_field(mlg_plan plan, void* spec, void* stream);
+
 /* Logarithmic proxies (Sec. 3.1, Eq. logproxy): the potentials are psi~ + c_psi Lambda and
  * chi~ + c_chi Lambda with Lambda(r) = ln(r^2 + ell^2), the spectral arrays holding the regular parts
  * psi~, chi~.  The proxy parts add u_phi = -2 c_psi r / (r^2 + ell^2), u_z = -c_chi grad_h^2 Lambda,

@@ -49,6 +49,7 @@ EXPORTS = ["mlg_plan_create", "mlg_plan_destroy", "mlg_plan_query", "mlg_plan_no
            "mlg_batch_get_config", "mlg_batch_autotune", "mlg_step_setup", "mlg_step_febe", "mlg_step_abcn",
            "mlg_truncate", "mlg_tp_advance", "mlg_filter_setup", "mlg_filter_apply", "mlg_filter_state",
            "mlg_eval_harmonic", "mlg_scalar_advance", "mlg_set_log_proxy", "mlg_tp_enstrophy",
+           "mlg_laplacian_solve", "mlg_remove_far_field",
            "mlg_closure_param_count", "mlg_closure_create", "mlg_closure_destroy",
            "mlg_closure_columns", "mlg_closure_set_params", "mlg_closure_get_params", "mlg_closure_get_grads",
            "mlg_closure_set_scales", "mlg_closure_get_scales", "mlg_closure_features", "mlg_closure_targets",
@@ -118,6 +119,8 @@ def lib() -> ctypes.CDLL:
     L.mlg_eval_harmonic.argtypes = [vp, vp, i32, i32, vp, ctypes.c_int64, vp, vp]
     L.mlg_scalar_advance.argtypes = [vp, i32, f64, vp, vp, i32, i32, vp, vp, vp]
     L.mlg_set_log_proxy.argtypes = [vp, f64, f64]
+    L.mlg_laplacian_solve.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    L.mlg_remove_far_field.argtypes = [vp, vp, vp]
     L.mlg_tp_enstrophy.argtypes = [vp, vp, vp, vp, vp, vp]
     L.mlg_closure_param_count.argtypes = []
     L.mlg_closure_create.argtypes = [ctypes.POINTER(mlg_closure_cfg), vp, ctypes.POINTER(vp)]
@@ -246,6 +249,17 @@ def mlg_eval_harmonic(plan: int, spec: int, m: int, kk: int, r: int, npts: int, 
 def mlg_scalar_advance(plan: int, kind: int, gamma: float, state: int, hist: int, nsteps: int, start: int, tmp: int,
                        ws: int, stream: int = 0) -> None:
     _check(lib().mlg_scalar_advance(plan, kind, gamma, state, hist, nsteps, start, tmp, ws, stream))
+
+
+MLG_LOG_PRESCRIBE, MLG_LOG_SOLVE = 0, 1
+
+
+def mlg_laplacian_solve(plan: int, variant: int, f: int, s: int, c: int, ws: int, stream: int = 0) -> None:
+    _check(lib().mlg_laplacian_solve(plan, variant, f, s, c, ws, stream))
+
+
+def mlg_remove_far_field(plan: int, spec: int, stream: int = 0) -> None:
+    _check(lib().mlg_remove_far_field(plan, spec, stream))
 
 
 def mlg_set_log_proxy(plan: int, c_psi: float, c_chi: float) -> None:
@@ -510,6 +524,19 @@ class Plan:
         mlg_scalar_advance(self.handle, kind, gamma, self._spec(s, "state"), self._spec(hist, "hist"), nsteps, start,
                            self._spec(tmp, "tmp", 3), self._ws(), self._stream())
         return tmp
+
+    def laplacian_solve(self, f, s, c=None, variant=MLG_LOG_SOLVE):
+        """s = (grad^2)^{-1} f; the m = k = 0 block prescribes c (MLG_LOG_PRESCRIBE, c a float) or
+        solves for it (MLG_LOG_SOLVE).  Returns the amplitude as a float64 device tensor of one entry."""
+        import torch
+        cbuf = torch.tensor([0.0 if c is None else float(c)], dtype=torch.float64, device=f"cuda:{self.device}")
+        mlg_laplacian_solve(self.handle, variant, self._spec(f, "f"), self._spec(s, "s"),
+                            _ptr(cbuf, "c", (torch.float64,), 1, self.device), self._ws(), self._stream())
+        return cbuf
+
+    def remove_far_field(self, spec):
+        """Remove the far-field level of every m = 0 harmonic of 'spec' in place."""
+        mlg_remove_far_field(self.handle, self._spec(spec), self._stream())
 
     def set_log_proxy(self, c_psi=0.0, c_chi=0.0):
         """Amplitudes of ln(r^2 + ell^2) carried by psi and chi beyond their regular parts."""

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmlg.so")
 OBJDIR = os.path.join(os.path.dirname(HERE), "_build")
 SOURCES = ["plan.cpp", "api.cpp", "kernels.hip", "fft256.hip", "gemm_fused.hip", "gemm_fold.hip", "gemm_split.hip",
-           "batch.hip", "step.hip", "closure.hip", "symeig.cpp"]
+           "batch.hip", "step.hip", "closure.hip", "symeig.cpp", "poisson.hip"]
 
 # -packed-fp32-ops is a device target feature (the host pass warns that it does not know it)
 FLAGS = [

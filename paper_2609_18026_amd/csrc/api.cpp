@@ -571,6 +571,26 @@ mlg_status mlg_tp_enstrophy(mlg_plan p, const void* psi, const void* chi, double
   return launch_energy(p, w.X + 3, enstrophy, w.T[0], s);   // the same quadrature on the vorticity
 }
 
+mlg_status mlg_laplacian_solve(mlg_plan p, int variant, const void* f, void* s, double* c, void* ws, void* stream) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!f || !s || !ws || !c) return fail(MLG_E_ARG, "null buffer");
+  if (f == s) return fail(MLG_E_ARG, "f and s must not alias");
+  if (variant != MLG_LOG_PRESCRIBE && variant != MLG_LOG_SOLVE) return fail(MLG_E_ARG, "unknown variant");
+  DeviceGuard guard(p->device);
+  Ws w = partition(p, ws);
+  double* c_in = variant == MLG_LOG_PRESCRIBE ? c : nullptr;
+  double* c_out = variant == MLG_LOG_SOLVE ? c : nullptr;
+  return launch_poisson(p, variant, static_cast<const double*>(f), static_cast<double*>(s), c_in, c_out, w.T[0],
+                        w.T[1], static_cast<hipStream_t>(stream));
+}
+
+mlg_status mlg_remove_far_field(mlg_plan p, void* spec, void* stream) {
+  if (mlg_status st = check_plan(p)) return st;
+  if (!spec) return fail(MLG_E_ARG, "null buffer");
+  DeviceGuard guard(p->device);
+  return launch_far_field(p, static_cast<double*>(spec), static_cast<hipStream_t>(stream));
+}
+
 mlg_status mlg_set_log_proxy(mlg_plan p, double c_psi, double c_chi) {
   if (mlg_status st = check_plan(p)) return st;
   if (!std::isfinite(c_psi) || !std::isfinite(c_chi)) return fail(MLG_E_ARG, "proxy amplitudes must be finite");

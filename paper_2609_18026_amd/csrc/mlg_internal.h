@@ -97,6 +97,9 @@ struct mlg_plan_s {
   double2* d_qfl = nullptr;
   double* d_qfr = nullptr;
   int max_rows_fwd = 0, max_rows_bwd = 0;
+  // inverse Laplacian of the m = k = 0 block (Eq. logproxy): [0] = g_0 - Dbar_{0,1:} shat^g and
+  // [n] = shat^g_n for n >= 1, the response of the solved degrees to the image g of grad_h^2 Lambda
+  double* d_poisson = nullptr;
   // split-bfloat16 tables (MLG_SPLIT_BF16 plans): hi / lo parts, rows padded to 32 entries
   unsigned short* d_split_syn[4] = {nullptr, nullptr, nullptr, nullptr};  // Pbar^T hi/lo, Tbar^T hi/lo [i][kpad]
   int64_t* d_split_syn_off = nullptr;
@@ -219,6 +222,11 @@ const mlg_plan_s* closure_plan(const mlg_closure_s* c);
 // active column bounds of the projection: m < mmax, |k| <= kmax
 void active_columns(const mlg_plan_s* p, int* mmax, int* kmax);
 mlg_status launch_mask_tri(const mlg_plan_s* p, double* spec, hipStream_t s);
+// poisson.hip: inverse Laplacian of a scalar (variant 0: prescribed amplitude *c_in, 1: solved into
+// *c_out; ws0: tau * nz complex, ws1: tau * nz reals), and the far-field level removal of m = 0
+mlg_status launch_poisson(const mlg_plan_s* p, int variant, const double* f, double* s, const double* c_in,
+                          double* c_out, double* ws0, double* ws1, hipStream_t st);
+mlg_status launch_far_field(const mlg_plan_s* p, double* spec, hipStream_t st);
 // fft256.hip: register-resident 256-point transforms (used when N_z or N_phi equals 256)
 mlg_status launch_zfft256(const mlg_plan_s* p, const double* const* in, double* const* out, int nf, int64_t rows,
                           int dir, const int32_t* row_m, int mask_m, int mask_k, hipStream_t s);

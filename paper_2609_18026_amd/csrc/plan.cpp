@@ -152,7 +152,7 @@ void free_plan_device(mlg_plan_s* p) {
                   p->d_split_syn_off, p->d_split_syn_kpad, p->d_split_prj[0], p->d_split_prj[1],
                   p->d_split_prj_off, p->d_split_zdft, p->d_step_fwd,
                   p->d_step_bwd, p->d_step_lam, p->d_step_u, p->d_step_qoff, p->d_step_loff, p->d_step_w,
-                  p->d_filter, p->d_logf, p->d_qfl, p->d_qfr};
+                  p->d_filter, p->d_logf, p->d_qfl, p->d_qfr, p->d_poisson};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }
@@ -492,7 +492,38 @@ mlg_status build_plan(mlg_plan_s* p) {
     p->max_rows_fwd = std::max(p->max_rows_fwd, f.rows);
     p->max_rows_bwd = std::max(p->max_rows_bwd, b.rows);
   }
+  // ---------------- inverse Laplacian, m = k = 0 block (Eq. logproxy): the response shat^g of the
+  // solved degrees n >= 1 to the image g of grad_h^2 Lambda, Dbar_0[1:, 1:] shat^g = g[1:] (as
+  // G[1:, 1:] y = -ell^2 g[1:], y = L shat^g), and den = g_0 - Dbar_{0,1:} shat^g, in long double
+  std::vector<double> poisson(std::max(nrc, 1), 0.0);
+  {
+    const ld ell2 = (ld)g.ell * (ld)g.ell;
+    const ld un[3] = {4.0L / 3.0L, -2.0L, 2.0L / 3.0L};
+    std::vector<ld> gv(nrc + 1, 0), G0(nrc + 2, 0), G1(nrc + 2, 0), G2(nrc + 2, 0);
+    for (int n = 0; n < 3 && n < nrc; ++n) gv[n] = un[n] / sqrtl((ld)(2 * n + 1) / 2.0L) / ell2;
+    for (int n = 0; n < nrc; ++n) {
+      const ld e0 = eps_nm(n, 0), e1 = eps_nm(n + 1, 0), e2 = eps_nm(n + 2, 0);
+      G0[n] = 1 + e0 * e0 + e1 * e1;
+      G1[n] = -2 * e1;
+      G2[n] = e1 * e2;
+    }
+    std::vector<ld> d(nrc + 1, 0), l1(nrc + 1, 0), l2(nrc + 1, 0), z(nrc + 1, 0), y(nrc + 3, 0);
+    for (int n = 1; n < nrc; ++n) {
+      if (n - 2 >= 1) l2[n] = G2[n - 2] / d[n - 2];
+      if (n - 1 >= 1) l1[n] = (G1[n - 1] - (n - 2 >= 1 ? l2[n] * d[n - 2] * l1[n - 1] : 0)) / d[n - 1];
+      d[n] = G0[n] - (n - 1 >= 1 ? l1[n] * l1[n] * d[n - 1] : 0) - (n - 2 >= 1 ? l2[n] * l2[n] * d[n - 2] : 0);
+      z[n] = -ell2 * gv[n] - (n - 1 >= 1 ? l1[n] * z[n - 1] : 0) - (n - 2 >= 1 ? l2[n] * z[n - 2] : 0);
+    }
+    for (int n = nrc - 1; n >= 1; --n)
+      y[n] = z[n] / d[n] - (n + 1 < nrc ? l1[n + 1] * y[n + 1] : 0) - (n + 2 < nrc ? l2[n + 2] * y[n + 2] : 0);
+    ld den = gv[0];
+    if (nrc > 1) den += G1[0] * y[1] / ell2;
+    if (nrc > 2) den += G2[0] * y[2] / ell2;
+    poisson[0] = (double)den;
+    for (int n = 1; n < nrc; ++n) poisson[n] = (double)(y[n] / ((ld)n * (n + 1)));
+  }
   mlg_status st;
+  if ((st = upload(&p->d_poisson, poisson))) return st;
   if ((st = upload(&p->d_Pb, Pb)) || (st = upload(&p->d_Pf, Pf)) || (st = upload(&p->d_Tb, Tb)) ||
       (st = upload(&p->d_Qf, Qf)) || (st = upload(&p->d_node, node)) || (st = upload(&p->d_tw_phi, twp)) ||
       (st = upload(&p->d_tw_z, twz)) || (st = upload(&p->d_row_m, rowm)) ||
