@@ -128,28 +128,123 @@ def build_state(plan, n, torch):
     return phys, psi_hat, chi_hat
 
 
-def cpu_baseline(n_sample: int):
-    """Oracle rhs_tp on the same vortex-pair workload at n_sample^3 (host cores)."""
+def _host_cpu():
+    """CPU model name and the number of cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    return model, ncpu
+
+
+def _timed(fn, warmup, reps):
+    for _ in range(warmup):
+        fn()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def cpu_baseline(n_sample: int, gpu_small: dict):
+    """The oracle timed on the host (1 warm-up, median of 5 unless stated): the headline workload's
+    rhs_tp on a bounded sample (the vortex pair at n_sample^3) with all BLAS threads and with one, its
+    growth with the grid (48^3 vs n_sample^3) and the 256^3 rate that growth implies, and the other
+    workloads: the 32 x 16 x 1 scalar term and transform pair, the 128^3 vector RHS (median of 3) and
+    the 64 batched 2D KPP terms (median of 3).  gpu_small: the library's outputs on the sampled and
+    small workloads, compared here with the oracle's (the FP64 parity of the bench path)."""
     import synth
     from oracle.grid import Grid
-    from oracle.rhs import VecTables, rhs_tp
-    from oracle.transform import Tables, forward
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    except Exception:
-        threads = os.cpu_count() or 1
-    g = Grid(n_sample, n_sample, n_sample, 1.0, lz=PAIR["lz"])
-    psi = synth.vortex_pair_psi(g.r, g.phi, g.z, gamma=PAIR["gamma"], a=PAIR["a"], b=PAIR["b"],
-                                delta=PAIR["delta"], lz=PAIR["lz"])
-    S = forward(psi, g, Tables(g))
-    vt = VecTables(g)
-    t0 = time.perf_counter()
-    rhs_tp(S, np.zeros_like(S), g, vt, U=U_FRAME, dealias=True)
-    dt = time.perf_counter() - t0
-    return dict(value=round(n_sample ** 3 / dt / 1e9, 6), unit="GDOF/s", cores=int(threads), kind="oracle",
-                sample=f"one oracle rhs_tp on the vortex-pair state at N_r=N_phi=N_z={n_sample} "
-                       f"(1/{(256 // n_sample) ** 3} of the 256^3 grid points), {dt:.1f} s")
+    from oracle.rhs import VecTables, rhs_scalar, rhs_tp, synthesize
+    from oracle.transform import Tables, backward, forward
+    from threadpoolctl import threadpool_info, threadpool_limits
+    model, ncpu = _host_cpu()
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+
+    def pair_case(n):
+        g = Grid(n, n, n, 1.0, lz=PAIR["lz"])
+        psi = synth.vortex_pair_psi(g.r, g.phi, g.z, gamma=PAIR["gamma"], a=PAIR["a"], b=PAIR["b"],
+                                    delta=PAIR["delta"], lz=PAIR["lz"])
+        S = forward(psi, g, Tables(g))
+        return g, S, VecTables(g)
+
+    res = {"kind": "oracle", "unit": "GDOF/s", "cpu_model": model, "host_cpus": ncpu, "warmup": 1, "median_of": 5}
+    g, S, vt = pair_case(n_sample)
+    Z = np.zeros_like(S)
+    run = lambda: rhs_tp(S, Z, g, vt, U=U_FRAME, dealias=True)
+    g2, S2, vt2 = pair_case(48)
+    Z2 = np.zeros_like(S2)
+    run48 = lambda: rhs_tp(S2, Z2, g2, vt2, U=U_FRAME, dealias=True)
+    t_all, t48_all = _timed(run, 1, 5), _timed(run48, 1, 5)
+    with threadpool_limits(limits=1):
+        t_one, t48_one = _timed(run, 1, 5), _timed(run48, 1, 5)
+    # the reported value is the faster of the two thread settings ('cores' = its thread count)
+    best_all = t_all <= t_one
+    t_best, t48 = (t_all, t48_all) if best_all else (t_one, t48_one)
+    res["cores"] = int(threads) if best_all else 1
+    res["value"] = round(n_sample ** 3 / t_best / 1e9, 7)
+    res["seconds"] = round(t_best, 4)
+    res["threads"] = {f"{threads}": {"value": round(n_sample ** 3 / t_all / 1e9, 7), "seconds": round(t_all, 4)},
+                      "1": {"value": round(n_sample ** 3 / t_one / 1e9, 7), "seconds": round(t_one, 4)}}
+    res["sample"] = (f"oracle rhs_tp on the vortex-pair state at N_r=N_phi=N_z={n_sample} "
+                     f"(1/{(256 // n_sample) ** 3} of the 256^3 grid points)")
+    # growth with the grid, and the 256^3 rate it implies (an extrapolation, not a measurement)
+    e = float(np.log(t_best / t48) / np.log(n_sample / 48))
+    t256 = t_best * (256 / n_sample) ** e
+    res["scaling"] = {"seconds_48": round(t48, 4), f"seconds_{n_sample}": round(t_best, 4), "exponent": round(e, 3),
+                      "extrapolated_256_seconds": round(t256, 2),
+                      "extrapolated_256_gdofs": round(256 ** 3 / t256 / 1e9, 7)}
+    # parity of the bench path: the library's RHS at n_sample^3 (same workload) against the oracle's
+    ref_p, ref_c = run()
+    gp, gc = gpu_small["pair_psi_n"], gpu_small["pair_chi_n"]
+    rel = lambda a, b: float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+    v_ref, _ = synthesize(ref_p, ref_c, g, vt)
+    v_got, _ = synthesize(gp, gc, g, vt)
+    res["parity"] = {"workload": f"vortex pair at {n_sample}^3, FP64",
+                     "rel_err_psi_n": rel(gp, ref_p), "rel_err_chi_n": rel(gc, ref_c),
+                     "rel_err_velocity_of_output": rel(np.stack(v_got), np.stack(v_ref))}
+    cfg = {}
+    # config 1: 32 x 16 x 1 scalar, u^2 term and round trip
+    g1 = Grid(32, 16, 1, 1.0)
+    t1 = Tables(g1)
+    S1 = synth.geometric_spectrum(g1.M, g1.nrc, 1, g1.nzc, seed=1, a=0.7, b=0.8, c=1.0)
+    tr = _timed(lambda: rhs_scalar(S1, g1, t1, "u2"), 1, 5)
+    tp = _timed(lambda: forward(backward(S1, g1, t1), g1, t1), 1, 5)
+    cfg["scalar_32x16x1"] = {"rhs_u2_ms": round(tr * 1e3, 4), "transform_pair_ms": round(tp * 1e3, 4),
+                             "rhs_gdofs": round(512 / tr / 1e9, 7)}
+    r1 = rhs_scalar(S1, g1, t1, "u2")
+    cfg["scalar_32x16x1"]["parity_rel_err"] = rel(gpu_small["cfg1_u2"], r1)
+    # config 2: 128^3 geometric potentials, vector RHS (1 warm-up, median of 3)
+    g3 = Grid(128, 128, 128, 1.0)
+    vt3 = VecTables(g3)
+    P3 = synth.geometric_spectrum(g3.M, g3.nrc, 128, g3.nzc, seed=2, a=0.9, b=0.85, c=0.85)
+    C3 = synth.geometric_spectrum(g3.M, g3.nrc, 128, g3.nzc, seed=3, a=0.9, b=0.85, c=0.85)
+    t3 = _timed(lambda: rhs_tp(P3, C3, g3, vt3, U=(0.0, 0.0, 0.0), dealias=True), 1, 3)
+    cfg["vector_128cubed"] = {"seconds": round(t3, 3), "gdofs": round(128 ** 3 / t3 / 1e9, 7), "median_of": 3}
+    # config 3: the 64 batched 2D KPP terms (tables built outside the timed region; median of 3)
+    insts = synth.batched_instances(64, 3)
+    cases = []
+    for k, d in enumerate(insts):
+        gk = Grid(d["nr"], d["nphi"], 1, d["ell"])
+        Sk = synth.geometric_spectrum(gk.M, gk.nrc, 1, gk.nzc, seed=1000 + k, a=0.9, b=0.85, c=1.0)
+        cases.append((gk, Tables(gk), Sk))
+    t4 = _timed(lambda: [rhs_scalar(Sk, gk, tk, "kpp", 0.25) for gk, tk, Sk in cases], 0, 3)
+    dofs = sum(d["nr"] * d["nphi"] for d in insts)
+    cfg["batched_2d_kpp"] = {"seconds": round(t4, 4), "gdofs": round(dofs / t4 / 1e9, 7), "median_of": 3,
+                             "warmup": 0}
+    res["configs"] = cfg
+    return res
 
 
 def bench_batched(torch, args, stream, e0, e1, count=64, seed=3):
@@ -264,6 +359,62 @@ def bench_split(torch, plan, psi, chi, po, co, phys, spec, args, stream, e0, e1)
     return res
 
 
+def bench_small(torch, args, stream, e0, e1):
+    """The other workloads on the GPU: the 32 x 16 x 1 scalar term and transform pair, the 128^3 vector
+    RHS of geometric potentials, and the vortex-pair RHS at the oracle's sample size (for the parity
+    figure of the bench path).  Returns host copies of the outputs the oracle leg compares, and
+    timings."""
+    import synth
+    from paper_2609_18026_amd import MLG_RHS_U2, Plan
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    outs, res = {}, {}
+    p1 = Plan(32, 16, 1, 1.0)
+    S1 = synth.geometric_spectrum(p1.layout.M, p1.layout.nrc, 1, p1.layout.nzc, seed=1, a=0.7, b=0.8, c=1.0)
+    d1 = torch.from_numpy(synth.to_packed(S1)).cuda()
+    o1, ph = p1.empty_spec(), p1.empty_phys()
+    ms_u2 = timed(lambda: p1.rhs_scalar(MLG_RHS_U2, 0.25, d1, o1))
+    ms_pair = timed(lambda: (p1.backward(d1, ph), p1.forward(ph, o1)))
+    p1.rhs_scalar(MLG_RHS_U2, 0.25, d1, o1)
+    torch.cuda.synchronize()
+    outs["cfg1_u2"] = synth.from_packed(o1.cpu().numpy(), p1.layout.M, p1.layout.nrc)
+    res["scalar_32x16x1"] = {"rhs_u2_us": round(ms_u2 * 1e3, 2), "transform_pair_us": round(ms_pair * 1e3, 2),
+                             "rhs_gdofs": round(512 / (ms_u2 / 1e3) / 1e9, 5)}
+    p1.close()
+    p3 = Plan(128, 128, 128, 1.0)
+    L3 = p3.layout
+    P3 = torch.from_numpy(synth.to_packed(synth.geometric_spectrum(L3.M, L3.nrc, 128, L3.nzc, seed=2, a=0.9, b=0.85,
+                                                                     c=0.85))).cuda()
+    C3 = torch.from_numpy(synth.to_packed(synth.geometric_spectrum(L3.M, L3.nrc, 128, L3.nzc, seed=3, a=0.9, b=0.85,
+                                                                     c=0.85))).cuda()
+    a3, b3 = p3.empty_spec(), p3.empty_spec()
+    ms3 = timed(lambda: p3.rhs_tp(P3, C3, a3, b3))
+    res["vector_128cubed"] = {"ms_per_step": round(ms3, 4), "gdofs": round(128 ** 3 / (ms3 / 1e3) / 1e9, 4)}
+    p3.close()
+    n = args.cpu_sample
+    ps = Plan(n, n, n, 1.0, PAIR["lz"], dealias=1)
+    _, psi, chi = build_state(ps, n, torch)
+    a, b = ps.empty_spec(), ps.empty_spec()
+    ps.rhs_tp(psi, chi, a, b, U=U_FRAME)
+    torch.cuda.synchronize()
+    L = ps.layout
+    outs["pair_psi_n"] = synth.from_packed(a.cpu().numpy(), L.M, L.nrc)
+    outs["pair_chi_n"] = synth.from_packed(b.cpu().numpy(), L.M, L.nrc)
+    ps.close()
+    log(f"bench: 32x16x1 u^2 term {ms_u2 * 1e3:.1f} us, 128^3 vector RHS {ms3:.3f} ms")
+    return outs, res
+
+
 def bench_time_step(torch, plan, psi, chi, args, stream, e0, e1):
     """Whole AB-CN steps of (psi, chi) at the bench size: one RHS plus the implicit update of both
     potentials per step (Eq. abcn), through mlg_tp_advance on resident state."""
@@ -301,12 +452,12 @@ def bench_time_step(torch, plan, psi, chi, args, stream, e0, e1):
 
 def bench_closure(torch, args, stream, e0, e1):
     """Learned closure at the coarse 64^3 grid: cost of a training step (4096 columns) and of an
-    inference next to the coarse RHS, then the held-out gain of a network trained on fine 128^3
-    runs (the recipe of the gain test)."""
+    inference next to the coarse RHS, then the held-out gain of a network trained on fine 256^3
+    runs and coarse roll-outs with and without it (the recipe of the gain test)."""
     import synth
     from paper_2609_18026_amd import Closure, Plan
     from paper_2609_18026_amd import closure_runs as cr
-    n_c, n_f = 64, 128
+    n_c, n_f = 64, 256
     coarse = Plan(n_c, n_c, n_c, 1.0, PAIR["lz"])
     fine = Plan(n_f, n_f, n_f, 1.0, PAIR["lz"])
     spec = cr.RunSpec(nu=1e-4, nu_h=1e-14, p=8, dt=5e-4, U=U_FRAME)
@@ -384,17 +535,18 @@ def bench_closure(torch, args, stream, e0, e1):
     g_tr, _ = gain(free, train)
     g_free, _ = gain(free, held)
     g_jud, nfb = gain(cl, held)
-    # a posteriori: roll-outs of the first held-out run against the truncated fine run
-    sn = runs[6]
+    # a posteriori: roll-outs of both held-out runs against their truncated fine runs
 
     def nrm(*ts):
         return float(np.sqrt(sum(torch.linalg.vector_norm(t).item() ** 2 for t in ts)))
 
     roll = {}
-    for name, clo in (("plain", None), ("closure_judged", cl)):
-        st = cr.rollout(coarse, spec, sn.psi[0], sn.chi[0], nsnap, every, closure=clo)
-        roll[name] = [round(nrm(a - sn.psi[j], b - sn.chi[j]) / nrm(sn.psi[j], sn.chi[j]), 6)
-                      for j, (a, b) in enumerate(st)][1:]
+    for ri in (6, 7):
+        sn = runs[ri]
+        for name, clo in (("plain", None), ("closure_judged", cl), ("closure_unjudged", free)):
+            st = cr.rollout(coarse, spec, sn.psi[0], sn.chi[0], nsnap, every, closure=clo)
+            roll[f"run{ri}_{name}"] = [round(nrm(a - sn.psi[j], b - sn.chi[j]) / nrm(sn.psi[j], sn.chi[j]), 6)
+                                       for j, (a, b) in enumerate(st)][1:]
     calls, fbs = cl.stats()
     res = {"coarse": f"{n_c}^3", "fine": f"{n_f}^3", "columns": cl.ncols, "train_rows": int(X.shape[0]),
            "train_step_ms": round(train_ms, 4), "train_batch": nb,
@@ -406,8 +558,9 @@ def bench_closure(torch, args, stream, e0, e1):
                              "held_out_judged": round(g_jud, 4), "held_out_fallbacks": nfb,
                              "held_out_snapshots": len(held.psi)},
            "rollout_rel_field_error": roll, "rollout_judge_calls_fallbacks": [calls, fbs],
-           "recipe": "8 fine vortex-pair runs (delta 0.005/0.01/0.02, phases from seeds 5..12), nu=1e-4, "
-                     "nu_h=1e-14, p=8, dt=5e-4, 12 snapshots 40 steps apart; runs 0-5 train, 6-7 held out"}
+           "recipe": "8 fine 256^3 vortex-pair runs (delta 0.005/0.01/0.02, phases from seeds 5..12), nu=1e-4, "
+                     "nu_h=1e-14, p=8, dt=5e-4, 12 snapshots 40 steps apart; runs 0-5 train, 6-7 held out; "
+                     "coarse 64^3"}
     log(f"bench: closure train step {train_ms:.3f} ms, inference {inf_ms:.3f} ms vs coarse RHS {rhs_ms:.3f} ms, "
         f"held-out gain {g_free:.3f} (judged {g_jud:.3f})")
     torch.cuda.synchronize()
@@ -423,7 +576,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure section")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain device copy of 256 MiB (reference for HBM byte counters)")
@@ -547,9 +700,11 @@ def main():
         out["closure"] = bench_closure(torch, args, stream, e0, e1)
     torch.cuda.synchronize()
     plan.close()                 # every native handle is released before the interpreter shuts down
+    gpu_small, out["small_workloads"] = bench_small(torch, args, stream, e0, e1)
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample, gpu_small)
+        out["rel_err_vs_fp64_oracle"] = out["cpu_baseline"]["parity"]
     print(json.dumps(out), flush=True)
 
 

@@ -2,12 +2,14 @@
 
 Recipe (all through the library): vortex pairs (Gamma = 2 pi, a = 0.1, b = 1, L_z = 8.6,
 U = (0, 1, 0)) with core displacement delta in {0.005, 0.01, 0.02} and phases drawn from seeds
-5 .. 12; fine runs at 128^3, coarse grid 64^3, nu = 1e-4, nu_h = 1e-14 with p = 8, dt = 5e-4;
+5 .. 12; fine runs at 256^3, coarse grid 64^3, nu = 1e-4, nu_h = 1e-14 with p = 8, dt = 5e-4;
 12 snapshots 40 steps apart (t in [0, 0.22]); runs 0 .. 5 train, runs 6 and 7 are held out.
 The network is trained by the library's own kernels (Adam, 3000 steps of 4096 columns) and
 judged a priori by ||T A_f - (A_c + C)|| / ||T A_f - A_c|| summed over held-out snapshots.
-The a-posteriori roll-out with the judge in place must stay finite; its error against the
-truncated fine run is printed next to the plain coarse roll-out's.
+A posteriori, coarse roll-outs of both held-out runs are compared with the truncated fine runs with
+and without the closure: the judged roll-outs must stay finite and their error is printed next to
+the plain solver's (the measured outcome: the network lowers the a-priori error but not the
+roll-out error, see the design notes).
 """
 import numpy as np
 import pytest
@@ -39,7 +41,7 @@ def test_closure_gain_on_held_out_runs():
         pytest.skip("no GPU")
     import paper_2609_18026_amd as m
     from paper_2609_18026_amd import closure_runs as cr
-    fine = m.Plan(128, 128, 128, ELL, LZ)
+    fine = m.Plan(256, 256, 256, ELL, LZ)
     coarse = m.Plan(64, 64, 64, ELL, LZ)
     spec = cr.RunSpec(nu=1e-4, nu_h=1e-14, p=8, dt=5e-4, U=(0.0, 1.0, 0.0))
     cr.setup(fine, spec)
@@ -92,11 +94,14 @@ def test_closure_gain_on_held_out_runs():
     assert g_free < 0.8
     assert g_judged <= 1.0 + 1e-12
 
-    # a posteriori: coarse roll-outs of the first held-out run against the truncated fine run
-    sn = runs[6]
-    for name, c in (("plain", None), ("closure", cl)):
-        st = cr.rollout(coarse, spec, sn.psi[0], sn.chi[0], nsnap, every, closure=c)
-        err = [_norm2(p - sn.psi[j], q - sn.chi[j]) / _norm2(sn.psi[j], sn.chi[j]) for j, (p, q) in enumerate(st)]
-        print("roll-out", name, "relative field error", [f"{e:.2e}" for e in err],
-              "judge (calls, fallbacks)", c.stats() if c else None, flush=True)
-        assert all(np.isfinite(e) for e in err)
+    # a posteriori: coarse roll-outs of the held-out runs against the truncated fine runs
+    for ri in (6, 7):
+        sn = runs[ri]
+        for name, c in (("plain", None), ("closure", cl)):
+            st = cr.rollout(coarse, spec, sn.psi[0], sn.chi[0], nsnap, every, closure=c)
+            err = [_norm2(p - sn.psi[j], q - sn.chi[j]) / _norm2(sn.psi[j], sn.chi[j]) for j, (p, q) in enumerate(st)]
+            print("roll-out", ri, name, "relative field error", [f"{e:.2e}" for e in err],
+                  "judge (calls, fallbacks)", c.stats() if c else None, flush=True)
+            assert all(np.isfinite(e) for e in err)
+    for h in (free, cl, fine, coarse):
+        h.close()
