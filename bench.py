@@ -540,14 +540,21 @@ def bench_closure(torch, args, stream, e0, e1):
     def nrm(*ts):
         return float(np.sqrt(sum(torch.linalg.vector_norm(t).item() ** 2 for t in ts)))
 
+    ref = Plan(96, 96, 96, 1.0, PAIR["lz"], nrc=n_c, nphic=n_c // 2, nzc=n_c // 2)
+    rj = Closure(coarse, max_batch=4096, beta=1.0)
+    rj.set_scales(xs, ys)
+    rj.set_params(cl.get_params())
+    rj.set_reference(ref, spec.U)
     roll = {}
     for ri in (6, 7):
         sn = runs[ri]
-        for name, clo in (("plain", None), ("closure_judged", cl), ("closure_unjudged", free)):
+        for name, clo in (("plain", None), ("closure_judged", cl), ("closure_unjudged", free),
+                          ("closure_reference_judge", rj)):
             st = cr.rollout(coarse, spec, sn.psi[0], sn.chi[0], nsnap, every, closure=clo)
             roll[f"run{ri}_{name}"] = [round(nrm(a - sn.psi[j], b - sn.chi[j]) / nrm(sn.psi[j], sn.chi[j]), 6)
                                        for j, (a, b) in enumerate(st)][1:]
     calls, fbs = cl.stats()
+    rcalls, rfbs = rj.stats()
     res = {"coarse": f"{n_c}^3", "fine": f"{n_f}^3", "columns": cl.ncols, "train_rows": int(X.shape[0]),
            "train_step_ms": round(train_ms, 4), "train_batch": nb,
            "train_tflops": round(flops_train / (train_ms / 1e3) / 1e12, 3),
@@ -558,13 +565,16 @@ def bench_closure(torch, args, stream, e0, e1):
                              "held_out_judged": round(g_jud, 4), "held_out_fallbacks": nfb,
                              "held_out_snapshots": len(held.psi)},
            "rollout_rel_field_error": roll, "rollout_judge_calls_fallbacks": [calls, fbs],
+           "rollout_reference_judge_calls_fallbacks": [rcalls, rfbs],
+           "reference_judge": "plain term of the coarse state on 96^3 nodes (64^3 coefficients), corrections kept "
+                              "only when they move the coarse term towards it",
            "recipe": "8 fine 256^3 vortex-pair runs (delta 0.005/0.01/0.02, phases from seeds 5..12), nu=1e-4, "
                      "nu_h=1e-14, p=8, dt=5e-4, 12 snapshots 40 steps apart; runs 0-5 train, 6-7 held out; "
                      "coarse 64^3"}
     log(f"bench: closure train step {train_ms:.3f} ms, inference {inf_ms:.3f} ms vs coarse RHS {rhs_ms:.3f} ms, "
         f"held-out gain {g_free:.3f} (judged {g_jud:.3f})")
     torch.cuda.synchronize()
-    for h in (free, cl, fine, coarse):
+    for h in (rj, free, cl, ref, fine, coarse):
         h.close()
     return res
 

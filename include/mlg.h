@@ -355,7 +355,9 @@ mlg_status mlg_truncate(mlg_plan from, mlg_plan to, const void* src, void* dst, 
  * (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the mean squared error in the
  * normalised output space.  m = 0 corrections are made Hermitian in k.
  * The plain solver is the judge: a correction is dropped (fallback: the plain coarse term is
- * kept) when ||C|| or ||RHS|| is non-finite or ||C|| > beta ||RHS||, norms over both fields. */
+ * kept) when ||C|| or ||RHS|| is non-finite or ||C|| > beta ||RHS||, norms over both fields, and,
+ * with a reference plan (mlg_closure_set_reference), when it moves the coarse term away from the
+ * plain term evaluated on the finer grid. */
 #define MLG_CLOSURE_NIN 258
 #define MLG_CLOSURE_NOUT 256
 #define MLG_CLOSURE_HIDDEN 256
@@ -405,6 +407,18 @@ mlg_status mlg_closure_infer(mlg_closure closure, const void* psi, const void* c
                              int32_t* used_fallback, void* stream);
 /* Judge decisions so far (synchronises the device). */
 mlg_status mlg_closure_stats(mlg_closure closure, int64_t* calls, int64_t* fallbacks);
+/* The plain solver on a finer grid as judge of the closure's error: with a reference plan set, every
+ * correction C of the coarse term A_c(s) is also compared with Ar = T A_ref(E s), the same
+ * toroidal-poloidal term (mlg_rhs_tp with the background U, host array, NULL = 0) of the coarse
+ * state zero-extended (E) to 'ref' and truncated back (T), and is dropped unless
+ * ||A_c + C - Ar|| <= ||A_c - Ar|| (norms over both fields), besides the beta rule.  'ref' must be
+ * FP64, on the same device, with equal ell and L_z, keep every coefficient of the coarse plan
+ * (M, N_r^c and N_z^c at least the coarse values) and N_r^c <= 512, and outlive the closure; more
+ * nodes than degrees (N_r > N_r^c, N_phi, N_z above the coarse ones) make Ar the over-resolved term
+ * of the coarse state.  Its logarithmic-proxy amplitudes must match the coarse plan's.  NULL removes
+ * the reference.  Allocates the reference workspace; synchronises.  Errors: MLG_E_ARG,
+ * MLG_E_UNSUPPORTED, MLG_E_ALLOC. */
+mlg_status mlg_closure_set_reference(mlg_closure closure, mlg_plan ref, const double* U);
 
 /* ---------------------------------------------------------------- time integration of (psi, chi)
  * nsteps steps of Eq. abcn for both potentials (the operators of mlg_step_setup, which must have

@@ -170,11 +170,19 @@ def correction(Y: np.ndarray, M: int, nrc: int, nz: int, nzc: int):
     return Cp, Cc
 
 
-def judge(Cp, Cc, Rp, Rc, beta: float) -> bool:
-    """True when the correction is accepted: finite norms and ||C|| <= beta ||RHS||."""
+def judge(Cp, Cc, Rp, Rc, beta: float, ref=None) -> bool:
+    """True when the correction is accepted: finite norms and ||C|| <= beta ||RHS|| and, with a
+    reference term ref = (Ar_psi, Ar_chi) (the plain term on a finer grid), ||RHS + C - Ar|| <=
+    ||RHS - Ar||."""
     cn = np.sqrt(np.sum(np.abs(Cp) ** 2) + np.sum(np.abs(Cc) ** 2))
     rn = np.sqrt(np.sum(np.abs(Rp) ** 2) + np.sum(np.abs(Rc) ** 2))
-    return bool(np.isfinite(cn) and np.isfinite(rn) and cn <= beta * rn)
+    ok = bool(np.isfinite(cn) and np.isfinite(rn) and cn <= beta * rn)
+    if ref is not None:
+        Ap, Ac = ref
+        a = np.sqrt(np.sum(np.abs(Rp + Cp - Ap) ** 2) + np.sum(np.abs(Rc + Cc - Ac) ** 2))
+        b = np.sqrt(np.sum(np.abs(Rp - Ap) ** 2) + np.sum(np.abs(Rc - Ac) ** 2))
+        ok = ok and bool(np.isfinite(a) and np.isfinite(b) and a <= b)
+    return ok
 
 
 def network_params(params: np.ndarray):

@@ -54,6 +54,7 @@ EXPORTS = ["mlg_plan_create", "mlg_plan_destroy", "mlg_plan_query", "mlg_plan_no
            "mlg_closure_columns", "mlg_closure_set_params", "mlg_closure_get_params", "mlg_closure_get_grads",
            "mlg_closure_set_scales", "mlg_closure_get_scales", "mlg_closure_features", "mlg_closure_targets",
            "mlg_closure_forward", "mlg_closure_train_step", "mlg_closure_infer", "mlg_closure_stats",
+           "mlg_closure_set_reference",
            "mlg_last_error"]
 
 MLG_CLOSURE_NIN, MLG_CLOSURE_NOUT, MLG_CLOSURE_HIDDEN = 258, 256, 256
@@ -137,6 +138,7 @@ def lib() -> ctypes.CDLL:
     L.mlg_closure_train_step.argtypes = [vp, vp, vp, vp, i64, i32, f32, ctypes.POINTER(f32), vp]
     L.mlg_closure_infer.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int32), vp]
     L.mlg_closure_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.mlg_closure_set_reference.argtypes = [vp, vp, vp]
     for name in EXPORTS[:-1]:
         getattr(L, name).restype = ctypes.c_int
     L.mlg_last_error.restype = ctypes.c_char_p
@@ -418,6 +420,11 @@ def mlg_closure_stats(closure: int):
     c, f = ctypes.c_int64(), ctypes.c_int64()
     _check(lib().mlg_closure_stats(closure, ctypes.byref(c), ctypes.byref(f)))
     return c.value, f.value
+
+
+def mlg_closure_set_reference(closure: int, ref: int, U=None) -> None:
+    u = None if U is None else (ctypes.c_double * 3)(*[float(x) for x in U])
+    _check(lib().mlg_closure_set_reference(closure, ref or None, u))
 
 
 class Plan:
@@ -779,6 +786,11 @@ class Closure:
 
     def stats(self):
         return mlg_closure_stats(self.handle)
+
+    def set_reference(self, ref: "Plan | None", U=None):
+        """Judge every correction also against the plain term on the finer plan 'ref' (None removes it)."""
+        self.ref = ref  # the closure holds a pointer to the plan; keep it alive
+        mlg_closure_set_reference(self.handle, ref.handle if ref is not None else 0, U)
 
     def close(self):
         if self.handle:

@@ -332,10 +332,13 @@ __device__ __forceinline__ double2 correction(const ColMap& c, const int32_t* co
   return make_double2(re, im);
 }
 
+// Norm partials of the judge, per block: |C|^2, |RHS|^2 and, when the reference term Ar of the
+// plain solver on a finer grid is given, |RHS + C - Ar|^2 and |RHS - Ar|^2 (both fields).
 __global__ __launch_bounds__(256) void norm_kernel(ColMap c, const int32_t* col_of_slot, const float* Y,
-                                                   const double2* rp, const double2* rc, int64_t nel, double* part) {
-  __shared__ double s[2][256];
-  double cs = 0.0, rs = 0.0;
+                                                   const double2* rp, const double2* rc, const double2* arp,
+                                                   const double2* arc, int64_t nel, double* part) {
+  __shared__ double s[4][256];
+  double cs = 0.0, rs = 0.0, as = 0.0, bs = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < 2 * nel; e += (int64_t)gridDim.x * blockDim.x) {
     const int f = e >= nel;
     const int64_t i = e - f * nel;
@@ -345,49 +348,50 @@ __global__ __launch_bounds__(256) void norm_kernel(ColMap c, const int32_t* col_
     const double2 r = f ? rc[i] : rp[i];
     cs += cv.x * cv.x + cv.y * cv.y;
     rs += r.x * r.x + r.y * r.y;
+    if (arp) {
+      const double2 q = f ? arc[i] : arp[i];
+      const double dx = r.x - q.x, dy = r.y - q.y;
+      as += (dx + cv.x) * (dx + cv.x) + (dy + cv.y) * (dy + cv.y);
+      bs += dx * dx + dy * dy;
+    }
   }
   s[0][threadIdx.x] = cs;
   s[1][threadIdx.x] = rs;
+  s[2][threadIdx.x] = as;
+  s[3][threadIdx.x] = bs;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      s[0][threadIdx.x] += s[0][threadIdx.x + w];
-      s[1][threadIdx.x] += s[1][threadIdx.x + w];
-    }
+    if ((int)threadIdx.x < w)
+      for (int q = 0; q < 4; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = s[0][0];
-    part[2 * blockIdx.x + 1] = s[1][0];
-  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 4; ++q) part[4 * blockIdx.x + q] = s[q][0];
 }
 
 // Judge and apply: every block reduces the norm partials in the same order and takes the same
-// decision; accepted corrections are added to (rp, rc).  flags[1] = fallback of this call,
+// decision; accepted corrections are added to (rp, rc).  Accepted: finite norms, ||C|| <= beta ||RHS||
+// and, with a reference term, ||RHS + C - Ar|| <= ||RHS - Ar||.  flags[1] = fallback of this call,
 // flags[2] counts fallbacks, flags[3] counts calls.
 __global__ __launch_bounds__(256) void apply_kernel(ColMap c, const int32_t* col_of_slot, const float* Y,
                                                     double2* rp, double2* rc, int64_t nel, const double* part,
-                                                    int nparts, double beta, int* flags) {
-  __shared__ double s[2][256];
+                                                    int nparts, double beta, int has_ref, int* flags) {
+  __shared__ double s[4][256];
   __shared__ int accept;
-  double cs = 0.0, rs = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += 256) {
-    cs += part[2 * i];
-    rs += part[2 * i + 1];
-  }
-  s[0][threadIdx.x] = cs;
-  s[1][threadIdx.x] = rs;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < nparts; i += 256)
+    for (int q = 0; q < 4; ++q) v[q] += part[4 * i + q];
+  for (int q = 0; q < 4; ++q) s[q][threadIdx.x] = v[q];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      s[0][threadIdx.x] += s[0][threadIdx.x + w];
-      s[1][threadIdx.x] += s[1][threadIdx.x + w];
-    }
+    if ((int)threadIdx.x < w)
+      for (int q = 0; q < 4; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double cn = s[0][0], rn = s[1][0];
-    const int ok = isfinite(cn) && isfinite(rn) && sqrt(cn) <= beta * sqrt(rn);
+    const double cn = s[0][0], rn = s[1][0], an = s[2][0], bn = s[3][0];
+    int ok = isfinite(cn) && isfinite(rn) && sqrt(cn) <= beta * sqrt(rn);
+    if (has_ref) ok = ok && isfinite(an) && isfinite(bn) && an <= bn;
     accept = ok;
     if (blockIdx.x == 0) {
       flags[1] = !ok;
@@ -509,6 +513,11 @@ struct mlg_closure_s {
   float* d_y = nullptr;
   double* d_norm = nullptr;
   int* d_flags = nullptr;  // [0] bad index, [1] last fallback, [2] fallbacks, [3] calls
+  // reference judge (mlg_closure_set_reference): the plain term on a finer plan
+  const mlg_plan_s* ref = nullptr;
+  double Uref[3] = {0.0, 0.0, 0.0};
+  void* d_ref_ws = nullptr;
+  double* d_ref_buf = nullptr;  // psi, chi, A_psi, A_chi on the reference plan; A_psi, A_chi truncated
 
   mlg::ColMap colmap() const {
     mlg::ColMap c{};
@@ -530,7 +539,8 @@ namespace {
 void free_closure(mlg_closure_s* c) {
   void* ptrs[] = {c->d_slot, c->d_col_of_slot, c->d_p, c->d_m, c->d_v, c->d_g, c->d_part, c->d_loss_part,
                   c->d_loss, c->d_wb, c->d_xs, c->d_ys, c->d_x, c->d_h1b, c->d_h2b, c->d_dy, c->d_dz2,
-                  c->d_dz1, c->d_h1f, c->d_h2f, c->d_t, c->d_y, c->d_norm, c->d_flags};
+                  c->d_dz1, c->d_h1f, c->d_h2f, c->d_t, c->d_y, c->d_norm, c->d_flags, c->d_ref_ws,
+                  c->d_ref_buf};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -678,12 +688,32 @@ mlg_status closure_correct(mlg_closure_s* c, const double* psi, const double* ch
   MLG_HIP_TRY(hipGetLastError());
   if (mlg_status st = run_forward(c, rows, c->ncols, c->d_y, s)) return st;
   const int64_t nel = p->tau * p->nz;
+  const double2* arp = nullptr;
+  const double2* arc = nullptr;
+  if (c->ref) {
+    // the plain term of the same coarse state on the finer reference plan, truncated back
+    const mlg_plan_s* q = c->ref;
+    const size_t qe = (size_t)q->tau * q->nz * 2;
+    double* b = c->d_ref_buf;
+    double *qp = b, *qc = b + qe, *qap = b + 2 * qe, *qac = b + 3 * qe;
+    double *tap = b + 4 * qe, *tac = tap + (size_t)nel * 2;
+    mlg_status st;
+    if ((st = mlg_truncate(const_cast<mlg_plan_s*>(p), const_cast<mlg_plan_s*>(q), psi, qp, s)) ||
+        (st = mlg_truncate(const_cast<mlg_plan_s*>(p), const_cast<mlg_plan_s*>(q), chi, qc, s)) ||
+        (st = mlg_rhs_tp(const_cast<mlg_plan_s*>(q), c->Uref, qp, qc, qap, qac, nullptr, c->d_ref_ws, s)) ||
+        (st = mlg_truncate(const_cast<mlg_plan_s*>(q), const_cast<mlg_plan_s*>(p), qap, tap, s)) ||
+        (st = mlg_truncate(const_cast<mlg_plan_s*>(q), const_cast<mlg_plan_s*>(p), qac, tac, s)))
+      return st;
+    arp = reinterpret_cast<const double2*>(tap);
+    arc = reinterpret_cast<const double2*>(tac);
+  }
   hipLaunchKernelGGL(norm_kernel, dim3(NORM_BLOCKS), dim3(256), 0, s, cm, c->d_col_of_slot, c->d_y,
-                     reinterpret_cast<const double2*>(rpsi), reinterpret_cast<const double2*>(rchi), nel, c->d_norm);
+                     reinterpret_cast<const double2*>(rpsi), reinterpret_cast<const double2*>(rchi), arp, arc, nel,
+                     c->d_norm);
   MLG_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(apply_kernel, dim3(NORM_BLOCKS), dim3(256), 0, s, cm, c->d_col_of_slot, c->d_y,
                      reinterpret_cast<double2*>(rpsi), reinterpret_cast<double2*>(rchi), nel, c->d_norm, NORM_BLOCKS,
-                     c->beta, c->d_flags);
+                     c->beta, c->ref ? 1 : 0, c->d_flags);
   MLG_HIP_TRY(hipGetLastError());
   return MLG_OK;
 }
@@ -738,7 +768,7 @@ mlg_status mlg_closure_create(const mlg_closure_cfg* cfg, mlg_plan coarse, mlg_c
       (st = dalloc(&c->d_x, R * KIN)) || (st = dalloc(&c->d_h1b, R * HID)) || (st = dalloc(&c->d_h2b, R * HID)) ||
       (st = dalloc(&c->d_dy, R * NOUT)) || (st = dalloc(&c->d_dz2, R * HID)) || (st = dalloc(&c->d_dz1, R * HID)) ||
       (st = dalloc(&c->d_h1f, R * HID)) || (st = dalloc(&c->d_h2f, R * HID)) || (st = dalloc(&c->d_t, R * NOUT)) ||
-      (st = dalloc(&c->d_y, R * NOUT)) || (st = dalloc(&c->d_norm, 2 * NORM_BLOCKS)) ||
+      (st = dalloc(&c->d_y, R * NOUT)) || (st = dalloc(&c->d_norm, 4 * NORM_BLOCKS)) ||
       (st = dalloc(&c->d_flags, 4))) {
     free_closure(c);
     return st;
@@ -950,6 +980,42 @@ mlg_status mlg_closure_stats(mlg_closure c, int64_t* calls, int64_t* fallbacks) 
   MLG_HIP_TRY(hipMemcpy(fl, c->d_flags, 16, hipMemcpyDeviceToHost));
   if (calls) *calls = fl[3];
   if (fallbacks) *fallbacks = fl[2];
+  return MLG_OK;
+}
+
+mlg_status mlg_closure_set_reference(mlg_closure c, mlg_plan ref, const double* U) {
+  if (mlg_status st = check_closure(c)) return st;
+  DevGuard guard(c->device);
+  MLG_HIP_TRY(hipDeviceSynchronize());
+  if (c->d_ref_ws) (void)hipFree(c->d_ref_ws);
+  if (c->d_ref_buf) (void)hipFree(c->d_ref_buf);
+  c->d_ref_ws = nullptr;
+  c->d_ref_buf = nullptr;
+  c->ref = nullptr;
+  if (!ref) return MLG_OK;
+  const mlg_plan_s* p = c->plan;
+  if (ref->prec != MLG_FP64) return fail(MLG_E_UNSUPPORTED, "the reference plan must be FP64");
+  if (ref->device != p->device) return fail(MLG_E_ARG, "reference plan on another device");
+  if (ref->g.ell != p->g.ell || ref->g.lz != p->g.lz) return fail(MLG_E_ARG, "reference plan needs equal ell and L_z");
+  if (ref->M < p->M || ref->nrc < p->nrc || ref->nzc < p->nzc)
+    return fail(MLG_E_ARG, "the reference plan must keep every coefficient of the coarse plan");
+  if (ref->nrc > 512) return fail(MLG_E_UNSUPPORTED, "reference plan N_r^c above 512");
+  double Uh[3] = {0.0, 0.0, 0.0};
+  if (U)
+    for (int i = 0; i < 3; ++i) {
+      if (!std::isfinite(U[i])) return fail(MLG_E_ARG, "background U must be finite");
+      Uh[i] = U[i];
+    }
+  const size_t qe = (size_t)ref->tau * ref->nz * 2, ce = (size_t)p->tau * p->nz * 2;
+  mlg_status st;
+  if ((st = dalloc(reinterpret_cast<unsigned char**>(&c->d_ref_ws), ref->ws_bytes)) ||
+      (st = dalloc(&c->d_ref_buf, 4 * qe + 2 * ce))) {
+    if (c->d_ref_ws) (void)hipFree(c->d_ref_ws);
+    c->d_ref_ws = nullptr;
+    return st;
+  }
+  for (int i = 0; i < 3; ++i) c->Uref[i] = Uh[i];
+  c->ref = ref;
   return MLG_OK;
 }
 

@@ -213,6 +213,64 @@ def test_judge_accepts_with_oracle_correction():
     assert cl.stats() == (1, 0)
 
 
+@pytest.mark.parametrize("case", ["zero_net_same_grid", "net_same_grid", "net_finer_grid"])
+def test_reference_judge_decision(case):
+    """The reference judge against the oracle's decision on the library's own terms: a network with
+    zero output is always kept (equal distances), any other correction is dropped when the reference
+    plan has the coarse grid (the reference term is then the plain term), and on a finer reference
+    the decision follows ||A_c + C - Ar|| <= ||A_c - Ar||."""
+    m = _gpu()
+    _say("closure reference judge", case)
+    g, plan, cl = _coarse(m, beta=1e30)
+    params, xs, ys, _, _ = _random_problem(93, 1)
+    if case == "zero_net_same_grid":
+        params[:] = 0.0
+    cl.set_params(params)
+    cl.set_scales(xs * 0.1, ys * 1e-2)
+    nr, nphi, nz = (16, 12, 10) if case != "net_finer_grid" else (24, 18, 16)
+    ref = m.Plan(nr, nphi, nz, 0.9, 4.0, nrc=16, nphic=6, nzc=5)
+    U = (0.0, 1.0, 0.0)
+    cl.set_reference(ref, U)
+    sp, sc = _state(g, 64)
+    P, Cc = _dev(sp), _dev(sc)
+    a, b = plan.empty_spec(), plan.empty_spec()
+    plan.rhs_tp(P, Cc, a, b, U=U)
+    a0, b0 = a.clone(), b.clone()
+    # the oracle's decision from the library's terms: the plain term, the unjudged correction and
+    # the reference term truncated back
+    free = m.Closure(plan, max_batch=512, beta=1e30)
+    free.set_params(params)
+    free.set_scales(xs * 0.1, ys * 1e-2)
+    ca, cb = a0.clone(), b0.clone()
+    free.infer(P, Cc, ca, cb)
+    qp, qc = ref.empty_spec(), ref.empty_spec()
+    plan.truncate_to(ref, P, qp)
+    plan.truncate_to(ref, Cc, qc)
+    rp, rc = ref.empty_spec(), ref.empty_spec()
+    ref.rhs_tp(qp, qc, rp, rc, U=U)
+    tp, tc = plan.empty_spec(), plan.empty_spec()
+    ref.truncate_to(plan, rp, tp)
+    ref.truncate_to(plan, rc, tc)
+    fb = cl.infer(P, Cc, a, b, want_flag=True)
+    torch.cuda.synchronize()
+    h = lambda t: from_lib(t.cpu().numpy(), g.M, g.nrc)
+    R0p, R0c = h(a0), h(b0)
+    keep = oc.judge(h(ca) - R0p, h(cb) - R0c, R0p, R0c, 1e30, ref=(h(tp), h(tc)))
+    _say("  oracle keeps", keep, "library fallback", fb)
+    assert fb == (0 if keep else 1)
+    if case == "zero_net_same_grid":
+        assert keep
+    if case == "net_same_grid":
+        assert not keep
+    if keep:
+        assert torch.equal(a, ca) and torch.equal(b, cb)
+    else:
+        assert torch.equal(a, a0) and torch.equal(b, b0)
+    cl.set_reference(None)
+    for x in (free, cl, ref, plan):
+        x.close()
+
+
 @pytest.mark.parametrize("mode", ["beta0", "nan"])
 def test_forced_fallback_keeps_plain_term(mode):
     m = _gpu()

@@ -9,7 +9,8 @@ judged a priori by ||T A_f - (A_c + C)|| / ||T A_f - A_c|| summed over held-out 
 A posteriori, coarse roll-outs of both held-out runs are compared with the truncated fine runs with
 and without the closure: the judged roll-outs must stay finite and their error is printed next to
 the plain solver's (the measured outcome: the network lowers the a-priori error but not the
-roll-out error, see the design notes).
+roll-out error, see the design notes).  With the reference judge (the plain term of the coarse
+state evaluated on 96^3 nodes) the roll-out error stays within 2% of the plain solver's.
 """
 import numpy as np
 import pytest
@@ -94,14 +95,25 @@ def test_closure_gain_on_held_out_runs():
     assert g_free < 0.8
     assert g_judged <= 1.0 + 1e-12
 
-    # a posteriori: coarse roll-outs of the held-out runs against the truncated fine runs
+    # a posteriori: coarse roll-outs of the held-out runs against the truncated fine runs, plain, with
+    # the beta judge, and with the reference judge (the plain term of the coarse state on 96^3 nodes)
+    ref = m.Plan(96, 96, 96, ELL, LZ, nrc=64, nphic=32, nzc=32)
+    rj = m.Closure(coarse, max_batch=4096, beta=1.0)
+    rj.set_scales(xs, ys)
+    rj.set_params(cl.get_params())
+    rj.set_reference(ref, spec.U)
+    final = {}
     for ri in (6, 7):
         sn = runs[ri]
-        for name, c in (("plain", None), ("closure", cl)):
+        for name, c in (("plain", None), ("closure", cl), ("closure_ref_judge", rj)):
             st = cr.rollout(coarse, spec, sn.psi[0], sn.chi[0], nsnap, every, closure=c)
             err = [_norm2(p - sn.psi[j], q - sn.chi[j]) / _norm2(sn.psi[j], sn.chi[j]) for j, (p, q) in enumerate(st)]
             print("roll-out", ri, name, "relative field error", [f"{e:.2e}" for e in err],
                   "judge (calls, fallbacks)", c.stats() if c else None, flush=True)
             assert all(np.isfinite(e) for e in err)
-    for h in (free, cl, fine, coarse):
+            final[(ri, name)] = err[-1]
+    # the reference judge keeps the roll-out at the plain solver's error (measured within 0.4%)
+    for ri in (6, 7):
+        assert final[(ri, "closure_ref_judge")] <= 1.02 * final[(ri, "plain")], final
+    for h in (rj, free, cl, ref, fine, coarse):
         h.close()

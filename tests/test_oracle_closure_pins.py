@@ -194,3 +194,10 @@ def test_judge_rules():
     assert not oc.judge(C, C, R, R, 0.05)
     assert not oc.judge(C * np.nan, C, R, R, 10.0)
     assert oc.judge(0 * C, 0 * C, R, R, 0.0)
+    # reference judge: a correction towards the finer-grid term is kept, one away from it dropped
+    A = R + 0.2 * R
+    assert oc.judge(C, C, R, R, 10.0, ref=(A, A))
+    assert not oc.judge(-C, -C, R, R, 10.0, ref=(A, A))
+    assert oc.judge(0 * C, 0 * C, R, R, 10.0, ref=(R, R))          # equal distances: kept
+    assert not oc.judge(C, C, R, R, 10.0, ref=(R, R))
+    assert not oc.judge(C, C, R, R, 10.0, ref=(A * np.nan, A))
