@@ -450,6 +450,45 @@ def bench_time_step(torch, plan, psi, chi, args, stream, e0, e1):
     return res
 
 
+def bench_closure_cost(torch, args, stream, e0, e1):
+    """Cost of the closure's kernels alone (for profiling): training steps of 4096 rows and inferences
+    on the 64^3 coarse grid, with random data and weights (no fine runs)."""
+    import synth
+    from paper_2609_18026_amd import Closure, Plan
+    coarse = Plan(64, 64, 64, 1.0, PAIR["lz"])
+    cl = Closure(coarse, max_batch=4096, beta=1e30)
+    r = np.random.default_rng(7)
+    rows = 4 * 4096
+    X = torch.from_numpy(r.standard_normal((rows, 258)).astype(np.float32)).cuda()
+    Y = torch.from_numpy(r.standard_normal((rows, 256)).astype(np.float32)).cuda()
+    cl.set_params(synth.closure_init(1))
+    batches = torch.from_numpy(synth.batch_indices(rows, 4096, args.steps + args.warmup, seed=3)).cuda()
+    for s_ in range(args.warmup):
+        cl.train_step(X, Y, batches[s_], 4096, 1e-4)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for s_ in range(args.steps):
+        cl.train_step(X, Y, batches[args.warmup + s_], 4096, 1e-4)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1) / args.steps
+    _, psi, chi = build_state(coarse, 64, torch)
+    Np, Nc = coarse.empty_spec(), coarse.empty_spec()
+    coarse.rhs_tp(psi, chi, Np, Nc, U=U_FRAME)
+    e0.record(stream)
+    for _ in range(args.steps):
+        cl.infer(psi, chi, Np, Nc)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    inf_ms = e0.elapsed_time(e1) / args.steps
+    flops = 3 * 2.0 * 4096 * (288 * 256 + 256 * 256 + 256 * 256)
+    cl.close()
+    coarse.close()
+    log(f"bench: closure train step {train_ms:.3f} ms, inference {inf_ms:.3f} ms (random data)")
+    return {"train_step_ms": round(train_ms, 4), "train_tflops": round(flops / (train_ms / 1e3) / 1e12, 3),
+            "infer_ms": round(inf_ms, 4)}
+
+
 def bench_closure(torch, args, stream, e0, e1):
     """Learned closure at the coarse 64^3 grid: cost of a training step (4096 columns) and of an
     inference next to the coarse RHS, then the held-out gain of a network trained on fine 256^3
@@ -588,6 +627,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure section")
+    ap.add_argument("--sections", default="all",
+                    help="comma list of the sections after the headline RHS and transform pair to run: split, "
+                         "batched, step, closure, closure_cost (training and inference cost on random data "
+                         "only, for profiling), small (and the oracle leg); default all but closure_cost")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain device copy of 256 MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -701,17 +744,26 @@ def main():
         "transform_pair": {"ms": round(pair_ms, 4), "gdofs": round(n ** 3 / (pair_ms / 1e3) / 1e9, 4)},
         "hbm_copy_reference": copy_ref,
     }
+    sections = set(args.sections.split(",")) if args.sections != "all" else None
+    want = lambda name: (sections is None and name != "closure_cost") or (sections is not None and name in sections)
     # split-bfloat16 products on the same state: time, and the errors against the FP64 result
-    out["split_bf16"] = bench_split(torch, plan, psi, chi, po, co, phys, spec, args, stream, e0, e1)
-    out["split_bf16"]["fp64_ms_per_step"] = round(ms, 4)
-    out["batched_2d"] = bench_batched(torch, args, stream, e0, e1)
-    out["time_step"] = bench_time_step(torch, plan, psi, chi, args, stream, e0, e1)
-    if not args.no_closure:
+    if want("split"):
+        out["split_bf16"] = bench_split(torch, plan, psi, chi, po, co, phys, spec, args, stream, e0, e1)
+        out["split_bf16"]["fp64_ms_per_step"] = round(ms, 4)
+    if want("batched"):
+        out["batched_2d"] = bench_batched(torch, args, stream, e0, e1)
+    if want("step"):
+        out["time_step"] = bench_time_step(torch, plan, psi, chi, args, stream, e0, e1)
+    if want("closure") and not args.no_closure:
         out["closure"] = bench_closure(torch, args, stream, e0, e1)
+    if want("closure_cost"):
+        out["closure_cost"] = bench_closure_cost(torch, args, stream, e0, e1)
     torch.cuda.synchronize()
     plan.close()                 # every native handle is released before the interpreter shuts down
-    gpu_small, out["small_workloads"] = bench_small(torch, args, stream, e0, e1)
-    if not args.no_cpu_baseline:
+    gpu_small = None
+    if want("small"):
+        gpu_small, out["small_workloads"] = bench_small(torch, args, stream, e0, e1)
+    if not args.no_cpu_baseline and gpu_small is not None:
         log("bench: timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample, gpu_small)
         out["rel_err_vs_fp64_oracle"] = out["cpu_baseline"]["parity"]
