@@ -39,27 +39,31 @@ U_FRAME = (0.0, 1.0, 0.0)
 # kernel source hashes to the one that was measured (profiles/rhs_tp_256cubed_kernels.md).
 _SUMMARY = "profiles/rhs_tp_256cubed_kernels.md"
 MEASURED_TRAFFIC = {
-    "synth_gemm": {"bytes": 1234839552, "launches": 1, "n": 256,
+    "synth_gemm": {"bytes": 1230354309, "launches": 1, "n": 256,
                    "source": "paper_2609_18026_amd/csrc/gemm_fold.hip",
-                   "sha256": "84d4cf04f47c93362325ec24de02171f7176c99070f937db2417af6cecfdbaac"},
-    "proj_gemm": {"bytes": 433386496, "launches": 1, "n": 256,
+                   "sha256": "84d4cf04f47c93362325ec24de02171f7176c99070f937db2417af6cecfdbaac",
+                   "profile_avg_ms": 0.5847, "mfma_counter_flops": 23.49e9, "mfma_busy_pct": 57.1},
+    "proj_gemm": {"bytes": 435622755, "launches": 1, "n": 256,
                   "source": "paper_2609_18026_amd/csrc/gemm_fold.hip",
-                  "sha256": "84d4cf04f47c93362325ec24de02171f7176c99070f937db2417af6cecfdbaac"},
-    "phi_fft": {"bytes": 1208582144, "launches": 1, "n": 256,
+                  "sha256": "84d4cf04f47c93362325ec24de02171f7176c99070f937db2417af6cecfdbaac",
+                  "profile_avg_ms": 0.2934, "mfma_counter_flops": 9.92e9, "mfma_busy_pct": 47.6},
+    "phi_fft": {"bytes": 1208585854, "launches": 1, "n": 256,
                 "source": "paper_2609_18026_amd/csrc/fft256.hip",
-                "sha256": "93a06b07484b790647c3f80faaeb11a12efd4b135ae8bd5e55a626eb1f9e92f9"},
-    "z_fft": {"bytes": 1610762240 + 541220864, "launches": 2, "n": 256,
+                "sha256": "93a06b07484b790647c3f80faaeb11a12efd4b135ae8bd5e55a626eb1f9e92f9",
+                "profile_avg_ms": 0.3400},
+    "z_fft": {"bytes": 1610641118 + 541195848, "launches": 2, "n": 256,
               "source": "paper_2609_18026_amd/csrc/fft256.hip",
               "sha256": "93a06b07484b790647c3f80faaeb11a12efd4b135ae8bd5e55a626eb1f9e92f9"},
-    "projection": {"bytes": 740914176, "launches": 1, "n": 256,
+    "projection": {"bytes": 740674066, "launches": 1, "n": 256,
                    "source": "paper_2609_18026_amd/csrc/kernels.hip",
-                   "sha256": "b3d0e4ee5e82d90e8185f96d07d59ea7c3e73802f459cf2275982a4f070f1e40"},
+                   "sha256": "86025379f5b0d354ca6fb9eba0a3cbbb53175d90075106a221c6c89107e2c08a",
+                   "profile_avg_ms": 0.2013},
 }
 
 
-def measured_traffic(kernel, n, per_launch=True):
-    """Measured HBM bytes of a kernel family (per launch, or per RHS step), or None when no record
-    matches the current source."""
+def measured_record(kernel, n):
+    """The profiled record of a kernel family (profiles/rhs_tp_256cubed_kernels.md) while its source
+    hashes to the one that was measured, else None."""
     import hashlib
     rec = MEASURED_TRAFFIC.get(kernel)
     if not rec or rec["n"] != n:
@@ -69,6 +73,15 @@ def measured_traffic(kernel, n, per_launch=True):
             if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
                 return None
     except OSError:
+        return None
+    return rec
+
+
+def measured_traffic(kernel, n, per_launch=True):
+    """Measured HBM bytes of a kernel family (per launch, or per RHS step), or None when no record
+    matches the current source."""
+    rec = measured_record(kernel, n)
+    if rec is None:
         return None
     return rec["bytes"] / rec["launches"] if per_launch else rec["bytes"]
 
@@ -715,6 +728,14 @@ def main():
                         frac=d["frac_fp64_peak"], traffic=measured_traffic(dom, n),
                         algorithmic_bytes_per_launch=work[dom]["bytes"],
                         work_per_launch=work[dom]["flops"] * args.steps / launches, avg_launch_ms=d["avg_launch_ms"])
+        rec = measured_record(dom, n)
+        if rec is not None and "profile_avg_ms" in rec:
+            wl = work[dom]["flops"] * args.steps / launches
+            roofline["profile"] = {"avg_launch_ms": rec["profile_avg_ms"],
+                                   "frac": round(wl / (rec["profile_avg_ms"] / 1e3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+                                   "mfma_counter_flops": rec.get("mfma_counter_flops"),
+                                   "mfma_busy_pct": rec.get("mfma_busy_pct"),
+                                   "source": _SUMMARY}
     else:
         launches = max(kern[dom][1], 1)
         roofline = dict(bound="hbm", kernel=dom, achieved=d["gbs"], peak=PEAK_HBM_GBS, unit="GB/s",
