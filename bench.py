@@ -6,7 +6,7 @@ Galerkin projection and the per-(m, k) elliptic solves (the whole transform roun
 plus the nonlinear term).  value = N_r N_phi N_z / (seconds per step) / 1e9 [GDOF/s].
 
 Further sections of the same JSON line: per-kernel times and roofline fractions, the transform
-pair, the split-bfloat16 RHS with its error, the batched 2D launch, whole AB-CN time steps, the
+pair, the FP32 and split-bfloat16 RHS (float data) with their bytes and errors, the batched 2D launch, whole AB-CN time steps, the
 learned closure (training / inference cost, held-out gain, roll-outs) and the oracle timed on
 the host.  --gpus N with N > 1 exits: the benchmark runs on exactly one GPU.
 """
@@ -297,78 +297,131 @@ def bench_batched(torch, args, stream, e0, e1, count=64, seed=3):
     return res
 
 
-def bench_split(torch, plan, psi, chi, po, co, phys, spec, args, stream, e0, e1):
-    """MLG_SPLIT_BF16 plan on the same state: RHS and transform-pair times beside FP64, and the errors
-    against the FP64 library result (itself within 1e-12 of the oracle): the nodal taps u, omega, N
+def reduced_work(nr, nphi, nz, M, nrc):
+    """Algorithmic HBM bytes per RHS step of each kernel family on a reduced-precision plan: float
+    data and intermediates (8-byte complex), 4-byte synthesis tables (FP32, or bfloat16 hi + lo),
+    FP64 projection tables and sources."""
+    tau = sum(max(nrc - m, 0) for m in range(M))
+    mmax, nkact = active_columns(nphi, nz, M, nrc)
+    tau_a = sum(max(nrc - m, 0) for m in range(mmax))
+    mixed = M * nr * nz * 8
+    f = 0.5 if nr % 2 == 0 else 1.0
+    return {"synth_gemm": f * 2 * tau * nr * 4 + 2 * tau * nz * 8 + 6 * mixed,
+            "proj_gemm": f * 2 * tau_a * nr * 8 + 3 * mmax * nr * nkact * 8 + 3 * tau_a * nkact * 16,
+            "phi_fft": 9 * mixed,
+            "z_fft": 6 * 2 * mixed + 3 * 2 * mmax * nr * nz * 8,
+            "projection": 3 * tau_a * nkact * 16 + 2 * tau * nz * 8}
+
+
+def bench_reduced(torch, prec, plan, psi, chi, fp64_kernels, args, stream, e0, e1):
+    """An MLG_FP32 or MLG_SPLIT_BF16 plan (float data) on the same state rounded to complex64: RHS and
+    transform-pair times and per-kernel times beside FP64, the algorithmic bytes of both, and the
+    errors against the FP64 library result on the same rounded inputs (that result is itself within
+    1e-12 of the oracle), so that they are the reduced arithmetic's own: the nodal taps u, omega, N
     and the sources C, K, Zhat, the output coefficients, and the velocity V(psi_N, chi_N) they
     represent (plain and area-weighted node norms, and relative to the nodal N)."""
-    from paper_2609_18026_amd import MLG_SPLIT_BF16, Plan
+    from paper_2609_18026_amd import MLG_FP32, Plan, mlg_timing_enable, mlg_timing_read
+    name = "fp32" if prec == MLG_FP32 else "split-bf16"
     n = plan.nr
     pe = plan.layout.phys_elems
     se = plan.layout.spec_elems
-    splan = Plan(n, n, n, 1.0, PAIR["lz"], dealias=1, prec=MLG_SPLIT_BF16)
-    sp, sc = splan.empty_spec(), splan.empty_spec()
+    rp = Plan(n, n, n, 1.0, PAIR["lz"], dealias=1, prec=prec)
+    p32, c32 = psi.to(torch.complex64), chi.to(torch.complex64)
+    psi_r, chi_r = p32.to(torch.complex128), c32.to(torch.complex128)   # the rounded state in FP64
+    sp, sc = rp.empty_spec(), rp.empty_spec()
     for _ in range(args.warmup):
-        splan.rhs_tp(psi, chi, sp, sc, U=U_FRAME)
+        rp.rhs_tp(p32, c32, sp, sc, U=U_FRAME)
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(args.steps):
-        splan.rhs_tp(psi, chi, sp, sc, U=U_FRAME)
+        rp.rhs_tp(p32, c32, sp, sc, U=U_FRAME)
     e1.record(stream)
     torch.cuda.synchronize()
-    sms = e0.elapsed_time(e1) / args.steps
-    sphys, sspec = splan.empty_phys(), splan.empty_spec()
-    splan.backward(psi, sphys)
+    rms = e0.elapsed_time(e1) / args.steps
+    families = ["synth_gemm", "proj_gemm", "phi_fft", "z_fft", "projection", "radial_gemm"]
+    mlg_timing_enable(rp.handle, True)
+    for f in families:
+        mlg_timing_read(rp.handle, f)
+    for _ in range(args.steps):
+        rp.rhs_tp(p32, c32, sp, sc, U=U_FRAME)
+    torch.cuda.synchronize()
+    kern = {f: mlg_timing_read(rp.handle, f) for f in families}
+    mlg_timing_enable(rp.handle, False)
+    bytes_r = reduced_work(n, n, n, plan.layout.M, plan.layout.nrc)
+    bytes_64 = {f: w["bytes"] for f, w in kernel_work(n, n, n, plan.layout.M, plan.layout.nrc).items()}
+    per_kernel = {}
+    for f in families[:5]:
+        t = kern[f][0] / args.steps
+        per_kernel[f] = {"ms_per_step": round(t, 4), "fp64_ms_per_step": fp64_kernels[f]["ms_per_step"],
+                         "algorithmic_bytes_per_step": bytes_r[f], "fp64_algorithmic_bytes_per_step": bytes_64[f],
+                         "gbs": round(bytes_r[f] / (t / 1e3) / 1e9, 1) if t > 0 else None}
+    # transform pair (float physical field)
+    rphys, rspec = rp.empty_phys(), rp.empty_spec()
+    rp.backward(p32, rphys)
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(args.steps):
-        splan.backward(psi, sphys)
-        splan.forward(sphys, sspec)
+        rp.backward(p32, rphys)
+        rp.forward(rphys, rspec)
     e1.record(stream)
     torch.cuda.synchronize()
-    spair_ms = e0.elapsed_time(e1) / args.steps
-    perr = float(torch.linalg.vector_norm(sphys - phys) / torch.linalg.vector_norm(phys))
-    serr = float(torch.linalg.vector_norm(sspec - spec) / torch.linalg.vector_norm(spec))
-    del sphys, sspec
-    # taps of both plans
-    t64, tsp = plan.taps_buffer(), splan.taps_buffer()
-    a, b = plan.empty_spec(), plan.empty_spec()
-    plan.rhs_tp(psi, chi, a, b, U=U_FRAME, taps=t64)
-    splan.rhs_tp(psi, chi, sp, sc, U=U_FRAME, taps=tsp)
-    torch.cuda.synchronize()
-    torch.cuda.synchronize()
-    splan.close()
+    pair_ms = e0.elapsed_time(e1) / args.steps
     rel = lambda x, y: float(torch.linalg.vector_norm(x - y) / torch.linalg.vector_norm(y))
-    taps = {"u": rel(tsp[:3 * pe], t64[:3 * pe]), "omega": rel(tsp[3 * pe:6 * pe], t64[3 * pe:6 * pe]),
-            "N": rel(tsp[6 * pe:9 * pe], t64[6 * pe:9 * pe])}
+    # FP64 references on the rounded inputs
+    phys64, spec64 = plan.empty_phys(), plan.empty_spec()
+    plan.backward(psi_r, phys64)
+    plan.forward(rphys.to(torch.float64), spec64)
+    torch.cuda.synchronize()
+    perr = rel(rphys.to(torch.float64), phys64)
+    serr = rel(rspec.to(torch.complex128), spec64)
+    del rphys, rspec, phys64, spec64
+    t64, tr = plan.taps_buffer(), rp.taps_buffer()
+    a, b = plan.empty_spec(), plan.empty_spec()
+    plan.rhs_tp(psi_r, chi_r, a, b, U=U_FRAME, taps=t64)
+    rp.rhs_tp(p32, c32, sp, sc, U=U_FRAME, taps=tr)
+    torch.cuda.synchronize()
+    rp.close()
+    taps = {"u": rel(tr[:3 * pe], t64[:3 * pe]), "omega": rel(tr[3 * pe:6 * pe], t64[3 * pe:6 * pe]),
+            "N": rel(tr[6 * pe:9 * pe], t64[6 * pe:9 * pe])}
     for j, nm in enumerate(("C", "K", "Zhat")):
         o = 9 * pe + 2 * j * se
-        taps[nm] = rel(tsp[o:o + 2 * se], t64[o:o + 2 * se])
+        taps[nm] = rel(tr[o:o + 2 * se], t64[o:o + 2 * se])
+    Nn = t64[6 * pe:9 * pe].view(3, n, n, n).clone()
+    del t64, tr
+    spd, scd = sp.to(torch.complex128), sc.to(torch.complex128)
     uw_ref = torch.empty(6 * pe, dtype=torch.float64, device="cuda")
-    uw_spl = torch.empty_like(uw_ref)
-    plan.synthesize(po, co, uw_ref)
-    plan.synthesize(sp, sc, uw_spl)
+    uw_red = torch.empty_like(uw_ref)
+    plan.synthesize(a, b, uw_ref)
+    plan.synthesize(spd, scd, uw_red)
     torch.cuda.synchronize()
     x, w, r = plan.nodes()
     area = torch.from_numpy(w / (1 - x) ** 2).cuda()
     vr = uw_ref[:3 * pe].view(3, n, n, n)
-    vs = uw_spl[:3 * pe].view(3, n, n, n)
+    vs = uw_red[:3 * pe].view(3, n, n, n)
     d2 = ((vs - vr) ** 2).sum(dim=(0, 1, 3))
     r2 = (vr ** 2).sum(dim=(0, 1, 3))
-    Nn = t64[6 * pe:9 * pe].view(3, n, n, n)
     n2 = (Nn ** 2).sum(dim=(0, 1, 3))
     vel = {"plain": rel(vs, vr), "area_weighted": float(torch.sqrt((d2 * area).sum() / (r2 * area).sum())),
            "plain_rel_to_N": float(torch.sqrt(d2.sum() / n2.sum())),
            "area_weighted_rel_to_N": float(torch.sqrt((d2 * area).sum() / (n2 * area).sum()))}
-    res = {"ms_per_step": round(sms, 4), "fp64_ms_per_step": None, "gdofs": round(n ** 3 / (sms / 1e3) / 1e9, 4),
-           "stages": "split: synthesis products, inverse z DFT products, transform-pair products; FP64: phi FFTs, "
-                     "cross product, forward z, projection sources, solves",
-           "rel_err_vs_fp64": {"velocity_of_output": vel, "psi_coefficients": rel(sp, po), "chi_coefficients": rel(sc, co),
-                               "taps": taps},
-           "transform_pair_ms": round(spair_ms, 4), "transform_pair_gdofs": round(n ** 3 / (spair_ms / 1e3) / 1e9, 4),
+    res = {"ms_per_step": round(rms, 4), "gdofs": round(n ** 3 / (rms / 1e3) / 1e9, 4),
+           "algorithmic_bytes_per_step": sum(bytes_r.values()),
+           "fp64_algorithmic_bytes_per_step": sum(bytes_64.values()),
+           "data": "float / complex64 arrays; the state is the FP64 state rounded to complex64",
+           "stages": ("FP32 MFMA" if prec == MLG_FP32 else "split bfloat16 MFMA (hi/lo, FP32 accumulation)") +
+                     ": synthesis and transform-pair radial products" +
+                     ("" if prec == MLG_FP32 else ", inverse z DFT products") +
+                     "; FP64 arithmetic on float-stored data: phi FFTs, cross product, z FFTs; FP64: projection "
+                     "source products and solves",
+           "kernels": per_kernel,
+           "rel_err_vs_fp64_same_inputs": {"velocity_of_output": vel, "psi_coefficients": rel(spd, a),
+                                           "chi_coefficients": rel(scd, b), "taps": taps},
+           "input_rounding_rel": rel(psi_r, psi),
+           "transform_pair_ms": round(pair_ms, 4), "transform_pair_gdofs": round(n ** 3 / (pair_ms / 1e3) / 1e9, 4),
            "rel_err_pair_backward_vs_fp64": perr, "rel_err_pair_forward_vs_fp64": serr}
-    log(f"bench: split-bf16 {sms:.3f} ms/step, velocity rel err {vel['plain']:.2e} (area {vel['area_weighted']:.2e}, "
-        f"vs |N| {vel['plain_rel_to_N']:.2e}); taps {taps}; pair {spair_ms:.3f} ms, rel err {perr:.2e} / {serr:.2e}")
+    log(f"bench: {name} {rms:.3f} ms/step, velocity rel err {vel['plain']:.2e} (area {vel['area_weighted']:.2e}, "
+        f"vs |N| {vel['plain_rel_to_N']:.2e}); taps {taps}; pair {pair_ms:.3f} ms, rel err {perr:.2e} / {serr:.2e}; "
+        f"kernels {per_kernel}")
     return res
 
 
@@ -641,7 +694,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure section")
     ap.add_argument("--sections", default="all",
-                    help="comma list of the sections after the headline RHS and transform pair to run: split, "
+                    help="comma list of the sections after the headline RHS and transform pair to run: fp32, split, "
                          "batched, step, closure, closure_cost (training and inference cost on random data "
                          "only, for profiling), small (and the oracle leg); default all but closure_cost")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -767,9 +820,14 @@ def main():
     }
     sections = set(args.sections.split(",")) if args.sections != "all" else None
     want = lambda name: (sections is None and name != "closure_cost") or (sections is not None and name in sections)
-    # split-bfloat16 products on the same state: time, and the errors against the FP64 result
+    # reduced-precision plans on the same state: time, bytes, and the errors against the FP64 result
+    if want("fp32"):
+        from paper_2609_18026_amd import MLG_FP32
+        out["fp32"] = bench_reduced(torch, MLG_FP32, plan, psi, chi, per_kernel, args, stream, e0, e1)
+        out["fp32"]["fp64_ms_per_step"] = round(ms, 4)
     if want("split"):
-        out["split_bf16"] = bench_split(torch, plan, psi, chi, po, co, phys, spec, args, stream, e0, e1)
+        from paper_2609_18026_amd import MLG_SPLIT_BF16
+        out["split_bf16"] = bench_reduced(torch, MLG_SPLIT_BF16, plan, psi, chi, per_kernel, args, stream, e0, e1)
         out["split_bf16"]["fp64_ms_per_step"] = round(ms, 4)
     if want("batched"):
         out["batched_2d"] = bench_batched(torch, args, stream, e0, e1)

@@ -20,8 +20,9 @@
  *  - One plan may be used from one stream at a time; concurrent streams need their
  *    own workspace buffers.
  *
- * Data layouts (plans: real = double, complex = interleaved double pair; FP32 batches:
- * float / interleaved float pair)
+ * Data layouts (MLG_FP64 plans: real = double, complex = interleaved double pair; MLG_FP32
+ * and MLG_SPLIT_BF16 plans and FP32 batches: float / interleaved float pair; real_bytes of
+ * mlg_plan_query says which)
  *  - physical field: real [N_z][N_r][N_phi], element (l, i, j) = s(r_i, phi_j, z_l),
  *    r_i ascending (x_i the Gauss-Legendre nodes, r = ell sqrt((1+x)/(1-x)), Eq. map),
  *    phi_j = 2 pi j / N_phi, z_l = L_z l / N_z.
@@ -57,17 +58,26 @@ typedef enum {
 
 typedef enum {
   MLG_FP64 = 0,        /* double data, FP64 arithmetic (MFMA f64 for the radial products)    */
-  MLG_FP32 = 1,        /* batches only: float data and streamed tables (built in FP64),       */
-                       /* FP32 arithmetic                                                    */
-  MLG_SPLIT_BF16 = 2   /* plans only: double data; the radial products of the transform pair, */
-                       /* the scalar RHS and the vector synthesis, and for N_z = 256 their    */
-                       /* z transforms as two radix-16 DFT products, on MFMA with hi/lo       */
-                       /* bfloat16 operands and FP32 accumulation (a_hi b_hi + a_hi b_lo +    */
-                       /* a_lo b_hi); the phi FFTs, pointwise products, the projection's      */
-                       /* forward z transforms, source products and solves stay FP64 (the   */
-                       /* solves are ill-conditioned along far-field directions and would     */
-                       /* amplify reduced-precision source errors)                            */
+  MLG_FP32 = 1,        /* float data.  Batches: streamed tables (built in FP64), FP32        */
+                       /* arithmetic.  Plans: the radial products of the transform pair, the */
+                       /* scalar RHS and the vector synthesis on FP32 MFMA with FP32 tables   */
+                       /* (built in FP64); the FFTs and pointwise products in FP64 arithmetic */
+                       /* on float-stored intermediates; the projection's source products    */
+                       /* and solves in FP64 (they read the float-stored N and are ill-      */
+                       /* conditioned along far-field directions, so reduced-precision       */
+                       /* products there would be amplified)                                 */
+  MLG_SPLIT_BF16 = 2   /* plans only, float data: the radial products of the transform pair,  */
+                       /* the scalar RHS and the vector synthesis, and their z transforms as  */
+                       /* two radix-16 DFT products, on MFMA with hi/lo bfloat16 operands and */
+                       /* FP32 accumulation (a_hi b_hi + a_hi b_lo + a_lo b_hi); the phi FFTs, */
+                       /* pointwise products, the projection's forward z transforms, source   */
+                       /* products and solves as for MLG_FP32                                 */
 } mlg_precision;
+
+/* Reduced-precision plans (MLG_FP32, MLG_SPLIT_BF16) need N_phi = N_z = 256, an even N_r,
+ * N_r <= 32768 and N_r^c <= 512; they serve mlg_forward, mlg_backward, mlg_rhs_scalar,
+ * mlg_rhs_tp and mlg_rhs_tp_noalloc (the taps stay double).  Every other plan entry point,
+ * the closure and truncation need MLG_FP64 plans and return MLG_E_UNSUPPORTED otherwise. */
 
 enum { MLG_RHS_U2 = 0, MLG_RHS_KPP = 1 };
 
@@ -91,7 +101,8 @@ typedef struct {
   int64_t workspace_bytes;  /* bytes of device workspace every call of this plan needs  */
   int32_t M;                /* stored azimuthal orders                                   */
   int32_t nrc, nzc;         /* resolved radial and axial chops                           */
-  int32_t real_bytes;       /* bytes of one real of the data arrays (8 for plans)        */
+  int32_t real_bytes;       /* bytes of one real of the data arrays (8 for MLG_FP64 plans, */
+                            /* 4 for MLG_FP32 and MLG_SPLIT_BF16 plans)                    */
   int32_t dealias_m, dealias_k;  /* largest kept m and |k| under the two-thirds mask     */
 } mlg_layout;
 
@@ -102,8 +113,8 @@ typedef struct mlg_plan_s* mlg_plan;
  * r d/dr Pbar, the horizontal-Laplacian Gram factors of Eq. del2h-entries and the FFT
  * twiddles, then copies them to 'device'.  Errors: MLG_E_ARG for bad sizes/chops/ell,
  * MLG_E_NONFINITE for non-finite ell or L_z, MLG_E_UNSUPPORTED for N_phi or N_z whose
- * factors are not all 2, 3 or 5, or N_phi, N_z above 1024, or a precision other than MLG_FP64
- * and MLG_SPLIT_BF16 (the data of both are double); MLG_E_ALLOC/DEVICE on HIP failure.
+ * factors are not all 2, 3 or 5, or N_phi, N_z above 1024, or a reduced-precision plan off its
+ * sizes (see above); MLG_E_ALLOC/DEVICE on HIP failure.
  * On failure *out is NULL and nothing is leaked.  For even N_r the FP64 radial products of the
  * vector RHS use the node symmetry x -> -x and the parity of Pbar_n^m (half the flops); the
  * environment variable MLG_RADIAL_FOLD=0, read at creation, selects the unfolded products. */

@@ -430,8 +430,9 @@ def mlg_closure_set_reference(closure: int, ref: int, U=None) -> None:
 class Plan:
     """A plan plus its workspace, for torch tensors on the plan's device.
 
-    Tensors: physical fields are float64 of shape (N_z, N_r, N_phi); spectral fields are
-    complex128 of shape (tau, N_z) (packed triangular rows, see include/mlg.h).
+    Tensors: physical fields are real of shape (N_z, N_r, N_phi); spectral fields are complex of
+    shape (tau, N_z) (packed triangular rows, see include/mlg.h): float64 / complex128 on MLG_FP64
+    plans, float32 / complex64 on MLG_FP32 and MLG_SPLIT_BF16 plans (``rdtype``, ``cdtype``).
     """
 
     def __init__(self, nr, nphi, nz=1, ell=1.0, lz=6.283185307179586, nrc=0, nphic=0, nzc=0,

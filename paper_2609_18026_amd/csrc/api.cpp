@@ -59,6 +59,13 @@ mlg_status check_plan(mlg_plan p) {
   return MLG_OK;
 }
 
+// entry points that work on FP64 data only
+mlg_status check_fp64(mlg_plan p, const char* what) {
+  if (!p) return fail(MLG_E_ARG, "plan is NULL");
+  if (p->prec != MLG_FP64) return fail(MLG_E_UNSUPPORTED, std::string(what) + " needs an MLG_FP64 plan");
+  return MLG_OK;
+}
+
 // Device-resident workspace of mlg_rhs_tp_noalloc: one copy per GPU, held from the first use of the
 // library on that GPU until the process ends.  Host code never uses the array's name as an
 // address: the device address of each GPU's copy comes from hipGetSymbolAddress.
@@ -116,8 +123,16 @@ mlg_status mlg_plan_create(const mlg_grid* grid, mlg_precision prec, int device,
   if (g.nr > 4096) return fail(MLG_E_UNSUPPORTED, "N_r above 4096");
   if (!factorable(g.nphi) || !factorable(g.nz))
     return fail(MLG_E_UNSUPPORTED, "N_phi and N_z must be <= 1024 with prime factors 2, 3, 5 only");
-  if (prec != MLG_FP64 && prec != MLG_SPLIT_BF16)
-    return fail(MLG_E_UNSUPPORTED, "plans support MLG_FP64 and MLG_SPLIT_BF16");
+  if (prec != MLG_FP64 && prec != MLG_FP32 && prec != MLG_SPLIT_BF16)
+    return fail(MLG_E_UNSUPPORTED, "unknown precision");
+  if (prec != MLG_FP64) {
+    // reduced-precision plans: float data, the register-resident 256-point FFTs and the folded products
+    if (g.nphi != 256 || g.nz != 256)
+      return fail(MLG_E_UNSUPPORTED, "MLG_FP32 and MLG_SPLIT_BF16 plans need N_phi = N_z = 256");
+    if (g.nr % 2 != 0) return fail(MLG_E_UNSUPPORTED, "MLG_FP32 and MLG_SPLIT_BF16 plans need an even N_r");
+    if ((int64_t)g.nr * g.nz > (int64_t(1) << 23) || g.nrc > 512)
+      return fail(MLG_E_UNSUPPORTED, "MLG_FP32 and MLG_SPLIT_BF16 plans need N_r <= 32768 and N_r^c <= 512");
+  }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
     return fail(MLG_E_ARG, "device index out of range or no HIP device");
@@ -142,6 +157,7 @@ mlg_status mlg_plan_create(const mlg_grid* grid, mlg_precision prec, int device,
   p->phi_nrad = factor_radices(g.nphi, p->phi_rad);
   p->z_nrad = factor_radices(g.nz, p->z_rad);
   if (const char* e = std::getenv("MLG_RADIAL_FOLD")) p->use_fold = std::strcmp(e, "0") != 0;
+  if (prec != MLG_FP64) p->use_fold = true;  // the reduced-precision paths are the folded ones
   mlg_status st = build_plan(p);
   if (st != MLG_OK) {
     std::string msg = g_last_error;
@@ -170,7 +186,7 @@ mlg_status mlg_plan_query(mlg_plan p, mlg_layout* out) {
   out->M = p->M;
   out->nrc = p->nrc;
   out->nzc = p->nzc;
-  out->real_bytes = 8;
+  out->real_bytes = p->prec == MLG_FP64 ? 8 : 4;
   out->dealias_m = p->dealias_m;
   out->dealias_k = p->dealias_k;
   return MLG_OK;
@@ -190,6 +206,7 @@ mlg_status mlg_plan_nodes(mlg_plan p, double* x, double* w, double* r) {
 // was created with MLG_RADIAL_FOLD=0), the generic batched GEMM otherwise.
 static mlg_status scalar_radial(const mlg_plan_s* p, int dir, const double* B, double* C, hipStream_t s) {
   if (p->prec == MLG_SPLIT_BF16) return launch_split_scalar(p, dir, B, C, s);
+  if (p->prec == MLG_FP32) return launch_scalar_fold(p, dir, B, C, s);
   if (p->use_fold && p->nr % 2 == 0) return launch_scalar_fold(p, dir, B, C, s);
   GemmProds pr{};
   pr.nprod = 1;
@@ -323,7 +340,7 @@ mlg_status mlg_rhs_tp_noalloc(mlg_plan p, const double* U, const void* psi, cons
 }
 
 mlg_status mlg_step_setup(mlg_plan p, const mlg_dissip* d) {
-  if (mlg_status st = check_plan(p)) return st;
+  if (mlg_status st = check_fp64(p, "mlg_step_setup")) return st;
   if (!d) return fail(MLG_E_ARG, "dissip is NULL");
   if (!std::isfinite(d->nu) || !std::isfinite(d->nu_h) || !std::isfinite(d->dt))
     return fail(MLG_E_NONFINITE, "non-finite step parameters");
@@ -334,7 +351,7 @@ mlg_status mlg_step_setup(mlg_plan p, const mlg_dissip* d) {
 }
 
 mlg_status mlg_step_febe(mlg_plan p, int half, const void* s, const void* A, void* out, void* stream) {
-  if (mlg_status st = check_plan(p)) return st;
+  if (mlg_status st = check_fp64(p, "mlg_step_febe")) return st;
   if (!p->step_ready) return fail(MLG_E_ARG, "mlg_step_setup has not been called");
   if (!s || !A || !out) return fail(MLG_E_ARG, "null buffer");
   if (out == s || out == A) return fail(MLG_E_ARG, "out must not alias the inputs");
@@ -344,7 +361,7 @@ mlg_status mlg_step_febe(mlg_plan p, int half, const void* s, const void* A, voi
 }
 
 mlg_status mlg_step_abcn(mlg_plan p, const void* s, const void* A_now, const void* A_prev, void* out, void* stream) {
-  if (mlg_status st = check_plan(p)) return st;
+  if (mlg_status st = check_fp64(p, "mlg_step_abcn")) return st;
   if (!p->step_ready) return fail(MLG_E_ARG, "mlg_step_setup has not been called");
   if (!s || !A_now || !A_prev || !out) return fail(MLG_E_ARG, "null buffer");
   if (out == s || out == A_now || out == A_prev) return fail(MLG_E_ARG, "out must not alias the inputs");
@@ -355,7 +372,7 @@ mlg_status mlg_step_abcn(mlg_plan p, const void* s, const void* A_now, const voi
 
 mlg_status mlg_eval_harmonic(mlg_plan p, const void* spec, int32_t m, int32_t kk, const double* r, int64_t npts,
                              void* out, void* stream) {
-  if (mlg_status st = check_plan(p)) return st;
+  if (mlg_status st = check_fp64(p, "mlg_eval_harmonic")) return st;
   if (!spec || !out || (npts > 0 && !r)) return fail(MLG_E_ARG, "null buffer");
   if (m < 0 || m >= p->M || kk < 0 || kk >= p->nz) return fail(MLG_E_ARG, "harmonic (m, kk) out of range");
   if (npts < 0) return fail(MLG_E_ARG, "npts must be >= 0");
@@ -365,7 +382,7 @@ mlg_status mlg_eval_harmonic(mlg_plan p, const void* spec, int32_t m, int32_t kk
 }
 
 mlg_status mlg_filter_setup(mlg_plan p, const mlg_filter_cfg* cfg) {
-  if (mlg_status st = check_plan(p)) return st;
+  if (mlg_status st = check_fp64(p, "mlg_filter_setup")) return st;
   if (!cfg) {
     p->filter_on = false;
     return MLG_OK;
@@ -398,7 +415,7 @@ mlg_status mlg_filter_setup(mlg_plan p, const mlg_filter_cfg* cfg) {
 }
 
 mlg_status mlg_filter_apply(mlg_plan p, int32_t slot, void* spec, void* stream) {
-  if (mlg_status st = check_plan(p)) return st;
+  if (mlg_status st = check_fp64(p, "mlg_filter_apply")) return st;
   if (!p->filter_on) return fail(MLG_E_ARG, "mlg_filter_setup has not enabled the filter");
   if (slot != 0 && slot != 1) return fail(MLG_E_ARG, "filter slot must be 0 or 1");
   if (!spec) return fail(MLG_E_ARG, "null buffer");
@@ -418,7 +435,7 @@ mlg_status mlg_filter_state(mlg_plan p, double* out4) {
 
 mlg_status mlg_tp_advance(mlg_plan p, const double* U, void* psi, void* chi, void* hist_psi, void* hist_chi,
                           int32_t nsteps, int32_t start, mlg_closure closure, void* tmp, void* ws, void* stream) {
-  if (mlg_status st = check_plan(p)) return st;
+  if (mlg_status st = check_fp64(p, "mlg_tp_advance")) return st;
   if (!p->step_ready) return fail(MLG_E_ARG, "mlg_step_setup has not been called");
   if (!psi || !chi || !hist_psi || !hist_chi || !tmp || !ws) return fail(MLG_E_ARG, "null buffer");
   if (nsteps < 0) return fail(MLG_E_ARG, "nsteps must be >= 0");
@@ -481,7 +498,7 @@ mlg_status mlg_tp_advance(mlg_plan p, const double* U, void* psi, void* chi, voi
 
 mlg_status mlg_scalar_advance(mlg_plan p, int32_t kind, double gamma, void* state, void* hist, int32_t nsteps,
                               int32_t start, void* tmp, void* ws, void* stream) {
-  if (mlg_status st = check_plan(p)) return st;
+  if (mlg_status st = check_fp64(p, "mlg_scalar_advance")) return st;
   if (!p->step_ready) return fail(MLG_E_ARG, "mlg_step_setup has not been called");
   if (!state || !hist || !tmp || !ws) return fail(MLG_E_ARG, "null buffer");
   if (kind != MLG_RHS_U2 && kind != MLG_RHS_KPP) return fail(MLG_E_ARG, "kind must be MLG_RHS_U2 or MLG_RHS_KPP");
@@ -524,17 +541,13 @@ mlg_status mlg_scalar_advance(mlg_plan p, int32_t kind, double gamma, void* stat
 }
 
 mlg_status mlg_synthesize(mlg_plan p, const void* psi, const void* chi, void* uw, void* ws, void* stream) {
-  if (mlg_status st = check_plan(p)) return st;
+  if (mlg_status st = check_fp64(p, "mlg_synthesize")) return st;
   if (!psi || !chi || !uw || !ws) return fail(MLG_E_ARG, "null buffer");
   DeviceGuard guard(p->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   Ws w = partition(p, ws);
   mlg_status st;
-  if (p->prec == MLG_SPLIT_BF16)
-    st = launch_split_synth(p, static_cast<const double*>(psi), static_cast<const double*>(chi), w.X, s);
-  else
-    st = launch_synth_gemm(p, static_cast<const double*>(psi), static_cast<const double*>(chi), w.X, s);
-  if (st) return st;
+  if ((st = launch_synth_gemm(p, static_cast<const double*>(psi), static_cast<const double*>(chi), w.X, s))) return st;
   if ((st = launch_proxy_fields(p, w.X, s))) return st;
   const int64_t mrows = (int64_t)p->M * p->nr;
   const size_t pe = (size_t)p->nz * p->nr * p->nphi;
@@ -546,9 +559,8 @@ mlg_status mlg_synthesize(mlg_plan p, const void* psi, const void* chi, void* uw
 }
 
 mlg_status mlg_tp_energy(mlg_plan p, const void* psi, const void* chi, double* energy, void* ws, void* stream) {
-  if (mlg_status st = check_plan(p)) return st;
+  if (mlg_status st = check_fp64(p, "mlg_tp_energy")) return st;
   if (!psi || !chi || !energy || !ws) return fail(MLG_E_ARG, "null buffer");
-  if (p->prec != MLG_FP64) return fail(MLG_E_UNSUPPORTED, "mlg_tp_energy: FP64 plans only");
   DeviceGuard guard(p->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   Ws w = partition(p, ws);
@@ -559,9 +571,8 @@ mlg_status mlg_tp_energy(mlg_plan p, const void* psi, const void* chi, double* e
 }
 
 mlg_status mlg_tp_enstrophy(mlg_plan p, const void* psi, const void* chi, double* enstrophy, void* ws, void* stream) {
-  if (mlg_status st = check_plan(p)) return st;
+  if (mlg_status st = check_fp64(p, "mlg_tp_enstrophy")) return st;
   if (!psi || !chi || !enstrophy || !ws) return fail(MLG_E_ARG, "null buffer");
-  if (p->prec != MLG_FP64) return fail(MLG_E_UNSUPPORTED, "mlg_tp_enstrophy: FP64 plans only");
   DeviceGuard guard(p->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   Ws w = partition(p, ws);
@@ -572,7 +583,7 @@ mlg_status mlg_tp_enstrophy(mlg_plan p, const void* psi, const void* chi, double
 }
 
 mlg_status mlg_laplacian_solve(mlg_plan p, int variant, const void* f, void* s, double* c, void* ws, void* stream) {
-  if (mlg_status st = check_plan(p)) return st;
+  if (mlg_status st = check_fp64(p, "mlg_laplacian_solve")) return st;
   if (!f || !s || !ws || !c) return fail(MLG_E_ARG, "null buffer");
   if (f == s) return fail(MLG_E_ARG, "f and s must not alias");
   if (variant != MLG_LOG_PRESCRIBE && variant != MLG_LOG_SOLVE) return fail(MLG_E_ARG, "unknown variant");
@@ -585,7 +596,7 @@ mlg_status mlg_laplacian_solve(mlg_plan p, int variant, const void* f, void* s, 
 }
 
 mlg_status mlg_remove_far_field(mlg_plan p, void* spec, void* stream) {
-  if (mlg_status st = check_plan(p)) return st;
+  if (mlg_status st = check_fp64(p, "mlg_remove_far_field")) return st;
   if (!spec) return fail(MLG_E_ARG, "null buffer");
   DeviceGuard guard(p->device);
   return launch_far_field(p, static_cast<double*>(spec), static_cast<hipStream_t>(stream));
@@ -594,6 +605,8 @@ mlg_status mlg_remove_far_field(mlg_plan p, void* spec, void* stream) {
 mlg_status mlg_set_log_proxy(mlg_plan p, double c_psi, double c_chi) {
   if (mlg_status st = check_plan(p)) return st;
   if (!std::isfinite(c_psi) || !std::isfinite(c_chi)) return fail(MLG_E_ARG, "proxy amplitudes must be finite");
+  if (p->prec != MLG_FP64 && (c_psi != 0.0 || c_chi != 0.0))
+    return fail(MLG_E_UNSUPPORTED, "logarithmic proxy amplitudes need an MLG_FP64 plan");
   p->log_cpsi = c_psi;
   p->log_cchi = c_chi;
   return MLG_OK;

@@ -43,5 +43,27 @@ __host__ __device__ inline unsigned xcd_blocks(int gx, int gy, int gz) {
   return 8u * (unsigned)gx * (unsigned)gy * (unsigned)((gz + 7) / 8);
 }
 
+// Storage conversions: reduced-precision plans keep fields as float / float2 in memory while the
+// kernels compute in double.
+__device__ __forceinline__ double2 ld2(const double2* p) { return *p; }
+__device__ __forceinline__ double2 ld2(const float2* p) {
+  const float2 v = *p;
+  return make_double2((double)v.x, (double)v.y);
+}
+__device__ __forceinline__ double2 to_d2(double2 a) { return a; }
+__device__ __forceinline__ double2 to_d2(float2 a) { return make_double2((double)a.x, (double)a.y); }
+__device__ __forceinline__ void st2(double2* p, double2 v) { *p = v; }
+__device__ __forceinline__ void st2(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+__device__ __forceinline__ double ld1(const double* p) { return *p; }
+__device__ __forceinline__ double ld1(const float* p) { return (double)*p; }
+__device__ __forceinline__ void st1(double* p, double v) { *p = v; }
+__device__ __forceinline__ void st1(float* p, double v) { *p = (float)v; }
+template <typename S2>
+__device__ __forceinline__ S2 czero();
+template <>
+__device__ __forceinline__ double2 czero<double2>() { return make_double2(0.0, 0.0); }
+template <>
+__device__ __forceinline__ float2 czero<float2>() { return make_float2(0.f, 0.f); }
+
 }  // namespace dev
 }  // namespace mlg

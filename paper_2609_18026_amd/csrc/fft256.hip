@@ -173,15 +173,16 @@ __device__ __forceinline__ void fft256w(double2 (&v)[8], double2* W, int s, cons
 // e / PL.  The per-lane byte offset is 32-bit (the launcher bounds the line count) and the rest of
 // the address is uniform.  GUARD (the last block, or fewer than 128 stored orders) reads orders
 // >= min(M, 128) and lines past the end as zero.
+template <typename S2>
 struct PairRegs {
-  double2 a[PL * 128 / VB], b[PL * 128 / VB];
+  S2 a[PL * 128 / VB], b[PL * 128 / VB];
 };
 
-template <bool GUARD>
-__device__ __forceinline__ void load_pair(PairRegs& r, const Phi256& g, int64_t q0, const double2* __restrict__ fa,
-                                          const double2* __restrict__ fb) {
+template <bool GUARD, typename S2>
+__device__ __forceinline__ void load_pair(PairRegs<S2>& r, const Phi256& g, int64_t q0, const S2* __restrict__ fa,
+                                          const S2* __restrict__ fb) {
   const int t = threadIdx.x;
-  const uint32_t off = (uint32_t)((t >> 3) * g.nlines + (t & 7)) * (uint32_t)sizeof(double2);
+  const uint32_t off = (uint32_t)((t >> 3) * g.nlines + (t & 7)) * (uint32_t)sizeof(S2);
   const int mmax = g.M < 128 ? g.M : 128;
   const bool line_ok = q0 + (t & 7) < g.nlines;
 #pragma unroll
@@ -190,12 +191,12 @@ __device__ __forceinline__ void load_pair(PairRegs& r, const Phi256& g, int64_t 
     const char* pa = reinterpret_cast<const char*>(fa + base) + off;
     const char* pb = reinterpret_cast<const char*>(fb + base) + off;
     if (!GUARD) {
-      r.a[it] = *reinterpret_cast<const double2*>(pa);
-      r.b[it] = *reinterpret_cast<const double2*>(pb);
+      r.a[it] = *reinterpret_cast<const S2*>(pa);
+      r.b[it] = *reinterpret_cast<const S2*>(pb);
     } else {
       const bool ok = line_ok && (t >> 3) + (VB / PL) * it < mmax;
-      r.a[it] = ok ? *reinterpret_cast<const double2*>(pa) : make_double2(0.0, 0.0);
-      r.b[it] = ok ? *reinterpret_cast<const double2*>(pb) : make_double2(0.0, 0.0);
+      r.a[it] = ok ? *reinterpret_cast<const S2*>(pa) : czero<S2>();
+      r.b[it] = ok ? *reinterpret_cast<const S2*>(pb) : czero<S2>();
     }
   }
 }
@@ -203,7 +204,8 @@ __device__ __forceinline__ void load_pair(PairRegs& r, const Phi256& g, int64_t 
 // Writes the pair into Z as the Hermitian spectrum of a + i b.  Orders 1..127 fill positions
 // m and 256 - m, order 0 position 0; only the Nyquist position 128 is cleared.  Starts with a
 // barrier (earlier readers of Z are done) and ends with one.
-__device__ __forceinline__ void store_pair(const PairRegs& r, double2 (*Z)[WROW]) {
+template <typename S2>
+__device__ __forceinline__ void store_pair(const PairRegs<S2>& r, double2 (*Z)[WROW]) {
   const int t = threadIdx.x;
   __syncthreads();
   if (t < PL) Z[t][zpos(128)] = make_double2(0.0, 0.0);
@@ -211,7 +213,7 @@ __device__ __forceinline__ void store_pair(const PairRegs& r, double2 (*Z)[WROW]
   for (int it = 0; it < PL * 128 / VB; ++it) {
     const int e = t + VB * it;
     const int ll = e & (PL - 1), m = e >> 3;
-    const double2 a = r.a[it], b = r.b[it];
+    const double2 a = to_d2(r.a[it]), b = to_d2(r.b[it]);
     if (m == 0) {
       Z[ll][0] = make_double2(a.x, b.x);
     } else {
@@ -224,8 +226,9 @@ __device__ __forceinline__ void store_pair(const PairRegs& r, double2 (*Z)[WROW]
 
 // Scatters the spectrum X (v[j] = X[s + 32 j]) of z = a + i b of each line to the harmonics of a
 // and b (orders m < M, scaled by 1/256; orders above mkeep written as zero).  Barriers at both ends.
+template <typename S2>
 __device__ __forceinline__ void scatter_pair_w(const double2 (&v)[8], double2 (*Z)[WROW], const Phi256& g,
-                                               int64_t q0, int ll, int s, double2* fa, double2* fb) {
+                                               int64_t q0, int ll, int s, S2* fa, S2* fb) {
   __syncthreads();  // every line's exchange reads are complete
 #pragma unroll
   for (int j = 0; j < 8; ++j) Z[ll][33 * j + s] = v[j];
@@ -244,18 +247,19 @@ __device__ __forceinline__ void scatter_pair_w(const double2 (&v)[8], double2 (*
       const double2 d = csub(zm, zc);
       B = make_double2(0.5 / 256.0 * d.y, -0.5 / 256.0 * d.x);
     }
-    fa[(int64_t)m * g.nlines + q] = A;
-    if (fb) fb[(int64_t)m * g.nlines + q] = B;
+    st2(fa + (int64_t)m * g.nlines + q, A);
+    if (fb) st2(fb + (int64_t)m * g.nlines + q, B);
   }
   __syncthreads();
 }
 
+template <typename S2>
 struct Six256 {
-  double2* f[6];
+  S2* f[6];
 };
 
-template <bool GUARD>
-__global__ __launch_bounds__(VB) void phi_vec256_kernel(Phi256 g, const double2* __restrict__ twg, Six256 fs,
+template <bool GUARD, typename S2>
+__global__ __launch_bounds__(VB) void phi_vec256_kernel(Phi256 g, const double2* __restrict__ twg, Six256<S2> fs,
                                                         const double* __restrict__ rinv, double Ux, double Uy,
                                                         double Uz, double* __restrict__ taps, int64_t blk0) {
   __shared__ double2 Z[PL][WROW];
@@ -266,7 +270,7 @@ __global__ __launch_bounds__(VB) void phi_vec256_kernel(Phi256 g, const double2*
   tw[t] = twg[t];  // VB == 256; visible after the first barrier of store_pair
   double2 v[8];
   double ur[8], up[8], uz[8], wr[8];
-  PairRegs pr;
+  PairRegs<S2> pr;
   // pair 0: (u_r, u_phi); the loads of each next pair are issued before the current transform
   load_pair<GUARD>(pr, g, q0, fs.f[0], fs.f[1]);
   store_pair(pr, Z);
@@ -332,7 +336,7 @@ __global__ __launch_bounds__(VB) void phi_vec256_kernel(Phi256 g, const double2*
 #pragma unroll
   for (int k = 0; k < 8; ++k) v[k] = make_double2(nzr[k], 0.0);
   fft256w<false>(v, Z[ll], s, tw);
-  scatter_pair_w(v, Z, g, q0, ll, s, fs.f[2], nullptr);
+  scatter_pair_w(v, Z, g, q0, ll, s, fs.f[2], (S2*)nullptr);
 }
 
 // ---------------------------------------------------------------- scalar phi stages (32-lane lines)
@@ -341,8 +345,9 @@ __global__ __launch_bounds__(VB) void phi_vec256_kernel(Phi256 g, const double2*
 // keeps its part; the forward stage transforms the pair, the even group stores the spectrum and the
 // harmonics of both lines are separated from it.  The twiddles are staged in LDS as in the vector
 // stage; the block barrier of the gather also publishes them.
+template <typename S2, typename S>
 __global__ __launch_bounds__(VB) void phi_bwd256_kernel(Phi256 g, const double2* __restrict__ twg,
-                                                        const double2* __restrict__ mixed, double* __restrict__ phys) {
+                                                        const S2* __restrict__ mixed, S* __restrict__ phys) {
   __shared__ double2 Z[PL][WROW];
   __shared__ double2 tw[256];
   const int t = threadIdx.x, ll = t / WL, s = t % WL;
@@ -355,8 +360,8 @@ __global__ __launch_bounds__(VB) void phi_bwd256_kernel(Phi256 g, const double2*
     const int e = t + VB * it;
     const int pr = e & (PL / 2 - 1), m = e / (PL / 2);
     const int64_t qa = q0 + 2 * pr, qb = qa + 1;
-    const double2 a = (m < mmax && qa < g.nlines) ? mixed[(int64_t)m * g.nlines + qa] : make_double2(0.0, 0.0);
-    const double2 b = (m < mmax && qb < g.nlines) ? mixed[(int64_t)m * g.nlines + qb] : make_double2(0.0, 0.0);
+    const double2 a = (m < mmax && qa < g.nlines) ? ld2(mixed + (int64_t)m * g.nlines + qa) : make_double2(0.0, 0.0);
+    const double2 b = (m < mmax && qb < g.nlines) ? ld2(mixed + (int64_t)m * g.nlines + qb) : make_double2(0.0, 0.0);
     double2* Zp = Z[2 * pr];
     if (m == 0) {
       Zp[0] = make_double2(a.x, b.x);
@@ -378,13 +383,14 @@ __global__ __launch_bounds__(VB) void phi_bwd256_kernel(Phi256 g, const double2*
     for (int k = 0; k < 8; ++k) {
       // select values, not addresses, so that v stays in registers
       const double re = v[k].x, im = v[k].y;
-      phys[phys_off(g, q) + s + 32 * k] = imag ? im : re;
+      st1(phys + phys_off(g, q) + s + 32 * k, imag ? im : re);
     }
   }
 }
 
+template <typename S, typename S2>
 __global__ __launch_bounds__(VB) void phi_fwd256_kernel(Phi256 g, const double2* __restrict__ twg,
-                                                        const double* __restrict__ phys, double2* __restrict__ mixed) {
+                                                        const S* __restrict__ phys, S2* __restrict__ mixed) {
   __shared__ double2 Z[PL][WROW];
   __shared__ double2 tw[256];
   const int t = threadIdx.x, ll = t / WL, s = t % WL;
@@ -394,8 +400,8 @@ __global__ __launch_bounds__(VB) void phi_fwd256_kernel(Phi256 g, const double2*
   double2 v[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const double a = (qa < g.nlines) ? phys[phys_off(g, qa) + s + 32 * j] : 0.0;
-    const double b = (qb < g.nlines) ? phys[phys_off(g, qb) + s + 32 * j] : 0.0;
+    const double a = (qa < g.nlines) ? ld1(phys + phys_off(g, qa) + s + 32 * j) : 0.0;
+    const double b = (qb < g.nlines) ? ld1(phys + phys_off(g, qb) + s + 32 * j) : 0.0;
     v[j] = make_double2(a, b);
   }
   __syncthreads();  // the twiddle table is staged
@@ -422,13 +428,13 @@ __global__ __launch_bounds__(VB) void phi_fwd256_kernel(Phi256 g, const double2*
         r = make_double2(0.5 / 256.0 * d.y, -0.5 / 256.0 * d.x);
       }
     }
-    mixed[(int64_t)m * g.nlines + q] = r;
+    st2(mixed + (int64_t)m * g.nlines + q, r);
   }
 }
 
 // u = B(u_hat), g(u) = u^2 or gamma u (1 - u), back to harmonics; one real line per 32 lanes
-template <int MODE>
-__global__ __launch_bounds__(VB) void phi_scalar256_kernel(Phi256 g, const double2* __restrict__ twg, double2* mixed,
+template <int MODE, typename S2>
+__global__ __launch_bounds__(VB) void phi_scalar256_kernel(Phi256 g, const double2* __restrict__ twg, S2* mixed,
                                                            double gamma) {
   __shared__ double2 Z[PL][WROW];
   __shared__ double2 tw[256];
@@ -442,7 +448,7 @@ __global__ __launch_bounds__(VB) void phi_scalar256_kernel(Phi256 g, const doubl
     const int e = t + VB * it;
     const int l2 = e & (PL - 1), m = e >> 3;
     const int64_t q = q0 + l2;
-    const double2 a = (m < mmax && q < g.nlines) ? mixed[(int64_t)m * g.nlines + q] : make_double2(0.0, 0.0);
+    const double2 a = (m < mmax && q < g.nlines) ? ld2(mixed + (int64_t)m * g.nlines + q) : make_double2(0.0, 0.0);
     if (m == 0) {
       Z[l2][0] = make_double2(a.x, 0.0);
     } else {
@@ -462,7 +468,7 @@ __global__ __launch_bounds__(VB) void phi_scalar256_kernel(Phi256 g, const doubl
     v[k] = make_double2(r, 0.0);
   }
   fft256w<false>(v, Z[ll], s, tw);
-  scatter_pair_w(v, Z, g, q0, ll, s, mixed, nullptr);
+  scatter_pair_w(v, Z, g, q0, ll, s, mixed, (S2*)nullptr);
 }
 
 // ---------------------------------------------------------------- z transforms (32-lane lines)
@@ -470,13 +476,14 @@ __global__ __launch_bounds__(VB) void phi_scalar256_kernel(Phi256 g, const doubl
 // line loads x[s + 32 j] straight into registers (32 lanes cover 512 contiguous bytes), fft256w
 // transforms the line within its wavefront and the lane stores X[s + 32 j]: the only block
 // barrier is the one after the twiddle table is staged.  In place when in == out.
+template <typename S2>
 struct ZFields {
-  const double2* in[6];
-  double2* out[6];
+  const S2* in[6];
+  S2* out[6];
 };
 
-template <bool INV>
-__global__ __launch_bounds__(VB) void zfft256w_kernel(const double2* __restrict__ twg, ZFields fs, int64_t rows,
+template <bool INV, typename S2>
+__global__ __launch_bounds__(VB) void zfft256w_kernel(const double2* __restrict__ twg, ZFields<S2> fs, int64_t rows,
                                                       int64_t per_field, int nzc, const int32_t* __restrict__ row_m,
                                                       int mask_m, int mask_k) {
   __shared__ double2 Z[PL][WROW];
@@ -487,16 +494,16 @@ __global__ __launch_bounds__(VB) void zfft256w_kernel(const double2* __restrict_
   const int64_t f = blockIdx.x / per_field;
   const int64_t row = (blockIdx.x - f * per_field) * PL + ll;
   if (row >= rows) return;  // no block barrier follows
-  const double2* __restrict__ x = fs.in[f] + row * 256;
+  const S2* __restrict__ x = fs.in[f] + row * 256;
   double2 v[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int kk = s + 32 * j;
-    const double2 a = x[kk];
+    const double2 a = ld2(x + kk);
     v[j] = (INV && !kkept(kk, 256, nzc)) ? make_double2(0.0, 0.0) : a;
   }
   fft256w<INV>(v, Z[ll], s, tw);
-  double2* __restrict__ y = fs.out[f] + row * 256;
+  S2* __restrict__ y = fs.out[f] + row * 256;
   const int mrow = (!INV && row_m) ? row_m[row] : 0;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
@@ -511,7 +518,7 @@ __global__ __launch_bounds__(VB) void zfft256w_kernel(const double2* __restrict_
       }
       if (!keep) a = make_double2(0.0, 0.0);
     }
-    y[kk] = a;
+    st2(y + kk, a);
   }
 }
 
@@ -533,22 +540,34 @@ mlg_status check(const char* what) {
 
 }  // namespace
 
-mlg_status launch_zfft256(const mlg_plan_s* p, const double* const* in, double* const* out, int nf, int64_t rows,
-                          int dir, const int32_t* row_m, int mask_m, int mask_k, hipStream_t s) {
-  if (nf < 1 || nf > 6) return fail(MLG_E_ARG, "z transform: 1 to 6 fields per launch");
-  ZFields fs{};
+// Reduced-precision plans (MLG_FP32, MLG_SPLIT_BF16) keep their fields as float / float2.
+static bool reduced(const mlg_plan_s* p) { return p->prec != MLG_FP64; }
+
+template <typename S2>
+static void zfft256_go(const mlg_plan_s* p, const double* const* in, double* const* out, int nf, int64_t rows, int dir,
+                       const int32_t* row_m, int mask_m, int mask_k, hipStream_t s) {
+  ZFields<S2> fs{};
   for (int i = 0; i < nf; ++i) {
-    fs.in[i] = reinterpret_cast<const double2*>(in[i]);
-    fs.out[i] = reinterpret_cast<double2*>(out[i]);
+    fs.in[i] = reinterpret_cast<const S2*>(in[i]);
+    fs.out[i] = reinterpret_cast<S2*>(out[i]);
   }
   const double2* tw = reinterpret_cast<const double2*>(p->d_tw_z);
   const int64_t per = (rows + PL - 1) / PL;
   dim3 grid((unsigned)(per * nf));
-  p->timing.begin("z_fft", s);
   if (dir > 0)
-    zfft256w_kernel<true><<<grid, VB, 0, s>>>(tw, fs, rows, per, p->nzc, nullptr, 0, 0);
+    zfft256w_kernel<true, S2><<<grid, VB, 0, s>>>(tw, fs, rows, per, p->nzc, nullptr, 0, 0);
   else
-    zfft256w_kernel<false><<<grid, VB, 0, s>>>(tw, fs, rows, per, p->nzc, row_m, mask_m, mask_k);
+    zfft256w_kernel<false, S2><<<grid, VB, 0, s>>>(tw, fs, rows, per, p->nzc, row_m, mask_m, mask_k);
+}
+
+mlg_status launch_zfft256(const mlg_plan_s* p, const double* const* in, double* const* out, int nf, int64_t rows,
+                          int dir, const int32_t* row_m, int mask_m, int mask_k, hipStream_t s) {
+  if (nf < 1 || nf > 6) return fail(MLG_E_ARG, "z transform: 1 to 6 fields per launch");
+  p->timing.begin("z_fft", s);
+  if (reduced(p))
+    zfft256_go<float2>(p, in, out, nf, rows, dir, row_m, mask_m, mask_k, s);
+  else
+    zfft256_go<double2>(p, in, out, nf, rows, dir, row_m, mask_m, mask_k, s);
   p->timing.end(s);
   return check("zfft256w_kernel");
 }
@@ -556,9 +575,13 @@ mlg_status launch_zfft256(const mlg_plan_s* p, const double* const* in, double* 
 mlg_status launch_phi256_forward(const mlg_plan_s* p, const double* phys, double* mixed, hipStream_t s) {
   Phi256 g = phi256_geom(p, false);
   dim3 grid((unsigned)((g.nlines + PL - 1) / PL));
+  const double2* tw = reinterpret_cast<const double2*>(p->d_tw_phi);
   p->timing.begin("phi_fft", s);
-  phi_fwd256_kernel<<<grid, VB, 0, s>>>(g, reinterpret_cast<const double2*>(p->d_tw_phi), phys,
-                                        reinterpret_cast<double2*>(mixed));
+  if (reduced(p))
+    phi_fwd256_kernel<float, float2><<<grid, VB, 0, s>>>(g, tw, reinterpret_cast<const float*>(phys),
+                                                         reinterpret_cast<float2*>(mixed));
+  else
+    phi_fwd256_kernel<double, double2><<<grid, VB, 0, s>>>(g, tw, phys, reinterpret_cast<double2*>(mixed));
   p->timing.end(s);
   return check("phi_fwd256_kernel");
 }
@@ -566,41 +589,62 @@ mlg_status launch_phi256_forward(const mlg_plan_s* p, const double* phys, double
 mlg_status launch_phi256_backward(const mlg_plan_s* p, const double* mixed, double* phys, hipStream_t s) {
   Phi256 g = phi256_geom(p, false);
   dim3 grid((unsigned)((g.nlines + PL - 1) / PL));
+  const double2* tw = reinterpret_cast<const double2*>(p->d_tw_phi);
   p->timing.begin("phi_fft", s);
-  phi_bwd256_kernel<<<grid, VB, 0, s>>>(g, reinterpret_cast<const double2*>(p->d_tw_phi),
-                                        reinterpret_cast<const double2*>(mixed), phys);
+  if (reduced(p))
+    phi_bwd256_kernel<float2, float><<<grid, VB, 0, s>>>(g, tw, reinterpret_cast<const float2*>(mixed),
+                                                         reinterpret_cast<float*>(phys));
+  else
+    phi_bwd256_kernel<double2, double><<<grid, VB, 0, s>>>(g, tw, reinterpret_cast<const double2*>(mixed), phys);
   p->timing.end(s);
   return check("phi_bwd256_kernel");
 }
 
-mlg_status launch_phi256_scalar(const mlg_plan_s* p, int kind, double gamma, double* mixed, hipStream_t s) {
-  Phi256 g = phi256_geom(p, p->g.dealias != 0);
+template <typename S2>
+static void phi_scalar_go(const mlg_plan_s* p, const Phi256& g, int kind, double gamma, double* mixed, hipStream_t s) {
   dim3 grid((unsigned)((g.nlines + PL - 1) / PL));
   const double2* tw = reinterpret_cast<const double2*>(p->d_tw_phi);
-  p->timing.begin("phi_fft", s);
   if (kind == MLG_RHS_U2)
-    phi_scalar256_kernel<MLG_RHS_U2><<<grid, VB, 0, s>>>(g, tw, reinterpret_cast<double2*>(mixed), gamma);
+    phi_scalar256_kernel<MLG_RHS_U2, S2><<<grid, VB, 0, s>>>(g, tw, reinterpret_cast<S2*>(mixed), gamma);
   else
-    phi_scalar256_kernel<MLG_RHS_KPP><<<grid, VB, 0, s>>>(g, tw, reinterpret_cast<double2*>(mixed), gamma);
+    phi_scalar256_kernel<MLG_RHS_KPP, S2><<<grid, VB, 0, s>>>(g, tw, reinterpret_cast<S2*>(mixed), gamma);
+}
+
+mlg_status launch_phi256_scalar(const mlg_plan_s* p, int kind, double gamma, double* mixed, hipStream_t s) {
+  Phi256 g = phi256_geom(p, p->g.dealias != 0);
+  p->timing.begin("phi_fft", s);
+  if (reduced(p))
+    phi_scalar_go<float2>(p, g, kind, gamma, mixed, s);
+  else
+    phi_scalar_go<double2>(p, g, kind, gamma, mixed, s);
   p->timing.end(s);
   return check("phi_scalar256_kernel");
 }
 
-mlg_status launch_phi256_vec(const mlg_plan_s* p, const double* U, double* const* f6, double* taps, hipStream_t s) {
-  Phi256 g = phi256_geom(p, p->g.dealias != 0);
-  Six256 six;
-  for (int i = 0; i < 6; ++i) six.f[i] = reinterpret_cast<double2*>(f6[i]);
+template <typename S2>
+static void phi_vec_go(const mlg_plan_s* p, const Phi256& g, const double* U, double* const* f6, double* taps,
+                       hipStream_t s) {
+  Six256<S2> six;
+  for (int i = 0; i < 6; ++i) six.f[i] = reinterpret_cast<S2*>(f6[i]);
   const double2* tw = reinterpret_cast<const double2*>(p->d_tw_phi);
   // interior blocks (all 8 lines present, 128 stored orders) load without guards; one more
   // launch covers the last partial block, if any
   const int64_t full = g.M >= 128 ? g.nlines / PL : 0;
   const int64_t nblk = (g.nlines + PL - 1) / PL;
-  p->timing.begin("phi_fft", s);
   if (full > 0)
-    phi_vec256_kernel<false><<<dim3((unsigned)full), VB, 0, s>>>(g, tw, six, p->d_node, U[0], U[1], U[2], taps, 0);
+    phi_vec256_kernel<false, S2><<<dim3((unsigned)full), VB, 0, s>>>(g, tw, six, p->d_node, U[0], U[1], U[2], taps, 0);
   if (nblk > full)
-    phi_vec256_kernel<true><<<dim3((unsigned)(nblk - full)), VB, 0, s>>>(g, tw, six, p->d_node, U[0], U[1], U[2],
-                                                                         taps, full);
+    phi_vec256_kernel<true, S2><<<dim3((unsigned)(nblk - full)), VB, 0, s>>>(g, tw, six, p->d_node, U[0], U[1], U[2],
+                                                                             taps, full);
+}
+
+mlg_status launch_phi256_vec(const mlg_plan_s* p, const double* U, double* const* f6, double* taps, hipStream_t s) {
+  Phi256 g = phi256_geom(p, p->g.dealias != 0);
+  p->timing.begin("phi_fft", s);
+  if (reduced(p))
+    phi_vec_go<float2>(p, g, U, f6, taps, s);
+  else
+    phi_vec_go<double2>(p, g, U, f6, taps, s);
   p->timing.end(s);
   return check("phi_vec256_kernel");
 }

@@ -30,16 +30,43 @@ constexpr int TM = 64;  // rows per block (half nodes, or pairs of degrees)
 constexpr int TC8 = 8;  // complex columns per block (re and im share the 16 MFMA columns)
 constexpr int TP = 8;   // k depth per LDS stage (pairs of degrees, or half nodes)
 
-#define MFMA(a, b, c) __builtin_amdgcn_mfma_f64_16x16x4f64((a), (b), (c), 0, 0, 0)
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// The 16 x 16 x 4 MFMA in the real type R of a plan's radial products: FP64 plans use
+// v_mfma_f64_16x16x4f64, MLG_FP32 plans v_mfma_f32_16x16x4f32.  Both take A[l % 16][l / 16] and
+// B[l / 16][l % 16] from lane l; accumulator value v of lane l holds C[row(l, v)][l % 16] with
+// row = l / 16 + 4 v (f64) or 4 (l / 16) + v (f32).
+template <typename R>
+struct Mma;
+template <>
+struct Mma<double> {
+  typedef double4_t acc;
+  static __device__ __forceinline__ acc op(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+  static __device__ __forceinline__ acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
+};
+template <>
+struct Mma<float> {
+  typedef float4_t acc;
+  static __device__ __forceinline__ acc op(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+  static __device__ __forceinline__ acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
+};
+#define MFMA(a, b, c) Mma<R>::op((a), (b), (c))
 
 __device__ __forceinline__ int kval(int kk, int nz) { return (2 * kk < nz) ? kk : kk - nz; }
 
+template <typename R, typename C2>
 struct FoldSynthArgs {
-  const double* Pb;        // backward Pbar tables, per m [n-m][i]
-  const double* Tb;        // backward Tbar tables
-  const double2* psi;
-  const double2* chi;
-  double2* out[6];         // mixed layout [m][i][kk]
+  const R* Pb;             // backward Pbar tables, per m [n-m][i]
+  const R* Tb;             // backward Tbar tables
+  const C2* psi;
+  const C2* chi;
+  C2* out[6];              // mixed layout [m][i][kk]
   const int64_t* off;
   const double* node;      // rinv[nr], q[nr], opx[nr]
   int nr, nrc, nz;
@@ -48,7 +75,8 @@ struct FoldSynthArgs {
 };
 
 // the Eq. tp harmonics of u and omega at node i from the seven products
-__device__ __forceinline__ void synth_write(const FoldSynthArgs& a, int m, int i, int kk, double kap,
+template <typename R, typename C2>
+__device__ __forceinline__ void synth_write(const FoldSynthArgs<R, C2>& a, int m, int i, int kk, double kap,
                                             const double2 (&p)[7]) {
   const int nr = a.nr, nz = a.nz;
   const double rinv = a.node[i], q = a.node[nr + i], opx = a.node[2 * nr + i];
@@ -64,19 +92,20 @@ __device__ __forceinline__ void synth_write(const FoldSynthArgs& a, int m, int i
                                   (-fm * kap * A1.y - q * (B4.y - 2.0 * opx * B3.y) - kap * kap * B2.y) * rinv);
   const double2 wz = make_double2(q * A3.x, q * A3.y);
   const int64_t o = ((int64_t)m * nr + i) * nz + kk;
-  a.out[0][o] = ur;
-  a.out[1][o] = up;
-  a.out[2][o] = uz;
-  a.out[3][o] = wr;
-  a.out[4][o] = wp;
-  a.out[5][o] = wz;
+  st2(a.out[0] + o, ur);
+  st2(a.out[1] + o, up);
+  st2(a.out[2] + o, uz);
+  st2(a.out[3] + o, wr);
+  st2(a.out[4] + o, wp);
+  st2(a.out[5] + o, wz);
 }
 
 // Block tile: 64 half nodes x 8 complex columns; the 16 MFMA columns hold [re 0..7 | im 0..7], so
 // lane l accumulates the real (l%16 < 8) or imaginary part of complex column (l%16) % 8; partner
 // lanes l and l ^ 8 exchange their parts in the epilogue, then one writes node i and the other
 // its mirror.
-__global__ __launch_bounds__(256, 2) void synth_fold_kernel(FoldSynthArgs a) {
+template <typename R, typename C2>
+__global__ __launch_bounds__(256, 2) void synth_fold_kernel(FoldSynthArgs<R, C2> a) {
   Tile3 tl;
   if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
   const int m = tl.z;
@@ -87,35 +116,35 @@ __global__ __launch_bounds__(256, 2) void synth_fold_kernel(FoldSynthArgs a) {
   const int K = a.nrc > m ? a.nrc - m : 0;
   const int KP = (K + 1) / 2;
   const int nr = a.nr, nz = a.nz;
-  const double* __restrict__ P = a.Pb + a.off[m] * nr;
-  const double* __restrict__ T = a.Tb + a.off[m] * nr;
-  const double2* __restrict__ ps = a.psi + a.off[m] * nz;
-  const double2* __restrict__ ch = a.chi + a.off[m] * nz;
+  const R* __restrict__ P = a.Pb + a.off[m] * nr;
+  const R* __restrict__ T = a.Tb + a.off[m] * nr;
+  const C2* __restrict__ ps = a.psi + a.off[m] * nz;
+  const C2* __restrict__ ch = a.chi + a.off[m] * nz;
 
-  __shared__ double As[2][2][2][TP][TM];  // [buf][P, T][parity][pair][half node]
-  __shared__ double Bs[2][2][2][TP][16];  // [buf][psi, chi][parity][pair][re 0..7 | im 0..7]
+  __shared__ R As[2][2][2][TP][TM];  // [buf][P, T][parity][pair][half node]
+  __shared__ R Bs[2][2][2][TP][16];  // [buf][psi, chi][parity][pair][re 0..7 | im 0..7]
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int cl = lane & 15;
-  double4_t acc[2][7];  // [parity][product]
+  typename Mma<R>::acc acc[2][7];  // [parity][product]
 #pragma unroll
   for (int s = 0; s < 2; ++s)
 #pragma unroll
-    for (int p = 0; p < 7; ++p) acc[s][p] = double4_t{0.0, 0.0, 0.0, 0.0};
+    for (int p = 0; p < 7; ++p) acc[s][p] = Mma<R>::zero();
 
   // Operands of the next two stages alternate between two register sets.  Every load is
   // unconditional (indices clamped into the table; entries outside it are zeroed when written to
   // LDS), so writing one set waits only for that set while the other set's loads stay in flight
   // across the MFMAs of the current stage.
   struct Stage {
-    double a[8];
-    double2 b;
+    R a[8];
+    C2 b;
   };
   Stage sx, sy;
   const int Kc = K > 0 ? K - 1 : 0;
   const int fld = tid >> 7, bpar = (tid >> 6) & 1, bkr = (tid >> 3) & 7, bcc = tid & 7;
   const int bkk = kk0 + bcc;
-  const double2* __restrict__ Bsrc = (fld ? ch : ps) + (bkk < nz ? bkk : nz - 1);
+  const C2* __restrict__ Bsrc = (fld ? ch : ps) + (bkk < nz ? bkk : nz - 1);
   auto load = [&](int jj0, Stage& d) {
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
@@ -133,11 +162,11 @@ __global__ __launch_bounds__(256, 2) void synth_fold_kernel(FoldSynthArgs a) {
       const int e = tid + 256 * t;
       const int par = (e >> 9) & 1, kr = (e >> 6) & 7, rr = e & 63;
       const bool ok = 2 * (jj0 + kr) + par < K && row0 + rr < half;
-      As[buf][t >> 2][par][kr][rr] = ok ? d.a[t] : 0.0;
+      As[buf][t >> 2][par][kr][rr] = ok ? d.a[t] : R(0);
     }
     const bool ok = 2 * (jj0 + bkr) + bpar < K && bkk < nz;
-    Bs[buf][fld][bpar][bkr][bcc] = ok ? d.b.x : 0.0;
-    Bs[buf][fld][bpar][bkr][8 + bcc] = ok ? d.b.y : 0.0;
+    Bs[buf][fld][bpar][bkr][bcc] = ok ? d.b.x : R(0);
+    Bs[buf][fld][bpar][bkr][8 + bcc] = ok ? d.b.y : R(0);
   };
   auto compute = [&](int buf, int kt) {
 #pragma unroll
@@ -145,13 +174,13 @@ __global__ __launch_bounds__(256, 2) void synth_fold_kernel(FoldSynthArgs a) {
       const int kr = ks + (lane >> 4);
 #pragma unroll
       for (int par = 0; par < 2; ++par) {
-        const double n = (double)(m + 2 * (kt * TP + kr) + par);
-        const double Ln = n * (n + 1.0);
-        const double aP = As[buf][0][par][kr][wave * 16 + cl];
-        const double aT = As[buf][1][par][kr][wave * 16 + cl];
-        const double bp = Bs[buf][0][par][kr][cl], bc = Bs[buf][1][par][kr][cl];
-        const double lp = Ln * bp, lc = Ln * bc;
-        double4_t(&c)[7] = acc[par];
+        const R n = (R)(m + 2 * (kt * TP + kr) + par);
+        const R Ln = n * (n + R(1));
+        const R aP = As[buf][0][par][kr][wave * 16 + cl];
+        const R aT = As[buf][1][par][kr][wave * 16 + cl];
+        const R bp = Bs[buf][0][par][kr][cl], bc = Bs[buf][1][par][kr][cl];
+        const R lp = Ln * bp, lc = Ln * bc;
+        typename Mma<R>::acc(&c)[7] = acc[par];
         c[0] = MFMA(aP, bp, c[0]);  // A1 = Pbar psi
         c[1] = MFMA(aT, bp, c[1]);  // A2 = Tbar psi
         c[2] = MFMA(aP, lp, c[2]);  // A3 = Pbar L psi
@@ -195,11 +224,11 @@ __global__ __launch_bounds__(256, 2) void synth_fold_kernel(FoldSynthArgs a) {
   constexpr bool tsign[7] = {false, true, false, false, true, false, true};
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int i = row0 + wave * 16 + (lane >> 4) + 4 * v;
+    const int i = row0 + wave * 16 + Mma<R>::row(lane, v);
     double2 val[7];
 #pragma unroll
     for (int p = 0; p < 7; ++p) {
-      const double e = acc[0][p][v], o = acc[1][p][v];
+      const double e = (double)acc[0][p][v], o = (double)acc[1][p][v];
       const double e2 = __shfl_xor(e, 8), o2 = __shfl_xor(o, 8);
       const double er = hi ? e2 : e, ei = hi ? e : e2, orr = hi ? o2 : o, oi = hi ? o : o2;
       // the low lane writes node i (E + O), the high lane the mirror node
@@ -210,10 +239,11 @@ __global__ __launch_bounds__(256, 2) void synth_fold_kernel(FoldSynthArgs a) {
   }
 }
 
+template <typename C2>
 struct FoldProjArgs {
   const double* Pf;        // forward W Pbar tables, per m [i][n-m]
   const double* Qf;        // forward W Q tables
-  const double2* in[3];    // harmonics of N_r/r, N_phi/r, N_z (mixed [m][i][kk])
+  const C2* in[3];         // harmonics of N_r/r, N_phi/r, N_z (mixed [m][i][kk]; float2 for reduced plans)
   double2* out[3];         // C, K', Zhat (packed triangular)
   const int64_t* off;
   int nr, nrc, nz, kmax, nkact;
@@ -228,7 +258,9 @@ __device__ __forceinline__ int active_kk(int a, int kmax, int nz) {
 // Block tile: 64 pairs of degrees (even and odd n - m) x 8 complex columns, [re | im] packed in
 // the 16 MFMA columns as in synth_fold_kernel; the low lane of a partner pair writes the even
 // degree, the high lane the odd one.
-__global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs a) {
+template <typename C2>
+__global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs<C2> a) {
+  typedef double R;
   Tile3 tl;
   if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
   const int m = tl.z;
@@ -256,7 +288,7 @@ __global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs a) {
   const int bf = tid >> 6, bkr = (tid >> 3) & 7, bcc = tid & 7;
   const int bca = c0 + bcc;
   const int bkk = (tid < 192 && bca < a.nkact) ? active_kk(bca, a.kmax, nz) : -1;
-  const double2* __restrict__ Xb = (tid < 192) ? a.in[bf] + (int64_t)m * nr * nz : nullptr;
+  const C2* __restrict__ Xb = (tid < 192) ? a.in[bf] + (int64_t)m * nr * nz : nullptr;
   // operands of the next two stages in registers (raw loads; sums and differences are formed
   // when they are written to LDS, so the loads stay in flight across the MFMAs)
   struct Stage {
@@ -277,8 +309,8 @@ __global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs a) {
     }
     const int i = i0 + bkr;
     const bool ok = bkk >= 0 && i < half;
-    d.x = ok ? Xb[(int64_t)i * nz + bkk] : make_double2(0.0, 0.0);
-    d.y = ok ? Xb[(int64_t)(nr - 1 - i) * nz + bkk] : make_double2(0.0, 0.0);
+    d.x = ok ? ld2(Xb + (int64_t)i * nz + bkk) : make_double2(0.0, 0.0);
+    d.y = ok ? ld2(Xb + (int64_t)(nr - 1 - i) * nz + bkk) : make_double2(0.0, 0.0);
   };
   auto store = [&](int buf, const Stage& d) {
 #pragma unroll
@@ -364,17 +396,19 @@ __global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs a) {
 constexpr int SC_N = 64;  // real columns per block
 constexpr int SC_P = 8;   // pairs (backward) or half nodes (forward) per LDS stage
 
+template <typename R>
 struct ScalarFoldArgs {
-  const double* A;   // backward: Pbar [m][n-m][i]; forward: w Pbar [m][i][n-m]
-  const double* B;   // backward: spectral rows [tau][ncol]; forward: harmonics [m][i][ncol]
-  double* C;         // backward: harmonics [m][i][ncol]; forward: spectral rows [tau][ncol]
+  const R* A;        // backward: Pbar [m][n-m][i]; forward: w Pbar [m][i][n-m]
+  const R* B;        // backward: spectral rows [tau][ncol]; forward: harmonics [m][i][ncol]
+  R* C;              // backward: harmonics [m][i][ncol]; forward: spectral rows [tau][ncol]
   const int64_t* off;
   int nr, nrc, ncol;
   int gx, gy, gz;
 };
 
 // backward: f(i) = E(i) + O(i), f(N-1-i) = E(i) - O(i), E / O over even / odd n - m, i < N/2
-__global__ __launch_bounds__(256) void scal_bwd_fold_kernel(ScalarFoldArgs a) {
+template <typename R>
+__global__ __launch_bounds__(256) void scal_bwd_fold_kernel(ScalarFoldArgs<R> a) {
   Tile3 tl;
   if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
   const int m = tl.z;
@@ -383,18 +417,18 @@ __global__ __launch_bounds__(256) void scal_bwd_fold_kernel(ScalarFoldArgs a) {
   if (row0 >= half || col0 >= ncol) return;
   const int K = a.nrc > m ? a.nrc - m : 0;
   const int KP = (K + 1) / 2;
-  const double* __restrict__ A = a.A + a.off[m] * nr;
-  const double* __restrict__ B = a.B + a.off[m] * ncol;
-  double* __restrict__ C = a.C + (int64_t)m * nr * ncol;
-  __shared__ double As[2][2][SC_P][TM];    // [buf][parity][pair][half node]
-  __shared__ double Bs[2][2][SC_P][SC_N];  // [buf][parity][pair][column]
+  const R* __restrict__ A = a.A + a.off[m] * nr;
+  const R* __restrict__ B = a.B + a.off[m] * ncol;
+  R* __restrict__ C = a.C + (int64_t)m * nr * ncol;
+  __shared__ R As[2][2][SC_P][TM];    // [buf][parity][pair][half node]
+  __shared__ R Bs[2][2][SC_P][SC_N];  // [buf][parity][pair][column]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, cl = lane & 15;
-  double4_t acc[2][4];
+  typename Mma<R>::acc acc[2][4];
 #pragma unroll
   for (int q = 0; q < 2; ++q)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[q][c] = double4_t{0.0, 0.0, 0.0, 0.0};
-  double ra[4], rb[4];
+    for (int c = 0; c < 4; ++c) acc[q][c] = Mma<R>::zero();
+  R ra[4], rb[4];
   auto load = [&](int p0) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -413,8 +447,8 @@ __global__ __launch_bounds__(256) void scal_bwd_fold_kernel(ScalarFoldArgs a) {
       const int e = tid + 256 * t;
       const int par = e >> 9, kr = (e >> 6) & 7, cc = e & 63;
       const bool jin = 2 * (p0 + kr) + par < K;
-      As[buf][par][kr][cc] = (jin && row0 + cc < half) ? ra[t] : 0.0;
-      Bs[buf][par][kr][cc] = (jin && col0 + cc < ncol) ? rb[t] : 0.0;
+      As[buf][par][kr][cc] = (jin && row0 + cc < half) ? ra[t] : R(0);
+      Bs[buf][par][kr][cc] = (jin && col0 + cc < ncol) ? rb[t] : R(0);
     }
   };
   const int nk = (KP + SC_P - 1) / SC_P;
@@ -431,7 +465,7 @@ __global__ __launch_bounds__(256) void scal_bwd_fold_kernel(ScalarFoldArgs a) {
       const int kr = ks + (lane >> 4);
 #pragma unroll
       for (int par = 0; par < 2; ++par) {
-        const double av = As[buf][par][kr][wave * 16 + cl];
+        const R av = As[buf][par][kr][wave * 16 + cl];
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[par][c] = MFMA(av, Bs[buf][par][kr][c * 16 + cl], acc[par][c]);
       }
@@ -445,9 +479,9 @@ __global__ __launch_bounds__(256) void scal_bwd_fold_kernel(ScalarFoldArgs a) {
     if (col >= ncol) continue;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int i = row0 + wave * 16 + (lane >> 4) + 4 * v;
+      const int i = row0 + wave * 16 + Mma<R>::row(lane, v);
       if (i >= half) continue;
-      const double e = acc[0][c][v], o = acc[1][c][v];
+      const R e = acc[0][c][v], o = acc[1][c][v];
       C[(int64_t)i * ncol + col] = e + o;
       C[(int64_t)(nr - 1 - i) * ncol + col] = e - o;
     }
@@ -455,7 +489,8 @@ __global__ __launch_bounds__(256) void scal_bwd_fold_kernel(ScalarFoldArgs a) {
 }
 
 // forward: even n - m rows contract with X_i + X_{N-1-i}, odd rows with the difference, i < N/2
-__global__ __launch_bounds__(256) void scal_fwd_fold_kernel(ScalarFoldArgs a) {
+template <typename R>
+__global__ __launch_bounds__(256) void scal_fwd_fold_kernel(ScalarFoldArgs<R> a) {
   Tile3 tl;
   if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
   const int m = tl.z;
@@ -464,18 +499,18 @@ __global__ __launch_bounds__(256) void scal_fwd_fold_kernel(ScalarFoldArgs a) {
   const int half = a.nr / 2, nr = a.nr, ncol = a.ncol;
   const int row0 = tl.y * TM, col0 = tl.x * SC_N;  // row0: pair index
   if (row0 >= KP || col0 >= ncol) return;
-  const double* __restrict__ A = a.A + a.off[m] * nr;      // [i][n-m], row length K
-  const double* __restrict__ B = a.B + (int64_t)m * nr * ncol;
-  double* __restrict__ C = a.C + a.off[m] * ncol;
-  __shared__ double As[2][2][SC_P][TM];    // [buf][parity][half node][pair]
-  __shared__ double Bs[2][2][SC_P][SC_N];  // [buf][sum, difference][half node][column]
+  const R* __restrict__ A = a.A + a.off[m] * nr;      // [i][n-m], row length K
+  const R* __restrict__ B = a.B + (int64_t)m * nr * ncol;
+  R* __restrict__ C = a.C + a.off[m] * ncol;
+  __shared__ R As[2][2][SC_P][TM];    // [buf][parity][half node][pair]
+  __shared__ R Bs[2][2][SC_P][SC_N];  // [buf][sum, difference][half node][column]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, cl = lane & 15;
-  double4_t acc[2][4];
+  typename Mma<R>::acc acc[2][4];
 #pragma unroll
   for (int q = 0; q < 2; ++q)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[q][c] = double4_t{0.0, 0.0, 0.0, 0.0};
-  double ra[4], rx[2], ry[2];
+    for (int c = 0; c < 4; ++c) acc[q][c] = Mma<R>::zero();
+  R ra[4], rx[2], ry[2];
   auto load = [&](int i0) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -501,15 +536,15 @@ __global__ __launch_bounds__(256) void scal_fwd_fold_kernel(ScalarFoldArgs a) {
       const int e = tid + 256 * t;
       const int par = e >> 9, kr = (e >> 6) & 7, rr = e & 63;
       const bool ok = i0 + kr < half && 2 * (row0 + rr) + par < K;
-      As[buf][par][kr][rr] = ok ? ra[t] : 0.0;
+      As[buf][par][kr][rr] = ok ? ra[t] : R(0);
     }
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       const int e = tid + 256 * t;
       const int kr = e >> 6, cc = e & 63;
       const bool ok = i0 + kr < half && col0 + cc < ncol;
-      Bs[buf][0][kr][cc] = ok ? rx[t] + ry[t] : 0.0;
-      Bs[buf][1][kr][cc] = ok ? rx[t] - ry[t] : 0.0;
+      Bs[buf][0][kr][cc] = ok ? rx[t] + ry[t] : R(0);
+      Bs[buf][1][kr][cc] = ok ? rx[t] - ry[t] : R(0);
     }
   };
   const int nk = (half + SC_P - 1) / SC_P;
@@ -524,7 +559,7 @@ __global__ __launch_bounds__(256) void scal_fwd_fold_kernel(ScalarFoldArgs a) {
       const int kr = ks + (lane >> 4);
 #pragma unroll
       for (int par = 0; par < 2; ++par) {
-        const double av = As[buf][par][kr][wave * 16 + cl];
+        const R av = As[buf][par][kr][wave * 16 + cl];
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[par][c] = MFMA(av, Bs[buf][par][kr][c * 16 + cl], acc[par][c]);
       }
@@ -538,7 +573,7 @@ __global__ __launch_bounds__(256) void scal_fwd_fold_kernel(ScalarFoldArgs a) {
     if (col >= ncol) continue;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int pr = row0 + wave * 16 + (lane >> 4) + 4 * v;
+      const int pr = row0 + wave * 16 + Mma<R>::row(lane, v);
 #pragma unroll
       for (int par = 0; par < 2; ++par) {
         const int j = 2 * pr + par;
@@ -556,14 +591,15 @@ mlg_status check(const char* what) {
 
 }  // namespace
 
-mlg_status launch_synth_fold(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,
-                             hipStream_t s) {
-  FoldSynthArgs a{};
-  a.Pb = p->d_Pb;
-  a.Tb = p->d_Tb;
-  a.psi = reinterpret_cast<const double2*>(psi);
-  a.chi = reinterpret_cast<const double2*>(chi);
-  for (int i = 0; i < 6; ++i) a.out[i] = reinterpret_cast<double2*>(out6[i]);
+template <typename R, typename C2>
+static void synth_fold_go(const mlg_plan_s* p, const R* Pb, const R* Tb, const double* psi, const double* chi,
+                          double* const* out6, hipStream_t s) {
+  FoldSynthArgs<R, C2> a{};
+  a.Pb = Pb;
+  a.Tb = Tb;
+  a.psi = reinterpret_cast<const C2*>(psi);
+  a.chi = reinterpret_cast<const C2*>(chi);
+  for (int i = 0; i < 6; ++i) a.out[i] = reinterpret_cast<C2*>(out6[i]);
   a.off = p->d_goff;
   a.node = p->d_node;
   a.nr = p->nr;
@@ -573,19 +609,30 @@ mlg_status launch_synth_fold(const mlg_plan_s* p, const double* psi, const doubl
   a.gx = (p->nz + TC8 - 1) / TC8;
   a.gy = (p->nr / 2 + TM - 1) / TM;
   a.gz = p->M;
+  synth_fold_kernel<R, C2><<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
+}
+
+// psi, chi: spectral arrays of the plan's data type; out6: mixed harmonics (float2 on MLG_FP32
+// plans, whose products run on FP32 MFMA with the FP32 tables)
+mlg_status launch_synth_fold(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,
+                             hipStream_t s) {
   p->timing.begin("synth_gemm", s);
-  synth_fold_kernel<<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
+  if (p->prec == MLG_FP32)
+    synth_fold_go<float, float2>(p, p->d_Pb32, p->d_Tb32, psi, chi, out6, s);
+  else
+    synth_fold_go<double, double2>(p, p->d_Pb, p->d_Tb, psi, chi, out6, s);
   p->timing.end(s);
   return check("synth_fold_kernel");
 }
 
-mlg_status launch_proj_fold(const mlg_plan_s* p, double* const* in3, double* const* out3, int mmax, int kmax,
-                            hipStream_t s) {
-  FoldProjArgs a{};
+template <typename C2>
+static void proj_fold_go(const mlg_plan_s* p, double* const* in3, double* const* out3, int kmax, int mmax,
+                         hipStream_t s) {
+  FoldProjArgs<C2> a{};
   a.Pf = p->d_Pf;
   a.Qf = p->d_Qf;
   for (int i = 0; i < 3; ++i) {
-    a.in[i] = reinterpret_cast<const double2*>(in3[i]);
+    a.in[i] = reinterpret_cast<const C2*>(in3[i]);
     a.out[i] = reinterpret_cast<double2*>(out3[i]);
   }
   a.off = p->d_goff;
@@ -595,22 +642,33 @@ mlg_status launch_proj_fold(const mlg_plan_s* p, double* const* in3, double* con
   a.kmax = kmax;
   a.nkact = (p->nz == 1) ? 1 : 2 * kmax + 1;
   a.kap0 = 2.0 * M_PI / p->g.lz;
-  if (mmax <= 0 || a.nkact <= 0) return MLG_OK;
   const int kp = (p->nrc + 1) / 2;
   a.gx = (a.nkact + TC8 - 1) / TC8;
   a.gy = (kp + TM - 1) / TM;
   a.gz = mmax;
+  proj_fold_kernel<C2><<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
+}
+
+// in3: harmonics of N (float2 on reduced-precision plans); out3: FP64 sources in every case
+mlg_status launch_proj_fold(const mlg_plan_s* p, double* const* in3, double* const* out3, int mmax, int kmax,
+                            hipStream_t s) {
+  const int nkact = (p->nz == 1) ? 1 : 2 * kmax + 1;
+  if (mmax <= 0 || nkact <= 0) return MLG_OK;
   p->timing.begin("proj_gemm", s);
-  proj_fold_kernel<<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
+  if (p->prec != MLG_FP64)
+    proj_fold_go<float2>(p, in3, out3, kmax, mmax, s);
+  else
+    proj_fold_go<double2>(p, in3, out3, kmax, mmax, s);
   p->timing.end(s);
   return check("proj_fold_kernel");
 }
 
-mlg_status launch_scalar_fold(const mlg_plan_s* p, int dir, const double* B, double* C, hipStream_t s) {
-  ScalarFoldArgs a{};
-  a.A = dir > 0 ? p->d_Pb : p->d_Pf;
-  a.B = B;
-  a.C = C;
+template <typename R>
+static void scalar_fold_go(const mlg_plan_s* p, int dir, const R* A, const double* B, double* C, hipStream_t s) {
+  ScalarFoldArgs<R> a{};
+  a.A = A;
+  a.B = reinterpret_cast<const R*>(B);
+  a.C = reinterpret_cast<R*>(C);
   a.off = p->d_goff;
   a.nr = p->nr;
   a.nrc = p->nrc;
@@ -618,11 +676,18 @@ mlg_status launch_scalar_fold(const mlg_plan_s* p, int dir, const double* B, dou
   a.gx = (a.ncol + SC_N - 1) / SC_N;
   a.gy = dir > 0 ? (p->nr / 2 + TM - 1) / TM : ((p->nrc + 1) / 2 + TM - 1) / TM;
   a.gz = p->M;
-  p->timing.begin("radial_gemm", s);
   if (dir > 0)
-    scal_bwd_fold_kernel<<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
+    scal_bwd_fold_kernel<R><<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
   else
-    scal_fwd_fold_kernel<<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
+    scal_fwd_fold_kernel<R><<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
+}
+
+mlg_status launch_scalar_fold(const mlg_plan_s* p, int dir, const double* B, double* C, hipStream_t s) {
+  p->timing.begin("radial_gemm", s);
+  if (p->prec == MLG_FP32)
+    scalar_fold_go<float>(p, dir, dir > 0 ? p->d_Pb32 : p->d_Pf32, B, C, s);
+  else
+    scalar_fold_go<double>(p, dir, dir > 0 ? p->d_Pb : p->d_Pf, B, C, s);
   p->timing.end(s);
   return check(dir > 0 ? "scal_bwd_fold_kernel" : "scal_fwd_fold_kernel");
 }

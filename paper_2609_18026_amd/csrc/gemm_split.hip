@@ -2,7 +2,8 @@
 // MLG_SPLIT_BF16).  Every operand x is represented as hi + lo with hi = bf16(x) and
 // lo = bf16(x - hi); a product is accumulated in FP32 as hi_a hi_b + hi_a lo_b + lo_a hi_b
 // (the lo_a lo_b term, ~2^-18 relative, is dropped) with v_mfma_f32_16x16x32_bf16.
-// Tables are split once on the host; the FP64 data are split while they are staged in LDS.
+// Tables are split once on the host; the data (float / float2: split plans keep their fields in FP32)
+// are split while they are staged in LDS.
 // The epilogues, layouts and outputs are those of the FP64 kernels in gemm_fused.hip.
 //
 // MFMA operand layout (16x16x32 bf16): lane l supplies A[l%16][8(l/16) .. 8(l/16)+7] and
@@ -56,13 +57,14 @@ __device__ __forceinline__ bf16x8 ldfrag(const unsigned short* p) {
   return __builtin_bit_cast(bf16x8, v);
 }
 
+template <typename C2>
 struct SplitSynthArgs {
   const unsigned short* tab[4];  // Pbar hi, Pbar lo, Tbar hi, Tbar lo: per m [i][kpad], k = n - m
   const int64_t* toff;           // per m element offset of the split tables
   const int32_t* kpad;           // per m padded K (multiple of 32)
-  const double2* psi;
-  const double2* chi;
-  double2* out[6];
+  const C2* psi;                 // spectra of the plan's data type (float2 on split plans)
+  const C2* chi;
+  C2* out[6];
   const int64_t* off;
   const double* node;
   int nr, nrc, nz;
@@ -71,11 +73,12 @@ struct SplitSynthArgs {
 };
 
 // B staging: [buf][var][col][k] with var = input(psi, chi) x scaled(1, L) x part(re, im) x (hi, lo).
-// The FP64 operands of the next two K stages and the table fragments of the next one are held in
+// The raw operands of the next two K stages and the table fragments of the next one are held in
 // registers as raw loads; the scaling by L and the bf16 split happen when they are written to LDS,
 // after the MFMAs of the current stage, so the loads stay in flight across them.  At 3 waves per
 // SIMD (156 VGPRs, the accumulators leave the AGPRs) the latency of the next stage is better hidden.
-__global__ __launch_bounds__(256, 3) void split_synth_kernel(SplitSynthArgs a) {
+template <typename C2>
+__global__ __launch_bounds__(256, 3) void split_synth_kernel(SplitSynthArgs<C2> a) {
   Tile3 tl;
   if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
   const int m = tl.z;
@@ -85,8 +88,8 @@ __global__ __launch_bounds__(256, 3) void split_synth_kernel(SplitSynthArgs a) {
   const int K = a.nrc > m ? a.nrc - m : 0;
   const int nr = a.nr, nz = a.nz;
   const int kp = a.kpad[m];
-  const double2* __restrict__ ps = a.psi + a.off[m] * nz;
-  const double2* __restrict__ ch = a.chi + a.off[m] * nz;
+  const C2* __restrict__ ps = a.psi + a.off[m] * nz;
+  const C2* __restrict__ ch = a.chi + a.off[m] * nz;
   __shared__ __attribute__((aligned(16))) unsigned short Bs[2][16][TC][TK];  // 32 KB
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rowl = row0 + wave * 16 + (lane & 15);
@@ -102,7 +105,7 @@ __global__ __launch_bounds__(256, 3) void split_synth_kernel(SplitSynthArgs a) {
 
   // each thread stages 2 (k, col) entries of psi and chi per chunk
   struct Stage {
-    double2 p[2], c[2];
+    C2 p[2], c[2];
   };
   auto load = [&](int k0, Stage& d) {
 #pragma unroll
@@ -110,8 +113,8 @@ __global__ __launch_bounds__(256, 3) void split_synth_kernel(SplitSynthArgs a) {
       const int e = tid + 256 * h;
       const int k = k0 + (e >> 4), kk = kk0 + (e & 15);
       const bool ok = k < K && kk < nz;
-      d.p[h] = ok ? ps[(int64_t)k * nz + kk] : make_double2(0.0, 0.0);
-      d.c[h] = ok ? ch[(int64_t)k * nz + kk] : make_double2(0.0, 0.0);
+      d.p[h] = ok ? ps[(int64_t)k * nz + kk] : czero<C2>();
+      d.c[h] = ok ? ch[(int64_t)k * nz + kk] : czero<C2>();
     }
   };
   auto store = [&](int buf, int k0, const Stage& d) {
@@ -201,12 +204,12 @@ __global__ __launch_bounds__(256, 3) void split_synth_kernel(SplitSynthArgs a) {
                                     (-fm * kap * A1.y - q * (B4.y - 2.0 * opx * B3.y) - kap * kap * B2.y) * rinv);
     const double2 wz = make_double2(q * A3.x, q * A3.y);
     const int64_t o = ((int64_t)m * nr + i) * nz + kk;
-    a.out[0][o] = ur;
-    a.out[1][o] = up;
-    a.out[2][o] = uz;
-    a.out[3][o] = wr;
-    a.out[4][o] = wp;
-    a.out[5][o] = wz;
+    st2(a.out[0] + o, ur);
+    st2(a.out[1] + o, up);
+    st2(a.out[2] + o, uz);
+    st2(a.out[3] + o, wr);
+    st2(a.out[4] + o, wp);
+    st2(a.out[5] + o, wz);
   }
 }
 
@@ -216,8 +219,8 @@ struct SplitScalarArgs {
   const int64_t* toff;           // per m element offset of the tables
   const int32_t* kpad;           // backward: per m row stride
   int ipad;                      // forward: row stride
-  const double2* in;             // backward: spectrum [tau][nz]; forward: harmonics [m][i][nz]
-  double2* out;                  // backward: harmonics [m][i][nz]; forward: spectrum [tau][nz]
+  const float2* in;              // backward: spectrum [tau][nz]; forward: harmonics [m][i][nz]
+  float2* out;                   // backward: harmonics [m][i][nz]; forward: spectrum [tau][nz]
   const int64_t* off;            // packed offset of each order
   int nr, nrc, nz;
   int gx, gy, gz;                // tiles: column blocks, row blocks, orders
@@ -226,7 +229,7 @@ struct SplitScalarArgs {
 // Radial products of the scalar transform pair (Sec. 4.1) with split-bfloat16 operands:
 // backward f_m[i][kk] = sum_n Pbar_n^m(x_i) s[n][kk], forward s[n][kk] = sum_i w_i Pbar_n^m(x_i)
 // f_m[i][kk].  The real table is the MFMA A operand; the re and im parts of the complex data are
-// two B operands.  The FP64 operands of the next two K stages and the table fragments of the next one
+// two B operands.  The raw operands of the next two K stages and the table fragments of the next one
 // are held in registers as raw loads and split into bf16 at the LDS store (as in split_synth_kernel).
 template <bool FWD>
 __global__ __launch_bounds__(256) void split_scalar_kernel(SplitScalarArgs a) {
@@ -241,8 +244,8 @@ __global__ __launch_bounds__(256) void split_scalar_kernel(SplitScalarArgs a) {
   if (row0 >= rows || kk0 >= a.nz) return;
   const int nz = a.nz;
   const int ld = FWD ? a.ipad : a.kpad[m];
-  const double2* __restrict__ X = a.in + (FWD ? (int64_t)m * a.nr : a.off[m]) * nz;
-  double2* __restrict__ Y = a.out + (FWD ? a.off[m] : (int64_t)m * a.nr) * nz;
+  const float2* __restrict__ X = a.in + (FWD ? (int64_t)m * a.nr : a.off[m]) * nz;
+  float2* __restrict__ Y = a.out + (FWD ? a.off[m] : (int64_t)m * a.nr) * nz;
   __shared__ __attribute__((aligned(16))) unsigned short Bs[2][4][TC][TK];  // [buf][re hi, re lo, im hi, im lo]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rowl = row0 + wave * 16 + (lane & 15);
@@ -253,14 +256,14 @@ __global__ __launch_bounds__(256) void split_scalar_kernel(SplitScalarArgs a) {
   for (int t = 0; t < 2; ++t) tp[t] = a.tab[t] + a.toff[m] + (int64_t)(rowok ? rowl : 0) * ld + kg;
   floatx4 acc[2] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
   struct Stage {
-    double2 v[2];
+    float2 v[2];
   };
   auto load = [&](int k0, Stage& d) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int e = tid + 256 * h;
       const int k = k0 + (e >> 4), kk = kk0 + (e & 15);
-      d.v[h] = (k < kdim && kk < nz) ? X[(int64_t)k * nz + kk] : make_double2(0.0, 0.0);
+      d.v[h] = (k < kdim && kk < nz) ? X[(int64_t)k * nz + kk] : make_float2(0.f, 0.f);
     }
   };
   auto store = [&](int buf, const Stage& d) {
@@ -312,7 +315,7 @@ __global__ __launch_bounds__(256) void split_scalar_kernel(SplitScalarArgs a) {
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int r = row0 + wave * 16 + 4 * (lane >> 4) + v;
-    if (r < rows) Y[(int64_t)r * nz + kk] = make_double2(acc[0][v], acc[1][v]);
+    if (r < rows) Y[(int64_t)r * nz + kk] = make_float2(acc[0][v], acc[1][v]);
   }
 }
 
@@ -328,8 +331,8 @@ __global__ __launch_bounds__(256) void split_scalar_kernel(SplitScalarArgs a) {
 // in the lane.  No LDS and no lane exchange; the per-lane constants come from a plan table.
 struct ZdftArgs {
   const uint4* tab;     // [dir][lane][10] (40 words, see plan construction)
-  const double2* in[6];
-  double2* out[6];
+  const float2* in[6];  // split plans keep their fields as float2
+  float2* out[6];
   int64_t rows;         // lines per field
   int64_t lines;        // rows x fields
   int nzc;
@@ -349,12 +352,12 @@ __global__ __launch_bounds__(256) void split_zdft_kernel(ZdftArgs a) {
   const int64_t L0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * ZD_LPW;
   if (L0 >= a.lines) return;
   const int g = lane >> 4, c = lane & 15;
-  double2 d[ZD_LPW][4];
+  float2 d[ZD_LPW][4];
 #pragma unroll
   for (int t = 0; t < ZD_LPW; ++t) {
     const int64_t L = L0 + t < a.lines ? L0 + t : L0;  // the last wave may hold fewer lines
     const int64_t f = L / a.rows, row = L - f * a.rows;
-    const double2* __restrict__ x = a.in[f] + row * 256;
+    const float2* __restrict__ x = a.in[f] + row * 256;
 #pragma unroll
     for (int j = 0; j < 4; ++j) d[t][j] = x[lane + 64 * j];
   }
@@ -374,8 +377,8 @@ __global__ __launch_bounds__(256) void split_zdft_kernel(ZdftArgs a) {
     u16x8 ah, al;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      double2 v = d[t][j];
-      if (INV && !zkept(lane + 64 * j, a.nzc)) v = make_double2(0.0, 0.0);
+      float2 v = d[t][j];
+      if (INV && !zkept(lane + 64 * j, a.nzc)) v = make_float2(0.f, 0.f);
       unsigned short h, l;
       split2(v.x, h, l);
       ah[2 * j] = h;
@@ -405,7 +408,7 @@ __global__ __launch_bounds__(256) void split_zdft_kernel(ZdftArgs a) {
     const floatx4 zr = mfma3(a2rh, a2rl, yh, yl, zero);
     const floatx4 zi = mfma3(a2ih, a2il, yh, yl, zero);
     const int64_t f = L / a.rows, row = L - f * a.rows;
-    double2* __restrict__ y = a.out[f] + row * 256;
+    float2* __restrict__ y = a.out[f] + row * 256;
     const int mrow = (!INV && a.row_m) ? a.row_m[row] : 0;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -420,7 +423,7 @@ __global__ __launch_bounds__(256) void split_zdft_kernel(ZdftArgs a) {
         }
         if (!keep) o = make_double2(0.0, 0.0);
       }
-      y[kk] = o;
+      st2(y + kk, o);
     }
   }
 }
@@ -435,13 +438,13 @@ mlg_status check(const char* what) {
 
 mlg_status launch_split_synth(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,
                               hipStream_t s) {
-  SplitSynthArgs a{};
+  SplitSynthArgs<float2> a{};
   for (int t = 0; t < 4; ++t) a.tab[t] = p->d_split_syn[t];
   a.toff = p->d_split_syn_off;
   a.kpad = p->d_split_syn_kpad;
-  a.psi = reinterpret_cast<const double2*>(psi);
-  a.chi = reinterpret_cast<const double2*>(chi);
-  for (int i = 0; i < 6; ++i) a.out[i] = reinterpret_cast<double2*>(out6[i]);
+  a.psi = reinterpret_cast<const float2*>(psi);
+  a.chi = reinterpret_cast<const float2*>(chi);
+  for (int i = 0; i < 6; ++i) a.out[i] = reinterpret_cast<float2*>(out6[i]);
   a.off = p->d_goff;
   a.node = p->d_node;
   a.nr = p->nr;
@@ -452,7 +455,7 @@ mlg_status launch_split_synth(const mlg_plan_s* p, const double* psi, const doub
   a.gy = (p->nr + TM - 1) / TM;
   a.gz = p->M;
   p->timing.begin("synth_gemm", s);
-  split_synth_kernel<<<xcd_blocks(a.gx, a.gy, a.gz), 256, 0, s>>>(a);
+  split_synth_kernel<float2><<<xcd_blocks(a.gx, a.gy, a.gz), 256, 0, s>>>(a);
   p->timing.end(s);
   return check("split_synth_kernel");
 }
@@ -464,8 +467,8 @@ mlg_status launch_split_scalar(const mlg_plan_s* p, int dir, const double* in, d
   a.toff = fwd ? p->d_split_prj_off : p->d_split_syn_off;
   a.kpad = p->d_split_syn_kpad;
   a.ipad = p->split_ipad;
-  a.in = reinterpret_cast<const double2*>(in);
-  a.out = reinterpret_cast<double2*>(out);
+  a.in = reinterpret_cast<const float2*>(in);
+  a.out = reinterpret_cast<float2*>(out);
   a.off = p->d_goff;
   a.nr = p->nr;
   a.nrc = p->nrc;
@@ -490,8 +493,8 @@ mlg_status launch_split_zdft(const mlg_plan_s* p, const double* const* in, doubl
   ZdftArgs a{};
   a.tab = reinterpret_cast<const uint4*>(p->d_split_zdft);
   for (int i = 0; i < nf; ++i) {
-    a.in[i] = reinterpret_cast<const double2*>(in[i]);
-    a.out[i] = reinterpret_cast<double2*>(out[i]);
+    a.in[i] = reinterpret_cast<const float2*>(in[i]);
+    a.out[i] = reinterpret_cast<float2*>(out[i]);
   }
   a.rows = rows;
   a.lines = rows * nf;

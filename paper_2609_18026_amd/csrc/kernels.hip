@@ -548,8 +548,8 @@ struct ProjArgs {
   const double2* __restrict__ Cs;
   const double2* __restrict__ Kp;
   const double2* __restrict__ Pc;
-  double2* __restrict__ psi;
-  double2* __restrict__ chi;
+  void* __restrict__ psi;        // outputs: double2, or float2 on reduced-precision plans
+  void* __restrict__ chi;
   double2* __restrict__ taps;    // C, K, Zhat (triangular) or null
   const double* __restrict__ gram;
   const int64_t* __restrict__ off;
@@ -642,7 +642,7 @@ __device__ __forceinline__ void add_entering(double2 (&y)[SMAX], int len, double
   }
 }
 
-template <bool TAPS, int SMAX>
+template <bool TAPS, int SMAX, typename O2>
 __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a) {
   extern __shared__ double sm[];
   const int m = blockIdx.y;
@@ -658,8 +658,8 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
       const int64_t row = e / a.nz;
       const int k = kval((int)(e - row * a.nz), a.nz);
       if (a.row_m[row] < a.mmax && (k < 0 ? -k : k) <= a.kmax) continue;
-      a.psi[e] = z;
-      a.chi[e] = z;
+      st2(reinterpret_cast<O2*>(a.psi) + e, z);
+      st2(reinterpret_cast<O2*>(a.chi) + e, z);
       if (TAPS) {
         a.taps[e] = z;
         a.taps[a.tri_elems + e] = z;
@@ -721,8 +721,8 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
   const double2* __restrict__ Cs = a.Cs + gbase * nz + kk;
   const double2* __restrict__ Kp = a.Kp + gbase * nz + kk;
   const double2* __restrict__ Zc = a.Pc + gbase * nz + kk;
-  double2* __restrict__ ps = a.psi + gbase * nz + kk;
-  double2* __restrict__ chv = a.chi + gbase * nz + kk;
+  O2* __restrict__ ps = reinterpret_cast<O2*>(a.psi) + gbase * nz + kk;
+  O2* __restrict__ chv = reinterpret_cast<O2*>(a.chi) + gbase * nz + kk;
   const int qrows = nrc + 2;
   const double2* __restrict__ qfl = a.qfl + (int64_t)m * qrows * a.nkact + slot;
   const double* __restrict__ qfr = a.qfr + (int64_t)m * qrows * a.nkact + slot;
@@ -850,7 +850,7 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
       if (j < len) {
         const int t = s0 + j;
         const double2 v = cscale(bp[j], srL[t]);
-        if (active) ps[(int64_t)t * nz] = v;
+        if (active) st2(ps + (int64_t)t * nz, v);
         gpr += sgw[t] * v.x;
         gpi += sgw[t] * v.y;
         yq[j] = cscale(cscale(bq[j], k0 ? -1.0 : srL[t]), -ell2);  // the chi source -ell^2 q
@@ -893,7 +893,7 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
       if (j < len) {
         const int t = s0 + j;
         const double2 v = cscale(yq[j], srL[t]);
-        if (active) chv[(int64_t)t * nz] = v;
+        if (active) st2(chv + (int64_t)t * nz, v);
         gcr += sgw[t] * v.x;
         gci += sgw[t] * v.y;
       }
@@ -914,8 +914,8 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
       double s[4] = {0.0, 0.0, 0.0, 0.0};
       for (int i = 0; i < PS_SEG; ++i)
         for (int v = 0; v < 4; ++v) s[v] += red[4 * (i * PS_COL + c) + v];
-      ps[0] = make_double2(-s[0] / sgw[0], -s[1] / sgw[0]);
-      chv[0] = make_double2(-s[2] / sgw[0], -s[3] / sgw[0]);
+      st2(ps, make_double2(-s[0] / sgw[0], -s[1] / sgw[0]));
+      st2(chv, make_double2(-s[2] / sgw[0], -s[3] / sgw[0]));
     }
   }
 }
@@ -1032,7 +1032,8 @@ __global__ void proxy_force_kernel(double2* __restrict__ psi_n, double2* __restr
 }
 
 // Zero every entry of the packed arrays whose (m, k) column is not active.
-__global__ void zero_inactive_kernel(double2* __restrict__ x0, double2* __restrict__ x1, double2* __restrict__ x2,
+template <typename O2>
+__global__ void zero_inactive_kernel(O2* __restrict__ x0, O2* __restrict__ x1, double2* __restrict__ x2,
                                      double2* __restrict__ x3, double2* __restrict__ x4,
                                      const int32_t* __restrict__ row_m, int64_t rows, int nz, int nzc, int mmax,
                                      int kmax) {
@@ -1044,8 +1045,8 @@ __global__ void zero_inactive_kernel(double2* __restrict__ x0, double2* __restri
     const bool active = row_m[row] < mmax && (k < 0 ? -k : k) <= kmax && kkept(kk, nz, nzc);
     if (active) continue;
     const double2 z = make_double2(0.0, 0.0);
-    x0[e] = z;
-    x1[e] = z;
+    st2(x0 + e, z);
+    st2(x1 + e, z);
     if (x2) { x2[e] = z; x3[e] = z; x4[e] = z; }
   }
 }
@@ -1107,6 +1108,7 @@ mlg_status launch_gemm(const mlg_plan_s* p, const GemmProds& prods, const GemmDe
 
 mlg_status launch_phi_forward(const mlg_plan_s* p, const double* phys, double* mixed, hipStream_t s) {
   if (p->nphi == 256 && p->use_fast_fft) return launch_phi256_forward(p, phys, mixed, s);
+  if (p->prec != MLG_FP64) return fail(MLG_E_UNSUPPORTED, "reduced-precision plans need N_phi = 256");
   PhiGeom g = phi_geom(p, false);
   const int lb = phi_lines_per_block(p->nphi);
   const int npair = lb / 2;
@@ -1122,6 +1124,7 @@ mlg_status launch_phi_forward(const mlg_plan_s* p, const double* phys, double* m
 
 mlg_status launch_phi_backward(const mlg_plan_s* p, const double* mixed, double* phys, hipStream_t s) {
   if (p->nphi == 256 && p->use_fast_fft) return launch_phi256_backward(p, mixed, phys, s);
+  if (p->prec != MLG_FP64) return fail(MLG_E_UNSUPPORTED, "reduced-precision plans need N_phi = 256");
   PhiGeom g = phi_geom(p, false);
   const int lb = phi_lines_per_block(p->nphi);
   const size_t shm = (size_t)2 * (lb / 2) * p->nphi * sizeof(double2);
@@ -1136,6 +1139,7 @@ mlg_status launch_phi_backward(const mlg_plan_s* p, const double* mixed, double*
 
 mlg_status launch_phi_scalar_rhs(const mlg_plan_s* p, int kind, double gamma, double* mixed, hipStream_t s) {
   if (p->nphi == 256 && p->use_fast_fft) return launch_phi256_scalar(p, kind, gamma, mixed, s);
+  if (p->prec != MLG_FP64) return fail(MLG_E_UNSUPPORTED, "reduced-precision plans need N_phi = 256");
   PhiGeom g = phi_geom(p, p->g.dealias != 0);
   const int lb = phi_lines_per_block(p->nphi);
   const size_t shm = (size_t)2 * (lb / 2) * p->nphi * sizeof(double2);
@@ -1155,6 +1159,7 @@ mlg_status launch_phi_vec_rhs(const mlg_plan_s* p, const double* U, double* cons
   // the 256-point kernel forms per-lane byte offsets of up to 31 lines of orders in 32 bits
   if (p->nphi == 256 && p->use_fast_fft && (int64_t)p->nr * p->nz <= (int64_t(1) << 23))
     return launch_phi256_vec(p, U, f6, taps, s);
+  if (p->prec != MLG_FP64) return fail(MLG_E_UNSUPPORTED, "reduced-precision plans need N_phi = 256");
   PhiGeom g = phi_geom(p, p->g.dealias != 0);
   int lb = 1024 / p->nphi;  // 4 buffers of n complex per line: 64 * lb * n bytes <= 64 KB
   if (lb < 1) lb = 1;
@@ -1177,6 +1182,7 @@ mlg_status launch_zfft_fields(const mlg_plan_s* p, const double* const* in, doub
   if (p->nz == 256 && p->prec == MLG_SPLIT_BF16 && !fp64_only)
     return launch_split_zdft(p, in, out, nf, rows, dir, row_m, mask_m, mask_k, s);
   if (p->nz == 256 && p->use_fast_fft) return launch_zfft256(p, in, out, nf, rows, dir, row_m, mask_m, mask_k, s);
+  if (p->prec != MLG_FP64) return fail(MLG_E_UNSUPPORTED, "reduced-precision plans need N_z = 256");
   for (int i = 0; i < nf; ++i)
     if (mlg_status st = launch_zfft(p, in[i], out[i], rows, dir, row_m, mask_m, mask_k, s)) return st;
   return MLG_OK;
@@ -1187,6 +1193,7 @@ mlg_status launch_zfft(const mlg_plan_s* p, const double* in, double* out, int64
   if (rows <= 0) return MLG_OK;
   if (p->nz == 256 && p->prec == MLG_SPLIT_BF16) return launch_split_zdft(p, &in, &out, 1, rows, dir, row_m, mask_m, mask_k, s);
   if (p->nz == 256 && p->use_fast_fft) return launch_zfft256(p, &in, &out, 1, rows, dir, row_m, mask_m, mask_k, s);
+  if (p->prec != MLG_FP64) return fail(MLG_E_UNSUPPORTED, "reduced-precision plans need N_z = 256");
   ZGeom g{};
   g.nz = p->nz;
   g.nzc = p->nzc;
@@ -1226,8 +1233,9 @@ mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, dou
   a.Cs = reinterpret_cast<const double2*>(src3[0]);
   a.Kp = reinterpret_cast<const double2*>(src3[1]);
   a.Pc = reinterpret_cast<const double2*>(src3[2]);
-  a.psi = reinterpret_cast<double2*>(psi_n);
-  a.chi = reinterpret_cast<double2*>(chi_n);
+  a.psi = psi_n;
+  a.chi = chi_n;
+  const bool red = p->prec != MLG_FP64;  // outputs in the plan's data type
   a.taps = reinterpret_cast<double2*>(taps_src);
   a.gram = p->d_gram;
   a.off = p->d_goff;  // the Gram offsets coincide with the triangular row offsets
@@ -1254,9 +1262,14 @@ mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, dou
     int blocks = (int)std::min<int64_t>((total + 255) / 256, 65536);
     double2* t0 = a.taps;
     p->timing.begin("projection", s);
-    zero_inactive_kernel<<<blocks, 256, 0, s>>>(a.psi, a.chi, t0, t0 ? t0 + p->tri_elems : nullptr,
-                                                t0 ? t0 + 2 * p->tri_elems : nullptr, p->d_row_m, p->tau, p->nz, p->nzc,
-                                                mmax, kmax);
+    if (red)
+      zero_inactive_kernel<float2><<<blocks, 256, 0, s>>>(
+          reinterpret_cast<float2*>(psi_n), reinterpret_cast<float2*>(chi_n), t0, t0 ? t0 + p->tri_elems : nullptr,
+          t0 ? t0 + 2 * p->tri_elems : nullptr, p->d_row_m, p->tau, p->nz, p->nzc, mmax, kmax);
+    else
+      zero_inactive_kernel<double2><<<blocks, 256, 0, s>>>(
+          reinterpret_cast<double2*>(psi_n), reinterpret_cast<double2*>(chi_n), t0, t0 ? t0 + p->tri_elems : nullptr,
+          t0 ? t0 + 2 * p->tri_elems : nullptr, p->d_row_m, p->tau, p->nz, p->nzc, mmax, kmax);
     p->timing.end(s);
     if (mlg_status st = check_launch("zero_inactive_kernel")) return st;
   }
@@ -1266,12 +1279,20 @@ mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, dou
                        sizeof(double);
     const bool wide = p->nrc - 1 > 8 * PS_SEG;
     p->timing.begin("projection", s);
-    if (a.taps) {
-      if (wide) projection_kernel<true, 16><<<grid, PS_SEG * PS_COL, shm, s>>>(a);
-      else projection_kernel<true, 8><<<grid, PS_SEG * PS_COL, shm, s>>>(a);
+    if (red) {
+      if (a.taps) {
+        if (wide) projection_kernel<true, 16, float2><<<grid, PS_SEG * PS_COL, shm, s>>>(a);
+        else projection_kernel<true, 8, float2><<<grid, PS_SEG * PS_COL, shm, s>>>(a);
+      } else {
+        if (wide) projection_kernel<false, 16, float2><<<grid, PS_SEG * PS_COL, shm, s>>>(a);
+        else projection_kernel<false, 8, float2><<<grid, PS_SEG * PS_COL, shm, s>>>(a);
+      }
+    } else if (a.taps) {
+      if (wide) projection_kernel<true, 16, double2><<<grid, PS_SEG * PS_COL, shm, s>>>(a);
+      else projection_kernel<true, 8, double2><<<grid, PS_SEG * PS_COL, shm, s>>>(a);
     } else {
-      if (wide) projection_kernel<false, 16><<<grid, PS_SEG * PS_COL, shm, s>>>(a);
-      else projection_kernel<false, 8><<<grid, PS_SEG * PS_COL, shm, s>>>(a);
+      if (wide) projection_kernel<false, 16, double2><<<grid, PS_SEG * PS_COL, shm, s>>>(a);
+      else projection_kernel<false, 8, double2><<<grid, PS_SEG * PS_COL, shm, s>>>(a);
     }
     p->timing.end(s);
   }

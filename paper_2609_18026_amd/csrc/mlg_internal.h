@@ -82,6 +82,10 @@ struct mlg_plan_s {
   double* d_Pf = nullptr;   // forward w*Pbar, per m [i][n-m]
   double* d_Tb = nullptr;   // backward Tbar = (1-x^2) dPbar/dx, per m [n-m][i]
   double* d_Qf = nullptr;   // forward w*(Tbar - 2(1+x)Pbar), per m [i][n-m]
+  // MLG_FP32 plans: the backward Pbar, Tbar and forward w Pbar tables rounded to float (same layouts)
+  float* d_Pb32 = nullptr;
+  float* d_Tb32 = nullptr;
+  float* d_Pf32 = nullptr;
   double* d_node = nullptr; // nodal vectors: rinv[nr], q[nr], opx[nr], area weight w ell^2/(1-x)^2 [nr]
   double* d_tw_phi = nullptr;  // exp(-2 pi i t / N_phi), interleaved
   double* d_tw_z = nullptr;    // exp(-2 pi i t / N_z), interleaved

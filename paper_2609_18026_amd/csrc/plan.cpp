@@ -152,7 +152,7 @@ void free_plan_device(mlg_plan_s* p) {
                   p->d_split_syn_off, p->d_split_syn_kpad, p->d_split_prj[0], p->d_split_prj[1],
                   p->d_split_prj_off, p->d_split_zdft, p->d_step_fwd,
                   p->d_step_bwd, p->d_step_lam, p->d_step_u, p->d_step_qoff, p->d_step_loff, p->d_step_w,
-                  p->d_filter, p->d_logf, p->d_qfl, p->d_qfr, p->d_poisson};
+                  p->d_filter, p->d_logf, p->d_qfl, p->d_qfr, p->d_poisson, p->d_Pb32, p->d_Tb32, p->d_Pf32};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }
@@ -261,6 +261,12 @@ mlg_status build_plan(mlg_plan_s* p) {
         Qf[base + (size_t)i * K + (n - m)] = (double)(wl[i] * Q);
       }
     }
+  }
+  // ---------------- FP32 tables (MLG_FP32 plans: products on FP32 MFMA)
+  if (p->prec == MLG_FP32) {
+    std::vector<float> pb(Pb.begin(), Pb.end()), tb(Tb.begin(), Tb.end()), pf(Pf.begin(), Pf.end());
+    mlg_status st2;
+    if ((st2 = upload(&p->d_Pb32, pb)) || (st2 = upload(&p->d_Tb32, tb)) || (st2 = upload(&p->d_Pf32, pf))) return st2;
   }
   // ---------------- split-bfloat16 tables (MLG_SPLIT_BF16 plans only)
   if (p->prec == MLG_SPLIT_BF16) {
