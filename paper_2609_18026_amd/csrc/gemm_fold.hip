@@ -28,7 +28,8 @@ using namespace ::mlg::dev;
 
 constexpr int TM = 64;  // rows per block (half nodes, or pairs of degrees)
 constexpr int TC8 = 8;  // complex columns per block (re and im share the 16 MFMA columns)
-constexpr int TP = 8;   // k depth per LDS stage (pairs of degrees, or half nodes)
+constexpr int TP = 8;   // k depth per LDS stage of the synthesis (pairs of degrees)
+constexpr int PD = 8;   // k depth per LDS stage of the projection products (half nodes)
 
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
@@ -246,14 +247,11 @@ struct FoldProjArgs {
   const C2* in[3];         // harmonics of N_r/r, N_phi/r, N_z (mixed [m][i][kk]; float2 for reduced plans)
   double2* out[3];         // C, K', Zhat (packed triangular)
   const int64_t* off;
-  int nr, nrc, nz, kmax, nkact;
+  int nr, nrc, nz, kmax;
+  ColBlocks cb;            // the aligned blocks of 8 active axial slots
   int gx, gy, gz;          // tiles: column blocks, pair blocks, orders
   double kap0;
 };
-
-__device__ __forceinline__ int active_kk(int a, int kmax, int nz) {
-  return (a <= kmax) ? a : nz - (2 * kmax + 1 - a);
-}
 
 // Block tile: 64 pairs of degrees (even and odd n - m) x 8 complex columns, [re | im] packed in
 // the 16 MFMA columns as in synth_fold_kernel; the low lane of a partner pair writes the even
@@ -267,14 +265,14 @@ __global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs<C2> a) {
   const int rows = a.nrc > m ? a.nrc - m : 0;
   const int KP = (rows + 1) / 2;
   const int row0 = tl.y * TM;  // pair index
-  const int c0 = tl.x * TC8;
-  if (row0 >= KP || c0 >= a.nkact) return;
+  const int c0 = tl.x * TC8;  // padded column index of the block's first slot
+  if (row0 >= KP) return;
   const int nr = a.nr, nz = a.nz, half = a.nr / 2;
   const double* __restrict__ P = a.Pf + a.off[m] * nr;
   const double* __restrict__ Q = a.Qf + a.off[m] * nr;
 
-  __shared__ double As[2][2][2][TP][TM];  // [buf][W Pbar, W Q_A][parity][half node][pair]
-  __shared__ double Bs[2][3][2][TP][16];  // [buf][a, b, c][sum, difference][half node][re 0..7 | im 0..7]
+  __shared__ double As[2][2][2][PD][TM];  // [buf][W Pbar, W Q_A][parity][half node][pair]
+  __shared__ double Bs[2][3][2][PD][16];  // [buf][a, b, c][sum, difference][half node][re 0..7 | im 0..7]
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int cl = lane & 15;
@@ -286,9 +284,13 @@ __global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs<C2> a) {
 
   // B staging: threads 0..191 each load one (field, half node, column) at both mirror nodes
   const int bf = tid >> 6, bkr = (tid >> 3) & 7, bcc = tid & 7;
-  const int bca = c0 + bcc;
-  const int bkk = (tid < 192 && bca < a.nkact) ? active_kk(bca, a.kmax, nz) : -1;
+  bool bact;
+  const int bkc = colblk_kk(a.cb, c0 + bcc, a.kmax, nz, bact);
+  const int bkk = (tid < 192 && bact) ? bkc : -1;
   const C2* __restrict__ Xb = (tid < 192) ? a.in[bf] + (int64_t)m * nr * nz : nullptr;
+  // the wave's 16 pairs may all lie past the column (the second row tile of a short order): it
+  // then skips its MFMAs and only helps to stage the operands
+  const bool wrows = 2 * (row0 + wave * 16) < rows;
   // operands of the next two stages in registers (raw loads; sums and differences are formed
   // when they are written to LDS, so the loads stay in flight across the MFMAs)
   struct Stage {
@@ -328,28 +330,30 @@ __global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs<C2> a) {
     }
   };
 
-  const int nk = (half + TP - 1) / TP;
+  const int nk = (half + PD - 1) / PD;
   load(0, ra);
   store(0, ra);
-  if (nk > 1) load(TP, ra);
+  if (nk > 1) load(PD, ra);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
-    if (kt + 2 < nk) load((kt + 2) * TP, rn);
+    if (kt + 2 < nk) load((kt + 2) * PD, rn);
+    if (wrows) {
 #pragma unroll
-    for (int ks = 0; ks < TP; ks += 4) {
-      const int kr = ks + (lane >> 4);
+      for (int ks = 0; ks < PD; ks += 4) {
+        const int kr = ks + (lane >> 4);
 #pragma unroll
-      for (int par = 0; par < 2; ++par) {
-        const int sp = par, sq = 1 - par;  // Pbar: even rows use sums; Q_A: even rows use differences
-        const double aP = As[buf][0][par][kr][wave * 16 + cl];
-        const double aQ = As[buf][1][par][kr][wave * 16 + cl];
-        double4_t(&c)[5] = acc[par];
-        c[0] = MFMA(aP, Bs[buf][0][sp][kr][cl], c[0]);  // Pa
-        c[1] = MFMA(aQ, Bs[buf][0][sq][kr][cl], c[1]);  // Q_A a
-        c[2] = MFMA(aP, Bs[buf][1][sp][kr][cl], c[2]);  // Pb
-        c[3] = MFMA(aQ, Bs[buf][1][sq][kr][cl], c[3]);  // Q_A b
-        c[4] = MFMA(aP, Bs[buf][2][sp][kr][cl], c[4]);  // Pc
+        for (int par = 0; par < 2; ++par) {
+          const int sp = par, sq = 1 - par;  // Pbar: even rows use sums; Q_A: even rows use differences
+          const double aP = As[buf][0][par][kr][wave * 16 + cl];
+          const double aQ = As[buf][1][par][kr][wave * 16 + cl];
+          double4_t(&c)[5] = acc[par];
+          c[0] = MFMA(aP, Bs[buf][0][sp][kr][cl], c[0]);  // Pa
+          c[1] = MFMA(aQ, Bs[buf][0][sq][kr][cl], c[1]);  // Q_A a
+          c[2] = MFMA(aP, Bs[buf][1][sp][kr][cl], c[2]);  // Pb
+          c[3] = MFMA(aQ, Bs[buf][1][sq][kr][cl], c[3]);  // Q_A b
+          c[4] = MFMA(aP, Bs[buf][2][sp][kr][cl], c[4]);  // Pc
+        }
       }
     }
     if (kt + 1 < nk) store(buf ^ 1, ra);
@@ -357,8 +361,9 @@ __global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs<C2> a) {
     __syncthreads();
   }
   const bool hi = cl >= 8;
-  const int cidx = c0 + (cl & 7);
-  const int kk = cidx < a.nkact ? active_kk(cidx, a.kmax, nz) : 0;
+  bool cact;
+  const int kc = colblk_kk(a.cb, c0 + (cl & 7), a.kmax, nz, cact);
+  const int kk = cact ? kc : 0;
   const double kap = a.kap0 * kval(kk, nz);
   const double fm = (double)m;
   const int64_t tb = a.off[m];
@@ -377,7 +382,7 @@ __global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs<C2> a) {
       val[p] = hi ? make_double2(recv, mine) : make_double2(mine, recv);
     }
     const int r = 2 * jj + par;
-    if (r >= rows || cidx >= a.nkact) continue;
+    if (r >= rows || !cact) continue;
     const double2 Pa = val[0], Pb = val[2], Pc = val[4];
     const double2 Qa = make_double2(val[1].x - 2.0 * Pa.x, val[1].y - 2.0 * Pa.y);
     const double2 Qb = make_double2(val[3].x - 2.0 * Pb.x, val[3].y - 2.0 * Pb.y);
@@ -408,7 +413,7 @@ struct ScalarFoldArgs {
 
 // backward: f(i) = E(i) + O(i), f(N-1-i) = E(i) - O(i), E / O over even / odd n - m, i < N/2
 template <typename R>
-__global__ __launch_bounds__(256) void scal_bwd_fold_kernel(ScalarFoldArgs<R> a) {
+__global__ __launch_bounds__(256, 3) void scal_bwd_fold_kernel(ScalarFoldArgs<R> a) {
   Tile3 tl;
   if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
   const int m = tl.z;
@@ -428,38 +433,37 @@ __global__ __launch_bounds__(256) void scal_bwd_fold_kernel(ScalarFoldArgs<R> a)
   for (int q = 0; q < 2; ++q)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[q][c] = Mma<R>::zero();
-  R ra[4], rb[4];
-  auto load = [&](int p0) {
+  // two register sets taken in turn, as in synth_fold_kernel: clamped unconditional loads two
+  // stages ahead, zeros applied at the LDS store
+  constexpr int NL = SC_P / 2;  // loads per thread and stage of each operand
+  struct Stage {
+    R a[NL], b[NL];
+  };
+  Stage sx, sy;
+  const int Kc = K > 0 ? K - 1 : 0;
+  auto load = [&](int p0, Stage& d) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < NL; ++t) {
       const int e = tid + 256 * t;  // [parity][pair][64]
-      const int par = e >> 9, kr = (e >> 6) & 7, cc = e & 63;
-      const int j = 2 * (p0 + kr) + par, jc = j < K ? j : K - 1;
-      const int i = row0 + cc, ic = i < half ? i : half - 1;
-      const int col = col0 + cc, cc2 = col < ncol ? col : ncol - 1;
-      ra[t] = A[(int64_t)jc * nr + ic];
-      rb[t] = B[(int64_t)jc * ncol + cc2];
+      const int par = e / (64 * SC_P), kr = (e / 64) % SC_P, cc = e % 64;
+      const int jc = min(2 * (p0 + kr) + par, Kc);
+      const int ic = min(row0 + cc, half - 1);
+      const int cc2 = min(col0 + cc, ncol - 1);
+      d.a[t] = A[(int64_t)jc * nr + ic];
+      d.b[t] = B[(int64_t)jc * ncol + cc2];
     }
   };
-  auto store = [&](int buf, int p0) {
+  auto store = [&](int buf, int p0, const Stage& d) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < NL; ++t) {
       const int e = tid + 256 * t;
-      const int par = e >> 9, kr = (e >> 6) & 7, cc = e & 63;
+      const int par = e / (64 * SC_P), kr = (e / 64) % SC_P, cc = e % 64;
       const bool jin = 2 * (p0 + kr) + par < K;
-      As[buf][par][kr][cc] = (jin && row0 + cc < half) ? ra[t] : R(0);
-      Bs[buf][par][kr][cc] = (jin && col0 + cc < ncol) ? rb[t] : R(0);
+      As[buf][par][kr][cc] = (jin && row0 + cc < half) ? d.a[t] : R(0);
+      Bs[buf][par][kr][cc] = (jin && col0 + cc < ncol) ? d.b[t] : R(0);
     }
   };
-  const int nk = (KP + SC_P - 1) / SC_P;
-  if (nk > 0) {
-    load(0);
-    store(0, 0);
-  }
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) load((kt + 1) * SC_P);
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int ks = 0; ks < SC_P; ks += 4) {
       const int kr = ks + (lane >> 4);
@@ -470,8 +474,29 @@ __global__ __launch_bounds__(256) void scal_bwd_fold_kernel(ScalarFoldArgs<R> a)
         for (int c = 0; c < 4; ++c) acc[par][c] = MFMA(av, Bs[buf][par][kr][c * 16 + cl], acc[par][c]);
       }
     }
-    if (kt + 1 < nk) store(buf ^ 1, (kt + 1) * SC_P);
+  };
+  const int nk = (KP + SC_P - 1) / SC_P;
+  if (nk > 0) {
+    load(0, sx);
+    store(0, 0, sx);
+    load(SC_P, sy);
     __syncthreads();
+    int kt = 0;
+    for (; kt + 1 < nk; kt += 2) {
+      load((kt + 2) * SC_P, sx);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(0);
+      __builtin_amdgcn_sched_barrier(0);
+      store(1, (kt + 1) * SC_P, sy);
+      __syncthreads();
+      load((kt + 3) * SC_P, sy);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(1);
+      __builtin_amdgcn_sched_barrier(0);
+      store(0, (kt + 2) * SC_P, sx);
+      __syncthreads();
+    }
+    if (kt < nk) compute(0);
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -490,7 +515,7 @@ __global__ __launch_bounds__(256) void scal_bwd_fold_kernel(ScalarFoldArgs<R> a)
 
 // forward: even n - m rows contract with X_i + X_{N-1-i}, odd rows with the difference, i < N/2
 template <typename R>
-__global__ __launch_bounds__(256) void scal_fwd_fold_kernel(ScalarFoldArgs<R> a) {
+__global__ __launch_bounds__(256, 3) void scal_fwd_fold_kernel(ScalarFoldArgs<R> a) {
   Tile3 tl;
   if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
   const int m = tl.z;
@@ -510,63 +535,86 @@ __global__ __launch_bounds__(256) void scal_fwd_fold_kernel(ScalarFoldArgs<R> a)
   for (int q = 0; q < 2; ++q)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[q][c] = Mma<R>::zero();
-  R ra[4], rx[2], ry[2];
-  auto load = [&](int i0) {
+  // the wave's 16 pairs may all lie past the column (the second row tile of a short order):
+  // it then skips its MFMAs and only helps to stage the operands
+  const bool wrows = 2 * (row0 + wave * 16) < K;
+  constexpr int NA = SC_P / 2, NX = SC_P / 4;  // table and field loads per thread and stage
+  struct Stage {
+    R a[NA], x[NX], y[NX];
+  };
+  Stage sx, sy;
+  const int Kc = K - 1;  // K > 0 here (row0 < KP)
+  auto load = [&](int i0, Stage& d) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < NA; ++t) {
       const int e = tid + 256 * t;  // [parity][half node][pair]
-      const int par = e >> 9, kr = (e >> 6) & 7, rr = e & 63;
-      const int i = i0 + kr, ic = i < half ? i : half - 1;
-      const int j = 2 * (row0 + rr) + par, jc = j < K ? j : K - 1;
-      ra[t] = A[(int64_t)ic * K + jc];
+      const int par = e / (64 * SC_P), kr = (e / 64) % SC_P, rr = e % 64;
+      const int ic = min(i0 + kr, half - 1);
+      const int jc = min(2 * (row0 + rr) + par, Kc);
+      d.a[t] = A[(int64_t)ic * K + jc];
     }
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < NX; ++t) {
       const int e = tid + 256 * t;  // [half node][column]
-      const int kr = e >> 6, cc = e & 63;
-      const int i = i0 + kr, ic = i < half ? i : half - 1;
-      const int col = col0 + cc, cc2 = col < ncol ? col : ncol - 1;
-      rx[t] = B[(int64_t)ic * ncol + cc2];
-      ry[t] = B[(int64_t)(nr - 1 - ic) * ncol + cc2];
+      const int kr = e / 64, cc = e % 64;
+      const int ic = min(i0 + kr, half - 1);
+      const int cc2 = min(col0 + cc, ncol - 1);
+      d.x[t] = B[(int64_t)ic * ncol + cc2];
+      d.y[t] = B[(int64_t)(nr - 1 - ic) * ncol + cc2];
     }
   };
-  auto store = [&](int buf, int i0) {
+  auto store = [&](int buf, int i0, const Stage& d) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < NA; ++t) {
       const int e = tid + 256 * t;
-      const int par = e >> 9, kr = (e >> 6) & 7, rr = e & 63;
+      const int par = e / (64 * SC_P), kr = (e / 64) % SC_P, rr = e % 64;
       const bool ok = i0 + kr < half && 2 * (row0 + rr) + par < K;
-      As[buf][par][kr][rr] = ok ? ra[t] : R(0);
+      As[buf][par][kr][rr] = ok ? d.a[t] : R(0);
     }
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < NX; ++t) {
       const int e = tid + 256 * t;
-      const int kr = e >> 6, cc = e & 63;
+      const int kr = e / 64, cc = e % 64;
       const bool ok = i0 + kr < half && col0 + cc < ncol;
-      Bs[buf][0][kr][cc] = ok ? rx[t] + ry[t] : R(0);
-      Bs[buf][1][kr][cc] = ok ? rx[t] - ry[t] : R(0);
+      Bs[buf][0][kr][cc] = ok ? d.x[t] + d.y[t] : R(0);
+      Bs[buf][1][kr][cc] = ok ? d.x[t] - d.y[t] : R(0);
     }
   };
-  const int nk = (half + SC_P - 1) / SC_P;
-  load(0);
-  store(0, 0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) load((kt + 1) * SC_P);
+  auto compute = [&](int buf) {
+    if (!wrows) return;
 #pragma unroll
     for (int ks = 0; ks < SC_P; ks += 4) {
       const int kr = ks + (lane >> 4);
 #pragma unroll
       for (int par = 0; par < 2; ++par) {
         const R av = As[buf][par][kr][wave * 16 + cl];
+        const int sd = par;  // even degrees contract with sums, odd with differences
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[par][c] = MFMA(av, Bs[buf][par][kr][c * 16 + cl], acc[par][c]);
+        for (int c = 0; c < 4; ++c) acc[par][c] = MFMA(av, Bs[buf][sd][kr][c * 16 + cl], acc[par][c]);
       }
     }
-    if (kt + 1 < nk) store(buf ^ 1, (kt + 1) * SC_P);
+  };
+  const int nk = (half + SC_P - 1) / SC_P;
+  load(0, sx);
+  store(0, 0, sx);
+  load(SC_P, sy);
+  __syncthreads();
+  int kt = 0;
+  for (; kt + 1 < nk; kt += 2) {
+    load((kt + 2) * SC_P, sx);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(0);
+    __builtin_amdgcn_sched_barrier(0);
+    store(1, (kt + 1) * SC_P, sy);
+    __syncthreads();
+    load((kt + 3) * SC_P, sy);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(1);
+    __builtin_amdgcn_sched_barrier(0);
+    store(0, (kt + 2) * SC_P, sx);
     __syncthreads();
   }
+  if (kt < nk) compute(0);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int col = col0 + c * 16 + cl;
@@ -640,10 +688,10 @@ static void proj_fold_go(const mlg_plan_s* p, double* const* in3, double* const*
   a.nrc = p->nrc;
   a.nz = p->nz;
   a.kmax = kmax;
-  a.nkact = (p->nz == 1) ? 1 : 2 * kmax + 1;
+  a.cb = col_blocks(kmax, p->nz);
   a.kap0 = 2.0 * M_PI / p->g.lz;
   const int kp = (p->nrc + 1) / 2;
-  a.gx = (a.nkact + TC8 - 1) / TC8;
+  a.gx = a.cb.nblk;
   a.gy = (kp + TM - 1) / TM;
   a.gz = mmax;
   proj_fold_kernel<C2><<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);

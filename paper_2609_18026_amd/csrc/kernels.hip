@@ -538,12 +538,14 @@ __global__ __launch_bounds__(256) void zfft_kernel(ZGeom g, FftRadices fr, const
 //
 // Every substitution is a linear recurrence of order two, y_t = a_t - al_t y_(t-+1) - be_t y_(t-+2),
 // so its value on a run of degrees is affine in the two values entering the run.  A column is
-// solved by PS_SEG threads, each owning a run of at most SMAX consecutive degrees: a thread sweeps
-// its run from a zero entering state while carrying the two homogeneous solutions (the 2 x 2 map
-// of the entering state), the entering states follow from composing the maps of the runs before
-// it (read from LDS), and the thread adds the homogeneous part.  Four such rounds: the forward
+// solved by the PS_SEG lanes of one half wave, each owning a run of at most SMAX consecutive
+// degrees: a lane sweeps its run from a zero entering state while carrying the two homogeneous
+// solutions (the 2 x 2 map of the entering state), the entering states follow from an exclusive
+// scan of the run maps across the half wave (lane shuffles; composition of affine maps is
+// associative), and the lane adds the homogeneous part.  Four such rounds: the forward
 // substitutions of psi and q, their back substitutions (then psi and q are final), the chi sweep
-// U w = -ell^2 q, and its back substitution.  Every intermediate stays in registers.
+// U w = -ell^2 q, and its back substitution.  Every intermediate stays in registers, and no round
+// waits for another wave.
 struct ProjArgs {
   const double2* __restrict__ Cs;
   const double2* __restrict__ Kp;
@@ -553,25 +555,21 @@ struct ProjArgs {
   double2* __restrict__ taps;    // C, K, Zhat (triangular) or null
   const double* __restrict__ gram;
   const int64_t* __restrict__ off;
-  const double2* __restrict__ qfl;  // q-operator factors (l1, l2), [m][t][slot], nrc + 2 rows per m
+  const double2* __restrict__ qfl;  // q-operator factors (l1, l2), [m][t][padded column], nrc + 2 rows per m
   const double* __restrict__ qfr;   // and reciprocal pivots
   const int32_t* __restrict__ row_m;  // order of each triangular row
   int64_t ngram, tri_elems, rows;
-  int nz, nrc, kmax, nkact, mmax;
+  int nz, nrc, kmax, mmax;
+  ColBlocks cb;                  // the aligned column blocks (one per block of the grid's x)
   double ell2, kap0;
 };
 
-__device__ __forceinline__ int active_slot(int a, int kmax, int nz) {
-  // a in [0, 2 kmax + 1): k = 0..kmax then k = -kmax..-1
-  return (a <= kmax) ? a : nz - (2 * kmax + 1 - a);
-}
-
-constexpr int PS_SEG = 32;  // threads (runs of degrees) per column
-constexpr int PS_COL = 8;   // columns per block
+constexpr int PS_SEG = 32;  // lanes (runs of degrees) per column: half a wave
+constexpr int PS_COL = 8;   // columns per block (two per wave)
 constexpr int PJ_PAD = 2;   // zero entries before and after each per-m coefficient table
 
-// LDS: 11 per-m tables of nrc + 2 PJ_PAD entries, then the run maps (16-byte aligned)
-__host__ __device__ constexpr size_t proj_maps_at(int nrc) { return (11 * ((size_t)nrc + 2 * PJ_PAD) + 1) & ~(size_t)1; }
+// LDS: 11 per-m tables of nrc + 2 PJ_PAD entries (doubles)
+__host__ __device__ constexpr size_t proj_tables_len(int nrc) { return 11 * ((size_t)nrc + 2 * PJ_PAD); }
 
 // The affine map of a run: (y_last, y_before) = (c, p) + [h0 h1; h2 h3] (entering y_1, y_2)
 struct RunMap {
@@ -609,19 +607,49 @@ __device__ __forceinline__ RunMap sweep_run(double2 (&y)[SMAX], const double2 (&
   return RunMap{yc, yp, e1c, e2c, e1p, e2p};
 }
 
-// Entering state of run r from the maps of the runs before it (UP: runs 0..r-1, else PS_SEG-1..r+1)
+__device__ __forceinline__ double2 shfl2(double2 v, int d, bool up) {
+  return up ? make_double2(__shfl_up(v.x, d, PS_SEG), __shfl_up(v.y, d, PS_SEG))
+            : make_double2(__shfl_down(v.x, d, PS_SEG), __shfl_down(v.y, d, PS_SEG));
+}
+
+__device__ __forceinline__ RunMap shfl_map(const RunMap& q, int d, bool up) {
+  RunMap o;
+  o.c = shfl2(q.c, d, up);
+  o.p = shfl2(q.p, d, up);
+  o.h0 = up ? __shfl_up(q.h0, d, PS_SEG) : __shfl_down(q.h0, d, PS_SEG);
+  o.h1 = up ? __shfl_up(q.h1, d, PS_SEG) : __shfl_down(q.h1, d, PS_SEG);
+  o.h2 = up ? __shfl_up(q.h2, d, PS_SEG) : __shfl_down(q.h2, d, PS_SEG);
+  o.h3 = up ? __shfl_up(q.h3, d, PS_SEG) : __shfl_down(q.h3, d, PS_SEG);
+  return o;
+}
+
+// A o B: the map of run B followed by run A
+__device__ __forceinline__ RunMap compose(const RunMap& A, const RunMap& B) {
+  RunMap o;
+  o.c = make_double2(A.c.x + A.h0 * B.c.x + A.h1 * B.p.x, A.c.y + A.h0 * B.c.y + A.h1 * B.p.y);
+  o.p = make_double2(A.p.x + A.h2 * B.c.x + A.h3 * B.p.x, A.p.y + A.h2 * B.c.y + A.h3 * B.p.y);
+  o.h0 = A.h0 * B.h0 + A.h1 * B.h2;
+  o.h1 = A.h0 * B.h1 + A.h1 * B.h3;
+  o.h2 = A.h2 * B.h0 + A.h3 * B.h2;
+  o.h3 = A.h2 * B.h1 + A.h3 * B.h3;
+  return o;
+}
+
+// Entering state (y_1, y_2) of run r, the composition of the runs before it applied to a zero
+// state (UP: runs 0..r-1 in order, else PS_SEG-1 down to r+1): an inclusive Kogge-Stone scan of
+// the maps over the PS_SEG lanes of the column, then the state left by the previous run.
 template <bool UP>
-__device__ __forceinline__ void enter_state(const RunMap* __restrict__ maps, int r, int c, double2& in1,
-                                            double2& in2) {
-  in1 = make_double2(0.0, 0.0);
-  in2 = in1;
-  const int n = UP ? r : PS_SEG - 1 - r;
-  for (int i = 0; i < n; ++i) {
-    const RunMap q = maps[(UP ? i : PS_SEG - 1 - i) * PS_COL + c];
-    const double2 o1 = make_double2(q.c.x + q.h0 * in1.x + q.h1 * in2.x, q.c.y + q.h0 * in1.y + q.h1 * in2.y);
-    const double2 o2 = make_double2(q.p.x + q.h2 * in1.x + q.h3 * in2.x, q.p.y + q.h2 * in1.y + q.h3 * in2.y);
-    in1 = o1;
-    in2 = o2;
+__device__ __forceinline__ void enter_state(RunMap q, int r, double2& in1, double2& in2) {
+#pragma unroll
+  for (int d = 1; d < PS_SEG; d *= 2) {
+    const RunMap o = shfl_map(q, d, UP);
+    if (UP ? r >= d : r + d < PS_SEG) q = compose(q, o);
+  }
+  in1 = shfl2(q.c, 1, UP);
+  in2 = shfl2(q.p, 1, UP);
+  if (UP ? r == 0 : r == PS_SEG - 1) {
+    in1 = make_double2(0.0, 0.0);
+    in2 = in1;
   }
 }
 
@@ -646,27 +674,6 @@ template <bool TAPS, int SMAX, typename O2>
 __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a) {
   extern __shared__ double sm[];
   const int m = blockIdx.y;
-  {
-    // every block first clears its share of the entries whose (m, k) column is not solved (the
-    // stores drain while the solves wait on their loads)
-    const int64_t total = a.rows * a.nz;
-    const int64_t nb = (int64_t)gridDim.x * gridDim.y, b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    const int64_t per = (total + nb - 1) / nb;
-    const int64_t e1 = min(total, (b + 1) * per);
-    const double2 z = make_double2(0.0, 0.0);
-    for (int64_t e = b * per + threadIdx.x; e < e1; e += blockDim.x) {
-      const int64_t row = e / a.nz;
-      const int k = kval((int)(e - row * a.nz), a.nz);
-      if (a.row_m[row] < a.mmax && (k < 0 ? -k : k) <= a.kmax) continue;
-      st2(reinterpret_cast<O2*>(a.psi) + e, z);
-      st2(reinterpret_cast<O2*>(a.chi) + e, z);
-      if (TAPS) {
-        a.taps[e] = z;
-        a.taps[a.tri_elems + e] = z;
-        a.taps[2 * a.tri_elems + e] = z;
-      }
-    }
-  }
   const int nrc = a.nrc;
   const int cnt = nrc - m;  // degrees n = m .. nrc-1 at index t = n - m
   const int i0 = (m > 0 ? m : 1) - m;  // first solved index (m = 0: n = 0 is the gauge row)
@@ -682,8 +689,98 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
   double* su2 = su1 + len_t;
   double* srL = su2 + len_t;
   double* sgw = srL + len_t;
-  RunMap* maps = reinterpret_cast<RunMap*>(sm + proj_maps_at(nrc));  // [PS_SEG][PS_COL]
   const int64_t gbase = a.off[m];
+  const int lane = threadIdx.x & 63;
+  const int c = (threadIdx.x >> 6) * 2 + (lane >> 5), r = lane & (PS_SEG - 1);  // column, run
+  const int nz = a.nz;
+  const int slot = blockIdx.x * PS_COL + c;  // padded column index
+  bool active;
+  const int kc = colblk_kk(a.cb, slot, a.kmax, nz, active);
+  const int kk = active ? kc : 0;  // inactive lanes load column 0 and store nothing
+  const int k = kval(kk, nz);
+  const bool k0 = k == 0;
+  const int nsol = cnt - i0;
+  const int S = (nsol + PS_SEG - 1) / PS_SEG;
+  const int s0 = i0 + r * S;
+  const int len = max(0, min(s0 + S, cnt) - s0);
+  const double2 z0 = make_double2(0.0, 0.0);
+  const double ell2 = a.ell2, inv_ell2 = 1.0 / a.ell2;
+  const double2* __restrict__ Cs = a.Cs + gbase * nz + kk;
+  const double2* __restrict__ Kp = a.Kp + gbase * nz + kk;
+  const double2* __restrict__ Zc = a.Pc + gbase * nz + kk;
+  O2* __restrict__ ps = reinterpret_cast<O2*>(a.psi) + gbase * nz + kk;
+  O2* __restrict__ chv = reinterpret_cast<O2*>(a.chi) + gbase * nz + kk;
+  const int qrows = nrc + 2;
+  const int ncolp = 8 * a.cb.nblk;
+  const double2* __restrict__ qfl = a.qfl + (int64_t)m * qrows * ncolp + slot;
+  const double* __restrict__ qfr = a.qfr + (int64_t)m * qrows * ncolp + slot;
+  auto tcl = [&](int t) { return t < 0 ? 0 : (t < cnt ? t : cnt - 1); };  // clamped into the column
+  auto lzv = [&](int t, double2 z) {
+    const double n = (double)(m + t);
+    return cscale(z, n * (n + 1.0));
+  };
+  // (G L Zhat)_t from L Zhat at t-2..t+2 (entries outside the column meet zero-padded couplings)
+  auto glz = [&](int t, double2 zm2, double2 zm1, double2 zc, double2 zp1, double2 zp2) {
+    double2 g = cscale(zc, sg0[t]);
+    g = cadd(g, cscale(zm1, sg1[t - 1]));
+    g = cadd(g, cscale(zm2, sg2[t - 2]));
+    g = cadd(g, cscale(zp1, sg1[t]));
+    return cadd(g, cscale(zp2, sg2[t]));
+  };
+
+  // ---- the loads of round 1 go out first: they need nothing from LDS, and they stay in flight
+  // while the block clears the inactive entries and stages its tables
+  double2 yp[SMAX], yq[SMAX];
+  double2 qf[SMAX], qx[2];
+  double qr[SMAX];
+  double2 zw[SMAX + 4];  // Zhat at t = s0 - 2 + i
+  // the sweeps of round 1 overwrite their sources in place (entry j is read before it is written)
+  double2 (&ap)[SMAX] = yp;
+  double2 (&aq)[SMAX] = yq;
+#pragma unroll
+  for (int i = 0; i < SMAX + 4; ++i) zw[i] = Zc[(int64_t)tcl(s0 - 2 + i) * nz];
+#pragma unroll
+  for (int j = 0; j < SMAX; ++j) {
+    const int t = tcl(s0 + j);
+    ap[j] = Cs[(int64_t)t * nz];
+    aq[j] = Kp[(int64_t)t * nz];
+    qf[j] = qfl[(int64_t)(s0 + j < qrows ? s0 + j : 0) * ncolp];
+    qr[j] = qfr[(int64_t)(s0 + j < qrows ? s0 + j : 0) * ncolp];
+  }
+  // the couplings of round 2 reach two rows past the run (rows past the column hold zeros)
+#pragma unroll
+  for (int j = 0; j < 2; ++j) qx[j] = qfl[(int64_t)(s0 + SMAX + j < qrows ? s0 + SMAX + j : 0) * ncolp];
+  {
+    // every block first clears its share of the entries whose (m, k) column is not solved (the
+    // stores drain while the solves wait on their loads): (1) a contiguous share of the rows of
+    // the orders m >= mmax, (2) its share of the rows of its own order m, slots kmax+1 .. nz-kmax-1
+    // (the |k| outside the kept band; empty when nz = 1)
+    const double2 z = make_double2(0.0, 0.0);
+    auto clear = [&](int64_t e) {
+      st2(reinterpret_cast<O2*>(a.psi) + e, z);
+      st2(reinterpret_cast<O2*>(a.chi) + e, z);
+      if (TAPS) {
+        a.taps[e] = z;
+        a.taps[a.tri_elems + e] = z;
+        a.taps[2 * a.tri_elems + e] = z;
+      }
+    };
+    const int64_t zb = a.off[a.mmax] * a.nz, total = a.rows * a.nz - zb;
+    const int64_t nb = (int64_t)gridDim.x * gridDim.y, b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const int64_t per = (total + nb - 1) / nb;
+    const int64_t e1 = min(total, (b + 1) * per);
+    for (int64_t e = b * per + threadIdx.x; e < e1; e += blockDim.x) clear(zb + e);
+    const int band = a.nz - 2 * a.kmax - 1;
+    if (band > 0) {
+      const int rows_m = a.nrc - m;
+      const int nrow = rows_m > (int)blockIdx.x ? (rows_m - (int)blockIdx.x + gridDim.x - 1) / gridDim.x : 0;
+      const int64_t base = a.off[m] * a.nz + a.kmax + 1;
+      for (int e = threadIdx.x; e < nrow * band; e += blockDim.x) {
+        const int i = e / band;
+        clear(base + (int64_t)(blockIdx.x + i * gridDim.x) * a.nz + (e - i * band));
+      }
+    }
+  }
   for (int e = threadIdx.x; e < len_t; e += blockDim.x) {
     const int t = e - PJ_PAD;
     const bool in = t >= 0 && t < cnt;
@@ -704,59 +801,9 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
   }
   __syncthreads();
 
-  const int c = threadIdx.x % PS_COL, r = threadIdx.x / PS_COL;
-  const int ca = blockIdx.x * PS_COL + c;
-  const bool active = ca < a.nkact;
-  const int slot = active ? ca : 0;  // inactive threads load column 0 and store nothing
-  const int nz = a.nz;
-  const int kk = active_slot(slot, a.kmax, nz);
-  const int k = kval(kk, nz);
-  const bool k0 = k == 0;
-  const int nsol = cnt - i0;
-  const int S = (nsol + PS_SEG - 1) / PS_SEG;
-  const int s0 = i0 + r * S;
-  const int len = max(0, min(s0 + S, cnt) - s0);
-  const double2 z0 = make_double2(0.0, 0.0);
-  const double ell2 = a.ell2, inv_ell2 = 1.0 / a.ell2;
-  const double2* __restrict__ Cs = a.Cs + gbase * nz + kk;
-  const double2* __restrict__ Kp = a.Kp + gbase * nz + kk;
-  const double2* __restrict__ Zc = a.Pc + gbase * nz + kk;
-  O2* __restrict__ ps = reinterpret_cast<O2*>(a.psi) + gbase * nz + kk;
-  O2* __restrict__ chv = reinterpret_cast<O2*>(a.chi) + gbase * nz + kk;
-  const int qrows = nrc + 2;
-  const double2* __restrict__ qfl = a.qfl + (int64_t)m * qrows * a.nkact + slot;
-  const double* __restrict__ qfr = a.qfr + (int64_t)m * qrows * a.nkact + slot;
-  auto tcl = [&](int t) { return t < 0 ? 0 : (t < cnt ? t : cnt - 1); };  // clamped into the column
-  auto lzv = [&](int t, double2 z) {
-    const double n = (double)(m + t);
-    return cscale(z, n * (n + 1.0));
-  };
-  // (G L Zhat)_t from L Zhat at t-2..t+2 (entries outside the column meet zero-padded couplings)
-  auto glz = [&](int t, double2 zm2, double2 zm1, double2 zc, double2 zp1, double2 zp2) {
-    double2 g = cscale(zc, sg0[t]);
-    g = cadd(g, cscale(zm1, sg1[t - 1]));
-    g = cadd(g, cscale(zm2, sg2[t - 2]));
-    g = cadd(g, cscale(zp1, sg1[t]));
-    return cadd(g, cscale(zp2, sg2[t]));
-  };
 
   // ---- round 1 (ascending): sources, forward substitutions of psi and q
-  double2 yp[SMAX], yq[SMAX];
-  double2 qf[SMAX];
   {
-    // the sweeps overwrite their sources in place (entry j is read before it is written)
-    double2 (&ap)[SMAX] = yp;
-    double2 (&aq)[SMAX] = yq;
-    double2 zw[SMAX + 4];  // Zhat at t = s0 - 2 + i
-#pragma unroll
-    for (int i = 0; i < SMAX + 4; ++i) zw[i] = Zc[(int64_t)tcl(s0 - 2 + i) * nz];
-#pragma unroll
-    for (int j = 0; j < SMAX; ++j) {
-      const int t = tcl(s0 + j);
-      ap[j] = Cs[(int64_t)t * nz];
-      aq[j] = Kp[(int64_t)t * nz];
-      qf[j] = qfl[(int64_t)(s0 + j < qrows ? s0 + j : 0) * a.nkact];
-    }
 #pragma unroll
     for (int j = 0; j < SMAX; ++j) {
       if (j < len) {
@@ -791,31 +838,24 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
       be = qf[j].y;
     };
     const RunMap mq = sweep_run<SMAX, true>(yq, aq, len, cq);
-    maps[r * PS_COL + c] = sweep_run<SMAX, true>(yp, ap, len, cp);
-    __syncthreads();
+    const RunMap mp = sweep_run<SMAX, true>(yp, ap, len, cp);
     double2 p1, p2, q1, q2;
-    enter_state<true>(maps, r, c, p1, p2);
-    __syncthreads();
-    maps[r * PS_COL + c] = mq;
-    __syncthreads();
-    enter_state<true>(maps, r, c, q1, q2);
+    enter_state<true>(mp, r, p1, p2);
+    enter_state<true>(mq, r, q1, q2);
     add_entering<SMAX, true>(yp, len, p1, p2, cp);
     add_entering<SMAX, true>(yq, len, q1, q2, cq);
-    __syncthreads();
   }
 
   // ---- round 2 (descending): back substitutions of psi and q; psi is final
   double gpr = 0.0, gpi = 0.0;
   {
-    double qr[SMAX];
+    // couplings to t + 1 and t + 2, from the factors loaded in round 1 (ascending j reads
+    // entries j + 1 and j + 2 before they are replaced)
 #pragma unroll
     for (int j = 0; j < SMAX; ++j) {
-      const int t = s0 + j;
-      // couplings to t + 1 and t + 2 (rows past the column hold zeros)
-      const double2 f1 = qfl[(int64_t)(t + 1 < qrows ? t + 1 : 0) * a.nkact];
-      const double2 f2 = qfl[(int64_t)(t + 2 < qrows ? t + 2 : 0) * a.nkact];
+      const double2 f1 = j + 1 < SMAX ? qf[j + 1] : qx[j + 1 - SMAX];
+      const double2 f2 = j + 2 < SMAX ? qf[j + 2] : qx[j + 2 - SMAX];
       qf[j] = make_double2(f1.x, f2.y);
-      qr[j] = qfr[(int64_t)(t < qrows ? t : 0) * a.nkact];
     }
 #pragma unroll
     for (int j = 0; j < SMAX; ++j) {
@@ -835,14 +875,10 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
     double2 (&bp)[SMAX] = yp;  // in place, as in round 1
     double2 (&bq)[SMAX] = yq;
     const RunMap mq = sweep_run<SMAX, false>(bq, yq, len, cq);
-    maps[r * PS_COL + c] = sweep_run<SMAX, false>(bp, yp, len, cp);
-    __syncthreads();
+    const RunMap mp = sweep_run<SMAX, false>(bp, yp, len, cp);
     double2 p1, p2, q1, q2;
-    enter_state<false>(maps, r, c, p1, p2);
-    __syncthreads();
-    maps[r * PS_COL + c] = mq;
-    __syncthreads();
-    enter_state<false>(maps, r, c, q1, q2);
+    enter_state<false>(mp, r, p1, p2);
+    enter_state<false>(mq, r, q1, q2);
     add_entering<SMAX, false>(bp, len, p1, p2, cp);
     add_entering<SMAX, false>(bq, len, q1, q2, cq);
 #pragma unroll
@@ -856,7 +892,6 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
         yq[j] = cscale(cscale(bq[j], k0 ? -1.0 : srL[t]), -ell2);  // the chi source -ell^2 q
       }
     }
-    __syncthreads();
   }
 
   // ---- round 3 (descending): U w = -ell^2 q
@@ -865,15 +900,12 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
       al = su1[s0 + j];
       be = su2[s0 + j];
     };
-    maps[r * PS_COL + c] = sweep_run<SMAX, false>(yp, yq, len, cw);
-    __syncthreads();
     double2 w1, w2;
-    enter_state<false>(maps, r, c, w1, w2);
+    enter_state<false>(sweep_run<SMAX, false>(yp, yq, len, cw), r, w1, w2);
     add_entering<SMAX, false>(yp, len, w1, w2, cw);
 #pragma unroll
     for (int j = 0; j < SMAX; ++j)
       if (j < len) yp[j] = cscale(yp[j], sru[s0 + j]);
-    __syncthreads();
   }
 
   // ---- round 4 (ascending): D U^T y = w; chi is final
@@ -883,10 +915,8 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
       al = su1[s0 + j - 1];
       be = su2[s0 + j - 2];
     };
-    maps[r * PS_COL + c] = sweep_run<SMAX, true>(yq, yp, len, cu);
-    __syncthreads();
     double2 c1, c2;
-    enter_state<true>(maps, r, c, c1, c2);
+    enter_state<true>(sweep_run<SMAX, true>(yq, yp, len, cu), r, c1, c2);
     add_entering<SMAX, true>(yq, len, c1, c2, cu);
 #pragma unroll
     for (int j = 0; j < SMAX; ++j) {
@@ -902,20 +932,17 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
 
   // ---- m = 0: the gauge row n = 0 from the sums over the column
   if (m == 0) {
-    __syncthreads();
-    double* red = reinterpret_cast<double*>(maps);
-    const int e = r * PS_COL + c;
-    red[4 * e + 0] = gpr;
-    red[4 * e + 1] = gpi;
-    red[4 * e + 2] = gcr;
-    red[4 * e + 3] = gci;
-    __syncthreads();
+    // sums over the column's runs (a butterfly over its half wave, the same order on every lane)
+#pragma unroll
+    for (int d = PS_SEG / 2; d >= 1; d /= 2) {
+      gpr += __shfl_xor(gpr, d, PS_SEG);
+      gpi += __shfl_xor(gpi, d, PS_SEG);
+      gcr += __shfl_xor(gcr, d, PS_SEG);
+      gci += __shfl_xor(gci, d, PS_SEG);
+    }
     if (r == 0 && active) {
-      double s[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int i = 0; i < PS_SEG; ++i)
-        for (int v = 0; v < 4; ++v) s[v] += red[4 * (i * PS_COL + c) + v];
-      st2(ps, make_double2(-s[0] / sgw[0], -s[1] / sgw[0]));
-      st2(chv, make_double2(-s[2] / sgw[0], -s[3] / sgw[0]));
+      st2(ps, make_double2(-gpr / sgw[0], -gpi / sgw[0]));
+      st2(chv, make_double2(-gcr / sgw[0], -gci / sgw[0]));
     }
   }
 }
@@ -1250,14 +1277,15 @@ mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, dou
   int mmax, kmax;
   active_columns(p, &mmax, &kmax);
   a.kmax = kmax;
-  a.nkact = p->nz == 1 ? 1 : 2 * kmax + 1;
+  a.cb = col_blocks(kmax, p->nz);
+  const int nkact = p->nz == 1 ? 1 : 2 * kmax + 1;
   a.mmax = mmax;
   a.ell2 = p->g.ell * p->g.ell;
   a.kap0 = 2.0 * M_PI / p->g.lz;
   // runs of at most SMAX degrees: ceil((nrc - 1) / PS_SEG) for the longest column (m = 0)
   if (p->nrc - 1 > 16 * PS_SEG) return fail(MLG_E_UNSUPPORTED, "projection solves: nrc above 513");
   const int64_t total = p->tau * p->nz;
-  const bool solve = mmax > 0 && a.nkact > 0;
+  const bool solve = mmax > 0 && nkact > 0;
   if (total > 0 && !solve) {  // otherwise the solve blocks clear the inactive entries
     int blocks = (int)std::min<int64_t>((total + 255) / 256, 65536);
     double2* t0 = a.taps;
@@ -1274,9 +1302,8 @@ mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, dou
     if (mlg_status st = check_launch("zero_inactive_kernel")) return st;
   }
   if (solve) {
-    dim3 grid((unsigned)((a.nkact + PS_COL - 1) / PS_COL), (unsigned)mmax);
-    const size_t shm = (proj_maps_at(p->nrc) + (size_t)PS_SEG * PS_COL * (sizeof(RunMap) / sizeof(double))) *
-                       sizeof(double);
+    dim3 grid((unsigned)a.cb.nblk, (unsigned)mmax);
+    const size_t shm = proj_tables_len(p->nrc) * sizeof(double);
     const bool wide = p->nrc - 1 > 8 * PS_SEG;
     p->timing.begin("projection", s);
     if (red) {

@@ -96,8 +96,8 @@ struct mlg_plan_s {
   int64_t* d_goff = nullptr;
   int64_t ngram = 0;
   // L D L^T factors of G + kap^2 ell^2 L^-1 for every active (m, k) column of the projection:
-  // (l1, l2) and 1 / pivot at [m][n - m][active k slot], nrc + 2 rows per order (rows past the
-  // column are zero); the identity for k = 0
+  // (l1, l2) and 1 / pivot at [m][n - m][padded column of the aligned blocks, see col_blocks],
+  // nrc + 2 rows per order (rows past the column and padding columns are zero); the identity for k = 0
   double2* d_qfl = nullptr;
   double* d_qfr = nullptr;
   int max_rows_fwd = 0, max_rows_bwd = 0;
@@ -225,6 +225,32 @@ mlg_status closure_correct(mlg_closure_s* c, const double* psi, const double* ch
 const mlg_plan_s* closure_plan(const mlg_closure_s* c);
 // active column bounds of the projection: m < mmax, |k| <= kmax
 void active_columns(const mlg_plan_s* p, int* mmax, int* kmax);
+
+// The projection's active axial slots (|k| <= kmax) in blocks of 8 consecutive FFT slots aligned
+// to 8, so that the 8 complex values of a row a block touches form one aligned 128-byte segment:
+// blocks 0 .. nbpos-1 cover slots 0 .. 8 nbpos - 1 (active where kk <= kmax), blocks nbpos ..
+// nblk-1 cover slots nstart .. (active where kk >= nz - kmax).  A padded column index
+// idx = 8 b + c (0 <= idx < 8 nblk) names one slot; the positive and negative ranges never share
+// an active slot because kmax < nz / 2 (or nz = 1 and kmax = 0).
+struct ColBlocks {
+  int nbpos, nstart, nblk;
+};
+__host__ __device__ inline ColBlocks col_blocks(int kmax, int nz) {
+  ColBlocks b;
+  b.nbpos = (kmax + 8) / 8;
+  b.nstart = ((nz - kmax) / 8) * 8;
+  b.nblk = b.nbpos + (kmax >= 1 ? (nz - b.nstart + 7) / 8 : 0);
+  return b;
+}
+__host__ __device__ inline int colblk_kk(const ColBlocks& b, int idx, int kmax, int nz, bool& active) {
+  if (idx < 8 * b.nbpos) {
+    active = idx <= kmax && idx < nz;
+    return idx;
+  }
+  const int kk = b.nstart + idx - 8 * b.nbpos;
+  active = kmax >= 1 && kk >= nz - kmax && kk < nz;
+  return kk;
+}
 mlg_status launch_mask_tri(const mlg_plan_s* p, double* spec, hipStream_t s);
 // poisson.hip: inverse Laplacian of a scalar (variant 0: prescribed amplitude *c_in, 1: solved into
 // *c_out; ws0: tau * nz complex, ws1: tau * nz reals), and the far-field level removal of m = 0

@@ -416,9 +416,11 @@ mlg_status build_plan(mlg_plan_s* p) {
   {
     int mmax = 0, kmax = 0;
     active_columns(p, &mmax, &kmax);
-    const int nkact = nz == 1 ? 1 : 2 * kmax + 1;
+    // columns in the aligned blocks of the projection (padded index; inactive entries stay zero)
+    const ColBlocks cb = col_blocks(kmax, nz);
+    const int ncolp = 8 * cb.nblk;
     const int rows = nrc + 2;
-    const size_t cells = (size_t)std::max(mmax, 0) * rows * nkact;
+    const size_t cells = (size_t)std::max(mmax, 0) * rows * ncolp;
     std::vector<double2> qfl(std::max<size_t>(cells, 1), make_double2(0.0, 0.0));
     std::vector<double> qfr(std::max<size_t>(cells, 1), 0.0);
     const ld kap0 = 2 * acosl(-1.0L) / (ld)p->g.lz, ell2 = (ld)p->g.ell * (ld)p->g.ell;
@@ -426,12 +428,14 @@ mlg_status build_plan(mlg_plan_s* p) {
     for (int m = 0; m < mmax; ++m) {
       const int cnt = nrc - m, i0 = std::max(m, 1) - m;
       const int64_t gb = gf.goff[m];
-      for (int a = 0; a < nkact; ++a) {
-        const int kk = (a <= kmax) ? a : nz - (2 * kmax + 1 - a);
+      for (int a = 0; a < ncolp; ++a) {
+        bool act = false;
+        const int kk = colblk_kk(cb, a, kmax, nz, act);
+        if (!act) continue;
         const int k = (2 * kk < nz) ? kk : kk - nz;
         const ld sk = kap0 * kap0 * (ld)k * (ld)k * ell2;
         for (int t = i0; t < cnt; ++t) {
-          const size_t o = ((size_t)m * rows + t) * nkact + a;
+          const size_t o = ((size_t)m * rows + t) * ncolp + a;
           if (k == 0) {  // q = -Zhat: no solve
             qfr[o] = 1.0;
             continue;
