@@ -76,7 +76,11 @@ __device__ __forceinline__ int64_t phys_off(const Phi256& g, int64_t q) {
 // 32 lanes of a line lie in one wavefront, so the exchanges need only wavefront-level ordering.
 constexpr int WL = 32;       // lanes per line
 constexpr int VB = PL * WL;  // threads per block: 8 lines, 4 wavefronts
-constexpr int WROW = 288;    // LDS entries per line (harmonics at zpos(p), both exchanges)
+// LDS entries per line (harmonics at zpos(p), both exchanges).  286 = 14 (mod 16): the 8 lines of a
+// block sit at distinct even entry offsets modulo 16 (the 64 banks), so the gathers and scatters
+// that touch one order of all 8 lines (and the next order in the next 8 lanes) are conflict-free;
+// with the twiddles a block stays within 40 KB of LDS (four blocks per CU)
+constexpr int WROW = 286;
 
 __device__ __forceinline__ int zpos(int p) { return 33 * (p >> 5) + (p & 31); }
 

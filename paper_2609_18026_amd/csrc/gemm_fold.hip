@@ -271,7 +271,9 @@ __global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs<C2> a) {
   const double* __restrict__ P = a.Pf + a.off[m] * nr;
   const double* __restrict__ Q = a.Qf + a.off[m] * nr;
 
-  __shared__ double As[2][2][2][PD][TM];  // [buf][W Pbar, W Q_A][parity][half node][pair]
+  // [buf][W Pbar, W Q_A][parity][half node][pair]; rows padded by 16 so that the four rows a
+  // wave reads at once fall on different banks
+  __shared__ double As[2][2][2][PD][TM + 16];
   __shared__ double Bs[2][3][2][PD][16];  // [buf][a, b, c][sum, difference][half node][re 0..7 | im 0..7]
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;

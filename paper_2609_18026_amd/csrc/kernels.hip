@@ -568,8 +568,19 @@ constexpr int PS_SEG = 32;  // lanes (runs of degrees) per column: half a wave
 constexpr int PS_COL = 8;   // columns per block (two per wave)
 constexpr int PJ_PAD = 2;   // zero entries before and after each per-m coefficient table
 
-// LDS: 11 per-m tables of nrc + 2 PJ_PAD entries (doubles)
-__host__ __device__ constexpr size_t proj_tables_len(int nrc) { return 11 * ((size_t)nrc + 2 * PJ_PAD); }
+// LDS: 11 per-m tables of nrc + 2 PJ_PAD entries (doubles), each with one spare double after
+// every 8 entries: the lanes of a half wave read entries 8 apart (one run each), which would
+// otherwise fall on 4 banks
+__host__ __device__ constexpr int proj_table_stride(int nrc) {
+  return (nrc + 2 * PJ_PAD) + (nrc + 2 * PJ_PAD) / 8 + 2;
+}
+__host__ __device__ constexpr size_t proj_tables_len(int nrc) { return 11 * (size_t)proj_table_stride(nrc); }
+
+// entry t (t >= -PJ_PAD) of a per-m table that starts PJ_PAD doubles into its slot
+struct PTab {
+  double* p;
+  __device__ __forceinline__ double& operator[](int t) const { return p[t + ((t + 8) >> 3)]; }
+};
 
 // The affine map of a run: (y_last, y_before) = (c, p) + [h0 h1; h2 h3] (entering y_1, y_2)
 struct RunMap {
@@ -678,17 +689,9 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
   const int cnt = nrc - m;  // degrees n = m .. nrc-1 at index t = n - m
   const int i0 = (m > 0 ? m : 1) - m;  // first solved index (m = 0: n = 0 is the gauge row)
   const int len_t = cnt + 2 * PJ_PAD;
-  double* sg0 = sm + PJ_PAD;
-  double* sg1 = sg0 + len_t;
-  double* sg2 = sg1 + len_t;
-  double* srd = sg2 + len_t;
-  double* sl1 = srd + len_t;
-  double* sl2 = sl1 + len_t;
-  double* sru = sl2 + len_t;
-  double* su1 = sru + len_t;
-  double* su2 = su1 + len_t;
-  double* srL = su2 + len_t;
-  double* sgw = srL + len_t;
+  const int tstr = proj_table_stride(nrc);
+  const PTab sg0{sm + PJ_PAD}, sg1{sg0.p + tstr}, sg2{sg1.p + tstr}, srd{sg2.p + tstr}, sl1{srd.p + tstr},
+      sl2{sl1.p + tstr}, sru{sl2.p + tstr}, su1{sru.p + tstr}, su2{su1.p + tstr}, srL{su2.p + tstr}, sgw{srL.p + tstr};
   const int64_t gbase = a.off[m];
   const int lane = threadIdx.x & 63;
   const int c = (threadIdx.x >> 6) * 2 + (lane >> 5), r = lane & (PS_SEG - 1);  // column, run
