@@ -495,8 +495,11 @@ __global__ __launch_bounds__(VB) void zfft256w_kernel(const double2* __restrict_
   const int t = threadIdx.x, ll = t / WL, s = t % WL;
   tw[t] = twg[t];
   __syncthreads();
-  const int64_t f = blockIdx.x / per_field;
-  const int64_t row = (blockIdx.x - f * per_field) * PL + ll;
+  // consecutive blocks take the same rows of every field, last rows first: the stage before wrote
+  // them last, so they are the ones still held by the last-level cache
+  const int64_t nf = gridDim.x / per_field;
+  const int64_t f = blockIdx.x % nf;
+  const int64_t row = (per_field - 1 - blockIdx.x / nf) * PL + ll;
   if (row >= rows) return;  // no block barrier follows
   const S2* __restrict__ x = fs.in[f] + row * 256;
   double2 v[8];
