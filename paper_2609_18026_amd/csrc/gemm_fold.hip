@@ -297,7 +297,8 @@ __global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs<C2> a) {
   // when they are written to LDS, so the loads stay in flight across the MFMAs)
   struct Stage {
     double p[4], q[4];
-    double2 x, y;
+    C2 x, y;  // raw (float2 on reduced-precision plans): converted at the LDS store, so the loads
+              // stay in flight across the MFMAs
   };
   Stage ra, rn;
   auto load = [&](int i0, Stage& d) {
@@ -313,8 +314,8 @@ __global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs<C2> a) {
     }
     const int i = i0 + bkr;
     const bool ok = bkk >= 0 && i < half;
-    d.x = ok ? ld2(Xb + (int64_t)i * nz + bkk) : make_double2(0.0, 0.0);
-    d.y = ok ? ld2(Xb + (int64_t)(nr - 1 - i) * nz + bkk) : make_double2(0.0, 0.0);
+    d.x = ok ? Xb[(int64_t)i * nz + bkk] : czero<C2>();
+    d.y = ok ? Xb[(int64_t)(nr - 1 - i) * nz + bkk] : czero<C2>();
   };
   auto store = [&](int buf, const Stage& d) {
 #pragma unroll
@@ -325,10 +326,11 @@ __global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs<C2> a) {
       As[buf][1][par][kr][rr] = d.q[t] + 2.0 * d.p[t];  // w Q_A = w Q + 2 w Pbar
     }
     if (tid < 192) {
-      Bs[buf][bf][0][bkr][bcc] = d.x.x + d.y.x;
-      Bs[buf][bf][0][bkr][8 + bcc] = d.x.y + d.y.y;
-      Bs[buf][bf][1][bkr][bcc] = d.x.x - d.y.x;
-      Bs[buf][bf][1][bkr][8 + bcc] = d.x.y - d.y.y;
+      const double2 x = to_d2(d.x), y = to_d2(d.y);
+      Bs[buf][bf][0][bkr][bcc] = x.x + y.x;
+      Bs[buf][bf][0][bkr][8 + bcc] = x.y + y.y;
+      Bs[buf][bf][1][bkr][bcc] = x.x - y.x;
+      Bs[buf][bf][1][bkr][8 + bcc] = x.y - y.y;
     }
   };
 
