@@ -344,29 +344,30 @@ __global__ __launch_bounds__(VB) void phi_vec256_kernel(Phi256 g, const double2*
 }
 
 // ---------------------------------------------------------------- scalar phi stages (32-lane lines)
-// Two real lines (2p, 2p+1) travel as one complex line z = a + i b: the backward stage packs their
-// harmonics as the Hermitian pair spectrum in row 2p of Z, both line groups transform it and each
-// keeps its part; the forward stage transforms the pair, the even group stores the spectrum and the
-// harmonics of both lines are separated from it.  The twiddles are staged in LDS as in the vector
-// stage; the block barrier of the gather also publishes them.
-template <typename S2, typename S>
-__global__ __launch_bounds__(VB) void phi_bwd256_kernel(Phi256 g, const double2* __restrict__ twg,
-                                                        const S2* __restrict__ mixed, S* __restrict__ phys) {
-  __shared__ double2 Z[PL][WROW];
-  __shared__ double2 tw[256];
-  const int t = threadIdx.x, ll = t / WL, s = t % WL;
-  const int64_t q0 = (int64_t)blockIdx.x * PL;
-  tw[t] = twg[t];
-  if (t < PL / 2) Z[2 * t][zpos(128)] = make_double2(0.0, 0.0);
+// Two real lines (2p, 2p+1) travel as one complex line z = a + i b, so a block of 8 line groups
+// covers 16 real lines and every 256-point transform is used for two of them.  The backward stage
+// packs the pair's harmonics as the Hermitian pair spectrum; the forward stage transforms the pair
+// and separates the harmonics of both lines from its spectrum.  Gathers and scatters touch one
+// order of 16 consecutive lines (256 contiguous bytes).  The twiddles are staged in LDS as in the
+// vector stage; the block barrier of the gather publishes them.
+constexpr int PL2 = 2 * PL;  // real lines per block of the scalar stages
+
+// Z[pr] = the pair spectrum of lines q0 + 2 pr and q0 + 2 pr + 1 (orders m < min(M, 128); the
+// Nyquist position cleared).  Ends with a block barrier.
+template <typename S2>
+__device__ __forceinline__ void gather_pairs16(double2 (*Z)[WROW], const Phi256& g, const S2* __restrict__ mixed,
+                                               int64_t q0) {
+  const int t = threadIdx.x;
+  if (t < PL) Z[t][zpos(128)] = make_double2(0.0, 0.0);
   const int mmax = g.M < 128 ? g.M : 128;
 #pragma unroll
-  for (int it = 0; it < (PL / 2) * 128 / VB; ++it) {
+  for (int it = 0; it < PL * 128 / VB; ++it) {
     const int e = t + VB * it;
-    const int pr = e & (PL / 2 - 1), m = e / (PL / 2);
+    const int pr = e & (PL - 1), m = e >> 3;
     const int64_t qa = q0 + 2 * pr, qb = qa + 1;
     const double2 a = (m < mmax && qa < g.nlines) ? ld2(mixed + (int64_t)m * g.nlines + qa) : make_double2(0.0, 0.0);
     const double2 b = (m < mmax && qb < g.nlines) ? ld2(mixed + (int64_t)m * g.nlines + qb) : make_double2(0.0, 0.0);
-    double2* Zp = Z[2 * pr];
+    double2* Zp = Z[pr];
     if (m == 0) {
       Zp[0] = make_double2(a.x, b.x);
     } else {
@@ -375,54 +376,26 @@ __global__ __launch_bounds__(VB) void phi_bwd256_kernel(Phi256 g, const double2*
     }
   }
   __syncthreads();
-  double2 v[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) v[j] = Z[ll & ~1][33 * j + s];
-  __syncthreads();  // the odd line reads the even row before any line overwrites its own row
-  fft256w<true>(v, Z[ll], s, tw);
-  const int64_t q = q0 + ll;
-  if (q < g.nlines) {
-    const bool imag = (ll & 1) != 0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      // select values, not addresses, so that v stays in registers
-      const double re = v[k].x, im = v[k].y;
-      st1(phys + phys_off(g, q) + s + 32 * k, imag ? im : re);
-    }
-  }
 }
 
-template <typename S, typename S2>
-__global__ __launch_bounds__(VB) void phi_fwd256_kernel(Phi256 g, const double2* __restrict__ twg,
-                                                        const S* __restrict__ phys, S2* __restrict__ mixed) {
-  __shared__ double2 Z[PL][WROW];
-  __shared__ double2 tw[256];
-  const int t = threadIdx.x, ll = t / WL, s = t % WL;
-  const int64_t q0 = (int64_t)blockIdx.x * PL;
-  tw[t] = twg[t];
-  const int64_t qa = q0 + (ll & ~1), qb = qa + 1;
-  double2 v[8];
+// Scatters the spectrum X (v[j] = X[s + 32 j]) of each group's pair to the harmonics of its two
+// lines (orders m < M, scaled by 1/256; orders above mkeep written as zero).  Barriers at both ends.
+template <typename S2>
+__device__ __forceinline__ void scatter_pairs16(const double2 (&v)[8], double2 (*Z)[WROW], const Phi256& g,
+                                                int64_t q0, int ll, int s, S2* __restrict__ out) {
+  __syncthreads();  // every group's exchange reads are complete
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const double a = (qa < g.nlines) ? ld1(phys + phys_off(g, qa) + s + 32 * j) : 0.0;
-    const double b = (qb < g.nlines) ? ld1(phys + phys_off(g, qb) + s + 32 * j) : 0.0;
-    v[j] = make_double2(a, b);
-  }
-  __syncthreads();  // the twiddle table is staged
-  fft256w<false>(v, Z[ll], s, tw);
-  __syncthreads();  // every line's exchange reads are complete
-  if ((ll & 1) == 0) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) Z[ll][33 * k + s] = v[k];
-  }
+  for (int j = 0; j < 8; ++j) Z[ll][33 * j + s] = v[j];
   __syncthreads();
-  for (int e = t; e < PL * g.M; e += VB) {
-    const int l2 = e & (PL - 1), m = e >> 3;
+  const int t = threadIdx.x;
+  const int mmax = g.M < 128 ? g.M : 128;
+  for (int e = t; e < PL2 * g.M; e += VB) {
+    const int l2 = e & (PL2 - 1), m = e >> 4;
     const int64_t q = q0 + l2;
     if (q >= g.nlines) continue;
     double2 r = make_double2(0.0, 0.0);
-    if (m < 128 && m <= g.mkeep) {
-      const double2* Zp = Z[l2 & ~1];
+    if (m < mmax && m <= g.mkeep) {
+      const double2* Zp = Z[l2 >> 1];
       const double2 zm = Zp[zpos(m)];
       const double2 zc = cconj(Zp[zpos((256 - m) & 255)]);
       if ((l2 & 1) == 0) {
@@ -432,50 +405,84 @@ __global__ __launch_bounds__(VB) void phi_fwd256_kernel(Phi256 g, const double2*
         r = make_double2(0.5 / 256.0 * d.y, -0.5 / 256.0 * d.x);
       }
     }
-    st2(mixed + (int64_t)m * g.nlines + q, r);
+    st2(out + (int64_t)m * g.nlines + q, r);
+  }
+  __syncthreads();
+}
+
+template <typename S2, typename S>
+__global__ __launch_bounds__(VB) void phi_bwd256_kernel(Phi256 g, const double2* __restrict__ twg,
+                                                        const S2* __restrict__ mixed, S* __restrict__ phys) {
+  __shared__ double2 Z[PL][WROW];
+  __shared__ double2 tw[256];
+  const int t = threadIdx.x, ll = t / WL, s = t % WL;
+  const int64_t q0 = (int64_t)blockIdx.x * PL2;
+  tw[t] = twg[t];
+  gather_pairs16(Z, g, mixed, q0);
+  double2 v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = Z[ll][33 * j + s];
+  fft256w<true>(v, Z[ll], s, tw);
+  const int64_t qa = q0 + 2 * ll, qb = qa + 1;
+  if (qa < g.nlines) {
+    const int64_t o = phys_off(g, qa) + s;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) st1(phys + o + 32 * k, v[k].x);
+  }
+  if (qb < g.nlines) {
+    const int64_t o = phys_off(g, qb) + s;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) st1(phys + o + 32 * k, v[k].y);
   }
 }
 
-// u = B(u_hat), g(u) = u^2 or gamma u (1 - u), back to harmonics; one real line per 32 lanes
+template <typename S, typename S2>
+__global__ __launch_bounds__(VB) void phi_fwd256_kernel(Phi256 g, const double2* __restrict__ twg,
+                                                        const S* __restrict__ phys, S2* __restrict__ mixed) {
+  __shared__ double2 Z[PL][WROW];
+  __shared__ double2 tw[256];
+  const int t = threadIdx.x, ll = t / WL, s = t % WL;
+  const int64_t q0 = (int64_t)blockIdx.x * PL2;
+  tw[t] = twg[t];
+  const int64_t qa = q0 + 2 * ll, qb = qa + 1;
+  const int64_t oa = qa < g.nlines ? phys_off(g, qa) + s : 0, ob = qb < g.nlines ? phys_off(g, qb) + s : 0;
+  double2 v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const double a = (qa < g.nlines) ? ld1(phys + oa + 32 * j) : 0.0;
+    const double b = (qb < g.nlines) ? ld1(phys + ob + 32 * j) : 0.0;
+    v[j] = make_double2(a, b);
+  }
+  __syncthreads();  // the twiddle table is staged
+  fft256w<false>(v, Z[ll], s, tw);
+  scatter_pairs16(v, Z, g, q0, ll, s, mixed);
+}
+
+// Scalar nonlinear term of Sec. 3.3 / Sec. 5.2 on two lines per group: inverse transform of the
+// pair, u^2 or gamma u (1 - u) on each real line, forward transform of the pair of products.
 template <int MODE, typename S2>
 __global__ __launch_bounds__(VB) void phi_scalar256_kernel(Phi256 g, const double2* __restrict__ twg, S2* mixed,
                                                            double gamma) {
   __shared__ double2 Z[PL][WROW];
   __shared__ double2 tw[256];
   const int t = threadIdx.x, ll = t / WL, s = t % WL;
-  const int64_t q0 = (int64_t)blockIdx.x * PL;
+  const int64_t q0 = (int64_t)blockIdx.x * PL2;
   tw[t] = twg[t];
-  if (t < PL) Z[t][zpos(128)] = make_double2(0.0, 0.0);
-  const int mmax = g.M < 128 ? g.M : 128;
-#pragma unroll
-  for (int it = 0; it < PL * 128 / VB; ++it) {
-    const int e = t + VB * it;
-    const int l2 = e & (PL - 1), m = e >> 3;
-    const int64_t q = q0 + l2;
-    const double2 a = (m < mmax && q < g.nlines) ? ld2(mixed + (int64_t)m * g.nlines + q) : make_double2(0.0, 0.0);
-    if (m == 0) {
-      Z[l2][0] = make_double2(a.x, 0.0);
-    } else {
-      Z[l2][zpos(m)] = a;
-      Z[l2][zpos(256 - m)] = cconj(a);
-    }
-  }
-  __syncthreads();
+  gather_pairs16(Z, g, mixed, q0);
   double2 v[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) v[j] = Z[ll][33 * j + s];
   fft256w<true>(v, Z[ll], s, tw);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const double u = v[k].x;
-    const double r = (MODE == MLG_RHS_U2) ? u * u : gamma * u * (1.0 - u);
-    v[k] = make_double2(r, 0.0);
+    const double ua = v[k].x, ub = v[k].y;
+    v[k] = (MODE == MLG_RHS_U2) ? make_double2(ua * ua, ub * ub)
+                                : make_double2(gamma * ua * (1.0 - ua), gamma * ub * (1.0 - ub));
   }
   fft256w<false>(v, Z[ll], s, tw);
-  scatter_pair_w(v, Z, g, q0, ll, s, mixed, (S2*)nullptr);
+  scatter_pairs16(v, Z, g, q0, ll, s, mixed);
 }
 
-// ---------------------------------------------------------------- z transforms (32-lane lines)
 // Contiguous lines of 256 samples, up to six fields per launch (blocks field-major).  Lane s of a
 // line loads x[s + 32 j] straight into registers (32 lanes cover 512 contiguous bytes), fft256w
 // transforms the line within its wavefront and the lane stores X[s + 32 j]: the only block
@@ -581,7 +588,7 @@ mlg_status launch_zfft256(const mlg_plan_s* p, const double* const* in, double* 
 
 mlg_status launch_phi256_forward(const mlg_plan_s* p, const double* phys, double* mixed, hipStream_t s) {
   Phi256 g = phi256_geom(p, false);
-  dim3 grid((unsigned)((g.nlines + PL - 1) / PL));
+  dim3 grid((unsigned)((g.nlines + PL2 - 1) / PL2));
   const double2* tw = reinterpret_cast<const double2*>(p->d_tw_phi);
   p->timing.begin("phi_fft", s);
   if (reduced(p))
@@ -595,7 +602,7 @@ mlg_status launch_phi256_forward(const mlg_plan_s* p, const double* phys, double
 
 mlg_status launch_phi256_backward(const mlg_plan_s* p, const double* mixed, double* phys, hipStream_t s) {
   Phi256 g = phi256_geom(p, false);
-  dim3 grid((unsigned)((g.nlines + PL - 1) / PL));
+  dim3 grid((unsigned)((g.nlines + PL2 - 1) / PL2));
   const double2* tw = reinterpret_cast<const double2*>(p->d_tw_phi);
   p->timing.begin("phi_fft", s);
   if (reduced(p))
@@ -609,7 +616,7 @@ mlg_status launch_phi256_backward(const mlg_plan_s* p, const double* mixed, doub
 
 template <typename S2>
 static void phi_scalar_go(const mlg_plan_s* p, const Phi256& g, int kind, double gamma, double* mixed, hipStream_t s) {
-  dim3 grid((unsigned)((g.nlines + PL - 1) / PL));
+  dim3 grid((unsigned)((g.nlines + PL2 - 1) / PL2));
   const double2* tw = reinterpret_cast<const double2*>(p->d_tw_phi);
   if (kind == MLG_RHS_U2)
     phi_scalar256_kernel<MLG_RHS_U2, S2><<<grid, VB, 0, s>>>(g, tw, reinterpret_cast<S2*>(mixed), gamma);
