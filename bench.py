@@ -261,21 +261,32 @@ def cpu_baseline(n_sample: int, gpu_small: dict):
 
 
 def bench_batched(torch, args, stream, e0, e1, count=64, seed=3):
-    """64 uneven 2D KPP instances in one persistent launch (autotuned), FP64 and FP32."""
+    """64 uneven 2D KPP instances (the batched reaction-diffusion recipe: Gaussian bumps u on uneven
+    grids, transformed by per-instance FP64 plans of the library) in three persistent launches
+    (autotuned), FP64 and FP32."""
     import synth
-    from paper_2609_18026_amd import MLG_FP32, Batch, mlg_grid
+    from paper_2609_18026_amd import MLG_FP32, Batch, Plan, mlg_grid
     insts = synth.batched_instances(count, seed)
     grids = [mlg_grid(d["nr"], d["nphi"], 1, 0, 0, 0, d["ell"], 2 * np.pi, 1) for d in insts]
     dofs = sum(d["nr"] * d["nphi"] for d in insts)
-    res = {"instances": count, "grid_points": dofs}
+    res = {"instances": count, "grid_points": dofs,
+           "input": "Gaussian bumps u = A exp(-|x - x0|^2 / (2 sigma^2)) per instance, forward-transformed in FP64"}
+    spectra = []
+    for d in insts:
+        with Plan(d["nr"], d["nphi"], 1, d["ell"], 2 * np.pi) as pk:
+            x, w, r = pk.nodes()
+            phi = 2 * np.pi * np.arange(d["nphi"]) / d["nphi"]
+            u = synth.gaussian_bump(r, phi, d["amp"], d["sigma"], d["x0"], d["y0"])[None]
+            sk = pk.empty_spec()
+            pk.forward(torch.from_numpy(np.ascontiguousarray(u)).cuda(), sk)
+            torch.cuda.synchronize()
+            spectra.append(sk[:, 0].clone())
     outs = {}
     for prec, name in ((0, "fp64"), (MLG_FP32, "fp32")):
         b = Batch(grids, prec=prec)
         sin = b.empty_spec()
-        for k, d in enumerate(insts):
-            M = d["nphi"] // 2
-            S = synth.geometric_spectrum(M, d["nr"], 1, 1, seed=1000 + k, a=0.9, b=0.85, c=1.0)
-            sin[int(b.offsets[k]):int(b.offsets[k + 1])] = torch.from_numpy(synth.to_packed(S)[:, 0]).to(sin.dtype).cuda()
+        for k, sk in enumerate(spectra):
+            sin[int(b.offsets[k]):int(b.offsets[k + 1])] = sk.to(sin.dtype)
         sout = b.empty_spec()
         chosen, tune_ms = b.autotune(0.25, sin, sout)
         for _ in range(args.warmup):
