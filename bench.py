@@ -39,25 +39,25 @@ U_FRAME = (0.0, 1.0, 0.0)
 # kernel source hashes to the one that was measured (profiles/rhs_tp_256cubed_kernels.md).
 _SUMMARY = "profiles/rhs_tp_256cubed_kernels.md"
 MEASURED_TRAFFIC = {
-    "synth_gemm": {"bytes": 1230354309, "launches": 1, "n": 256,
+    "synth_gemm": {"bytes": 1233099161, "launches": 1, "n": 256,
                    "source": "paper_2609_18026_amd/csrc/gemm_fold.hip",
-                   "sha256": "84d4cf04f47c93362325ec24de02171f7176c99070f937db2417af6cecfdbaac",
-                   "profile_avg_ms": 0.5847, "mfma_counter_flops": 23.49e9, "mfma_busy_pct": 57.1},
-    "proj_gemm": {"bytes": 435622755, "launches": 1, "n": 256,
+                   "sha256": "2939c7e59d7766134d5c8f5edaede3b25a5421c1c73a7c1c9c256c5413980c35",
+                   "profile_avg_ms": 0.5767, "mfma_counter_flops": 23.49e9, "mfma_busy_pct": 57.0},
+    "proj_gemm": {"bytes": 432848665, "launches": 1, "n": 256,
                   "source": "paper_2609_18026_amd/csrc/gemm_fold.hip",
-                  "sha256": "84d4cf04f47c93362325ec24de02171f7176c99070f937db2417af6cecfdbaac",
-                  "profile_avg_ms": 0.2934, "mfma_counter_flops": 9.92e9, "mfma_busy_pct": 47.6},
-    "phi_fft": {"bytes": 1208585854, "launches": 1, "n": 256,
+                  "sha256": "2939c7e59d7766134d5c8f5edaede3b25a5421c1c73a7c1c9c256c5413980c35",
+                  "profile_avg_ms": 0.2808, "mfma_counter_flops": 8.82e9, "mfma_busy_pct": 42.4},
+    "phi_fft": {"bytes": 1208374834, "launches": 1, "n": 256,
                 "source": "paper_2609_18026_amd/csrc/fft256.hip",
-                "sha256": "93a06b07484b790647c3f80faaeb11a12efd4b135ae8bd5e55a626eb1f9e92f9",
-                "profile_avg_ms": 0.3400},
-    "z_fft": {"bytes": 1610641118 + 541195848, "launches": 2, "n": 256,
+                "sha256": "74322a2edc0650c5b2fe33aab5345d8752c9754b60a4a8e17dbe069440a06476",
+                "profile_avg_ms": 0.3127},
+    "z_fft": {"bytes": 1610685052 + 541187611, "launches": 2, "n": 256,
               "source": "paper_2609_18026_amd/csrc/fft256.hip",
-              "sha256": "93a06b07484b790647c3f80faaeb11a12efd4b135ae8bd5e55a626eb1f9e92f9"},
-    "projection": {"bytes": 740674066, "launches": 1, "n": 256,
+              "sha256": "74322a2edc0650c5b2fe33aab5345d8752c9754b60a4a8e17dbe069440a06476"},
+    "projection": {"bytes": 519392734, "launches": 1, "n": 256,
                    "source": "paper_2609_18026_amd/csrc/kernels.hip",
-                   "sha256": "86025379f5b0d354ca6fb9eba0a3cbbb53175d90075106a221c6c89107e2c08a",
-                   "profile_avg_ms": 0.2013},
+                   "sha256": "90dc6d4af36482c08607add01ef558c8cead0e056a43b3296a40141e0da0ea6b",
+                   "profile_avg_ms": 0.1806},
 }
 
 
