@@ -3,7 +3,8 @@
 * 256^3 (the bench plan: N_r = N_phi = N_z = 256, ell = 1, L_z = 8.6, two-thirds mask, FP64): the
   vortex-pair stream function plus a small geometric poloidal part.  The oracle computes sampled
   outputs one by one, each stage from the library's own previous stage: forward-transform columns
-  from the physical field; backward-transform values at points; nodal u and omega at points from
+  from the physical field (the leading columns, random ones and high orders m >= 96, each also
+  checked at its own scale); backward-transform values at points; nodal u and omega at points from
   (psi, chi); N = (U + u) x omega at every node from the library's u and omega; the Galerkin sources
   at sampled columns from the library's N; the backward error of the elliptic solves at those
   columns from the library's sources.
@@ -107,6 +108,10 @@ def test_full_size_256_sampled():
     # forward transform: sampled columns from the physical field
     # the pair is odd in x (even orders vanish): sample the largest columns and some random ones
     cols = _pick_columns(psi_host, 6, 4, seed=5)
+    # and high orders, whose columns are orders of magnitude smaller than the leading ones
+    hi_m = np.zeros((g.M, g.nz), dtype=bool)
+    hi_m[96:] = True
+    cols += [c for c in _pick_columns(psi_host, 2, 2, seed=6, allowed=hi_m) if c not in cols]
     _say("  columns", cols)
     _say("  forward columns")
     fc = forward_columns(f, g, cols)
@@ -115,6 +120,15 @@ def test_full_size_256_sampled():
     err = rel(got, want)
     _say("  forward columns rel", err)
     assert err < TOL
+    # column by column, at the column's own scale: an error confined to a small column must stay
+    # within 1e-12 of that column plus 1e-13 of the largest sampled column (rounding spread from the
+    # large orders by the azimuthal FFT)
+    big = max(np.linalg.norm(fc[c]) for c in cols)
+    for mm, kk in cols:
+        e_c = np.linalg.norm(psi_host[mm, :, kk] - fc[(mm, kk)])
+        n_c = np.linalg.norm(fc[(mm, kk)])
+        _say(f"    column (m={mm}, kk={kk}): |col| / max = {n_c / big:.1e}, error / max = {e_c / big:.1e}")
+        assert e_c <= 1e-12 * n_c + 1e-13 * big, (mm, kk, e_c, n_c, big)
 
     # backward transform: values at points from the library's coefficients
     _say("  backward points")
@@ -158,6 +172,9 @@ def test_full_size_256_sampled():
     from oracle.rhs import dealias_mask
     Cl, Kl, Zl = (from_lib(src[i], g.M, g.nrc) for i in range(3))
     acols = _pick_columns(Cl, 5, 4, seed=6, allowed=dealias_mask(g)) + [(0, 0), (85, 85)]
+    hi = dealias_mask(g).copy()
+    hi[:64] = False
+    acols += [c for c in _pick_columns(Cl, 1, 2, seed=8, allowed=hi) if c not in acols]
     _say("  columns", acols)
     pc = projection_sources_columns(nodal[6], nodal[7], nodal[8], g, vt, acols)
     for i, name in enumerate(("C", "K", "Z")):
@@ -166,6 +183,16 @@ def test_full_size_256_sampled():
         e = rel(lib_v, ref_v)
         _say("  source", name, "rel", e)
         assert e < TOL
+        # column by column at the column's own scale (as for the forward columns).  The curl-type
+        # sources are a cancelling residual of N for this near-steady pair (|C| ~ |N| / 90), which
+        # enlarges rounding about 90 times: a large column reaches 1.2e-12 of itself (measured; the
+        # normwise figure is 9e-13), a small one 4e-13 of the largest column
+        big = max(np.linalg.norm(pc[c][i]) for c in acols)
+        for c in acols:
+            e_c = np.linalg.norm((Cl, Kl, Zl)[i][c[0], :, c[1]] - pc[c][i])
+            n_c = np.linalg.norm(pc[c][i])
+            _say(f"    source {name} column {c}: |col| / max = {n_c / big:.1e}, error / max = {e_c / big:.1e}")
+            assert e_c <= 4e-12 * n_c + 1e-12 * big, (name, c, e_c, n_c, big)
     _say("  solves at columns")
     pl, cl = from_lib(po.cpu().numpy(), g.M, g.nrc), from_lib(co.cpu().numpy(), g.M, g.nrc)
     worst = max(_column_backward_error(g, mm, kk, pl[mm, :, kk], cl[mm, :, kk], Cl[mm, :, kk], Kl[mm, :, kk],
