@@ -28,7 +28,6 @@ using namespace ::mlg::dev;
 
 constexpr int TM = 64;  // rows per block (half nodes, or pairs of degrees)
 constexpr int TC8 = 8;  // complex columns per block (re and im share the 16 MFMA columns)
-constexpr int TP = 8;   // k depth per LDS stage of the synthesis (pairs of degrees)
 constexpr int PD = 8;   // k depth per LDS stage of the projection products (half nodes)
 
 typedef float float4_t __attribute__((ext_vector_type(4)));
@@ -101,11 +100,16 @@ __device__ __forceinline__ void synth_write(const FoldSynthArgs<R, C2>& a, int m
   st2(a.out[5] + o, wz);
 }
 
-// Block tile: 64 half nodes x 8 complex columns; the 16 MFMA columns hold [re 0..7 | im 0..7], so
-// lane l accumulates the real (l%16 < 8) or imaginary part of complex column (l%16) % 8; partner
-// lanes l and l ^ 8 exchange their parts in the epilogue, then one writes node i and the other
-// its mirror.
-template <typename R, typename C2>
+// Block tile: 64 half nodes x 8 complex columns; wavefront w takes 16 half nodes.  The 16 MFMA
+// columns hold [re 0..7 | im 0..7], so lane l accumulates the real (l%16 < 8) or imaginary part of
+// complex column (l%16) % 8; partner lanes l and l ^ 8 exchange their parts in the epilogue, then
+// one writes node i and the other its mirror.  Each wavefront loads its own operands straight into
+// the MFMA layouts, D k-steps (of 4 pairs) ahead in a register ring: the table rows of its 16
+// nodes (private to it) and the spectra of the block's 8 columns (which the four wavefronts read
+// alike, from the L1 cache).  No LDS and no block barrier, so the kernel holds 3 waves per SIMD
+// (with LDS staging and a barrier per stage it held 2 and ran 8% longer).  Loads are clamped into
+// the tables; degrees past the column are zeroed on the spectrum side.
+template <typename R, typename C2, int D>
 __global__ __launch_bounds__(256, 2) void synth_fold_kernel(FoldSynthArgs<R, C2> a) {
   Tile3 tl;
   if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
@@ -113,115 +117,73 @@ __global__ __launch_bounds__(256, 2) void synth_fold_kernel(FoldSynthArgs<R, C2>
   const int half = a.nr / 2;
   const int row0 = tl.y * TM;
   const int kk0 = tl.x * TC8;
-  if (row0 >= half || kk0 >= a.nz) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (row0 + wave * 16 >= half || kk0 >= a.nz) return;
   const int K = a.nrc > m ? a.nrc - m : 0;
   const int KP = (K + 1) / 2;
   const int nr = a.nr, nz = a.nz;
   const R* __restrict__ P = a.Pb + a.off[m] * nr;
   const R* __restrict__ T = a.Tb + a.off[m] * nr;
-  const C2* __restrict__ ps = a.psi + a.off[m] * nz;
-  const C2* __restrict__ ch = a.chi + a.off[m] * nz;
-
-  __shared__ R As[2][2][2][TP][TM];  // [buf][P, T][parity][pair][half node]
-  __shared__ R Bs[2][2][2][TP][16];  // [buf][psi, chi][parity][pair][re 0..7 | im 0..7]
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int cl = lane & 15;
-  typename Mma<R>::acc acc[2][7];  // [parity][product]
+  const R* __restrict__ ps = reinterpret_cast<const R*>(a.psi + a.off[m] * nz);
+  const R* __restrict__ ch = reinterpret_cast<const R*>(a.chi + a.off[m] * nz);
+  const int cl = lane & 15, kq = lane >> 4;
+  const int inode = min(row0 + wave * 16 + cl, half - 1);
+  const int kk = kk0 + (cl & 7), part = cl >> 3;
+  const bool colok = kk < nz;
+  const int boff = 2 * (colok ? kk : 0) + part;  // real component of column kk (re or im)
+  typename Mma<R>::acc acc[2][7];
 #pragma unroll
-  for (int s = 0; s < 2; ++s)
+  for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
-    for (int p = 0; p < 7; ++p) acc[s][p] = Mma<R>::zero();
-
-  // Operands of the next two stages alternate between two register sets.  Every load is
-  // unconditional (indices clamped into the table; entries outside it are zeroed when written to
-  // LDS), so writing one set waits only for that set while the other set's loads stay in flight
-  // across the MFMAs of the current stage.
-  struct Stage {
-    R a[8];
-    C2 b;
+    for (int p = 0; p < 7; ++p) acc[s2][p] = Mma<R>::zero();
+  struct Step {
+    R p[2], t[2], bp[2], bc[2];
   };
-  Stage sx, sy;
+  Step st[D];
   const int Kc = K > 0 ? K - 1 : 0;
-  const int fld = tid >> 7, bpar = (tid >> 6) & 1, bkr = (tid >> 3) & 7, bcc = tid & 7;
-  const int bkk = kk0 + bcc;
-  const C2* __restrict__ Bsrc = (fld ? ch : ps) + (bkk < nz ? bkk : nz - 1);
-  auto load = [&](int jj0, Stage& d) {
+  auto load = [&](int ks, Step& d) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int e = tid + 256 * t;
-      const int par = (e >> 9) & 1, kr = (e >> 6) & 7, rr = e & 63;
-      const int j = min(2 * (jj0 + kr) + par, Kc), i = min(row0 + rr, half - 1);
-      d.a[t] = ((t >> 2) ? T : P)[(int64_t)j * nr + i];
+    for (int par = 0; par < 2; ++par) {
+      const int j = min(2 * (4 * ks + kq) + par, Kc);
+      d.p[par] = P[(int64_t)j * nr + inode];
+      d.t[par] = T[(int64_t)j * nr + inode];
+      d.bp[par] = ps[(int64_t)j * 2 * nz + boff];
+      d.bc[par] = ch[(int64_t)j * 2 * nz + boff];
     }
-    const int j = min(2 * (jj0 + bkr) + bpar, Kc);
-    d.b = Bsrc[(int64_t)j * nz];
   };
-  auto store = [&](int buf, int jj0, const Stage& d) {
+  auto compute = [&](int ks, const Step& d) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int e = tid + 256 * t;
-      const int par = (e >> 9) & 1, kr = (e >> 6) & 7, rr = e & 63;
-      const bool ok = 2 * (jj0 + kr) + par < K && row0 + rr < half;
-      As[buf][t >> 2][par][kr][rr] = ok ? d.a[t] : R(0);
+    for (int par = 0; par < 2; ++par) {
+      const int j = 2 * (4 * ks + kq) + par;
+      const bool ok = j < K && colok;
+      const R n = (R)(m + j);
+      const R Ln = n * (n + R(1));
+      const R bp = ok ? d.bp[par] : R(0), bc = ok ? d.bc[par] : R(0);
+      const R lp = Ln * bp, lc = Ln * bc;
+      typename Mma<R>::acc(&c)[7] = acc[par];
+      c[0] = MFMA(d.p[par], bp, c[0]);
+      c[1] = MFMA(d.t[par], bp, c[1]);
+      c[2] = MFMA(d.p[par], lp, c[2]);
+      c[3] = MFMA(d.p[par], bc, c[3]);
+      c[4] = MFMA(d.t[par], bc, c[4]);
+      c[5] = MFMA(d.p[par], lc, c[5]);
+      c[6] = MFMA(d.t[par], lc, c[6]);
     }
-    const bool ok = 2 * (jj0 + bkr) + bpar < K && bkk < nz;
-    Bs[buf][fld][bpar][bkr][bcc] = ok ? d.b.x : R(0);
-    Bs[buf][fld][bpar][bkr][8 + bcc] = ok ? d.b.y : R(0);
   };
-  auto compute = [&](int buf, int kt) {
+  const int nks = (KP + 3) / 4;
+  if (nks > 0) {
 #pragma unroll
-    for (int ks = 0; ks < TP; ks += 4) {
-      const int kr = ks + (lane >> 4);
+    for (int d = 0; d < D; ++d) load(d, st[d]);
+    for (int k0 = 0; k0 < nks; k0 += D) {
 #pragma unroll
-      for (int par = 0; par < 2; ++par) {
-        const R n = (R)(m + 2 * (kt * TP + kr) + par);
-        const R Ln = n * (n + R(1));
-        const R aP = As[buf][0][par][kr][wave * 16 + cl];
-        const R aT = As[buf][1][par][kr][wave * 16 + cl];
-        const R bp = Bs[buf][0][par][kr][cl], bc = Bs[buf][1][par][kr][cl];
-        const R lp = Ln * bp, lc = Ln * bc;
-        typename Mma<R>::acc(&c)[7] = acc[par];
-        c[0] = MFMA(aP, bp, c[0]);  // A1 = Pbar psi
-        c[1] = MFMA(aT, bp, c[1]);  // A2 = Tbar psi
-        c[2] = MFMA(aP, lp, c[2]);  // A3 = Pbar L psi
-        c[3] = MFMA(aP, bc, c[3]);  // B1 = Pbar chi
-        c[4] = MFMA(aT, bc, c[4]);  // B2 = Tbar chi
-        c[5] = MFMA(aP, lc, c[5]);  // B3 = Pbar L chi
-        c[6] = MFMA(aT, lc, c[6]);  // B4 = Tbar L chi
+      for (int d = 0; d < D; ++d) {
+        if (k0 + d < nks) compute(k0 + d, st[d]);
+        load(k0 + d + D, st[d]);
       }
     }
-  };
-
-  const int nk = (KP + TP - 1) / TP;
-  if (nk > 0) {
-    load(0, sx);
-    store(0, 0, sx);
-    load(TP, sy);
-    __syncthreads();
-    // stages in pairs (LDS buffer 0, then 1); a stage past the last is loaded from clamped
-    // addresses and written as zeros, and an odd last stage is multiplied after the loop
-    int kt = 0;
-    for (; kt + 1 < nk; kt += 2) {
-      load((kt + 2) * TP, sx);
-      __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
-      compute(0, kt);
-      __builtin_amdgcn_sched_barrier(0);  // and the LDS writes (which wait for their set) after them
-      store(1, (kt + 1) * TP, sy);
-      __syncthreads();
-      load((kt + 3) * TP, sy);
-      __builtin_amdgcn_sched_barrier(0);
-      compute(1, kt + 1);
-      __builtin_amdgcn_sched_barrier(0);
-      store(0, (kt + 2) * TP, sx);
-      __syncthreads();
-    }
-    if (kt < nk) compute(0, kt);
   }
   const bool hi = cl >= 8;
-  const int kk = kk0 + (cl & 7);
-  const double kap = a.kap0 * kval(kk < nz ? kk : 0, nz);
-  // Tbar-type products (A2, B2, B4) flip sign with the node
+  const double kap = a.kap0 * kval(colok ? kk : 0, nz);
   constexpr bool tsign[7] = {false, true, false, false, true, false, true};
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -232,11 +194,10 @@ __global__ __launch_bounds__(256, 2) void synth_fold_kernel(FoldSynthArgs<R, C2>
       const double e = (double)acc[0][p][v], o = (double)acc[1][p][v];
       const double e2 = __shfl_xor(e, 8), o2 = __shfl_xor(o, 8);
       const double er = hi ? e2 : e, ei = hi ? e : e2, orr = hi ? o2 : o, oi = hi ? o : o2;
-      // the low lane writes node i (E + O), the high lane the mirror node
       val[p] = !hi ? make_double2(er + orr, ei + oi)
                    : (tsign[p] ? make_double2(orr - er, oi - ei) : make_double2(er - orr, ei - oi));
     }
-    if (i < half && kk < nz) synth_write(a, m, hi ? nr - 1 - i : i, kk, kap, val);
+    if (i < half && colok) synth_write(a, m, hi ? nr - 1 - i : i, kk, kap, val);
   }
 }
 
@@ -661,7 +622,7 @@ static void synth_fold_go(const mlg_plan_s* p, const R* Pb, const R* Tb, const d
   a.gx = (p->nz + TC8 - 1) / TC8;
   a.gy = (p->nr / 2 + TM - 1) / TM;
   a.gz = p->M;
-  synth_fold_kernel<R, C2><<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
+  synth_fold_kernel<R, C2, 2><<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
 }
 
 // psi, chi: spectral arrays of the plan's data type; out6: mixed harmonics (float2 on MLG_FP32
