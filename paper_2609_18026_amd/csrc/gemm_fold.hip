@@ -28,7 +28,6 @@ using namespace ::mlg::dev;
 
 constexpr int TM = 64;  // rows per block (half nodes, or pairs of degrees)
 constexpr int TC8 = 8;  // complex columns per block (re and im share the 16 MFMA columns)
-constexpr int PD = 8;   // k depth per LDS stage of the projection products (half nodes)
 
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
@@ -215,135 +214,110 @@ struct FoldProjArgs {
 };
 
 // Block tile: 64 pairs of degrees (even and odd n - m) x 8 complex columns, [re | im] packed in
-// the 16 MFMA columns as in synth_fold_kernel; the low lane of a partner pair writes the even
-// degree, the high lane the odd one.
-template <typename C2>
-__global__ __launch_bounds__(256, 2) void proj_fold_kernel(FoldProjArgs<C2> a) {
+// the 16 MFMA columns as in synth_fold_kernel; wavefront w takes 16 pairs, the low lane of a partner
+// pair writes the even degree, the high lane the odd one.  Register-fed like the synthesis: each
+// wavefront loads its table rows (its 16 pairs, both parities) and the block's field values at a
+// half node and its mirror straight into the MFMA layouts, D k-steps (of 4 half nodes) ahead, and
+// forms the sums, differences and W Q_A = W Q + 2 W Pbar in registers.  No LDS and no barrier: at
+// D = 1 the kernel holds 4 waves per SIMD (with LDS staging it held 2 and ran 12% longer).  Loads
+// are clamped; half nodes past the last are zeroed on the field side, and the entries of pairs
+// past the column and of inactive columns are computed but not stored.  Fields are float2 on
+// reduced-precision plans (converted after the load has landed).
+template <typename C2, int D>
+__global__ __launch_bounds__(256, 4) void proj_fold_kernel(FoldProjArgs<C2> a) {
   typedef double R;
+  typedef decltype(C2().x) S;  // storage real type of the fields
   Tile3 tl;
   if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
   const int m = tl.z;
   const int rows = a.nrc > m ? a.nrc - m : 0;
   const int KP = (rows + 1) / 2;
-  const int row0 = tl.y * TM;  // pair index
-  const int c0 = tl.x * TC8;  // padded column index of the block's first slot
-  if (row0 >= KP) return;
+  const int row0 = tl.y * TM;
+  const int c0 = tl.x * TC8;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int pr0 = row0 + wave * 16;
+  if (pr0 >= KP) return;
   const int nr = a.nr, nz = a.nz, half = a.nr / 2;
   const double* __restrict__ P = a.Pf + a.off[m] * nr;
   const double* __restrict__ Q = a.Qf + a.off[m] * nr;
-
-  // [buf][W Pbar, W Q_A][parity][half node][pair]; rows padded by 16 so that the four rows a
-  // wave reads at once fall on different banks
-  __shared__ double As[2][2][2][PD][TM + 16];
-  __shared__ double Bs[2][3][2][PD][16];  // [buf][a, b, c][sum, difference][half node][re 0..7 | im 0..7]
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int cl = lane & 15;
-  double4_t acc[2][5];  // [parity][Pa, Q_A a, Pb, Q_A b, Pc]
-#pragma unroll
-  for (int s = 0; s < 2; ++s)
-#pragma unroll
-    for (int p = 0; p < 5; ++p) acc[s][p] = double4_t{0.0, 0.0, 0.0, 0.0};
-
-  // B staging: threads 0..191 each load one (field, half node, column) at both mirror nodes
-  const int bf = tid >> 6, bkr = (tid >> 3) & 7, bcc = tid & 7;
-  bool bact;
-  const int bkc = colblk_kk(a.cb, c0 + bcc, a.kmax, nz, bact);
-  const int bkk = (tid < 192 && bact) ? bkc : -1;
-  const C2* __restrict__ Xb = (tid < 192) ? a.in[bf] + (int64_t)m * nr * nz : nullptr;
-  // the wave's 16 pairs may all lie past the column (the second row tile of a short order): it
-  // then skips its MFMAs and only helps to stage the operands
-  const bool wrows = 2 * (row0 + wave * 16) < rows;
-  // operands of the next two stages in registers (raw loads; sums and differences are formed
-  // when they are written to LDS, so the loads stay in flight across the MFMAs)
-  struct Stage {
-    double p[4], q[4];
-    C2 x, y;  // raw (float2 on reduced-precision plans): converted at the LDS store, so the loads
-              // stay in flight across the MFMAs
-  };
-  Stage ra, rn;
-  auto load = [&](int i0, Stage& d) {
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int e = tid + 256 * t;
-      const int par = e >> 9, kr = (e >> 6) & 7, rr = e & 63;
-      const int i = i0 + kr, j = 2 * (row0 + rr) + par;
-      const bool ok = i < half && j < rows;
-      const int64_t idx = (int64_t)i * rows + j;
-      d.p[t] = ok ? P[idx] : 0.0;
-      d.q[t] = ok ? Q[idx] : 0.0;
-    }
-    const int i = i0 + bkr;
-    const bool ok = bkk >= 0 && i < half;
-    d.x = ok ? Xb[(int64_t)i * nz + bkk] : czero<C2>();
-    d.y = ok ? Xb[(int64_t)(nr - 1 - i) * nz + bkk] : czero<C2>();
-  };
-  auto store = [&](int buf, const Stage& d) {
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int e = tid + 256 * t;
-      const int par = e >> 9, kr = (e >> 6) & 7, rr = e & 63;
-      As[buf][0][par][kr][rr] = d.p[t];
-      As[buf][1][par][kr][rr] = d.q[t] + 2.0 * d.p[t];  // w Q_A = w Q + 2 w Pbar
-    }
-    if (tid < 192) {
-      const double2 x = to_d2(d.x), y = to_d2(d.y);
-      Bs[buf][bf][0][bkr][bcc] = x.x + y.x;
-      Bs[buf][bf][0][bkr][8 + bcc] = x.y + y.y;
-      Bs[buf][bf][1][bkr][bcc] = x.x - y.x;
-      Bs[buf][bf][1][bkr][8 + bcc] = x.y - y.y;
-    }
-  };
-
-  const int nk = (half + PD - 1) / PD;
-  load(0, ra);
-  store(0, ra);
-  if (nk > 1) load(PD, ra);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 2 < nk) load((kt + 2) * PD, rn);
-    if (wrows) {
-#pragma unroll
-      for (int ks = 0; ks < PD; ks += 4) {
-        const int kr = ks + (lane >> 4);
-#pragma unroll
-        for (int par = 0; par < 2; ++par) {
-          const int sp = par, sq = 1 - par;  // Pbar: even rows use sums; Q_A: even rows use differences
-          const double aP = As[buf][0][par][kr][wave * 16 + cl];
-          const double aQ = As[buf][1][par][kr][wave * 16 + cl];
-          double4_t(&c)[5] = acc[par];
-          c[0] = MFMA(aP, Bs[buf][0][sp][kr][cl], c[0]);  // Pa
-          c[1] = MFMA(aQ, Bs[buf][0][sq][kr][cl], c[1]);  // Q_A a
-          c[2] = MFMA(aP, Bs[buf][1][sp][kr][cl], c[2]);  // Pb
-          c[3] = MFMA(aQ, Bs[buf][1][sq][kr][cl], c[3]);  // Q_A b
-          c[4] = MFMA(aP, Bs[buf][2][sp][kr][cl], c[4]);  // Pc
-        }
-      }
-    }
-    if (kt + 1 < nk) store(buf ^ 1, ra);
-    ra = rn;
-    __syncthreads();
-  }
-  const bool hi = cl >= 8;
+  const int cl = lane & 15, kq = lane >> 4;
+  const int j0 = min(2 * (pr0 + cl), rows - 1), j1 = min(2 * (pr0 + cl) + 1, rows - 1);
   bool cact;
   const int kc = colblk_kk(a.cb, c0 + (cl & 7), a.kmax, nz, cact);
   const int kk = cact ? kc : 0;
+  const int part = cl >> 3;
+  const S* __restrict__ X[3];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) X[f] = reinterpret_cast<const S*>(a.in[f] + (int64_t)m * nr * nz) + 2 * kk + part;
+  double4_t acc[2][5];
+#pragma unroll
+  for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+    for (int p = 0; p < 5; ++p) acc[s2][p] = double4_t{0.0, 0.0, 0.0, 0.0};
+  struct Step {
+    R p[2], q[2];
+    S x[3], y[3];
+  };
+  Step st[D];
+  auto load = [&](int ks, Step& d) {
+    const int i = min(4 * ks + kq, half - 1);
+    d.p[0] = P[(int64_t)i * rows + j0];
+    d.p[1] = P[(int64_t)i * rows + j1];
+    d.q[0] = Q[(int64_t)i * rows + j0];
+    d.q[1] = Q[(int64_t)i * rows + j1];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      d.x[f] = X[f][(int64_t)i * 2 * nz];
+      d.y[f] = X[f][(int64_t)(nr - 1 - i) * 2 * nz];
+    }
+  };
+  auto compute = [&](int ks, const Step& d) {
+    const bool iv = 4 * ks + kq < half;
+    double sm[3], df[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      const double x = iv ? (double)d.x[f] : 0.0, y = iv ? (double)d.y[f] : 0.0;
+      sm[f] = x + y;
+      df[f] = x - y;
+    }
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+      const double aP = d.p[par], aQ = d.q[par] + 2.0 * d.p[par];  // w Q_A = w Q + 2 w Pbar
+      const double* bp = par ? df : sm;  // Pbar: even rows use sums
+      const double* bq = par ? sm : df;  // Q_A: even rows use differences
+      double4_t(&c)[5] = acc[par];
+      c[0] = MFMA(aP, bp[0], c[0]);
+      c[1] = MFMA(aQ, bq[0], c[1]);
+      c[2] = MFMA(aP, bp[1], c[2]);
+      c[3] = MFMA(aQ, bq[1], c[3]);
+      c[4] = MFMA(aP, bp[2], c[4]);
+    }
+  };
+  const int nks = (half + 3) / 4;
+#pragma unroll
+  for (int d = 0; d < D; ++d) load(d, st[d]);
+  for (int k0 = 0; k0 < nks; k0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      if (k0 + d < nks) compute(k0 + d, st[d]);
+      load(k0 + d + D, st[d]);
+    }
+  }
+  const bool hi = cl >= 8;
   const double kap = a.kap0 * kval(kk, nz);
   const double fm = (double)m;
   const int64_t tb = a.off[m];
   const int par = hi ? 1 : 0;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int jj = row0 + wave * 16 + (lane >> 4) + 4 * v;
+    const int jj = pr0 + (lane >> 4) + 4 * v;
     double2 val[5];
 #pragma unroll
     for (int p = 0; p < 5; ++p) {
-      // partner exchange: the low lane gathers the even-degree value, the high lane the odd one
       const double e = acc[0][p][v], o = acc[1][p][v];
-      const double send = hi ? e : o;            // what the partner needs
+      const double send = hi ? e : o;
       const double recv = __shfl_xor(send, 8);
-      const double mine = hi ? o : e;            // own part (re for low, im for high) of own parity
+      const double mine = hi ? o : e;
       val[p] = hi ? make_double2(recv, mine) : make_double2(mine, recv);
     }
     const int r = 2 * jj + par;
@@ -659,7 +633,7 @@ static void proj_fold_go(const mlg_plan_s* p, double* const* in3, double* const*
   a.gx = a.cb.nblk;
   a.gy = (kp + TM - 1) / TM;
   a.gz = mmax;
-  proj_fold_kernel<C2><<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
+  proj_fold_kernel<C2, 1><<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
 }
 
 // in3: harmonics of N (float2 on reduced-precision plans); out3: FP64 sources in every case
