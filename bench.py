@@ -39,14 +39,14 @@ U_FRAME = (0.0, 1.0, 0.0)
 # kernel source hashes to the one that was measured (profiles/rhs_tp_256cubed_kernels.md).
 _SUMMARY = "profiles/rhs_tp_256cubed_kernels.md"
 MEASURED_TRAFFIC = {
-    "synth_gemm": {"bytes": 1233099161, "launches": 1, "n": 256,
+    "synth_gemm": {"bytes": 1192190750, "launches": 1, "n": 256,
                    "source": "paper_2609_18026_amd/csrc/gemm_fold.hip",
-                   "sha256": "2939c7e59d7766134d5c8f5edaede3b25a5421c1c73a7c1c9c256c5413980c35",
-                   "profile_avg_ms": 0.5767, "mfma_counter_flops": 23.49e9, "mfma_busy_pct": 57.0},
-    "proj_gemm": {"bytes": 432848665, "launches": 1, "n": 256,
+                   "sha256": "b0e399c5104fd674093a4e87748b55518f97b73a1f2d612cd5164aeacab46c54",
+                   "profile_avg_ms": 0.5198, "mfma_counter_flops": 23.02e9, "mfma_busy_pct": 62.1},
+    "proj_gemm": {"bytes": 438487816, "launches": 1, "n": 256,
                   "source": "paper_2609_18026_amd/csrc/gemm_fold.hip",
-                  "sha256": "2939c7e59d7766134d5c8f5edaede3b25a5421c1c73a7c1c9c256c5413980c35",
-                  "profile_avg_ms": 0.2808, "mfma_counter_flops": 8.82e9, "mfma_busy_pct": 42.4},
+                  "sha256": "b0e399c5104fd674093a4e87748b55518f97b73a1f2d612cd5164aeacab46c54",
+                  "profile_avg_ms": 0.2453, "mfma_counter_flops": 8.82e9, "mfma_busy_pct": 49.8},
     "phi_fft": {"bytes": 1208374834, "launches": 1, "n": 256,
                 "source": "paper_2609_18026_amd/csrc/fft256.hip",
                 "sha256": "74322a2edc0650c5b2fe33aab5345d8752c9754b60a4a8e17dbe069440a06476",
