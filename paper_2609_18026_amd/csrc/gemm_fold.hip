@@ -474,9 +474,11 @@ __global__ __launch_bounds__(256, 3) void scal_fwd_fold_kernel(ScalarFoldArgs<R>
   for (int q = 0; q < 2; ++q)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[q][c] = Mma<R>::zero();
-  // the wave's 16 pairs may all lie past the column (the second row tile of a short order):
-  // it then skips its MFMAs and only helps to stage the operands
-  const bool wrows = 2 * (row0 + wave * 16) < K;
+  // wavefront w takes the block's columns 16 w .. 16 w + 15 for all its pairs, in 4 groups of 16;
+  // groups wholly past the column (the second row tile of a short order) are skipped by every
+  // wavefront alike, so the SIMDs stay evenly loaded (with 16 pairs per wavefront, the one that
+  // held the first pairs worked on every tile and the others idled on short orders)
+  const int ng = min(4, (KP - row0 + 15) / 16);
   constexpr int NA = SC_P / 2, NX = SC_P / 4;  // table and field loads per thread and stage
   struct Stage {
     R a[NA], x[NX], y[NX];
@@ -520,16 +522,16 @@ __global__ __launch_bounds__(256, 3) void scal_fwd_fold_kernel(ScalarFoldArgs<R>
     }
   };
   auto compute = [&](int buf) {
-    if (!wrows) return;
 #pragma unroll
     for (int ks = 0; ks < SC_P; ks += 4) {
       const int kr = ks + (lane >> 4);
 #pragma unroll
       for (int par = 0; par < 2; ++par) {
-        const R av = As[buf][par][kr][wave * 16 + cl];
-        const int sd = par;  // even degrees contract with sums, odd with differences
+        // even degrees contract with sums, odd with differences
+        const R bv = Bs[buf][par][kr][wave * 16 + cl];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[par][c] = MFMA(av, Bs[buf][sd][kr][c * 16 + cl], acc[par][c]);
+        for (int g = 0; g < 4; ++g)
+          if (g < ng) acc[par][g] = MFMA(As[buf][par][kr][g * 16 + cl], bv, acc[par][g]);
       }
     }
   };
@@ -554,17 +556,17 @@ __global__ __launch_bounds__(256, 3) void scal_fwd_fold_kernel(ScalarFoldArgs<R>
     __syncthreads();
   }
   if (kt < nk) compute(0);
+  const int col = col0 + wave * 16 + cl;
+  if (col >= ncol) return;
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int col = col0 + c * 16 + cl;
-    if (col >= ncol) continue;
+  for (int g = 0; g < 4; ++g) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int pr = row0 + wave * 16 + Mma<R>::row(lane, v);
+      const int pr = row0 + g * 16 + Mma<R>::row(lane, v);
 #pragma unroll
       for (int par = 0; par < 2; ++par) {
         const int j = 2 * pr + par;
-        if (j < K) C[(int64_t)j * ncol + col] = acc[par][c][v];
+        if (j < K) C[(int64_t)j * ncol + col] = acc[par][g][v];
       }
     }
   }
