@@ -29,7 +29,8 @@ import numpy as np
 
 from .basis import laplacian_matrix
 from .grid import Grid
-from .rhs import VecTables, cross_with_background, projection_sources, solve_projection, synthesize, dealias_mask
+from .rhs import (VecTables, apply_mask, cross_with_background, dealias_mask, projection_sources,
+                  solve_projection, synthesize)
 
 
 def laplacian_image(nrc: int, ell: float) -> np.ndarray:
@@ -58,7 +59,10 @@ def synthesize_log(psi, chi, g: Grid, vt: VecTables, c_psi: float, c_chi: float)
 def rhs_tp_log(psi, chi, g: Grid, vt: VecTables, U=(0.0, 0.0, 0.0), dealias: bool = True, c_psi: float = 0.0,
                c_chi: float = 0.0, taps: dict | None = None):
     """rhs_tp of the regular parts when the potentials carry proxy amplitudes (the projection keeps
-    the decay gauge: the amplitudes do not change)."""
+    the decay gauge: the amplitudes do not change).  Dealiasing masks the regular parts on the way
+    in, as in rhs_tp; the proxies are axisymmetric and axially uniform (m = 0, k = 0)."""
+    if dealias:
+        psi, chi = apply_mask(psi, g), apply_mask(chi, g)
     u, w = synthesize_log(psi, chi, g, vt, c_psi, c_chi)
     Nr_, Np_, Nz_ = cross_with_background(u, w, U, g)
     C, K, Z = projection_sources(Nr_, Np_, Nz_, g, vt)

@@ -3,13 +3,17 @@
 Test infrastructure only (see the package header).
 
 Scalar (Sec. 3.3; Sec. 5.2, Eq. kpp):
-    R(shat) = Mask( F( g( B(shat) ) ) ),  g(u) = u^2  or  g(u) = gamma u (1 - u),
+    R(shat) = Mask( F( g( B( Mask(shat) ) ) ) ),  g(u) = u^2  or  g(u) = gamma u (1 - u),
 with the conventional two-thirds mask in phi and z (keep m <= floor((N_phi-1)/3),
-|k| <= floor((N_z-1)/3)); no radial margin (N_r^c = N_r in the paper's runs).
+|k| <= floor((N_z-1)/3)); no radial margin (N_r^c = N_r in the paper's runs).  The mask is
+the dealiasing margin between the periodic chops and the collocation counts (Sec. 3.3): the
+fields that enter the product hold no mode in the margin, and the product keeps none there, so
+it applies on the way in as well as on the way out.
 
 Vector (Sec. 3.2 Eq. tp, Sec. 5.3 Eq. tp-evolution):
     (psi_N, chi_N) = Mask( P[ (U + u) x omega ] ),  u = curl(psi z) + curl curl(chi z),
-    omega = curl u, U a uniform Cartesian background (the moving frame of Sec. 5.3).
+    omega = curl u of the masked potentials (Mask(psi), Mask(chi)), U a uniform Cartesian
+    background (the moving frame of Sec. 5.3).
 The velocity and vorticity harmonics at the nodes are the plain curl formulas
 in cylindrical coordinates; r d/dr of a harmonic is Tbar = (1-x^2) dPbar/dx, and
 the horizontal Laplacian of Pbar_n^m(x(r)) is -n(n+1) (1-x)^2/ell^2 Pbar_n^m, which
@@ -60,8 +64,9 @@ def apply_mask(S: np.ndarray, g: Grid) -> np.ndarray:
 
 def rhs_scalar(S: np.ndarray, g: Grid, t: Tables, kind: str, gamma: float = 0.25,
                dealias: bool = True) -> np.ndarray:
-    """R = Mask(F(g(B(S)))) with g = u^2 ('u2') or gamma u (1 - u) ('kpp')."""
-    u = backward(S, g, t)
+    """R = Mask(F(g(B(Mask(S))))) with g = u^2 ('u2') or gamma u (1 - u) ('kpp'); without
+    dealiasing, R = F(g(B(S)))."""
+    u = backward(apply_mask(S, g) if dealias else S, g, t)
     if kind == "u2":
         v = u * u
     elif kind == "kpp":
@@ -279,11 +284,14 @@ def solve_projection(C, K, Z, g: Grid, dealias: bool = True):
 
 def rhs_tp(psi: np.ndarray, chi: np.ndarray, g: Grid, vt: VecTables, U=(0.0, 0.0, 0.0),
            dealias: bool = True, taps: dict | None = None):
-    """(psi_N, chi_N) = Mask(P[(U+u) x omega]) for the toroidal-poloidal pair (psi, chi).
+    """(psi_N, chi_N) = Mask(P[(U+u) x omega]) for the toroidal-poloidal pair (psi, chi), u and
+    omega those of (Mask(psi), Mask(chi)) when dealiasing.
 
     ``taps``, if given, receives the intermediate quantities the parity tests
     compare: nodal u, omega, N and the sources C, K, Zhat.
     """
+    if dealias:
+        psi, chi = apply_mask(psi, g), apply_mask(chi, g)
     u, w = synthesize(psi, chi, g, vt)
     Nr_, Np_, Nz_ = cross_with_background(u, w, U, g)
     C, K, Z = projection_sources(Nr_, Np_, Nz_, g, vt)

@@ -318,3 +318,42 @@ def test_abcn_second_order_on_heat_mode():
     errs = [_heat_mode_error(96, dt) for dt in (0.1, 0.05, 0.025)]
     p = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all((p > 1.7) & (p < 2.2)), p
+
+
+# ------------------------------------------------------------------ two-thirds rule
+
+def _embed(S, gc, gf):
+    """Spectrum S of grid gc placed on the finer periodic grid gf (same radial grid and chop)."""
+    Sf = np.zeros((gf.M, gc.nrc, gf.nz), complex)
+    for kk, k in enumerate(gc.kvals()):
+        Sf[:gc.M, :, k % gf.nz] = S[:, :, kk]
+    return Sf
+
+
+def _kept_pairs(gc):
+    keep = np.arange(gc.M)[:, None] <= gc.dealias_m()
+    keep = keep & ((np.abs(gc.kvals()) <= gc.dealias_k()) & gc.kmask())[None, :]
+    return [(m, kk, k) for m in range(gc.M) for kk, k in enumerate(gc.kvals()) if keep[m, kk]]
+
+
+@pytest.mark.parametrize("kind", ["u2", "kpp"])
+def test_scalar_rhs_two_thirds_rule_is_alias_free(kind):
+    # Sec. 3.3: the periodic directions are dealiased by the two-thirds margin.  The input carries
+    # modes in the margin as well; the masked RHS on (N_phi, N_z) must equal the RHS of the masked
+    # input on (2 N_phi, 2 N_z), where the product of the kept modes does not alias in phi or z,
+    # on every kept (m, k).  A mask applied only to the output lets the margin modes alias into
+    # the kept ones and fails this.
+    gc = Grid(10, 12, 6, 0.9, lz=3.0)
+    gf = Grid(10, 24, 12, 0.9, lz=3.0)
+    S = synth.geometric_spectrum(gc.M, gc.nrc, gc.nz, gc.nzc, seed=41, a=0.8, b=0.9, c=0.9)
+    from oracle.rhs import apply_mask
+    assert np.abs(S - apply_mask(S, gc)).max() > 0.05  # the margin is populated
+    Rc = rhs_scalar(S, gc, Tables(gc), kind, 0.3)
+    Rf = rhs_scalar(_embed(apply_mask(S, gc), gc, gf), gf, Tables(gf), kind, 0.3)
+    big = np.abs(Rc).max()
+    for m, kk, k in _kept_pairs(gc):
+        assert np.abs(Rc[m, :, kk] - Rf[m, :, k % gf.nz]).max() < 1e-13 * big, (m, k)
+    # nothing leaves the mask, and margin-only input has no product
+    assert np.abs(Rc - apply_mask(Rc, gc)).max() == 0.0
+    margin = S - apply_mask(S, gc)
+    assert np.abs(rhs_scalar(margin, gc, Tables(gc), kind, 0.3)).max() == 0.0

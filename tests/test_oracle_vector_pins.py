@@ -203,3 +203,36 @@ def test_sampled_evaluations_agree_with_the_full_oracle():
     for (m, kk), (c, k, z) in pc.items():
         for got, want in ((c, C), (k, K), (z, Z)):
             np.testing.assert_allclose(got, want[m, :, kk], rtol=0, atol=1e-12 * np.abs(want).max())
+
+
+def test_rhs_tp_two_thirds_rule_is_alias_free():
+    # as the scalar pin: the masked (psi_N, chi_N) on (N_phi, N_z) equal those of the masked
+    # potentials on (2 N_phi, 2 N_z) on every kept (m, k), though the input populates the margin
+    from oracle.rhs import apply_mask
+    gc = Grid(10, 12, 6, 1.1, lz=4.0)
+    gf = Grid(10, 24, 12, 1.1, lz=4.0)
+    psi = synth.geometric_spectrum(gc.M, gc.nrc, gc.nz, gc.nzc, seed=43, a=0.7, b=0.9, c=0.9)
+    chi = synth.geometric_spectrum(gc.M, gc.nrc, gc.nz, gc.nzc, seed=44, a=0.7, b=0.9, c=0.9)
+    U = (0.2, -0.1, 0.3)
+    ac, bc = rhs_tp(psi, chi, gc, VecTables(gc), U=U)
+
+    def embed(S):
+        Sf = np.zeros((gf.M, gc.nrc, gf.nz), complex)
+        for kk, k in enumerate(gc.kvals()):
+            Sf[:gc.M, :, k % gf.nz] = S[:, :, kk]
+        return Sf
+
+    af, bf = rhs_tp(embed(apply_mask(psi, gc)), embed(apply_mask(chi, gc)), gf, VecTables(gf), U=U)
+    kept = (np.arange(gc.M)[:, None] <= gc.dealias_m()) & \
+        ((np.abs(gc.kvals()) <= gc.dealias_k()) & gc.kmask())[None, :]
+    big = max(np.abs(ac).max(), np.abs(bc).max())
+    for m in range(gc.M):
+        for kk, k in enumerate(gc.kvals()):
+            if kept[m, kk]:
+                assert np.abs(ac[m, :, kk] - af[m, :, k % gf.nz]).max() < 1e-12 * big, (m, k)
+                assert np.abs(bc[m, :, kk] - bf[m, :, k % gf.nz]).max() < 1e-12 * big, (m, k)
+            else:
+                assert np.abs(ac[m, :, kk]).max() == 0.0 and np.abs(bc[m, :, kk]).max() == 0.0
+    # margin-only potentials produce nothing (the background alone carries no gradient-free part)
+    a0, b0 = rhs_tp(psi - apply_mask(psi, gc), chi - apply_mask(chi, gc), gc, VecTables(gc), U=U)
+    assert np.abs(a0).max() == 0.0 and np.abs(b0).max() == 0.0
