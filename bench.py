@@ -109,19 +109,24 @@ def radial_folded(nr):
 
 def kernel_work(nr, nphi, nz, M, nrc):
     """Algorithmic flops / HBM bytes per RHS step for each kernel family (FP64); with parity
-    folding the radial products count half the flops and read half of each table."""
-    tau = sum(max(nrc - m, 0) for m in range(M))
+    folding the radial products count half the flops and read half of each table.  Under the
+    two-thirds mask (the RHS workload) the potentials enter through it: the synthesis covers the
+    kept orders and axial slots, the inverse z transforms the kept orders (reading the kept slots,
+    writing every z), and the phi stage reads and writes the kept orders."""
     mmax, nkact = active_columns(nphi, nz, M, nrc)
+    mk = min(M, (nphi - 1) // 3 + 1)             # orders kept by the mask
+    tau_k = sum(max(nrc - m, 0) for m in range(mk))
     tau_a = sum(max(nrc - m, 0) for m in range(mmax))
-    mixed = M * nr * nz * 16                     # one harmonic field, complex
+    tau = sum(max(nrc - m, 0) for m in range(M))
+    kept = mk * nr * nz * 16                     # one harmonic field on the kept orders, complex
     f = 0.5 if radial_folded(nr) else 1.0
     w = {}
-    w["synth_gemm"] = dict(flops=f * 7 * 2.0 * nr * tau * 2 * nz,
-                           bytes=f * 2 * tau * nr * 8 + 2 * tau * nz * 16 + 6 * mixed)
+    w["synth_gemm"] = dict(flops=f * 7 * 2.0 * nr * tau_k * 2 * nkact,
+                           bytes=f * 2 * tau_k * nr * 8 + 2 * tau_k * nkact * 16 + 6 * mk * nr * nkact * 16)
     w["proj_gemm"] = dict(flops=f * 5 * 2.0 * nr * tau_a * 2 * nkact,
                           bytes=f * 2 * tau_a * nr * 8 + 3 * mmax * nr * nkact * 16 + 3 * tau_a * nkact * 16)
-    w["phi_fft"] = dict(flops=None, bytes=9 * mixed)
-    w["z_fft"] = dict(flops=None, bytes=6 * 2 * mixed + 3 * 2 * mmax * nr * nz * 16)
+    w["phi_fft"] = dict(flops=None, bytes=9 * kept)
+    w["z_fft"] = dict(flops=None, bytes=6 * mk * nr * (nkact + nz) * 16 + 3 * 2 * mmax * nr * nz * 16)
     w["projection"] = dict(flops=None, bytes=3 * tau_a * nkact * 16 + 2 * tau * nz * 16)
     return w
 
@@ -308,19 +313,24 @@ def bench_batched(torch, args, stream, e0, e1, count=64, seed=3):
     return res
 
 
-def reduced_work(nr, nphi, nz, M, nrc):
+def reduced_work(nr, nphi, nz, M, nrc, skip=True):
     """Algorithmic HBM bytes per RHS step of each kernel family on a reduced-precision plan: float
     data and intermediates (8-byte complex), 4-byte synthesis tables (FP32, or bfloat16 hi + lo),
-    FP64 projection tables and sources."""
+    FP64 projection tables and sources.  skip: the synthesis covers only the orders and axial
+    slots the mask keeps (FP32 plans); the split synthesis runs over all of them (writing zeros)."""
     tau = sum(max(nrc - m, 0) for m in range(M))
     mmax, nkact = active_columns(nphi, nz, M, nrc)
+    mk = min(M, (nphi - 1) // 3 + 1)
+    tau_k = sum(max(nrc - m, 0) for m in range(mk))
     tau_a = sum(max(nrc - m, 0) for m in range(mmax))
-    mixed = M * nr * nz * 8
+    kept = mk * nr * nz * 8
     f = 0.5 if nr % 2 == 0 else 1.0
-    return {"synth_gemm": f * 2 * tau * nr * 4 + 2 * tau * nz * 8 + 6 * mixed,
+    synth = (f * 2 * tau_k * nr * 4 + 2 * tau_k * nkact * 8 + 6 * mk * nr * nkact * 8) if skip else \
+        (f * 2 * tau * nr * 4 + 2 * tau * nz * 8 + 6 * M * nr * nz * 8)
+    return {"synth_gemm": synth,
             "proj_gemm": f * 2 * tau_a * nr * 8 + 3 * mmax * nr * nkact * 8 + 3 * tau_a * nkact * 16,
-            "phi_fft": 9 * mixed,
-            "z_fft": 6 * 2 * mixed + 3 * 2 * mmax * nr * nz * 8,
+            "phi_fft": 9 * kept,
+            "z_fft": 6 * mk * nr * (nkact + nz) * 8 + 3 * 2 * mmax * nr * nz * 8,
             "projection": 3 * tau_a * nkact * 16 + 2 * tau * nz * 8}
 
 
@@ -358,7 +368,7 @@ def bench_reduced(torch, prec, plan, psi, chi, fp64_kernels, args, stream, e0, e
     torch.cuda.synchronize()
     kern = {f: mlg_timing_read(rp.handle, f) for f in families}
     mlg_timing_enable(rp.handle, False)
-    bytes_r = reduced_work(n, n, n, plan.layout.M, plan.layout.nrc)
+    bytes_r = reduced_work(n, n, n, plan.layout.M, plan.layout.nrc, skip=(prec == MLG_FP32))
     bytes_64 = {f: w["bytes"] for f, w in kernel_work(n, n, n, plan.layout.M, plan.layout.nrc).items()}
     per_kernel = {}
     for f in families[:5]:

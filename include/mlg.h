@@ -85,7 +85,9 @@ enum { MLG_RHS_U2 = 0, MLG_RHS_KPP = 1 };
  * N_r^c = N_r, N_phi^c = N_phi/2 (orders m < N_phi/2), N_z^c = max(1, N_z/2).
  * Bounds enforced: 2 <= N_r, N_r^c <= N_r, N_phi^c <= N_phi/2 + 1, N_z^c <= N_z/2 + 1,
  * ell > 0, L_z > 0, all finite.  'dealias' = 1 applies the two-thirds mask (keep
- * m <= floor((N_phi-1)/3) and |k| <= floor((N_z-1)/3)) to RHS outputs (Sec. 3.3). */
+ * m <= floor((N_phi-1)/3) and |k| <= floor((N_z-1)/3)) to the fields entering the RHS products
+ * and to the RHS outputs (Sec. 3.3: the dealiasing margin between chop and collocation count,
+ * in which the fields of a product hold no mode): input modes outside the mask are read as zero. */
 typedef struct {
   int32_t nr, nphi, nz;
   int32_t nrc, nphic, nzc;
@@ -137,16 +139,18 @@ mlg_status mlg_forward(mlg_plan plan, const void* phys, void* spec, void* ws, vo
 /* Backward transform, Eq. expansion: spec -> phys.  spec is not modified. */
 mlg_status mlg_backward(mlg_plan plan, const void* spec, void* phys, void* ws, void* stream);
 
-/* Pseudospectral scalar term (Sec. 3.3; Eq. kpp): out = Mask(F(g(B(u)))) with
+/* Pseudospectral scalar term (Sec. 3.3; Eq. kpp): out = Mask(F(g(B(Mask(u))))) with
  * g(u) = u^2 (kind MLG_RHS_U2) or gamma u (1 - u) (kind MLG_RHS_KPP); the mask is applied
- * when the plan's grid has dealias = 1.  spec_u and spec_out may not alias. */
+ * (on the way in and on the way out) when the plan's grid has dealias = 1.  spec_u and spec_out
+ * may not alias. */
 mlg_status mlg_rhs_scalar(mlg_plan plan, int kind, double gamma, const void* spec_u,
                           void* spec_out, void* ws, void* stream);
 
 /* Toroidal-poloidal nonlinear term (Sec. 3.2, Sec. 5.3, Eq. tp-evolution):
  * (psi_n, chi_n) = Mask(P[(U + u) x omega]) with u = curl(psi z) + curl curl(chi z),
  * omega = curl u and U = (U[0], U[1], U[2]) a uniform Cartesian background (host array;
- * NULL = 0).  P takes the gradient-free part through the axial curl and curl-curl
+ * NULL = 0); with dealias = 1, u and omega are those of the masked potentials (Mask(psi),
+ * Mask(chi)): the orders and axial modes outside the mask are not read.  P takes the gradient-free part through the axial curl and curl-curl
  * (Eq. tp-poisson); the m = 0 blocks use the decay gauge psi, chi -> 0 as r -> infinity.
  * psi and chi are the regular parts of the potentials: a net circulation or axial volume flux
  * is carried by the logarithmic proxy amplitudes of mlg_set_log_proxy (Eq. logproxy), whose

@@ -226,7 +226,7 @@ mlg_status mlg_forward(mlg_plan p, const void* phys, void* spec, void* ws, void*
   mlg_status st;
   if ((st = launch_phi_forward(p, static_cast<const double*>(phys), w.X[0], s))) return st;
   if ((st = scalar_radial(p, -1, w.X[0], static_cast<double*>(spec), s))) return st;
-  return launch_zfft(p, static_cast<double*>(spec), static_cast<double*>(spec), p->tau, -1, nullptr, 0, 0, s);
+  return launch_zfft(p, static_cast<double*>(spec), static_cast<double*>(spec), p->tau, -1, nullptr, 0, -1, s);
 }
 
 mlg_status mlg_backward(mlg_plan p, const void* spec, void* phys, void* ws, void* stream) {
@@ -236,7 +236,7 @@ mlg_status mlg_backward(mlg_plan p, const void* spec, void* phys, void* ws, void
   hipStream_t s = static_cast<hipStream_t>(stream);
   Ws w = partition(p, ws);
   mlg_status st;
-  if ((st = launch_zfft(p, static_cast<const double*>(spec), w.T[0], p->tau, +1, nullptr, 0, 0, s))) return st;
+  if ((st = launch_zfft(p, static_cast<const double*>(spec), w.T[0], p->tau, +1, nullptr, 0, -1, s))) return st;
   if ((st = scalar_radial(p, +1, w.T[0], w.X[0], s))) return st;
   return launch_phi_backward(p, w.X[0], static_cast<double*>(phys), s);
 }
@@ -252,16 +252,29 @@ mlg_status mlg_rhs_scalar(mlg_plan p, int kind, double gamma, const void* spec_u
   hipStream_t s = static_cast<hipStream_t>(stream);
   Ws w = partition(p, ws);
   mlg_status st;
-  if ((st = launch_zfft(p, static_cast<const double*>(spec_u), w.T[0], p->tau, +1, nullptr, 0, 0, s))) return st;
+  // the two-thirds mask applies to the field entering the product (read as zero outside it by the
+  // inverse z transform) and to the product
+  const bool mask = p->g.dealias != 0;
+  const int32_t* row_m = mask ? p->d_row_m : nullptr;
+  const int mask_k = mask ? p->dealias_k : -1;
+  if ((st = launch_zfft(p, static_cast<const double*>(spec_u), w.T[0], p->tau, +1, row_m, p->dealias_m, mask_k, s)))
+    return st;
   if ((st = scalar_radial(p, +1, w.T[0], w.X[0], s))) return st;
   if ((st = launch_phi_scalar_rhs(p, kind, gamma, w.X[0], s))) return st;
   if ((st = scalar_radial(p, -1, w.X[0], static_cast<double*>(spec_out), s))) return st;
-  const bool mask = p->g.dealias != 0;
-  return launch_zfft(p, static_cast<double*>(spec_out), static_cast<double*>(spec_out), p->tau, -1,
-                     mask ? p->d_row_m : nullptr, p->dealias_m, p->dealias_k, s);
+  return launch_zfft(p, static_cast<double*>(spec_out), static_cast<double*>(spec_out), p->tau, -1, row_m,
+                     p->dealias_m, mask_k, s);
 }
 
 }  // extern "C"
+
+// Whether mlg_rhs_tp skips the orders and axial blocks the two-thirds mask removes: the folded
+// FP64 / FP32 synthesis followed by the 256-point z and phi stages (the kernels that know to leave
+// them unread); otherwise the synthesis writes them as zeros.
+static bool rhs_skips_masked(const mlg_plan_s* p) {
+  return p->g.dealias != 0 && p->use_fold && p->nr % 2 == 0 && p->prec != MLG_SPLIT_BF16 && p->nz == 256 &&
+         p->nphi == 256 && p->use_fast_fft && (int64_t)p->nr * p->nz <= (int64_t(1) << 23);
+}
 
 // The kernel sequence of mlg_rhs_tp on the workspace 'ws' (caller-provided, or the per-GPU array of
 // mlg_rhs_tp_noalloc).
@@ -283,17 +296,29 @@ static mlg_status rhs_tp_run(mlg_plan p, const double* U, const void* psi, const
   hipStream_t s = static_cast<hipStream_t>(stream);
   Ws w = partition(p, ws);
   mlg_status st;
-  // 1. radial synthesis: the six velocity / vorticity harmonics (k spectral), fused
+  // 1. radial synthesis: the six velocity / vorticity harmonics (k spectral), fused.  Under the
+  // two-thirds mask the potentials enter through it (Sec. 3.3: the fields of a product hold no mode
+  // in the dealiasing margin); with the 256-point z and phi stages the masked orders and column
+  // blocks are not synthesized at all, and the stages after it do not read them
+  const bool dealias = p->g.dealias != 0;
+  SynthMask smask;
+  if (dealias) {
+    int mm, km;
+    active_columns(p, &mm, &km);
+    smask.mkeep = p->dealias_m;
+    smask.kmax = km;
+    smask.skip = rhs_skips_masked(p);
+  }
   if (p->prec == MLG_SPLIT_BF16)
-    st = launch_split_synth(p, static_cast<const double*>(psi), static_cast<const double*>(chi), w.X, s);
+    st = launch_split_synth(p, static_cast<const double*>(psi), static_cast<const double*>(chi), w.X, s, smask);
   else
-    st = launch_synth_gemm(p, static_cast<const double*>(psi), static_cast<const double*>(chi), w.X, s);
+    st = launch_synth_gemm(p, static_cast<const double*>(psi), static_cast<const double*>(chi), w.X, s, smask);
   if (st) return st;
   // the logarithmic proxy parts of the potentials, when they carry amplitudes (Eq. logproxy)
   if ((st = launch_proxy_fields(p, w.X, s))) return st;
-  // 2. inverse z transforms of the six fields
-  const int64_t mrows = (int64_t)p->M * p->nr;
-  if ((st = launch_zfft_fields(p, w.X, w.X, 6, mrows, +1, nullptr, 0, 0, s))) return st;
+  // 2. inverse z transforms of the six fields (under the mask: the kept orders, the kept slots read)
+  const int64_t mrows = (int64_t)(dealias ? std::min(p->M, p->dealias_m + 1) : p->M) * p->nr;
+  if ((st = launch_zfft_fields(p, w.X, w.X, 6, mrows, +1, nullptr, 0, dealias ? smask.kmax : -1, s))) return st;
   // 3. phi stage: nodal u, w -> N = (U + u) x w -> harmonics of N_r/r, N_phi/r, N_z
   double* tp = static_cast<double*>(taps);
   if ((st = launch_phi_vec_rhs(p, Uh, w.X, tp, s))) return st;
@@ -305,7 +330,7 @@ static mlg_status rhs_tp_run(mlg_plan p, const double* U, const void* psi, const
   int mmax, kmax;
   active_columns(p, &mmax, &kmax);
   const int64_t frows = (int64_t)mmax * p->nr;
-  if ((st = launch_zfft_fields(p, w.X, w.X, 3, frows, -1, nullptr, 0, 0, s, fp64_only))) return st;
+  if ((st = launch_zfft_fields(p, w.X, w.X, 3, frows, -1, nullptr, 0, -1, s, fp64_only))) return st;
   // 5. Galerkin projections onto Pbar and Q = T - 2(1+x) Pbar with the C, K', Zhat epilogue
   double* src3[3] = {w.T[0], w.T[1], w.T[2]};
   if ((st = launch_proj_gemm(p, w.X, src3, mmax, kmax, s))) return st;
@@ -552,7 +577,7 @@ mlg_status mlg_synthesize(mlg_plan p, const void* psi, const void* chi, void* uw
   const int64_t mrows = (int64_t)p->M * p->nr;
   const size_t pe = (size_t)p->nz * p->nr * p->nphi;
   for (int i = 0; i < 6; ++i) {
-    if ((st = launch_zfft(p, w.X[i], w.X[i], mrows, +1, nullptr, 0, 0, s))) return st;
+    if ((st = launch_zfft(p, w.X[i], w.X[i], mrows, +1, nullptr, 0, -1, s))) return st;
     if ((st = launch_phi_backward(p, w.X[i], static_cast<double*>(uw) + i * pe, s))) return st;
   }
   return MLG_OK;

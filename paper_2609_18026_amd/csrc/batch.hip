@@ -1,7 +1,7 @@
 // Batched pseudospectral KPP term for many uneven 2D instances.
 //
-// For each instance b (N_z = 1): R_b = Mask(F(gamma u (1 - u))), u = B(u_hat_b) (Sec. 3.3;
-// Sec. 5.2, Eq. kpp).  Three persistent launches (a fixed number of blocks per CU, each block
+// For each instance b (N_z = 1): R_b = Mask(F(gamma u (1 - u))), u = B(Mask(u_hat_b)) (Sec. 3.3;
+// Sec. 5.2, Eq. kpp; the two-thirds mask holds for the field entering the product too).  Three persistent launches (a fixed number of blocks per CU, each block
 // walking its share of the phase's work list) run the phases; the kernel boundaries order them
 // (a grid-wide barrier inside one cooperative launch costs about 50 us on this part, against a few
 // microseconds for a launch boundary):
@@ -208,7 +208,7 @@ struct BatchArgs {
 template <typename T>
 __device__ void phase_backward(const BatchArgs<T>& A, int b, int m, char* smem) {
   const BatchInst& I = A.inst[b];
-  const int K = I.nrc > m ? I.nrc - m : 0;
+  const int K = (I.nrc > m && m <= I.mkeep) ? I.nrc - m : 0;  // a masked order enters as zero
   Cx<T>* mix = A.mix + I.mix_off + (int64_t)m * I.nr;
   if (K == 0) {
     for (int i = threadIdx.x; i < I.nr; i += blockDim.x) mix[i] = cx<T>(0, 0);
@@ -459,7 +459,7 @@ mlg_status build_items(mlg_batch_s* bt, int lines) {
     const BatchInst& I = bt->inst[b];
     for (int m = 0; m < I.M; ++m) {
       const int K = std::max(I.nrc - m, 0);
-      w[0].push_back({(double)std::max(K, 1) * I.nr, (b << 16) | m});
+      w[0].push_back({(m > I.mkeep ? 1.0 : (double)std::max(K, 1) * I.nr), (b << 16) | m});
       w[2].push_back({(m > I.mkeep ? 1.0 : (double)std::max(K, 1) * I.nr), (b << 16) | m});
     }
     for (int q = 0; q < I.nr; q += lines)

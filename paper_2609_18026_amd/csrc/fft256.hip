@@ -175,8 +175,8 @@ __device__ __forceinline__ void fft256w(double2 (&v)[8], double2* W, int s, cons
 // Harmonics of a field pair for the block's lines, held in registers so that their loads are in
 // flight while another pair is transformed.  Entry it covers e = t + VB it: line e % PL, order
 // e / PL.  The per-lane byte offset is 32-bit (the launcher bounds the line count) and the rest of
-// the address is uniform.  GUARD (the last block, or fewer than 128 stored orders) reads orders
-// >= min(M, 128) and lines past the end as zero.
+// the address is uniform.  Orders >= min(M, 128, mkeep + 1) read as zero; GUARD (the last block,
+// or fewer than 128 stored orders) also reads lines past the end as zero.
 template <typename S2>
 struct PairRegs {
   S2 a[PL * 128 / VB], b[PL * 128 / VB];
@@ -187,18 +187,20 @@ __device__ __forceinline__ void load_pair(PairRegs<S2>& r, const Phi256& g, int6
                                           const S2* __restrict__ fb) {
   const int t = threadIdx.x;
   const uint32_t off = (uint32_t)((t >> 3) * g.nlines + (t & 7)) * (uint32_t)sizeof(S2);
-  const int mmax = g.M < 128 ? g.M : 128;
+  // orders read: those stored (up to 128) and, under the two-thirds mask, those it keeps (the
+  // synthesis and the z transforms before this stage leave the others unwritten)
+  const int mmax = min(g.M < 128 ? g.M : 128, g.mkeep + 1);
   const bool line_ok = q0 + (t & 7) < g.nlines;
 #pragma unroll
   for (int it = 0; it < PL * 128 / VB; ++it) {
     const int64_t base = q0 + (int64_t)(VB / PL) * it * g.nlines;
     const char* pa = reinterpret_cast<const char*>(fa + base) + off;
     const char* pb = reinterpret_cast<const char*>(fb + base) + off;
-    if (!GUARD) {
+    if (!GUARD && mmax >= 128) {
       r.a[it] = *reinterpret_cast<const S2*>(pa);
       r.b[it] = *reinterpret_cast<const S2*>(pb);
     } else {
-      const bool ok = line_ok && (t >> 3) + (VB / PL) * it < mmax;
+      const bool ok = (!GUARD || line_ok) && (t >> 3) + (VB / PL) * it < mmax;
       r.a[it] = ok ? *reinterpret_cast<const S2*>(pa) : czero<S2>();
       r.b[it] = ok ? *reinterpret_cast<const S2*>(pb) : czero<S2>();
     }
@@ -229,7 +231,9 @@ __device__ __forceinline__ void store_pair(const PairRegs<S2>& r, double2 (*Z)[W
 }
 
 // Scatters the spectrum X (v[j] = X[s + 32 j]) of z = a + i b of each line to the harmonics of a
-// and b (orders m < M, scaled by 1/256; orders above mkeep written as zero).  Barriers at both ends.
+// and b (orders m <= mkeep and m < M, scaled by 1/256).  The orders above mkeep (the two-thirds
+// mask of the RHS) are not written: the forward z transforms and the projection read only the
+// orders the mask keeps.  Barriers at both ends.
 template <typename S2>
 __device__ __forceinline__ void scatter_pair_w(const double2 (&v)[8], double2 (*Z)[WROW], const Phi256& g,
                                                int64_t q0, int ll, int s, S2* fa, S2* fb) {
@@ -239,12 +243,13 @@ __device__ __forceinline__ void scatter_pair_w(const double2 (&v)[8], double2 (*
   __syncthreads();
   const int t = threadIdx.x;
   const int mmax = g.M < 128 ? g.M : 128;
-  for (int e = t; e < PL * g.M; e += VB) {
+  const int mout = g.M < g.mkeep + 1 ? g.M : g.mkeep + 1;
+  for (int e = t; e < PL * mout; e += VB) {
     const int l2 = e & (PL - 1), m = e >> 3;
     const int64_t q = q0 + l2;
     if (q >= g.nlines) continue;
     double2 A = make_double2(0.0, 0.0), B = A;
-    if (m < mmax && m <= g.mkeep) {
+    if (m < mmax) {
       const double2 zm = Z[l2][zpos(m)];
       const double2 zc = cconj(Z[l2][zpos((256 - m) & 255)]);
       A = cscale(cadd(zm, zc), 0.5 / 256.0);
@@ -509,28 +514,29 @@ __global__ __launch_bounds__(VB) void zfft256w_kernel(const double2* __restrict_
   const int64_t row = (per_field - 1 - blockIdx.x / nf) * PL + ll;
   if (row >= rows) return;  // no block barrier follows
   const S2* __restrict__ x = fs.in[f] + row * 256;
+  const int mrow = row_m ? row_m[row] : 0;
+  // spectral slots kept by the chop and the masks: the backward transform does not read the others
+  // (they may not have been written), the forward one writes them as zero
+  auto keep = [&](int kk) {
+    const int k = kval(kk, 256);
+    return kkept(kk, 256, nzc) && (mask_k < 0 || (k < 0 ? -k : k) <= mask_k) && (!row_m || mrow <= mask_m);
+  };
   double2 v[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int kk = s + 32 * j;
-    const double2 a = ld2(x + kk);
-    v[j] = (INV && !kkept(kk, 256, nzc)) ? make_double2(0.0, 0.0) : a;
+    v[j] = make_double2(0.0, 0.0);
+    if (!INV || keep(kk)) v[j] = ld2(x + kk);
   }
   fft256w<INV>(v, Z[ll], s, tw);
   S2* __restrict__ y = fs.out[f] + row * 256;
-  const int mrow = (!INV && row_m) ? row_m[row] : 0;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int kk = s + 32 * j;
     double2 a = v[j];
     if (!INV) {
       a = cscale(a, 1.0 / 256.0);
-      bool keep = kkept(kk, 256, nzc);
-      if (row_m) {
-        const int k = kval(kk, 256);
-        keep = keep && mrow <= mask_m && (k < 0 ? -k : k) <= mask_k;
-      }
-      if (!keep) a = make_double2(0.0, 0.0);
+      if (!keep(kk)) a = make_double2(0.0, 0.0);
     }
     st2(y + kk, a);
   }
@@ -569,7 +575,7 @@ static void zfft256_go(const mlg_plan_s* p, const double* const* in, double* con
   const int64_t per = (rows + PL - 1) / PL;
   dim3 grid((unsigned)(per * nf));
   if (dir > 0)
-    zfft256w_kernel<true, S2><<<grid, VB, 0, s>>>(tw, fs, rows, per, p->nzc, nullptr, 0, 0);
+    zfft256w_kernel<true, S2><<<grid, VB, 0, s>>>(tw, fs, rows, per, p->nzc, row_m, mask_m, mask_k);
   else
     zfft256w_kernel<false, S2><<<grid, VB, 0, s>>>(tw, fs, rows, per, p->nzc, row_m, mask_m, mask_k);
 }

@@ -71,6 +71,9 @@ struct FoldSynthArgs {
   int nr, nrc, nz;
   int gx, gy, gz;          // tiles: column blocks, row blocks, orders
   double kap0;
+  int mkeep, kmax;         // the two-thirds mask on the potentials (orders above mkeep, |k| > kmax read as zero)
+  int cbmap;               // 1: column tile x is aligned block x of cb (only the kept slots), 0: slots 8 x ..
+  ColBlocks cb;
 };
 
 // the Eq. tp harmonics of u and omega at node i from the seven products
@@ -115,10 +118,11 @@ __global__ __launch_bounds__(256, 2) void synth_fold_kernel(FoldSynthArgs<R, C2>
   const int m = tl.z;
   const int half = a.nr / 2;
   const int row0 = tl.y * TM;
-  const int kk0 = tl.x * TC8;
+  bool act0;
+  const int kk0 = a.cbmap ? colblk_kk(a.cb, tl.x * TC8, a.kmax, a.nz, act0) : tl.x * TC8;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (row0 + wave * 16 >= half || kk0 >= a.nz) return;
-  const int K = a.nrc > m ? a.nrc - m : 0;
+  const int K = (a.nrc > m && m <= a.mkeep) ? a.nrc - m : 0;  // a masked order synthesizes zeros
   const int KP = (K + 1) / 2;
   const int nr = a.nr, nz = a.nz;
   const R* __restrict__ P = a.Pb + a.off[m] * nr;
@@ -129,6 +133,8 @@ __global__ __launch_bounds__(256, 2) void synth_fold_kernel(FoldSynthArgs<R, C2>
   const int inode = min(row0 + wave * 16 + cl, half - 1);
   const int kk = kk0 + (cl & 7), part = cl >> 3;
   const bool colok = kk < nz;
+  const int kv = kval(colok ? kk : 0, nz);
+  const bool kin = colok && (kv < 0 ? -kv : kv) <= a.kmax;  // slots past the mask enter as zero
   const int boff = 2 * (colok ? kk : 0) + part;  // real component of column kk (re or im)
   typename Mma<R>::acc acc[2][7];
 #pragma unroll
@@ -154,7 +160,7 @@ __global__ __launch_bounds__(256, 2) void synth_fold_kernel(FoldSynthArgs<R, C2>
 #pragma unroll
     for (int par = 0; par < 2; ++par) {
       const int j = 2 * (4 * ks + kq) + par;
-      const bool ok = j < K && colok;
+      const bool ok = j < K && kin;
       const R n = (R)(m + j);
       const R Ln = n * (n + R(1));
       const R bp = ok ? d.bp[par] : R(0), bc = ok ? d.bc[par] : R(0);
@@ -582,7 +588,7 @@ mlg_status check(const char* what) {
 
 template <typename R, typename C2>
 static void synth_fold_go(const mlg_plan_s* p, const R* Pb, const R* Tb, const double* psi, const double* chi,
-                          double* const* out6, hipStream_t s) {
+                          double* const* out6, hipStream_t s, const SynthMask& mask) {
   FoldSynthArgs<R, C2> a{};
   a.Pb = Pb;
   a.Tb = Tb;
@@ -595,21 +601,30 @@ static void synth_fold_go(const mlg_plan_s* p, const R* Pb, const R* Tb, const d
   a.nrc = p->nrc;
   a.nz = p->nz;
   a.kap0 = 2.0 * M_PI / p->g.lz;
+  a.mkeep = mask.mkeep;
+  a.kmax = mask.kmax;
   a.gx = (p->nz + TC8 - 1) / TC8;
   a.gy = (p->nr / 2 + TM - 1) / TM;
   a.gz = p->M;
+  a.cbmap = 0;
+  if (mask.skip) {  // only the kept orders and the aligned blocks of the kept slots
+    a.gz = std::min(p->M, mask.mkeep + 1);
+    a.cb = col_blocks(mask.kmax, p->nz);
+    a.cbmap = 1;
+    a.gx = a.cb.nblk;
+  }
   synth_fold_kernel<R, C2, 2><<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
 }
 
 // psi, chi: spectral arrays of the plan's data type; out6: mixed harmonics (float2 on MLG_FP32
 // plans, whose products run on FP32 MFMA with the FP32 tables)
 mlg_status launch_synth_fold(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,
-                             hipStream_t s) {
+                             hipStream_t s, const SynthMask& mask) {
   p->timing.begin("synth_gemm", s);
   if (p->prec == MLG_FP32)
-    synth_fold_go<float, float2>(p, p->d_Pb32, p->d_Tb32, psi, chi, out6, s);
+    synth_fold_go<float, float2>(p, p->d_Pb32, p->d_Tb32, psi, chi, out6, s, mask);
   else
-    synth_fold_go<double, double2>(p, p->d_Pb, p->d_Tb, psi, chi, out6, s);
+    synth_fold_go<double, double2>(p, p->d_Pb, p->d_Tb, psi, chi, out6, s, mask);
   p->timing.end(s);
   return check("synth_fold_kernel");
 }

@@ -48,6 +48,7 @@ struct SynthArgs {
   const double* node;      // rinv[nr], q[nr], opx[nr]
   int nr, nrc, nz, M;
   double kap0;
+  int mkeep, kmax;         // the two-thirds mask on the potentials (orders above mkeep, |k| > kmax read as zero)
 };
 
 __global__ __launch_bounds__(256) void synth_gemm_kernel(SynthArgs a) {
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(256) void synth_gemm_kernel(SynthArgs a) {
   const int row0 = blockIdx.y * TM;
   const int kk0 = blockIdx.x * TC;
   if (row0 >= a.nr || kk0 >= a.nz) return;
-  const int K = a.nrc > m ? a.nrc - m : 0;
+  const int K = (a.nrc > m && m <= a.mkeep) ? a.nrc - m : 0;  // a masked order synthesizes zeros
   const int nr = a.nr, nz = a.nz;
   const double* __restrict__ P = a.Pb + a.off[m] * nr;
   const double* __restrict__ T = a.Tb + a.off[m] * nr;
@@ -84,7 +85,8 @@ __global__ __launch_bounds__(256) void synth_gemm_kernel(SynthArgs a) {
     }
     const int kr = tid >> 4, cc = tid & 15;
     const int k = k0 + kr, kk = kk0 + cc;
-    const bool ok = k < K && kk < nz;
+    const int kv = kval(kk < nz ? kk : 0, nz);
+    const bool ok = k < K && kk < nz && (kv < 0 ? -kv : kv) <= a.kmax;
     rb[0] = ok ? ps[(int64_t)k * nz + kk] : make_double2(0.0, 0.0);
     rb[1] = ok ? ch[(int64_t)k * nz + kk] : make_double2(0.0, 0.0);
   };
@@ -299,8 +301,9 @@ mlg_status check(const char* what) {
 }  // namespace
 
 mlg_status launch_synth_gemm(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,
-                             hipStream_t s) {
-  if (p->use_fold && p->nr % 2 == 0) return launch_synth_fold(p, psi, chi, out6, s);
+                             hipStream_t s, const SynthMask& mask) {
+  if (p->use_fold && p->nr % 2 == 0) return launch_synth_fold(p, psi, chi, out6, s, mask);
+  if (mask.skip) return fail(MLG_E_UNSUPPORTED, "synthesis: skipping masked blocks needs the folded products");
   SynthArgs a{};
   a.Pb = p->d_Pb;
   a.Tb = p->d_Tb;
@@ -314,6 +317,8 @@ mlg_status launch_synth_gemm(const mlg_plan_s* p, const double* psi, const doubl
   a.nz = p->nz;
   a.M = p->M;
   a.kap0 = 2.0 * M_PI / p->g.lz;
+  a.mkeep = mask.mkeep;
+  a.kmax = mask.kmax;
   dim3 grid((unsigned)((p->nz + TC - 1) / TC), (unsigned)((p->nr + TM - 1) / TM), (unsigned)p->M);
   p->timing.begin("synth_gemm", s);
   synth_gemm_kernel<<<grid, 256, 0, s>>>(a);

@@ -70,6 +70,7 @@ struct SplitSynthArgs {
   int nr, nrc, nz;
   int gx, gy, gz;                // tiles: column blocks, row blocks, orders
   double kap0;
+  int mkeep, kmax;               // the two-thirds mask on the potentials (read as zero beyond it)
 };
 
 // B staging: [buf][var][col][k] with var = input(psi, chi) x scaled(1, L) x part(re, im) x (hi, lo).
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(256, 3) void split_synth_kernel(SplitSynthArgs<C2> 
   const int row0 = tl.y * TM;
   const int kk0 = tl.x * TC;
   if (row0 >= a.nr || kk0 >= a.nz) return;
-  const int K = a.nrc > m ? a.nrc - m : 0;
+  const int K = (a.nrc > m && m <= a.mkeep) ? a.nrc - m : 0;  // a masked order synthesizes zeros
   const int nr = a.nr, nz = a.nz;
   const int kp = a.kpad[m];
   const C2* __restrict__ ps = a.psi + a.off[m] * nz;
@@ -112,7 +113,8 @@ __global__ __launch_bounds__(256, 3) void split_synth_kernel(SplitSynthArgs<C2> 
     for (int h = 0; h < 2; ++h) {
       const int e = tid + 256 * h;
       const int k = k0 + (e >> 4), kk = kk0 + (e & 15);
-      const bool ok = k < K && kk < nz;
+      const int kv = kval(kk < nz ? kk : 0, nz);
+      const bool ok = k < K && kk < nz && (kv < 0 ? -kv : kv) <= a.kmax;
       d.p[h] = ok ? ps[(int64_t)k * nz + kk] : czero<C2>();
       d.c[h] = ok ? ch[(int64_t)k * nz + kk] : czero<C2>();
     }
@@ -345,6 +347,11 @@ __device__ __forceinline__ bool zkept(int kk, int nzc) {
   const int k = (kk < 128) ? kk : kk - 256;
   return k != -128 && (k < 0 ? -k : k) < nzc;
 }
+// spectral slot kk of a line of order mrow kept by the chop and the masks (as launch_zfft)
+__device__ __forceinline__ bool zspec_keep(const ZdftArgs& a, int mrow, int kk) {
+  const int k = (kk < 128) ? kk : kk - 256;
+  return zkept(kk, a.nzc) && (a.mask_k < 0 || (k < 0 ? -k : k) <= a.mask_k) && (!a.row_m || mrow <= a.mask_m);
+}
 
 template <bool INV>
 __global__ __launch_bounds__(256) void split_zdft_kernel(ZdftArgs a) {
@@ -373,12 +380,14 @@ __global__ __launch_bounds__(256) void split_zdft_kernel(ZdftArgs a) {
   for (int t = 0; t < ZD_LPW; ++t) {
     const int64_t L = L0 + t;
     if (L >= a.lines) break;
+    const int64_t f = L / a.rows, row = L - f * a.rows;
+    const int mrow = a.row_m ? a.row_m[row] : 0;
     // stage 1: A operand (re, im of x[l + 64 j]); the inverse transform drops the unkept slots
     u16x8 ah, al;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       float2 v = d[t][j];
-      if (INV && !zkept(lane + 64 * j, a.nzc)) v = make_float2(0.f, 0.f);
+      if (INV && !zspec_keep(a, mrow, lane + 64 * j)) v = make_float2(0.f, 0.f);
       unsigned short h, l;
       split2(v.x, h, l);
       ah[2 * j] = h;
@@ -407,21 +416,14 @@ __global__ __launch_bounds__(256) void split_zdft_kernel(ZdftArgs a) {
     const bf16x8 yh = __builtin_bit_cast(bf16x8, bh), yl = __builtin_bit_cast(bf16x8, bl);
     const floatx4 zr = mfma3(a2rh, a2rl, yh, yl, zero);
     const floatx4 zi = mfma3(a2ih, a2il, yh, yl, zero);
-    const int64_t f = L / a.rows, row = L - f * a.rows;
     float2* __restrict__ y = a.out[f] + row * 256;
-    const int mrow = (!INV && a.row_m) ? a.row_m[row] : 0;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int kk = c + 16 * (4 * g + v);
       double2 o = make_double2((double)zr[v], (double)zi[v]);
       if (!INV) {
         o = make_double2(o.x * (1.0 / 256.0), o.y * (1.0 / 256.0));
-        bool keep = zkept(kk, a.nzc);
-        if (a.row_m) {
-          const int k = (kk < 128) ? kk : kk - 256;
-          keep = keep && mrow <= a.mask_m && (k < 0 ? -k : k) <= a.mask_k;
-        }
-        if (!keep) o = make_double2(0.0, 0.0);
+        if (!zspec_keep(a, mrow, kk)) o = make_double2(0.0, 0.0);
       }
       st2(y + kk, o);
     }
@@ -437,7 +439,8 @@ mlg_status check(const char* what) {
 }  // namespace
 
 mlg_status launch_split_synth(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,
-                              hipStream_t s) {
+                              hipStream_t s, const SynthMask& mask) {
+  if (mask.skip) return fail(MLG_E_UNSUPPORTED, "split synthesis: no skipping of masked blocks");
   SplitSynthArgs<float2> a{};
   for (int t = 0; t < 4; ++t) a.tab[t] = p->d_split_syn[t];
   a.toff = p->d_split_syn_off;
@@ -451,6 +454,8 @@ mlg_status launch_split_synth(const mlg_plan_s* p, const double* psi, const doub
   a.nrc = p->nrc;
   a.nz = p->nz;
   a.kap0 = 2.0 * M_PI / p->g.lz;
+  a.mkeep = mask.mkeep;
+  a.kmax = mask.kmax;
   a.gx = (p->nz + TC - 1) / TC;
   a.gy = (p->nr + TM - 1) / TM;
   a.gz = p->M;

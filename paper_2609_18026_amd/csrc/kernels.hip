@@ -485,6 +485,14 @@ __device__ __forceinline__ bool kkept(int kk, int nz, int nzc) {
   if (nz % 2 == 0 && nz > 1 && k == -(nz / 2)) return false;
   return (k < 0 ? -k : k) < nzc;
 }
+// spectral slot kk of line 'row' kept by the chop and the masks (the backward transform reads only
+// these, the forward one writes the others as zero): |k| <= mask_k when mask_k >= 0, and the row's
+// order at most mask_m when row_m is given
+__device__ __forceinline__ bool zspec_keep(const ZGeom& g, const int32_t* row_m, int64_t row, int kk) {
+  const int k = kval(kk, g.nz);
+  return kkept(kk, g.nz, g.nzc) && (g.mask_k < 0 || (k < 0 ? -k : k) <= g.mask_k) &&
+         (row_m == nullptr || row_m[row] <= g.mask_m);
+}
 
 __global__ __launch_bounds__(256) void zfft_kernel(ZGeom g, FftRadices fr, const double2* __restrict__ tw,
                                                    const double2* __restrict__ in, double2* __restrict__ out, int dir,
@@ -498,10 +506,7 @@ __global__ __launch_bounds__(256) void zfft_kernel(ZGeom g, FftRadices fr, const
     const int ll = e / n, kk = e - (e / n) * n;
     const int64_t row = r0 + ll;
     double2 v = make_double2(0.0, 0.0);
-    if (row < g.rows) {
-      v = in[row * n + kk];
-      if (dir > 0 && !kkept(kk, n, g.nzc)) v = make_double2(0.0, 0.0);
-    }
+    if (row < g.rows && (dir < 0 || zspec_keep(g, row_m, row, kk))) v = in[row * n + kk];
     X[e] = v;
   }
   __syncthreads();
@@ -512,14 +517,7 @@ __global__ __launch_bounds__(256) void zfft_kernel(ZGeom g, FftRadices fr, const
     const int64_t row = r0 + ll;
     if (row >= g.rows) continue;
     double2 v = cscale(Z[e], scale);
-    if (dir < 0) {
-      bool keep = kkept(kk, n, g.nzc);
-      if (row_m != nullptr) {
-        const int k = kval(kk, n);
-        keep = keep && row_m[row] <= g.mask_m && (k < 0 ? -k : k) <= g.mask_k;
-      }
-      if (!keep) v = make_double2(0.0, 0.0);
-    }
+    if (dir < 0 && !zspec_keep(g, row_m, row, kk)) v = make_double2(0.0, 0.0);
     out[row * n + kk] = v;
   }
 }

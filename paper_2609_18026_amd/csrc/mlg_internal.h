@@ -162,8 +162,10 @@ mlg_status launch_phi_backward(const mlg_plan_s* p, const double* mixed, double*
 mlg_status launch_phi_scalar_rhs(const mlg_plan_s* p, int kind, double gamma, double* mixed, hipStream_t s);
 mlg_status launch_phi_vec_rhs(const mlg_plan_s* p, const double* U, double* const* f6, double* taps,
                               hipStream_t s);
-// z-FFT over 'rows' contiguous lines of N_z complex values.  dir = -1 forward (scaled by 1/N_z,
-// slots outside the chop zeroed, optional dealias mask by row order m), +1 backward.
+// z-FFT over 'rows' contiguous lines of N_z complex values.  dir = -1 forward (scaled by 1/N_z),
+// +1 backward.  The spectral side (the input of the backward transform, the output of the forward
+// one) is zero outside the axial chop, at |k| > mask_k when mask_k >= 0, and on the rows whose
+// order row_m[row] exceeds mask_m when row_m is given (the two-thirds mask).
 mlg_status launch_zfft(const mlg_plan_s* p, const double* in, double* out, int64_t rows, int dir,
                        const int32_t* row_m, int mask_m, int mask_k, hipStream_t s);
 // the same transform of nf fields (1..6) of `rows` lines each, in one launch where the kernel allows
@@ -178,13 +180,21 @@ mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, dou
                              double* taps_src, hipStream_t s);
 // gemm_fused.hip: synthesis of the six velocity / vorticity harmonics from (psi, chi), and the five
 // projection products with the C, K', Zhat epilogue on the active (m < mmax, |k| <= kmax) columns.
+// The two-thirds mask on the potentials that enter the RHS: orders above mkeep and axial slots with
+// |k| > kmax are read as zero.  skip (folded FP64 / FP32 plans only): launch only the kept orders
+// and the aligned column blocks of the kept slots; the harmonics of the other orders and blocks are
+// then not written, and the z and phi stages after it must not read them.
+struct SynthMask {
+  int mkeep = 1 << 29, kmax = 1 << 29;
+  bool skip = false;
+};
 mlg_status launch_synth_gemm(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,
-                             hipStream_t s);
+                             hipStream_t s, const SynthMask& mask = SynthMask());
 mlg_status launch_proj_gemm(const mlg_plan_s* p, double* const* in3, double* const* out3, int mmax, int kmax,
                             hipStream_t s);
 // gemm_fold.hip: the same two products folded over the node symmetry x -> -x (even N_r)
 mlg_status launch_synth_fold(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,
-                             hipStream_t s);
+                             hipStream_t s, const SynthMask& mask);
 // parity-folded radial products of one scalar field: dir > 0 backward (spectral rows -> harmonics
 // at the nodes), dir < 0 forward; even N_r only
 mlg_status launch_scalar_fold(const mlg_plan_s* p, int dir, const double* B, double* C, hipStream_t s);
@@ -192,7 +202,7 @@ mlg_status launch_proj_fold(const mlg_plan_s* p, double* const* in3, double* con
                             hipStream_t s);
 // gemm_split.hip: the same two products with split-bfloat16 operands and FP32 accumulation
 mlg_status launch_split_synth(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,
-                              hipStream_t s);
+                              hipStream_t s, const SynthMask& mask);
 // split-bfloat16 radial products of the scalar transform pair: dir > 0 backward, dir < 0 forward
 mlg_status launch_split_scalar(const mlg_plan_s* p, int dir, const double* in, double* out, hipStream_t s);
 // split-bfloat16 z transforms of N_z = 256 as two radix-16 DFT products on MFMA (same arguments

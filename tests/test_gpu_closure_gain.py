@@ -12,9 +12,11 @@ the plain solver's (the measured outcome: the network lowers the a-priori error 
 roll-out error, see the design notes).  With the reference judge (the plain term of the coarse
 state evaluated on 96^3 nodes) nearly every correction is rejected and the roll-out follows the
 plain solver's: its error, as the root mean square over the 11 later snapshots, stays within 10% of
-the plain solver's (measured 1.01 and 1.05), while the unjudged network's grows past 50 times it.
-The error at a single snapshot is not the measure: the few accepted corrections shift the phase of
-its oscillation in time by up to 20%.
+the plain solver's (measured 1.00 and 1.02).  The roll-out with the size judge
+||C|| <= beta ||RHS|| is printed beside them and not bounded: it depends on which corrections
+the size judge happens to pass (measured 1.13 and 17 times the plain error on the two held-out
+runs).  The error at a single snapshot is not the measure: the few accepted corrections shift the
+phase of its oscillation in time by up to 20%.
 """
 import numpy as np
 import pytest
@@ -120,6 +122,5 @@ def test_closure_gain_on_held_out_runs():
     # the reference judge keeps the roll-out at the plain solver's error
     for ri in (6, 7):
         assert final[(ri, "closure_ref_judge")] <= 1.10 * final[(ri, "plain")], final
-        assert final[(ri, "closure")] > 10.0 * final[(ri, "closure_ref_judge")], final
     for h in (rj, free, cl, ref, fine, coarse):
         h.close()
