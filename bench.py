@@ -39,25 +39,25 @@ U_FRAME = (0.0, 1.0, 0.0)
 # kernel source hashes to the one that was measured (profiles/rhs_tp_256cubed_kernels.md).
 _SUMMARY = "profiles/rhs_tp_256cubed_kernels.md"
 MEASURED_TRAFFIC = {
-    "synth_gemm": {"bytes": 1192190750, "launches": 1, "n": 256,
+    "synth_gemm": {"bytes": 569433887, "launches": 1, "n": 256,
                    "source": "paper_2609_18026_amd/csrc/gemm_fold.hip",
-                   "sha256": "b0e399c5104fd674093a4e87748b55518f97b73a1f2d612cd5164aeacab46c54",
-                   "profile_avg_ms": 0.5198, "mfma_counter_flops": 23.02e9, "mfma_busy_pct": 62.1},
-    "proj_gemm": {"bytes": 438487816, "launches": 1, "n": 256,
+                   "sha256": "54043c42dd09ef4d4de812fa28234c96d5f0a7eac1c769701a1a5a8fcb7738e3",
+                   "profile_avg_ms": 0.2764, "mfma_counter_flops": 11.77e9, "mfma_busy_pct": 58.9},
+    "proj_gemm": {"bytes": 444546322, "launches": 1, "n": 256,
                   "source": "paper_2609_18026_amd/csrc/gemm_fold.hip",
-                  "sha256": "b0e399c5104fd674093a4e87748b55518f97b73a1f2d612cd5164aeacab46c54",
-                  "profile_avg_ms": 0.2453, "mfma_counter_flops": 8.82e9, "mfma_busy_pct": 49.8},
-    "phi_fft": {"bytes": 1208374834, "launches": 1, "n": 256,
+                  "sha256": "54043c42dd09ef4d4de812fa28234c96d5f0a7eac1c769701a1a5a8fcb7738e3",
+                  "profile_avg_ms": 0.2414, "mfma_counter_flops": 8.82e9, "mfma_busy_pct": 50.1},
+    "phi_fft": {"bytes": 812034567, "launches": 1, "n": 256,
                 "source": "paper_2609_18026_amd/csrc/fft256.hip",
-                "sha256": "74322a2edc0650c5b2fe33aab5345d8752c9754b60a4a8e17dbe069440a06476",
-                "profile_avg_ms": 0.3127},
-    "z_fft": {"bytes": 1610685052 + 541187611, "launches": 2, "n": 256,
+                "sha256": "812f94a6926c47f4ba872ef13d6a27fc8013d6bc796b8f6f4d8e955c4eb4291f",
+                "profile_avg_ms": 0.2894},
+    "z_fft": {"bytes": 913160315 + 541183201, "launches": 2, "n": 256,
               "source": "paper_2609_18026_amd/csrc/fft256.hip",
-              "sha256": "74322a2edc0650c5b2fe33aab5345d8752c9754b60a4a8e17dbe069440a06476"},
-    "projection": {"bytes": 519392734, "launches": 1, "n": 256,
+              "sha256": "812f94a6926c47f4ba872ef13d6a27fc8013d6bc796b8f6f4d8e955c4eb4291f"},
+    "projection": {"bytes": 517791044, "launches": 1, "n": 256,
                    "source": "paper_2609_18026_amd/csrc/kernels.hip",
-                   "sha256": "90dc6d4af36482c08607add01ef558c8cead0e056a43b3296a40141e0da0ea6b",
-                   "profile_avg_ms": 0.1806},
+                   "sha256": "b8b78c8fd72c227e8a8ff48478d1a1ceaa27757b849b4ff4314d28fbe59deaea",
+                   "profile_avg_ms": 0.1795},
 }
 
 
