@@ -267,7 +267,9 @@ struct Six256 {
   S2* f[6];
 };
 
-template <bool GUARD, typename S2>
+// TAPS: also store the nodal u, omega and N (the parity taps); without them the kernel fits 3
+// waves per SIMD (156 VGPRs against 212 with the tap stores)
+template <bool GUARD, bool TAPS, typename S2>
 __global__ __launch_bounds__(VB) void phi_vec256_kernel(Phi256 g, const double2* __restrict__ twg, Six256<S2> fs,
                                                         const double* __restrict__ rinv, double Ux, double Uy,
                                                         double Uz, double* __restrict__ taps, int64_t blk0) {
@@ -325,7 +327,7 @@ __global__ __launch_bounds__(VB) void phi_vec256_kernel(Phi256 g, const double2*
     const double Nr = Up * wz - Uzz * wp;
     const double Np = Uzz * wr[k] - Ur * wz;
     const double Nz = Ur * wp - Up * wr[k];
-    if (taps != nullptr && valid) {
+    if (TAPS && valid) {
       const int64_t o = phys_off(g, q) + j;
       taps[0 * pe + o] = ur[k];
       taps[1 * pe + o] = up[k];
@@ -651,11 +653,20 @@ static void phi_vec_go(const mlg_plan_s* p, const Phi256& g, const double* U, do
   // launch covers the last partial block, if any
   const int64_t full = g.M >= 128 ? g.nlines / PL : 0;
   const int64_t nblk = (g.nlines + PL - 1) / PL;
-  if (full > 0)
-    phi_vec256_kernel<false, S2><<<dim3((unsigned)full), VB, 0, s>>>(g, tw, six, p->d_node, U[0], U[1], U[2], taps, 0);
-  if (nblk > full)
-    phi_vec256_kernel<true, S2><<<dim3((unsigned)(nblk - full)), VB, 0, s>>>(g, tw, six, p->d_node, U[0], U[1], U[2],
-                                                                             taps, full);
+  const double* node = p->d_node;
+  if (full > 0) {
+    if (taps)
+      phi_vec256_kernel<false, true, S2><<<dim3((unsigned)full), VB, 0, s>>>(g, tw, six, node, U[0], U[1], U[2], taps, 0);
+    else
+      phi_vec256_kernel<false, false, S2><<<dim3((unsigned)full), VB, 0, s>>>(g, tw, six, node, U[0], U[1], U[2], taps, 0);
+  }
+  if (nblk > full) {
+    const dim3 grid((unsigned)(nblk - full));
+    if (taps)
+      phi_vec256_kernel<true, true, S2><<<grid, VB, 0, s>>>(g, tw, six, node, U[0], U[1], U[2], taps, full);
+    else
+      phi_vec256_kernel<true, false, S2><<<grid, VB, 0, s>>>(g, tw, six, node, U[0], U[1], U[2], taps, full);
+  }
 }
 
 mlg_status launch_phi256_vec(const mlg_plan_s* p, const double* U, double* const* f6, double* taps, hipStream_t s) {
