@@ -39,25 +39,25 @@ U_FRAME = (0.0, 1.0, 0.0)
 # kernel source hashes to the one that was measured (profiles/rhs_tp_256cubed_kernels.md).
 _SUMMARY = "profiles/rhs_tp_256cubed_kernels.md"
 MEASURED_TRAFFIC = {
-    "synth_gemm": {"bytes": 569433887, "launches": 1, "n": 256,
+    "synth_gemm": {"bytes": 570527157, "launches": 1, "n": 256,
                    "source": "paper_2609_18026_amd/csrc/gemm_fold.hip",
                    "sha256": "54043c42dd09ef4d4de812fa28234c96d5f0a7eac1c769701a1a5a8fcb7738e3",
-                   "profile_avg_ms": 0.2764, "mfma_counter_flops": 11.77e9, "mfma_busy_pct": 58.9},
-    "proj_gemm": {"bytes": 444546322, "launches": 1, "n": 256,
+                   "profile_avg_ms": 0.2834, "mfma_counter_flops": 11.77e9, "mfma_busy_pct": 59.1},
+    "proj_gemm": {"bytes": 449438455, "launches": 1, "n": 256,
                   "source": "paper_2609_18026_amd/csrc/gemm_fold.hip",
                   "sha256": "54043c42dd09ef4d4de812fa28234c96d5f0a7eac1c769701a1a5a8fcb7738e3",
-                  "profile_avg_ms": 0.2414, "mfma_counter_flops": 8.82e9, "mfma_busy_pct": 50.1},
-    "phi_fft": {"bytes": 812034567, "launches": 1, "n": 256,
+                  "profile_avg_ms": 0.2479, "mfma_counter_flops": 8.82e9, "mfma_busy_pct": 50.2},
+    "phi_fft": {"bytes": 811903189, "launches": 1, "n": 256,
                 "source": "paper_2609_18026_amd/csrc/fft256.hip",
-                "sha256": "812f94a6926c47f4ba872ef13d6a27fc8013d6bc796b8f6f4d8e955c4eb4291f",
-                "profile_avg_ms": 0.2894},
-    "z_fft": {"bytes": 913160315 + 541183201, "launches": 2, "n": 256,
+                "sha256": "f0c28d5e0b39affa6f53fec79ba317e96da7fbc20fa931356e50b81047b5e738",
+                "profile_avg_ms": 0.2249},
+    "z_fft": {"bytes": 913152751 + 541193175, "launches": 2, "n": 256,
               "source": "paper_2609_18026_amd/csrc/fft256.hip",
-              "sha256": "812f94a6926c47f4ba872ef13d6a27fc8013d6bc796b8f6f4d8e955c4eb4291f"},
-    "projection": {"bytes": 517791044, "launches": 1, "n": 256,
+              "sha256": "f0c28d5e0b39affa6f53fec79ba317e96da7fbc20fa931356e50b81047b5e738"},
+    "projection": {"bytes": 519651032, "launches": 1, "n": 256,
                    "source": "paper_2609_18026_amd/csrc/kernels.hip",
                    "sha256": "b8b78c8fd72c227e8a8ff48478d1a1ceaa27757b849b4ff4314d28fbe59deaea",
-                   "profile_avg_ms": 0.1795},
+                   "profile_avg_ms": 0.1837},
 }
 
 
