@@ -219,18 +219,22 @@ struct FoldProjArgs {
   double kap0;
 };
 
-// Block tile: 64 pairs of degrees (even and odd n - m) x 8 complex columns, [re | im] packed in
-// the 16 MFMA columns as in synth_fold_kernel; wavefront w takes 16 pairs, the low lane of a partner
-// pair writes the even degree, the high lane the odd one.  Register-fed like the synthesis: each
-// wavefront loads its table rows (its 16 pairs, both parities) and the block's field values at a
-// half node and its mirror straight into the MFMA layouts, D k-steps (of 4 half nodes) ahead, and
-// forms the sums, differences and W Q_A = W Q + 2 W Pbar in registers.  No LDS and no barrier: at
-// D = 1 the kernel holds 4 waves per SIMD (with LDS staging it held 2 and ran 12% longer).  Loads
+// Block tile: 64 RG pairs of degrees (even and odd n - m) x 8 complex columns, [re | im] packed in
+// the 16 MFMA columns as in synth_fold_kernel; wavefront w takes RG groups of 16 pairs, the low
+// lane of a partner pair writes the even degree, the high lane the odd one.  Register-fed like the
+// synthesis: each wavefront loads its table rows (its pairs, both parities) and the block's field
+// values at a half node and its mirror straight into the MFMA layouts, D k-steps (of 4 half nodes)
+// ahead, and forms the sums, differences and W Q_A = W Q + 2 W Pbar in registers.  No LDS and no
+// barrier.  With RG = 2 the six field loads of a k-step feed 20 MFMAs instead of 10 (14 loads per 20
+// MFMAs against 10 per 10), at 2 waves per SIMD: 0.236 -> 0.222 ms at 256^3 against RG = 1 at 4
+// waves per SIMD (and with LDS staging the kernel held 2 waves and ran 12% longer than RG = 1).  Loads
 // are clamped; half nodes past the last are zeroed on the field side, and the entries of pairs
 // past the column and of inactive columns are computed but not stored.  Fields are float2 on
 // reduced-precision plans (converted after the load has landed).
-template <typename C2, int D>
-__global__ __launch_bounds__(256, 4) void proj_fold_kernel(FoldProjArgs<C2> a) {
+constexpr int PROJ_RG = 2;  // row groups of 16 pairs per wavefront
+
+template <typename C2, int D, int RG>
+__global__ __launch_bounds__(256, RG == 1 ? 4 : 2) void proj_fold_kernel(FoldProjArgs<C2> a) {
   typedef double R;
   typedef decltype(C2().x) S;  // storage real type of the fields
   Tile3 tl;
@@ -238,16 +242,22 @@ __global__ __launch_bounds__(256, 4) void proj_fold_kernel(FoldProjArgs<C2> a) {
   const int m = tl.z;
   const int rows = a.nrc > m ? a.nrc - m : 0;
   const int KP = (rows + 1) / 2;
-  const int row0 = tl.y * TM;
+  const int row0 = tl.y * TM * RG;
   const int c0 = tl.x * TC8;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int pr0 = row0 + wave * 16;
+  const int pr0 = row0 + wave * 16 * RG;
   if (pr0 >= KP) return;
+  const int ng = min(RG, (KP - pr0 + 15) / 16);  // row groups of this wavefront holding pairs
   const int nr = a.nr, nz = a.nz, half = a.nr / 2;
   const double* __restrict__ P = a.Pf + a.off[m] * nr;
   const double* __restrict__ Q = a.Qf + a.off[m] * nr;
   const int cl = lane & 15, kq = lane >> 4;
-  const int j0 = min(2 * (pr0 + cl), rows - 1), j1 = min(2 * (pr0 + cl) + 1, rows - 1);
+  int j0[RG], j1[RG];
+#pragma unroll
+  for (int g = 0; g < RG; ++g) {
+    j0[g] = min(2 * (pr0 + 16 * g + cl), rows - 1);
+    j1[g] = min(2 * (pr0 + 16 * g + cl) + 1, rows - 1);
+  }
   bool cact;
   const int kc = colblk_kk(a.cb, c0 + (cl & 7), a.kmax, nz, cact);
   const int kk = cact ? kc : 0;
@@ -255,22 +265,27 @@ __global__ __launch_bounds__(256, 4) void proj_fold_kernel(FoldProjArgs<C2> a) {
   const S* __restrict__ X[3];
 #pragma unroll
   for (int f = 0; f < 3; ++f) X[f] = reinterpret_cast<const S*>(a.in[f] + (int64_t)m * nr * nz) + 2 * kk + part;
-  double4_t acc[2][5];
+  double4_t acc[RG][2][5];
 #pragma unroll
-  for (int s2 = 0; s2 < 2; ++s2)
+  for (int g = 0; g < RG; ++g)
 #pragma unroll
-    for (int p = 0; p < 5; ++p) acc[s2][p] = double4_t{0.0, 0.0, 0.0, 0.0};
+    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+      for (int p = 0; p < 5; ++p) acc[g][s2][p] = double4_t{0.0, 0.0, 0.0, 0.0};
   struct Step {
-    R p[2], q[2];
+    R p[RG][2], q[RG][2];
     S x[3], y[3];
   };
   Step st[D];
   auto load = [&](int ks, Step& d) {
     const int i = min(4 * ks + kq, half - 1);
-    d.p[0] = P[(int64_t)i * rows + j0];
-    d.p[1] = P[(int64_t)i * rows + j1];
-    d.q[0] = Q[(int64_t)i * rows + j0];
-    d.q[1] = Q[(int64_t)i * rows + j1];
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      d.p[g][0] = P[(int64_t)i * rows + j0[g]];
+      d.p[g][1] = P[(int64_t)i * rows + j1[g]];
+      d.q[g][0] = Q[(int64_t)i * rows + j0[g]];
+      d.q[g][1] = Q[(int64_t)i * rows + j1[g]];
+    }
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
       d.x[f] = X[f][(int64_t)i * 2 * nz];
@@ -287,16 +302,20 @@ __global__ __launch_bounds__(256, 4) void proj_fold_kernel(FoldProjArgs<C2> a) {
       df[f] = x - y;
     }
 #pragma unroll
-    for (int par = 0; par < 2; ++par) {
-      const double aP = d.p[par], aQ = d.q[par] + 2.0 * d.p[par];  // w Q_A = w Q + 2 w Pbar
-      const double* bp = par ? df : sm;  // Pbar: even rows use sums
-      const double* bq = par ? sm : df;  // Q_A: even rows use differences
-      double4_t(&c)[5] = acc[par];
-      c[0] = MFMA(aP, bp[0], c[0]);
-      c[1] = MFMA(aQ, bq[0], c[1]);
-      c[2] = MFMA(aP, bp[1], c[2]);
-      c[3] = MFMA(aQ, bq[1], c[3]);
-      c[4] = MFMA(aP, bp[2], c[4]);
+    for (int g = 0; g < RG; ++g) {
+      if (g >= ng) break;
+#pragma unroll
+      for (int par = 0; par < 2; ++par) {
+        const double aP = d.p[g][par], aQ = d.q[g][par] + 2.0 * d.p[g][par];  // w Q_A = w Q + 2 w Pbar
+        const double* bp = par ? df : sm;  // Pbar: even rows use sums
+        const double* bq = par ? sm : df;  // Q_A: even rows use differences
+        double4_t(&c)[5] = acc[g][par];
+        c[0] = MFMA(aP, bp[0], c[0]);
+        c[1] = MFMA(aQ, bq[0], c[1]);
+        c[2] = MFMA(aP, bp[1], c[2]);
+        c[3] = MFMA(aQ, bq[1], c[3]);
+        c[4] = MFMA(aP, bp[2], c[4]);
+      }
     }
   };
   const int nks = (half + 3) / 4;
@@ -315,26 +334,29 @@ __global__ __launch_bounds__(256, 4) void proj_fold_kernel(FoldProjArgs<C2> a) {
   const int64_t tb = a.off[m];
   const int par = hi ? 1 : 0;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int jj = pr0 + (lane >> 4) + 4 * v;
-    double2 val[5];
+  for (int g = 0; g < RG; ++g) {
 #pragma unroll
-    for (int p = 0; p < 5; ++p) {
-      const double e = acc[0][p][v], o = acc[1][p][v];
-      const double send = hi ? e : o;
-      const double recv = __shfl_xor(send, 8);
-      const double mine = hi ? o : e;
-      val[p] = hi ? make_double2(recv, mine) : make_double2(mine, recv);
+    for (int v = 0; v < 4; ++v) {
+      const int jj = pr0 + 16 * g + (lane >> 4) + 4 * v;
+      double2 val[5];
+#pragma unroll
+      for (int p = 0; p < 5; ++p) {
+        const double e = acc[g][0][p][v], o = acc[g][1][p][v];
+        const double send = hi ? e : o;
+        const double recv = __shfl_xor(send, 8);
+        const double mine = hi ? o : e;
+        val[p] = hi ? make_double2(recv, mine) : make_double2(mine, recv);
+      }
+      const int r = 2 * jj + par;
+      if (r >= rows || !cact) continue;
+      const double2 Pa = val[0], Pb = val[2], Pc = val[4];
+      const double2 Qa = make_double2(val[1].x - 2.0 * Pa.x, val[1].y - 2.0 * Pa.y);
+      const double2 Qb = make_double2(val[3].x - 2.0 * Pb.x, val[3].y - 2.0 * Pb.y);
+      const int64_t o = (tb + r) * nz + kk;
+      a.out[0][o] = make_double2(-Qb.x + fm * Pa.y, -Qb.y - fm * Pa.x);
+      a.out[1][o] = make_double2(kap * Qa.y - fm * kap * Pb.x, -kap * Qa.x - fm * kap * Pb.y);
+      a.out[2][o] = Pc;
     }
-    const int r = 2 * jj + par;
-    if (r >= rows || !cact) continue;
-    const double2 Pa = val[0], Pb = val[2], Pc = val[4];
-    const double2 Qa = make_double2(val[1].x - 2.0 * Pa.x, val[1].y - 2.0 * Pa.y);
-    const double2 Qb = make_double2(val[3].x - 2.0 * Pb.x, val[3].y - 2.0 * Pb.y);
-    const int64_t o = (tb + r) * nz + kk;
-    a.out[0][o] = make_double2(-Qb.x + fm * Pa.y, -Qb.y - fm * Pa.x);
-    a.out[1][o] = make_double2(kap * Qa.y - fm * kap * Pb.x, -kap * Qa.x - fm * kap * Pb.y);
-    a.out[2][o] = Pc;
   }
 }
 
@@ -648,9 +670,9 @@ static void proj_fold_go(const mlg_plan_s* p, double* const* in3, double* const*
   a.kap0 = 2.0 * M_PI / p->g.lz;
   const int kp = (p->nrc + 1) / 2;
   a.gx = a.cb.nblk;
-  a.gy = (kp + TM - 1) / TM;
+  a.gy = (kp + TM * PROJ_RG - 1) / (TM * PROJ_RG);
   a.gz = mmax;
-  proj_fold_kernel<C2, 1><<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
+  proj_fold_kernel<C2, 1, PROJ_RG><<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
 }
 
 // in3: harmonics of N (float2 on reduced-precision plans); out3: FP64 sources in every case
