@@ -317,7 +317,7 @@ def reduced_work(nr, nphi, nz, M, nrc, skip=True):
     """Algorithmic HBM bytes per RHS step of each kernel family on a reduced-precision plan: float
     data and intermediates (8-byte complex), 4-byte synthesis tables (FP32, or bfloat16 hi + lo),
     FP64 projection tables and sources.  skip: the synthesis covers only the orders and axial
-    slots the mask keeps (FP32 plans); the split synthesis runs over all of them (writing zeros)."""
+    slots the mask keeps (as both reduced-precision syntheses do at 256^3)."""
     tau = sum(max(nrc - m, 0) for m in range(M))
     mmax, nkact = active_columns(nphi, nz, M, nrc)
     mk = min(M, (nphi - 1) // 3 + 1)
@@ -368,7 +368,7 @@ def bench_reduced(torch, prec, plan, psi, chi, fp64_kernels, args, stream, e0, e
     torch.cuda.synchronize()
     kern = {f: mlg_timing_read(rp.handle, f) for f in families}
     mlg_timing_enable(rp.handle, False)
-    bytes_r = reduced_work(n, n, n, plan.layout.M, plan.layout.nrc, skip=(prec == MLG_FP32))
+    bytes_r = reduced_work(n, n, n, plan.layout.M, plan.layout.nrc)
     bytes_64 = {f: w["bytes"] for f, w in kernel_work(n, n, n, plan.layout.M, plan.layout.nrc).items()}
     per_kernel = {}
     for f in families[:5]:

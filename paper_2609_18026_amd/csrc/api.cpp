@@ -269,11 +269,13 @@ mlg_status mlg_rhs_scalar(mlg_plan p, int kind, double gamma, const void* spec_u
 }  // extern "C"
 
 // Whether mlg_rhs_tp skips the orders and axial blocks the two-thirds mask removes: the folded
-// FP64 / FP32 synthesis followed by the 256-point z and phi stages (the kernels that know to leave
-// them unread); otherwise the synthesis writes them as zeros.
+// FP64 / FP32 or the split synthesis followed by the 256-point z (or split z DFT) and phi stages
+// (the kernels that leave them unread, or discard what they read there); otherwise the synthesis
+// writes them as zeros.
 static bool rhs_skips_masked(const mlg_plan_s* p) {
-  return p->g.dealias != 0 && p->use_fold && p->nr % 2 == 0 && p->prec != MLG_SPLIT_BF16 && p->nz == 256 &&
-         p->nphi == 256 && p->use_fast_fft && (int64_t)p->nr * p->nz <= (int64_t(1) << 23);
+  const bool synth_ok = p->prec == MLG_SPLIT_BF16 || (p->use_fold && p->nr % 2 == 0);
+  return p->g.dealias != 0 && synth_ok && p->nz == 256 && p->nphi == 256 && p->use_fast_fft &&
+         (int64_t)p->nr * p->nz <= (int64_t(1) << 23);
 }
 
 // The kernel sequence of mlg_rhs_tp on the workspace 'ws' (caller-provided, or the per-GPU array of

@@ -71,6 +71,8 @@ struct SplitSynthArgs {
   int gx, gy, gz;                // tiles: column blocks, row blocks, orders
   double kap0;
   int mkeep, kmax;               // the two-thirds mask on the potentials (read as zero beyond it)
+  int nbpos, nstart;             // nbpos > 0: column tile x < nbpos starts at slot TC x, the others at
+                                 // nstart + TC (x - nbpos) (the aligned tiles of the kept slots)
 };
 
 // B staging: [buf][var][col][k] with var = input(psi, chi) x scaled(1, L) x part(re, im) x (hi, lo).
@@ -84,7 +86,7 @@ __global__ __launch_bounds__(256, 3) void split_synth_kernel(SplitSynthArgs<C2> 
   if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
   const int m = tl.z;
   const int row0 = tl.y * TM;
-  const int kk0 = tl.x * TC;
+  const int kk0 = (a.nbpos > 0 && tl.x >= a.nbpos) ? a.nstart + (tl.x - a.nbpos) * TC : tl.x * TC;
   if (row0 >= a.nr || kk0 >= a.nz) return;
   const int K = (a.nrc > m && m <= a.mkeep) ? a.nrc - m : 0;  // a masked order synthesizes zeros
   const int nr = a.nr, nz = a.nz;
@@ -440,7 +442,6 @@ mlg_status check(const char* what) {
 
 mlg_status launch_split_synth(const mlg_plan_s* p, const double* psi, const double* chi, double* const* out6,
                               hipStream_t s, const SynthMask& mask) {
-  if (mask.skip) return fail(MLG_E_UNSUPPORTED, "split synthesis: no skipping of masked blocks");
   SplitSynthArgs<float2> a{};
   for (int t = 0; t < 4; ++t) a.tab[t] = p->d_split_syn[t];
   a.toff = p->d_split_syn_off;
@@ -459,6 +460,18 @@ mlg_status launch_split_synth(const mlg_plan_s* p, const double* psi, const doub
   a.gx = (p->nz + TC - 1) / TC;
   a.gy = (p->nr + TM - 1) / TM;
   a.gz = p->M;
+  a.nbpos = 0;
+  if (mask.skip) {  // only the kept orders and the TC-aligned tiles of the kept slots |k| <= kmax
+    a.gz = std::min(p->M, mask.mkeep + 1);
+    a.nbpos = (mask.kmax + TC) / TC;                    // tiles from slot 0 through slot kmax
+    a.nstart = ((p->nz - mask.kmax) / TC) * TC;         // the first tile holding slot nz - kmax
+    const int nneg = mask.kmax >= 1 ? (p->nz - a.nstart + TC - 1) / TC : 0;
+    if (a.nstart < TC * a.nbpos) {                      // the two ranges meet: every tile
+      a.nbpos = 0;
+    } else {
+      a.gx = a.nbpos + nneg;
+    }
+  }
   p->timing.begin("synth_gemm", s);
   split_synth_kernel<float2><<<xcd_blocks(a.gx, a.gy, a.gz), 256, 0, s>>>(a);
   p->timing.end(s);

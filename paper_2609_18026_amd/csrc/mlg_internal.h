@@ -181,9 +181,9 @@ mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, dou
 // gemm_fused.hip: synthesis of the six velocity / vorticity harmonics from (psi, chi), and the five
 // projection products with the C, K', Zhat epilogue on the active (m < mmax, |k| <= kmax) columns.
 // The two-thirds mask on the potentials that enter the RHS: orders above mkeep and axial slots with
-// |k| > kmax are read as zero.  skip (folded FP64 / FP32 plans only): launch only the kept orders
-// and the aligned column blocks of the kept slots; the harmonics of the other orders and blocks are
-// then not written, and the z and phi stages after it must not read them.
+// |k| > kmax are read as zero.  skip (folded and split synthesis): launch only the kept orders and
+// the aligned column blocks of the kept slots; the harmonics of the other orders and blocks are
+// then not written, and the z and phi stages after it must not use them.
 struct SynthMask {
   int mkeep = 1 << 29, kmax = 1 << 29;
   bool skip = false;
