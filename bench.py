@@ -112,7 +112,8 @@ def kernel_work(nr, nphi, nz, M, nrc):
     folding the radial products count half the flops and read half of each table.  Under the
     two-thirds mask (the RHS workload) the potentials enter through it: the synthesis covers the
     kept orders and axial slots, the inverse z transforms the kept orders (reading the kept slots,
-    writing every z), and the phi stage reads and writes the kept orders."""
+    writing every z), the phi stage reads and writes the kept orders, and the forward z transforms
+    write the kept slots only (the projection products read no others)."""
     mmax, nkact = active_columns(nphi, nz, M, nrc)
     mk = min(M, (nphi - 1) // 3 + 1)             # orders kept by the mask
     tau_k = sum(max(nrc - m, 0) for m in range(mk))
@@ -126,7 +127,8 @@ def kernel_work(nr, nphi, nz, M, nrc):
     w["proj_gemm"] = dict(flops=f * 5 * 2.0 * nr * tau_a * 2 * nkact,
                           bytes=f * 2 * tau_a * nr * 8 + 3 * mmax * nr * nkact * 16 + 3 * tau_a * nkact * 16)
     w["phi_fft"] = dict(flops=None, bytes=9 * kept)
-    w["z_fft"] = dict(flops=None, bytes=6 * mk * nr * (nkact + nz) * 16 + 3 * 2 * mmax * nr * nz * 16)
+    # forward: the three fields of the active orders, read whole, written on the kept slots only
+    w["z_fft"] = dict(flops=None, bytes=6 * mk * nr * (nkact + nz) * 16 + 3 * mmax * nr * (nz + nkact) * 16)
     w["projection"] = dict(flops=None, bytes=3 * tau_a * nkact * 16 + 2 * tau * nz * 16)
     return w
 
@@ -330,7 +332,7 @@ def reduced_work(nr, nphi, nz, M, nrc, skip=True):
     return {"synth_gemm": synth,
             "proj_gemm": f * 2 * tau_a * nr * 8 + 3 * mmax * nr * nkact * 8 + 3 * tau_a * nkact * 16,
             "phi_fft": 9 * kept,
-            "z_fft": 6 * mk * nr * (nkact + nz) * 8 + 3 * 2 * mmax * nr * nz * 8,
+            "z_fft": 6 * mk * nr * (nkact + nz) * 8 + 3 * mmax * nr * (nz + nkact) * 8,
             "projection": 3 * tau_a * nkact * 16 + 2 * tau * nz * 8}
 
 

@@ -332,7 +332,8 @@ static mlg_status rhs_tp_run(mlg_plan p, const double* U, const void* psi, const
   int mmax, kmax;
   active_columns(p, &mmax, &kmax);
   const int64_t frows = (int64_t)mmax * p->nr;
-  if ((st = launch_zfft_fields(p, w.X, w.X, 3, frows, -1, nullptr, 0, -1, s, fp64_only))) return st;
+  // the projection products read only the slots |k| <= kmax: the others need not be written
+  if ((st = launch_zfft_fields(p, w.X, w.X, 3, frows, -1, nullptr, 0, kmax, s, fp64_only, true))) return st;
   // 5. Galerkin projections onto Pbar and Q = T - 2(1+x) Pbar with the C, K', Zhat epilogue
   double* src3[3] = {w.T[0], w.T[1], w.T[2]};
   if ((st = launch_proj_gemm(p, w.X, src3, mmax, kmax, s))) return st;

@@ -500,10 +500,12 @@ struct ZFields {
   S2* out[6];
 };
 
+// kept_only (forward): slots outside the chop and the masks are not stored at all (for callers that
+// read only the kept slots) instead of being written as zero
 template <bool INV, typename S2>
 __global__ __launch_bounds__(VB) void zfft256w_kernel(const double2* __restrict__ twg, ZFields<S2> fs, int64_t rows,
                                                       int64_t per_field, int nzc, const int32_t* __restrict__ row_m,
-                                                      int mask_m, int mask_k) {
+                                                      int mask_m, int mask_k, int kept_only) {
   __shared__ double2 Z[PL][WROW];
   __shared__ double2 tw[256];
   const int t = threadIdx.x, ll = t / WL, s = t % WL;
@@ -538,7 +540,10 @@ __global__ __launch_bounds__(VB) void zfft256w_kernel(const double2* __restrict_
     double2 a = v[j];
     if (!INV) {
       a = cscale(a, 1.0 / 256.0);
-      if (!keep(kk)) a = make_double2(0.0, 0.0);
+      if (!keep(kk)) {
+        if (kept_only) continue;
+        a = make_double2(0.0, 0.0);
+      }
     }
     st2(y + kk, a);
   }
@@ -567,7 +572,7 @@ static bool reduced(const mlg_plan_s* p) { return p->prec != MLG_FP64; }
 
 template <typename S2>
 static void zfft256_go(const mlg_plan_s* p, const double* const* in, double* const* out, int nf, int64_t rows, int dir,
-                       const int32_t* row_m, int mask_m, int mask_k, hipStream_t s) {
+                       const int32_t* row_m, int mask_m, int mask_k, bool kept_only, hipStream_t s) {
   ZFields<S2> fs{};
   for (int i = 0; i < nf; ++i) {
     fs.in[i] = reinterpret_cast<const S2*>(in[i]);
@@ -577,19 +582,19 @@ static void zfft256_go(const mlg_plan_s* p, const double* const* in, double* con
   const int64_t per = (rows + PL - 1) / PL;
   dim3 grid((unsigned)(per * nf));
   if (dir > 0)
-    zfft256w_kernel<true, S2><<<grid, VB, 0, s>>>(tw, fs, rows, per, p->nzc, row_m, mask_m, mask_k);
+    zfft256w_kernel<true, S2><<<grid, VB, 0, s>>>(tw, fs, rows, per, p->nzc, row_m, mask_m, mask_k, 0);
   else
-    zfft256w_kernel<false, S2><<<grid, VB, 0, s>>>(tw, fs, rows, per, p->nzc, row_m, mask_m, mask_k);
+    zfft256w_kernel<false, S2><<<grid, VB, 0, s>>>(tw, fs, rows, per, p->nzc, row_m, mask_m, mask_k, kept_only ? 1 : 0);
 }
 
 mlg_status launch_zfft256(const mlg_plan_s* p, const double* const* in, double* const* out, int nf, int64_t rows,
-                          int dir, const int32_t* row_m, int mask_m, int mask_k, hipStream_t s) {
+                          int dir, const int32_t* row_m, int mask_m, int mask_k, hipStream_t s, bool kept_only) {
   if (nf < 1 || nf > 6) return fail(MLG_E_ARG, "z transform: 1 to 6 fields per launch");
   p->timing.begin("z_fft", s);
   if (reduced(p))
-    zfft256_go<float2>(p, in, out, nf, rows, dir, row_m, mask_m, mask_k, s);
+    zfft256_go<float2>(p, in, out, nf, rows, dir, row_m, mask_m, mask_k, kept_only, s);
   else
-    zfft256_go<double2>(p, in, out, nf, rows, dir, row_m, mask_m, mask_k, s);
+    zfft256_go<double2>(p, in, out, nf, rows, dir, row_m, mask_m, mask_k, kept_only, s);
   p->timing.end(s);
   return check("zfft256w_kernel");
 }

@@ -1205,11 +1205,13 @@ mlg_status launch_phi_vec_rhs(const mlg_plan_s* p, const double* U, double* cons
 }
 
 mlg_status launch_zfft_fields(const mlg_plan_s* p, const double* const* in, double* const* out, int nf, int64_t rows,
-                              int dir, const int32_t* row_m, int mask_m, int mask_k, hipStream_t s, bool fp64_only) {
+                              int dir, const int32_t* row_m, int mask_m, int mask_k, hipStream_t s, bool fp64_only,
+                              bool kept_only) {
   if (rows <= 0 || nf <= 0) return MLG_OK;
   if (p->nz == 256 && p->prec == MLG_SPLIT_BF16 && !fp64_only)
     return launch_split_zdft(p, in, out, nf, rows, dir, row_m, mask_m, mask_k, s);
-  if (p->nz == 256 && p->use_fast_fft) return launch_zfft256(p, in, out, nf, rows, dir, row_m, mask_m, mask_k, s);
+  if (p->nz == 256 && p->use_fast_fft)
+    return launch_zfft256(p, in, out, nf, rows, dir, row_m, mask_m, mask_k, s, kept_only);
   if (p->prec != MLG_FP64) return fail(MLG_E_UNSUPPORTED, "reduced-precision plans need N_z = 256");
   for (int i = 0; i < nf; ++i)
     if (mlg_status st = launch_zfft(p, in[i], out[i], rows, dir, row_m, mask_m, mask_k, s)) return st;

@@ -171,10 +171,11 @@ mlg_status launch_zfft(const mlg_plan_s* p, const double* in, double* out, int64
 // the same transform of nf fields (1..6) of `rows` lines each, in one launch where the kernel allows
 // axial modal kinetic energy from the velocity harmonics u_r, u_phi, u_z (mixed layout)
 mlg_status launch_energy(const mlg_plan_s* p, double* const* u3, double* energy, double* scratch, hipStream_t s);
-// (fp64_only: the FP64 transforms also on a split-bfloat16 plan)
+// (fp64_only: the FP64 transforms also on a split-bfloat16 plan; kept_only: the forward transform
+// may leave the slots outside the chop and masks unwritten, where the 256-point kernel runs)
 mlg_status launch_zfft_fields(const mlg_plan_s* p, const double* const* in, double* const* out, int nf, int64_t rows,
                               int dir, const int32_t* row_m, int mask_m, int mask_k, hipStream_t s,
-                              bool fp64_only = false);
+                              bool fp64_only = false, bool kept_only = false);
 // Elliptic solves from the projection sources (C, K', Zhat); taps_src receives C, K, Zhat.
 mlg_status launch_projection(const mlg_plan_s* p, const double* const* src3, double* psi_n, double* chi_n,
                              double* taps_src, hipStream_t s);
@@ -269,7 +270,8 @@ mlg_status launch_poisson(const mlg_plan_s* p, int variant, const double* f, dou
 mlg_status launch_far_field(const mlg_plan_s* p, double* spec, hipStream_t st);
 // fft256.hip: register-resident 256-point transforms (used when N_z or N_phi equals 256)
 mlg_status launch_zfft256(const mlg_plan_s* p, const double* const* in, double* const* out, int nf, int64_t rows,
-                          int dir, const int32_t* row_m, int mask_m, int mask_k, hipStream_t s);
+                          int dir, const int32_t* row_m, int mask_m, int mask_k, hipStream_t s,
+                          bool kept_only = false);
 mlg_status launch_phi256_forward(const mlg_plan_s* p, const double* phys, double* mixed, hipStream_t s);
 mlg_status launch_phi256_backward(const mlg_plan_s* p, const double* mixed, double* phys, hipStream_t s);
 mlg_status launch_phi256_scalar(const mlg_plan_s* p, int kind, double gamma, double* mixed, hipStream_t s);
