@@ -225,12 +225,14 @@ struct FoldProjArgs {
 // synthesis: each wavefront loads its table rows (its pairs, both parities) and the block's field
 // values at a half node and its mirror straight into the MFMA layouts, D k-steps (of 4 half nodes)
 // ahead, and forms the sums, differences and W Q_A = W Q + 2 W Pbar in registers.  No LDS and no
-// barrier.  With RG = 2 the six field loads of a k-step feed 20 MFMAs instead of 10 (14 loads per 20
-// MFMAs against 10 per 10), at 2 waves per SIMD: 0.236 -> 0.222 ms at 256^3 against RG = 1 at 4
-// waves per SIMD (and with LDS staging the kernel held 2 waves and ran 12% longer than RG = 1).  Loads
+// barrier.  With RG = 2 the six field loads of a k-step feed 20 MFMAs instead of 10, at 2 waves per
+// SIMD: 0.236 -> 0.222 ms at 256^3 against RG = 1 at 4 waves per SIMD (and with LDS staging the
+// kernel held 2 waves and ran 12% longer than RG = 1); each pair's two table entries then come in
+// one 16-byte load (10 loads per 20 MFMAs), 0.220 -> 0.211 ms.  Loads
 // are clamped; half nodes past the last are zeroed on the field side, and the entries of pairs
 // past the column and of inactive columns are computed but not stored.  Fields are float2 on
 // reduced-precision plans (converted after the load has landed).
+typedef double PairLd __attribute__((ext_vector_type(2), aligned(8)));  // two adjacent table entries
 constexpr int PROJ_RG = 2;  // row groups of 16 pairs per wavefront
 
 template <typename C2, int D, int RG>
@@ -252,12 +254,9 @@ __global__ __launch_bounds__(256, RG == 1 ? 4 : 2) void proj_fold_kernel(FoldPro
   const double* __restrict__ P = a.Pf + a.off[m] * nr;
   const double* __restrict__ Q = a.Qf + a.off[m] * nr;
   const int cl = lane & 15, kq = lane >> 4;
-  int j0[RG], j1[RG];
+  int j0[RG];  // even degree of the lane's pair in each group (clamped into the column)
 #pragma unroll
-  for (int g = 0; g < RG; ++g) {
-    j0[g] = min(2 * (pr0 + 16 * g + cl), rows - 1);
-    j1[g] = min(2 * (pr0 + 16 * g + cl) + 1, rows - 1);
-  }
+  for (int g = 0; g < RG; ++g) j0[g] = min(2 * (pr0 + 16 * g + cl), rows - 1);
   bool cact;
   const int kc = colblk_kk(a.cb, c0 + (cl & 7), a.kmax, nz, cact);
   const int kk = cact ? kc : 0;
@@ -279,12 +278,17 @@ __global__ __launch_bounds__(256, RG == 1 ? 4 : 2) void proj_fold_kernel(FoldPro
   Step st[D];
   auto load = [&](int ks, Step& d) {
     const int i = min(4 * ks + kq, half - 1);
+    // the even and odd degree of a pair are adjacent in the [i][n - m] tables: one 16-byte load
+    // (8-byte aligned) takes both.  Where j0 is the column's last degree the second value is the
+    // first entry of node i + 1 (i < N_r / 2, inside the table), read for a row that is not stored
 #pragma unroll
     for (int g = 0; g < RG; ++g) {
-      d.p[g][0] = P[(int64_t)i * rows + j0[g]];
-      d.p[g][1] = P[(int64_t)i * rows + j1[g]];
-      d.q[g][0] = Q[(int64_t)i * rows + j0[g]];
-      d.q[g][1] = Q[(int64_t)i * rows + j1[g]];
+      const PairLd pv = *reinterpret_cast<const PairLd*>(P + (int64_t)i * rows + j0[g]);
+      const PairLd qv = *reinterpret_cast<const PairLd*>(Q + (int64_t)i * rows + j0[g]);
+      d.p[g][0] = pv.x;
+      d.p[g][1] = pv.y;
+      d.q[g][0] = qv.x;
+      d.q[g][1] = qv.y;
     }
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
