@@ -316,8 +316,8 @@ mlg_status mlg_timing_read(mlg_plan plan, const char* kernel, double* total_ms, 
  * Many independent 2D fields (N_z = 1) of uneven sizes, each with its own grid, advanced by three
  * persistent launches (backward transforms, azimuthal stage, forward projections, each block walking
  * its share of the phase's cost-sorted work list): the pseudospectral KPP term
- * R_b = Mask(F(gamma u (1 - u))), u = B(u_hat_b), of Sec. 3.3 and Sec. 5.2 (Eq. kpp), for every
- * instance b.  Spectra of all instances are packed in one device buffer: instance b occupies the
+ * R_b = Mask(F(gamma u (1 - u))), u = B(Mask(u_hat_b)), of Sec. 3.3 and Sec. 5.2 (Eq. kpp), for
+ * every instance b with dealias = 1 in its grid (orders above the two-thirds mask are read as zero).  Spectra of all instances are packed in one device buffer: instance b occupies the
  * complex elements [spec_offsets[b], spec_offsets[b+1]) in the packed triangular layout of a
  * single 2D plan.  Data are complex128 (MLG_FP64) or complex64 (MLG_FP32); tables and the in-kernel
  * Legendre recurrence are built in FP64. */
