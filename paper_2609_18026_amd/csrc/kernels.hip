@@ -616,22 +616,6 @@ __device__ __forceinline__ RunMap sweep_run(double2 (&y)[SMAX], const double2 (&
   return RunMap{yc, yp, e1c, e2c, e1p, e2p};
 }
 
-__device__ __forceinline__ double2 shfl2(double2 v, int d, bool up) {
-  return up ? make_double2(__shfl_up(v.x, d, PS_SEG), __shfl_up(v.y, d, PS_SEG))
-            : make_double2(__shfl_down(v.x, d, PS_SEG), __shfl_down(v.y, d, PS_SEG));
-}
-
-__device__ __forceinline__ RunMap shfl_map(const RunMap& q, int d, bool up) {
-  RunMap o;
-  o.c = shfl2(q.c, d, up);
-  o.p = shfl2(q.p, d, up);
-  o.h0 = up ? __shfl_up(q.h0, d, PS_SEG) : __shfl_down(q.h0, d, PS_SEG);
-  o.h1 = up ? __shfl_up(q.h1, d, PS_SEG) : __shfl_down(q.h1, d, PS_SEG);
-  o.h2 = up ? __shfl_up(q.h2, d, PS_SEG) : __shfl_down(q.h2, d, PS_SEG);
-  o.h3 = up ? __shfl_up(q.h3, d, PS_SEG) : __shfl_down(q.h3, d, PS_SEG);
-  return o;
-}
-
 // A o B: the map of run B followed by run A
 __device__ __forceinline__ RunMap compose(const RunMap& A, const RunMap& B) {
   RunMap o;
@@ -644,19 +628,76 @@ __device__ __forceinline__ RunMap compose(const RunMap& A, const RunMap& B) {
   return o;
 }
 
+// DPP lane moves of a double (two 32-bit moves): lanes whose source lies outside the pattern, and
+// rows outside ROWMASK, keep 'old'.  The moves are VALU operations and need no LDS round trip.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ double dpp_d(double old, double v) {
+  const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)o, (int)(unsigned)x, CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(x >> 32), CTRL, ROWMASK, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+constexpr int DPP_ROW_SHL = 0x100, DPP_ROW_SHR = 0x110, DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138,
+              DPP_ROW_BCAST15 = 0x142;
+
+// the map of the lane the pattern names; lanes without a source receive the identity map
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ RunMap dpp_map(const RunMap& q) {
+  RunMap o;
+  o.c = make_double2(dpp_d<CTRL, ROWMASK>(0.0, q.c.x), dpp_d<CTRL, ROWMASK>(0.0, q.c.y));
+  o.p = make_double2(dpp_d<CTRL, ROWMASK>(0.0, q.p.x), dpp_d<CTRL, ROWMASK>(0.0, q.p.y));
+  o.h0 = dpp_d<CTRL, ROWMASK>(1.0, q.h0);
+  o.h1 = dpp_d<CTRL, ROWMASK>(0.0, q.h1);
+  o.h2 = dpp_d<CTRL, ROWMASK>(0.0, q.h2);
+  o.h3 = dpp_d<CTRL, ROWMASK>(1.0, q.h3);
+  return o;
+}
+
+// every lane of a group of 32 reads lane 16 of its group (ds_swizzle, bit mode with or-mask 16)
+__device__ __forceinline__ double swz_lane16(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)(unsigned)x, 16 << 5);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(x >> 32), 16 << 5);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Entering state (y_1, y_2) of run r, the composition of the runs before it applied to a zero
-// state (UP: runs 0..r-1 in order, else PS_SEG-1 down to r+1): an inclusive Kogge-Stone scan of
-// the maps over the PS_SEG lanes of the column, then the state left by the previous run.
+// state (UP: runs 0..r-1 in order, else PS_SEG-1 down to r+1).  The column's 32 lanes are two
+// rows of 16: an inclusive scan of the maps within each row by DPP row shifts of 1, 2, 4, 8 (lanes
+// past the row's edge compose with the identity), then the rows join: ascending, the second row
+// composes with the last lane of the first (DPP row broadcast); descending, the first row composes
+// with the first lane of the second (swizzle).  The state left by the previous run is then a
+// one-lane DPP wave shift.  Against a Kogge-Stone scan over 32 lanes with LDS permutes, 0.173 ->
+// 0.158 ms for the solves at 256^3.
 template <bool UP>
 __device__ __forceinline__ void enter_state(RunMap q, int r, double2& in1, double2& in2) {
-#pragma unroll
-  for (int d = 1; d < PS_SEG; d *= 2) {
-    const RunMap o = shfl_map(q, d, UP);
-    if (UP ? r >= d : r + d < PS_SEG) q = compose(q, o);
+  static_assert(PS_SEG == 32, "two DPP rows of 16 lanes per column");
+  if (UP) {
+    q = compose(q, dpp_map<DPP_ROW_SHR + 1>(q));
+    q = compose(q, dpp_map<DPP_ROW_SHR + 2>(q));
+    q = compose(q, dpp_map<DPP_ROW_SHR + 4>(q));
+    q = compose(q, dpp_map<DPP_ROW_SHR + 8>(q));
+    q = compose(q, dpp_map<DPP_ROW_BCAST15, 0xa>(q));  // lane 15 (47) into the lanes of row 1 (3)
+    in1 = make_double2(dpp_d<DPP_WAVE_SHR1>(0.0, q.c.x), dpp_d<DPP_WAVE_SHR1>(0.0, q.c.y));
+    in2 = make_double2(dpp_d<DPP_WAVE_SHR1>(0.0, q.p.x), dpp_d<DPP_WAVE_SHR1>(0.0, q.p.y));
+  } else {
+    q = compose(q, dpp_map<DPP_ROW_SHL + 1>(q));
+    q = compose(q, dpp_map<DPP_ROW_SHL + 2>(q));
+    q = compose(q, dpp_map<DPP_ROW_SHL + 4>(q));
+    q = compose(q, dpp_map<DPP_ROW_SHL + 8>(q));
+    RunMap o;
+    o.c = make_double2(swz_lane16(q.c.x), swz_lane16(q.c.y));
+    o.p = make_double2(swz_lane16(q.p.x), swz_lane16(q.p.y));
+    o.h0 = swz_lane16(q.h0);
+    o.h1 = swz_lane16(q.h1);
+    o.h2 = swz_lane16(q.h2);
+    o.h3 = swz_lane16(q.h3);
+    if (r >= 16) o = RunMap{make_double2(0.0, 0.0), make_double2(0.0, 0.0), 1.0, 0.0, 0.0, 1.0};
+    q = compose(q, o);
+    in1 = make_double2(dpp_d<DPP_WAVE_SHL1>(0.0, q.c.x), dpp_d<DPP_WAVE_SHL1>(0.0, q.c.y));
+    in2 = make_double2(dpp_d<DPP_WAVE_SHL1>(0.0, q.p.x), dpp_d<DPP_WAVE_SHL1>(0.0, q.p.y));
   }
-  in1 = shfl2(q.c, 1, UP);
-  in2 = shfl2(q.p, 1, UP);
-  if (UP ? r == 0 : r == PS_SEG - 1) {
+  if (UP ? r == 0 : r == PS_SEG - 1) {  // the first run in sweep order enters from zero
     in1 = make_double2(0.0, 0.0);
     in2 = in1;
   }
