@@ -721,7 +721,7 @@ __device__ __forceinline__ void add_entering(double2 (&y)[SMAX], int len, double
 }
 
 template <bool TAPS, int SMAX, typename O2>
-__global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a) {
+__global__ __launch_bounds__(PS_SEG * PS_COL, SMAX <= 8 ? 2 : 1) void projection_kernel(ProjArgs a) {
   extern __shared__ double sm[];
   const int m = blockIdx.y;
   const int nrc = a.nrc;
@@ -770,8 +770,8 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
     return cadd(g, cscale(zp2, sg2[t]));
   };
 
-  // ---- the loads of round 1 go out first: they need nothing from LDS, and they stay in flight
-  // while the block clears the inactive entries and stages its tables
+  // ---- the source loads of round 1 go out first: they need nothing from LDS, and they stay in
+  // flight while the block clears the inactive entries and stages its tables
   double2 yp[SMAX], yq[SMAX];
   double2 qf[SMAX], qx[2];
   double qr[SMAX];
@@ -786,12 +786,7 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
     const int t = tcl(s0 + j);
     ap[j] = Cs[(int64_t)t * nz];
     aq[j] = Kp[(int64_t)t * nz];
-    qf[j] = qfl[(int64_t)(s0 + j < qrows ? s0 + j : 0) * ncolp];
-    qr[j] = qfr[(int64_t)(s0 + j < qrows ? s0 + j : 0) * ncolp];
   }
-  // the couplings of round 2 reach two rows past the run (rows past the column hold zeros)
-#pragma unroll
-  for (int j = 0; j < 2; ++j) qx[j] = qfl[(int64_t)(s0 + SMAX + j < qrows ? s0 + SMAX + j : 0) * ncolp];
   {
     // every block first clears its share of the entries whose (m, k) column is not solved (the
     // stores drain while the solves wait on their loads): (1) a contiguous share of the rows of
@@ -871,6 +866,12 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
       a.taps[a.tri_elems + gbase * nz + kk] = make_double2(Kq.x + g.x * inv_ell2, Kq.y + g.y * inv_ell2);
       a.taps[2 * a.tri_elems + gbase * nz + kk] = za;
     }
+    // the q-operator factors load only now, when Zhat is no longer held, and arrive while the psi
+    // sweep and its scan run; the factors of round 2 follow the q scan.  Against loading them with
+    // the sources (216 registers, the psi and q sweeps side by side): 178 registers and 0.158 ->
+    // 0.137 ms at 256^3
+#pragma unroll
+    for (int j = 0; j < SMAX; ++j) qf[j] = qfl[(int64_t)(s0 + j < qrows ? s0 + j : 0) * ncolp];
     auto cp = [&](int j, double& al, double& be) {
       al = sl1[s0 + j];
       be = sl2[s0 + j];
@@ -879,12 +880,17 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
       al = qf[j].x;
       be = qf[j].y;
     };
-    const RunMap mq = sweep_run<SMAX, true>(yq, aq, len, cq);
     const RunMap mp = sweep_run<SMAX, true>(yp, ap, len, cp);
     double2 p1, p2, q1, q2;
     enter_state<true>(mp, r, p1, p2);
-    enter_state<true>(mq, r, q1, q2);
     add_entering<SMAX, true>(yp, len, p1, p2, cp);
+    const RunMap mq = sweep_run<SMAX, true>(yq, aq, len, cq);
+    enter_state<true>(mq, r, q1, q2);
+    // the factors of round 2 alone
+#pragma unroll
+    for (int j = 0; j < SMAX; ++j) qr[j] = qfr[(int64_t)(s0 + j < qrows ? s0 + j : 0) * ncolp];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) qx[j] = qfl[(int64_t)(s0 + SMAX + j < qrows ? s0 + SMAX + j : 0) * ncolp];
     add_entering<SMAX, true>(yq, len, q1, q2, cq);
   }
 
@@ -916,12 +922,12 @@ __global__ __launch_bounds__(PS_SEG * PS_COL) void projection_kernel(ProjArgs a)
     };
     double2 (&bp)[SMAX] = yp;  // in place, as in round 1
     double2 (&bq)[SMAX] = yq;
-    const RunMap mq = sweep_run<SMAX, false>(bq, yq, len, cq);
-    const RunMap mp = sweep_run<SMAX, false>(bp, yp, len, cp);
     double2 p1, p2, q1, q2;
+    const RunMap mp = sweep_run<SMAX, false>(bp, yp, len, cp);
     enter_state<false>(mp, r, p1, p2);
-    enter_state<false>(mq, r, q1, q2);
     add_entering<SMAX, false>(bp, len, p1, p2, cp);
+    const RunMap mq = sweep_run<SMAX, false>(bq, yq, len, cq);
+    enter_state<false>(mq, r, q1, q2);
     add_entering<SMAX, false>(bq, len, q1, q2, cq);
 #pragma unroll
     for (int j = 0; j < SMAX; ++j) {
