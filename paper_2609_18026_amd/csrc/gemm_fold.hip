@@ -63,6 +63,15 @@ struct Mma<float> {
 
 __device__ __forceinline__ int kval(int kk, int nz) { return (2 * kk < nz) ? kk : kk - nz; }
 
+// the value of lane l ^ 8 within each row of 16 lanes: a DPP rotation of the row by 8 (a VALU move,
+// no LDS round trip as with __shfl_xor)
+__device__ __forceinline__ double xor8(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)x, 0x128, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), 0x128, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 template <typename R, typename C2>
 struct FoldSynthArgs {
   const R* Pb;             // backward Pbar tables, per m [n-m][i]
@@ -201,7 +210,7 @@ __global__ __launch_bounds__(256, 2) void synth_fold_kernel(FoldSynthArgs<R, C2>
 #pragma unroll
     for (int p = 0; p < 7; ++p) {
       const double e = (double)acc[0][p][v], o = (double)acc[1][p][v];
-      const double e2 = __shfl_xor(e, 8), o2 = __shfl_xor(o, 8);
+      const double e2 = xor8(e), o2 = xor8(o);
       const double er = hi ? e2 : e, ei = hi ? e : e2, orr = hi ? o2 : o, oi = hi ? o : o2;
       val[p] = !hi ? make_double2(er + orr, ei + oi)
                    : (tsign[p] ? make_double2(orr - er, oi - ei) : make_double2(er - orr, ei - oi));
@@ -351,7 +360,7 @@ __global__ __launch_bounds__(256, RG == 1 ? 4 : 2) void proj_fold_kernel(FoldPro
       for (int p = 0; p < 5; ++p) {
         const double e = acc[g][0][p][v], o = acc[g][1][p][v];
         const double send = hi ? e : o;
-        const double recv = __shfl_xor(send, 8);
+        const double recv = xor8(send);
         const double mine = hi ? o : e;
         val[p] = hi ? make_double2(recv, mine) : make_double2(mine, recv);
       }
