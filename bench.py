@@ -129,7 +129,11 @@ def kernel_work(nr, nphi, nz, M, nrc):
     w["phi_fft"] = dict(flops=None, bytes=9 * kept)
     # forward: the three fields of the active orders, read whole, written on the kept slots only
     w["z_fft"] = dict(flops=None, bytes=6 * mk * nr * (nkact + nz) * 16 + 3 * mmax * nr * (nz + nkact) * 16)
-    w["projection"] = dict(flops=None, bytes=3 * tau_a * nkact * 16 + 2 * tau * nz * 16)
+    # the solves: sources, potentials (zeros outside the solved columns) and, like the radial
+    # products' tables, their plan operators: the q-operator factors (l1, l2 and a pivot, 24 B per
+    # solved entry) and 11 per-order Gram and factor tables (8 B per solved degree)
+    w["projection"] = dict(flops=None, bytes=3 * tau_a * nkact * 16 + 2 * tau * nz * 16 + 24 * tau_a * nkact
+                           + 11 * 8 * tau_a)
     return w
 
 
@@ -333,7 +337,7 @@ def reduced_work(nr, nphi, nz, M, nrc, skip=True):
             "proj_gemm": f * 2 * tau_a * nr * 8 + 3 * mmax * nr * nkact * 8 + 3 * tau_a * nkact * 16,
             "phi_fft": 9 * kept,
             "z_fft": 6 * mk * nr * (nkact + nz) * 8 + 3 * mmax * nr * (nz + nkact) * 8,
-            "projection": 3 * tau_a * nkact * 16 + 2 * tau * nz * 8}
+            "projection": 3 * tau_a * nkact * 16 + 2 * tau * nz * 8 + 24 * tau_a * nkact + 11 * 8 * tau_a}
 
 
 def bench_reduced(torch, prec, plan, psi, chi, fp64_kernels, args, stream, e0, e1):
