@@ -206,7 +206,7 @@ def sample_rhs_256(torch, plan, psi, n, npts=16, seed=11):
     N = tp[6 * pe:9 * pe].view(3, n, n, n).cpu().numpy()
     src = tp[9 * pe:].cpu().numpy().view(np.complex128).reshape(3, plan.tau, n)
     out = {"pts": pts, "uw": uw, "N": N, "src": src, "psi": psi.cpu().numpy(), "chi": chi.cpu().numpy(),
-           "M": plan.layout.M, "nrc": plan.layout.nrc, "n": n}
+           "psi_n": po.cpu().numpy(), "chi_n": co.cpu().numpy(), "M": plan.layout.M, "nrc": plan.layout.nrc, "n": n}
     del tp, po, co
     return out
 
@@ -255,10 +255,31 @@ def parity_256_sampled(s256):
     for i, name in enumerate(("C", "K", "Zhat")):
         srcerr[name] = rel(np.concatenate([src[i][m, :, kk] for m, kk in cols]),
                            np.concatenate([pc[c][i] for c in cols]))
+    # the solves: backward error ||A x - b|| / (||A|| ||x|| + ||b||) of the library's potentials at the
+    # columns against the library's sources, with the oracle's truncated Laplacian (Eq. del2h-entries)
+    # and, at m = 0, its gauge row (Sec. 3.2: D psi_N = -C, (D - kappa^2) q = K, D chi_N = q)
+    from oracle.basis import laplacian_matrix
+    Po = synth.from_packed(s256["psi_n"].reshape(-1, n), M, nrc)
+    Co = synth.from_packed(s256["chi_n"].reshape(-1, n), M, nrc)
+    kap = g.kappa()
+    worst = 0.0
+    for m, kk in cols:
+        D = laplacian_matrix(m, nrc, g.ell)
+        Dg = D.copy()
+        if m == 0:
+            Dg[0, :] = np.sqrt((2 * np.arange(nrc) + 1) / 2.0)
+        nA = np.linalg.norm(Dg, 2)
+        b = -src[0][m, m:, kk].copy()
+        q = -src[2][m, m:, kk] if kap[kk] == 0 else np.linalg.solve(D - kap[kk] ** 2 * np.eye(D.shape[0]), src[1][m, m:, kk])
+        for x, rhs in ((Po[m, m:, kk], b), (Co[m, m:, kk], q.copy())):
+            if m == 0:
+                rhs[0] = 0
+            worst = max(worst, float(np.linalg.norm(Dg @ x - rhs) / (nA * np.linalg.norm(x) + np.linalg.norm(rhs))))
     return {"workload": f"vortex pair psi with chi = 1e-2 x a geometric spectrum at {n}^3, FP64, sampled",
             "nodes": len(pts), "columns": [list(c) for c in cols],
             "rel_err_u_omega_at_nodes": rel(uw, ref_uw), "rel_err_N_at_nodes": rel(got_N, ref_N),
-            "rel_err_sources_at_columns": srcerr}
+            "rel_err_sources_at_columns": srcerr, "solve_backward_error_at_columns": worst,
+            "solve_backward_error_bound": 2 * nrc * float(np.finfo(np.float64).eps)}
 
 
 def cpu_baseline(n_sample: int, gpu_small: dict):
