@@ -501,23 +501,28 @@ __global__ __launch_bounds__(256, 3) void scal_bwd_fold_kernel(ScalarFoldArgs<R>
   }
 }
 
-// forward: even n - m rows contract with X_i + X_{N-1-i}, odd rows with the difference, i < N/2
+// forward: even n - m rows contract with X_i + X_{N-1-i}, odd rows with the difference, i < N/2.
+// One block of 8 wavefronts covers 2 TM pairs of an order for 64 columns: wavefronts 0..3 the first
+// TM of them, 4..7 the next TM, both halves on the same staged sums and differences of the
+// fields (with two blocks of TM pairs, each staged them; the second was partly empty on every order
+// at N_r = 256): 0.335 -> 0.328 ms for the transform pair at 256^3.
 template <typename R>
-__global__ __launch_bounds__(256, 3) void scal_fwd_fold_kernel(ScalarFoldArgs<R> a) {
+__global__ __launch_bounds__(512) void scal_fwd_fold_kernel(ScalarFoldArgs<R> a) {
   Tile3 tl;
   if (!xcd_tile(a.gx, a.gy, a.gz, tl)) return;
   const int m = tl.z;
   const int K = a.nrc > m ? a.nrc - m : 0;
   const int KP = (K + 1) / 2;
   const int half = a.nr / 2, nr = a.nr, ncol = a.ncol;
-  const int row0 = tl.y * TM, col0 = tl.x * SC_N;  // row0: pair index
-  if (row0 >= KP || col0 >= ncol) return;
+  const int rowb = tl.y * 2 * TM, col0 = tl.x * SC_N;  // the block covers pairs rowb .. rowb + 2 TM - 1
+  if (rowb >= KP || col0 >= ncol) return;
   const R* __restrict__ A = a.A + a.off[m] * nr;      // [i][n-m], row length K
   const R* __restrict__ B = a.B + (int64_t)m * nr * ncol;
   R* __restrict__ C = a.C + a.off[m] * ncol;
-  __shared__ R As[2][2][SC_P][TM];    // [buf][parity][half node][pair]
+  __shared__ R As[2][2][SC_P][2 * TM];  // [buf][parity][half node][pair]
   __shared__ R Bs[2][2][SC_P][SC_N];  // [buf][sum, difference][half node][column]
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, cl = lane & 15;
+  const int tid = threadIdx.x, lane = tid & 63, wave = (tid >> 6) & 3, cl = lane & 15;
+  const int rloc = (tid >> 8) * TM, row0 = rowb + rloc;  // waves 4..7 take the block's pairs TM .. 2 TM - 1
   typename Mma<R>::acc acc[2][4];
 #pragma unroll
   for (int q = 0; q < 2; ++q)
@@ -527,7 +532,7 @@ __global__ __launch_bounds__(256, 3) void scal_fwd_fold_kernel(ScalarFoldArgs<R>
   // groups wholly past the column (the second row tile of a short order) are skipped by every
   // wavefront alike, so the SIMDs stay evenly loaded (with 16 pairs per wavefront, the one that
   // held the first pairs worked on every tile and the others idled on short orders)
-  const int ng = min(4, (KP - row0 + 15) / 16);
+  const int ng = max(0, min(4, (KP - row0 + 15) / 16));
   // 16-byte loads: the even and odd degree of a pair (adjacent in the [i][n - m] table; the odd one
   // of a last unpaired degree is the first entry of node i + 1, inside the table, and is not stored),
   // and two adjacent columns of the harmonics
@@ -539,19 +544,21 @@ __global__ __launch_bounds__(256, 3) void scal_fwd_fold_kernel(ScalarFoldArgs<R>
     P2 x[NX], y[NX];
   };
   Stage sx, sy;
-  const int Kc = K - 1;  // K > 0 here (row0 < KP)
+  const int Kc = K - 1;  // K > 0 here (rowb < KP)
   auto load = [&](int i0, Stage& d) {
 #pragma unroll
     for (int t = 0; t < NA; ++t) {
-      const int e = tid + 256 * t;  // [half node][pair]
-      const int kr = e / 64, rr = e % 64;
+      const int e = tid + 512 * t;  // [half node][pair]
+      const int kr = e / 128, rr = e % 128;
       const int ic = min(i0 + kr, half - 1);
-      const int jc = min(2 * (row0 + rr), Kc);
+      const int jc = min(2 * (rowb + rr), Kc);
       d.a[t] = *reinterpret_cast<const P2u*>(A + (int64_t)ic * K + jc);
     }
 #pragma unroll
     for (int t = 0; t < NX; ++t) {
-      const int e = tid + 256 * t;  // [half node][32 pairs of columns]
+      // [half node][32 pairs of columns]; threads 256..511 repeat the loads of 0..255 (unconditional
+      // loads keep the wait counts uniform) and do not store them
+      const int e = (tid & 255) + 256 * t;
       const int kr = e / 32, c2 = 2 * (e % 32);
       const int ic = min(i0 + kr, half - 1);
       const int cc2 = min(col0 + c2, ncol - 2);
@@ -562,12 +569,13 @@ __global__ __launch_bounds__(256, 3) void scal_fwd_fold_kernel(ScalarFoldArgs<R>
   auto store = [&](int buf, int i0, const Stage& d) {
 #pragma unroll
     for (int t = 0; t < NA; ++t) {
-      const int e = tid + 256 * t;
-      const int kr = e / 64, rr = e % 64;
+      const int e = tid + 512 * t;
+      const int kr = e / 128, rr = e % 128;
       const bool iok = i0 + kr < half;
-      As[buf][0][kr][rr] = (iok && 2 * (row0 + rr) < K) ? d.a[t].x : R(0);
-      As[buf][1][kr][rr] = (iok && 2 * (row0 + rr) + 1 < K) ? d.a[t].y : R(0);
+      As[buf][0][kr][rr] = (iok && 2 * (rowb + rr) < K) ? d.a[t].x : R(0);
+      As[buf][1][kr][rr] = (iok && 2 * (rowb + rr) + 1 < K) ? d.a[t].y : R(0);
     }
+    if (tid >= 256) return;
 #pragma unroll
     for (int t = 0; t < NX; ++t) {
       const int e = tid + 256 * t;
@@ -590,7 +598,7 @@ __global__ __launch_bounds__(256, 3) void scal_fwd_fold_kernel(ScalarFoldArgs<R>
         const R bv = Bs[buf][par][kr][wave * 16 + cl];
 #pragma unroll
         for (int g = 0; g < 4; ++g)
-          if (g < ng) acc[par][g] = MFMA(As[buf][par][kr][g * 16 + cl], bv, acc[par][g]);
+          if (g < ng) acc[par][g] = MFMA(As[buf][par][kr][rloc + g * 16 + cl], bv, acc[par][g]);
       }
     }
   };
@@ -731,12 +739,12 @@ static void scalar_fold_go(const mlg_plan_s* p, int dir, const R* A, const doubl
   a.nrc = p->nrc;
   a.ncol = 2 * p->nz;
   a.gx = (a.ncol + SC_N - 1) / SC_N;
-  a.gy = dir > 0 ? (p->nr / 2 + TM - 1) / TM : ((p->nrc + 1) / 2 + TM - 1) / TM;
+  a.gy = dir > 0 ? (p->nr / 2 + TM - 1) / TM : ((p->nrc + 1) / 2 + 2 * TM - 1) / (2 * TM);
   a.gz = p->M;
   if (dir > 0)
     scal_bwd_fold_kernel<R><<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
   else
-    scal_fwd_fold_kernel<R><<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 256, 0, s>>>(a);
+    scal_fwd_fold_kernel<R><<<dim3(xcd_blocks(a.gx, a.gy, a.gz)), 512, 0, s>>>(a);
 }
 
 mlg_status launch_scalar_fold(const mlg_plan_s* p, int dir, const double* B, double* C, hipStream_t s) {
